@@ -1,0 +1,240 @@
+"""FP64 CPU oracle of the compact third-order gas-kinetic scheme (test infrastructure).
+
+A plain C implementation (``gks_oracle.c``) of one time step of the scheme,
+written from the paper (Ji, Zhao, Shyy & Xu, compact GKS on tetrahedra) and
+sharing no code with the HIP library.  Only ``tests/``, the smoke check and
+the benchmark's CPU-baseline leg may import this package.
+
+``build()`` compiles ``libgks_oracle.so`` next to this file with gcc
+(``-O2``, OpenMP, no fast-math); ``Oracle`` wraps a mesh and exposes the
+per-kernel and per-step entry points as numpy functions.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gks_oracle.c")
+_LIB = os.path.join(_HERE, "libgks_oracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle library (serial-order arithmetic, OpenMP loops)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC", "-shared",
+               "-ffp-contract=off", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("K", ctypes.c_double), ("mu", ctypes.c_double),
+                ("prandtl", ctypes.c_double), ("eps_tau", ctypes.c_double),
+                ("c_tau", ctypes.c_double), ("eps_weno", ctypes.c_double),
+                ("lw2", ctypes.c_double * 3), ("lw1", ctypes.c_double * 2),
+                ("viscous", ctypes.c_int32), ("nonlinear", ctypes.c_int32)]
+
+
+def make_config(gamma=1.4, mu=0.0, prandtl=1.0, viscous=False, nonlinear=True,
+                eps_tau=0.01, c_tau=1.0, eps_weno=1e-8, lw2=(100.0, 10.0, 1.0),
+                lw1=(10.0, 1.0), K=None) -> Config:
+    """Scheme parameters; linear weights are given as ratios and normalised."""
+    c = Config()
+    c.gamma = gamma
+    c.K = (5.0 - 3.0 * gamma) / (gamma - 1.0) if K is None else K
+    c.mu = mu
+    c.prandtl = prandtl
+    c.eps_tau = eps_tau
+    c.c_tau = c_tau
+    c.eps_weno = eps_weno
+    s2 = sum(lw2)
+    s1 = sum(lw1)
+    for i in range(3):
+        c.lw2[i] = lw2[i] / s2
+    for i in range(2):
+        c.lw1[i] = lw1[i] / s1
+    c.viscous = 1 if viscous else 0
+    c.nonlinear = 1 if nonlinear else 0
+    return c
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        D = ctypes.c_double
+        I64 = ctypes.c_int64
+        L.or_create.restype = P
+        L.or_create.argtypes = [ctypes.POINTER(Config), I64, P, I64, P, I64, P, P, P, P]
+        L.or_destroy.argtypes = [P]
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_set_threads.restype = ctypes.c_int
+        for name in ("or_geometry",):
+            getattr(L, name).argtypes = [P, P, P, P, P]
+        L.or_face_geometry.argtypes = [P, P, P, P]
+        L.or_slopes.argtypes = [P, P, P]
+        L.or_reconstruct.argtypes = [P, P, P, P, P, P]
+        L.or_face_terms.argtypes = [P, P, P, D, P]
+        L.or_stage.argtypes = [P, ctypes.c_int, D, P, P]
+        L.or_step.argtypes = [P, D, P, P]
+        L.or_compute_dt.argtypes = [P, P, D]
+        L.or_compute_dt.restype = D
+        L.or_conservation_sums.argtypes = [P, P, P]
+        L.or_point_flux.argtypes = [ctypes.POINTER(Config), P, P, P, P, P, D, P]
+        L.or_point_flux_density.argtypes = [ctypes.POINTER(Config), P, P, P, P, P, D, D, P]
+        L.or_maxwell_moments.argtypes = [ctypes.POINTER(Config), P, P]
+        L.or_volume_rule.argtypes = [P, P]
+        L.or_face_rule.argtypes = [P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def set_threads(n: int) -> int:
+    return _load().or_set_threads(int(n))
+
+
+class Oracle:
+    """The oracle bound to one mesh and one configuration."""
+
+    def __init__(self, mesh, cfg: Config):
+        L = _load()
+        self.cfg = cfg
+        self.nc = mesh.n_cell
+        self.nf = mesh.n_face
+        self._keep = [np.ascontiguousarray(mesh.xyz, np.float64),
+                      np.ascontiguousarray(mesh.tet, np.int64),
+                      np.ascontiguousarray(mesh.face_vert, np.int64),
+                      np.ascontiguousarray(mesh.face_cell, np.int64),
+                      np.ascontiguousarray(mesh.face_tag, np.int32),
+                      np.ascontiguousarray(mesh.face_shift, np.float64)]
+        xyz, tet, fv, fc, ft, fs = self._keep
+        self._h = L.or_create(ctypes.byref(cfg), mesh.n_vert, _p(xyz), self.nc, _p(tet),
+                              self.nf, _p(fv), _p(fc), _p(ft), _p(fs))
+        if not self._h:
+            raise ValueError("oracle rejected the mesh")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.or_destroy(h)
+            self._h = None
+
+    def geometry(self):
+        n = self.nc
+        vol, cen, m2, dr = np.empty(n), np.empty((3, n)), np.empty((6, n)), np.empty(n)
+        _load().or_geometry(self._h, _p(vol), _p(cen), _p(m2), _p(dr))
+        return vol, cen, m2, dr
+
+    def face_geometry(self):
+        nf = self.nf
+        area, nrm, gp = np.empty(nf), np.empty((3, nf)), np.empty((3, 3, nf))
+        _load().or_face_geometry(self._h, _p(area), _p(nrm), _p(gp))
+        return area, nrm, gp
+
+    def slopes(self, W):
+        W = _f64(W)
+        b = np.empty((15, self.nc))
+        _load().or_slopes(self._h, _p(W), _p(b))
+        return b
+
+    def reconstruct(self, W, gW, with_p2=False):
+        W, gW = _f64(W), _f64(gW)
+        coef = np.empty((50, self.nc))
+        flag = np.empty(self.nc, np.int32)
+        p2 = np.empty((50, self.nc)) if with_p2 else None
+        _load().or_reconstruct(self._h, _p(W), _p(gW), _p(coef), _p(flag),
+                               _p(p2) if with_p2 else None)
+        return (coef, flag, p2) if with_p2 else (coef, flag)
+
+    def face_terms(self, W, gW, dt):
+        W, gW = _f64(W), _f64(gW)
+        out = np.empty((20, self.nf))
+        rc = _load().or_face_terms(self._h, _p(W), _p(gW), float(dt), _p(out))
+        if rc:
+            raise RuntimeError("oracle face terms failed")
+        return out
+
+    def stage(self, stage, dt, W, gW):
+        W, gW = _f64(W).copy(), _f64(gW).copy()
+        rc = _load().or_stage(self._h, int(stage), float(dt), _p(W), _p(gW))
+        if rc:
+            raise RuntimeError(f"oracle stage {stage} failed ({rc})")
+        return W, gW
+
+    def step(self, dt, W, gW):
+        W, gW = _f64(W).copy(), _f64(gW).copy()
+        rc = _load().or_step(self._h, float(dt), _p(W), _p(gW))
+        if rc:
+            raise RuntimeError(f"oracle step failed ({rc})")
+        return W, gW
+
+    def compute_dt(self, W, cfl):
+        W = _f64(W)
+        return float(_load().or_compute_dt(self._h, _p(W), float(cfl)))
+
+    def conservation_sums(self, W):
+        W = _f64(W)
+        out = np.empty(5)
+        _load().or_conservation_sums(self._h, _p(W), _p(out))
+        return out
+
+
+def point_flux(cfg: Config, n, Wl, gWl, Wr, gWr, dt):
+    """F(dt), F(dt/2), W(0), W(dt) at one interface point (global frame)."""
+    args = [_f64(x) for x in (n, Wl, gWl, Wr, gWr)]
+    out = np.empty(20)
+    rc = _load().or_point_flux(ctypes.byref(cfg), *[_p(a) for a in args], float(dt), _p(out))
+    if rc:
+        raise RuntimeError("oracle point flux failed")
+    return out.reshape(4, 5)
+
+
+def point_flux_density(cfg: Config, n, Wl, gWl, Wr, gWr, dt, t):
+    args = [_f64(x) for x in (n, Wl, gWl, Wr, gWr)]
+    out = np.empty(5)
+    rc = _load().or_point_flux_density(ctypes.byref(cfg), *[_p(a) for a in args], float(dt),
+                                       float(t), _p(out))
+    if rc:
+        raise RuntimeError("oracle point flux density failed")
+    return out
+
+
+def maxwell_moments(cfg: Config, W):
+    W = _f64(W)
+    out = np.empty(54)
+    rc = _load().or_maxwell_moments(ctypes.byref(cfg), _p(W), _p(out))
+    if rc:
+        raise RuntimeError("non-physical state")
+    return {"u": out[0:10], "u_pos": out[10:20], "u_neg": out[20:30], "v": out[30:40],
+            "w": out[40:50], "xi2": out[50:54]}
+
+
+def volume_rule():
+    p, w = np.empty(15), np.empty(5)
+    _load().or_volume_rule(_p(p), _p(w))
+    return p.reshape(5, 3), w
+
+
+def face_rule():
+    p, w = np.empty(6), np.empty(3)
+    _load().or_face_rule(_p(p), _p(w))
+    return p.reshape(3, 2), w

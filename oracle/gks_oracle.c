@@ -1,0 +1,1343 @@
+/*
+ * gks_oracle.c -- test infrastructure, not part of the product.
+ *
+ * Plain, slow, FP64 reference of the third-order compact gas-kinetic scheme
+ * (GKS) on tetrahedra of Ji, Zhao, Shyy & Xu.  Every function follows the
+ * paper's steps in its order and notation; it is deliberately unoptimised:
+ *
+ *   - geometry by the paper's own quadratures (Sec. 2.1 three-point face rule,
+ *     Sec. 4.1 five-point volume rule, weight of the centre point read as
+ *     -2/15 so that the rule integrates cubics exactly);
+ *   - reconstruction solves the least-squares (step 1) and constrained
+ *     least-squares (step 2) systems cell by cell, every stage, by Gaussian
+ *     elimination with partial pivoting (Secs. 4.1-4.3);
+ *   - the gas-kinetic solver expands every integrand into monomials in
+ *     (u, v, w, xi^2) and takes Maxwellian moments term by term, and solves
+ *     the 5x5 moment systems for the microscopic slopes numerically
+ *     (Sec. 2.2, eqs. 2nd-flux, co, new-equ-part);
+ *   - two-stage fourth-order time stepping and Gauss-theorem gradient update
+ *     (Secs. 2.3 and 3).
+ *
+ * Loops over cells and faces may run under OpenMP; every output element is
+ * written by exactly one iteration, and all sums run in a fixed serial
+ * order, so results do not depend on the thread count.
+ *
+ * Readings of silent or ambiguous passages (both this file and the library
+ * follow them): polynomials are fitted in coordinates centred at the target
+ * centroid and scaled by h = |Omega|^(1/3); least-squares rows are the
+ * averaged (divided by |Omega_m|) equations with unit weights; the smoothness
+ * factor |Delta_0| of the two-step indicator is |Omega_0|^(2/3); each
+ * multi-index enters the smoothness indicator once; the positivity fallback
+ * acts per cell on all five components; p_l, p_r of the collision time are
+ * the reconstructed point pressures; tau = mu / p^c; the stage-2 flux uses
+ * the same dt with the time origin reset; the Prandtl number enters through
+ * a correction of the time-integrated energy flux by (1/Pr - 1) times the
+ * time-integrated heat flux of the interface distribution about U^c.
+ */
+#include "gks_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NC 5 /* conservative components */
+
+/* ======================================================================== */
+/* small dense linear algebra                                               */
+/* ======================================================================== */
+
+/* Solve A X = B by Gaussian elimination with partial pivoting.  A is n x n
+ * (row-major, destroyed), B is n x m (row-major, overwritten by X).
+ * Returns 0, or -1 if a pivot is exactly zero. */
+static int gepp(int n, int m, double *A, double *B)
+{
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = fabs(A[k * n + k]);
+        for (int i = k + 1; i < n; ++i) {
+            double v = fabs(A[i * n + k]);
+            if (v > best) { best = v; p = i; }
+        }
+        if (best == 0.0) return -1;
+        if (p != k) {
+            for (int j = 0; j < n; ++j) { double t = A[k*n+j]; A[k*n+j] = A[p*n+j]; A[p*n+j] = t; }
+            for (int j = 0; j < m; ++j) { double t = B[k*m+j]; B[k*m+j] = B[p*m+j]; B[p*m+j] = t; }
+        }
+        for (int i = k + 1; i < n; ++i) {
+            double f = A[i * n + k] / A[k * n + k];
+            if (f == 0.0) continue;
+            for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+            for (int j = 0; j < m; ++j) B[i * m + j] -= f * B[k * m + j];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        for (int j = 0; j < m; ++j) {
+            double s = B[k * m + j];
+            for (int i = k + 1; i < n; ++i) s -= A[k * n + i] * B[i * m + j];
+            B[k * m + j] = s / A[k * n + k];
+        }
+    }
+    return 0;
+}
+
+/* ======================================================================== */
+/* quadrature rules of the paper                                            */
+/* ======================================================================== */
+
+/* Sec. 4.1 (eq. base-int-change and the rule after it): five points on the
+ * reference tetrahedron; centre weight -2/15, the other four 3/40. */
+static const double VQ_PTS[5][3] = {
+    {0.25, 0.25, 0.25},
+    {0.5, 1.0 / 6.0, 1.0 / 6.0},
+    {1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0},
+    {1.0 / 6.0, 1.0 / 6.0, 0.5},
+    {1.0 / 6.0, 0.5, 1.0 / 6.0},
+};
+static const double VQ_W[5] = {-2.0 / 15.0, 3.0 / 40.0, 3.0 / 40.0, 3.0 / 40.0, 3.0 / 40.0};
+
+/* Sec. 2.1: three Gauss points on the reference triangle, weights 1/3
+ * (the factor 1/2 of the reference area is applied separately). */
+static const double FQ_PTS[3][2] = {
+    {1.0 / 6.0, 1.0 / 6.0}, {2.0 / 3.0, 1.0 / 6.0}, {1.0 / 6.0, 2.0 / 3.0}};
+static const double FQ_W[3] = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0};
+
+void or_volume_rule(double pts[15], double w[5])
+{
+    for (int q = 0; q < 5; ++q) {
+        for (int d = 0; d < 3; ++d) pts[3 * q + d] = VQ_PTS[q][d];
+        w[q] = VQ_W[q];
+    }
+}
+
+void or_face_rule(double pts[6], double w[3])
+{
+    for (int q = 0; q < 3; ++q) {
+        pts[2 * q] = FQ_PTS[q][0];
+        pts[2 * q + 1] = FQ_PTS[q][1];
+        w[q] = FQ_W[q];
+    }
+}
+
+/* Linear (straight-edged) isoparametric tetrahedron: X = v0 + xi (v1-v0) +
+ * eta (v2-v0) + zeta (v3-v0), the quadratic map of Sec. 4.1 when every edge
+ * is straight. */
+static void tet_map(const double v[4][3], const double xi[3], double X[3])
+{
+    for (int d = 0; d < 3; ++d)
+        X[d] = v[0][d] + xi[0] * (v[1][d] - v[0][d]) + xi[1] * (v[2][d] - v[0][d]) +
+               xi[2] * (v[3][d] - v[0][d]);
+}
+
+static double tet_jac(const double v[4][3])
+{
+    double a[3], b[3], c[3];
+    for (int d = 0; d < 3; ++d) {
+        a[d] = v[1][d] - v[0][d];
+        b[d] = v[2][d] - v[0][d];
+        c[d] = v[3][d] - v[0][d];
+    }
+    return a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+           a[2] * (b[0] * c[1] - b[1] * c[0]);
+}
+
+/* Average over a tetrahedron of y^k, y = (x - origin) / h, for |k| <= 2:
+ * out[0] = 1, out[1..3] = y_j, out[4..9] = (yy_xx, yy_yy, yy_zz, yy_xy,
+ * yy_xz, yy_yz), by the five-point rule. */
+static void tet_avg_monomials(const double v[4][3], const double origin[3], double h,
+                              double out[10])
+{
+    double s[10] = {0};
+    double wsum = 0.0;
+    for (int q = 0; q < 5; ++q) {
+        double X[3], y[3];
+        tet_map(v, VQ_PTS[q], X);
+        for (int d = 0; d < 3; ++d) y[d] = (X[d] - origin[d]) / h;
+        double w = VQ_W[q];
+        s[0] += w;
+        s[1] += w * y[0]; s[2] += w * y[1]; s[3] += w * y[2];
+        s[4] += w * y[0] * y[0]; s[5] += w * y[1] * y[1]; s[6] += w * y[2] * y[2];
+        s[7] += w * y[0] * y[1]; s[8] += w * y[0] * y[2]; s[9] += w * y[1] * y[2];
+        wsum += w;
+    }
+    for (int i = 0; i < 10; ++i) out[i] = s[i] / wsum;
+}
+
+/* ======================================================================== */
+/* mesh and geometry                                                        */
+/* ======================================================================== */
+
+struct or_ctx {
+    or_config cfg;
+    int64_t nc, nf;
+    double (*cv)[4][3];   /* cell vertex coordinates */
+    double *vol;          /* |Omega| */
+    double (*cen)[3];     /* centroid */
+    double (*m2)[6];      /* centroid second moments / |Omega| */
+    double *dr;           /* inscribed-sphere estimate 3|Omega| / sum |Gamma| */
+    int64_t (*nbr)[4];    /* von Neumann neighbours (-1: none) */
+    int64_t (*cface)[4];  /* the face shared with each neighbour slot */
+    double (*noff)[4][3]; /* translation that brings the neighbour next to the cell */
+    int64_t (*fcell)[2];
+    int32_t *ftag;
+    double (*fshift)[3];
+    double *farea;
+    double (*fnorm)[3];
+    double (*fgp)[3][3];  /* Gauss points, owner frame */
+    /* stage storage */
+    double *Wn, *Ln, *Ltn, *FW0; /* W^n [5][nc], L(W^n), dL/dt(W^n), stage-1 W_k(0) sums [5][nf] */
+    double *slopes, *coef, *fterm;
+    int32_t *flag;
+    int have_stage1;
+};
+
+int or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+static void *xcalloc(size_t n, size_t s) { return calloc(n ? n : 1, s); }
+
+void or_destroy(or_ctx *c)
+{
+    if (!c) return;
+    free(c->cv); free(c->vol); free(c->cen); free(c->m2); free(c->dr);
+    free(c->nbr); free(c->cface); free(c->noff); free(c->fcell); free(c->ftag);
+    free(c->fshift); free(c->farea); free(c->fnorm); free(c->fgp);
+    free(c->Wn); free(c->Ln); free(c->Ltn); free(c->FW0);
+    free(c->slopes); free(c->coef); free(c->fterm); free(c->flag);
+    free(c);
+}
+
+or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
+                  int64_t n_cell, const int64_t *tet, int64_t n_face,
+                  const int64_t *face_vert, const int64_t *face_cell,
+                  const int32_t *face_tag, const double *face_shift)
+{
+    if (!cfg || n_cell <= 0 || n_face <= 0 || n_vert <= 0) return NULL;
+    or_ctx *c = (or_ctx *)xcalloc(1, sizeof(or_ctx));
+    c->cfg = *cfg;
+    c->nc = n_cell;
+    c->nf = n_face;
+    int64_t nc = n_cell, nf = n_face;
+    c->cv = xcalloc(nc, sizeof(*c->cv));
+    c->vol = xcalloc(nc, sizeof(double));
+    c->cen = xcalloc(nc, sizeof(*c->cen));
+    c->m2 = xcalloc(nc, sizeof(*c->m2));
+    c->dr = xcalloc(nc, sizeof(double));
+    c->nbr = xcalloc(nc, sizeof(*c->nbr));
+    c->cface = xcalloc(nc, sizeof(*c->cface));
+    c->noff = xcalloc(nc, sizeof(*c->noff));
+    c->fcell = xcalloc(nf, sizeof(*c->fcell));
+    c->ftag = xcalloc(nf, sizeof(int32_t));
+    c->fshift = xcalloc(nf, sizeof(*c->fshift));
+    c->farea = xcalloc(nf, sizeof(double));
+    c->fnorm = xcalloc(nf, sizeof(*c->fnorm));
+    c->fgp = xcalloc(nf, sizeof(*c->fgp));
+    c->Wn = xcalloc(5 * nc, sizeof(double));
+    c->Ln = xcalloc(5 * nc, sizeof(double));
+    c->Ltn = xcalloc(5 * nc, sizeof(double));
+    c->FW0 = xcalloc(5 * nf, sizeof(double));
+    c->slopes = xcalloc(15 * nc, sizeof(double));
+    c->coef = xcalloc(50 * nc, sizeof(double));
+    c->fterm = xcalloc(20 * nf, sizeof(double));
+    c->flag = xcalloc(nc, sizeof(int32_t));
+
+    /* cells: |Omega| = |J| / 6, centroid and second moments by the 5-point rule */
+    for (int64_t i = 0; i < nc; ++i) {
+        for (int a = 0; a < 4; ++a) {
+            int64_t vv = tet[4 * i + a];
+            if (vv < 0 || vv >= n_vert) { or_destroy(c); return NULL; }
+            for (int d = 0; d < 3; ++d) c->cv[i][a][d] = xyz[3 * vv + d];
+        }
+        double J = fabs(tet_jac(c->cv[i]));
+        if (!(J > 0.0)) { or_destroy(c); return NULL; }
+        c->vol[i] = J / 6.0;
+        double zero[3] = {0, 0, 0}, mono[10];
+        tet_avg_monomials(c->cv[i], zero, 1.0, mono);
+        for (int d = 0; d < 3; ++d) c->cen[i][d] = mono[1 + d];
+        tet_avg_monomials(c->cv[i], c->cen[i], 1.0, mono);
+        for (int k = 0; k < 6; ++k) c->m2[i][k] = mono[4 + k];
+        for (int a = 0; a < 4; ++a) { c->nbr[i][a] = -1; c->cface[i][a] = -1; }
+    }
+
+    /* faces: area, owner-outward unit normal and the three Gauss points */
+    double *sumarea = xcalloc(nc, sizeof(double));
+    for (int64_t f = 0; f < nf; ++f) {
+        int64_t L = face_cell[2 * f], R = face_cell[2 * f + 1];
+        if (L < 0 || L >= nc || R >= nc) { free(sumarea); or_destroy(c); return NULL; }
+        c->fcell[f][0] = L;
+        c->fcell[f][1] = R;
+        c->ftag[f] = face_tag[f];
+        for (int d = 0; d < 3; ++d) c->fshift[f][d] = face_shift[3 * f + d];
+        double x[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int d = 0; d < 3; ++d) x[a][d] = xyz[3 * face_vert[3 * f + a] + d];
+        double Xxi[3], Xeta[3], cr[3];
+        for (int d = 0; d < 3; ++d) { Xxi[d] = x[1][d] - x[0][d]; Xeta[d] = x[2][d] - x[0][d]; }
+        cr[0] = Xxi[1] * Xeta[2] - Xxi[2] * Xeta[1];
+        cr[1] = Xxi[2] * Xeta[0] - Xxi[0] * Xeta[2];
+        cr[2] = Xxi[0] * Xeta[1] - Xxi[1] * Xeta[0];
+        double nrm = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        if (!(nrm > 0.0)) { free(sumarea); or_destroy(c); return NULL; }
+        c->farea[f] = 0.5 * nrm;
+        for (int q = 0; q < 3; ++q) {
+            double xi = FQ_PTS[q][0], eta = FQ_PTS[q][1];
+            for (int d = 0; d < 3; ++d)
+                c->fgp[f][q][d] = x[0][d] * (1.0 - xi - eta) + x[1][d] * xi + x[2][d] * eta;
+        }
+        double out = 0.0;
+        for (int d = 0; d < 3; ++d) out += cr[d] * (c->fgp[f][0][d] - c->cen[L][d]);
+        double sgn = out > 0 ? 1.0 : -1.0;
+        for (int d = 0; d < 3; ++d) c->fnorm[f][d] = sgn * cr[d] / nrm;
+        sumarea[L] += c->farea[f];
+        if (R >= 0) sumarea[R] += c->farea[f];
+        /* neighbour slots */
+        int ok = 0;
+        for (int a = 0; a < 4 && R >= 0; ++a)
+            if (c->cface[L][a] < 0) {
+                c->cface[L][a] = f; c->nbr[L][a] = R;
+                for (int d = 0; d < 3; ++d) c->noff[L][a][d] = c->fshift[f][d];
+                ok = 1; break;
+            }
+        if (R < 0) {
+            for (int a = 0; a < 4; ++a)
+                if (c->cface[L][a] < 0) { c->cface[L][a] = f; ok = 1; break; }
+        }
+        if (!ok) { free(sumarea); or_destroy(c); return NULL; }
+        if (R >= 0) {
+            ok = 0;
+            for (int a = 0; a < 4; ++a)
+                if (c->cface[R][a] < 0) {
+                    c->cface[R][a] = f; c->nbr[R][a] = L;
+                    for (int d = 0; d < 3; ++d) c->noff[R][a][d] = -c->fshift[f][d];
+                    ok = 1; break;
+                }
+            if (!ok) { free(sumarea); or_destroy(c); return NULL; }
+        }
+    }
+    /* Sec. 5, eq. time-step: inscribed-sphere estimate */
+    for (int64_t i = 0; i < nc; ++i) c->dr[i] = 3.0 * c->vol[i] / sumarea[i];
+    free(sumarea);
+    for (int64_t i = 0; i < nc; ++i)
+        for (int a = 0; a < 4; ++a)
+            if (c->cface[i][a] < 0) { or_destroy(c); return NULL; }
+    return c;
+}
+
+int or_geometry(const or_ctx *c, double *vol, double *cen, double *mom2, double *dr)
+{
+    int64_t n = c->nc;
+    for (int64_t i = 0; i < n; ++i) {
+        if (vol) vol[i] = c->vol[i];
+        if (dr) dr[i] = c->dr[i];
+        for (int d = 0; d < 3 && cen; ++d) cen[d * n + i] = c->cen[i][d];
+        for (int k = 0; k < 6 && mom2; ++k) mom2[k * n + i] = c->m2[i][k];
+    }
+    return 0;
+}
+
+int or_face_geometry(const or_ctx *c, double *area, double *normal, double *gp)
+{
+    int64_t n = c->nf;
+    for (int64_t f = 0; f < n; ++f) {
+        if (area) area[f] = c->farea[f];
+        for (int d = 0; d < 3 && normal; ++d) normal[d * n + f] = c->fnorm[f][d];
+        for (int q = 0; q < 3 && gp; ++q)
+            for (int d = 0; d < 3; ++d) gp[(3 * q + d) * n + f] = c->fgp[f][q][d];
+    }
+    return 0;
+}
+
+/* vertices of neighbour slot a of cell i, translated next to cell i */
+static void neighbour_vertices(const or_ctx *c, int64_t i, int a, double v[4][3])
+{
+    int64_t m = c->nbr[i][a];
+    for (int k = 0; k < 4; ++k)
+        for (int d = 0; d < 3; ++d) v[k][d] = c->cv[m][k][d] + c->noff[i][a][d];
+}
+
+/* ======================================================================== */
+/* reconstruction, step 1 (Sec. 4.3): P^1 by least squares on the cell     */
+/* averages of the von Neumann neighbours                                   */
+/* ======================================================================== */
+
+static void slopes_cell(const or_ctx *c, int64_t i, const double *W, double b[NC][3])
+{
+    int64_t n = c->nc;
+    double h = cbrt(c->vol[i]);
+    double D[4][3];
+    int nn = 0;
+    int64_t mm[4];
+    for (int a = 0; a < 4; ++a) {
+        if (c->nbr[i][a] < 0) continue;
+        double v[4][3], mono[10];
+        neighbour_vertices(c, i, a, v);
+        tet_avg_monomials(v, c->cen[i], h, mono);
+        /* row m: average over Omega_m of the linear basis y_j (zero mean on Omega_0) */
+        for (int d = 0; d < 3; ++d) D[nn][d] = mono[1 + d];
+        mm[nn++] = c->nbr[i][a];
+    }
+    /* normal equations (D^T D) b' = D^T (Q_m - Q_0) for all components */
+    double A[9], B[3 * NC];
+    for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s) {
+            double t = 0;
+            for (int k = 0; k < nn; ++k) t += D[k][r] * D[k][s];
+            A[3 * r + s] = t;
+        }
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < NC; ++q) {
+            double t = 0;
+            for (int k = 0; k < nn; ++k) t += D[k][r] * (W[q * n + mm[k]] - W[q * n + i]);
+            B[r * NC + q] = t;
+        }
+    if (nn < 3 || gepp(3, NC, A, B) != 0) {
+        for (int q = 0; q < NC; ++q)
+            for (int d = 0; d < 3; ++d) b[q][d] = 0.0;
+        return;
+    }
+    for (int q = 0; q < NC; ++q)
+        for (int d = 0; d < 3; ++d) b[q][d] = B[d * NC + q] / h; /* back to physical units */
+}
+
+int or_slopes(or_ctx *c, const double *W, double *b)
+{
+    int64_t n = c->nc;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double s[NC][3];
+        slopes_cell(c, i, W, s);
+        for (int q = 0; q < NC; ++q)
+            for (int d = 0; d < 3; ++d) b[(3 * q + d) * n + i] = s[q][d];
+    }
+    return 0;
+}
+
+/* ======================================================================== */
+/* reconstruction, step 2 (Secs. 4.1-4.3)                                   */
+/* ======================================================================== */
+
+/* polynomial about the centroid: value c0, gradient G, Hessian H
+ * (xx,yy,zz,xy,xz,yz) -- P(r) = c0 + G.r + 1/2 r^T H r */
+typedef struct { double c0, G[3], H[6]; } qpoly_t;
+
+static double quad_eval(const qpoly_t *p, const double r[3])
+{
+    return p->c0 + p->G[0] * r[0] + p->G[1] * r[1] + p->G[2] * r[2] +
+           0.5 * (p->H[0] * r[0] * r[0] + p->H[1] * r[1] * r[1] + p->H[2] * r[2] * r[2]) +
+           p->H[3] * r[0] * r[1] + p->H[4] * r[0] * r[2] + p->H[5] * r[1] * r[2];
+}
+
+static void quad_grad(const qpoly_t *p, const double r[3], double g[3])
+{
+    g[0] = p->G[0] + p->H[0] * r[0] + p->H[3] * r[1] + p->H[4] * r[2];
+    g[1] = p->G[1] + p->H[3] * r[0] + p->H[1] * r[1] + p->H[5] * r[2];
+    g[2] = p->G[2] + p->H[4] * r[0] + p->H[5] * r[1] + p->H[2] * r[2];
+}
+
+static qpoly_t quad_lin(double a, const qpoly_t *p, double b, const qpoly_t *q)
+{
+    qpoly_t r;
+    r.c0 = a * p->c0 + b * q->c0;
+    for (int d = 0; d < 3; ++d) r.G[d] = a * p->G[d] + b * q->G[d];
+    for (int k = 0; k < 6; ++k) r.H[k] = a * p->H[k] + b * q->H[k];
+    return r;
+}
+
+/* exponent vectors of the 9 basis monomials y^k, 1 <= |k| <= 2 (eq. base) */
+static const int KEXP[9][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0}, {0, 2, 0},
+                               {0, 0, 2}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+
+/* average of y^e for |e| <= 2 from the monomial table of tet_avg_monomials */
+static double mono_lookup(const double mono[10], int ex, int ey, int ez)
+{
+    int s = ex + ey + ez;
+    if (s == 0) return mono[0];
+    if (s == 1) return ex ? mono[1] : (ey ? mono[2] : mono[3]);
+    if (ex == 2) return mono[4];
+    if (ey == 2) return mono[5];
+    if (ez == 2) return mono[6];
+    if (ex && ey) return mono[7];
+    if (ex && ez) return mono[8];
+    return mono[9];
+}
+
+/* Constrained least squares for P^2 (eqs. large-stenci-condition-1/2):
+ * equality rows reproduce the neighbour averages, least-squares rows the
+ * neighbour averaged derivatives; the cell's own averaged derivative is not
+ * used.  Solved through the KKT system.  Returns per component the
+ * polynomial about the centroid. */
+static void p2_cell(const or_ctx *c, int64_t i, const double *W, const double *gW,
+                    qpoly_t P2[NC])
+{
+    int64_t n = c->nc;
+    double h = cbrt(c->vol[i]);
+    double mono0[10];
+    tet_avg_monomials(c->cv[i], c->cen[i], h, mono0);
+    double E[4][9], e[4][NC], A[12][9], bb[12][NC];
+    int ne = 0, na = 0;
+    for (int a = 0; a < 4; ++a) {
+        int64_t m = c->nbr[i][a];
+        if (m < 0) continue;
+        double v[4][3], mono[10];
+        neighbour_vertices(c, i, a, v);
+        tet_avg_monomials(v, c->cen[i], h, mono);
+        for (int k = 0; k < 9; ++k)
+            E[ne][k] = mono_lookup(mono, KEXP[k][0], KEXP[k][1], KEXP[k][2]) -
+                       mono_lookup(mono0, KEXP[k][0], KEXP[k][1], KEXP[k][2]);
+        for (int q = 0; q < NC; ++q) e[ne][q] = W[q * n + m] - W[q * n + i];
+        ++ne;
+        for (int j = 0; j < 3; ++j) {
+            for (int k = 0; k < 9; ++k) {
+                int ex[3] = {KEXP[k][0], KEXP[k][1], KEXP[k][2]};
+                int kj = ex[j];
+                if (kj == 0) { A[na][k] = 0.0; continue; }
+                ex[j] -= 1;
+                A[na][k] = kj * mono_lookup(mono, ex[0], ex[1], ex[2]);
+            }
+            for (int q = 0; q < NC; ++q) bb[na][q] = h * gW[(3 * q + j) * n + m];
+            ++na;
+        }
+    }
+    /* KKT: [A^T A  E^T; E  0] [a; lambda] = [A^T b; e] */
+    int N = 9 + ne;
+    double K[13 * 13], B[13 * NC];
+    memset(K, 0, sizeof(K));
+    memset(B, 0, sizeof(B));
+    for (int r = 0; r < 9; ++r) {
+        for (int s = 0; s < 9; ++s) {
+            double t = 0;
+            for (int k = 0; k < na; ++k) t += A[k][r] * A[k][s];
+            K[r * N + s] = t;
+        }
+        for (int s = 0; s < ne; ++s) K[r * N + 9 + s] = E[s][r];
+        for (int q = 0; q < NC; ++q) {
+            double t = 0;
+            for (int k = 0; k < na; ++k) t += A[k][r] * bb[k][q];
+            B[r * NC + q] = t;
+        }
+    }
+    for (int s = 0; s < ne; ++s) {
+        for (int r = 0; r < 9; ++r) K[(9 + s) * N + r] = E[s][r];
+        for (int q = 0; q < NC; ++q) B[(9 + s) * NC + q] = e[s][q];
+    }
+    int rc = gepp(N, NC, K, B);
+    for (int q = 0; q < NC; ++q) {
+        qpoly_t *p = &P2[q];
+        double Q0 = W[q * n + i];
+        if (rc != 0) {
+            memset(p, 0, sizeof(*p));
+            p->c0 = Q0;
+            continue;
+        }
+        double ak[9];
+        for (int k = 0; k < 9; ++k) ak[k] = B[k * NC + q];
+        /* P^2(y) = Q0 + sum_k a_k (y^k - <y^k>_0); back to physical r = h y */
+        p->c0 = Q0;
+        for (int k = 3; k < 9; ++k)
+            p->c0 -= ak[k] * mono_lookup(mono0, KEXP[k][0], KEXP[k][1], KEXP[k][2]);
+        for (int d = 0; d < 3; ++d) p->G[d] = ak[d] / h;
+        p->H[0] = 2.0 * ak[3] / (h * h);
+        p->H[1] = 2.0 * ak[4] / (h * h);
+        p->H[2] = 2.0 * ak[5] / (h * h);
+        p->H[3] = ak[6] / (h * h);
+        p->H[4] = ak[7] / (h * h);
+        p->H[5] = ak[8] / (h * h);
+    }
+}
+
+/* eq. smooth-indicator for a polynomial about the centroid of cell i, with
+ * derivatives up to order r; the integrals use the five-point rule (exact
+ * for the quadratic integrands that occur here). */
+static double smoothness(const or_ctx *c, int64_t i, const qpoly_t *p, int r)
+{
+    double vol = c->vol[i];
+    double s1 = 0.0, wsum = 0.0;
+    for (int q = 0; q < 5; ++q) {
+        double X[3], rr[3], g[3];
+        tet_map(c->cv[i], VQ_PTS[q], X);
+        for (int d = 0; d < 3; ++d) rr[d] = X[d] - c->cen[i][d];
+        quad_grad(p, rr, g);
+        s1 += VQ_W[q] * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        wsum += VQ_W[q];
+    }
+    /* integral over Omega = |Omega| * average */
+    double beta = pow(vol, 2.0 / 3.0 - 1.0) * vol * (s1 / wsum);
+    if (r >= 2) {
+        double s2 = 0.0;
+        for (int k = 0; k < 6; ++k) s2 += p->H[k] * p->H[k];
+        beta += pow(vol, 4.0 / 3.0 - 1.0) * vol * s2;
+    }
+    return beta;
+}
+
+/* Gauss points of the four faces of cell i, relative to its centroid */
+static int cell_face_points(const or_ctx *c, int64_t i, double r[12][3])
+{
+    int k = 0;
+    for (int a = 0; a < 4; ++a) {
+        int64_t f = c->cface[i][a];
+        double sh[3] = {0, 0, 0};
+        if (c->fcell[f][1] == i)
+            for (int d = 0; d < 3; ++d) sh[d] = c->fshift[f][d];
+        for (int q = 0; q < 3; ++q, ++k)
+            for (int d = 0; d < 3; ++d) r[k][d] = c->fgp[f][q][d] - sh[d] - c->cen[i][d];
+    }
+    return k;
+}
+
+/* Secs. 4.2-4.3: multi-resolution WENO with the two-step indicator for P^0 */
+static int reconstruct_cell(const or_ctx *c, int64_t i, const double *W, const double *gW,
+                            const double *slopes, qpoly_t R[NC], qpoly_t *p2out)
+{
+    const or_config *cf = &c->cfg;
+    int64_t n = c->nc;
+    qpoly_t P2[NC];
+    p2_cell(c, i, W, gW, P2);
+    if (p2out)
+        for (int q = 0; q < NC; ++q) p2out[q] = P2[q];
+    double vol23 = pow(c->vol[i], 2.0 / 3.0);
+    const double g22 = cf->lw2[0], g12 = cf->lw2[1], g02 = cf->lw2[2];
+    const double g11 = cf->lw1[0], g01 = cf->lw1[1];
+    const double eps = cf->eps_weno;
+    for (int q = 0; q < NC; ++q) {
+        double Q0 = W[q * n + i];
+        qpoly_t P0;
+        memset(&P0, 0, sizeof(P0));
+        P0.c0 = Q0;
+        qpoly_t P1 = P0;
+        for (int d = 0; d < 3; ++d) P1.G[d] = slopes[(3 * q + d) * n + i];
+        if (!cf->nonlinear) { R[q] = P2[q]; continue; }
+        /* indicators of P^1 and P^2 */
+        double beta1 = smoothness(c, i, &P1, 1);
+        double beta2 = smoothness(c, i, &P2[q], 2);
+        /* eq. p0-non-linear-weight: indicator of P^0 from the neighbours' slopes */
+        double b0[4];
+        int nb = 0;
+        for (int a = 0; a < 4; ++a) {
+            int64_t m = c->nbr[i][a];
+            if (m < 0) continue;
+            double s = 0;
+            for (int d = 0; d < 3; ++d) {
+                double v = slopes[(3 * q + d) * n + m];
+                s += v * v;
+            }
+            b0[nb++] = vol23 * s;
+        }
+        double beta0 = 0.0;
+        if (nb > 0) {
+            double sum = 0.0;
+            int npair = 0;
+            for (int j = 0; j < nb; ++j)
+                for (int k = 0; k < j; ++k) { sum += fabs(b0[j] - b0[k]); ++npair; }
+            double sigma1 = npair ? pow(sum / npair, 4.0 / 3.0) : 0.0;
+            double w[4], ws = 0.0;
+            for (int j = 0; j < nb; ++j) { w[j] = 1.0 + sigma1 / (eps + b0[j]); ws += w[j]; }
+            for (int j = 0; j < nb; ++j) beta0 += (w[j] / ws) * b0[j];
+        }
+        /* global indicator and nonlinear weights (eq. non-linear-weight) */
+        double sigma = pow(0.5 * (fabs(beta2 - beta1) + fabs(beta2 - beta0)), 4.0 / 3.0);
+        double w2 = g22 * (1.0 + pow(sigma / (eps + beta2), 2.0));
+        double w1 = g12 * (1.0 + pow(sigma / (eps + beta1), 2.0));
+        double w0 = g02 * (1.0 + pow(sigma / (eps + beta0), 2.0));
+        double ws = w0 + w1 + w2;
+        w0 /= ws; w1 /= ws; w2 /= ws;
+        /* the three hierarchical polynomials and their weighted sum */
+        qpoly_t p0 = P0;
+        qpoly_t p1 = quad_lin(1.0 / g11, &P1, -g01 / g11, &P0);
+        qpoly_t t = quad_lin(1.0 / g22, &P2[q], -g12 / g22, &p1);
+        qpoly_t p2 = quad_lin(1.0, &t, -g02 / g22, &p0);
+        qpoly_t s = quad_lin(w2, &p2, w1, &p1);
+        R[q] = quad_lin(1.0, &s, w0, &p0);
+    }
+    /* positivity of density and pressure at the cell's face Gauss points;
+     * otherwise the first-order (constant) reconstruction */
+    double r[12][3];
+    int np = cell_face_points(c, i, r);
+    int bad = 0;
+    for (int k = 0; k < np && !bad; ++k) {
+        double v[NC];
+        for (int q = 0; q < NC; ++q) v[q] = quad_eval(&R[q], r[k]);
+        double rho = v[0];
+        double pr = (cf->gamma - 1.0) * (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho);
+        if (!(rho > 0.0) || !(pr > 0.0)) bad = 1;
+    }
+    if (bad) {
+        for (int q = 0; q < NC; ++q) {
+            memset(&R[q], 0, sizeof(qpoly_t));
+            R[q].c0 = W[q * n + i];
+        }
+    }
+    return bad;
+}
+
+static void pack_quad(const qpoly_t *p, double *out, int64_t n, int64_t i, int q)
+{
+    double *o = out + (size_t)(10 * q) * n + i;
+    o[0] = p->c0;
+    for (int d = 0; d < 3; ++d) o[(1 + d) * n] = p->G[d];
+    for (int k = 0; k < 6; ++k) o[(4 + k) * n] = p->H[k];
+}
+
+int or_reconstruct(or_ctx *c, const double *W, const double *gW, double *coef, int32_t *flag,
+                   double *p2coef)
+{
+    int64_t n = c->nc;
+    or_slopes(c, W, c->slopes);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        qpoly_t R[NC], P2[NC];
+        int bad = reconstruct_cell(c, i, W, gW, c->slopes, R, P2);
+        for (int q = 0; q < NC; ++q) {
+            pack_quad(&R[q], coef, n, i, q);
+            if (p2coef) pack_quad(&P2[q], p2coef, n, i, q);
+        }
+        if (flag) flag[i] = bad;
+    }
+    return 0;
+}
+
+/* ======================================================================== */
+/* gas-kinetic solver (Sec. 2.2)                                            */
+/* ======================================================================== */
+
+/* A polynomial in the particle velocity (u, v, w) and xi^2, kept as an
+ * unsimplified list of monomials c u^e0 v^e1 w^e2 (xi^2)^e3. */
+#define MAXMONO 1024
+#define NMOM 12
+typedef struct { double c; int e[4]; } mono_t;
+typedef struct { int n; mono_t m[MAXMONO]; } poly_t;
+
+static void poly_zero(poly_t *p) { p->n = 0; }
+static void poly_term(poly_t *p, double c, int eu, int ev, int ew, int ex)
+{
+    if (p->n >= MAXMONO) abort();
+    mono_t *t = &p->m[p->n++];
+    t->c = c; t->e[0] = eu; t->e[1] = ev; t->e[2] = ew; t->e[3] = ex;
+}
+static void poly_mul(const poly_t *a, const poly_t *b, poly_t *out)
+{
+    poly_zero(out);
+    for (int i = 0; i < a->n; ++i)
+        for (int j = 0; j < b->n; ++j)
+            poly_term(out, a->m[i].c * b->m[j].c, a->m[i].e[0] + b->m[j].e[0],
+                      a->m[i].e[1] + b->m[j].e[1], a->m[i].e[2] + b->m[j].e[2],
+                      a->m[i].e[3] + b->m[j].e[3]);
+}
+static void poly_add_to(poly_t *acc, const poly_t *p, double s)
+{
+    for (int i = 0; i < p->n; ++i)
+        poly_term(acc, s * p->m[i].c, p->m[i].e[0], p->m[i].e[1], p->m[i].e[2], p->m[i].e[3]);
+}
+
+/* psi = (1, u, v, w, (u^2 + v^2 + w^2 + xi^2) / 2) */
+static void poly_psi(int j, poly_t *p)
+{
+    poly_zero(p);
+    switch (j) {
+    case 0: poly_term(p, 1.0, 0, 0, 0, 0); break;
+    case 1: poly_term(p, 1.0, 1, 0, 0, 0); break;
+    case 2: poly_term(p, 1.0, 0, 1, 0, 0); break;
+    case 3: poly_term(p, 1.0, 0, 0, 1, 0); break;
+    default:
+        poly_term(p, 0.5, 2, 0, 0, 0); poly_term(p, 0.5, 0, 2, 0, 0);
+        poly_term(p, 0.5, 0, 0, 2, 0); poly_term(p, 0.5, 0, 0, 0, 1);
+    }
+}
+/* s = s_j psi_j */
+static void poly_slope(const double s[5], poly_t *p)
+{
+    poly_zero(p);
+    for (int j = 0; j < 5; ++j) {
+        poly_t t;
+        poly_psi(j, &t);
+        poly_add_to(p, &t, s[j]);
+    }
+}
+static void poly_velocity(int d, poly_t *p) /* u_d */
+{
+    poly_zero(p);
+    poly_term(p, 1.0, d == 0, d == 1, d == 2, 0);
+}
+
+/* Maxwellian g = rho (lam/pi)^((K+3)/2) exp(-lam((u-U)^2+(v-V)^2+(w-W)^2+xi^2)),
+ * determined from W by eq. get-glr: rho E = rho (|U|^2/2 + (K+3)/(4 lam)).
+ * Moments are normalised by rho. */
+typedef struct {
+    double rho, U, V, Wv, lam;
+    double mu[NMOM], mup[NMOM], mun[NMOM], mv[NMOM], mw[NMOM], mx[4];
+} maxw_t;
+
+enum { FULL = 0, POS = 1, NEG = 2 };
+
+static void full_moments(double U, double lam, double *m)
+{
+    m[0] = 1.0;
+    m[1] = U;
+    for (int k = 0; k + 2 < NMOM; ++k) m[k + 2] = U * m[k + 1] + (k + 1) / (2.0 * lam) * m[k];
+}
+
+static int maxwellian(const or_config *cf, const double W[5], maxw_t *g)
+{
+    double K = cf->K;
+    g->rho = W[0];
+    if (!(g->rho > 0.0)) return -1;
+    g->U = W[1] / W[0];
+    g->V = W[2] / W[0];
+    g->Wv = W[3] / W[0];
+    double ein = W[4] / W[0] - 0.5 * (g->U * g->U + g->V * g->V + g->Wv * g->Wv);
+    if (!(ein > 0.0)) return -1;
+    g->lam = (K + 3.0) / (4.0 * ein);
+    double lam = g->lam;
+    full_moments(g->U, lam, g->mu);
+    full_moments(g->V, lam, g->mv);
+    full_moments(g->Wv, lam, g->mw);
+    /* half spaces: <u^0>_{u>0} = erfc(-sqrt(lam) U)/2,
+     * <u^1>_{u>0} = U <u^0>_{u>0} + exp(-lam U^2) / (2 sqrt(pi lam)); the
+     * same three-term recursion as the full moments holds above order 1 */
+    double sl = sqrt(lam), ex = exp(-lam * g->U * g->U) / (2.0 * sqrt(M_PI * lam));
+    g->mup[0] = 0.5 * erfc(-sl * g->U);
+    g->mup[1] = g->U * g->mup[0] + ex;
+    g->mun[0] = 0.5 * erfc(sl * g->U);
+    g->mun[1] = g->U * g->mun[0] - ex;
+    for (int k = 0; k + 2 < NMOM; ++k) {
+        g->mup[k + 2] = g->U * g->mup[k + 1] + (k + 1) / (2.0 * lam) * g->mup[k];
+        g->mun[k + 2] = g->U * g->mun[k + 1] + (k + 1) / (2.0 * lam) * g->mun[k];
+    }
+    /* internal variables: K Gaussian degrees of freedom of variance 1/(2 lam) */
+    g->mx[0] = 1.0;
+    g->mx[1] = K / (2.0 * lam);
+    g->mx[2] = K * (K + 2.0) / (4.0 * lam * lam);
+    g->mx[3] = K * (K + 2.0) * (K + 4.0) / (8.0 * lam * lam * lam);
+    return 0;
+}
+
+/* normalised moment of a polynomial: integral of p g over the chosen half of
+ * u, divided by rho */
+static double moment(const poly_t *p, const maxw_t *g, int half)
+{
+    const double *mu = half == POS ? g->mup : (half == NEG ? g->mun : g->mu);
+    double s = 0.0;
+    for (int i = 0; i < p->n; ++i) {
+        const mono_t *t = &p->m[i];
+        if (t->e[0] >= NMOM || t->e[1] >= NMOM || t->e[2] >= NMOM || t->e[3] > 3) abort();
+        s += t->c * mu[t->e[0]] * g->mv[t->e[1]] * g->mw[t->e[2]] * g->mx[t->e[3]];
+    }
+    return s;
+}
+
+/* vector of moments <X psi_j>, j = 0..4 */
+static void moment_psi(const poly_t *X, const maxw_t *g, int half, double out[5])
+{
+    for (int j = 0; j < 5; ++j) {
+        poly_t psi, t;
+        poly_psi(j, &psi);
+        poly_mul(X, &psi, &t);
+        out[j] = moment(&t, g, half);
+    }
+}
+
+/* eq. co: solve <psi psi^T> s = rhs (normalised by rho) for the slope s */
+static int solve_slope(const maxw_t *g, const double rhs[5], double s[5])
+{
+    double M[25], B[5];
+    for (int j = 0; j < 5; ++j)
+        for (int k = 0; k < 5; ++k) {
+            poly_t a, b, t;
+            poly_psi(j, &a);
+            poly_psi(k, &b);
+            poly_mul(&a, &b, &t);
+            M[5 * j + k] = moment(&t, g, FULL);
+        }
+    for (int j = 0; j < 5; ++j) B[j] = rhs[j];
+    if (gepp(5, 1, M, B) != 0) return -1;
+    for (int j = 0; j < 5; ++j) s[j] = B[j];
+    return 0;
+}
+
+/* A from the compatibility condition <A + a_x u + a_y v + a_z w> = 0 */
+static int solve_time_slope(const maxw_t *g, double a[3][5], double A[5])
+{
+    double rhs[5] = {0, 0, 0, 0, 0};
+    for (int d = 0; d < 3; ++d) {
+        poly_t sp, ud, t;
+        poly_slope(a[d], &sp);
+        poly_velocity(d, &ud);
+        poly_mul(&ud, &sp, &t);
+        double m[5];
+        moment_psi(&t, g, FULL, m);
+        for (int j = 0; j < 5; ++j) rhs[j] -= m[j];
+    }
+    return solve_slope(g, rhs, A);
+}
+
+/* rotation of eq. rotate-matrix-3d (Lambda when n1 = -1) */
+static void rotation(const double n[3], double T[3][3])
+{
+    if (n[0] == -1.0) {
+        T[0][0] = -1; T[0][1] = 0; T[0][2] = 0;
+        T[1][0] = 0; T[1][1] = -1; T[1][2] = 0;
+        T[2][0] = 0; T[2][1] = 0; T[2][2] = 1;
+        return;
+    }
+    double n1 = n[0], n2 = n[1], n3 = n[2];
+    T[0][0] = n1; T[0][1] = n2; T[0][2] = n3;
+    T[1][0] = -n2; T[1][1] = n1 + n3 * n3 / (1.0 + n1); T[1][2] = -n2 * n3 / (1.0 + n1);
+    T[2][0] = -n3; T[2][1] = -n2 * n3 / (1.0 + n1); T[2][2] = 1.0 - n3 * n3 / (1.0 + n1);
+}
+
+/* state and gradient into the local frame: W~ = T W; derivative along local
+ * axis j is sum_i T_ji d/dx_i, then T on the components */
+static void to_local(const double T[3][3], const double W[5], const double gW[15],
+                     double Wl[5], double gl[3][5])
+{
+    Wl[0] = W[0];
+    Wl[4] = W[4];
+    for (int r = 0; r < 3; ++r) Wl[1 + r] = T[r][0] * W[1] + T[r][1] * W[2] + T[r][2] * W[3];
+    for (int j = 0; j < 3; ++j) {
+        double dW[5];
+        for (int q = 0; q < 5; ++q)
+            dW[q] = T[j][0] * gW[3 * q + 0] + T[j][1] * gW[3 * q + 1] + T[j][2] * gW[3 * q + 2];
+        gl[j][0] = dW[0];
+        gl[j][4] = dW[4];
+        for (int r = 0; r < 3; ++r) gl[j][1 + r] = T[r][0] * dW[1] + T[r][1] * dW[2] + T[r][2] * dW[3];
+    }
+}
+
+/* back to the global frame with T^{-1} = T^T */
+static void to_global(const double T[3][3], const double Fl[5], double F[5])
+{
+    F[0] = Fl[0];
+    F[4] = Fl[4];
+    for (int r = 0; r < 3; ++r) F[1 + r] = T[0][r] * Fl[1] + T[1][r] * Fl[2] + T[2][r] * Fl[3];
+}
+
+/* Moment vectors of the three parts of eq. 2nd-flux for one Maxwellian:
+ *   F0 = <u psi>, F1 = sum_d <u u_d (a_d.psi) psi>, F2 = <u (A.psi) psi>,
+ *   V0 = <psi>,   V1 = sum_d <u_d (a_d.psi) psi>,   V2 = <(A.psi) psi>,
+ *   Q0..Q2 = the same with the heat-flux weight in place of u psi. */
+typedef struct { double F[3][5], V[3][5], Q[3]; } parts_t;
+
+static void part_moments(const maxw_t *g, int half, double a[3][5], const double A[5],
+                         const poly_t *qw, parts_t *P)
+{
+    poly_t one, u, sumF, sumV, As, t, tt;
+    poly_zero(&one);
+    poly_term(&one, 1.0, 0, 0, 0, 0);
+    poly_velocity(0, &u);
+    poly_zero(&sumV);
+    for (int d = 0; d < 3; ++d) {
+        poly_t sp, ud;
+        poly_slope(a[d], &sp);
+        poly_velocity(d, &ud);
+        poly_mul(&ud, &sp, &t);
+        poly_add_to(&sumV, &t, 1.0);
+    }
+    poly_mul(&u, &sumV, &sumF);
+    poly_slope(A, &As);
+    moment_psi(&u, g, half, P->F[0]);
+    moment_psi(&sumF, g, half, P->F[1]);
+    poly_mul(&u, &As, &t);
+    moment_psi(&t, g, half, P->F[2]);
+    moment_psi(&one, g, half, P->V[0]);
+    moment_psi(&sumV, g, half, P->V[1]);
+    moment_psi(&As, g, half, P->V[2]);
+    P->Q[0] = moment(qw, g, half);
+    poly_mul(qw, &sumV, &tt);
+    P->Q[1] = moment(&tt, g, half);
+    poly_mul(qw, &As, &tt);
+    P->Q[2] = moment(&tt, g, half);
+}
+
+/* Everything the time-dependent distribution of eq. 2nd-flux needs at one
+ * point, in the local frame. */
+typedef struct {
+    double rhoc, rhol, rhor, tau, taun;
+    parts_t c, l, r;
+} interface_t;
+
+static int build_interface(const or_config *cf, const double Wl[5], double gl[3][5],
+                           const double Wr[5], double gr[3][5], double dt, interface_t *I)
+{
+    maxw_t ml, mr, mc;
+    if (maxwellian(cf, Wl, &ml) || maxwellian(cf, Wr, &mr)) return -1;
+    /* microscopic slopes of both sides, eq. co */
+    double al[3][5], ar[3][5];
+    for (int d = 0; d < 3; ++d) {
+        double bl[5], br[5];
+        for (int q = 0; q < 5; ++q) { bl[q] = gl[d][q] / ml.rho; br[q] = gr[d][q] / mr.rho; }
+        if (solve_slope(&ml, bl, al[d]) || solve_slope(&mr, br, ar[d])) return -1;
+    }
+    /* eq. new-equ-part: kinetic weighting of the equilibrium and its slopes */
+    double Wc[5], gc[3][5];
+    {
+        poly_t one;
+        poly_zero(&one);
+        poly_term(&one, 1.0, 0, 0, 0, 0);
+        double mp[5], mn[5];
+        moment_psi(&one, &ml, POS, mp);
+        moment_psi(&one, &mr, NEG, mn);
+        for (int q = 0; q < 5; ++q) Wc[q] = ml.rho * mp[q] + mr.rho * mn[q];
+        for (int d = 0; d < 3; ++d) {
+            poly_t sl, sr;
+            poly_slope(al[d], &sl);
+            poly_slope(ar[d], &sr);
+            moment_psi(&sl, &ml, POS, mp);
+            moment_psi(&sr, &mr, NEG, mn);
+            for (int q = 0; q < 5; ++q) gc[d][q] = ml.rho * mp[q] + mr.rho * mn[q];
+        }
+    }
+    if (maxwellian(cf, Wc, &mc)) return -1;
+    double ac[3][5], Ac[5], Al[5] = {0, 0, 0, 0, 0}, Ar[5] = {0, 0, 0, 0, 0};
+    for (int d = 0; d < 3; ++d) {
+        double b[5];
+        for (int q = 0; q < 5; ++q) b[q] = gc[d][q] / mc.rho;
+        if (solve_slope(&mc, b, ac[d])) return -1;
+    }
+    if (solve_time_slope(&mc, ac, Ac)) return -1;
+    /* collision times (Sec. 2.2) */
+    double pl = ml.rho / (2.0 * ml.lam), pr = mr.rho / (2.0 * mr.lam), pc = mc.rho / (2.0 * mc.lam);
+    double jump = cf->c_tau * fabs((pl - pr) / (pl + pr)) * dt;
+    if (cf->viscous) {
+        I->tau = cf->mu / pc;
+        I->taun = cf->mu / pc + jump;
+    } else {
+        I->tau = 0.0;
+        I->taun = cf->eps_tau * dt + jump;
+    }
+    if (I->tau > 0.0) {
+        if (solve_time_slope(&ml, al, Al) || solve_time_slope(&mr, ar, Ar)) return -1;
+    }
+    /* heat-flux weight (u-U^c)(|u-U^c|^2 + xi^2)/2 about the interface velocity */
+    poly_t du, dv, dw, c2, t, qw;
+    poly_zero(&du); poly_term(&du, 1.0, 1, 0, 0, 0); poly_term(&du, -mc.U, 0, 0, 0, 0);
+    poly_zero(&dv); poly_term(&dv, 1.0, 0, 1, 0, 0); poly_term(&dv, -mc.V, 0, 0, 0, 0);
+    poly_zero(&dw); poly_term(&dw, 1.0, 0, 0, 1, 0); poly_term(&dw, -mc.Wv, 0, 0, 0, 0);
+    poly_zero(&c2);
+    poly_mul(&du, &du, &t); poly_add_to(&c2, &t, 1.0);
+    poly_mul(&dv, &dv, &t); poly_add_to(&c2, &t, 1.0);
+    poly_mul(&dw, &dw, &t); poly_add_to(&c2, &t, 1.0);
+    poly_term(&c2, 1.0, 0, 0, 0, 1);
+    poly_mul(&du, &c2, &qw);
+    for (int i = 0; i < qw.n; ++i) qw.m[i].c *= 0.5;
+
+    I->rhoc = mc.rho;
+    I->rhol = ml.rho;
+    I->rhor = mr.rho;
+    part_moments(&mc, FULL, ac, Ac, &qw, &I->c);
+    part_moments(&ml, POS, al, Al, &qw, &I->l);
+    part_moments(&mr, NEG, ar, Ar, &qw, &I->r);
+    return 0;
+}
+
+/* time integral over [0, delta] of eq. 2nd-flux taken against u psi */
+static void integrated_flux(const or_config *cf, const interface_t *I, double delta, double F[5])
+{
+    double tau = I->tau, tn = I->taun;
+    double e = exp(-delta / tn);
+    double E1 = tn * (1.0 - e);
+    double E2 = tn * tn * (1.0 - e) - tn * delta * e;
+    double c1 = delta - E1;
+    double c2 = E2 + tau * E1 - tau * delta;
+    double c3 = 0.5 * delta * delta - tau * delta + tau * E1;
+    double c4 = E1;
+    double c5 = -(tau * E1 + E2);
+    double c6 = -tau * E1;
+    for (int q = 0; q < 5; ++q)
+        F[q] = I->rhoc * (c1 * I->c.F[0][q] + c2 * I->c.F[1][q] + c3 * I->c.F[2][q]) +
+               I->rhol * (c4 * I->l.F[0][q] + c5 * I->l.F[1][q] + c6 * I->l.F[2][q]) +
+               I->rhor * (c4 * I->r.F[0][q] + c5 * I->r.F[1][q] + c6 * I->r.F[2][q]);
+    if (cf->prandtl != 1.0) {
+        double qh = I->rhoc * (c1 * I->c.Q[0] + c2 * I->c.Q[1] + c3 * I->c.Q[2]) +
+                    I->rhol * (c4 * I->l.Q[0] + c5 * I->l.Q[1] + c6 * I->l.Q[2]) +
+                    I->rhor * (c4 * I->r.Q[0] + c5 * I->r.Q[1] + c6 * I->r.Q[2]);
+        F[4] += (1.0 / cf->prandtl - 1.0) * qh;
+    }
+}
+
+/* the coefficients of eq. 2nd-flux at time t (un-integrated) */
+static void point_coeffs(const interface_t *I, double t, double d[6])
+{
+    double tau = I->tau, e = exp(-t / I->taun);
+    d[0] = 1.0 - e;
+    d[1] = (t + tau) * e - tau;
+    d[2] = t - tau + tau * e;
+    d[3] = e;
+    d[4] = -(tau + t) * e;
+    d[5] = -tau * e;
+}
+
+/* eq. point-interface: conservative variables of the distribution at time t */
+static void point_state(const interface_t *I, double t, double Wt[5])
+{
+    double d[6];
+    point_coeffs(I, t, d);
+    for (int q = 0; q < 5; ++q)
+        Wt[q] = I->rhoc * (d[0] * I->c.V[0][q] + d[1] * I->c.V[1][q] + d[2] * I->c.V[2][q]) +
+                I->rhol * (d[3] * I->l.V[0][q] + d[4] * I->l.V[1][q] + d[5] * I->l.V[2][q]) +
+                I->rhor * (d[3] * I->r.V[0][q] + d[4] * I->r.V[1][q] + d[5] * I->r.V[2][q]);
+}
+
+static void point_flux_density(const or_config *cf, const interface_t *I, double t, double F[5])
+{
+    double d[6];
+    point_coeffs(I, t, d);
+    for (int q = 0; q < 5; ++q)
+        F[q] = I->rhoc * (d[0] * I->c.F[0][q] + d[1] * I->c.F[1][q] + d[2] * I->c.F[2][q]) +
+               I->rhol * (d[3] * I->l.F[0][q] + d[4] * I->l.F[1][q] + d[5] * I->l.F[2][q]) +
+               I->rhor * (d[3] * I->r.F[0][q] + d[4] * I->r.F[1][q] + d[5] * I->r.F[2][q]);
+    if (cf->prandtl != 1.0) {
+        double qh = I->rhoc * (d[0] * I->c.Q[0] + d[1] * I->c.Q[1] + d[2] * I->c.Q[2]) +
+                    I->rhol * (d[3] * I->l.Q[0] + d[4] * I->l.Q[1] + d[5] * I->l.Q[2]) +
+                    I->rhor * (d[3] * I->r.Q[0] + d[4] * I->r.Q[1] + d[5] * I->r.Q[2]);
+        F[4] += (1.0 / cf->prandtl - 1.0) * qh;
+    }
+}
+
+/* gas-kinetic solver at one point in the global frame; out[20] =
+ * F(dt), F(dt/2), W(0), W(dt) */
+static int gks_point(const or_config *cf, const double n[3], const double Wl[5],
+                     const double gWl[15], const double Wr[5], const double gWr[15],
+                     double dt, double out[20])
+{
+    double T[3][3], wl[5], wr[5], gl[3][5], gr[3][5];
+    rotation(n, T);
+    to_local(T, Wl, gWl, wl, gl);
+    to_local(T, Wr, gWr, wr, gr);
+    interface_t I;
+    if (build_interface(cf, wl, gl, wr, gr, dt, &I)) return -1;
+    double loc[4][5];
+    integrated_flux(cf, &I, dt, loc[0]);
+    integrated_flux(cf, &I, 0.5 * dt, loc[1]);
+    point_state(&I, 0.0, loc[2]);
+    point_state(&I, dt, loc[3]);
+    for (int k = 0; k < 4; ++k) to_global(T, loc[k], out + 5 * k);
+    return 0;
+}
+
+int or_point_flux(const or_config *cf, const double n[3], const double Wl[5],
+                  const double gWl[15], const double Wr[5], const double gWr[15], double dt,
+                  double out[20])
+{
+    return gks_point(cf, n, Wl, gWl, Wr, gWr, dt, out);
+}
+
+int or_point_flux_density(const or_config *cf, const double n[3], const double Wl[5],
+                          const double gWl[15], const double Wr[5], const double gWr[15],
+                          double dt, double t, double out[5])
+{
+    double T[3][3], wl[5], wr[5], gl[3][5], gr[3][5], loc[5];
+    rotation(n, T);
+    to_local(T, Wl, gWl, wl, gl);
+    to_local(T, Wr, gWr, wr, gr);
+    interface_t I;
+    if (build_interface(cf, wl, gl, wr, gr, dt, &I)) return -1;
+    point_flux_density(cf, &I, t, loc);
+    to_global(T, loc, out);
+    return 0;
+}
+
+int or_maxwell_moments(const or_config *cf, const double W[5], double out[54])
+{
+    maxw_t g;
+    if (maxwellian(cf, W, &g)) return -1;
+    for (int k = 0; k < 10; ++k) {
+        out[k] = g.mu[k];
+        out[10 + k] = g.mup[k];
+        out[20 + k] = g.mun[k];
+        out[30 + k] = g.mv[k];
+        out[40 + k] = g.mw[k];
+    }
+    for (int k = 0; k < 4; ++k) out[50 + k] = g.mx[k];
+    return 0;
+}
+
+/* ======================================================================== */
+/* face terms and the two-stage update (Secs. 2.1, 2.3, 3)                  */
+/* ======================================================================== */
+
+static void quad_from_coef(const double *coef, int64_t n, int64_t i, int q, qpoly_t *p)
+{
+    const double *o = coef + (size_t)(10 * q) * n + i;
+    p->c0 = o[0];
+    for (int d = 0; d < 3; ++d) p->G[d] = o[(1 + d) * n];
+    for (int k = 0; k < 6; ++k) p->H[k] = o[(4 + k) * n];
+}
+
+static int face_terms(or_ctx *c, const double *coef, double dt, double *out)
+{
+    int64_t n = c->nc, nf = c->nf;
+    int err = 0;
+#pragma omp parallel for schedule(static) reduction(| : err)
+    for (int64_t f = 0; f < nf; ++f) {
+        int64_t L = c->fcell[f][0], R = c->fcell[f][1];
+        double acc[20];
+        for (int k = 0; k < 20; ++k) acc[k] = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            double rl[3], rr[3];
+            for (int d = 0; d < 3; ++d) {
+                rl[d] = c->fgp[f][q][d] - c->cen[L][d];
+                rr[d] = c->fgp[f][q][d] - c->fshift[f][d] - (R >= 0 ? c->cen[R][d] : 0.0);
+            }
+            double Wl[5], gWl[15], Wr[5], gWr[15];
+            for (int k = 0; k < 5; ++k) {
+                qpoly_t p;
+                quad_from_coef(coef, n, L, k, &p);
+                Wl[k] = quad_eval(&p, rl);
+                quad_grad(&p, rl, gWl + 3 * k);
+                if (R >= 0) {
+                    quad_from_coef(coef, n, R, k, &p);
+                    Wr[k] = quad_eval(&p, rr);
+                    quad_grad(&p, rr, gWr + 3 * k);
+                }
+            }
+            if (R < 0) { err |= 1; continue; } /* walls: not in this oracle yet */
+            double o[20];
+            if (gks_point(&c->cfg, c->fnorm[f], Wl, gWl, Wr, gWr, dt, o)) { err |= 1; continue; }
+            /* eq. linear-system: F = (4 F(dt/2) - F(dt)) / dt,
+             * dF/dt = 4 (F(dt) - 2 F(dt/2)) / dt^2 */
+            double w = FQ_W[q] * c->farea[f];
+            for (int k = 0; k < 5; ++k) {
+                acc[k] += w * (4.0 * o[5 + k] - o[k]) / dt;
+                acc[5 + k] += w * 4.0 * (o[k] - 2.0 * o[5 + k]) / (dt * dt);
+                acc[10 + k] += w * o[10 + k];
+                acc[15 + k] += w * o[15 + k];
+            }
+        }
+        for (int k = 0; k < 20; ++k) out[(size_t)k * nf + f] = acc[k];
+    }
+    return err ? -1 : 0;
+}
+
+int or_face_terms(or_ctx *c, const double *W, const double *gW, double dt, double *out)
+{
+    or_reconstruct(c, W, gW, c->coef, c->flag, NULL);
+    return face_terms(c, c->coef, dt, out);
+}
+
+/* eq. flux-operator for every cell, gathered in serial face order:
+ * L = -(1/|Omega|) sum (+-) |Gamma| sum_k w_k F_k, same for dL/dt, and the
+ * Gauss-theorem gradient (eq. gauss-formula) of interface values Wf[5][nf] */
+static void gather(const or_ctx *c, const double *ft, const double *Wf, double *L, double *Lt,
+                   double *grad)
+{
+    int64_t n = c->nc, nf = c->nf;
+    if (L) memset(L, 0, sizeof(double) * 5 * n);
+    if (Lt) memset(Lt, 0, sizeof(double) * 5 * n);
+    if (grad) memset(grad, 0, sizeof(double) * 15 * n);
+    for (int64_t f = 0; f < nf; ++f) {
+        int64_t side[2] = {c->fcell[f][0], c->fcell[f][1]};
+        for (int s = 0; s < 2; ++s) {
+            int64_t i = side[s];
+            if (i < 0) continue;
+            double sg = s == 0 ? 1.0 : -1.0;
+            for (int q = 0; q < 5; ++q) {
+                if (L) L[q * n + i] -= sg * ft[(size_t)q * nf + f];
+                if (Lt) Lt[q * n + i] -= sg * ft[(size_t)(5 + q) * nf + f];
+                if (grad)
+                    for (int d = 0; d < 3; ++d)
+                        grad[(3 * q + d) * n + i] += sg * Wf[(size_t)q * nf + f] * c->fnorm[f][d];
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double iv = 1.0 / c->vol[i];
+        for (int q = 0; q < 5; ++q) {
+            if (L) L[q * n + i] *= iv;
+            if (Lt) Lt[q * n + i] *= iv;
+        }
+        for (int k = 0; k < 15 && grad; ++k) grad[k * n + i] *= iv;
+    }
+}
+
+int or_stage(or_ctx *c, int stage, double dt, double *W, double *gW)
+{
+    int64_t n = c->nc, nf = c->nf;
+    if (stage != 1 && stage != 2) return -1;
+    if (stage == 2 && !c->have_stage1) return -1;
+    or_reconstruct(c, W, gW, c->coef, c->flag, NULL);
+    if (face_terms(c, c->coef, dt, c->fterm)) return -2;
+    double *Wf = (double *)malloc(sizeof(double) * 5 * nf);
+    double *L = (double *)malloc(sizeof(double) * 5 * n);
+    double *Lt = (double *)malloc(sizeof(double) * 5 * n);
+    if (stage == 1) {
+        /* eq. step-du with a linear-in-time f: f* = (f(0) + f(dt)) / 2 */
+        for (int64_t f = 0; f < nf; ++f)
+            for (int q = 0; q < 5; ++q) {
+                double w0 = c->fterm[(size_t)(10 + q) * nf + f];
+                double w1 = c->fterm[(size_t)(15 + q) * nf + f];
+                c->FW0[(size_t)q * nf + f] = w0;
+                Wf[(size_t)q * nf + f] = 0.5 * (w0 + w1);
+            }
+        gather(c, c->fterm, Wf, L, Lt, gW);
+        /* eq. s2o4, first stage */
+        for (int64_t k = 0; k < 5 * n; ++k) {
+            c->Wn[k] = W[k];
+            c->Ln[k] = L[k];
+            c->Ltn[k] = Lt[k];
+            W[k] = W[k] + 0.5 * dt * L[k] + 0.125 * dt * dt * Lt[k];
+        }
+        c->have_stage1 = 1;
+    } else {
+        /* f^{n+1} = f^n + dt f_t*, f_t* = (f*(dt) - f*(0)) / dt */
+        for (int64_t f = 0; f < nf; ++f)
+            for (int q = 0; q < 5; ++q)
+                Wf[(size_t)q * nf + f] = c->FW0[(size_t)q * nf + f] +
+                                         c->fterm[(size_t)(15 + q) * nf + f] -
+                                         c->fterm[(size_t)(10 + q) * nf + f];
+        gather(c, c->fterm, Wf, L, Lt, gW);
+        /* eq. s2o4, second stage: only dL/dt(W*) enters */
+        for (int64_t k = 0; k < 5 * n; ++k)
+            W[k] = c->Wn[k] + dt * c->Ln[k] + dt * dt / 6.0 * (c->Ltn[k] + 2.0 * Lt[k]);
+        c->have_stage1 = 0;
+    }
+    free(Wf); free(L); free(Lt);
+    return 0;
+}
+
+int or_step(or_ctx *c, double dt, double *W, double *gW)
+{
+    int rc = or_stage(c, 1, dt, W, gW);
+    if (rc) return rc;
+    return or_stage(c, 2, dt, W, gW);
+}
+
+/* eq. time-step */
+double or_compute_dt(const or_ctx *c, const double *W, double cfl)
+{
+    int64_t n = c->nc;
+    const or_config *cf = &c->cfg;
+    double best = INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        double rho = W[i], u = W[n + i] / rho, v = W[2 * n + i] / rho, w = W[3 * n + i] / rho;
+        double p = (cf->gamma - 1.0) * (W[4 * n + i] - 0.5 * rho * (u * u + v * v + w * w));
+        double a = sqrt(cf->gamma * p / rho);
+        double s = c->dr[i] / (sqrt(u * u + v * v + w * w) + a);
+        if (s < best) best = s;
+        if (cf->viscous && cf->mu > 0.0) {
+            double nu = cf->mu / rho;
+            double sv = c->dr[i] * c->dr[i] / (3.0 * nu);
+            if (sv < best) best = sv;
+        }
+    }
+    return cfl * best;
+}
+
+void or_conservation_sums(const or_ctx *c, const double *W, double out[5])
+{
+    int64_t n = c->nc;
+    for (int q = 0; q < 5; ++q) {
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i) s += c->vol[i] * W[q * n + i];
+        out[q] = s;
+    }
+}

@@ -1,0 +1,97 @@
+/*
+ * gks_oracle.h -- test infrastructure, not part of the product.
+ *
+ * A plain, slow FP64 CPU implementation of one time step of the third-order
+ * compact gas-kinetic scheme on tetrahedral meshes (Ji, Zhao, Shyy & Xu,
+ * "Two-step multi-resolution reconstruction-based compact gas-kinetic scheme
+ * on tetrahedral mesh").  The HIP library is checked against it.  It shares
+ * no code with that library.  Only tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load it.
+ *
+ * Array layouts match the library's public interface: cell fields are
+ * component-major, W[5][n_cell] = (rho, rho u, rho v, rho w, rho E) and
+ * gW[15][n_cell] with component c, direction d at row 3c+d.
+ */
+#ifndef GKS_ORACLE_H
+#define GKS_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double gamma;     /* ratio of specific heats */
+    double K;         /* internal degrees of freedom, (5 - 3 gamma) / (gamma - 1) */
+    double mu;        /* dynamic viscosity (used when viscous != 0) */
+    double prandtl;   /* Prandtl number; 1 leaves the BGK heat flux unchanged */
+    double eps_tau;   /* epsilon of the numerical collision time (0.01) */
+    double c_tau;     /* C of the pressure-jump term (1) */
+    double eps_weno;  /* epsilon of the nonlinear weights (1e-8) */
+    double lw2[3];    /* linear weights gamma_{2,2}, gamma_{1,2}, gamma_{0,2} (sum 1) */
+    double lw1[2];    /* linear weights gamma_{1,1}, gamma_{0,1} (sum 1) */
+    int32_t viscous;  /* 0: Euler (tau = 0); 1: Navier-Stokes (tau = mu / p) */
+    int32_t nonlinear;/* 1: multi-resolution WENO weights; 0: R = P^2 (linear) */
+} or_config;
+
+typedef struct or_ctx or_ctx;
+
+/* Build the oracle's mesh and geometry.  Returns NULL on a malformed mesh. */
+or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
+                  int64_t n_cell, const int64_t *tet, int64_t n_face,
+                  const int64_t *face_vert, const int64_t *face_cell,
+                  const int32_t *face_tag, const double *face_shift);
+void or_destroy(or_ctx *ctx);
+int or_set_threads(int n);
+
+/* Geometry: volume[n], centroid[3][n], second moment about the centroid
+ * [6][n] (xx,yy,zz,xy,xz,yz, divided by the volume), inscribed radius dr[n]. */
+int or_geometry(const or_ctx *ctx, double *vol, double *cen, double *mom2, double *dr);
+/* Per-face area[nf], unit normal[3][nf] (outward from the owner),
+ * Gauss points [3 points][3][nf]. */
+int or_face_geometry(const or_ctx *ctx, double *area, double *normal, double *gp);
+
+/* Reconstruction step 1: slopes b[15][n] (component c, direction d at 3c+d). */
+int or_slopes(or_ctx *ctx, const double *W, double *b);
+/* Reconstruction step 2: final polynomial R(x) = c0 + G.r + 1/2 r^T H r about
+ * the centroid, coef[50][n] = per component (c0, Gx, Gy, Gz, Hxx, Hyy, Hzz,
+ * Hxy, Hxz, Hyz); flag[n] = 1 where the positivity fallback fired.
+ * p2coef (optional, same layout) receives the linear P^2 fit. */
+int or_reconstruct(or_ctx *ctx, const double *W, const double *gW, double *coef,
+                   int32_t *flag, double *p2coef);
+/* Face terms for a state (W, gW) and step dt: out[20][nf] =
+ * |Gamma| sum_k w_k of (F_k (5), dF_k/dt (5), W_k(0) (5), W_k(dt) (5)),
+ * in the global frame, normal outward from the owner. */
+int or_face_terms(or_ctx *ctx, const double *W, const double *gW, double dt, double *out);
+
+/* One stage of the two-stage fourth-order step, in place on (W, gW).
+ * Stage 1 expects W^n and leaves W*; stage 2 expects W* and leaves W^{n+1}. */
+int or_stage(or_ctx *ctx, int stage, double dt, double *W, double *gW);
+int or_step(or_ctx *ctx, double dt, double *W, double *gW);
+double or_compute_dt(const or_ctx *ctx, const double *W, double cfl);
+void or_conservation_sums(const or_ctx *ctx, const double *W, double out[5]);
+
+/* Gas-kinetic solver at one interface point, global frame.  n: unit normal,
+ * Wl/Wr: states, gWl/gWr[15] gradients (3c+d).  out[20] = F(dt), F(dt/2)
+ * (time integrals of the flux density), W(0), W(dt). */
+int or_point_flux(const or_config *cfg, const double n[3], const double Wl[5],
+                  const double gWl[15], const double Wr[5], const double gWr[15],
+                  double dt, double out[20]);
+/* Flux density F(t) (not integrated) at the same point, out[5]. */
+int or_point_flux_density(const or_config *cfg, const double n[3], const double Wl[5],
+                          const double gWl[15], const double Wr[5], const double gWr[15],
+                          double dt, double t, double out[5]);
+/* Normalised velocity moments of the Maxwellian of W (local frame as given):
+ * out[0..9] <u^k>, out[10..19] <u^k>_{u>0}, out[20..29] <u^k>_{u<0},
+ * out[30..39] <v^k>, out[40..49] <w^k>, out[50..53] <xi^{2k}>. */
+int or_maxwell_moments(const or_config *cfg, const double W[5], double out[54]);
+/* Five-point volume rule and three-point face rule, as used (reference
+ * elements): points[5][3] weights[5]; points[3][2] weights[3]. */
+void or_volume_rule(double pts[15], double w[5]);
+void or_face_rule(double pts[6], double w[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

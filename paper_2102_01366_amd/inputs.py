@@ -1,0 +1,299 @@
+"""Seeded synthetic inputs for the compact third-order gas-kinetic scheme.
+
+This module is shared by the HIP path, the tests and the benchmark.  It holds
+none of the scheme's arithmetic: it only builds tetrahedral meshes (a Kuhn
+split of a jittered hexahedral grid, periodic or walled), their face
+adjacency, and exact cell averages of analytic initial fields (values and
+gradients) by a high-order collapsed Gauss rule.  Nothing here computes a
+volume, a normal, a reconstruction or a flux.
+
+Array conventions (the library's C-ABI uses the same ones):
+
+* ``xyz``        float64 [n_vert, 3]
+* ``tet``        int64   [n_cell, 4]   vertex ids, positively oriented
+* ``face_vert``  int64   [n_face, 3]   vertex ids of the face as seen from the owner
+* ``face_cell``  int64   [n_face, 2]   (owner, neighbour); neighbour = -1 on a wall
+* ``face_tag``   int32   [n_face]      FACE_* below
+* ``face_shift`` float64 [n_face, 3]   translation that carries the neighbour's
+  geometry into the owner's frame (non-zero only across a periodic seam)
+
+Cell fields are component-major: ``W[5, n_cell]`` holds (rho, rho u, rho v,
+rho w, rho E) and ``gW[15, n_cell]`` holds the cell-averaged gradient, with
+component ``c`` and direction ``d`` at row ``3 c + d``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from itertools import permutations
+
+import numpy as np
+
+FACE_INTERIOR = 0
+FACE_PERIODIC = 1
+FACE_SLIP = 2
+
+
+@dataclass
+class TetMesh:
+    xyz: np.ndarray
+    tet: np.ndarray
+    face_vert: np.ndarray
+    face_cell: np.ndarray
+    face_tag: np.ndarray
+    face_shift: np.ndarray
+    length: float
+    n: int
+    periodic: bool
+
+    @property
+    def n_cell(self) -> int:
+        return int(self.tet.shape[0])
+
+    @property
+    def n_face(self) -> int:
+        return int(self.face_vert.shape[0])
+
+    @property
+    def n_vert(self) -> int:
+        return int(self.xyz.shape[0])
+
+
+def _kuhn_local_tets():
+    """Six tetrahedra of the unit cube sharing the (0,0,0)-(1,1,1) diagonal,
+    one per axis permutation, as corner offsets, all positively oriented."""
+    out = []
+    for perm in permutations(range(3)):
+        c = [np.zeros(3, dtype=np.int64)]
+        for ax in perm:
+            nxt = c[-1].copy()
+            nxt[ax] += 1
+            c.append(nxt)
+        c = np.array(c)
+        det = np.linalg.det((c[1:] - c[0]).astype(float))
+        if det < 0:
+            c[[1, 2]] = c[[2, 1]]
+        out.append(c)
+    return np.array(out)  # [6, 4, 3]
+
+
+def kuhn_cube_mesh(n: int, length: float = 1.0, jitter: float = 0.1, seed: int = 0,
+                   periodic: bool = True) -> TetMesh:
+    """Cube [0, length]^3 split into n^3 hexahedra, each into 6 Kuhn tetrahedra.
+
+    Vertices are displaced by iid U(-jitter h, jitter h) per axis (numpy
+    ``default_rng(seed)``, PCG64), h = length / n.  On a periodic mesh every
+    vertex is jittered and periodic images share one displacement.  On a
+    walled mesh, boundary vertices only slide tangentially.
+    """
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    h = length / n
+    rng = np.random.default_rng(seed)
+    g = np.arange(n + 1)
+    I, J, K = np.meshgrid(g, g, g, indexing="ij")
+    grid = np.stack([I, J, K], axis=-1).reshape(-1, 3)  # vertex id -> grid index
+    if periodic:
+        disp = rng.uniform(-jitter * h, jitter * h, size=(n, n, n, 3))
+        wrapped = grid % n
+        d = disp[wrapped[:, 0], wrapped[:, 1], wrapped[:, 2]]
+    else:
+        disp = rng.uniform(-jitter * h, jitter * h, size=(n + 1, n + 1, n + 1, 3))
+        d = disp.reshape(-1, 3).copy()
+        on_wall = (grid == 0) | (grid == n)
+        d[on_wall] = 0.0
+        wrapped = grid
+    xyz = (grid * length) / n + d
+
+    def vid(ijk):
+        return (ijk[..., 0] * (n + 1) + ijk[..., 1]) * (n + 1) + ijk[..., 2]
+
+    local = _kuhn_local_tets()  # [6,4,3]
+    hexes = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"),
+                     axis=-1).reshape(-1, 3)
+    corners = hexes[:, None, None, :] + local[None, :, :, :]  # [n^3, 6, 4, 3]
+    tet = vid(corners).reshape(-1, 4).astype(np.int64)
+    nc = tet.shape[0]
+
+    # all cell faces: face opposite local vertex a
+    opp = np.array([[1, 2, 3], [0, 2, 3], [0, 1, 3], [0, 1, 2]])
+    cf = tet[:, opp]  # [nc, 4, 3] unwrapped vertex ids
+    nw = n if periodic else n + 1
+    wg = wrapped  # vertex id -> wrapped grid index
+    wid = (wg[:, 0] * nw + wg[:, 1]) * nw + wg[:, 2]
+    cfw = np.sort(wid[cf], axis=-1)  # [nc,4,3]
+    M = np.int64(nw ** 3)
+    key = (cfw[..., 0] * M + cfw[..., 1]) * M + cfw[..., 2]
+    key = key.reshape(-1)
+    owner_cell = np.repeat(np.arange(nc, dtype=np.int64), 4)
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    same_next = np.zeros(ks.shape[0], dtype=bool)
+    same_next[:-1] = ks[:-1] == ks[1:]
+    if np.any(same_next[:-1] & same_next[1:]):
+        raise RuntimeError("a face is shared by more than two cells")
+    pair_first = np.nonzero(same_next)[0]
+    paired = np.zeros(ks.shape[0], dtype=bool)
+    paired[pair_first] = True
+    paired[pair_first + 1] = True
+    single = np.nonzero(~paired)[0]
+    if periodic and single.size:
+        raise RuntimeError("unmatched face on a periodic mesh")
+
+    a_idx = order[pair_first]
+    b_idx = order[pair_first + 1]
+    ca, cb = owner_cell[a_idx], owner_cell[b_idx]
+    swap = ca > cb
+    own_idx = np.where(swap, b_idx, a_idx)
+    nb_idx = np.where(swap, a_idx, b_idx)
+    own = owner_cell[own_idx]
+    nb = owner_cell[nb_idx]
+    fv_own = cf.reshape(-1, 3)[own_idx]
+    fv_nb = cf.reshape(-1, 3)[nb_idx]
+
+    # periodic shift: match the owner's first face vertex inside the neighbour's face
+    w0 = wid[fv_own[:, 0]]
+    match = wid[fv_nb] == w0[:, None]
+    k0 = np.argmax(match, axis=1)
+    v_nb = fv_nb[np.arange(fv_nb.shape[0]), k0]
+    dg = grid[fv_own[:, 0]] - grid[v_nb]
+    if np.any((dg != 0) & (np.abs(dg) != n)):
+        raise RuntimeError("inconsistent periodic face pairing")
+    shift = (dg // n).astype(np.float64) * length
+    tag = np.where(np.any(dg != 0, axis=1), FACE_PERIODIC, FACE_INTERIOR).astype(np.int32)
+
+    face_vert = fv_own
+    face_cell = np.stack([own, nb], axis=1)
+    face_shift = shift
+    face_tag = tag
+    if single.size:
+        s_idx = order[single]
+        face_vert = np.concatenate([face_vert, cf.reshape(-1, 3)[s_idx]])
+        face_cell = np.concatenate(
+            [face_cell, np.stack([owner_cell[s_idx], -np.ones(s_idx.size, np.int64)], axis=1)])
+        face_shift = np.concatenate([face_shift, np.zeros((s_idx.size, 3))])
+        face_tag = np.concatenate([face_tag, np.full(s_idx.size, FACE_SLIP, np.int32)])
+
+    # faces ordered by owner, then neighbour: a locality-friendly default order
+    fo = np.lexsort((face_cell[:, 1], face_cell[:, 0]))
+    return TetMesh(xyz=np.ascontiguousarray(xyz), tet=np.ascontiguousarray(tet),
+                   face_vert=np.ascontiguousarray(face_vert[fo]),
+                   face_cell=np.ascontiguousarray(face_cell[fo]),
+                   face_tag=np.ascontiguousarray(face_tag[fo]),
+                   face_shift=np.ascontiguousarray(face_shift[fo]),
+                   length=float(length), n=int(n), periodic=bool(periodic))
+
+
+# ----------------------------------------------------------------------------
+# collapsed Gauss rule on the reference tetrahedron (Duffy map of a cube rule)
+# ----------------------------------------------------------------------------
+
+def tet_rule(npts: int = 6):
+    """Barycentric-free reference points (xi, eta, zeta) and weights that sum to 1.
+
+    Gauss-Legendre on [0,1]^3 mapped by xi=a, eta=(1-a)b, zeta=(1-a)(1-b)c with
+    Jacobian (1-a)^2 (1-b); exact for polynomials of degree <= 2 npts - 3.
+    """
+    x, w = np.polynomial.legendre.leggauss(npts)
+    x = 0.5 * (x + 1.0)
+    w = 0.5 * w
+    A, B, C = np.meshgrid(x, x, x, indexing="ij")
+    WA, WB, WC = np.meshgrid(w, w, w, indexing="ij")
+    xi = A
+    eta = (1 - A) * B
+    zeta = (1 - A) * (1 - B) * C
+    wt = WA * WB * WC * (1 - A) ** 2 * (1 - B)
+    pts = np.stack([xi.ravel(), eta.ravel(), zeta.ravel()], axis=1)
+    wt = wt.ravel()
+    return pts, wt / wt.sum()
+
+
+def cell_points(mesh: TetMesh, pts: np.ndarray) -> np.ndarray:
+    """Physical points [n_cell, n_pts, 3] of reference points inside every tet."""
+    v = mesh.xyz[mesh.tet]  # [nc,4,3]
+    e = v[:, 1:, :] - v[:, :1, :]  # [nc,3,3]
+    return v[:, None, 0, :] + np.einsum("qk,ckd->cqd", pts, e)
+
+
+# ----------------------------------------------------------------------------
+# analytic fields: each returns (Q[5,...], dQ[5,3,...]) at points X[...,3]
+# ----------------------------------------------------------------------------
+
+def sine_wave_field(gamma: float = 1.4, amp: float = 0.2, length: float = 1.0,
+                    vel=(1.0, 1.0, 1.0), p: float = 1.0, t: float = 0.0):
+    """Density wave rho = 1 + amp sin(2 pi (x+y+z - (u+v+w) t) / length), uniform u, p."""
+    kk = 2.0 * np.pi / length
+    u = np.asarray(vel, dtype=float)
+
+    def f(X):
+        ph = kk * (X[..., 0] - u[0] * t + X[..., 1] - u[1] * t + X[..., 2] - u[2] * t)
+        rho = 1.0 + amp * np.sin(ph)
+        drho = amp * kk * np.cos(ph)
+        Q = np.stack([rho, rho * u[0], rho * u[1], rho * u[2],
+                      p / (gamma - 1.0) + 0.5 * rho * (u @ u)])
+        dr = np.stack([drho, drho, drho])  # d rho / dx_j, j = 0..2
+        dQ = np.stack([dr, dr * u[0], dr * u[1], dr * u[2], 0.5 * (u @ u) * dr])
+        return Q, dQ
+    return f
+
+
+def taylor_green_field(gamma: float = 1.4, mach: float = 0.1, u0: float = 1.0,
+                       rho0: float = 1.0, ell: float = 1.0):
+    """Taylor-Green vortex on [0, 2 pi ell]^3 with an isothermal start (rho = rho0 p / p0)."""
+    p0 = rho0 * u0 * u0 / (gamma * mach * mach)
+
+    def f(X):
+        x, y, z = X[..., 0] / ell, X[..., 1] / ell, X[..., 2] / ell
+        sx, cx, sy, cy, sz, cz = np.sin(x), np.cos(x), np.sin(y), np.cos(y), np.sin(z), np.cos(z)
+        u = u0 * sx * cy * cz
+        v = -u0 * cx * sy * cz
+        w = np.zeros_like(u)
+        ux, uy, uz = u0 * cx * cy * cz / ell, -u0 * sx * sy * cz / ell, -u0 * sx * cy * sz / ell
+        vx, vy, vz = u0 * sx * sy * cz / ell, -u0 * cx * cy * cz / ell, u0 * cx * sy * sz / ell
+        c2x, c2y, c2z = np.cos(2 * x), np.cos(2 * y), np.cos(2 * z)
+        k = rho0 * u0 * u0 / 16.0
+        p = p0 + k * (c2x + c2y) * (c2z + 2.0)
+        px = k * (-2.0 * np.sin(2 * x)) * (c2z + 2.0) / ell
+        py = k * (-2.0 * np.sin(2 * y)) * (c2z + 2.0) / ell
+        pz = k * (c2x + c2y) * (-2.0 * np.sin(2 * z)) / ell
+        rho = rho0 * p / p0
+        rx, ry, rz = rho0 * px / p0, rho0 * py / p0, rho0 * pz / p0
+        ke = 0.5 * (u * u + v * v)
+        kex, key, kez = u * ux + v * vx, u * uy + v * vy, u * uz + v * vz
+        Q = np.stack([rho, rho * u, rho * v, rho * w, p / (gamma - 1.0) + rho * ke])
+        dQ = np.stack([
+            np.stack([rx, ry, rz]),
+            np.stack([rx * u + rho * ux, ry * u + rho * uy, rz * u + rho * uz]),
+            np.stack([rx * v + rho * vx, ry * v + rho * vy, rz * v + rho * vz]),
+            np.stack([np.zeros_like(x)] * 3),
+            np.stack([px / (gamma - 1.0) + rx * ke + rho * kex,
+                      py / (gamma - 1.0) + ry * ke + rho * key,
+                      pz / (gamma - 1.0) + rz * ke + rho * kez]),
+        ])
+        return Q, dQ
+    return f
+
+
+def cell_averages(mesh: TetMesh, field, npts: int = 6, chunk: int = 65536):
+    """Exact (to quadrature) cell averages of a field and of its gradient.
+
+    Returns ``W[5, n_cell]`` and ``gW[15, n_cell]`` (row 3 c + d)."""
+    pts, wt = tet_rule(npts)
+    nc = mesh.n_cell
+    W = np.empty((5, nc))
+    gW = np.empty((15, nc))
+    v_all = mesh.xyz[mesh.tet]
+    for s in range(0, nc, chunk):
+        v = v_all[s:s + chunk]
+        e = v[:, 1:, :] - v[:, :1, :]
+        X = v[:, None, 0, :] + np.einsum("qk,ckd->cqd", pts, e)
+        Q, dQ = field(X)  # Q [5, c, q], dQ [5, 3, c, q]
+        W[:, s:s + chunk] = Q @ wt
+        gW[:, s:s + chunk] = (dQ @ wt).reshape(15, -1)
+    return W, gW
+
+
+def conservative_to_primitive(W: np.ndarray, gamma: float):
+    rho = W[0]
+    u = W[1:4] / rho
+    p = (gamma - 1.0) * (W[4] - 0.5 * rho * np.sum(u * u, axis=0))
+    return rho, u, p
