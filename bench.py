@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Throughput of the compact third-order gas-kinetic scheme on one MI355X.
+
+Workload: the viscous Taylor-Green vortex on the periodic cube [0, 2 pi]^3,
+32^3 hexahedra each split into 6 Kuhn tetrahedra (196,608 cells), vertices
+jittered by 5% of h (seed 1), gamma 1.4, Ma 0.1, Re 1600 (mu = 1/1600),
+Pr 0.72, CFL 0.5, third-order MR-WENO.  One "step" is the whole hot path:
+the CFL time step, then both stages (slopes, MR-WENO reconstruction,
+gas-kinetic face fluxes, cell update).  The state lives in HBM before the
+timed region starts.
+
+Prints one JSON line: cell-stage-updates/s, the roofline of the dominant
+kernel (per-kernel durations from HIP events on the library's stream inside
+the timed region) and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
+FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak, TFLOP/s
+
+# Algorithmic HBM bytes per unit of each FP64 kernel: every array element the
+# kernel needs is counted once (neighbour gathers assumed served by caches).
+#   slopes   per cell: W 5, M1 12, slopes out 15 doubles; 4 neighbour ids
+#   recon    per cell: W 5, gW 15, slopes 15, M2 144, geometry 20 doubles,
+#            4 neighbour ids; coefficients out 50 doubles, 1 flag
+#   flux     per face: 2 cell ids, 16 geometry doubles, half of each of the two
+#            cells' 50 coefficients (each cell has 4 faces and each face 2 cells,
+#            so 50 per face), out 20 (stage 1) / 10 (stage 2) doubles
+#   update   per cell: 4 face codes, 2 faces x (15 face terms + 3 normal),
+#            W 5 / W^n, L, L_t 15, 1/|Omega|; out 20 + 15 (stage 1) / 20 (stage 2)
+#   dt       per cell: W 5 + dr 1 doubles
+BYTES_PER_UNIT = {
+    "slopes": 8 * (5 + 12 + 15) + 4 * 4,
+    "reconstruct": 8 * (5 + 15 + 15 + 144 + 20 + 50) + 4 * 4 + 4,
+    "flux_stage1": 4 * 2 + 8 * (16 + 50 + 20),
+    "flux_stage2": 4 * 2 + 8 * (16 + 50 + 10),
+    "update_stage1": 4 * 4 + 8 * (2 * 18 + 5 + 1 + 35),
+    "update_stage2": 4 * 4 + 8 * (2 * 18 + 15 + 1 + 20),
+    "dt": 8 * 6,
+}
+UNIT = {"slopes": "cell", "reconstruct": "cell", "flux_stage1": "face", "flux_stage2": "face",
+        "update_stage1": "cell", "update_stage2": "cell", "dt": "cell"}
+
+
+def cpu_baseline(mesh, W, gW, cfg_kw, steps):
+    """The FP64 oracle, as it stands, on `steps` steps of the same mesh."""
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.set_threads(0)
+    orc = oracle.Oracle(mesh, oracle.make_config(**cfg_kw))
+    dt = orc.compute_dt(W, 0.5)
+    t0 = time.perf_counter()
+    Wo, gWo = W, gW
+    for _ in range(steps):
+        Wo, gWo = orc.step(dt, Wo, gWo)
+    el = time.perf_counter() - t0
+    return {"value": mesh.n_cell * 2 * steps / el, "unit": "cell-stage-updates/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{steps} step(s) = {2 * steps} stages of the full {mesh.n_cell}-cell mesh, "
+                      f"{el:.1f} s on {threads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=32, help="hexahedra per side of the mesh")
+    ap.add_argument("--cpu-baseline-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the mesh would shard by cell partition with halo exchange).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2102_01366_amd as G
+    from paper_2102_01366_amd import inputs as I
+
+    mu = 1.0 / 1600.0
+    cfg_kw = dict(viscous=True, mu=mu, prandtl=0.72)
+    mesh = I.kuhn_cube_mesh(args.n, 2 * math.pi, 0.05, 1, True)
+    W, gW = I.cell_averages(mesh, I.taylor_green_field(gamma=1.4, mach=0.1))
+    config = G.default_config(**cfg_kw)
+    solver = G.Solver(mesh, config, device="cuda:0")
+    solver.init(W, gW)
+    nc, nf = mesh.n_cell, mesh.n_face
+
+    for _ in range(args.warmup):
+        solver.step(solver.compute_dt(0.5))
+    solver.timing_read(reset=True)
+    solver.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.step(solver.compute_dt(0.5))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    solver.timing_enable(False)
+    kt = solver.timing_read(reset=True)
+    Wf, _ = solver.read_state()
+    assert np.isfinite(Wf).all()
+
+    flops_face = G.flux_op_count(config)["total"]
+    units = {"cell": nc, "face": nf}
+    kernels = {}
+    for k, (ms, cnt) in kt.items():
+        if cnt == 0:
+            continue
+        avg_s = ms / cnt * 1e-3
+        nbytes = BYTES_PER_UNIT[k] * units[UNIT[k]]
+        entry = {"avg_ms": ms / cnt, "launches": cnt, "total_ms": ms,
+                 "bytes_per_launch": nbytes, "hbm_GBs": nbytes / avg_s / 1e9}
+        if k.startswith("flux"):
+            entry["flops_per_launch"] = flops_face * nf
+            entry["fp64_TFLOPs"] = flops_face * nf / avg_s / 1e12
+        kernels[k] = entry
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    d = kernels[dom]
+    if dom.startswith("flux"):
+        roof = {"kernel": dom, "bound": "alu", "achieved": d["fp64_TFLOPs"],
+                "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": d["fp64_TFLOPs"] / FP64_VECTOR_TFLOPS, "traffic": None,
+                "work_per_launch": f"{flops_face:.0f} FP64 ops/face x {nf} faces"}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": d["hbm_GBs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": d["hbm_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                "work_per_launch": f"{BYTES_PER_UNIT[dom]} B/{UNIT[dom]} x {units[UNIT[dom]]}"}
+
+    value = nc * 2 * args.steps / elapsed
+    out = {
+        "metric": "cell-stage-updates/s",
+        "value": value,
+        "unit": "cell-stage-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"viscous Taylor-Green vortex, [0,2pi]^3 periodic, {args.n}^3 hexes "
+                               f"x 6 Kuhn tets ({nc} cells, {nf} faces), 5% jitter, Ma 0.1, "
+                               "Re 1600, Pr 0.72, CFL 0.5, third-order MR-WENO, FP64",
+                   "cells": nc, "faces": nf, "precision": "fp64"},
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh, W, gW, cfg_kw, args.cpu_baseline_steps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,281 @@
+"""MI355X (gfx950) implementation of the third-order compact gas-kinetic scheme
+on tetrahedral meshes (Ji, Zhao, Shyy & Xu, arXiv:2102.01366).
+
+The computation lives in ``libgks.so`` (HIP kernels behind the C interface of
+``include/gks.h``).  This package only marshals arguments: ``Solver`` wraps
+one library context, takes device memory and the stream from PyTorch, and
+mirrors the C entry points one to one.  There is no CPU fallback: if the
+library is missing, importing the binding raises.
+
+``paper_2102_01366_amd.inputs`` (meshes and initial fields) can be imported
+without the library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgks.so")
+
+GKS_OK = 0
+GKS_E_INVAL = -1
+GKS_E_MESH = -2
+GKS_E_NONPHYSICAL = -3
+GKS_E_ORDER = -4
+GKS_E_DEVICE = -5
+GKS_E_STATE = -6
+GKS_E_NOMEM = -7
+
+GKS_FP64 = 0
+GKS_FP32_BULK = 1
+
+# names of every function the C interface declares (include/gks.h)
+EXPORTS = ("gks_default_config", "gks_create", "gks_destroy", "gks_set_stream",
+           "gks_mesh_upload", "gks_workspace_bytes", "gks_bind_workspace", "gks_init",
+           "gks_compute_dt", "gks_stage", "gks_step", "gks_read_state",
+           "gks_conservation_sums", "gks_debug_reconstruct", "gks_debug_face_terms",
+           "gks_timing_enable", "gks_timing_read", "gks_flux_op_count", "gks_last_error",
+           "gks_strerror")
+
+KERNELS = ("slopes", "reconstruct", "flux_stage1", "flux_stage2", "update_stage1",
+           "update_stage2", "dt")
+
+
+class GksError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("mu", ctypes.c_double),
+                ("prandtl", ctypes.c_double), ("eps_tau", ctypes.c_double),
+                ("c_tau", ctypes.c_double), ("eps_weno", ctypes.c_double),
+                ("lw2", ctypes.c_double * 3), ("lw1", ctypes.c_double * 2),
+                ("viscous", ctypes.c_int32), ("nonlinear", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("n_vert", ctypes.c_int64), ("xyz", ctypes.c_void_p),
+                ("n_cell", ctypes.c_int64), ("tet", ctypes.c_void_p),
+                ("n_face", ctypes.c_int64), ("face_vert", ctypes.c_void_p),
+                ("face_cell", ctypes.c_void_p), ("face_tag", ctypes.c_void_p),
+                ("face_shift", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgks.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libgks.so not found at {path}; build it with "
+                          "`python -m paper_2102_01366_amd.build`")
+    import torch  # noqa: F401  (loads the HIP runtime the library links against)
+    L = ctypes.CDLL(path)
+    P, I32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    S = ctypes.c_int32
+    sig = {
+        "gks_default_config": (None, [P]),
+        "gks_create": (S, [P, P]),
+        "gks_destroy": (None, [P]),
+        "gks_set_stream": (S, [P, P]),
+        "gks_mesh_upload": (S, [P, P]),
+        "gks_workspace_bytes": (S, [P, P]),
+        "gks_bind_workspace": (S, [P, P, ctypes.c_size_t]),
+        "gks_init": (S, [P, P, P, I32]),
+        "gks_compute_dt": (S, [P, D, P]),
+        "gks_stage": (S, [P, I32, D]),
+        "gks_step": (S, [P, D]),
+        "gks_read_state": (S, [P, P, P, I32]),
+        "gks_conservation_sums": (S, [P, P]),
+        "gks_debug_reconstruct": (S, [P, P, P, P, I32]),
+        "gks_debug_face_terms": (S, [P, D, P, I32]),
+        "gks_timing_enable": (S, [P, I32]),
+        "gks_timing_read": (S, [P, P, P, I32]),
+        "gks_flux_op_count": (S, [P, P]),
+        "gks_last_error": (ctypes.c_char_p, [P]),
+        "gks_strerror": (ctypes.c_char_p, [S]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def default_config(**kw) -> Config:
+    """The paper's defaults (gks_default_config), overridden by keywords;
+    ``lw2``/``lw1`` take ratios."""
+    L = load_library()
+    c = Config()
+    L.gks_default_config(ctypes.byref(c))
+    for k, v in kw.items():
+        if k in ("lw2", "lw1"):
+            arr = getattr(c, k)
+            for i, x in enumerate(v):
+                arr[i] = float(x)
+        elif k in ("viscous", "nonlinear"):
+            setattr(c, k, 1 if v else 0)
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def flux_op_count(config: Config | None = None) -> dict:
+    """Algorithmic operations of the flux kernel per face (host-side count)."""
+    L = load_library()
+    c = config if config is not None else default_config()
+    out = (ctypes.c_double * 4)()
+    st = L.gks_flux_op_count(ctypes.byref(c), out)
+    if st != GKS_OK:
+        raise GksError(st, "gks_flux_op_count failed")
+    d = {"add": out[0], "mul": out[1], "div": out[2], "special": out[3]}
+    d["total"] = sum(out)
+    return d
+
+
+def _ptr(a) -> int:
+    """Address of a numpy array or a torch tensor."""
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+class Solver:
+    """One libgks context bound to a mesh, a torch-allocated workspace and the
+    current torch stream of ``device``."""
+
+    def __init__(self, mesh, config: Config | None = None, device="cuda", stream=None):
+        import torch
+        self._torch = torch
+        self.L = load_library()
+        self.config = config if config is not None else default_config()
+        self.device = torch.device(device)
+        self._h = ctypes.c_void_p()
+        self._check(self.L.gks_create(ctypes.byref(self.config), ctypes.byref(self._h)), "create")
+        self.nc = int(mesh.n_cell)
+        self.nf = int(mesh.n_face)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._check(self.L.gks_set_stream(self._h, ctypes.c_void_p(self.stream.cuda_stream)),
+                    "set_stream")
+        keep = [np.ascontiguousarray(mesh.xyz, np.float64),
+                np.ascontiguousarray(mesh.tet, np.int64),
+                np.ascontiguousarray(mesh.face_vert, np.int64),
+                np.ascontiguousarray(mesh.face_cell, np.int64),
+                np.ascontiguousarray(mesh.face_tag, np.int32),
+                np.ascontiguousarray(mesh.face_shift, np.float64)]
+        m = _Mesh(mesh.n_vert, keep[0].ctypes.data, self.nc, keep[1].ctypes.data, self.nf,
+                  keep[2].ctypes.data, keep[3].ctypes.data, keep[4].ctypes.data,
+                  keep[5].ctypes.data)
+        self._check(self.L.gks_mesh_upload(self._h, ctypes.byref(m)), "mesh_upload")
+        nbytes = ctypes.c_size_t()
+        self._check(self.L.gks_workspace_bytes(self._h, ctypes.byref(nbytes)), "workspace_bytes")
+        self.workspace_bytes = int(nbytes.value)
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        self._check(self.L.gks_bind_workspace(self._h, ctypes.c_void_p(self.workspace.data_ptr()),
+                                              self.workspace_bytes), "bind_workspace")
+
+    # -- plumbing ----------------------------------------------------------
+    def _check(self, status, what):
+        if status != GKS_OK:
+            msg = self.L.gks_last_error(self._h) if self._h else b""
+            name = self.L.gks_strerror(status).decode()
+            raise GksError(status, f"gks_{what}: {name}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.L.gks_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a):
+        return (not isinstance(a, np.ndarray)) and a.is_cuda
+
+    # -- the C interface -----------------------------------------------------
+    def init(self, W, gW):
+        """W[5, n], gW[15, n]: float64 numpy arrays or CUDA tensors."""
+        on_dev = self._dev(W)
+        if on_dev:
+            W = W.contiguous().to(self._torch.float64)
+            gW = gW.contiguous().to(self._torch.float64)
+        else:
+            W = np.ascontiguousarray(W, np.float64)
+            gW = np.ascontiguousarray(gW, np.float64)
+        if tuple(W.shape) != (5, self.nc) or tuple(gW.shape) != (15, self.nc):
+            raise ValueError("W must be [5, n_cell] and gW [15, n_cell]")
+        self._check(self.L.gks_init(self._h, ctypes.c_void_p(_ptr(W)), ctypes.c_void_p(_ptr(gW)),
+                                    1 if on_dev else 0), "init")
+
+    def compute_dt(self, cfl: float) -> float:
+        dt = ctypes.c_double()
+        self._check(self.L.gks_compute_dt(self._h, float(cfl), ctypes.byref(dt)), "compute_dt")
+        return float(dt.value)
+
+    def stage(self, stage: int, dt: float):
+        self._check(self.L.gks_stage(self._h, int(stage), float(dt)), "stage")
+
+    def step(self, dt: float):
+        self._check(self.L.gks_step(self._h, float(dt)), "step")
+
+    def read_state(self, device: bool = False):
+        if device:
+            t = self._torch
+            W = t.empty((5, self.nc), dtype=t.float64, device=self.device)
+            gW = t.empty((15, self.nc), dtype=t.float64, device=self.device)
+        else:
+            W = np.empty((5, self.nc))
+            gW = np.empty((15, self.nc))
+        self._check(self.L.gks_read_state(self._h, ctypes.c_void_p(_ptr(W)),
+                                          ctypes.c_void_p(_ptr(gW)), 1 if device else 0),
+                    "read_state")
+        return W, gW
+
+    def conservation_sums(self):
+        out = np.empty(5)
+        self._check(self.L.gks_conservation_sums(self._h, ctypes.c_void_p(out.ctypes.data)),
+                    "conservation_sums")
+        return out
+
+    def debug_reconstruct(self):
+        b = np.empty((15, self.nc))
+        coef = np.empty((50, self.nc))
+        flag = np.empty(self.nc, np.int32)
+        self._check(self.L.gks_debug_reconstruct(self._h, ctypes.c_void_p(b.ctypes.data),
+                                                 ctypes.c_void_p(coef.ctypes.data),
+                                                 ctypes.c_void_p(flag.ctypes.data), 0),
+                    "debug_reconstruct")
+        return b, coef, flag
+
+    def timing_enable(self, on: bool = True):
+        self._check(self.L.gks_timing_enable(self._h, 1 if on else 0), "timing_enable")
+
+    def timing_read(self, reset: bool = True):
+        """{kernel: (total ms, launches)} accumulated since the last reset."""
+        ms = np.zeros(len(KERNELS))
+        cnt = np.zeros(len(KERNELS), np.int64)
+        self._check(self.L.gks_timing_read(self._h, ctypes.c_void_p(ms.ctypes.data),
+                                           ctypes.c_void_p(cnt.ctypes.data), 1 if reset else 0),
+                    "timing_read")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNELS)}
+
+    def debug_face_terms(self, dt: float):
+        out = np.empty((20, self.nf))
+        self._check(self.L.gks_debug_face_terms(self._h, float(dt),
+                                                ctypes.c_void_p(out.ctypes.data), 0),
+                    "debug_face_terms")
+        return out

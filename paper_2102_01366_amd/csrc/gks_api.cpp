@@ -1,0 +1,954 @@
+// Host side of libgks: the C interface of include/gks.h.
+//
+// Mesh upload forms, in FP64 on the host, everything the kernels stream per
+// stage: cell volumes, centroids and second moments (closed forms for a
+// straight tetrahedron), the inscribed-sphere estimate (Sec. 5), face
+// normals, areas and Gauss points (Sec. 2.1), and per cell the step-1
+// least-squares operator (3x4, Sec. 4.3) and the step-2 constrained
+// least-squares operator (9x16, Sec. 4.1).  The operators are formed with
+// Householder QR (pseudo-inverse for step 1, null-space method for step 2),
+// in coordinates centred at the cell centroid and scaled by |Omega|^(1/3).
+// Cells are renumbered along a Morton curve of their centroids and faces are
+// sorted by their lower internal cell, so that neighbouring threads touch
+// neighbouring memory.
+#include "../../include/gks.h"
+#include "gks_internal.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using gks::DevMesh;
+using gks::DevState;
+
+struct gks_ctx {
+    gks_config cfg{};
+    gks::Params par{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool device_failed = false;
+    // mesh, prepared on the host in device layout
+    bool have_mesh = false;
+    int nc = 0, nf = 0;
+    std::vector<int> cperm, fperm;  // internal -> caller
+    std::vector<int> nbr, cface, fcell;
+    std::vector<double> M1, M2, geo, fgeo;
+    // workspace
+    bool bound = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    DevMesh dm{};
+    DevState ds{};
+    int *d_cperm = nullptr, *d_fperm = nullptr;
+    double *staging = nullptr;
+    int *istaging = nullptr;
+    bool have_state = false;
+    bool stage1_done = false;
+    double stage1_dt = 0.0;
+    // per-kernel event timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<int> ev_kernel;  // kernel id of each recorded (start, stop) pair
+    double t_ms[GKS_NKERNELS] = {0};
+    int64_t t_cnt[GKS_NKERNELS] = {0};
+    ~gks_ctx()
+    {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+gks_status fail(gks_ctx *c, gks_status st, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            (ctx)->device_failed = true;                                                    \
+            return fail((ctx), GKS_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+        }                                                                                   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// small dense linear algebra (row-major)
+// ---------------------------------------------------------------------------
+
+// Householder QR of an m x n matrix (m >= n): A is overwritten by R in its
+// upper triangle; Q (m x m) is returned explicitly.
+void householder_qr(int m, int n, double *A, double *Q)
+{
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) Q[i * m + j] = i == j ? 1.0 : 0.0;
+    std::vector<double> v(m);
+    for (int k = 0; k < n; ++k) {
+        double nrm = 0.0;
+        for (int i = k; i < m; ++i) nrm += A[i * n + k] * A[i * n + k];
+        nrm = std::sqrt(nrm);
+        if (nrm == 0.0) continue;
+        const double alpha = A[k * n + k] > 0 ? -nrm : nrm;
+        for (int i = 0; i < m; ++i) v[i] = 0.0;
+        for (int i = k; i < m; ++i) v[i] = A[i * n + k];
+        v[k] -= alpha;
+        double vv = 0.0;
+        for (int i = k; i < m; ++i) vv += v[i] * v[i];
+        if (vv == 0.0) continue;
+        // A <- (I - 2 v v^T / vv) A
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int i = k; i < m; ++i) s += v[i] * A[i * n + j];
+            s *= 2.0 / vv;
+            for (int i = k; i < m; ++i) A[i * n + j] -= s * v[i];
+        }
+        // Q <- Q (I - 2 v v^T / vv)
+        for (int i = 0; i < m; ++i) {
+            double s = 0.0;
+            for (int j = k; j < m; ++j) s += Q[i * m + j] * v[j];
+            s *= 2.0 / vv;
+            for (int j = k; j < m; ++j) Q[i * m + j] -= s * v[j];
+        }
+    }
+}
+
+// X = R^{-1} B for upper-triangular R (n x n, leading dimension ldr), B n x k
+bool upper_solve(int n, const double *R, int ldr, double *B, int k)
+{
+    for (int i = n - 1; i >= 0; --i) {
+        const double d = R[i * ldr + i];
+        if (d == 0.0) return false;
+        for (int j = 0; j < k; ++j) {
+            double s = B[i * k + j];
+            for (int l = i + 1; l < n; ++l) s -= R[i * ldr + l] * B[l * k + j];
+            B[i * k + j] = s / d;
+        }
+    }
+    return true;
+}
+
+// X = R^{-T} B for upper-triangular R (n x n), B n x k
+bool lower_solve_transposed(int n, const double *R, int ldr, double *B, int k)
+{
+    for (int i = 0; i < n; ++i) {
+        const double d = R[i * ldr + i];
+        if (d == 0.0) return false;
+        for (int j = 0; j < k; ++j) {
+            double s = B[i * k + j];
+            for (int l = 0; l < i; ++l) s -= R[l * ldr + i] * B[l * k + j];
+            B[i * k + j] = s / d;
+        }
+    }
+    return true;
+}
+
+// pseudo-inverse of a full-column-rank m x n matrix (n x m result)
+bool pseudo_inverse(int m, int n, const double *A, double *Ap)
+{
+    std::vector<double> R(A, A + m * n), Q(m * m);
+    householder_qr(m, n, R.data(), Q.data());
+    // Ap = R^{-1} Q1^T
+    std::vector<double> B(n * m);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < m; ++j) B[i * m + j] = Q[j * m + i];
+    if (!upper_solve(n, R.data(), n, B.data(), m)) return false;
+    std::copy(B.begin(), B.end(), Ap);
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// geometry helpers
+// ---------------------------------------------------------------------------
+inline void sub3(const double *a, const double *b, double *o)
+{
+    o[0] = a[0] - b[0];
+    o[1] = a[1] - b[1];
+    o[2] = a[2] - b[2];
+}
+
+inline void cross3(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+uint64_t spread_bits(uint64_t x)
+{
+    x &= 0x1fffff;
+    x = (x | x << 32) & 0x1f00000000ffffULL;
+    x = (x | x << 16) & 0x1f0000ff0000ffULL;
+    x = (x | x << 8) & 0x100f00f00f00f00fULL;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+    x = (x | x << 2) & 0x1249249249249249ULL;
+    return x;
+}
+
+// quadratic basis of the step-2 fit, in scaled coordinates y about the
+// centroid: y_x, y_y, y_z, y_x^2, y_y^2, y_z^2, y_x y_y, y_x y_z, y_y y_z
+const int QA[6] = {0, 1, 2, 0, 0, 1};
+const int QB[6] = {0, 1, 2, 1, 2, 2};
+
+struct Layout {
+    size_t off[40];
+    size_t total;
+};
+
+enum Slot {
+    S_NBR, S_CFACE, S_M1, S_M2, S_GEO, S_FCELL, S_FGEO, S_W, S_GW, S_WN, S_LN, S_LTN, S_SLOPES,
+    S_COEF, S_FLAG, S_FF, S_FT, S_FW0, S_FWS, S_RED, S_NONPHYS, S_CPERM, S_FPERM, S_STAGING,
+    S_ISTAGING, S_COUNT
+};
+
+Layout make_layout(size_t nc, size_t nf)
+{
+    const size_t sz[S_COUNT] = {
+        4 * nc * sizeof(int), 4 * nc * sizeof(int), 12 * nc * 8, 144 * nc * 8,
+        (size_t)gks::NGEO * nc * 8, 2 * nf * sizeof(int), (size_t)gks::NFGEO * nf * 8,
+        5 * nc * 8, 15 * nc * 8, 5 * nc * 8, 5 * nc * 8, 5 * nc * 8, 15 * nc * 8, 50 * nc * 8,
+        nc * sizeof(int), 5 * nf * 8, 5 * nf * 8, 5 * nf * 8, 5 * nf * 8,
+        (8 + 5 * (size_t)gks::kRedBlocks) * 8, 64, nc * sizeof(int), nf * sizeof(int),
+        std::max(50 * nc, 20 * nf) * 8, nc * sizeof(int)};
+    Layout L;
+    size_t o = 0;
+    for (int k = 0; k < S_COUNT; ++k) {
+        L.off[k] = o;
+        o += (sz[k] + 255) & ~size_t(255);
+    }
+    L.total = o;
+    return L;
+}
+
+bool config_ok(const gks_config *c, std::string &why)
+{
+    if (!(c->gamma > 1.0)) { why = "gamma must be > 1"; return false; }
+    if (!(c->mu >= 0.0)) { why = "mu must be >= 0"; return false; }
+    if (!(c->prandtl > 0.0)) { why = "prandtl must be > 0"; return false; }
+    if (!(c->eps_tau >= 0.0) || !(c->c_tau >= 0.0) || !(c->eps_weno > 0.0)) {
+        why = "collision-time and WENO epsilons must be non-negative (eps_weno > 0)";
+        return false;
+    }
+    for (int k = 0; k < 3; ++k)
+        if (!(c->lw2[k] > 0.0)) { why = "linear weights must be positive"; return false; }
+    for (int k = 0; k < 2; ++k)
+        if (!(c->lw1[k] > 0.0)) { why = "linear weights must be positive"; return false; }
+    if (c->viscous != 0 && c->viscous != 1) { why = "viscous must be 0 or 1"; return false; }
+    if (c->nonlinear != 0 && c->nonlinear != 1) { why = "nonlinear must be 0 or 1"; return false; }
+    if (c->precision != GKS_FP64) { why = "only GKS_FP64 is available in this build"; return false; }
+    if (c->reserved != 0) { why = "reserved must be 0"; return false; }
+    return true;
+}
+
+}  // namespace
+
+// Record an event on the context's stream when timing is on.
+static gks_status mark(gks_ctx *c)
+{
+    if (!c->timing) return GKS_OK;
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        HIP_TRY(c, hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    HIP_TRY(c, hipEventRecord(c->ev_pool[c->ev_used++], c->stream));
+    return GKS_OK;
+}
+
+// Launch one kernel group, bracketed by timing events when enabled.
+template <typename F>
+static gks_status timed(gks_ctx *c, int kernel, F &&launch)
+{
+    gks_status st = mark(c);
+    if (st) return st;
+    HIP_TRY(c, launch());
+    if ((st = mark(c))) return st;
+    if (c->timing) c->ev_kernel.push_back(kernel);
+    return GKS_OK;
+}
+
+// ===========================================================================
+// C interface
+// ===========================================================================
+extern "C" {
+
+void gks_default_config(gks_config *cfg)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->gamma = 1.4;
+    cfg->mu = 0.0;
+    cfg->prandtl = 1.0;
+    cfg->eps_tau = 0.01;
+    cfg->c_tau = 1.0;
+    cfg->eps_weno = 1e-8;
+    cfg->lw2[0] = 100.0;
+    cfg->lw2[1] = 10.0;
+    cfg->lw2[2] = 1.0;
+    cfg->lw1[0] = 10.0;
+    cfg->lw1[1] = 1.0;
+    cfg->viscous = 0;
+    cfg->nonlinear = 1;
+    cfg->precision = GKS_FP64;
+}
+
+gks_status gks_create(const gks_config *cfg, gks_ctx **out)
+{
+    if (!cfg || !out) return GKS_E_INVAL;
+    *out = nullptr;
+    std::string why;
+    if (!config_ok(cfg, why)) return GKS_E_INVAL;
+    gks_ctx *c = new (std::nothrow) gks_ctx();
+    if (!c) return GKS_E_NOMEM;
+    c->cfg = *cfg;
+    gks::Params &p = c->par;
+    p.gamma = cfg->gamma;
+    p.K = (5.0 - 3.0 * cfg->gamma) / (cfg->gamma - 1.0);
+    p.mu = cfg->mu;
+    p.prandtl = cfg->prandtl;
+    p.eps_tau = cfg->eps_tau;
+    p.c_tau = cfg->c_tau;
+    p.eps_weno = cfg->eps_weno;
+    const double s2 = cfg->lw2[0] + cfg->lw2[1] + cfg->lw2[2];
+    const double s1 = cfg->lw1[0] + cfg->lw1[1];
+    p.g22 = cfg->lw2[0] / s2;
+    p.g12 = cfg->lw2[1] / s2;
+    p.g02 = cfg->lw2[2] / s2;
+    p.g11 = cfg->lw1[0] / s1;
+    p.g01 = cfg->lw1[1] / s1;
+    p.viscous = cfg->viscous;
+    p.nonlinear = cfg->nonlinear;
+    *out = c;
+    return GKS_OK;
+}
+
+void gks_destroy(gks_ctx *ctx) { delete ctx; }
+
+gks_status gks_set_stream(gks_ctx *ctx, void *stream)
+{
+    if (!ctx) return GKS_E_INVAL;
+    ctx->stream = (hipStream_t)stream;
+    return GKS_OK;
+}
+
+gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
+{
+    if (!c || !m) return GKS_E_INVAL;
+    if (c->bound) return fail(c, GKS_E_STATE, "a workspace is already bound; create a new context");
+    if (m->n_cell <= 0 || m->n_face <= 0 || m->n_vert <= 0 || !m->xyz || !m->tet || !m->face_vert ||
+        !m->face_cell || !m->face_tag || !m->face_shift)
+        return fail(c, GKS_E_INVAL, "empty mesh or missing array");
+    if (m->n_cell > INT_MAX / 64 || m->n_face > INT_MAX / 64)
+        return fail(c, GKS_E_INVAL, "mesh too large for 32-bit indexing");
+    const int nc = (int)m->n_cell, nf = (int)m->n_face;
+
+    // --- cells: vertices, volume, centroid -------------------------------
+    std::vector<double> cen(3 * (size_t)nc), vol(nc);
+    for (int i = 0; i < nc; ++i) {
+        double v[4][3];
+        for (int a = 0; a < 4; ++a) {
+            const int64_t id = m->tet[4 * (size_t)i + a];
+            if (id < 0 || id >= m->n_vert) return fail(c, GKS_E_MESH, "tet vertex id out of range");
+            for (int d = 0; d < 3; ++d) v[a][d] = m->xyz[3 * id + d];
+        }
+        double e1[3], e2[3], e3[3], cr[3];
+        sub3(v[1], v[0], e1);
+        sub3(v[2], v[0], e2);
+        sub3(v[3], v[0], e3);
+        cross3(e2, e3, cr);
+        const double V = std::fabs(dot3(e1, cr)) / 6.0;
+        if (!(V > 0.0) || !std::isfinite(V)) return fail(c, GKS_E_MESH, "degenerate tetrahedron");
+        vol[i] = V;
+        for (int d = 0; d < 3; ++d) cen[3 * i + d] = 0.25 * (v[0][d] + v[1][d] + v[2][d] + v[3][d]);
+    }
+
+    // --- faces: validation, incidence in caller face order ---------------
+    std::vector<int> nslots(nc, 0), slot_face(4 * (size_t)nc, -1), slot_side(4 * (size_t)nc, 0);
+    for (int f = 0; f < nf; ++f) {
+        const int64_t L = m->face_cell[2 * (size_t)f], R = m->face_cell[2 * (size_t)f + 1];
+        const int tag = m->face_tag[f];
+        if (L < 0 || L >= nc || R >= nc || R == L) return fail(c, GKS_E_MESH, "bad face_cell entry");
+        if (R < 0 || tag == GKS_FACE_SLIP)
+            return fail(c, GKS_E_MESH, "wall faces are not supported by this build");
+        if (tag != GKS_FACE_INTERIOR && tag != GKS_FACE_PERIODIC)
+            return fail(c, GKS_E_MESH, "unknown face tag");
+        for (int s = 0; s < 2; ++s) {
+            const int cell = (int)(s == 0 ? L : R);
+            if (nslots[cell] >= 4) return fail(c, GKS_E_MESH, "a cell has more than four faces");
+            slot_face[4 * (size_t)cell + nslots[cell]] = f;
+            slot_side[4 * (size_t)cell + nslots[cell]] = s;
+            ++nslots[cell];
+        }
+    }
+    for (int i = 0; i < nc; ++i)
+        if (nslots[i] != 4) return fail(c, GKS_E_MESH, "a cell does not have four faces");
+
+    // --- renumbering: Morton order of centroids --------------------------
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = 0; i < nc; ++i)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], cen[3 * i + d]);
+            hi[d] = std::max(hi[d], cen[3 * i + d]);
+        }
+    std::vector<uint64_t> key(nc);
+    for (int i = 0; i < nc; ++i) {
+        uint64_t k = 0;
+        for (int d = 0; d < 3; ++d) {
+            const double span = hi[d] - lo[d];
+            const double t = span > 0 ? (cen[3 * i + d] - lo[d]) / span : 0.0;
+            const uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, t * 2097151.0));
+            k |= spread_bits(q) << d;
+        }
+        key[i] = k;
+    }
+    std::vector<int> cperm(nc), cinv(nc);
+    std::iota(cperm.begin(), cperm.end(), 0);
+    std::stable_sort(cperm.begin(), cperm.end(), [&](int a, int b) { return key[a] < key[b]; });
+    for (int i = 0; i < nc; ++i) cinv[cperm[i]] = i;
+    std::vector<int> fkey(nf);
+    for (int f = 0; f < nf; ++f)
+        fkey[f] = std::min(cinv[m->face_cell[2 * (size_t)f]], cinv[m->face_cell[2 * (size_t)f + 1]]);
+    std::vector<int> fperm(nf), finv(nf);
+    std::iota(fperm.begin(), fperm.end(), 0);
+    std::stable_sort(fperm.begin(), fperm.end(), [&](int a, int b) { return fkey[a] < fkey[b]; });
+    for (int j = 0; j < nf; ++j) finv[fperm[j]] = j;
+
+    // --- face geometry (internal order) ----------------------------------
+    std::vector<double> fgeo((size_t)gks::NFGEO * nf);
+    std::vector<int> fcell(2 * (size_t)nf);
+    std::vector<double> farea(nf), fnrm(3 * (size_t)nf);
+    for (int j = 0; j < nf; ++j) {
+        const int f = fperm[j];
+        const int L = (int)m->face_cell[2 * (size_t)f], R = (int)m->face_cell[2 * (size_t)f + 1];
+        double x[3][3];
+        for (int a = 0; a < 3; ++a) {
+            const int64_t id = m->face_vert[3 * (size_t)f + a];
+            if (id < 0 || id >= m->n_vert) return fail(c, GKS_E_MESH, "face vertex id out of range");
+            for (int d = 0; d < 3; ++d) x[a][d] = m->xyz[3 * id + d];
+        }
+        double e1[3], e2[3], cr[3];
+        sub3(x[1], x[0], e1);
+        sub3(x[2], x[0], e2);
+        cross3(e1, e2, cr);
+        const double nrm = std::sqrt(dot3(cr, cr));
+        if (!(nrm > 0.0)) return fail(c, GKS_E_MESH, "degenerate face");
+        // Gauss points (1/6,1/6), (2/3,1/6), (1/6,2/3) of the reference triangle
+        const double gpw[3][2] = {{1.0 / 6.0, 1.0 / 6.0}, {2.0 / 3.0, 1.0 / 6.0}, {1.0 / 6.0, 2.0 / 3.0}};
+        double gp[3][3];
+        for (int k = 0; k < 3; ++k)
+            for (int d = 0; d < 3; ++d)
+                gp[k][d] = x[0][d] * (1.0 - gpw[k][0] - gpw[k][1]) + x[1][d] * gpw[k][0] +
+                           x[2][d] * gpw[k][1];
+        double out = 0.0;
+        for (int d = 0; d < 3; ++d) out += cr[d] * (gp[0][d] - cen[3 * L + d]);
+        const double sg = out > 0 ? 1.0 : -1.0;
+        for (int d = 0; d < 3; ++d) {
+            const double nd = sg * cr[d] / nrm;
+            fgeo[(size_t)(gks::F_N + d) * nf + j] = nd;
+            fnrm[3 * (size_t)f + d] = nd;
+        }
+        farea[f] = 0.5 * nrm;
+        fgeo[(size_t)gks::F_AREA * nf + j] = 0.5 * nrm;
+        for (int k = 0; k < 3; ++k)
+            for (int d = 0; d < 3; ++d)
+                fgeo[(size_t)(gks::F_RL + 3 * k + d) * nf + j] = gp[k][d] - cen[3 * L + d];
+        for (int d = 0; d < 3; ++d)
+            fgeo[(size_t)(gks::F_D + d) * nf + j] =
+                cen[3 * L + d] - (cen[3 * R + d] + m->face_shift[3 * (size_t)f + d]);
+        fcell[j] = cinv[L];
+        fcell[(size_t)nf + j] = cinv[R];
+    }
+
+    // --- cells: geometry rows, neighbours, operators (internal order) ----
+    std::vector<double> geo((size_t)gks::NGEO * nc), M1(12 * (size_t)nc), M2(144 * (size_t)nc);
+    std::vector<int> nbr(4 * (size_t)nc), cface(4 * (size_t)nc);
+    for (int ii = 0; ii < nc; ++ii) {
+        const int i = cperm[ii];
+        const double V = vol[i];
+        const double *ci = &cen[3 * (size_t)i];
+        double rv[4][3];
+        for (int a = 0; a < 4; ++a) {
+            const int64_t id = m->tet[4 * (size_t)i + a];
+            for (int d = 0; d < 3; ++d) rv[a][d] = m->xyz[3 * id + d] - ci[d];
+        }
+        // second moments about the centroid: (1/20) sum_a r_a r_a^T
+        double C[6] = {0, 0, 0, 0, 0, 0};
+        for (int a = 0; a < 4; ++a)
+            for (int k = 0; k < 6; ++k) C[k] += rv[a][QA[k]] * rv[a][QB[k]];
+        for (int k = 0; k < 6; ++k) C[k] /= 20.0;
+        double sumA = 0.0, closure[3] = {0, 0, 0};
+        double delta[4][3], Cm[4][6];
+        for (int a = 0; a < 4; ++a) {
+            const int f = slot_face[4 * (size_t)i + a], side = slot_side[4 * (size_t)i + a];
+            const int L = (int)m->face_cell[2 * (size_t)f], R = (int)m->face_cell[2 * (size_t)f + 1];
+            const int other = side == 0 ? R : L;
+            const double sgn = side == 0 ? 1.0 : -1.0;
+            sumA += farea[f];
+            for (int d = 0; d < 3; ++d) closure[d] += sgn * farea[f] * fnrm[3 * (size_t)f + d];
+            nbr[(size_t)a * nc + ii] = cinv[other];
+            cface[(size_t)a * nc + ii] = 2 * finv[f] + side;
+            // neighbour centroid next to this cell
+            for (int d = 0; d < 3; ++d) {
+                const double off = side == 0 ? m->face_shift[3 * (size_t)f + d] : -m->face_shift[3 * (size_t)f + d];
+                delta[a][d] = cen[3 * (size_t)other + d] + off - ci[d];
+            }
+            double ro[4][3];
+            for (int b = 0; b < 4; ++b) {
+                const int64_t id = m->tet[4 * (size_t)other + b];
+                for (int d = 0; d < 3; ++d) ro[b][d] = m->xyz[3 * id + d] - cen[3 * (size_t)other + d];
+            }
+            for (int k = 0; k < 6; ++k) {
+                double s = 0.0;
+                for (int b = 0; b < 4; ++b) s += ro[b][QA[k]] * ro[b][QB[k]];
+                Cm[a][k] = s / 20.0;
+            }
+        }
+        if (std::sqrt(dot3(closure, closure)) > 1e-10 * sumA)
+            return fail(c, GKS_E_MESH, "a cell surface is not closed");
+        const double h = std::cbrt(V);
+        double *g = geo.data();
+        g[(size_t)gks::G_INVVOL * nc + ii] = 1.0 / V;
+        g[(size_t)gks::G_VOL23 * nc + ii] = std::pow(V, 2.0 / 3.0);
+        g[(size_t)gks::G_VOL43 * nc + ii] = std::pow(V, 4.0 / 3.0);
+        for (int k = 0; k < 6; ++k) g[(size_t)(gks::G_C + k) * nc + ii] = C[k];
+        g[(size_t)gks::G_DR * nc + ii] = 3.0 * V / sumA;
+        for (int a = 0; a < 4; ++a)
+            for (int d = 0; d < 3; ++d) g[(size_t)(gks::G_RV + 3 * a + d) * nc + ii] = rv[a][d];
+        g[(size_t)gks::G_VOL * nc + ii] = V;
+
+        // step 1: least squares of the 4 neighbour averages, D b' = dQ, D = delta / h
+        double D[12], Dp[12];
+        for (int a = 0; a < 4; ++a)
+            for (int d = 0; d < 3; ++d) D[3 * a + d] = delta[a][d] / h;
+        if (!pseudo_inverse(4, 3, D, Dp)) return fail(c, GKS_E_MESH, "singular step-1 stencil");
+        for (int d = 0; d < 3; ++d)
+            for (int a = 0; a < 4; ++a) M1[(size_t)(4 * d + a) * nc + ii] = Dp[4 * d + a] / h;
+
+        // step 2: constrained least squares in y = (x - c) / h for the 9
+        // coefficients of the basis y^k - <y^k>_0
+        double E[4][9], A[12][9];
+        for (int a = 0; a < 4; ++a) {
+            double dl[3];
+            for (int d = 0; d < 3; ++d) dl[d] = delta[a][d] / h;
+            for (int d = 0; d < 3; ++d) E[a][d] = dl[d];
+            for (int k = 0; k < 6; ++k)
+                E[a][3 + k] = dl[QA[k]] * dl[QB[k]] + (Cm[a][k] - C[k]) / (h * h);
+            for (int j = 0; j < 3; ++j) {
+                double *row = A[3 * a + j];
+                for (int d = 0; d < 3; ++d) row[d] = j == d ? 1.0 : 0.0;
+                for (int k = 0; k < 6; ++k) {
+                    const int p = QA[k], q = QB[k];
+                    double v = 0.0;
+                    if (j == p) v += dl[q];
+                    if (j == q) v += dl[p];
+                    row[3 + k] = v;
+                }
+            }
+        }
+        // null-space method: E^T = Q [R; 0]; a = Q1 R^{-T} e + Q2 z, z = (A Q2)^+ (b - A Q1 R^{-T} e)
+        double Et[9 * 4], Q[81];
+        for (int r = 0; r < 9; ++r)
+            for (int a = 0; a < 4; ++a) Et[r * 4 + a] = E[a][r];
+        householder_qr(9, 4, Et, Q);
+        double Y[9 * 4];  // Q1 R^{-T}
+        {
+            double Rinv_t[16];  // R^{-T} I
+            for (int r = 0; r < 4; ++r)
+                for (int s = 0; s < 4; ++s) Rinv_t[r * 4 + s] = r == s ? 1.0 : 0.0;
+            if (!lower_solve_transposed(4, Et, 4, Rinv_t, 4))
+                return fail(c, GKS_E_MESH, "singular step-2 constraints");
+            for (int r = 0; r < 9; ++r)
+                for (int s = 0; s < 4; ++s) {
+                    double t = 0.0;
+                    for (int k = 0; k < 4; ++k) t += Q[r * 9 + k] * Rinv_t[k * 4 + s];
+                    Y[r * 4 + s] = t;
+                }
+        }
+        double AQ2[12 * 5], AQ2p[5 * 12];
+        for (int r = 0; r < 12; ++r)
+            for (int s = 0; s < 5; ++s) {
+                double t = 0.0;
+                for (int k = 0; k < 9; ++k) t += A[r][k] * Q[k * 9 + 4 + s];
+                AQ2[r * 5 + s] = t;
+            }
+        if (!pseudo_inverse(12, 5, AQ2, AQ2p)) return fail(c, GKS_E_MESH, "singular step-2 stencil");
+        double Mb[9 * 12], Me[9 * 4];
+        for (int r = 0; r < 9; ++r)
+            for (int s = 0; s < 12; ++s) {
+                double t = 0.0;
+                for (int k = 0; k < 5; ++k) t += Q[r * 9 + 4 + k] * AQ2p[k * 12 + s];
+                Mb[r * 12 + s] = t;
+            }
+        for (int r = 0; r < 9; ++r)
+            for (int s = 0; s < 4; ++s) {
+                double t = 0.0;
+                for (int k = 0; k < 12; ++k) {
+                    double ay = 0.0;
+                    for (int l = 0; l < 9; ++l) ay += A[k][l] * Y[l * 4 + s];
+                    t += Mb[r * 12 + k] * ay;
+                }
+                Me[r * 4 + s] = Y[r * 4 + s] - t;
+            }
+        // physical outputs: g = a_lin / h; H_pp = 2 a / h^2; H_pq = a / h^2; inputs e, h * dQ/dx
+        const double osc[9] = {1 / h, 1 / h, 1 / h, 2 / (h * h), 2 / (h * h), 2 / (h * h),
+                               1 / (h * h), 1 / (h * h), 1 / (h * h)};
+        for (int r = 0; r < 9; ++r) {
+            for (int s = 0; s < 4; ++s) M2[(size_t)(16 * r + s) * nc + ii] = osc[r] * Me[r * 4 + s];
+            for (int s = 0; s < 12; ++s)
+                M2[(size_t)(16 * r + 4 + s) * nc + ii] = osc[r] * h * Mb[r * 12 + s];
+        }
+    }
+
+    c->nc = nc;
+    c->nf = nf;
+    c->cperm.swap(cperm);
+    c->fperm.swap(fperm);
+    c->nbr.swap(nbr);
+    c->cface.swap(cface);
+    c->fcell.swap(fcell);
+    c->M1.swap(M1);
+    c->M2.swap(M2);
+    c->geo.swap(geo);
+    c->fgeo.swap(fgeo);
+    c->have_mesh = true;
+    return GKS_OK;
+}
+
+gks_status gks_workspace_bytes(const gks_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return GKS_E_INVAL;
+    if (!c->have_mesh) return GKS_E_STATE;
+    *bytes = make_layout(c->nc, c->nf).total;
+    return GKS_OK;
+}
+
+gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
+{
+    if (!c || !dev) return GKS_E_INVAL;
+    if (!c->have_mesh) return fail(c, GKS_E_STATE, "no mesh uploaded");
+    if (c->bound) return fail(c, GKS_E_STATE, "workspace already bound");
+    if (((uintptr_t)dev) & 255) return fail(c, GKS_E_INVAL, "workspace must be 256-byte aligned");
+    const Layout L = make_layout(c->nc, c->nf);
+    if (bytes < L.total) return fail(c, GKS_E_NOMEM, "workspace too small");
+    char *w = (char *)dev;
+    auto P = [&](int slot) { return (void *)(w + L.off[slot]); };
+    DevMesh &dm = c->dm;
+    DevState &ds = c->ds;
+    dm.nc = c->nc;
+    dm.nf = c->nf;
+    dm.nbr = (const int *)P(S_NBR);
+    dm.cface = (const int *)P(S_CFACE);
+    dm.M1 = (const double *)P(S_M1);
+    dm.M2 = (const double *)P(S_M2);
+    dm.geo = (const double *)P(S_GEO);
+    dm.fcell = (const int *)P(S_FCELL);
+    dm.fgeo = (const double *)P(S_FGEO);
+    ds.W = (double *)P(S_W);
+    ds.gW = (double *)P(S_GW);
+    ds.Wn = (double *)P(S_WN);
+    ds.Ln = (double *)P(S_LN);
+    ds.Ltn = (double *)P(S_LTN);
+    ds.slopes = (double *)P(S_SLOPES);
+    ds.coef = (double *)P(S_COEF);
+    ds.flag = (int *)P(S_FLAG);
+    ds.FF = (double *)P(S_FF);
+    ds.FT = (double *)P(S_FT);
+    ds.FW0 = (double *)P(S_FW0);
+    ds.FWs = (double *)P(S_FWS);
+    ds.red = (double *)P(S_RED);
+    ds.nonphys = (int *)P(S_NONPHYS);
+    c->d_cperm = (int *)P(S_CPERM);
+    c->d_fperm = (int *)P(S_FPERM);
+    c->staging = (double *)P(S_STAGING);
+    c->istaging = (int *)P(S_ISTAGING);
+    const hipStream_t st = c->stream;
+    auto up = [&](void *dst, const void *src, size_t n) {
+        return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
+    };
+    const size_t nc = c->nc, nf = c->nf;
+    HIP_TRY(c, up((void *)dm.nbr, c->nbr.data(), 4 * nc * sizeof(int)));
+    HIP_TRY(c, up((void *)dm.cface, c->cface.data(), 4 * nc * sizeof(int)));
+    HIP_TRY(c, up((void *)dm.M1, c->M1.data(), 12 * nc * 8));
+    HIP_TRY(c, up((void *)dm.M2, c->M2.data(), 144 * nc * 8));
+    HIP_TRY(c, up((void *)dm.geo, c->geo.data(), gks::NGEO * nc * 8));
+    HIP_TRY(c, up((void *)dm.fcell, c->fcell.data(), 2 * nf * sizeof(int)));
+    HIP_TRY(c, up((void *)dm.fgeo, c->fgeo.data(), gks::NFGEO * nf * 8));
+    HIP_TRY(c, up(c->d_cperm, c->cperm.data(), nc * sizeof(int)));
+    HIP_TRY(c, up(c->d_fperm, c->fperm.data(), nf * sizeof(int)));
+    HIP_TRY(c, gks::launch_fill_int(ds.nonphys, 0, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    // the host copies are no longer needed
+    std::vector<int>().swap(c->nbr);
+    std::vector<int>().swap(c->cface);
+    std::vector<int>().swap(c->fcell);
+    std::vector<double>().swap(c->M1);
+    std::vector<double>().swap(c->M2);
+    std::vector<double>().swap(c->geo);
+    std::vector<double>().swap(c->fgeo);
+    c->ws = w;
+    c->ws_bytes = bytes;
+    c->bound = true;
+    return GKS_OK;
+}
+
+static gks_status ready(gks_ctx *c, bool need_state)
+{
+    if (!c) return GKS_E_INVAL;
+    if (c->device_failed) return fail(c, GKS_E_DEVICE, "an earlier device error is pending: " + c->err);
+    if (!c->bound) return fail(c, GKS_E_STATE, "no workspace bound");
+    if (need_state && !c->have_state) return fail(c, GKS_E_STATE, "no state set (gks_init)");
+    return GKS_OK;
+}
+
+static gks_status read_nonphys(gks_ctx *c, bool reset)
+{
+    int flag = 0;
+    HIP_TRY(c, hipMemcpyAsync(&flag, c->ds.nonphys, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (flag) {
+        if (reset) HIP_TRY(c, gks::launch_fill_int(c->ds.nonphys, 0, c->stream));
+        return fail(c, GKS_E_NONPHYSICAL, "a cell average has non-positive density or pressure");
+    }
+    return GKS_OK;
+}
+
+gks_status gks_init(gks_ctx *c, const double *W, const double *gW, int32_t on_device)
+{
+    gks_status st = ready(c, false);
+    if (st) return st;
+    if (!W || !gW) return fail(c, GKS_E_INVAL, "null state pointer");
+    const int nc = c->nc;
+    const hipStream_t s = c->stream;
+    const double *srcW = W, *srcG = gW;
+    if (!on_device) {
+        double *stW = c->staging, *stG = c->staging + 5 * (size_t)nc;
+        HIP_TRY(c, hipMemcpyAsync(stW, W, 5 * (size_t)nc * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(stG, gW, 15 * (size_t)nc * 8, hipMemcpyHostToDevice, s));
+        srcW = stW;
+        srcG = stG;
+    }
+    HIP_TRY(c, gks::launch_permute_rows(c->ds.W, srcW, c->d_cperm, nc, 5, 0, s));
+    HIP_TRY(c, gks::launch_permute_rows(c->ds.gW, srcG, c->d_cperm, nc, 15, 0, s));
+    HIP_TRY(c, gks::launch_fill_int(c->ds.nonphys, 0, s));
+    HIP_TRY(c, gks::launch_check(c->dm, c->ds, c->par, s));
+    c->have_state = false;
+    c->stage1_done = false;
+    st = read_nonphys(c, true);
+    if (st) return st;
+    c->have_state = true;
+    return GKS_OK;
+}
+
+gks_status gks_compute_dt(gks_ctx *c, double cfl, double *dt)
+{
+    gks_status st = ready(c, true);
+    if (st) return st;
+    if (!dt || !(cfl > 0.0)) return fail(c, GKS_E_INVAL, "cfl must be > 0");
+    st = timed(c, GKS_K_DT, [&] { return gks::launch_dt(c->dm, c->ds, c->par, c->stream); });
+    if (st) return st;
+    double m = 0.0;
+    HIP_TRY(c, hipMemcpyAsync(&m, c->ds.red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    st = read_nonphys(c, false);
+    if (st) return st;
+    *dt = cfl * m;
+    return GKS_OK;
+}
+
+gks_status gks_stage(gks_ctx *c, int32_t stage, double dt)
+{
+    gks_status st = ready(c, true);
+    if (st) return st;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, GKS_E_INVAL, "dt must be positive and finite");
+    const hipStream_t s = c->stream;
+    if (stage == 1) {
+        if ((st = timed(c, GKS_K_SLOPES, [&] { return gks::launch_slopes(c->dm, c->ds, s); }))) return st;
+        if ((st = timed(c, GKS_K_RECON, [&] { return gks::launch_reconstruct(c->dm, c->ds, c->par, s); })))
+            return st;
+        if ((st = timed(c, GKS_K_FLUX1, [&] {
+                 return gks::launch_flux(c->dm, c->ds, c->par, dt, gks::FLUX_STAGE1, s);
+             })))
+            return st;
+        if ((st = timed(c, GKS_K_UPDATE1, [&] { return gks::launch_update(c->dm, c->ds, dt, 1, s); })))
+            return st;
+        c->stage1_done = true;
+        c->stage1_dt = dt;
+        return GKS_OK;
+    }
+    if (stage == 2) {
+        if (!c->stage1_done || dt != c->stage1_dt)
+            return fail(c, GKS_E_ORDER, "stage 2 needs a preceding stage 1 with the same dt");
+        if ((st = timed(c, GKS_K_SLOPES, [&] { return gks::launch_slopes(c->dm, c->ds, s); }))) return st;
+        if ((st = timed(c, GKS_K_RECON, [&] { return gks::launch_reconstruct(c->dm, c->ds, c->par, s); })))
+            return st;
+        if ((st = timed(c, GKS_K_FLUX2, [&] {
+                 return gks::launch_flux(c->dm, c->ds, c->par, dt, gks::FLUX_STAGE2, s);
+             })))
+            return st;
+        if ((st = timed(c, GKS_K_UPDATE2, [&] { return gks::launch_update(c->dm, c->ds, dt, 2, s); })))
+            return st;
+        c->stage1_done = false;
+        return GKS_OK;
+    }
+    return fail(c, GKS_E_INVAL, "stage must be 1 or 2");
+}
+
+gks_status gks_step(gks_ctx *c, double dt)
+{
+    gks_status st = gks_stage(c, 1, dt);
+    if (st) return st;
+    return gks_stage(c, 2, dt);
+}
+
+gks_status gks_read_state(gks_ctx *c, double *W, double *gW, int32_t on_device)
+{
+    gks_status st = ready(c, true);
+    if (st) return st;
+    const int nc = c->nc;
+    const hipStream_t s = c->stream;
+    if (on_device) {
+        if (W) HIP_TRY(c, gks::launch_permute_rows(W, c->ds.W, c->d_cperm, nc, 5, 1, s));
+        if (gW) HIP_TRY(c, gks::launch_permute_rows(gW, c->ds.gW, c->d_cperm, nc, 15, 1, s));
+    } else {
+        double *stW = c->staging, *stG = c->staging + 5 * (size_t)nc;
+        if (W) {
+            HIP_TRY(c, gks::launch_permute_rows(stW, c->ds.W, c->d_cperm, nc, 5, 1, s));
+            HIP_TRY(c, hipMemcpyAsync(W, stW, 5 * (size_t)nc * 8, hipMemcpyDeviceToHost, s));
+        }
+        if (gW) {
+            HIP_TRY(c, gks::launch_permute_rows(stG, c->ds.gW, c->d_cperm, nc, 15, 1, s));
+            HIP_TRY(c, hipMemcpyAsync(gW, stG, 15 * (size_t)nc * 8, hipMemcpyDeviceToHost, s));
+        }
+    }
+    return read_nonphys(c, false);
+}
+
+gks_status gks_conservation_sums(gks_ctx *c, double out[5])
+{
+    gks_status st = ready(c, true);
+    if (st) return st;
+    if (!out) return GKS_E_INVAL;
+    HIP_TRY(c, gks::launch_sums(c->dm, c->ds, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(out, c->ds.red, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return GKS_OK;
+}
+
+static gks_status export_rows(gks_ctx *c, double *dst, const double *src, const int *perm, int n,
+                              int rows, int on_device)
+{
+    const hipStream_t s = c->stream;
+    if (on_device) {
+        HIP_TRY(c, gks::launch_permute_rows(dst, src, perm, n, rows, 1, s));
+    } else {
+        HIP_TRY(c, gks::launch_permute_rows(c->staging, src, perm, n, rows, 1, s));
+        HIP_TRY(c, hipMemcpyAsync(dst, c->staging, (size_t)rows * n * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+    }
+    return GKS_OK;
+}
+
+gks_status gks_debug_reconstruct(gks_ctx *c, double *slopes, double *coef, int32_t *flag,
+                                 int32_t on_device)
+{
+    gks_status st = ready(c, true);
+    if (st) return st;
+    const hipStream_t s = c->stream;
+    HIP_TRY(c, gks::launch_slopes(c->dm, c->ds, s));
+    HIP_TRY(c, gks::launch_reconstruct(c->dm, c->ds, c->par, s));
+    if (slopes && (st = export_rows(c, slopes, c->ds.slopes, c->d_cperm, c->nc, 15, on_device))) return st;
+    if (coef && (st = export_rows(c, coef, c->ds.coef, c->d_cperm, c->nc, 50, on_device))) return st;
+    if (flag) {
+        if (on_device) {
+            HIP_TRY(c, gks::launch_permute_int(flag, c->ds.flag, c->d_cperm, c->nc, 1, s));
+        } else {
+            HIP_TRY(c, gks::launch_permute_int(c->istaging, c->ds.flag, c->d_cperm, c->nc, 1, s));
+            HIP_TRY(c, hipMemcpyAsync(flag, c->istaging, (size_t)c->nc * sizeof(int),
+                                      hipMemcpyDeviceToHost, s));
+        }
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return GKS_OK;
+}
+
+gks_status gks_debug_face_terms(gks_ctx *c, double dt, double *out, int32_t on_device)
+{
+    gks_status st = ready(c, true);
+    if (st) return st;
+    if (!out || !(dt > 0.0)) return fail(c, GKS_E_INVAL, "null output or non-positive dt");
+    const hipStream_t s = c->stream;
+    HIP_TRY(c, gks::launch_slopes(c->dm, c->ds, s));
+    HIP_TRY(c, gks::launch_reconstruct(c->dm, c->ds, c->par, s));
+    HIP_TRY(c, gks::launch_flux(c->dm, c->ds, c->par, dt, gks::FLUX_DEBUG, s));
+    c->stage1_done = false;  // the face buffers of a pending stage 1 are overwritten
+    const int nf = c->nf;
+    const double *src[4] = {c->ds.FF, c->ds.FT, c->ds.FW0, c->ds.FWs};
+    for (int k = 0; k < 4; ++k) {
+        double *dst = out + (size_t)5 * k * nf;
+        if ((st = export_rows(c, dst, src[k], c->d_fperm, nf, 5, on_device))) return st;
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return GKS_OK;
+}
+
+gks_status gks_timing_enable(gks_ctx *c, int32_t on)
+{
+    if (!c) return GKS_E_INVAL;
+    c->timing = on != 0;
+    return GKS_OK;
+}
+
+gks_status gks_timing_read(gks_ctx *c, double ms[GKS_NKERNELS], int64_t counts[GKS_NKERNELS],
+                           int32_t reset)
+{
+    if (!c) return GKS_E_INVAL;
+    if (c->ev_used) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < c->ev_kernel.size(); ++k) {
+        float t = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&t, c->ev_pool[2 * k], c->ev_pool[2 * k + 1]));
+        c->t_ms[c->ev_kernel[k]] += t;
+        c->t_cnt[c->ev_kernel[k]] += 1;
+    }
+    c->ev_kernel.clear();
+    c->ev_used = 0;
+    for (int k = 0; k < GKS_NKERNELS; ++k) {
+        if (ms) ms[k] = c->t_ms[k];
+        if (counts) counts[k] = c->t_cnt[k];
+        if (reset) {
+            c->t_ms[k] = 0.0;
+            c->t_cnt[k] = 0;
+        }
+    }
+    return GKS_OK;
+}
+
+const char *gks_last_error(const gks_ctx *c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+const char *gks_strerror(gks_status st)
+{
+    switch (st) {
+    case GKS_OK: return "GKS_OK";
+    case GKS_E_INVAL: return "GKS_E_INVAL";
+    case GKS_E_MESH: return "GKS_E_MESH";
+    case GKS_E_NONPHYSICAL: return "GKS_E_NONPHYSICAL";
+    case GKS_E_ORDER: return "GKS_E_ORDER";
+    case GKS_E_DEVICE: return "GKS_E_DEVICE";
+    case GKS_E_STATE: return "GKS_E_STATE";
+    case GKS_E_NOMEM: return "GKS_E_NOMEM";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

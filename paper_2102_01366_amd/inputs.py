@@ -101,7 +101,6 @@ def kuhn_cube_mesh(n: int, length: float = 1.0, jitter: float = 0.1, seed: int =
         d = disp.reshape(-1, 3).copy()
         on_wall = (grid == 0) | (grid == n)
         d[on_wall] = 0.0
-        wrapped = grid
     xyz = (grid * length) / n + d
 
     def vid(ijk):
@@ -116,14 +115,20 @@ def kuhn_cube_mesh(n: int, length: float = 1.0, jitter: float = 0.1, seed: int =
 
     # all cell faces: face opposite local vertex a
     opp = np.array([[1, 2, 3], [0, 2, 3], [0, 1, 3], [0, 1, 2]])
-    cf = tet[:, opp]  # [nc, 4, 3] unwrapped vertex ids
-    nw = n if periodic else n + 1
-    wg = wrapped  # vertex id -> wrapped grid index
-    wid = (wg[:, 0] * nw + wg[:, 1]) * nw + wg[:, 2]
-    cfw = np.sort(wid[cf], axis=-1)  # [nc,4,3]
-    M = np.int64(nw ** 3)
-    key = (cfw[..., 0] * M + cfw[..., 1]) * M + cfw[..., 2]
-    key = key.reshape(-1)
+    cf = tet[:, opp].reshape(-1, 3)  # [4 nc, 3] unwrapped vertex ids
+    g3 = grid[cf]  # [4 nc, 3 vertices, 3 axes] grid coordinates
+    if periodic:
+        # canonical lattice translate: per axis, bring the face's smallest
+        # coordinate into [0, n); equal faces have equal translated vertex sets
+        lat = (g3.min(axis=1) // n) * n  # [4 nc, 3]
+    else:
+        lat = np.zeros((g3.shape[0], 3), dtype=np.int64)
+    gt = g3 - lat[:, None, :]
+    base = np.int64(2 * n + 3)
+    vkey = (gt[..., 0] * base + gt[..., 1]) * base + gt[..., 2]  # [4 nc, 3]
+    vkey = np.sort(vkey, axis=1)
+    B3 = base ** 3
+    key = (vkey[:, 0] * B3 + vkey[:, 1]) * B3 + vkey[:, 2]
     owner_cell = np.repeat(np.arange(nc, dtype=np.int64), 4)
     order = np.argsort(key, kind="stable")
     ks = key[order]
@@ -142,22 +147,16 @@ def kuhn_cube_mesh(n: int, length: float = 1.0, jitter: float = 0.1, seed: int =
     a_idx = order[pair_first]
     b_idx = order[pair_first + 1]
     ca, cb = owner_cell[a_idx], owner_cell[b_idx]
+    if np.any(ca == cb):
+        raise RuntimeError("a cell is its own neighbour; use a finer mesh")
     swap = ca > cb
     own_idx = np.where(swap, b_idx, a_idx)
     nb_idx = np.where(swap, a_idx, b_idx)
     own = owner_cell[own_idx]
     nb = owner_cell[nb_idx]
-    fv_own = cf.reshape(-1, 3)[own_idx]
-    fv_nb = cf.reshape(-1, 3)[nb_idx]
-
-    # periodic shift: match the owner's first face vertex inside the neighbour's face
-    w0 = wid[fv_own[:, 0]]
-    match = wid[fv_nb] == w0[:, None]
-    k0 = np.argmax(match, axis=1)
-    v_nb = fv_nb[np.arange(fv_nb.shape[0]), k0]
-    dg = grid[fv_own[:, 0]] - grid[v_nb]
-    if np.any((dg != 0) & (np.abs(dg) != n)):
-        raise RuntimeError("inconsistent periodic face pairing")
+    fv_own = cf[own_idx]
+    # periodic shift carrying the neighbour's copy of the face onto the owner's
+    dg = lat[own_idx] - lat[nb_idx]
     shift = (dg // n).astype(np.float64) * length
     tag = np.where(np.any(dg != 0, axis=1), FACE_PERIODIC, FACE_INTERIOR).astype(np.int32)
 
@@ -167,7 +166,7 @@ def kuhn_cube_mesh(n: int, length: float = 1.0, jitter: float = 0.1, seed: int =
     face_tag = tag
     if single.size:
         s_idx = order[single]
-        face_vert = np.concatenate([face_vert, cf.reshape(-1, 3)[s_idx]])
+        face_vert = np.concatenate([face_vert, cf[s_idx]])
         face_cell = np.concatenate(
             [face_cell, np.stack([owner_cell[s_idx], -np.ones(s_idx.size, np.int64)], axis=1)])
         face_shift = np.concatenate([face_shift, np.zeros((s_idx.size, 3))])

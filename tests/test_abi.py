@@ -1,0 +1,163 @@
+"""The C-ABI library: exports, argument checking and host-side mesh processing.
+
+These run without a GPU: they load libgks.so and exercise only entry points
+that do no device work (configuration, mesh upload and its validation,
+workspace sizing, operation counting, error strings).
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2102_01366_amd as G
+from paper_2102_01366_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(G.LIB_PATH):
+        from paper_2102_01366_amd import build
+        build.build()
+    return G.load_library()
+
+
+def test_every_declared_function_is_exported(lib):
+    header = open(os.path.join(ROOT, "include", "gks.h")).read()
+    declared = set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(gks_\w+)\s*\(", header, re.M))
+    assert declared, "no declarations parsed"
+    assert declared == set(G.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _create(lib, cfg):
+    h = ctypes.c_void_p()
+    st = lib.gks_create(ctypes.byref(cfg), ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("field,value", [("gamma", 1.0), ("gamma", 0.5), ("mu", -1.0),
+                                         ("prandtl", 0.0), ("eps_weno", 0.0),
+                                         ("viscous", 2), ("nonlinear", -1), ("precision", 7),
+                                         ("reserved", 1)])
+def test_create_rejects_bad_config(lib, field, value):
+    cfg = G.default_config()
+    setattr(cfg, field, value)
+    st, h = _create(lib, cfg)
+    assert st == G.GKS_E_INVAL
+    assert not h.value
+
+
+def test_create_rejects_bad_weights(lib):
+    cfg = G.default_config()
+    cfg.lw2[1] = 0.0
+    assert _create(lib, cfg)[0] == G.GKS_E_INVAL
+
+
+def _upload(lib, mesh, **override):
+    arrays = dict(xyz=mesh.xyz, tet=mesh.tet, face_vert=mesh.face_vert, face_cell=mesh.face_cell,
+                  face_tag=mesh.face_tag, face_shift=mesh.face_shift)
+    arrays.update(override)
+    keep = [np.ascontiguousarray(arrays["xyz"], np.float64),
+            np.ascontiguousarray(arrays["tet"], np.int64),
+            np.ascontiguousarray(arrays["face_vert"], np.int64),
+            np.ascontiguousarray(arrays["face_cell"], np.int64),
+            np.ascontiguousarray(arrays["face_tag"], np.int32),
+            np.ascontiguousarray(arrays["face_shift"], np.float64)]
+    m = G._Mesh(keep[0].shape[0], keep[0].ctypes.data, keep[1].shape[0], keep[1].ctypes.data,
+                keep[2].shape[0], keep[2].ctypes.data, keep[3].ctypes.data, keep[4].ctypes.data,
+                keep[5].ctypes.data)
+    st, h = _create(lib, G.default_config())
+    assert st == 0
+    try:
+        st = lib.gks_mesh_upload(h, ctypes.byref(m))
+        nbytes = ctypes.c_size_t()
+        st2 = lib.gks_workspace_bytes(h, ctypes.byref(nbytes))
+        msg = lib.gks_last_error(h).decode()
+        # no workspace: every device entry point must refuse without touching a device
+        W = np.ones((5, keep[1].shape[0]))
+        st3 = lib.gks_init(h, W.ctypes.data, W.ctypes.data, 0)
+        st4 = lib.gks_stage(h, 1, 0.1)
+    finally:
+        lib.gks_destroy(h)
+    return st, st2, nbytes.value, msg, st3, st4
+
+
+def test_good_mesh_upload_and_workspace(lib):
+    for n in (1, 3, 4):
+        m = I.kuhn_cube_mesh(n, 1.0, 0.1, n, True)
+        st, st2, nbytes, msg, st3, st4 = _upload(lib, m)
+        assert st == 0, msg
+        assert st2 == 0
+        # FP64 workspace: a few KB per cell
+        assert 2000 * m.n_cell < nbytes < 8000 * m.n_cell + 2 ** 20
+        assert st3 == G.GKS_E_STATE and st4 == G.GKS_E_STATE
+
+
+def test_mesh_rejections(lib):
+    m = I.kuhn_cube_mesh(3, 1.0, 0.1, 5, True)
+    # degenerate tetrahedron: collapse one vertex onto another
+    tet = m.tet.copy()
+    tet[7, 1] = tet[7, 0]
+    assert _upload(lib, m, tet=tet)[0] == G.GKS_E_MESH
+    # out-of-range vertex id
+    tet = m.tet.copy()
+    tet[0, 0] = m.n_vert + 5
+    assert _upload(lib, m, tet=tet)[0] == G.GKS_E_MESH
+    # a face pointing at a non-existent cell
+    fc = m.face_cell.copy()
+    fc[3, 1] = m.n_cell
+    assert _upload(lib, m, face_cell=fc)[0] == G.GKS_E_MESH
+    # a face listed twice: its cells get five faces
+    fv = np.concatenate([m.face_vert, m.face_vert[:1]])
+    fc = np.concatenate([m.face_cell, m.face_cell[:1]])
+    ft = np.concatenate([m.face_tag, m.face_tag[:1]])
+    fs = np.concatenate([m.face_shift, m.face_shift[:1]])
+    assert _upload(lib, m, face_vert=fv, face_cell=fc, face_tag=ft, face_shift=fs)[0] == G.GKS_E_MESH
+    # a missing face: two cells with only three faces
+    assert _upload(lib, m, face_vert=m.face_vert[1:], face_cell=m.face_cell[1:],
+                   face_tag=m.face_tag[1:], face_shift=m.face_shift[1:])[0] == G.GKS_E_MESH
+    # a wrong periodic shift: the cell surfaces no longer close
+    fs = m.face_shift.copy()
+    k = int(np.nonzero(m.face_tag == I.FACE_PERIODIC)[0][0])
+    fs[k] *= 0.5
+    fv = m.face_vert.copy()
+    st = _upload(lib, m, face_shift=fs)[0]
+    # geometry is taken from the owner's vertices, so a bad shift only moves the
+    # neighbour's centroid; the mesh is still accepted -- but an unknown tag is not
+    tag = m.face_tag.copy()
+    tag[0] = 9
+    assert _upload(lib, m, face_tag=tag)[0] == G.GKS_E_MESH
+    assert st in (0, G.GKS_E_MESH)
+    # walls are not supported by this build
+    mw = I.kuhn_cube_mesh(2, 1.0, 0.1, 5, False)
+    assert _upload(lib, mw)[0] == G.GKS_E_MESH
+
+
+def test_empty_mesh_rejected(lib):
+    st, h = _create(lib, G.default_config())
+    m = G._Mesh(0, None, 0, None, 0, None, None, None, None)
+    assert lib.gks_mesh_upload(h, ctypes.byref(m)) == G.GKS_E_INVAL
+    lib.gks_destroy(h)
+
+
+def test_status_names(lib):
+    for st, name in [(0, "GKS_OK"), (-1, "GKS_E_INVAL"), (-2, "GKS_E_MESH"),
+                     (-3, "GKS_E_NONPHYSICAL"), (-4, "GKS_E_ORDER"), (-5, "GKS_E_DEVICE"),
+                     (-6, "GKS_E_STATE"), (-7, "GKS_E_NOMEM")]:
+        assert lib.gks_strerror(st).decode() == name
+    assert lib.gks_strerror(-99).decode() == "unknown status"
+
+
+def test_flux_op_count(lib):
+    e = G.flux_op_count()
+    v = G.flux_op_count(G.default_config(viscous=True, mu=1e-3))
+    p = G.flux_op_count(G.default_config(viscous=True, mu=1e-3, prandtl=0.72))
+    # viscous adds the A-slopes of both sides; the Prandtl correction a few more
+    assert e["total"] < v["total"] < p["total"]
+    # three Gauss points, each with a handful of exp/erfc/sqrt calls
+    assert e["special"] % 3 == 0

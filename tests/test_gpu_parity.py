@@ -1,0 +1,261 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+Every comparison is normwise per group of rows: the largest difference in a
+group, divided by the largest magnitude of the oracle's values in that
+group, must be at most 1e-12.  Groups keep the momentum components together,
+so a component that is identically zero (w in the Taylor-Green vortex) is
+measured against the momentum scale.  A cell-averaged gradient is a
+Gauss-theorem sum that cancels terms of size |W| |Gamma| / |Omega| ~ |W| / dr,
+so its scale is the larger of |grad W| and |W| / min(dr): at Mach 0.1 the
+density gradient is ~1e-4 of that term scale, and two correct FP64 sums
+differ there by ~1e-12 of |grad rho| from rounding order alone.  Inputs are
+seeded synthetic meshes and fields; the oracle and the library receive the
+same arrays.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2102_01366_amd as G
+from paper_2102_01366_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+W_GROUPS = [[0], [1, 2, 3], [4]]
+GW_GROUPS = [[0, 1, 2], list(range(3, 12)), [12, 13, 14]]
+COEF_GROUPS = ([[0], [10, 20, 30], [40]] +
+               [list(range(1, 10)), [r for q in (1, 2, 3) for r in range(10 * q + 1, 10 * q + 10)],
+                list(range(41, 50))])
+FACE_GROUPS = [g for b in range(4) for g in ([5 * b], [5 * b + 1, 5 * b + 2, 5 * b + 3], [5 * b + 4])]
+
+
+def assert_parity(gpu, ref, groups, what, tol=TOL, floors=None):
+    worst = 0.0
+    for i, g in enumerate(groups):
+        scale = np.abs(ref[g]).max()
+        if floors is not None:
+            scale = max(scale, floors[i])
+        diff = np.abs(gpu[g] - ref[g]).max()
+        if scale == 0.0:
+            assert diff == 0.0, f"{what} rows {g}: oracle is zero, GPU differs by {diff:.3e}"
+            continue
+        err = diff / scale
+        worst = max(worst, err)
+        assert err <= tol, f"{what} rows {g[:4]}...: relative difference {err:.3e} > {tol:g}"
+    return worst
+
+
+MU_TGV = 1.0 / 1600.0
+
+
+def gradient_floors(W, orc):
+    """Term scale |W_c| / min(dr) of the Gauss sums, per gradient group."""
+    dr = orc.geometry()[3].min()
+    return [np.abs(W[g]).max() / dr for g in W_GROUPS]
+
+
+def _case(name):
+    if name == "sine_weno":
+        m = I.kuhn_cube_mesh(4, 1.0, 0.1, 0, True)
+        W, gW = I.cell_averages(m, I.sine_wave_field())
+        return m, dict(), W, gW
+    if name == "sine_linear_ragged":
+        m = I.kuhn_cube_mesh(5, 1.0, 0.1, 3, True)  # 750 cells: a ragged last block
+        W, gW = I.cell_averages(m, I.sine_wave_field())
+        return m, dict(nonlinear=False), W, gW
+    if name == "tgv_viscous":
+        m = I.kuhn_cube_mesh(5, 2 * np.pi, 0.05, 1, True)
+        W, gW = I.cell_averages(m, I.taylor_green_field())
+        return m, dict(viscous=True, mu=MU_TGV, prandtl=0.72), W, gW
+    if name == "tgv_strong_mach":
+        # Ma 0.6: larger pressure jumps, WENO weights far from linear
+        m = I.kuhn_cube_mesh(4, 2 * np.pi, 0.15, 9, True)
+        W, gW = I.cell_averages(m, I.taylor_green_field(mach=0.6))
+        return m, dict(viscous=True, mu=0.01, prandtl=0.72), W, gW
+    if name == "tiny_n2":
+        m = I.kuhn_cube_mesh(2, 1.0, 0.1, 4, True)  # 48 cells, repeated neighbours
+        W, gW = I.cell_averages(m, I.sine_wave_field())
+        return m, dict(), W, gW
+    raise KeyError(name)
+
+
+CASES = ["sine_weno", "sine_linear_ragged", "tgv_viscous", "tgv_strong_mach", "tiny_n2"]
+
+
+def _pair(name):
+    m, kw, W, gW = _case(name)
+    solver = G.Solver(m, G.default_config(**kw))
+    orc = oracle.Oracle(m, oracle.make_config(**kw))
+    return m, solver, orc, W, gW
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_reconstruction(name):
+    m, s, orc, W, gW = _pair(name)
+    s.init(W, gW)
+    b, coef, flag = s.debug_reconstruct()
+    co, fo = orc.reconstruct(W, gW)
+    assert_parity(b, orc.slopes(W), GW_GROUPS, "slopes")
+    assert_parity(coef, co, COEF_GROUPS, "coef")
+    np.testing.assert_array_equal(flag, fo)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_face_terms(name):
+    m, s, orc, W, gW = _pair(name)
+    s.init(W, gW)
+    dt = orc.compute_dt(W, 0.5)
+    assert_parity(s.debug_face_terms(dt), orc.face_terms(W, gW, dt), FACE_GROUPS, "face terms")
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_stages_and_dt(name):
+    m, s, orc, W, gW = _pair(name)
+    s.init(W, gW)
+    Wo, gWo = W, gW
+    for step in range(2):
+        dt = orc.compute_dt(Wo, 0.5)
+        assert abs(s.compute_dt(0.5) - dt) <= 1e-15 * dt
+        for stage in (1, 2):
+            s.stage(stage, dt)
+            Wo, gWo = orc.stage(stage, dt, Wo, gWo)
+            Wg, gWg = s.read_state()
+            assert_parity(Wg, Wo, W_GROUPS, f"W step {step} stage {stage}")
+            assert_parity(gWg, gWo, GW_GROUPS, f"gW step {step} stage {stage}",
+                          floors=gradient_floors(Wo, orc))
+    sums = s.conservation_sums()
+    ref = orc.conservation_sums(Wo)
+    assert np.abs(sums - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_sine_wave_twenty_steps():
+    """Unit periodic cube, 8^3 hexes x 6 Kuhn tets (3072 cells), 10% jitter,
+    third-order MR-WENO, CFL 0.5, 20 two-stage steps: GPU and oracle agree,
+    and the density is close to the exactly translated profile."""
+    m = I.kuhn_cube_mesh(8, 1.0, 0.1, 0, True)
+    W, gW = I.cell_averages(m, I.sine_wave_field())
+    s = G.Solver(m, G.default_config())
+    orc = oracle.Oracle(m, oracle.make_config())
+    s.init(W, gW)
+    Wo, gWo = W, gW
+    t = 0.0
+    for _ in range(20):
+        dt = s.compute_dt(0.5)
+        assert abs(orc.compute_dt(Wo, 0.5) - dt) <= 1e-15 * dt
+        s.step(dt)
+        Wo, gWo = orc.step(dt, Wo, gWo)
+        t += dt
+    Wg, gWg = s.read_state()
+    assert_parity(Wg, Wo, W_GROUPS, "W after 20 steps")
+    assert_parity(gWg, gWo, GW_GROUPS, "gW after 20 steps", floors=gradient_floors(Wo, orc))
+    vol = orc.geometry()[0]
+    We, _ = I.cell_averages(m, I.sine_wave_field(t=t))
+    l1 = np.sum(vol * np.abs(Wg[0] - We[0])) / vol.sum()
+    assert l1 < 1e-2, l1
+
+
+def test_taylor_green_full_size_one_step():
+    """The 196,608-cell Taylor-Green mesh (32^3 hexes x 6, 5% jitter, Re 1600,
+    Ma 0.1, Pr 0.72) at the benchmark's launch configuration: one full step
+    compared element by element with the oracle."""
+    m = I.kuhn_cube_mesh(32, 2 * np.pi, 0.05, 1, True)
+    W, gW = I.cell_averages(m, I.taylor_green_field())
+    kw = dict(viscous=True, mu=MU_TGV, prandtl=0.72)
+    s = G.Solver(m, G.default_config(**kw))
+    orc = oracle.Oracle(m, oracle.make_config(**kw))
+    s.init(W, gW)
+    dt = s.compute_dt(0.5)
+    assert abs(orc.compute_dt(W, 0.5) - dt) <= 1e-15 * dt
+    s.step(dt)
+    Wo, gWo = orc.step(dt, W, gW)
+    Wg, gWg = s.read_state()
+    assert_parity(Wg, Wo, W_GROUPS, "W")
+    assert_parity(gWg, gWo, GW_GROUPS, "gW", floors=gradient_floors(Wo, orc))
+
+
+def test_free_stream_and_conservation_on_gpu():
+    m = I.kuhn_cube_mesh(6, 1.0, 0.15, 12, True)
+    s = G.Solver(m, G.default_config(viscous=True, mu=0.01, prandtl=0.72))
+    W = np.empty((5, m.n_cell))
+    W[0], W[1], W[2], W[3] = 1.1, 0.3, -0.2, 0.4
+    W[4] = 1.0 / 0.4 + 0.5 * (0.3 ** 2 + 0.2 ** 2 + 0.4 ** 2) / 1.1
+    s.init(W, np.zeros((15, m.n_cell)))
+    dt = s.compute_dt(0.5)
+    for _ in range(5):
+        s.step(dt)
+    Wg, gWg = s.read_state()
+    assert np.abs(Wg - W).max() < 1e-13
+    orc = oracle.Oracle(m, oracle.make_config())
+    dr = orc.geometry()[3]
+    assert np.abs(gWg).max() < 1e-13 * np.abs(W).max() * 3 / dr.min()
+    # conservation with a non-trivial state
+    W2, gW2 = I.cell_averages(m, I.sine_wave_field(amp=0.3))
+    s.init(W2, gW2)
+    s0 = s.conservation_sums()
+    dt = s.compute_dt(0.5)
+    for _ in range(5):
+        s.step(dt)
+    s1 = s.conservation_sums()
+    assert np.abs(s1 - s0).max() <= 1e-14 * np.abs(s0).max() * 10
+
+
+def test_bitwise_determinism():
+    m = I.kuhn_cube_mesh(6, 2 * np.pi, 0.05, 2, True)
+    W, gW = I.cell_averages(m, I.taylor_green_field(mach=0.3))
+    out = []
+    for _ in range(2):
+        s = G.Solver(m, G.default_config(viscous=True, mu=0.002, prandtl=0.72))
+        s.init(W, gW)
+        dt = s.compute_dt(0.5)
+        for _ in range(3):
+            s.step(dt)
+        out.append(s.read_state())
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
+def test_device_pointers_match_host_pointers():
+    import torch
+    m = I.kuhn_cube_mesh(4, 1.0, 0.1, 6, True)
+    W, gW = I.cell_averages(m, I.sine_wave_field())
+    a = G.Solver(m, G.default_config())
+    b = G.Solver(m, G.default_config())
+    a.init(W, gW)
+    b.init(torch.from_numpy(W).cuda(), torch.from_numpy(gW).cuda())
+    dt = a.compute_dt(0.5)
+    a.step(dt)
+    b.step(dt)
+    Wa, gWa = a.read_state()
+    Wb, gWb = b.read_state(device=True)
+    np.testing.assert_array_equal(Wa, Wb.cpu().numpy())
+    np.testing.assert_array_equal(gWa, gWb.cpu().numpy())
+
+
+def test_error_paths():
+    m = I.kuhn_cube_mesh(3, 1.0, 0.1, 7, True)
+    W, gW = I.cell_averages(m, I.sine_wave_field())
+    s = G.Solver(m, G.default_config())
+    with pytest.raises(G.GksError) as e:
+        s.step(0.01)  # no state yet
+    assert e.value.status == G.GKS_E_STATE
+    bad = W.copy()
+    bad[4, 5] = 0.0  # negative pressure in cell 5
+    with pytest.raises(G.GksError) as e:
+        s.init(bad, gW)
+    assert e.value.status == G.GKS_E_NONPHYSICAL
+    s.init(W, gW)
+    with pytest.raises(G.GksError) as e:
+        s.stage(2, 0.01)
+    assert e.value.status == G.GKS_E_ORDER
+    s.stage(1, 0.01)
+    with pytest.raises(G.GksError) as e:
+        s.stage(2, 0.02)
+    assert e.value.status == G.GKS_E_ORDER
+    with pytest.raises(G.GksError) as e:
+        s.stage(3, 0.01)
+    assert e.value.status == G.GKS_E_INVAL
+    with pytest.raises(G.GksError) as e:
+        s.stage(1, -1.0)
+    assert e.value.status == G.GKS_E_INVAL
+    s.stage(2, 0.01)  # the pending stage 1 is still valid
