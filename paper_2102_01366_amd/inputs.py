@@ -218,18 +218,22 @@ def cell_points(mesh: TetMesh, pts: np.ndarray) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 def sine_wave_field(gamma: float = 1.4, amp: float = 0.2, length: float = 1.0,
-                    vel=(1.0, 1.0, 1.0), p: float = 1.0, t: float = 0.0):
-    """Density wave rho = 1 + amp sin(2 pi (x+y+z - (u+v+w) t) / length), uniform u, p."""
+                    vel=(1.0, 1.0, 1.0), p: float = 1.0, t: float = 0.0,
+                    direction=(1.0, 1.0, 1.0)):
+    """Density wave rho = 1 + amp sin(2 pi d.(x - u t) / length), uniform u and p;
+    d has integer components so that the wave is periodic on the cube."""
     kk = 2.0 * np.pi / length
     u = np.asarray(vel, dtype=float)
+    dv = np.asarray(direction, dtype=float)
 
     def f(X):
-        ph = kk * (X[..., 0] - u[0] * t + X[..., 1] - u[1] * t + X[..., 2] - u[2] * t)
+        ph = kk * ((X[..., 0] - u[0] * t) * dv[0] + (X[..., 1] - u[1] * t) * dv[1] +
+                   (X[..., 2] - u[2] * t) * dv[2])
         rho = 1.0 + amp * np.sin(ph)
         drho = amp * kk * np.cos(ph)
         Q = np.stack([rho, rho * u[0], rho * u[1], rho * u[2],
                       p / (gamma - 1.0) + 0.5 * rho * (u @ u)])
-        dr = np.stack([drho, drho, drho])  # d rho / dx_j, j = 0..2
+        dr = np.stack([drho * dv[0], drho * dv[1], drho * dv[2]])  # d rho / dx_j
         dQ = np.stack([dr, dr * u[0], dr * u[1], dr * u[2], 0.5 * (u @ u) * dr])
         return Q, dQ
     return f
