@@ -152,40 +152,118 @@ GKS_HD void micro_slope(const Prim<R> &g, R K, const R b[5], R a[5])
     a[0] = b[0] - U * a[1] - V * a[2] - W * a[3] - R(0.5) * a[4] * q2;
 }
 
-// Kinetic part of one side (u > 0 for the left state, u < 0 for the right):
-// adds the slopes' contribution to the interface gradients gc, and the
-// side's terms of eq. 2nd-flux to the time integrals Fo, point values Wo and
-// time-integrated point values Io.
+// Heat flux about U^c of a moment pair: with F = <u psi Y> and V = <psi Y>,
+// <(u-U)((u-U)^2 + (v-V)^2 + (w-W)^2 + xi^2) Y>/2 =
+//   F4 - U F1 - V F2 - W F3 + (|U|^2/2 + U^2) F0 - U V4 + U V V2 + U W V3 - U |U|^2/2 V0
 template <typename R>
-GKS_HD void side_terms(const Params &p, const Prim<R> &g, const Tab<R> &Th, const R gr[3][5], R tau,
-                       const R cF[2][3], const R cW[2][3], R gc[3][5], R Fo[2][5], R Wo[2][5],
-                       R Io[2][5])
+GKS_HD R heat_moment(const R Uc[3], const R F[5], const R V[5])
+{
+    const R U = Uc[0], Vv = Uc[1], W = Uc[2], U2 = U * U + Vv * Vv + W * W;
+    return F[4] - U * F[1] - Vv * F[2] - W * F[3] + (R(0.5) * U2 + U * U) * F[0] - U * V[4] +
+           U * Vv * V[2] + U * W * V[3] - R(0.5) * U * U2 * V[0];
+}
+
+// The interface-time coefficients of eq. 2nd-flux.  cF[k][0..5]: time
+// integrals over [0, delta_k], delta = (dt, dt/2), of the six coefficients
+// (equilibrium: 1 - e, (t + tau) e - tau, t - tau + tau e; kinetic: e,
+// -(tau + t) e, -tau e, with e = exp(-t/tau_n)); cW[0..5]: the same
+// coefficients at t = dt.  At t = 0 they are (0, 0, 0, 1, -tau, -tau).
+template <typename R>
+struct TimeCoef {
+    R tau, cF[2][6], cW[6];
+};
+
+template <typename R, bool VISC>
+GKS_HD void time_coefficients(R tau, R taun, R dt, TimeCoef<R> &tc)
+{
+    tc.tau = tau;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const R del = k == 0 ? dt : R(0.5) * dt;
+        const R e = exp(-del / taun);
+        const R E1 = taun * (R(1) - e);
+        const R E2 = taun * taun * (R(1) - e) - taun * del * e;
+        if (VISC) {
+            tc.cF[k][0] = del - E1;
+            tc.cF[k][1] = E2 + tau * E1 - tau * del;
+            tc.cF[k][2] = R(0.5) * del * del - tau * del + tau * E1;
+            tc.cF[k][3] = E1;
+            tc.cF[k][4] = -(tau * E1 + E2);
+            tc.cF[k][5] = -tau * E1;
+        } else {
+            tc.cF[k][0] = del - E1;
+            tc.cF[k][1] = E2;
+            tc.cF[k][2] = R(0.5) * del * del;
+            tc.cF[k][3] = E1;
+            tc.cF[k][4] = -E2;
+            tc.cF[k][5] = R(0);
+        }
+    }
+    const R et = exp(-dt / taun);
+    tc.cW[0] = R(1) - et;
+    tc.cW[3] = et;
+    if (VISC) {
+        tc.cW[1] = (dt + tau) * et - tau;
+        tc.cW[2] = dt - tau + tau * et;
+        tc.cW[4] = -(tau + dt) * et;
+        tc.cW[5] = -tau * et;
+    } else {
+        tc.cW[1] = dt * et;
+        tc.cW[2] = dt;
+        tc.cW[4] = -dt * et;
+        tc.cW[5] = R(0);
+    }
+}
+
+// Adds the part a, b, c of eq. 2nd-flux with moment vectors F_j = <u psi Y_j>,
+// V_j = <psi Y_j> (Y_0 = 1, Y_1 = slopes term, Y_2 = time-slope term) to the
+// time integrals Fo, the point values Wo (t = 0, dt), and, with the Prandtl
+// correction, the heat flux into the energy flux.
+template <typename R, bool PRFIX>
+GKS_HD void add_part(const Params &p, R rho, const R *cF0, const R *cF1, const R *cW0, const R *cW1,
+                     const R F[3][5], const R V[3][5], const R Uc[3], R Fo[2][5], R Wo[2][5])
+{
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        Fo[0][q] += rho * (cF0[0] * F[0][q] + cF0[1] * F[1][q] + cF0[2] * F[2][q]);
+        Fo[1][q] += rho * (cF1[0] * F[0][q] + cF1[1] * F[1][q] + cF1[2] * F[2][q]);
+        Wo[0][q] += rho * (cW0[0] * V[0][q] + cW0[1] * V[1][q] + cW0[2] * V[2][q]);
+        Wo[1][q] += rho * (cW1[0] * V[0][q] + cW1[1] * V[1][q] + cW1[2] * V[2][q]);
+    }
+    if (PRFIX) {
+        const R fac = R(1.0 / p.prandtl - 1.0);
+        const R h0 = heat_moment(Uc, F[0], V[0]), h1 = heat_moment(Uc, F[1], V[1]),
+                h2 = heat_moment(Uc, F[2], V[2]);
+        Fo[0][4] += fac * rho * (cF0[0] * h0 + cF0[1] * h1 + cF0[2] * h2);
+        Fo[1][4] += fac * rho * (cF1[0] * h0 + cF1[1] * h1 + cF1[2] * h2);
+    }
+}
+
+// Kinetic part of one side (u > 0 for the left state, u < 0 for the right),
+// given its half-line seeds <1>, <u>: the slopes' contribution to the
+// interface gradients gc, and the side's terms of eq. 2nd-flux.
+template <typename R, bool VISC, bool PRFIX>
+GKS_HD void side_terms(const Params &p, const Prim<R> &g, R m0, R m1, const R gr[3][5],
+                       const TimeCoef<R> &tc, const R Uc[3], R gc[3][5], R Fo[2][5], R Wo[2][5])
 {
     const R K = R(p.K);
-    R a[3][5];
-    const R ir = R(1) / g.rho;
+    Tab<R> Th;
+    {
+        const R h = R(0.5) / g.lam;
+        Th.u[0] = m0;
+        Th.u[1] = m1;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        R b[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) b[q] = gr[d][q] * ir;
-        micro_slope(g, K, b, a[d]);
-        contract<0, 0, 0>(Th, a[d], g.rho, gc[d]);
+        for (int k = 0; k + 2 < 7; ++k) Th.u[k + 2] = g.U * Th.u[k + 1] + R(k + 1) * h * Th.u[k];
     }
-    // <u psi>, sum_d <u u_d (a_d.psi) psi>, and their point-value analogues
-    R F0[5], F1[5] = {R(0), R(0), R(0), R(0), R(0)}, V0[5], V1[5] = {R(0), R(0), R(0), R(0), R(0)};
-    psi_mom<1, 0, 0>(Th, F0);
-    psi_mom<0, 0, 0>(Th, V0);
-    contract<2, 0, 0>(Th, a[0], R(1), F1);
-    contract<1, 1, 0>(Th, a[1], R(1), F1);
-    contract<1, 0, 1>(Th, a[2], R(1), F1);
-    contract<1, 0, 0>(Th, a[0], R(1), V1);
-    contract<0, 1, 0>(Th, a[1], R(1), V1);
-    contract<0, 0, 1>(Th, a[2], R(1), V1);
-    R F2[5] = {R(0), R(0), R(0), R(0), R(0)}, V2[5] = {R(0), R(0), R(0), R(0), R(0)};
-    if (tau > R(0)) {
-        // A of this side from its full-space compatibility condition
-        Tab<R> Tf;
+    vw_tables(g, K, Th);
+    R F[3][5], V[3][5];
+    psi_mom<1, 0, 0>(Th, F[0]);
+    psi_mom<0, 0, 0>(Th, V[0]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) F[1][q] = V[1][q] = F[2][q] = V[2][q] = R(0);
+    R B[5] = {R(0), R(0), R(0), R(0), R(0)};
+    Tab<R> Tf;
+    if (VISC) {
         gauss_moments<7>(g.U, g.lam, Tf.u);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
@@ -194,151 +272,137 @@ GKS_HD void side_terms(const Params &p, const Prim<R> &g, const Tab<R> &Th, cons
         }
         Tf.xi2 = Th.xi2;
         Tf.xi4 = Th.xi4;
-        R B[5] = {R(0), R(0), R(0), R(0), R(0)}, A[5];
-        contract<1, 0, 0>(Tf, a[0], R(-1), B);
-        contract<0, 1, 0>(Tf, a[1], R(-1), B);
-        contract<0, 0, 1>(Tf, a[2], R(-1), B);
-        micro_slope(g, K, B, A);
-        contract<1, 0, 0>(Th, A, R(1), F2);
-        contract<0, 0, 0>(Th, A, R(1), V2);
     }
+    const R ir = R(1) / g.rho;
+    // one direction at a time: a_d, its share of g^c_{x_d}, of
+    // sum_d <u u_d (a_d.psi) psi> and of sum_d <u_d (a_d.psi) psi>
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int d = 0; d < 3; ++d) {
+        R b[5], a[5];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            Fo[k][q] += g.rho * (cF[k][0] * F0[q] + cF[k][1] * F1[q] + cF[k][2] * F2[q]);
-            Wo[k][q] += g.rho * (cW[k][0] * V0[q] + cW[k][1] * V1[q] + cW[k][2] * V2[q]);
-            Io[k][q] += g.rho * (cF[k][0] * V0[q] + cF[k][1] * V1[q] + cF[k][2] * V2[q]);
+        for (int q = 0; q < 5; ++q) b[q] = gr[d][q] * ir;
+        micro_slope(g, K, b, a);
+        contract<0, 0, 0>(Th, a, g.rho, gc[d]);
+        if (d == 0) {
+            contract<2, 0, 0>(Th, a, R(1), F[1]);
+            contract<1, 0, 0>(Th, a, R(1), V[1]);
+            if (VISC) contract<1, 0, 0>(Tf, a, R(-1), B);
+        } else if (d == 1) {
+            contract<1, 1, 0>(Th, a, R(1), F[1]);
+            contract<0, 1, 0>(Th, a, R(1), V[1]);
+            if (VISC) contract<0, 1, 0>(Tf, a, R(-1), B);
+        } else {
+            contract<1, 0, 1>(Th, a, R(1), F[1]);
+            contract<0, 0, 1>(Th, a, R(1), V[1]);
+            if (VISC) contract<0, 0, 1>(Tf, a, R(-1), B);
         }
+    }
+    if (VISC) {
+        // A of this side from its full-space compatibility condition
+        R A[5];
+        micro_slope(g, K, B, A);
+        contract<1, 0, 0>(Th, A, R(1), F[2]);
+        contract<0, 0, 0>(Th, A, R(1), V[2]);
+    }
+    const R cW0[3] = {R(1), -tc.tau, -tc.tau};
+    add_part<R, PRFIX>(p, g.rho, tc.cF[0] + 3, tc.cF[1] + 3, cW0, tc.cW + 3, F, V, Uc, Fo, Wo);
 }
 
 // Time-dependent distribution of eq. 2nd-flux at one interface point, face
 // frame.  Outputs: Fo[0] = F(dt), Fo[1] = F(dt/2) (time integrals of the
 // flux), Wo[0] = W(0), Wo[1] = W(dt).
-template <typename R>
+template <typename R, bool VISC, bool PRFIX>
 GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], const R wr[5],
                       const R gr[3][5], R Fo[2][5], R Wo[2][5])
 {
     const R K = R(p.K);
     const Prim<R> gL = primitive(wl, K), gR = primitive(wr, K);
-    Tab<R> TL, TR;
-    half_moments<7>(gL.U, gL.lam, true, TL.u);
-    vw_tables(gL, K, TL);
-    half_moments<7>(gR.U, gR.lam, false, TR.u);
-    vw_tables(gR, K, TR);
-    // eq. new-equ-part: W^c from the two half Maxwellians
-    R Wc[5], t[5];
-    psi_mom<0, 0, 0>(TL, Wc);
-    psi_mom<0, 0, 0>(TR, t);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) Wc[q] = gL.rho * Wc[q] + gR.rho * t[q];
+    // half-line seeds <1> and <u> of both sides
+    R l0, l1, r0, r1;
+    {
+        const R sl = sqrt(gL.lam), e = exp(-gL.lam * gL.U * gL.U) / (R(2) * sqrt(R(M_PI) * gL.lam));
+        l0 = R(0.5) * erfc(-sl * gL.U);
+        l1 = gL.U * l0 + e;
+        const R sr = sqrt(gR.lam), f = exp(-gR.lam * gR.U * gR.U) / (R(2) * sqrt(R(M_PI) * gR.lam));
+        r0 = R(0.5) * erfc(sr * gR.U);
+        r1 = gR.U * r0 - f;
+    }
+    // eq. new-equ-part: W^c = rho_l <psi>_{u>0} + rho_r <psi>_{u<0}
+    R Wc[5];
+    {
+        const R hl = R(0.5) / gL.lam, hr = R(0.5) / gR.lam;
+        const R l2 = gL.U * l1 + hl * l0, r2 = gR.U * r1 + hr * r0;
+        const R tl = gL.V * gL.V + gL.W * gL.W + (R(2) + K) * hl;
+        const R tr = gR.V * gR.V + gR.W * gR.W + (R(2) + K) * hr;
+        Wc[0] = gL.rho * l0 + gR.rho * r0;
+        Wc[1] = gL.rho * l1 + gR.rho * r1;
+        Wc[2] = gL.rho * (gL.V * l0) + gR.rho * (gR.V * r0);
+        Wc[3] = gL.rho * (gL.W * l0) + gR.rho * (gR.W * r0);
+        Wc[4] = gL.rho * (R(0.5) * (l2 + l0 * tl)) + gR.rho * (R(0.5) * (r2 + r0 * tr));
+    }
     const Prim<R> gC = primitive(Wc, K);
+    const R Uc[3] = {gC.U, gC.V, gC.W};
     // collision times (Sec. 2.2)
     const R pl = gL.rho * R(0.5) / gL.lam, pr = gR.rho * R(0.5) / gR.lam, pc = gC.rho * R(0.5) / gC.lam;
     const R jump = R(p.c_tau) * fabs((pl - pr) / (pl + pr)) * dt;
     R tau, taun;
-    if (p.viscous) {
+    if (VISC) {
         tau = R(p.mu) / pc;
-        taun = R(p.mu) / pc + jump;
+        taun = tau + jump;
     } else {
         tau = R(0);
         taun = R(p.eps_tau) * dt + jump;
     }
-    // time integrals over [0, delta] of the coefficients of eq. 2nd-flux (tau_n
-    // in the exponentials, tau elsewhere) for delta = dt, dt/2, and the point
-    // coefficients at t = 0, dt
-    R cF[2][6], cW[2][6];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const R del = k == 0 ? dt : R(0.5) * dt;
-        const R e = exp(-del / taun);
-        const R E1 = taun * (R(1) - e);
-        const R E2 = taun * taun * (R(1) - e) - taun * del * e;
-        cF[k][0] = del - E1;
-        cF[k][1] = E2 + tau * E1 - tau * del;
-        cF[k][2] = R(0.5) * del * del - tau * del + tau * E1;
-        cF[k][3] = E1;
-        cF[k][4] = -(tau * E1 + E2);
-        cF[k][5] = -tau * E1;
-        const R tt = k == 0 ? R(0) : dt;
-        const R et = k == 0 ? R(1) : exp(-tt / taun);
-        cW[k][0] = R(1) - et;
-        cW[k][1] = (tt + tau) * et - tau;
-        cW[k][2] = tt - tau + tau * et;
-        cW[k][3] = et;
-        cW[k][4] = -(tau + tt) * et;
-        cW[k][5] = -tau * et;
-    }
+    TimeCoef<R> tc;
+    time_coefficients<R, VISC>(tau, taun, dt, tc);
 #pragma unroll
     for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            Fo[k][q] = R(0);
-            Wo[k][q] = R(0);
-        }
-    R Io[2][5]; // time integrals of W(t), for the Prandtl correction
+        for (int q = 0; q < 5; ++q) Fo[k][q] = Wo[k][q] = R(0);
     R gc[3][5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        Io[0][q] = Io[1][q] = R(0);
-        gc[0][q] = gc[1][q] = gc[2][q] = R(0);
-    }
-    {
-        const R cFk[2][3] = {{cF[0][3], cF[0][4], cF[0][5]}, {cF[1][3], cF[1][4], cF[1][5]}};
-        const R cWk[2][3] = {{cW[0][3], cW[0][4], cW[0][5]}, {cW[1][3], cW[1][4], cW[1][5]}};
-        side_terms(p, gL, TL, gl, tau, cFk, cWk, gc, Fo, Wo, Io);
-        side_terms(p, gR, TR, gr, tau, cFk, cWk, gc, Fo, Wo, Io);
-    }
-    // equilibrium part: g^c, its slopes a^c and A^c
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) gc[d][q] = R(0);
+    side_terms<R, VISC, PRFIX>(p, gL, l0, l1, gl, tc, Uc, gc, Fo, Wo);
+    side_terms<R, VISC, PRFIX>(p, gR, r0, r1, gr, tc, Uc, gc, Fo, Wo);
+    // equilibrium part: g^c with slopes a^c (from g^c_x) and A^c
     Tab<R> TC;
     gauss_moments<7>(gC.U, gC.lam, TC.u);
     vw_tables(gC, K, TC);
-    R ac[3][5];
+    R F[3][5], V[3][5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) F[1][q] = V[1][q] = F[2][q] = V[2][q] = R(0);
     const R irc = R(1) / gC.rho;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        R b[5];
+        R b[5], a[5];
 #pragma unroll
         for (int q = 0; q < 5; ++q) b[q] = gc[d][q] * irc;
-        micro_slope(gC, K, b, ac[d]);
-    }
-    R Bc[5] = {R(0), R(0), R(0), R(0), R(0)}, nB[5], Ac[5];
-    contract<1, 0, 0>(TC, ac[0], R(1), Bc);
-    contract<0, 1, 0>(TC, ac[1], R(1), Bc);
-    contract<0, 0, 1>(TC, ac[2], R(1), Bc);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) nB[q] = -Bc[q];
-    micro_slope(gC, K, nB, Ac);
-    R F0[5], F1[5] = {R(0), R(0), R(0), R(0), R(0)}, F2[5] = {R(0), R(0), R(0), R(0), R(0)}, V0[5],
-             V2[5] = {R(0), R(0), R(0), R(0), R(0)};
-    psi_mom<1, 0, 0>(TC, F0);
-    psi_mom<0, 0, 0>(TC, V0);
-    contract<2, 0, 0>(TC, ac[0], R(1), F1);
-    contract<1, 1, 0>(TC, ac[1], R(1), F1);
-    contract<1, 0, 1>(TC, ac[2], R(1), F1);
-    contract<1, 0, 0>(TC, Ac, R(1), F2);
-    contract<0, 0, 0>(TC, Ac, R(1), V2);
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            Fo[k][q] += gC.rho * (cF[k][0] * F0[q] + cF[k][1] * F1[q] + cF[k][2] * F2[q]);
-            Wo[k][q] += gC.rho * (cW[k][0] * V0[q] + cW[k][1] * Bc[q] + cW[k][2] * V2[q]);
-            Io[k][q] += gC.rho * (cF[k][0] * V0[q] + cF[k][1] * Bc[q] + cF[k][2] * V2[q]);
-        }
-    if (p.prandtl != 1.0) {
-        // heat flux about U^c of the time-integrated distribution, from the
-        // integrated flux and state: (u-U)((u-U)^2 + (v-V)^2 + (w-W)^2 + xi^2)/2
-        const R U = gC.U, V = gC.V, W = gC.W, U2 = U * U + V * V + W * W;
-        const R fac = R(1.0 / p.prandtl - 1.0);
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const R *F = Fo[k], *I = Io[k];
-            const R q = F[4] - U * F[1] - V * F[2] - W * F[3] + (R(0.5) * U2 + U * U) * F[0] -
-                        U * I[4] + U * V * I[2] + U * W * I[3] - R(0.5) * U * U2 * I[0];
-            Fo[k][4] += fac * q;
+        micro_slope(gC, K, b, a);
+        if (d == 0) {
+            contract<1, 0, 0>(TC, a, R(1), V[1]);
+            contract<2, 0, 0>(TC, a, R(1), F[1]);
+        } else if (d == 1) {
+            contract<0, 1, 0>(TC, a, R(1), V[1]);
+            contract<1, 1, 0>(TC, a, R(1), F[1]);
+        } else {
+            contract<0, 0, 1>(TC, a, R(1), V[1]);
+            contract<1, 0, 1>(TC, a, R(1), F[1]);
         }
     }
+    {
+        R nB[5], Ac[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) nB[q] = -V[1][q];
+        micro_slope(gC, K, nB, Ac);
+        contract<1, 0, 0>(TC, Ac, R(1), F[2]);
+        contract<0, 0, 0>(TC, Ac, R(1), V[2]);
+    }
+    psi_mom<1, 0, 0>(TC, F[0]);
+    psi_mom<0, 0, 0>(TC, V[0]);
+    const R cW0[3] = {R(0), R(0), R(0)};
+    add_part<R, PRFIX>(p, gC.rho, tc.cF[0], tc.cF[1], cW0, tc.cW, F, V, Uc, Fo, Wo);
 }
 
 // rotation of eq. rotate-matrix-3d (Lambda when n1 = -1)
@@ -400,44 +464,56 @@ GKS_HD void to_global(const R T[3][3], const R l[5], R gout[5])
     for (int a = 0; a < 3; ++a) gout[1 + a] = T[0][a] * l[1] + T[1][a] * l[2] + T[2][a] * l[3];
 }
 
-// All terms of one face: acc[0] = |Gamma| sum_k w_k F_k, acc[1] the same for
-// dF/dt (eq. linear-system), acc[2] / acc[3] the same for W_k(0) / W_k(dt).
-// rl[k]: Gauss point k relative to the owner centroid; dv: owner centroid
-// minus the neighbour's (translated) centroid.
-template <typename R, typename CoefL, typename CoefR>
-GKS_HD void face_terms(const Params &p, R dt, const R nrm[3], R area, const R rl[3][3], const R dv[3],
-                       const CoefL &cl, const CoefR &cr, R acc[4][5])
+// Terms of one Gauss point k of a face, weighted by w_k |Gamma| = |Gamma|/3:
+// acc[0] = F_k, acc[1] = dF_k/dt (eq. linear-system), acc[2] = W_k(0),
+// acc[3] = W_k(dt), all in the global frame.  r: the Gauss point relative to
+// the owner centroid; dv: owner centroid minus the neighbour's (translated).
+template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR>
+GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, const R r[3], const R dv[3],
+                              const CoefL &cl, const CoefR &cr, R acc[4][5])
 {
     const R w = area * R(1.0 / 3.0);
     R T[3][3];
     rotation(nrm, T);
+    R rr[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) rr[d] = r[d] + dv[d];
+    R wl[5], gl[3][5], wr[5], gr[3][5];
+    eval_local(cl, r, T, wl, gl);
+    eval_local(cr, rr, T, wr, gr);
+    R Fo[2][5], Wo[2][5];
+    gks_point<R, VISC, PRFIX>(p, dt, wl, gl, wr, gr, Fo, Wo);
+    R F1[5], Fh[5], W0[5], W1[5];
+    to_global(T, Fo[0], F1);
+    to_global(T, Fo[1], Fh);
+    to_global(T, Wo[0], W0);
+    to_global(T, Wo[1], W1);
+    const R idt = R(1) / dt;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        acc[0][q] = w * (R(4) * Fh[q] - F1[q]) * idt;
+        acc[1][q] = w * R(4) * (F1[q] - R(2) * Fh[q]) * (idt * idt);
+        acc[2][q] = w * W0[q];
+        acc[3][q] = w * W1[q];
+    }
+}
+
+// All terms of one face: the sum over its three Gauss points, in order.
+template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR>
+GKS_HD void face_terms(const Params &p, R dt, const R nrm[3], R area, const R rl[3][3], const R dv[3],
+                       const CoefL &cl, const CoefR &cr, R acc[4][5])
+{
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[a][q] = R(0);
-    const R idt = R(1) / dt;
     for (int k = 0; k < 3; ++k) {
-        R rr[3];
+        R t[4][5];
+        gauss_point_terms<R, VISC, PRFIX>(p, dt, nrm, area, rl[k], dv, cl, cr, t);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) rr[d] = rl[k][d] + dv[d];
-        R wl[5], gl[3][5], wr[5], gr[3][5];
-        eval_local(cl, rl[k], T, wl, gl);
-        eval_local(cr, rr, T, wr, gr);
-        R Fo[2][5], Wo[2][5];
-        gks_point(p, dt, wl, gl, wr, gr, Fo, Wo);
-        R F1[5], Fh[5], W0[5], W1[5];
-        to_global(T, Fo[0], F1);
-        to_global(T, Fo[1], Fh);
-        to_global(T, Wo[0], W0);
-        to_global(T, Wo[1], W1);
-        // eq. linear-system
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            acc[0][q] += w * (R(4) * Fh[q] - F1[q]) * idt;
-            acc[1][q] += w * R(4) * (F1[q] - R(2) * Fh[q]) * (idt * idt);
-            acc[2][q] += w * W0[q];
-            acc[3][q] += w * W1[q];
-        }
+            for (int q = 0; q < 5; ++q) acc[a][q] += t[a][q];
     }
 }
 

@@ -55,27 +55,38 @@ __global__ __launch_bounds__(kBlock) void slopes_kernel(DevMesh m, DevState s)
 // ===========================================================================
 __device__ __forceinline__ double pow43(double x) { return pow(x, 4.0 / 3.0); }
 
-__global__ __launch_bounds__(kBlock) void reconstruct_kernel(DevMesh m, DevState s, Params p)
-{
-    const int i = gid();
-    const int n = m.nc;
-    if (i >= n) return;
-    const double *geo = m.geo;
-    const double vol23 = geo[(size_t)G_VOL23 * n + i];
-    const double vol43 = geo[(size_t)G_VOL43 * n + i];
-    double C[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) C[k] = geo[(size_t)(G_C + k) * n + i];
-    int nb[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) nb[a] = m.nbr[a * n + i];
+// One block reconstructs kRecCells cells with one wavefront per conservative
+// component: thread (q, l) fits component q of cell l, so each thread holds a
+// single component's stencil and coefficients.  The five wavefronts read the
+// same rows of M2 (one HBM read, four cache hits).  The coefficients meet in
+// LDS for the cell-wide positivity check: wavefront a evaluates the three
+// Gauss points of the face opposite vertex a, wavefront 4 checks the cell
+// average.
+constexpr int kRecCells = 64;
+constexpr int kRecThreads = 5 * kRecCells;
 
-    double R[5][10];
-    double Q0s[5];
+__global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, DevState s, Params p)
+{
+    __shared__ double sR[5][10][kRecCells];
+    __shared__ double sQ0[5][kRecCells];
+    __shared__ int sBad[5][kRecCells];
+    const int n = m.nc;
+    const int q = threadIdx.x / kRecCells;  // component, uniform over the wavefront
+    const int l = threadIdx.x % kRecCells;
+    const int i = blockIdx.x * kRecCells + l;
+    const bool live = i < n;
+    const double *geo = m.geo;
+
+    if (live) {
+        const double vol23 = geo[(size_t)G_VOL23 * n + i];
+        const double vol43 = geo[(size_t)G_VOL43 * n + i];
+        double C[6];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
+        for (int k = 0; k < 6; ++k) C[k] = geo[(size_t)(G_C + k) * n + i];
+        int nb[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) nb[a] = m.nbr[a * n + i];
         const double Q0 = s.W[(size_t)q * n + i];
-        Q0s[q] = Q0;
         double d[16];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
@@ -93,126 +104,151 @@ __global__ __launch_bounds__(kBlock) void reconstruct_kernel(DevMesh m, DevState
             for (int k = 0; k < 16; ++k) acc += m.M2[(size_t)(16 * r + k) * n + i] * d[k];
             c[r] = acc;
         }
-        // P^2 about the centroid: value at the centroid keeps the mean
+        // P^2 about the centroid: its value at the centroid keeps the mean
         const double c0 = Q0 - 0.5 * (c[3] * C[0] + c[4] * C[1] + c[5] * C[2]) -
                           (c[6] * C[3] + c[7] * C[4] + c[8] * C[5]);
+        double R[10];
         if (!p.nonlinear) {
-            R[q][0] = c0;
+            R[0] = c0;
 #pragma unroll
-            for (int k = 0; k < 9; ++k) R[q][1 + k] = c[k];
-            continue;
-        }
-        double b[3];
+            for (int k = 0; k < 9; ++k) R[1 + k] = c[k];
+        } else {
+            double b[3];
 #pragma unroll
-        for (int dd = 0; dd < 3; ++dd) b[dd] = s.slopes[(size_t)(3 * q + dd) * n + i];
-        // beta_1 = |Omega|^(2/3) |b|^2
-        const double beta1 = vol23 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
-        // beta_2 = |Omega|^(2/3) (|g|^2 + tr(H C H)) + |Omega|^(4/3) sum of the six H^2
-        const double Hm[3][3] = {{c[3], c[6], c[7]}, {c[6], c[4], c[8]}, {c[7], c[8], c[5]}};
-        const double Cm[3][3] = {{C[0], C[3], C[4]}, {C[3], C[1], C[5]}, {C[4], C[5], C[2]}};
-        double trHCH = 0.0;
+            for (int dd = 0; dd < 3; ++dd) b[dd] = s.slopes[(size_t)(3 * q + dd) * n + i];
+            // beta_1 = |Omega|^(2/3) |b|^2
+            const double beta1 = vol23 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+            // beta_2 = |Omega|^(2/3) (|g|^2 + tr(H C H)) + |Omega|^(4/3) sum of the six H^2
+            const double Hm[3][3] = {{c[3], c[6], c[7]}, {c[6], c[4], c[8]}, {c[7], c[8], c[5]}};
+            const double Cm[3][3] = {{C[0], C[3], C[4]}, {C[3], C[1], C[5]}, {C[4], C[5], C[2]}};
+            double trHCH = 0.0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+            for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int bb = 0; bb < 3; ++bb) {
-                double hc = 0.0;
+                for (int bb = 0; bb < 3; ++bb) {
+                    double hc = 0.0;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) hc += Hm[a][k] * Cm[k][bb];
-                trHCH += hc * Hm[bb][a];
+                    for (int k = 0; k < 3; ++k) hc += Hm[a][k] * Cm[k][bb];
+                    trHCH += hc * Hm[bb][a];
+                }
+            double h2 = 0.0;
+#pragma unroll
+            for (int k = 3; k < 9; ++k) h2 += c[k] * c[k];
+            const double beta2 = vol23 * (c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + trHCH) + vol43 * h2;
+            // beta_0 from the neighbours' slopes (eq. p0-non-linear-weight), over
+            // the neighbours present, pairs (j, k < j) in slot order
+            double b0[4];
+            bool hv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                hv[a] = nb[a] >= 0;
+                double ss = 0.0;
+                if (hv[a]) {
+#pragma unroll
+                    for (int dd = 0; dd < 3; ++dd) {
+                        const double v = s.slopes[(size_t)(3 * q + dd) * n + nb[a]];
+                        ss += v * v;
+                    }
+                }
+                b0[a] = vol23 * ss;
             }
-        double h2 = 0.0;
+            double beta0 = 0.0;
+            {
+                double sum = 0.0;
+                int np = 0, nn = 0;
 #pragma unroll
-        for (int k = 3; k < 9; ++k) h2 += c[k] * c[k];
-        const double beta2 = vol23 * (c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + trHCH) + vol43 * h2;
-        // beta_0 from the neighbours' slopes (eq. p0-non-linear-weight)
-        double b0[4];
-        int nn = 0;
+                for (int j = 0; j < 4; ++j) {
+                    nn += hv[j] ? 1 : 0;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            if (nb[a] < 0) continue;
-            double ss = 0.0;
+                    for (int k = 0; k < j; ++k)
+                        if (hv[j] && hv[k]) {
+                            sum += fabs(b0[j] - b0[k]);
+                            ++np;
+                        }
+                }
+                if (nn > 0) {
+                    const double sig1 = np ? pow43(sum / np) : 0.0;
+                    double w[4], ws = 0.0;
 #pragma unroll
-            for (int dd = 0; dd < 3; ++dd) {
-                const double v = s.slopes[(size_t)(3 * q + dd) * n + nb[a]];
-                ss += v * v;
+                    for (int j = 0; j < 4; ++j) {
+                        w[j] = hv[j] ? 1.0 + sig1 / (p.eps_weno + b0[j]) : 0.0;
+                        if (hv[j]) ws += w[j];
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (hv[j]) beta0 += (w[j] / ws) * b0[j];
+                }
             }
-            b0[nn++] = vol23 * ss;
-        }
-        double beta0 = 0.0;
-        if (nn > 0) {
-            double sum = 0.0;
-            int np = 0;
-            for (int j = 0; j < nn; ++j)
-                for (int k = 0; k < j; ++k) { sum += fabs(b0[j] - b0[k]); ++np; }
-            const double sig1 = np ? pow43(sum / np) : 0.0;
-            double w[4], ws = 0.0;
-            for (int j = 0; j < nn; ++j) { w[j] = 1.0 + sig1 / (p.eps_weno + b0[j]); ws += w[j]; }
-            for (int j = 0; j < nn; ++j) beta0 += (w[j] / ws) * b0[j];
-        }
-        const double sig = pow43(0.5 * (fabs(beta2 - beta1) + fabs(beta2 - beta0)));
-        const double r2 = sig / (p.eps_weno + beta2), r1 = sig / (p.eps_weno + beta1),
-                     r0 = sig / (p.eps_weno + beta0);
-        double w2 = p.g22 * (1.0 + r2 * r2);
-        double w1 = p.g12 * (1.0 + r1 * r1);
-        double w0 = p.g02 * (1.0 + r0 * r0);
-        const double ws = w0 + w1 + w2;
-        w2 /= ws;
-        w1 /= ws;
-        w0 /= ws;
-        (void)w0;
-        // R = w22 p2 + w12 p1 + w02 p0 collapsed: Q0 + alpha (P^2 - Q0) + lin (P^1 - Q0)
-        const double alpha = w2 / p.g22;
-        const double lin = w1 / p.g11 - w2 * p.g12 / (p.g22 * p.g11);
-        R[q][0] = Q0 + alpha * (c0 - Q0);
+            const double sig = pow43(0.5 * (fabs(beta2 - beta1) + fabs(beta2 - beta0)));
+            const double r2 = sig / (p.eps_weno + beta2), r1 = sig / (p.eps_weno + beta1),
+                         r0 = sig / (p.eps_weno + beta0);
+            double w2 = p.g22 * (1.0 + r2 * r2);
+            double w1 = p.g12 * (1.0 + r1 * r1);
+            const double w0 = p.g02 * (1.0 + r0 * r0);
+            const double ws = w0 + w1 + w2;
+            w2 /= ws;
+            w1 /= ws;
+            // R = w22 p2 + w12 p1 + w02 p0 collapsed: Q0 + alpha (P^2 - Q0) + lin (P^1 - Q0)
+            const double alpha = w2 / p.g22;
+            const double lin = w1 / p.g11 - w2 * p.g12 / (p.g22 * p.g11);
+            R[0] = Q0 + alpha * (c0 - Q0);
 #pragma unroll
-        for (int dd = 0; dd < 3; ++dd) R[q][1 + dd] = alpha * c[dd] + lin * b[dd];
+            for (int dd = 0; dd < 3; ++dd) R[1 + dd] = alpha * c[dd] + lin * b[dd];
 #pragma unroll
-        for (int k = 3; k < 9; ++k) R[q][1 + k] = alpha * c[k];
+            for (int k = 3; k < 9; ++k) R[1 + k] = alpha * c[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 10; ++k) sR[q][k][l] = R[k];
+        sQ0[q][l] = Q0;
     }
+    __syncthreads();
 
-    // non-physical cell average: flag it (the fallback cannot repair it)
-    {
-        const double rho = Q0s[0];
-        const double pr = (p.gamma - 1.0) *
-                          (Q0s[4] - 0.5 * (Q0s[1] * Q0s[1] + Q0s[2] * Q0s[2] + Q0s[3] * Q0s[3]) / rho);
-        if (!(rho > 0.0) || !(pr > 0.0)) *s.nonphys = 1;
-    }
-    // positivity at the Gauss points of the four faces: GP = r_k / 2 - r_a / 6
-    double rv[4][3];
+    int bad = 0;
+    if (live) {
+        if (q < 4) {
+            // Gauss points of the face opposite vertex q: r_k / 2 - r_q / 6, k != q
+            double rv[4][3];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int dd = 0; dd < 3; ++dd) rv[a][dd] = geo[(size_t)(G_RV + 3 * a + dd) * n + i];
-    bool bad = false;
+                for (int dd = 0; dd < 3; ++dd) rv[a][dd] = geo[(size_t)(G_RV + 3 * a + dd) * n + i];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+            for (int k = 0; k < 4; ++k) {
+                if (k == q) continue;
+                double r[3];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (k == a) continue;
-            double r[3];
+                for (int dd = 0; dd < 3; ++dd) r[dd] = 0.5 * rv[k][dd] - rv[q][dd] / 6.0;
+                double v[5];
 #pragma unroll
-            for (int dd = 0; dd < 3; ++dd) r[dd] = 0.5 * rv[k][dd] - rv[a][dd] / 6.0;
-            double v[5];
+                for (int c = 0; c < 5; ++c) {
+                    double cf[10];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                const double *c = R[q];
-                v[q] = c[0] + c[1] * r[0] + c[2] * r[1] + c[3] * r[2] +
-                       0.5 * (c[4] * r[0] * r[0] + c[5] * r[1] * r[1] + c[6] * r[2] * r[2]) +
-                       c[7] * r[0] * r[1] + c[8] * r[0] * r[2] + c[9] * r[1] * r[2];
+                    for (int kk = 0; kk < 10; ++kk) cf[kk] = sR[c][kk][l];
+                    v[c] = cf[0] + cf[1] * r[0] + cf[2] * r[1] + cf[3] * r[2] +
+                           0.5 * (cf[4] * r[0] * r[0] + cf[5] * r[1] * r[1] + cf[6] * r[2] * r[2]) +
+                           cf[7] * r[0] * r[1] + cf[8] * r[0] * r[2] + cf[9] * r[1] * r[2];
+                }
+                const double pr =
+                    (p.gamma - 1.0) * (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
+                if (!(v[0] > 0.0) || !(pr > 0.0)) bad = 1;
             }
-            const double pr =
-                (p.gamma - 1.0) * (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
-            bad = bad || !(v[0] > 0.0) || !(pr > 0.0);
+        } else {
+            // a non-physical cell average cannot be repaired by the fallback
+            const double rho = sQ0[0][l];
+            const double pr = (p.gamma - 1.0) *
+                              (sQ0[4][l] - 0.5 * (sQ0[1][l] * sQ0[1][l] + sQ0[2][l] * sQ0[2][l] +
+                                                  sQ0[3][l] * sQ0[3][l]) / rho);
+            if (!(rho > 0.0) || !(pr > 0.0)) *s.nonphys = 1;
         }
     }
-    s.flag[i] = bad ? 1 : 0;
+    sBad[q][l] = bad;
+    __syncthreads();
+    if (live) {
+        const bool anybad = (sBad[0][l] | sBad[1][l] | sBad[2][l] | sBad[3][l]) != 0;
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-#pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            const double v = bad ? (k == 0 ? Q0s[q] : 0.0) : R[q][k];
-            s.coef[(size_t)(10 * q + k) * n + i] = v;
-        }
+        for (int k = 0; k < 10; ++k)
+            s.coef[(size_t)(10 * q + k) * n + i] = anybad ? (k == 0 ? sQ0[q][l] : 0.0) : sR[q][k][l];
+        if (q == 0) s.flag[i] = anybad ? 1 : 0;
     }
 }
 
@@ -228,27 +264,51 @@ struct DevCoef {
     }
 };
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void flux_kernel(DevMesh m, DevState s, Params p, double dt)
+// Three lanes per face, one per Gauss point: 21 faces per wavefront (lane 63
+// idle).  The lanes of a face are summed in Gauss-point order by shuffles and
+// the first lane writes the face.
+constexpr int kFluxThreads = 256;
+constexpr int kFacesPerWave = 21;
+constexpr int kFacesPerBlock = kFacesPerWave * (kFluxThreads / 64);
+
+template <int MODE, bool VISC, bool PRFIX>
+__global__ __launch_bounds__(kFluxThreads) void flux_kernel(DevMesh m, DevState s, Params p, double dt)
 {
-    const int f = gid();
     const int nf = m.nf, n = m.nc;
-    if (f >= nf) return;
-    const int L = m.fcell[f], R = m.fcell[nf + f];
-    const double *fg = m.fgeo;
-    double nrm[3], dv[3], rl[3][3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        nrm[d] = fg[(size_t)(F_N + d) * nf + f];
-        dv[d] = fg[(size_t)(F_D + d) * nf + f];
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) rl[k][d] = fg[(size_t)(F_RL + 3 * k + d) * nf + f];
-    const double area = fg[(size_t)F_AREA * nf + f];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int slot = lane / 3, k = lane - 3 * slot;
+    const int f = blockIdx.x * kFacesPerBlock + wave * kFacesPerWave + slot;
+    const bool live = slot < kFacesPerWave && f < nf;
     double acc[4][5];
-    face_terms<double>(p, dt, nrm, area, rl, dv, DevCoef{s.coef, n, L}, DevCoef{s.coef, n, R}, acc);
+    if (live) {
+        const int L = m.fcell[f], R = m.fcell[nf + f];
+        const double *fg = m.fgeo;
+        double nrm[3], dv[3], r[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            nrm[d] = fg[(size_t)(F_N + d) * nf + f];
+            dv[d] = fg[(size_t)(F_D + d) * nf + f];
+            r[d] = fg[(size_t)(F_RL + 3 * k + d) * nf + f];
+        }
+        const double area = fg[(size_t)F_AREA * nf + f];
+        gauss_point_terms<double, VISC, PRFIX>(p, dt, nrm, area, r, dv, DevCoef{s.coef, n, L},
+                                               DevCoef{s.coef, n, R}, acc);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) acc[a][q] = 0.0;
+    }
+    // sum the three Gauss points of each face onto its first lane
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const double v1 = __shfl_down(acc[a][q], 1, 64);
+            const double v2 = __shfl_down(acc[a][q], 2, 64);
+            acc[a][q] = (acc[a][q] + v1) + v2;
+        }
+    if (!live || k != 0) return;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         const size_t o = (size_t)q * nf + f;
@@ -267,6 +327,22 @@ __global__ __launch_bounds__(kBlock) void flux_kernel(DevMesh m, DevState s, Par
             s.FWs[o] = acc[3][q];
         }
     }
+}
+
+template <int MODE>
+static void launch_flux_mode(const DevMesh &m, const DevState &s, const Params &p, double dt,
+                             hipStream_t st)
+{
+    const dim3 grid((unsigned)((m.nf + kFacesPerBlock - 1) / kFacesPerBlock)), block(kFluxThreads);
+    const bool visc = p.viscous != 0, prfix = p.prandtl != 1.0;
+    if (visc && prfix)
+        hipLaunchKernelGGL((flux_kernel<MODE, true, true>), grid, block, 0, st, m, s, p, dt);
+    else if (visc)
+        hipLaunchKernelGGL((flux_kernel<MODE, true, false>), grid, block, 0, st, m, s, p, dt);
+    else if (prfix)
+        hipLaunchKernelGGL((flux_kernel<MODE, false, true>), grid, block, 0, st, m, s, p, dt);
+    else
+        hipLaunchKernelGGL((flux_kernel<MODE, false, false>), grid, block, 0, st, m, s, p, dt);
 }
 
 // ===========================================================================
@@ -471,7 +547,8 @@ hipError_t launch_slopes(const DevMesh &m, const DevState &s, hipStream_t st)
 
 hipError_t launch_reconstruct(const DevMesh &m, const DevState &s, const Params &p, hipStream_t st)
 {
-    hipLaunchKernelGGL(reconstruct_kernel, grid_for(m.nc), dim3(kBlock), 0, st, m, s, p);
+    hipLaunchKernelGGL(reconstruct_kernel, dim3((unsigned)((m.nc + kRecCells - 1) / kRecCells)),
+                       dim3(kRecThreads), 0, st, m, s, p);
     return hipGetLastError();
 }
 
@@ -479,11 +556,11 @@ hipError_t launch_flux(const DevMesh &m, const DevState &s, const Params &p, dou
                        hipStream_t st)
 {
     if (mode == FLUX_STAGE1)
-        hipLaunchKernelGGL(flux_kernel<FLUX_STAGE1>, grid_for(m.nf), dim3(kBlock), 0, st, m, s, p, dt);
+        launch_flux_mode<FLUX_STAGE1>(m, s, p, dt, st);
     else if (mode == FLUX_STAGE2)
-        hipLaunchKernelGGL(flux_kernel<FLUX_STAGE2>, grid_for(m.nf), dim3(kBlock), 0, st, m, s, p, dt);
+        launch_flux_mode<FLUX_STAGE2>(m, s, p, dt, st);
     else
-        hipLaunchKernelGGL(flux_kernel<FLUX_DEBUG>, grid_for(m.nf), dim3(kBlock), 0, st, m, s, p, dt);
+        launch_flux_mode<FLUX_DEBUG>(m, s, p, dt, st);
     return hipGetLastError();
 }
 

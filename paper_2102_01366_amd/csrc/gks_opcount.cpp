@@ -75,7 +75,15 @@ extern "C" gks_status gks_flux_op_count(const gks_config *cfg, double counts[4])
     for (int d = 0; d < 3; ++d) dv[d] = Cnt(0.02 + 0.001 * d);
     Cnt acc[4][5];
     tally = Tally{};
-    gks::face_terms<Cnt>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, HostCoef{cl}, HostCoef{cr}, acc);
+    const HostCoef L{cl}, R{cr};
+    if (p.viscous && p.prandtl != 1.0)
+        gks::face_terms<Cnt, true, true>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc);
+    else if (p.viscous)
+        gks::face_terms<Cnt, true, false>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc);
+    else if (p.prandtl != 1.0)
+        gks::face_terms<Cnt, false, true>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc);
+    else
+        gks::face_terms<Cnt, false, false>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc);
     counts[0] = (double)tally.add;
     counts[1] = (double)tally.mul;
     counts[2] = (double)tally.div;
