@@ -53,6 +53,12 @@ UNIT = {"slopes": "cell", "reconstruct": "cell", "flux_stage1": "face", "flux_st
         "update_stage1": "cell", "update_stage2": "cell", "dt": "cell"}
 
 
+def I_cell_volumes(mesh):
+    import numpy as np
+    v = mesh.xyz[mesh.tet]
+    return np.abs(np.linalg.det(v[:, 1:] - v[:, :1])) / 6.0
+
+
 def cpu_baseline(mesh, W, gW, cfg_kw, steps):
     """The FP64 oracle, as it stands, on `steps` steps of the same mesh."""
     import oracle
@@ -79,6 +85,7 @@ def main():
     ap.add_argument("--n", type=int, default=32, help="hexahedra per side of the mesh")
     ap.add_argument("--cpu-baseline-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -142,6 +149,30 @@ def main():
                 "work_per_launch": f"{BYTES_PER_UNIT[dom]} B/{UNIT[dom]} x {units[UNIT[dom]]}"}
 
     value = nc * 2 * args.steps / elapsed
+
+    fp32 = None
+    if not args.no_fp32:
+        # FP32-bulk leg: the same workload, steps and time-step rule; its
+        # density L1 difference from the FP64 run and conservation drift
+        s32 = G.Solver(mesh, G.default_config(precision=G.GKS_FP32_BULK, **cfg_kw), device="cuda:0")
+        s32.init(W, gW)
+        sums0 = s32.conservation_sums()
+        for _ in range(args.warmup):
+            s32.step(s32.compute_dt(0.5))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            s32.step(s32.compute_dt(0.5))
+        torch.cuda.synchronize()
+        el32 = time.perf_counter() - t1
+        W32, _ = s32.read_state()
+        sums1 = s32.conservation_sums()
+        vol = I_cell_volumes(mesh)
+        fp32 = {"value": nc * 2 * args.steps / el32, "unit": "cell-stage-updates/s",
+                "ms_per_step": el32 / args.steps * 1e3, "speedup_vs_fp64": elapsed / el32,
+                "l1_density_vs_fp64": float(np.sum(vol * np.abs(W32[0] - Wf[0])) / np.sum(vol * Wf[0])),
+                "conservation_drift": float(np.max(np.abs(sums1 - sums0) / np.abs(sums0).max())),
+                "dtype": "fp32 bulk / fp64 state"}
     out = {
         "metric": "cell-stage-updates/s",
         "value": value,
@@ -162,6 +193,7 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    out["fp32_bulk"] = fp32
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, W, gW, cfg_kw, args.cpu_baseline_steps)
     else:

@@ -35,9 +35,10 @@ struct gks_ctx {
     // mesh, prepared on the host in device layout
     bool have_mesh = false;
     int nc = 0, nf = 0;
+    bool fp32 = false;              // FP32-bulk form
     std::vector<int> cperm, fperm;  // internal -> caller
     std::vector<int> nbr, cface, fcell;
-    std::vector<double> M1, M2, geo, fgeo;
+    std::vector<double> M1, M2, geoR, geoD, fgeo, fnrm;
     // workspace
     bool bound = false;
     char *ws = nullptr;
@@ -205,18 +206,20 @@ struct Layout {
 };
 
 enum Slot {
-    S_NBR, S_CFACE, S_M1, S_M2, S_GEO, S_FCELL, S_FGEO, S_W, S_GW, S_WN, S_LN, S_LTN, S_SLOPES,
-    S_COEF, S_FLAG, S_FF, S_FT, S_FW0, S_FWS, S_RED, S_NONPHYS, S_CPERM, S_FPERM, S_STAGING,
-    S_ISTAGING, S_COUNT
+    S_NBR, S_CFACE, S_M1, S_M2, S_GEOR, S_GEOD, S_FCELL, S_FGEO, S_FNRM, S_W, S_GW, S_WN, S_LN, S_LTN,
+    S_SLOPES, S_COEF, S_FLAG, S_FF, S_FT, S_FW0, S_FWS, S_RED, S_NONPHYS, S_CPERM, S_FPERM,
+    S_STAGING, S_ISTAGING, S_COUNT
 };
 
-Layout make_layout(size_t nc, size_t nf)
+// bs: bytes of a bulk element (8 in FP64, 4 in FP32-bulk)
+Layout make_layout(size_t nc, size_t nf, size_t bs)
 {
     const size_t sz[S_COUNT] = {
-        4 * nc * sizeof(int), 4 * nc * sizeof(int), 12 * nc * 8, 144 * nc * 8,
-        (size_t)gks::NGEO * nc * 8, 2 * nf * sizeof(int), (size_t)gks::NFGEO * nf * 8,
-        5 * nc * 8, 15 * nc * 8, 5 * nc * 8, 5 * nc * 8, 5 * nc * 8, 15 * nc * 8, 50 * nc * 8,
-        nc * sizeof(int), 5 * nf * 8, 5 * nf * 8, 5 * nf * 8, 5 * nf * 8,
+        4 * nc * sizeof(int), 4 * nc * sizeof(int), 12 * nc * bs, 144 * nc * bs,
+        (size_t)gks::NGEO_R * nc * bs, (size_t)gks::NGEO_D * nc * 8, 2 * nf * sizeof(int),
+        (size_t)gks::NFGEO * nf * bs, 3 * nf * 8,
+        5 * nc * 8, 15 * nc * 8, 5 * nc * 8, 5 * nc * 8, 5 * nc * 8, 15 * nc * bs, 50 * nc * bs,
+        nc * sizeof(int), 5 * nf * bs, 5 * nf * bs, 5 * nf * bs, 5 * nf * bs,
         (8 + 5 * (size_t)gks::kRedBlocks) * 8, 64, nc * sizeof(int), nf * sizeof(int),
         std::max(50 * nc, 20 * nf) * 8, nc * sizeof(int)};
     Layout L;
@@ -244,7 +247,7 @@ bool config_ok(const gks_config *c, std::string &why)
         if (!(c->lw1[k] > 0.0)) { why = "linear weights must be positive"; return false; }
     if (c->viscous != 0 && c->viscous != 1) { why = "viscous must be 0 or 1"; return false; }
     if (c->nonlinear != 0 && c->nonlinear != 1) { why = "nonlinear must be 0 or 1"; return false; }
-    if (c->precision != GKS_FP64) { why = "only GKS_FP64 is available in this build"; return false; }
+    if (c->precision != GKS_FP64 && c->precision != GKS_FP32_BULK) { why = "unknown precision"; return false; }
     if (c->reserved != 0) { why = "reserved must be 0"; return false; }
     return true;
 }
@@ -327,6 +330,7 @@ gks_status gks_create(const gks_config *cfg, gks_ctx **out)
     p.g01 = cfg->lw1[1] / s1;
     p.viscous = cfg->viscous;
     p.nonlinear = cfg->nonlinear;
+    c->fp32 = cfg->precision == GKS_FP32_BULK;
     *out = c;
     return GKS_OK;
 }
@@ -423,7 +427,7 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
     for (int j = 0; j < nf; ++j) finv[fperm[j]] = j;
 
     // --- face geometry (internal order) ----------------------------------
-    std::vector<double> fgeo((size_t)gks::NFGEO * nf);
+    std::vector<double> fgeo((size_t)gks::NFGEO * nf), fnrm64(3 * (size_t)nf);
     std::vector<int> fcell(2 * (size_t)nf);
     std::vector<double> farea(nf), fnrm(3 * (size_t)nf);
     for (int j = 0; j < nf; ++j) {
@@ -454,6 +458,7 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
         for (int d = 0; d < 3; ++d) {
             const double nd = sg * cr[d] / nrm;
             fgeo[(size_t)(gks::F_N + d) * nf + j] = nd;
+            fnrm64[(size_t)d * nf + j] = nd;
             fnrm[3 * (size_t)f + d] = nd;
         }
         farea[f] = 0.5 * nrm;
@@ -469,7 +474,8 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
     }
 
     // --- cells: geometry rows, neighbours, operators (internal order) ----
-    std::vector<double> geo((size_t)gks::NGEO * nc), M1(12 * (size_t)nc), M2(144 * (size_t)nc);
+    std::vector<double> geoR((size_t)gks::NGEO_R * nc), geoD((size_t)gks::NGEO_D * nc);
+    std::vector<double> M1(12 * (size_t)nc), M2(144 * (size_t)nc);
     std::vector<int> nbr(4 * (size_t)nc), cface(4 * (size_t)nc);
     for (int ii = 0; ii < nc; ++ii) {
         const int i = cperm[ii];
@@ -515,15 +521,15 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
         if (std::sqrt(dot3(closure, closure)) > 1e-10 * sumA)
             return fail(c, GKS_E_MESH, "a cell surface is not closed");
         const double h = std::cbrt(V);
-        double *g = geo.data();
-        g[(size_t)gks::G_INVVOL * nc + ii] = 1.0 / V;
+        double *g = geoR.data(), *gd = geoD.data();
+        gd[(size_t)gks::G_INVVOL * nc + ii] = 1.0 / V;
+        gd[(size_t)gks::G_DR * nc + ii] = 3.0 * V / sumA;
+        gd[(size_t)gks::G_VOL * nc + ii] = V;
         g[(size_t)gks::G_VOL23 * nc + ii] = std::pow(V, 2.0 / 3.0);
         g[(size_t)gks::G_VOL43 * nc + ii] = std::pow(V, 4.0 / 3.0);
         for (int k = 0; k < 6; ++k) g[(size_t)(gks::G_C + k) * nc + ii] = C[k];
-        g[(size_t)gks::G_DR * nc + ii] = 3.0 * V / sumA;
         for (int a = 0; a < 4; ++a)
             for (int d = 0; d < 3; ++d) g[(size_t)(gks::G_RV + 3 * a + d) * nc + ii] = rv[a][d];
-        g[(size_t)gks::G_VOL * nc + ii] = V;
 
         // step 1: least squares of the 4 neighbour averages, D b' = dQ, D = delta / h
         double D[12], Dp[12];
@@ -617,8 +623,10 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
     c->fcell.swap(fcell);
     c->M1.swap(M1);
     c->M2.swap(M2);
-    c->geo.swap(geo);
+    c->geoR.swap(geoR);
+    c->geoD.swap(geoD);
     c->fgeo.swap(fgeo);
+    c->fnrm.swap(fnrm64);
     c->have_mesh = true;
     return GKS_OK;
 }
@@ -627,7 +635,7 @@ gks_status gks_workspace_bytes(const gks_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return GKS_E_INVAL;
     if (!c->have_mesh) return GKS_E_STATE;
-    *bytes = make_layout(c->nc, c->nf).total;
+    *bytes = make_layout(c->nc, c->nf, c->fp32 ? 4 : 8).total;
     return GKS_OK;
 }
 
@@ -637,7 +645,7 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     if (!c->have_mesh) return fail(c, GKS_E_STATE, "no mesh uploaded");
     if (c->bound) return fail(c, GKS_E_STATE, "workspace already bound");
     if (((uintptr_t)dev) & 255) return fail(c, GKS_E_INVAL, "workspace must be 256-byte aligned");
-    const Layout L = make_layout(c->nc, c->nf);
+    const Layout L = make_layout(c->nc, c->nf, c->fp32 ? 4 : 8);
     if (bytes < L.total) return fail(c, GKS_E_NOMEM, "workspace too small");
     char *w = (char *)dev;
     auto P = [&](int slot) { return (void *)(w + L.off[slot]); };
@@ -647,23 +655,25 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     dm.nf = c->nf;
     dm.nbr = (const int *)P(S_NBR);
     dm.cface = (const int *)P(S_CFACE);
-    dm.M1 = (const double *)P(S_M1);
-    dm.M2 = (const double *)P(S_M2);
-    dm.geo = (const double *)P(S_GEO);
+    dm.M1 = P(S_M1);
+    dm.M2 = P(S_M2);
+    dm.geoR = P(S_GEOR);
+    dm.geoD = (const double *)P(S_GEOD);
     dm.fcell = (const int *)P(S_FCELL);
-    dm.fgeo = (const double *)P(S_FGEO);
+    dm.fgeo = P(S_FGEO);
+    dm.fnrm = (const double *)P(S_FNRM);
     ds.W = (double *)P(S_W);
     ds.gW = (double *)P(S_GW);
     ds.Wn = (double *)P(S_WN);
     ds.Ln = (double *)P(S_LN);
     ds.Ltn = (double *)P(S_LTN);
-    ds.slopes = (double *)P(S_SLOPES);
-    ds.coef = (double *)P(S_COEF);
+    ds.slopes = P(S_SLOPES);
+    ds.coef = P(S_COEF);
     ds.flag = (int *)P(S_FLAG);
-    ds.FF = (double *)P(S_FF);
-    ds.FT = (double *)P(S_FT);
-    ds.FW0 = (double *)P(S_FW0);
-    ds.FWs = (double *)P(S_FWS);
+    ds.FF = P(S_FF);
+    ds.FT = P(S_FT);
+    ds.FW0 = P(S_FW0);
+    ds.FWs = P(S_FWS);
     ds.red = (double *)P(S_RED);
     ds.nonphys = (int *)P(S_NONPHYS);
     c->d_cperm = (int *)P(S_CPERM);
@@ -675,13 +685,24 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
         return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
     };
     const size_t nc = c->nc, nf = c->nf;
+    // bulk arrays are formed in FP64 and, in the FP32-bulk form, rounded once here
+    std::vector<float> tmp;
+    auto up_bulk = [&](const void *dst, const std::vector<double> &src) {
+        if (!c->fp32) return up((void *)dst, src.data(), src.size() * 8);
+        tmp.assign(src.begin(), src.end());
+        hipError_t e = up((void *)dst, tmp.data(), tmp.size() * 4);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        return e;
+    };
     HIP_TRY(c, up((void *)dm.nbr, c->nbr.data(), 4 * nc * sizeof(int)));
     HIP_TRY(c, up((void *)dm.cface, c->cface.data(), 4 * nc * sizeof(int)));
-    HIP_TRY(c, up((void *)dm.M1, c->M1.data(), 12 * nc * 8));
-    HIP_TRY(c, up((void *)dm.M2, c->M2.data(), 144 * nc * 8));
-    HIP_TRY(c, up((void *)dm.geo, c->geo.data(), gks::NGEO * nc * 8));
+    HIP_TRY(c, up_bulk(dm.M1, c->M1));
+    HIP_TRY(c, up_bulk(dm.M2, c->M2));
+    HIP_TRY(c, up_bulk(dm.geoR, c->geoR));
+    HIP_TRY(c, up((void *)dm.geoD, c->geoD.data(), gks::NGEO_D * nc * 8));
     HIP_TRY(c, up((void *)dm.fcell, c->fcell.data(), 2 * nf * sizeof(int)));
-    HIP_TRY(c, up((void *)dm.fgeo, c->fgeo.data(), gks::NFGEO * nf * 8));
+    HIP_TRY(c, up_bulk(dm.fgeo, c->fgeo));
+    HIP_TRY(c, up((void *)dm.fnrm, c->fnrm.data(), 3 * nf * 8));
     HIP_TRY(c, up(c->d_cperm, c->cperm.data(), nc * sizeof(int)));
     HIP_TRY(c, up(c->d_fperm, c->fperm.data(), nf * sizeof(int)));
     HIP_TRY(c, gks::launch_fill_int(ds.nonphys, 0, st));
@@ -692,8 +713,10 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     std::vector<int>().swap(c->fcell);
     std::vector<double>().swap(c->M1);
     std::vector<double>().swap(c->M2);
-    std::vector<double>().swap(c->geo);
+    std::vector<double>().swap(c->geoR);
+    std::vector<double>().swap(c->geoD);
     std::vector<double>().swap(c->fgeo);
+    std::vector<double>().swap(c->fnrm);
     c->ws = w;
     c->ws_bytes = bytes;
     c->bound = true;
@@ -736,8 +759,8 @@ gks_status gks_init(gks_ctx *c, const double *W, const double *gW, int32_t on_de
         srcW = stW;
         srcG = stG;
     }
-    HIP_TRY(c, gks::launch_permute_rows(c->ds.W, srcW, c->d_cperm, nc, 5, 0, s));
-    HIP_TRY(c, gks::launch_permute_rows(c->ds.gW, srcG, c->d_cperm, nc, 15, 0, s));
+    HIP_TRY(c, gks::launch_permute_rows(c->ds.W, srcW, c->d_cperm, nc, 5, 0, false, s));
+    HIP_TRY(c, gks::launch_permute_rows(c->ds.gW, srcG, c->d_cperm, nc, 15, 0, false, s));
     HIP_TRY(c, gks::launch_fill_int(c->ds.nonphys, 0, s));
     HIP_TRY(c, gks::launch_check(c->dm, c->ds, c->par, s));
     c->have_state = false;
@@ -770,14 +793,14 @@ gks_status gks_stage(gks_ctx *c, int32_t stage, double dt)
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, GKS_E_INVAL, "dt must be positive and finite");
     const hipStream_t s = c->stream;
     if (stage == 1) {
-        if ((st = timed(c, GKS_K_SLOPES, [&] { return gks::launch_slopes(c->dm, c->ds, s); }))) return st;
-        if ((st = timed(c, GKS_K_RECON, [&] { return gks::launch_reconstruct(c->dm, c->ds, c->par, s); })))
+        if ((st = timed(c, GKS_K_SLOPES, [&] { return gks::launch_slopes(c->dm, c->ds, c->fp32, s); }))) return st;
+        if ((st = timed(c, GKS_K_RECON, [&] { return gks::launch_reconstruct(c->dm, c->ds, c->par, c->fp32, s); })))
             return st;
         if ((st = timed(c, GKS_K_FLUX1, [&] {
-                 return gks::launch_flux(c->dm, c->ds, c->par, dt, gks::FLUX_STAGE1, s);
+                 return gks::launch_flux(c->dm, c->ds, c->par, dt, gks::FLUX_STAGE1, c->fp32, s);
              })))
             return st;
-        if ((st = timed(c, GKS_K_UPDATE1, [&] { return gks::launch_update(c->dm, c->ds, dt, 1, s); })))
+        if ((st = timed(c, GKS_K_UPDATE1, [&] { return gks::launch_update(c->dm, c->ds, dt, 1, c->fp32, s); })))
             return st;
         c->stage1_done = true;
         c->stage1_dt = dt;
@@ -786,14 +809,14 @@ gks_status gks_stage(gks_ctx *c, int32_t stage, double dt)
     if (stage == 2) {
         if (!c->stage1_done || dt != c->stage1_dt)
             return fail(c, GKS_E_ORDER, "stage 2 needs a preceding stage 1 with the same dt");
-        if ((st = timed(c, GKS_K_SLOPES, [&] { return gks::launch_slopes(c->dm, c->ds, s); }))) return st;
-        if ((st = timed(c, GKS_K_RECON, [&] { return gks::launch_reconstruct(c->dm, c->ds, c->par, s); })))
+        if ((st = timed(c, GKS_K_SLOPES, [&] { return gks::launch_slopes(c->dm, c->ds, c->fp32, s); }))) return st;
+        if ((st = timed(c, GKS_K_RECON, [&] { return gks::launch_reconstruct(c->dm, c->ds, c->par, c->fp32, s); })))
             return st;
         if ((st = timed(c, GKS_K_FLUX2, [&] {
-                 return gks::launch_flux(c->dm, c->ds, c->par, dt, gks::FLUX_STAGE2, s);
+                 return gks::launch_flux(c->dm, c->ds, c->par, dt, gks::FLUX_STAGE2, c->fp32, s);
              })))
             return st;
-        if ((st = timed(c, GKS_K_UPDATE2, [&] { return gks::launch_update(c->dm, c->ds, dt, 2, s); })))
+        if ((st = timed(c, GKS_K_UPDATE2, [&] { return gks::launch_update(c->dm, c->ds, dt, 2, c->fp32, s); })))
             return st;
         c->stage1_done = false;
         return GKS_OK;
@@ -815,16 +838,16 @@ gks_status gks_read_state(gks_ctx *c, double *W, double *gW, int32_t on_device)
     const int nc = c->nc;
     const hipStream_t s = c->stream;
     if (on_device) {
-        if (W) HIP_TRY(c, gks::launch_permute_rows(W, c->ds.W, c->d_cperm, nc, 5, 1, s));
-        if (gW) HIP_TRY(c, gks::launch_permute_rows(gW, c->ds.gW, c->d_cperm, nc, 15, 1, s));
+        if (W) HIP_TRY(c, gks::launch_permute_rows(W, c->ds.W, c->d_cperm, nc, 5, 1, false, s));
+        if (gW) HIP_TRY(c, gks::launch_permute_rows(gW, c->ds.gW, c->d_cperm, nc, 15, 1, false, s));
     } else {
         double *stW = c->staging, *stG = c->staging + 5 * (size_t)nc;
         if (W) {
-            HIP_TRY(c, gks::launch_permute_rows(stW, c->ds.W, c->d_cperm, nc, 5, 1, s));
+            HIP_TRY(c, gks::launch_permute_rows(stW, c->ds.W, c->d_cperm, nc, 5, 1, false, s));
             HIP_TRY(c, hipMemcpyAsync(W, stW, 5 * (size_t)nc * 8, hipMemcpyDeviceToHost, s));
         }
         if (gW) {
-            HIP_TRY(c, gks::launch_permute_rows(stG, c->ds.gW, c->d_cperm, nc, 15, 1, s));
+            HIP_TRY(c, gks::launch_permute_rows(stG, c->ds.gW, c->d_cperm, nc, 15, 1, false, s));
             HIP_TRY(c, hipMemcpyAsync(gW, stG, 15 * (size_t)nc * 8, hipMemcpyDeviceToHost, s));
         }
     }
@@ -842,14 +865,15 @@ gks_status gks_conservation_sums(gks_ctx *c, double out[5])
     return GKS_OK;
 }
 
-static gks_status export_rows(gks_ctx *c, double *dst, const double *src, const int *perm, int n,
+// scatter bulk rows (widened to double) to the caller's order
+static gks_status export_rows(gks_ctx *c, double *dst, const void *src, const int *perm, int n,
                               int rows, int on_device)
 {
     const hipStream_t s = c->stream;
     if (on_device) {
-        HIP_TRY(c, gks::launch_permute_rows(dst, src, perm, n, rows, 1, s));
+        HIP_TRY(c, gks::launch_permute_rows(dst, src, perm, n, rows, 1, c->fp32, s));
     } else {
-        HIP_TRY(c, gks::launch_permute_rows(c->staging, src, perm, n, rows, 1, s));
+        HIP_TRY(c, gks::launch_permute_rows(c->staging, src, perm, n, rows, 1, c->fp32, s));
         HIP_TRY(c, hipMemcpyAsync(dst, c->staging, (size_t)rows * n * 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
     }
@@ -862,8 +886,8 @@ gks_status gks_debug_reconstruct(gks_ctx *c, double *slopes, double *coef, int32
     gks_status st = ready(c, true);
     if (st) return st;
     const hipStream_t s = c->stream;
-    HIP_TRY(c, gks::launch_slopes(c->dm, c->ds, s));
-    HIP_TRY(c, gks::launch_reconstruct(c->dm, c->ds, c->par, s));
+    HIP_TRY(c, gks::launch_slopes(c->dm, c->ds, c->fp32, s));
+    HIP_TRY(c, gks::launch_reconstruct(c->dm, c->ds, c->par, c->fp32, s));
     if (slopes && (st = export_rows(c, slopes, c->ds.slopes, c->d_cperm, c->nc, 15, on_device))) return st;
     if (coef && (st = export_rows(c, coef, c->ds.coef, c->d_cperm, c->nc, 50, on_device))) return st;
     if (flag) {
@@ -885,12 +909,12 @@ gks_status gks_debug_face_terms(gks_ctx *c, double dt, double *out, int32_t on_d
     if (st) return st;
     if (!out || !(dt > 0.0)) return fail(c, GKS_E_INVAL, "null output or non-positive dt");
     const hipStream_t s = c->stream;
-    HIP_TRY(c, gks::launch_slopes(c->dm, c->ds, s));
-    HIP_TRY(c, gks::launch_reconstruct(c->dm, c->ds, c->par, s));
-    HIP_TRY(c, gks::launch_flux(c->dm, c->ds, c->par, dt, gks::FLUX_DEBUG, s));
+    HIP_TRY(c, gks::launch_slopes(c->dm, c->ds, c->fp32, s));
+    HIP_TRY(c, gks::launch_reconstruct(c->dm, c->ds, c->par, c->fp32, s));
+    HIP_TRY(c, gks::launch_flux(c->dm, c->ds, c->par, dt, gks::FLUX_DEBUG, c->fp32, s));
     c->stage1_done = false;  // the face buffers of a pending stage 1 are overwritten
     const int nf = c->nf;
-    const double *src[4] = {c->ds.FF, c->ds.FT, c->ds.FW0, c->ds.FWs};
+    const void *src[4] = {c->ds.FF, c->ds.FT, c->ds.FW0, c->ds.FWs};
     for (int k = 0; k < 4; ++k) {
         double *dst = out + (size_t)5 * k * nf;
         if ((st = export_rows(c, dst, src[k], c->d_fperm, nf, 5, on_device))) return st;

@@ -405,7 +405,20 @@ GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], co
     add_part<R, PRFIX>(p, gC.rho, tc.cF[0], tc.cF[1], cW0, tc.cW, F, V, Uc, Fo, Wo);
 }
 
-// rotation of eq. rotate-matrix-3d (Lambda when n1 = -1)
+// Whether the face frame uses the cancellation-free form of 1/(1 + n1).
+template <typename R>
+struct RobustFrame {
+    static constexpr bool value = false;
+};
+template <>
+struct RobustFrame<float> {
+    static constexpr bool value = true;
+};
+
+// rotation of eq. rotate-matrix-3d (Lambda when n1 = -1).  For a unit normal
+// 1/(1 + n1) = (1 - n1)/(n2^2 + n3^2); in FP32 the right-hand side is used
+// when n1 < 0, where 1 + n1 would cancel (normals close to -e1 are common on
+// jittered meshes).  FP64 keeps the printed form.
 template <typename R>
 GKS_HD void rotation(const R n[3], R T[3][3])
 {
@@ -415,7 +428,12 @@ GKS_HD void rotation(const R n[3], R T[3][3])
         T[2][0] = R(0); T[2][1] = R(0); T[2][2] = R(1);
         return;
     }
-    const R n1 = n[0], n2 = n[1], n3 = n[2], ip = R(1) / (R(1) + n1);
+    const R n1 = n[0], n2 = n[1], n3 = n[2];
+    R ip;
+    if (RobustFrame<R>::value && n1 < R(0))
+        ip = (R(1) - n1) / (n2 * n2 + n3 * n3);
+    else
+        ip = R(1) / (R(1) + n1);
     T[0][0] = n1; T[0][1] = n2; T[0][2] = n3;
     T[1][0] = -n2; T[1][1] = n1 + n3 * n3 * ip; T[1][2] = -n2 * n3 * ip;
     T[2][0] = -n3; T[2][1] = -n2 * n3 * ip; T[2][2] = R(1) - n3 * n3 * ip;

@@ -1,5 +1,12 @@
 // Internal definitions shared by the host side of libgks (gks_api.cpp) and
 // its HIP kernels (gks_kernels.hip).  Not part of the public interface.
+//
+// Two precision forms share one layout: in FP64 every bulk array holds
+// doubles; in FP32-bulk the per-stage bulk arrays (least-squares operators,
+// reconstruction geometry, slopes, coefficients, face geometry and face
+// terms) hold floats, while the state (W, grad W, stage-1 copies), the
+// geometry the cell update, time step and conservation sums read, and the
+// normals of the Gauss-theorem sums stay in FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,19 +23,25 @@ struct Params {
     int viscous, nonlinear;
 };
 
-// Per-cell geometry rows of DevMesh::geo ([NGEO][nc], internal cell order).
-enum GeoRow {
-    G_INVVOL = 0,  // 1 / |Omega|
-    G_VOL23 = 1,   // |Omega|^(2/3)
-    G_VOL43 = 2,   // |Omega|^(4/3)
-    G_C = 3,       // 6 rows: centroid second moments / |Omega| (xx,yy,zz,xy,xz,yz)
-    G_DR = 9,      // 3 |Omega| / sum |Gamma|
-    G_RV = 10,     // 12 rows: vertex a, direction d at G_RV + 3a + d, relative to the centroid
-    G_VOL = 22,    // |Omega|
-    NGEO = 23
+// Rows of DevMesh::geoR ([NGEO_R][nc], bulk precision): what the
+// reconstruction reads.
+enum GeoRRow {
+    G_VOL23 = 0,   // |Omega|^(2/3)
+    G_VOL43 = 1,   // |Omega|^(4/3)
+    G_C = 2,       // 6 rows: centroid second moments / |Omega| (xx,yy,zz,xy,xz,yz)
+    G_RV = 8,      // 12 rows: vertex a, direction d at G_RV + 3a + d, relative to the centroid
+    NGEO_R = 20
 };
 
-// Per-face rows of DevMesh::fgeo ([NFGEO][nf], internal face order).
+// Rows of DevMesh::geoD ([NGEO_D][nc], FP64).
+enum GeoDRow {
+    G_INVVOL = 0,  // 1 / |Omega|
+    G_DR = 1,      // 3 |Omega| / sum |Gamma|
+    G_VOL = 2,     // |Omega|
+    NGEO_D = 3
+};
+
+// Rows of DevMesh::fgeo ([NFGEO][nf], bulk precision, internal face order).
 enum FaceRow {
     F_N = 0,       // 3 rows: unit normal, outward from the owner
     F_AREA = 3,    // |Gamma|
@@ -40,51 +53,57 @@ enum FaceRow {
 // Device view of the mesh (all pointers into the caller's workspace).
 struct DevMesh {
     int nc, nf;
-    const int *nbr;    // [4][nc] neighbour internal id, -1 on a wall
-    const int *cface;  // [4][nc] 2 * face + side (side 1: the cell is the face's neighbour)
-    const double *M1;  // [12][nc] slopes b_d = sum_m M1[4d+m] (Q_m - Q_0)
-    const double *M2;  // [144][nc] (g, H) = M2 . (Q_m - Q_0 (4); dQ_m/dx_d (12, index 4+3m+d))
-    const double *geo; // [NGEO][nc]
-    const int *fcell;  // [2][nf] owner, neighbour (-1 on a wall)
-    const double *fgeo;// [NFGEO][nf]
+    const int *nbr;     // [4][nc] neighbour internal id, -1 on a wall
+    const int *cface;   // [4][nc] 2 * face + side (side 1: the cell is the face's neighbour)
+    const void *M1;     // [12][nc] slopes b_d = sum_m M1[4d+m] (Q_m - Q_0)
+    const void *M2;     // [144][nc] (g, H) = M2 . (Q_m - Q_0 (4); dQ_m/dx_d (12, index 4+3m+d))
+    const void *geoR;   // [NGEO_R][nc]
+    const double *geoD; // [NGEO_D][nc]
+    const int *fcell;   // [2][nf] owner, neighbour (-1 on a wall)
+    const void *fgeo;   // [NFGEO][nf]
+    const double *fnrm; // [3][nf] unit normal in FP64 (the Gauss sums of the cell update)
 };
 
 // Device view of the state and per-stage scratch.
 struct DevState {
     double *W, *gW;         // [5][nc], [15][nc] current state (stage input / output)
     double *Wn, *Ln, *Ltn;  // [5][nc] each: W^n and L, dL/dt of stage 1
-    double *slopes;         // [15][nc]
-    double *coef;           // [50][nc]
+    void *slopes;           // [15][nc]
+    void *coef;             // [50][nc]
     int *flag;              // [nc] positivity fallback taken
-    double *FF, *FT, *FW0, *FWs; // [5][nf] each: face flux, its time derivative,
-                                 // interface W(0) of stage 1, interface W for the gradient
+    void *FF, *FT, *FW0, *FWs; // [5][nf] each: face flux, its time derivative,
+                               // interface W(0) of stage 1, interface W for the gradient
     double *red;            // reduction scratch
     int *nonphys;           // [1] set when a cell average is non-physical
 };
 
 enum FluxMode { FLUX_STAGE1 = 0, FLUX_STAGE2 = 1, FLUX_DEBUG = 2 };
 
-// kernel launchers (gks_kernels.hip); each returns the hipError_t of the launch
-hipError_t launch_slopes(const DevMesh &m, const DevState &s, hipStream_t st);
-hipError_t launch_reconstruct(const DevMesh &m, const DevState &s, const Params &p, hipStream_t st);
+// kernel launchers (gks_kernels.hip); fp32 selects the FP32-bulk form;
+// each returns the hipError_t of the launch
+hipError_t launch_slopes(const DevMesh &m, const DevState &s, bool fp32, hipStream_t st);
+hipError_t launch_reconstruct(const DevMesh &m, const DevState &s, const Params &p, bool fp32,
+                              hipStream_t st);
 hipError_t launch_flux(const DevMesh &m, const DevState &s, const Params &p, double dt, int mode,
-                       hipStream_t st);
-hipError_t launch_update(const DevMesh &m, const DevState &s, double dt, int stage, hipStream_t st);
+                       bool fp32, hipStream_t st);
+hipError_t launch_update(const DevMesh &m, const DevState &s, double dt, int stage, bool fp32,
+                         hipStream_t st);
 // dt: writes min over cells of the CFL bound (without the CFL factor) to s.red[0]
 hipError_t launch_dt(const DevMesh &m, const DevState &s, const Params &p, hipStream_t st);
 // conservation sums: writes sum_i |Omega_i| W_i to s.red[0..4]
 hipError_t launch_sums(const DevMesh &m, const DevState &s, hipStream_t st);
 // physical check of the state: sets *s.nonphys when rho <= 0 or p <= 0
 hipError_t launch_check(const DevMesh &m, const DevState &s, const Params &p, hipStream_t st);
-// dst[r][perm[i]] = src[r][i] (scatter to caller order) or dst[r][i] = src[r][perm[i]] (gather)
-hipError_t launch_permute_rows(double *dst, const double *src, const int *perm, int n, int rows,
-                               int scatter, hipStream_t st);
+// dst[r][perm[i]] = src[r][i] (scatter to caller order) or dst[r][i] = src[r][perm[i]]
+// (gather); src_f32 reads floats and widens them
+hipError_t launch_permute_rows(double *dst, const void *src, const int *perm, int n, int rows,
+                               int scatter, bool src_f32, hipStream_t st);
 hipError_t launch_permute_int(int *dst, const int *src, const int *perm, int n, int scatter,
                               hipStream_t st);
 // *p = v (a one-thread kernel, so that no memset node is needed)
 hipError_t launch_fill_int(int *p, int v, hipStream_t st);
 
-// block size for all one-thread-per-item kernels
+// block size for the one-thread-per-item kernels
 constexpr int kBlock = 256;
 // number of blocks of the reduction kernels' first pass
 constexpr int kRedBlocks = 1024;

@@ -17,30 +17,35 @@ __device__ __forceinline__ int gid() { return blockIdx.x * blockDim.x + threadId
 
 // ===========================================================================
 // A1: reconstruction step 1 (Sec. 4.3) -- P^1 slopes b = M1 (Q_m - Q_0)
+// R is the bulk type (double, or float in the FP32-bulk form); the
+// differences Q_m - Q_0 are formed in FP64 before any rounding.
 // ===========================================================================
+template <typename R>
 __global__ __launch_bounds__(kBlock) void slopes_kernel(DevMesh m, DevState s)
 {
     const int i = gid();
     const int n = m.nc;
     if (i >= n) return;
+    const R *M1 = static_cast<const R *>(m.M1);
+    R *slopes = static_cast<R *>(s.slopes);
     int nb[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) nb[a] = m.nbr[a * n + i];
-    double M[12];
+    R M[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) M[k] = m.M1[(size_t)k * n + i];
+    for (int k = 0; k < 12; ++k) M[k] = M1[(size_t)k * n + i];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         const double Q0 = s.W[(size_t)q * n + i];
-        double dq[4];
+        R dq[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) dq[a] = nb[a] >= 0 ? s.W[(size_t)q * n + nb[a]] - Q0 : 0.0;
+        for (int a = 0; a < 4; ++a) dq[a] = nb[a] >= 0 ? R(s.W[(size_t)q * n + nb[a]] - Q0) : R(0);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            double b = 0.0;
+            R b = R(0);
 #pragma unroll
             for (int a = 0; a < 4; ++a) b += M[4 * d + a] * dq[a];
-            s.slopes[(size_t)(3 * q + d) * n + i] = b;
+            slopes[(size_t)(3 * q + d) * n + i] = b;
         }
     }
 }
@@ -53,7 +58,8 @@ __global__ __launch_bounds__(kBlock) void slopes_kernel(DevMesh m, DevState s)
 //   R = Q0 + alpha (P^2 - Q0) + lin (P^1 - Q0); positivity at the 12 face
 //   Gauss points, else P^0 for all components.
 // ===========================================================================
-__device__ __forceinline__ double pow43(double x) { return pow(x, 4.0 / 3.0); }
+template <typename R>
+__device__ __forceinline__ R pow43(R x) { return pow(x, R(4.0 / 3.0)); }
 
 // One block reconstructs kRecCells cells with one wavefront per conservative
 // component: thread (q, l) fits component q of cell l, so each thread holds a
@@ -65,9 +71,10 @@ __device__ __forceinline__ double pow43(double x) { return pow(x, 4.0 / 3.0); }
 constexpr int kRecCells = 64;
 constexpr int kRecThreads = 5 * kRecCells;
 
+template <typename R>
 __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, DevState s, Params p)
 {
-    __shared__ double sR[5][10][kRecCells];
+    __shared__ R sR[5][10][kRecCells];
     __shared__ double sQ0[5][kRecCells];
     __shared__ int sBad[5][kRecCells];
     const int n = m.nc;
@@ -75,86 +82,91 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
     const int l = threadIdx.x % kRecCells;
     const int i = blockIdx.x * kRecCells + l;
     const bool live = i < n;
-    const double *geo = m.geo;
+    const R *geo = static_cast<const R *>(m.geoR);
+    const R *M2 = static_cast<const R *>(m.M2);
+    const R *slopes = static_cast<const R *>(s.slopes);
+    R *coef = static_cast<R *>(s.coef);
+    const R eps = R(p.eps_weno), g22 = R(p.g22), g12 = R(p.g12), g02 = R(p.g02), g11 = R(p.g11);
 
     if (live) {
-        const double vol23 = geo[(size_t)G_VOL23 * n + i];
-        const double vol43 = geo[(size_t)G_VOL43 * n + i];
-        double C[6];
+        const R vol23 = geo[(size_t)G_VOL23 * n + i];
+        const R vol43 = geo[(size_t)G_VOL43 * n + i];
+        R C[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) C[k] = geo[(size_t)(G_C + k) * n + i];
         int nb[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) nb[a] = m.nbr[a * n + i];
         const double Q0 = s.W[(size_t)q * n + i];
-        double d[16];
+        R d[16];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             const bool has = nb[a] >= 0;
-            d[a] = has ? s.W[(size_t)q * n + nb[a]] - Q0 : 0.0;
+            d[a] = has ? R(s.W[(size_t)q * n + nb[a]] - Q0) : R(0);
 #pragma unroll
             for (int dd = 0; dd < 3; ++dd)
-                d[4 + 3 * a + dd] = has ? s.gW[(size_t)(3 * q + dd) * n + nb[a]] : 0.0;
+                d[4 + 3 * a + dd] = has ? R(s.gW[(size_t)(3 * q + dd) * n + nb[a]]) : R(0);
         }
-        double c[9];
+        R c[9];
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
-            double acc = 0.0;
+            R acc = R(0);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) acc += m.M2[(size_t)(16 * r + k) * n + i] * d[k];
+            for (int k = 0; k < 16; ++k) acc += M2[(size_t)(16 * r + k) * n + i] * d[k];
             c[r] = acc;
         }
-        // P^2 about the centroid: its value at the centroid keeps the mean
-        const double c0 = Q0 - 0.5 * (c[3] * C[0] + c[4] * C[1] + c[5] * C[2]) -
-                          (c[6] * C[3] + c[7] * C[4] + c[8] * C[5]);
-        double R[10];
+        // P^2 about the centroid: its value at the centroid, c0 = Q0 + corr,
+        // keeps the mean
+        const R corr = -(R(0.5) * (c[3] * C[0] + c[4] * C[1] + c[5] * C[2]) +
+                         (c[6] * C[3] + c[7] * C[4] + c[8] * C[5]));
+        R Rq[10];
         if (!p.nonlinear) {
-            R[0] = c0;
+            Rq[0] = R(Q0 + double(corr));
 #pragma unroll
-            for (int k = 0; k < 9; ++k) R[1 + k] = c[k];
+            for (int k = 0; k < 9; ++k) Rq[1 + k] = c[k];
         } else {
-            double b[3];
+            R b[3];
 #pragma unroll
-            for (int dd = 0; dd < 3; ++dd) b[dd] = s.slopes[(size_t)(3 * q + dd) * n + i];
+            for (int dd = 0; dd < 3; ++dd) b[dd] = slopes[(size_t)(3 * q + dd) * n + i];
             // beta_1 = |Omega|^(2/3) |b|^2
-            const double beta1 = vol23 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+            const R beta1 = vol23 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
             // beta_2 = |Omega|^(2/3) (|g|^2 + tr(H C H)) + |Omega|^(4/3) sum of the six H^2
-            const double Hm[3][3] = {{c[3], c[6], c[7]}, {c[6], c[4], c[8]}, {c[7], c[8], c[5]}};
-            const double Cm[3][3] = {{C[0], C[3], C[4]}, {C[3], C[1], C[5]}, {C[4], C[5], C[2]}};
-            double trHCH = 0.0;
+            const R Hm[3][3] = {{c[3], c[6], c[7]}, {c[6], c[4], c[8]}, {c[7], c[8], c[5]}};
+            const R Cm[3][3] = {{C[0], C[3], C[4]}, {C[3], C[1], C[5]}, {C[4], C[5], C[2]}};
+            R trHCH = R(0);
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
                 for (int bb = 0; bb < 3; ++bb) {
-                    double hc = 0.0;
+                    R hc = R(0);
 #pragma unroll
                     for (int k = 0; k < 3; ++k) hc += Hm[a][k] * Cm[k][bb];
                     trHCH += hc * Hm[bb][a];
                 }
-            double h2 = 0.0;
+            R h2 = R(0);
 #pragma unroll
             for (int k = 3; k < 9; ++k) h2 += c[k] * c[k];
-            const double beta2 = vol23 * (c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + trHCH) + vol43 * h2;
+            const R beta2 = vol23 * (c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + trHCH) + vol43 * h2;
             // beta_0 from the neighbours' slopes (eq. p0-non-linear-weight), over
             // the neighbours present, pairs (j, k < j) in slot order
-            double b0[4];
+            R b0[4];
             bool hv[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 hv[a] = nb[a] >= 0;
-                double ss = 0.0;
+                R ss = R(0);
                 if (hv[a]) {
 #pragma unroll
                     for (int dd = 0; dd < 3; ++dd) {
-                        const double v = s.slopes[(size_t)(3 * q + dd) * n + nb[a]];
+                        const R v = slopes[(size_t)(3 * q + dd) * n + nb[a]];
                         ss += v * v;
                     }
                 }
                 b0[a] = vol23 * ss;
             }
-            double beta0 = 0.0;
+            R beta0 = R(0);
             {
-                double sum = 0.0;
+                R sum = R(0);
                 int np = 0, nn = 0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -167,11 +179,11 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
                         }
                 }
                 if (nn > 0) {
-                    const double sig1 = np ? pow43(sum / np) : 0.0;
-                    double w[4], ws = 0.0;
+                    const R sig1 = np ? pow43(sum / R(np)) : R(0);
+                    R w[4], ws = R(0);
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        w[j] = hv[j] ? 1.0 + sig1 / (p.eps_weno + b0[j]) : 0.0;
+                        w[j] = hv[j] ? R(1) + sig1 / (eps + b0[j]) : R(0);
                         if (hv[j]) ws += w[j];
                     }
 #pragma unroll
@@ -179,26 +191,25 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
                         if (hv[j]) beta0 += (w[j] / ws) * b0[j];
                 }
             }
-            const double sig = pow43(0.5 * (fabs(beta2 - beta1) + fabs(beta2 - beta0)));
-            const double r2 = sig / (p.eps_weno + beta2), r1 = sig / (p.eps_weno + beta1),
-                         r0 = sig / (p.eps_weno + beta0);
-            double w2 = p.g22 * (1.0 + r2 * r2);
-            double w1 = p.g12 * (1.0 + r1 * r1);
-            const double w0 = p.g02 * (1.0 + r0 * r0);
-            const double ws = w0 + w1 + w2;
+            const R sig = pow43(R(0.5) * (fabs(beta2 - beta1) + fabs(beta2 - beta0)));
+            const R r2 = sig / (eps + beta2), r1 = sig / (eps + beta1), r0 = sig / (eps + beta0);
+            R w2 = g22 * (R(1) + r2 * r2);
+            R w1 = g12 * (R(1) + r1 * r1);
+            const R w0 = g02 * (R(1) + r0 * r0);
+            const R ws = w0 + w1 + w2;
             w2 /= ws;
             w1 /= ws;
             // R = w22 p2 + w12 p1 + w02 p0 collapsed: Q0 + alpha (P^2 - Q0) + lin (P^1 - Q0)
-            const double alpha = w2 / p.g22;
-            const double lin = w1 / p.g11 - w2 * p.g12 / (p.g22 * p.g11);
-            R[0] = Q0 + alpha * (c0 - Q0);
+            const R alpha = w2 / g22;
+            const R lin = w1 / g11 - w2 * g12 / (g22 * g11);
+            Rq[0] = R(Q0 + double(alpha * corr));
 #pragma unroll
-            for (int dd = 0; dd < 3; ++dd) R[1 + dd] = alpha * c[dd] + lin * b[dd];
+            for (int dd = 0; dd < 3; ++dd) Rq[1 + dd] = alpha * c[dd] + lin * b[dd];
 #pragma unroll
-            for (int k = 3; k < 9; ++k) R[1 + k] = alpha * c[k];
+            for (int k = 3; k < 9; ++k) Rq[1 + k] = alpha * c[k];
         }
 #pragma unroll
-        for (int k = 0; k < 10; ++k) sR[q][k][l] = R[k];
+        for (int k = 0; k < 10; ++k) sR[q][k][l] = Rq[k];
         sQ0[q][l] = Q0;
     }
     __syncthreads();
@@ -207,7 +218,7 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
     if (live) {
         if (q < 4) {
             // Gauss points of the face opposite vertex q: r_k / 2 - r_q / 6, k != q
-            double rv[4][3];
+            R rv[4][3];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -215,22 +226,22 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (k == q) continue;
-                double r[3];
+                R r[3];
 #pragma unroll
-                for (int dd = 0; dd < 3; ++dd) r[dd] = 0.5 * rv[k][dd] - rv[q][dd] / 6.0;
-                double v[5];
+                for (int dd = 0; dd < 3; ++dd) r[dd] = R(0.5) * rv[k][dd] - rv[q][dd] / R(6);
+                R v[5];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
-                    double cf[10];
+                    R cf[10];
 #pragma unroll
                     for (int kk = 0; kk < 10; ++kk) cf[kk] = sR[c][kk][l];
                     v[c] = cf[0] + cf[1] * r[0] + cf[2] * r[1] + cf[3] * r[2] +
-                           0.5 * (cf[4] * r[0] * r[0] + cf[5] * r[1] * r[1] + cf[6] * r[2] * r[2]) +
+                           R(0.5) * (cf[4] * r[0] * r[0] + cf[5] * r[1] * r[1] + cf[6] * r[2] * r[2]) +
                            cf[7] * r[0] * r[1] + cf[8] * r[0] * r[2] + cf[9] * r[1] * r[2];
                 }
-                const double pr =
-                    (p.gamma - 1.0) * (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
-                if (!(v[0] > 0.0) || !(pr > 0.0)) bad = 1;
+                const R pr = R(p.gamma - 1.0) *
+                             (v[4] - R(0.5) * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
+                if (!(v[0] > R(0)) || !(pr > R(0))) bad = 1;
             }
         } else {
             // a non-physical cell average cannot be repaired by the fallback
@@ -247,7 +258,7 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
         const bool anybad = (sBad[0][l] | sBad[1][l] | sBad[2][l] | sBad[3][l]) != 0;
 #pragma unroll
         for (int k = 0; k < 10; ++k)
-            s.coef[(size_t)(10 * q + k) * n + i] = anybad ? (k == 0 ? sQ0[q][l] : 0.0) : sR[q][k][l];
+            coef[(size_t)(10 * q + k) * n + i] = anybad ? (k == 0 ? R(sQ0[q][l]) : R(0)) : sR[q][k][l];
         if (q == 0) s.flag[i] = anybad ? 1 : 0;
     }
 }
@@ -255,10 +266,11 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
 // ===========================================================================
 // B: gas-kinetic flux (Sec. 2.2) at the three Gauss points of each face
 // ===========================================================================
+template <typename R>
 struct DevCoef {
-    const double *coef;
+    const R *coef;
     int n, cell;
-    __device__ __forceinline__ double operator()(int q, int k) const
+    __device__ __forceinline__ R operator()(int q, int k) const
     {
         return coef[(size_t)(10 * q + k) * n + cell];
     }
@@ -268,44 +280,51 @@ struct DevCoef {
 // idle).  The lanes of a face are summed in Gauss-point order by shuffles and
 // the first lane writes the face.
 constexpr int kFluxThreads = 256;
+#ifndef GKS_FLUX_MIN_WAVES
+#define GKS_FLUX_MIN_WAVES 1
+#endif
 constexpr int kFacesPerWave = 21;
 constexpr int kFacesPerBlock = kFacesPerWave * (kFluxThreads / 64);
 
-template <int MODE, bool VISC, bool PRFIX>
-__global__ __launch_bounds__(kFluxThreads) void flux_kernel(DevMesh m, DevState s, Params p, double dt)
+template <typename R, int MODE, bool VISC, bool PRFIX>
+__global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(DevMesh m, DevState s, Params p, double dt_)
 {
     const int nf = m.nf, n = m.nc;
+    const R dt = R(dt_);
+    const R *coef = static_cast<const R *>(s.coef);
+    R *FF = static_cast<R *>(s.FF), *FT = static_cast<R *>(s.FT), *FW0 = static_cast<R *>(s.FW0),
+      *FWs = static_cast<R *>(s.FWs);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane / 3, k = lane - 3 * slot;
     const int f = blockIdx.x * kFacesPerBlock + wave * kFacesPerWave + slot;
     const bool live = slot < kFacesPerWave && f < nf;
-    double acc[4][5];
+    R acc[4][5];
     if (live) {
-        const int L = m.fcell[f], R = m.fcell[nf + f];
-        const double *fg = m.fgeo;
-        double nrm[3], dv[3], r[3];
+        const int L = m.fcell[f], Rc = m.fcell[nf + f];
+        const R *fg = static_cast<const R *>(m.fgeo);
+        R nrm[3], dv[3], r[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             nrm[d] = fg[(size_t)(F_N + d) * nf + f];
             dv[d] = fg[(size_t)(F_D + d) * nf + f];
             r[d] = fg[(size_t)(F_RL + 3 * k + d) * nf + f];
         }
-        const double area = fg[(size_t)F_AREA * nf + f];
-        gauss_point_terms<double, VISC, PRFIX>(p, dt, nrm, area, r, dv, DevCoef{s.coef, n, L},
-                                               DevCoef{s.coef, n, R}, acc);
+        const R area = fg[(size_t)F_AREA * nf + f];
+        gauss_point_terms<R, VISC, PRFIX>(p, dt, nrm, area, r, dv, DevCoef<R>{coef, n, L},
+                                          DevCoef<R>{coef, n, Rc}, acc);
     } else {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int q = 0; q < 5; ++q) acc[a][q] = 0.0;
+            for (int q = 0; q < 5; ++q) acc[a][q] = R(0);
     }
     // sum the three Gauss points of each face onto its first lane
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            const double v1 = __shfl_down(acc[a][q], 1, 64);
-            const double v2 = __shfl_down(acc[a][q], 2, 64);
+            const R v1 = __shfl_down(acc[a][q], 1, 64);
+            const R v2 = __shfl_down(acc[a][q], 2, 64);
             acc[a][q] = (acc[a][q] + v1) + v2;
         }
     if (!live || k != 0) return;
@@ -313,47 +332,49 @@ __global__ __launch_bounds__(kFluxThreads) void flux_kernel(DevMesh m, DevState 
     for (int q = 0; q < 5; ++q) {
         const size_t o = (size_t)q * nf + f;
         if (MODE == FLUX_STAGE1) {
-            s.FF[o] = acc[0][q];
-            s.FT[o] = acc[1][q];
-            s.FW0[o] = acc[2][q];
-            s.FWs[o] = 0.5 * (acc[2][q] + acc[3][q]);
+            FF[o] = acc[0][q];
+            FT[o] = acc[1][q];
+            FW0[o] = acc[2][q];
+            FWs[o] = R(0.5) * (acc[2][q] + acc[3][q]);
         } else if (MODE == FLUX_STAGE2) {
-            s.FT[o] = acc[1][q];
-            s.FWs[o] = acc[3][q] - acc[2][q];
+            FT[o] = acc[1][q];
+            FWs[o] = acc[3][q] - acc[2][q];
         } else {
-            s.FF[o] = acc[0][q];
-            s.FT[o] = acc[1][q];
-            s.FW0[o] = acc[2][q];
-            s.FWs[o] = acc[3][q];
+            FF[o] = acc[0][q];
+            FT[o] = acc[1][q];
+            FW0[o] = acc[2][q];
+            FWs[o] = acc[3][q];
         }
     }
 }
 
-template <int MODE>
+template <typename R, int MODE>
 static void launch_flux_mode(const DevMesh &m, const DevState &s, const Params &p, double dt,
                              hipStream_t st)
 {
     const dim3 grid((unsigned)((m.nf + kFacesPerBlock - 1) / kFacesPerBlock)), block(kFluxThreads);
     const bool visc = p.viscous != 0, prfix = p.prandtl != 1.0;
     if (visc && prfix)
-        hipLaunchKernelGGL((flux_kernel<MODE, true, true>), grid, block, 0, st, m, s, p, dt);
+        hipLaunchKernelGGL((flux_kernel<R, MODE, true, true>), grid, block, 0, st, m, s, p, dt);
     else if (visc)
-        hipLaunchKernelGGL((flux_kernel<MODE, true, false>), grid, block, 0, st, m, s, p, dt);
+        hipLaunchKernelGGL((flux_kernel<R, MODE, true, false>), grid, block, 0, st, m, s, p, dt);
     else if (prfix)
-        hipLaunchKernelGGL((flux_kernel<MODE, false, true>), grid, block, 0, st, m, s, p, dt);
+        hipLaunchKernelGGL((flux_kernel<R, MODE, false, true>), grid, block, 0, st, m, s, p, dt);
     else
-        hipLaunchKernelGGL((flux_kernel<MODE, false, false>), grid, block, 0, st, m, s, p, dt);
+        hipLaunchKernelGGL((flux_kernel<R, MODE, false, false>), grid, block, 0, st, m, s, p, dt);
 }
 
 // ===========================================================================
 // C: cell update (eqs. flux-operator, s2o4, gauss-formula, step-du)
 // ===========================================================================
-template <int STAGE>
+template <typename R, int STAGE>
 __global__ __launch_bounds__(kBlock) void update_kernel(DevMesh m, DevState s, double dt)
 {
     const int i = gid();
     const int n = m.nc, nf = m.nf;
     if (i >= n) return;
+    const R *FF = static_cast<const R *>(s.FF), *FT = static_cast<const R *>(s.FT),
+            *FW0 = static_cast<const R *>(s.FW0), *FWs = static_cast<const R *>(s.FWs);
     double L[5] = {0, 0, 0, 0, 0}, Lt[5] = {0, 0, 0, 0, 0}, G[15];
 #pragma unroll
     for (int k = 0; k < 15; ++k) G[k] = 0.0;
@@ -364,18 +385,18 @@ __global__ __launch_bounds__(kBlock) void update_kernel(DevMesh m, DevState s, d
         const double sg = (code & 1) ? -1.0 : 1.0;
         double nrm[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) nrm[d] = m.fgeo[(size_t)(F_N + d) * nf + f];
+        for (int d = 0; d < 3; ++d) nrm[d] = m.fnrm[(size_t)d * nf + f];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             const size_t o = (size_t)q * nf + f;
-            if (STAGE == 1) L[q] -= sg * s.FF[o];
-            Lt[q] -= sg * s.FT[o];
-            const double wf = STAGE == 1 ? s.FWs[o] : s.FW0[o] + s.FWs[o];
+            if (STAGE == 1) L[q] -= sg * double(FF[o]);
+            Lt[q] -= sg * double(FT[o]);
+            const double wf = STAGE == 1 ? double(FWs[o]) : double(FW0[o]) + double(FWs[o]);
 #pragma unroll
             for (int d = 0; d < 3; ++d) G[3 * q + d] += sg * wf * nrm[d];
         }
     }
-    const double iv = m.geo[(size_t)G_INVVOL * n + i];
+    const double iv = m.geoD[(size_t)G_INVVOL * n + i];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         const size_t o = (size_t)q * n + i;
@@ -422,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void dt_pass1(DevMesh m, DevState s, Params
         const double u = s.W[n + i] * ir, v = s.W[2 * n + i] * ir, w = s.W[3 * n + i] * ir;
         const double pr = (p.gamma - 1.0) * (s.W[4 * n + i] - 0.5 * rho * (u * u + v * v + w * w));
         const double a = sqrt(p.gamma * pr / rho);
-        const double dr = m.geo[(size_t)G_DR * n + i];
+        const double dr = m.geoD[(size_t)G_DR * n + i];
         double b = dr / (sqrt(u * u + v * v + w * w) + a);
         if (p.viscous && p.mu > 0.0) b = fmin(b, dr * dr / (3.0 * (p.mu / rho)));
         if (!(rho > 0.0) || !(pr > 0.0)) *s.nonphys = 1;
@@ -460,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void sums_pass1(DevMesh m, DevState s)
     const int n = m.nc;
     double acc[5] = {0, 0, 0, 0, 0};
     for (int i = gid(); i < n; i += gridDim.x * blockDim.x) {
-        const double v = m.geo[(size_t)G_VOL * n + i];
+        const double v = m.geoD[(size_t)G_VOL * n + i];
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[q] += v * s.W[(size_t)q * n + i];
     }
@@ -506,18 +527,18 @@ __global__ __launch_bounds__(kBlock) void check_kernel(DevMesh m, DevState s, Pa
     if (!(rho > 0.0) || !(pr > 0.0)) *s.nonphys = 1;
 }
 
-__global__ __launch_bounds__(kBlock) void permute_rows_kernel(double *dst, const double *src,
-                                                              const int *perm, int n, int rows,
-                                                              int scatter)
+template <typename S>
+__global__ __launch_bounds__(kBlock) void permute_rows_kernel(double *dst, const S *src, const int *perm,
+                                                              int n, int rows, int scatter)
 {
     const int i = gid();
     if (i >= n) return;
     const int j = perm[i];
     for (int r = 0; r < rows; ++r) {
         if (scatter)
-            dst[(size_t)r * n + j] = src[(size_t)r * n + i];
+            dst[(size_t)r * n + j] = double(src[(size_t)r * n + i]);
         else
-            dst[(size_t)r * n + i] = src[(size_t)r * n + j];
+            dst[(size_t)r * n + i] = double(src[(size_t)r * n + j]);
     }
 }
 
@@ -539,37 +560,63 @@ __global__ void fill_int_kernel(int *p, int v) { *p = v; }
 // ===========================================================================
 static inline dim3 grid_for(int n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
-hipError_t launch_slopes(const DevMesh &m, const DevState &s, hipStream_t st)
+hipError_t launch_slopes(const DevMesh &m, const DevState &s, bool fp32, hipStream_t st)
 {
-    hipLaunchKernelGGL(slopes_kernel, grid_for(m.nc), dim3(kBlock), 0, st, m, s);
+    if (fp32)
+        hipLaunchKernelGGL(slopes_kernel<float>, grid_for(m.nc), dim3(kBlock), 0, st, m, s);
+    else
+        hipLaunchKernelGGL(slopes_kernel<double>, grid_for(m.nc), dim3(kBlock), 0, st, m, s);
     return hipGetLastError();
 }
 
-hipError_t launch_reconstruct(const DevMesh &m, const DevState &s, const Params &p, hipStream_t st)
+hipError_t launch_reconstruct(const DevMesh &m, const DevState &s, const Params &p, bool fp32,
+                              hipStream_t st)
 {
-    hipLaunchKernelGGL(reconstruct_kernel, dim3((unsigned)((m.nc + kRecCells - 1) / kRecCells)),
-                       dim3(kRecThreads), 0, st, m, s, p);
+    const dim3 grid((unsigned)((m.nc + kRecCells - 1) / kRecCells)), block(kRecThreads);
+    if (fp32)
+        hipLaunchKernelGGL(reconstruct_kernel<float>, grid, block, 0, st, m, s, p);
+    else
+        hipLaunchKernelGGL(reconstruct_kernel<double>, grid, block, 0, st, m, s, p);
     return hipGetLastError();
+}
+
+template <typename R>
+static void launch_flux_r(const DevMesh &m, const DevState &s, const Params &p, double dt, int mode,
+                          hipStream_t st)
+{
+    if (mode == FLUX_STAGE1)
+        launch_flux_mode<R, FLUX_STAGE1>(m, s, p, dt, st);
+    else if (mode == FLUX_STAGE2)
+        launch_flux_mode<R, FLUX_STAGE2>(m, s, p, dt, st);
+    else
+        launch_flux_mode<R, FLUX_DEBUG>(m, s, p, dt, st);
 }
 
 hipError_t launch_flux(const DevMesh &m, const DevState &s, const Params &p, double dt, int mode,
-                       hipStream_t st)
+                       bool fp32, hipStream_t st)
 {
-    if (mode == FLUX_STAGE1)
-        launch_flux_mode<FLUX_STAGE1>(m, s, p, dt, st);
-    else if (mode == FLUX_STAGE2)
-        launch_flux_mode<FLUX_STAGE2>(m, s, p, dt, st);
+    if (fp32)
+        launch_flux_r<float>(m, s, p, dt, mode, st);
     else
-        launch_flux_mode<FLUX_DEBUG>(m, s, p, dt, st);
+        launch_flux_r<double>(m, s, p, dt, mode, st);
     return hipGetLastError();
 }
 
-hipError_t launch_update(const DevMesh &m, const DevState &s, double dt, int stage, hipStream_t st)
+hipError_t launch_update(const DevMesh &m, const DevState &s, double dt, int stage, bool fp32,
+                         hipStream_t st)
 {
-    if (stage == 1)
-        hipLaunchKernelGGL(update_kernel<1>, grid_for(m.nc), dim3(kBlock), 0, st, m, s, dt);
-    else
-        hipLaunchKernelGGL(update_kernel<2>, grid_for(m.nc), dim3(kBlock), 0, st, m, s, dt);
+    const dim3 g = grid_for(m.nc), b(kBlock);
+    if (fp32) {
+        if (stage == 1)
+            hipLaunchKernelGGL((update_kernel<float, 1>), g, b, 0, st, m, s, dt);
+        else
+            hipLaunchKernelGGL((update_kernel<float, 2>), g, b, 0, st, m, s, dt);
+    } else {
+        if (stage == 1)
+            hipLaunchKernelGGL((update_kernel<double, 1>), g, b, 0, st, m, s, dt);
+        else
+            hipLaunchKernelGGL((update_kernel<double, 2>), g, b, 0, st, m, s, dt);
+    }
     return hipGetLastError();
 }
 
@@ -595,12 +642,16 @@ hipError_t launch_check(const DevMesh &m, const DevState &s, const Params &p, hi
     return hipGetLastError();
 }
 
-hipError_t launch_permute_rows(double *dst, const double *src, const int *perm, int n, int rows,
-                               int scatter, hipStream_t st)
+hipError_t launch_permute_rows(double *dst, const void *src, const int *perm, int n, int rows,
+                               int scatter, bool src_f32, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(permute_rows_kernel, grid_for(n), dim3(kBlock), 0, st, dst, src, perm, n, rows,
-                       scatter);
+    if (src_f32)
+        hipLaunchKernelGGL(permute_rows_kernel<float>, grid_for(n), dim3(kBlock), 0, st, dst,
+                           static_cast<const float *>(src), perm, n, rows, scatter);
+    else
+        hipLaunchKernelGGL(permute_rows_kernel<double>, grid_for(n), dim3(kBlock), 0, st, dst,
+                           static_cast<const double *>(src), perm, n, rows, scatter);
     return hipGetLastError();
 }
 
