@@ -86,6 +86,9 @@ def main():
     ap.add_argument("--cpu-baseline-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk leg")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with a 256 MiB fill and a 256 MiB device copy (calibrates "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE against known byte counts)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -159,12 +162,16 @@ def main():
         sums0 = s32.conservation_sums()
         for _ in range(args.warmup):
             s32.step(s32.compute_dt(0.5))
+        s32.timing_read(reset=True)
+        s32.timing_enable(True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.steps):
             s32.step(s32.compute_dt(0.5))
         torch.cuda.synchronize()
         el32 = time.perf_counter() - t1
+        s32.timing_enable(False)
+        kt32 = s32.timing_read(reset=True)
         W32, _ = s32.read_state()
         sums1 = s32.conservation_sums()
         vol = I_cell_volumes(mesh)
@@ -172,7 +179,8 @@ def main():
                 "ms_per_step": el32 / args.steps * 1e3, "speedup_vs_fp64": elapsed / el32,
                 "l1_density_vs_fp64": float(np.sum(vol * np.abs(W32[0] - Wf[0])) / np.sum(vol * Wf[0])),
                 "conservation_drift": float(np.max(np.abs(sums1 - sums0) / np.abs(sums0).max())),
-                "dtype": "fp32 bulk / fp64 state"}
+                "dtype": "fp32 bulk / fp64 state",
+                "kernels_ms": {k: ms / cnt for k, (ms, cnt) in kt32.items() if cnt}}
     out = {
         "metric": "cell-stage-updates/s",
         "value": value,
@@ -198,6 +206,13 @@ def main():
         out["cpu_baseline"] = cpu_baseline(mesh, W, gW, cfg_kw, args.cpu_baseline_steps)
     else:
         out["cpu_baseline"] = None
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

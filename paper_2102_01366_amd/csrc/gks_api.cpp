@@ -215,7 +215,8 @@ enum Slot {
 Layout make_layout(size_t nc, size_t nf, size_t bs)
 {
     const size_t sz[S_COUNT] = {
-        4 * nc * sizeof(int), 4 * nc * sizeof(int), 12 * nc * bs, 144 * nc * bs,
+        4 * nc * sizeof(int), 4 * nc * sizeof(int), 12 * nc * bs,
+        (size_t)gks::kM2Rows * gks::m2_padded_cells(nc) * bs,
         (size_t)gks::NGEO_R * nc * bs, (size_t)gks::NGEO_D * nc * 8, 2 * nf * sizeof(int),
         (size_t)gks::NFGEO * nf * bs, 3 * nf * 8,
         5 * nc * 8, 15 * nc * 8, 5 * nc * 8, 5 * nc * 8, 5 * nc * 8, 15 * nc * bs, 50 * nc * bs,
@@ -475,7 +476,7 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
 
     // --- cells: geometry rows, neighbours, operators (internal order) ----
     std::vector<double> geoR((size_t)gks::NGEO_R * nc), geoD((size_t)gks::NGEO_D * nc);
-    std::vector<double> M1(12 * (size_t)nc), M2(144 * (size_t)nc);
+    std::vector<double> M1(12 * (size_t)nc), M2(gks::kM2Rows * gks::m2_padded_cells(nc), 0.0);
     std::vector<int> nbr(4 * (size_t)nc), cface(4 * (size_t)nc);
     for (int ii = 0; ii < nc; ++ii) {
         const int i = cperm[ii];
@@ -608,9 +609,9 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
         const double osc[9] = {1 / h, 1 / h, 1 / h, 2 / (h * h), 2 / (h * h), 2 / (h * h),
                                1 / (h * h), 1 / (h * h), 1 / (h * h)};
         for (int r = 0; r < 9; ++r) {
-            for (int s = 0; s < 4; ++s) M2[(size_t)(16 * r + s) * nc + ii] = osc[r] * Me[r * 4 + s];
+            for (int s = 0; s < 4; ++s) M2[gks::m2_index(16 * r + s, ii)] = osc[r] * Me[r * 4 + s];
             for (int s = 0; s < 12; ++s)
-                M2[(size_t)(16 * r + 4 + s) * nc + ii] = osc[r] * h * Mb[r * 12 + s];
+                M2[gks::m2_index(16 * r + 4 + s, ii)] = osc[r] * h * Mb[r * 12 + s];
         }
     }
 

@@ -56,7 +56,8 @@ struct DevMesh {
     const int *nbr;     // [4][nc] neighbour internal id, -1 on a wall
     const int *cface;   // [4][nc] 2 * face + side (side 1: the cell is the face's neighbour)
     const void *M1;     // [12][nc] slopes b_d = sum_m M1[4d+m] (Q_m - Q_0)
-    const void *M2;     // [144][nc] (g, H) = M2 . (Q_m - Q_0 (4); dQ_m/dx_d (12, index 4+3m+d))
+    const void *M2;     // tiled [ceil(nc/64)][144][64]: (g, H) = M2 . (Q_m - Q_0 (4);
+                        // dQ_m/dx_d (12, index 4+3m+d)); entry (row, i) at m2_index(row, i)
     const void *geoR;   // [NGEO_R][nc]
     const double *geoD; // [NGEO_D][nc]
     const int *fcell;   // [2][nf] owner, neighbour (-1 on a wall)
@@ -102,6 +103,17 @@ hipError_t launch_permute_int(int *dst, const int *src, const int *perm, int n, 
                               hipStream_t st);
 // *p = v (a one-thread kernel, so that no memset node is needed)
 hipError_t launch_fill_int(int *p, int v, hipStream_t st);
+
+// cells per tile of the second-step operator M2: the 144 rows of the 64 cells
+// of a tile are contiguous, so that one reconstruction block streams its
+// operators as a single block of memory; the last tile is zero-padded
+constexpr int kM2Tile = 64;
+constexpr int kM2Rows = 144;
+__host__ __device__ inline size_t m2_index(int row, int i)
+{
+    return ((size_t)(i / kM2Tile) * kM2Rows + row) * kM2Tile + (size_t)(i % kM2Tile);
+}
+inline size_t m2_padded_cells(size_t nc) { return (nc + kM2Tile - 1) / kM2Tile * kM2Tile; }
 
 // block size for the one-thread-per-item kernels
 constexpr int kBlock = 256;

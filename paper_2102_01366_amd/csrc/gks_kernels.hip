@@ -34,12 +34,20 @@ __global__ __launch_bounds__(kBlock) void slopes_kernel(DevMesh m, DevState s)
     R M[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) M[k] = M1[(size_t)k * n + i];
+    // clamp missing neighbours to the cell itself so that every load is issued
+    // unconditionally (no exec-masked branch per gather)
+    int nbc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) nbc[a] = nb[a] >= 0 ? nb[a] : i;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         const double Q0 = s.W[(size_t)q * n + i];
+        double wn[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) wn[a] = s.W[(size_t)q * n + nbc[a]];
         R dq[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) dq[a] = nb[a] >= 0 ? R(s.W[(size_t)q * n + nb[a]] - Q0) : R(0);
+        for (int a = 0; a < 4; ++a) dq[a] = nb[a] >= 0 ? R(wn[a] - Q0) : R(0);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             R b = R(0);
@@ -61,44 +69,80 @@ __global__ __launch_bounds__(kBlock) void slopes_kernel(DevMesh m, DevState s)
 template <typename R>
 __device__ __forceinline__ R pow43(R x) { return pow(x, R(4.0 / 3.0)); }
 
-// One block reconstructs kRecCells cells with one wavefront per conservative
-// component: thread (q, l) fits component q of cell l, so each thread holds a
-// single component's stencil and coefficients.  The five wavefronts read the
-// same rows of M2 (one HBM read, four cache hits).  The coefficients meet in
-// LDS for the cell-wide positivity check: wavefront a evaluates the three
-// Gauss points of the face opposite vertex a, wavefront 4 checks the cell
-// average.
-constexpr int kRecCells = 64;
+// One block reconstructs one tile of kRecCells cells with one wavefront per
+// conservative component: thread (q, l) fits component q of cell l, so each
+// thread holds a single component's stencil and coefficients.  The tile's
+// operators M2 are streamed once through LDS in kM2Chunk-row chunks shared by
+// the five wavefronts (the next chunk is prefetched into registers while the
+// current one is used).  The coefficients then meet in LDS for the cell-wide
+// positivity check: wavefront a evaluates the three Gauss points of the face
+// opposite vertex a, wavefront 4 checks the cell average.
+constexpr int kRecCells = kM2Tile;
 constexpr int kRecThreads = 5 * kRecCells;
+constexpr int kM2Chunk = 48;                 // three output rows of 16 operator rows
+constexpr int kM2Chunks = kM2Rows / kM2Chunk;
+static_assert(kM2Chunk * kM2Chunks == kM2Rows && kM2Chunk % 16 == 0, "M2 chunking");
+
+// one chunk of a tile as 16-byte vectors, spread over the block
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <typename R>
+struct M2Chunk {
+    static constexpr int kVec = kM2Chunk * kRecCells * (int)sizeof(R) / 16;
+    static constexpr int kPer = (kVec + kRecThreads - 1) / kRecThreads;
+    u32x4 v[kPer];
+    __device__ __forceinline__ void load(const R *tile, int chunk)
+    {
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(tile + (size_t)chunk * kM2Chunk * kRecCells);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int t = threadIdx.x + j * kRecThreads;
+            if (t < kVec) v[j] = src[t];
+        }
+    }
+    __device__ __forceinline__ void store(R *lds) const
+    {
+        u32x4 *dst = reinterpret_cast<u32x4 *>(lds);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int t = threadIdx.x + j * kRecThreads;
+            if (t < kVec) dst[t] = v[j];
+        }
+    }
+};
 
 template <typename R>
 __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, DevState s, Params p)
 {
-    __shared__ R sR[5][10][kRecCells];
+    // the operator chunks and, after the fit, the coefficients share one buffer
+    constexpr int kBuf = 5 * 10 * kRecCells > kM2Chunk * kRecCells ? 5 * 10 * kRecCells
+                                                                   : kM2Chunk * kRecCells;
+    __shared__ __align__(16) R sBuf[kBuf];
     __shared__ double sQ0[5][kRecCells];
     __shared__ int sBad[5][kRecCells];
+    R (*sR)[10][kRecCells] = reinterpret_cast<R (*)[10][kRecCells]>(sBuf);
     const int n = m.nc;
     const int q = threadIdx.x / kRecCells;  // component, uniform over the wavefront
     const int l = threadIdx.x % kRecCells;
     const int i = blockIdx.x * kRecCells + l;
     const bool live = i < n;
     const R *geo = static_cast<const R *>(m.geoR);
-    const R *M2 = static_cast<const R *>(m.M2);
+    const R *tile = static_cast<const R *>(m.M2) + (size_t)blockIdx.x * kM2Rows * kRecCells;
     const R *slopes = static_cast<const R *>(s.slopes);
     R *coef = static_cast<R *>(s.coef);
     const R eps = R(p.eps_weno), g22 = R(p.g22), g12 = R(p.g12), g02 = R(p.g02), g11 = R(p.g11);
 
-    if (live) {
-        const R vol23 = geo[(size_t)G_VOL23 * n + i];
-        const R vol43 = geo[(size_t)G_VOL43 * n + i];
-        R C[6];
+    M2Chunk<R> pre;
+    pre.load(tile, 0);
+
+    int nb[4] = {-1, -1, -1, -1};
+    double Q0 = 0.0;
+    R d[16];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) C[k] = geo[(size_t)(G_C + k) * n + i];
-        int nb[4];
+    for (int k = 0; k < 16; ++k) d[k] = R(0);
+    if (live) {
 #pragma unroll
         for (int a = 0; a < 4; ++a) nb[a] = m.nbr[a * n + i];
-        const double Q0 = s.W[(size_t)q * n + i];
-        R d[16];
+        Q0 = s.W[(size_t)q * n + i];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             const bool has = nb[a] >= 0;
@@ -107,14 +151,33 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
             for (int dd = 0; dd < 3; ++dd)
                 d[4 + 3 * a + dd] = has ? R(s.gW[(size_t)(3 * q + dd) * n + nb[a]]) : R(0);
         }
-        R c[9];
+    }
+    R c[9];
 #pragma unroll
-        for (int r = 0; r < 9; ++r) {
+    for (int t = 0; t < kM2Chunks; ++t) {
+        if (t > 0) __syncthreads();  // the previous chunk has been used
+        pre.store(sBuf);
+        __syncthreads();
+        if (t + 1 < kM2Chunks) pre.load(tile, t + 1);
+#pragma unroll
+        for (int rr = 0; rr < kM2Chunk / 16; ++rr) {
             R acc = R(0);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) acc += M2[(size_t)(16 * r + k) * n + i] * d[k];
-            c[r] = acc;
+            for (int k = 0; k < 16; ++k) acc += sBuf[(16 * rr + k) * kRecCells + l] * d[k];
+            // an empty ordering point: the sums are formed here, not sunk past the
+            // barriers to their first use (which would hold every chunk in registers)
+            asm volatile("" : "+v"(acc));
+            c[t * (kM2Chunk / 16) + rr] = acc;
         }
+    }
+    __syncthreads();  // sBuf now holds the coefficients
+
+    if (live) {
+        const R vol23 = geo[(size_t)G_VOL23 * n + i];
+        const R vol43 = geo[(size_t)G_VOL43 * n + i];
+        R C[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) C[k] = geo[(size_t)(G_C + k) * n + i];
         // P^2 about the centroid: its value at the centroid, c0 = Q0 + corr,
         // keeps the mean
         const R corr = -(R(0.5) * (c[3] * C[0] + c[4] * C[1] + c[5] * C[2]) +
