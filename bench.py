@@ -34,17 +34,17 @@ FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak, TFLOP/s
 #   slopes   per cell: W 5, M1 12, slopes out 15 doubles; 4 neighbour ids
 #   recon    per cell: W 5, gW 15, slopes 15, M2 144, geometry 20 doubles,
 #            4 neighbour ids; coefficients out 50 doubles, 1 flag
-#   flux     per face: 2 cell ids, 16 geometry doubles, half of each of the two
-#            cells' 50 coefficients (each cell has 4 faces and each face 2 cells,
-#            so 50 per face), out 20 (stage 1) / 10 (stage 2) doubles
+#   flux     per face: 2 cell ids, 16 geometry doubles, the coefficients (50 per
+#            cell, read by its 4 faces; 2 faces per cell, so 25 per face), out
+#            20 (stage 1) / 10 (stage 2) doubles
 #   update   per cell: 4 face codes, 2 faces x (15 face terms + 3 normal),
 #            W 5 / W^n, L, L_t 15, 1/|Omega|; out 20 + 15 (stage 1) / 20 (stage 2)
 #   dt       per cell: W 5 + dr 1 doubles
 BYTES_PER_UNIT = {
     "slopes": 8 * (5 + 12 + 15) + 4 * 4,
     "reconstruct": 8 * (5 + 15 + 15 + 144 + 20 + 50) + 4 * 4 + 4,
-    "flux_stage1": 4 * 2 + 8 * (16 + 50 + 20),
-    "flux_stage2": 4 * 2 + 8 * (16 + 50 + 10),
+    "flux_stage1": 4 * 2 + 8 * (16 + 25 + 20),
+    "flux_stage2": 4 * 2 + 8 * (16 + 25 + 10),
     "update_stage1": 4 * 4 + 8 * (2 * 18 + 5 + 1 + 35),
     "update_stage2": 4 * 4 + 8 * (2 * 18 + 15 + 1 + 20),
     "dt": 8 * 6,
@@ -87,8 +87,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk leg")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="end with a 256 MiB fill and a 256 MiB device copy (calibrates "
-                         "rocprofv3 FETCH_SIZE / WRITE_SIZE against known byte counts)")
+                    help="end with a 256 MiB fill (writes 256 MiB) and a 256 MiB elementwise add "
+                         "(reads and writes 256 MiB): known byte counts that calibrate rocprofv3 "
+                         "FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -110,14 +111,15 @@ def main():
     solver.init(W, gW)
     nc, nf = mesh.n_cell, mesh.n_face
 
+    # each step: dt = CFL bound on the device, then both stages with that dt
     for _ in range(args.warmup):
-        solver.step(solver.compute_dt(0.5))
+        solver.step_cfl(0.5)
     solver.timing_read(reset=True)
     solver.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        solver.step(solver.compute_dt(0.5))
+        solver.step_cfl(0.5)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     solver.timing_enable(False)
@@ -161,13 +163,13 @@ def main():
         s32.init(W, gW)
         sums0 = s32.conservation_sums()
         for _ in range(args.warmup):
-            s32.step(s32.compute_dt(0.5))
+            s32.step_cfl(0.5)
         s32.timing_read(reset=True)
         s32.timing_enable(True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.steps):
-            s32.step(s32.compute_dt(0.5))
+            s32.step_cfl(0.5)
         torch.cuda.synchronize()
         el32 = time.perf_counter() - t1
         s32.timing_enable(False)
@@ -211,7 +213,7 @@ def main():
         b = torch.empty_like(a)
         a.fill_(1)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.add(a, 1, out=b)
         torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 

@@ -132,6 +132,15 @@ gks_status gks_compute_dt(gks_ctx *ctx, double cfl, double *dt);
 gks_status gks_stage(gks_ctx *ctx, int32_t stage, double dt);
 /* Stage 1 followed by stage 2. */
 gks_status gks_step(gks_ctx *ctx, double dt);
+/* One whole step whose time step never leaves the device (asynchronous, no
+ * host synchronisation): dt = cfl * the bound of gks_compute_dt on the
+ * current state, then stage 1 and stage 2 with that dt.  Same arithmetic as
+ * gks_compute_dt followed by gks_step.  GKS_E_INVAL for a cfl that is not
+ * positive and finite, GKS_E_ORDER while a stage 1 is pending.  A
+ * non-physical state surfaces at the next blocking call. */
+gks_status gks_step_cfl(gks_ctx *ctx, double cfl);
+/* The time step of the last gks_step_cfl or gks_compute_dt (blocking). */
+gks_status gks_last_dt(gks_ctx *ctx, double *dt);
 /* Copy the state out (blocking when on_device == 0).  Reports a pending
  * non-physical flag as GKS_E_NONPHYSICAL. */
 gks_status gks_read_state(gks_ctx *ctx, double *W, double *gW, int32_t on_device);

@@ -35,7 +35,8 @@ GKS_FP32_BULK = 1
 # names of every function the C interface declares (include/gks.h)
 EXPORTS = ("gks_default_config", "gks_create", "gks_destroy", "gks_set_stream",
            "gks_mesh_upload", "gks_workspace_bytes", "gks_bind_workspace", "gks_init",
-           "gks_compute_dt", "gks_stage", "gks_step", "gks_read_state",
+           "gks_compute_dt", "gks_stage", "gks_step", "gks_step_cfl", "gks_last_dt",
+           "gks_read_state",
            "gks_conservation_sums", "gks_debug_reconstruct", "gks_debug_face_terms",
            "gks_timing_enable", "gks_timing_read", "gks_flux_op_count", "gks_last_error",
            "gks_strerror")
@@ -94,6 +95,8 @@ def load_library(path: str = LIB_PATH):
         "gks_compute_dt": (S, [P, D, P]),
         "gks_stage": (S, [P, I32, D]),
         "gks_step": (S, [P, D]),
+        "gks_step_cfl": (S, [P, D]),
+        "gks_last_dt": (S, [P, P]),
         "gks_read_state": (S, [P, P, P, I32]),
         "gks_conservation_sums": (S, [P, P]),
         "gks_debug_reconstruct": (S, [P, P, P, P, I32]),
@@ -231,6 +234,15 @@ class Solver:
 
     def step(self, dt: float):
         self._check(self.L.gks_step(self._h, float(dt)), "step")
+
+    def step_cfl(self, cfl: float):
+        """One step with dt = cfl x the CFL bound, computed and used on the device."""
+        self._check(self.L.gks_step_cfl(self._h, float(cfl)), "step_cfl")
+
+    def last_dt(self) -> float:
+        dt = ctypes.c_double()
+        self._check(self.L.gks_last_dt(self._h, ctypes.byref(dt)), "last_dt")
+        return float(dt.value)
 
     def read_state(self, device: bool = False):
         if device:

@@ -776,15 +776,32 @@ gks_status gks_compute_dt(gks_ctx *c, double cfl, double *dt)
 {
     gks_status st = ready(c, true);
     if (st) return st;
-    if (!dt || !(cfl > 0.0)) return fail(c, GKS_E_INVAL, "cfl must be > 0");
-    st = timed(c, GKS_K_DT, [&] { return gks::launch_dt(c->dm, c->ds, c->par, c->stream); });
+    if (!dt || !(cfl > 0.0) || !std::isfinite(cfl)) return fail(c, GKS_E_INVAL, "cfl must be positive and finite");
+    st = timed(c, GKS_K_DT, [&] { return gks::launch_dt(c->dm, c->ds, c->par, cfl, c->stream); });
     if (st) return st;
-    double m = 0.0;
-    HIP_TRY(c, hipMemcpyAsync(&m, c->ds.red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    double v = 0.0;
+    HIP_TRY(c, hipMemcpyAsync(&v, c->ds.red + gks::kRedDt, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     st = read_nonphys(c, false);
     if (st) return st;
-    *dt = cfl * m;
+    *dt = v;
     return GKS_OK;
+}
+
+// One stage; the time step is dt, or *dtp when dtp is not null.
+static gks_status stage_impl(gks_ctx *c, int stage, double dt, const double *dtp)
+{
+    gks_status st;
+    const hipStream_t s = c->stream;
+    if ((st = timed(c, GKS_K_SLOPES, [&] { return gks::launch_slopes(c->dm, c->ds, c->fp32, s); }))) return st;
+    if ((st = timed(c, GKS_K_RECON, [&] { return gks::launch_reconstruct(c->dm, c->ds, c->par, c->fp32, s); })))
+        return st;
+    const int mode = stage == 1 ? gks::FLUX_STAGE1 : gks::FLUX_STAGE2;
+    if ((st = timed(c, stage == 1 ? GKS_K_FLUX1 : GKS_K_FLUX2, [&] {
+             return gks::launch_flux(c->dm, c->ds, c->par, dt, dtp, mode, c->fp32, s);
+         })))
+        return st;
+    return timed(c, stage == 1 ? GKS_K_UPDATE1 : GKS_K_UPDATE2,
+                 [&] { return gks::launch_update(c->dm, c->ds, dt, dtp, stage, c->fp32, s); });
 }
 
 gks_status gks_stage(gks_ctx *c, int32_t stage, double dt)
@@ -792,17 +809,8 @@ gks_status gks_stage(gks_ctx *c, int32_t stage, double dt)
     gks_status st = ready(c, true);
     if (st) return st;
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, GKS_E_INVAL, "dt must be positive and finite");
-    const hipStream_t s = c->stream;
     if (stage == 1) {
-        if ((st = timed(c, GKS_K_SLOPES, [&] { return gks::launch_slopes(c->dm, c->ds, c->fp32, s); }))) return st;
-        if ((st = timed(c, GKS_K_RECON, [&] { return gks::launch_reconstruct(c->dm, c->ds, c->par, c->fp32, s); })))
-            return st;
-        if ((st = timed(c, GKS_K_FLUX1, [&] {
-                 return gks::launch_flux(c->dm, c->ds, c->par, dt, gks::FLUX_STAGE1, c->fp32, s);
-             })))
-            return st;
-        if ((st = timed(c, GKS_K_UPDATE1, [&] { return gks::launch_update(c->dm, c->ds, dt, 1, c->fp32, s); })))
-            return st;
+        if ((st = stage_impl(c, 1, dt, nullptr))) return st;
         c->stage1_done = true;
         c->stage1_dt = dt;
         return GKS_OK;
@@ -810,15 +818,7 @@ gks_status gks_stage(gks_ctx *c, int32_t stage, double dt)
     if (stage == 2) {
         if (!c->stage1_done || dt != c->stage1_dt)
             return fail(c, GKS_E_ORDER, "stage 2 needs a preceding stage 1 with the same dt");
-        if ((st = timed(c, GKS_K_SLOPES, [&] { return gks::launch_slopes(c->dm, c->ds, c->fp32, s); }))) return st;
-        if ((st = timed(c, GKS_K_RECON, [&] { return gks::launch_reconstruct(c->dm, c->ds, c->par, c->fp32, s); })))
-            return st;
-        if ((st = timed(c, GKS_K_FLUX2, [&] {
-                 return gks::launch_flux(c->dm, c->ds, c->par, dt, gks::FLUX_STAGE2, c->fp32, s);
-             })))
-            return st;
-        if ((st = timed(c, GKS_K_UPDATE2, [&] { return gks::launch_update(c->dm, c->ds, dt, 2, c->fp32, s); })))
-            return st;
+        if ((st = stage_impl(c, 2, dt, nullptr))) return st;
         c->stage1_done = false;
         return GKS_OK;
     }
@@ -830,6 +830,32 @@ gks_status gks_step(gks_ctx *c, double dt)
     gks_status st = gks_stage(c, 1, dt);
     if (st) return st;
     return gks_stage(c, 2, dt);
+}
+
+gks_status gks_step_cfl(gks_ctx *c, double cfl)
+{
+    gks_status st = ready(c, true);
+    if (st) return st;
+    if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(c, GKS_E_INVAL, "cfl must be positive and finite");
+    if (c->stage1_done) return fail(c, GKS_E_ORDER, "a stage 1 is pending: finish it with stage 2 first");
+    st = timed(c, GKS_K_DT, [&] { return gks::launch_dt(c->dm, c->ds, c->par, cfl, c->stream); });
+    if (st) return st;
+    const double *dtp = c->ds.red + gks::kRedDt;
+    if ((st = stage_impl(c, 1, 0.0, dtp))) return st;
+    return stage_impl(c, 2, 0.0, dtp);
+}
+
+gks_status gks_last_dt(gks_ctx *c, double *dt)
+{
+    gks_status st = ready(c, true);
+    if (st) return st;
+    if (!dt) return fail(c, GKS_E_INVAL, "null output");
+    double v = 0.0;
+    HIP_TRY(c, hipMemcpyAsync(&v, c->ds.red + gks::kRedDt, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    st = read_nonphys(c, false);
+    if (st) return st;
+    *dt = v;
+    return GKS_OK;
 }
 
 gks_status gks_read_state(gks_ctx *c, double *W, double *gW, int32_t on_device)
@@ -912,7 +938,7 @@ gks_status gks_debug_face_terms(gks_ctx *c, double dt, double *out, int32_t on_d
     const hipStream_t s = c->stream;
     HIP_TRY(c, gks::launch_slopes(c->dm, c->ds, c->fp32, s));
     HIP_TRY(c, gks::launch_reconstruct(c->dm, c->ds, c->par, c->fp32, s));
-    HIP_TRY(c, gks::launch_flux(c->dm, c->ds, c->par, dt, gks::FLUX_DEBUG, c->fp32, s));
+    HIP_TRY(c, gks::launch_flux(c->dm, c->ds, c->par, dt, nullptr, gks::FLUX_DEBUG, c->fp32, s));
     c->stage1_done = false;  // the face buffers of a pending stage 1 are overwritten
     const int nf = c->nf;
     const void *src[4] = {c->ds.FF, c->ds.FT, c->ds.FW0, c->ds.FWs};

@@ -85,12 +85,16 @@ enum FluxMode { FLUX_STAGE1 = 0, FLUX_STAGE2 = 1, FLUX_DEBUG = 2 };
 hipError_t launch_slopes(const DevMesh &m, const DevState &s, bool fp32, hipStream_t st);
 hipError_t launch_reconstruct(const DevMesh &m, const DevState &s, const Params &p, bool fp32,
                               hipStream_t st);
-hipError_t launch_flux(const DevMesh &m, const DevState &s, const Params &p, double dt, int mode,
-                       bool fp32, hipStream_t st);
-hipError_t launch_update(const DevMesh &m, const DevState &s, double dt, int stage, bool fp32,
-                         hipStream_t st);
-// dt: writes min over cells of the CFL bound (without the CFL factor) to s.red[0]
-hipError_t launch_dt(const DevMesh &m, const DevState &s, const Params &p, hipStream_t st);
+// flux and update take the time step from *dtp when dtp is not null (a time
+// step that stays on the device), else from dt
+hipError_t launch_flux(const DevMesh &m, const DevState &s, const Params &p, double dt,
+                       const double *dtp, int mode, bool fp32, hipStream_t st);
+hipError_t launch_update(const DevMesh &m, const DevState &s, double dt, const double *dtp,
+                         int stage, bool fp32, hipStream_t st);
+// dt: writes the min over cells of the CFL bound (without the CFL factor) to
+// s.red[0] and cfl times it, the time step, to s.red[kRedDt]
+hipError_t launch_dt(const DevMesh &m, const DevState &s, const Params &p, double cfl,
+                     hipStream_t st);
 // conservation sums: writes sum_i |Omega_i| W_i to s.red[0..4]
 hipError_t launch_sums(const DevMesh &m, const DevState &s, hipStream_t st);
 // physical check of the state: sets *s.nonphys when rho <= 0 or p <= 0
@@ -119,5 +123,7 @@ inline size_t m2_padded_cells(size_t nc) { return (nc + kM2Tile - 1) / kM2Tile *
 constexpr int kBlock = 256;
 // number of blocks of the reduction kernels' first pass
 constexpr int kRedBlocks = 1024;
+// slot of s.red that holds the last time step (slots 0..4 take the sums)
+constexpr int kRedDt = 6;
 
 }  // namespace gks

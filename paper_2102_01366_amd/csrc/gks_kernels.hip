@@ -15,6 +15,20 @@ namespace gks {
 
 __device__ __forceinline__ int gid() { return blockIdx.x * blockDim.x + threadIdx.x; }
 
+// Workgroups go to the chip's 8 XCDs round-robin (workgroup b to XCD b mod 8),
+// and each XCD has its own L2.  The kernels that gather neighbours renumber
+// their workgroups so that each XCD takes one contiguous range of cells or
+// faces: ranges adjacent in the space-filling order, whose neighbour gathers
+// then hit the L2 that loaded them.  A bijection of [0, gridDim.x).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block()
+{
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int q = nb / kXcds, r = nb % kXcds, x = b % kXcds, k = b / kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+__device__ __forceinline__ int xcd_gid() { return xcd_block() * blockDim.x + threadIdx.x; }
+
 // ===========================================================================
 // A1: reconstruction step 1 (Sec. 4.3) -- P^1 slopes b = M1 (Q_m - Q_0)
 // R is the bulk type (double, or float in the FP32-bulk form); the
@@ -23,7 +37,7 @@ __device__ __forceinline__ int gid() { return blockIdx.x * blockDim.x + threadId
 template <typename R>
 __global__ __launch_bounds__(kBlock) void slopes_kernel(DevMesh m, DevState s)
 {
-    const int i = gid();
+    const int i = xcd_gid();
     const int n = m.nc;
     if (i >= n) return;
     const R *M1 = static_cast<const R *>(m.M1);
@@ -123,10 +137,11 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
     const int n = m.nc;
     const int q = threadIdx.x / kRecCells;  // component, uniform over the wavefront
     const int l = threadIdx.x % kRecCells;
-    const int i = blockIdx.x * kRecCells + l;
+    const int tb = xcd_block();
+    const int i = tb * kRecCells + l;
     const bool live = i < n;
     const R *geo = static_cast<const R *>(m.geoR);
-    const R *tile = static_cast<const R *>(m.M2) + (size_t)blockIdx.x * kM2Rows * kRecCells;
+    const R *tile = static_cast<const R *>(m.M2) + (size_t)tb * kM2Rows * kRecCells;
     const R *slopes = static_cast<const R *>(s.slopes);
     R *coef = static_cast<R *>(s.coef);
     const R eps = R(p.eps_weno), g22 = R(p.g22), g12 = R(p.g12), g02 = R(p.g02), g11 = R(p.g11);
@@ -350,16 +365,17 @@ constexpr int kFacesPerWave = 21;
 constexpr int kFacesPerBlock = kFacesPerWave * (kFluxThreads / 64);
 
 template <typename R, int MODE, bool VISC, bool PRFIX>
-__global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(DevMesh m, DevState s, Params p, double dt_)
+__global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(DevMesh m, DevState s, Params p, double dt_,
+                                                                             const double *dtp)
 {
     const int nf = m.nf, n = m.nc;
-    const R dt = R(dt_);
+    const R dt = R(dtp ? *dtp : dt_);
     const R *coef = static_cast<const R *>(s.coef);
     R *FF = static_cast<R *>(s.FF), *FT = static_cast<R *>(s.FT), *FW0 = static_cast<R *>(s.FW0),
       *FWs = static_cast<R *>(s.FWs);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane / 3, k = lane - 3 * slot;
-    const int f = blockIdx.x * kFacesPerBlock + wave * kFacesPerWave + slot;
+    const int f = xcd_block() * kFacesPerBlock + wave * kFacesPerWave + slot;
     const bool live = slot < kFacesPerWave && f < nf;
     R acc[4][5];
     if (live) {
@@ -413,27 +429,28 @@ __global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(
 
 template <typename R, int MODE>
 static void launch_flux_mode(const DevMesh &m, const DevState &s, const Params &p, double dt,
-                             hipStream_t st)
+                             const double *dtp, hipStream_t st)
 {
     const dim3 grid((unsigned)((m.nf + kFacesPerBlock - 1) / kFacesPerBlock)), block(kFluxThreads);
     const bool visc = p.viscous != 0, prfix = p.prandtl != 1.0;
     if (visc && prfix)
-        hipLaunchKernelGGL((flux_kernel<R, MODE, true, true>), grid, block, 0, st, m, s, p, dt);
+        hipLaunchKernelGGL((flux_kernel<R, MODE, true, true>), grid, block, 0, st, m, s, p, dt, dtp);
     else if (visc)
-        hipLaunchKernelGGL((flux_kernel<R, MODE, true, false>), grid, block, 0, st, m, s, p, dt);
+        hipLaunchKernelGGL((flux_kernel<R, MODE, true, false>), grid, block, 0, st, m, s, p, dt, dtp);
     else if (prfix)
-        hipLaunchKernelGGL((flux_kernel<R, MODE, false, true>), grid, block, 0, st, m, s, p, dt);
+        hipLaunchKernelGGL((flux_kernel<R, MODE, false, true>), grid, block, 0, st, m, s, p, dt, dtp);
     else
-        hipLaunchKernelGGL((flux_kernel<R, MODE, false, false>), grid, block, 0, st, m, s, p, dt);
+        hipLaunchKernelGGL((flux_kernel<R, MODE, false, false>), grid, block, 0, st, m, s, p, dt, dtp);
 }
 
 // ===========================================================================
 // C: cell update (eqs. flux-operator, s2o4, gauss-formula, step-du)
 // ===========================================================================
 template <typename R, int STAGE>
-__global__ __launch_bounds__(kBlock) void update_kernel(DevMesh m, DevState s, double dt)
+__global__ __launch_bounds__(kBlock) void update_kernel(DevMesh m, DevState s, double dt_, const double *dtp)
 {
-    const int i = gid();
+    const double dt = dtp ? *dtp : dt_;
+    const int i = xcd_gid();
     const int n = m.nc, nf = m.nf;
     if (i >= n) return;
     const R *FF = static_cast<const R *>(s.FF), *FT = static_cast<const R *>(s.FT),
@@ -523,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void dt_pass1(DevMesh m, DevState s, Params
     }
 }
 
-__global__ __launch_bounds__(kBlock) void min_pass2(DevState s, int nparts)
+__global__ __launch_bounds__(kBlock) void min_pass2(DevState s, int nparts, double cfl)
 {
     __shared__ double sm[kBlock / 64];
     double best = INFINITY;
@@ -535,6 +552,7 @@ __global__ __launch_bounds__(kBlock) void min_pass2(DevState s, int nparts)
         double b = sm[0];
         for (int k = 1; k < kBlock / 64; ++k) b = fmin(b, sm[k]);
         s.red[0] = b;
+        s.red[kRedDt] = cfl * b;
     }
 }
 
@@ -644,51 +662,52 @@ hipError_t launch_reconstruct(const DevMesh &m, const DevState &s, const Params 
 }
 
 template <typename R>
-static void launch_flux_r(const DevMesh &m, const DevState &s, const Params &p, double dt, int mode,
-                          hipStream_t st)
+static void launch_flux_r(const DevMesh &m, const DevState &s, const Params &p, double dt,
+                          const double *dtp, int mode, hipStream_t st)
 {
     if (mode == FLUX_STAGE1)
-        launch_flux_mode<R, FLUX_STAGE1>(m, s, p, dt, st);
+        launch_flux_mode<R, FLUX_STAGE1>(m, s, p, dt, dtp, st);
     else if (mode == FLUX_STAGE2)
-        launch_flux_mode<R, FLUX_STAGE2>(m, s, p, dt, st);
+        launch_flux_mode<R, FLUX_STAGE2>(m, s, p, dt, dtp, st);
     else
-        launch_flux_mode<R, FLUX_DEBUG>(m, s, p, dt, st);
+        launch_flux_mode<R, FLUX_DEBUG>(m, s, p, dt, dtp, st);
 }
 
-hipError_t launch_flux(const DevMesh &m, const DevState &s, const Params &p, double dt, int mode,
-                       bool fp32, hipStream_t st)
+hipError_t launch_flux(const DevMesh &m, const DevState &s, const Params &p, double dt,
+                       const double *dtp, int mode, bool fp32, hipStream_t st)
 {
     if (fp32)
-        launch_flux_r<float>(m, s, p, dt, mode, st);
+        launch_flux_r<float>(m, s, p, dt, dtp, mode, st);
     else
-        launch_flux_r<double>(m, s, p, dt, mode, st);
+        launch_flux_r<double>(m, s, p, dt, dtp, mode, st);
     return hipGetLastError();
 }
 
-hipError_t launch_update(const DevMesh &m, const DevState &s, double dt, int stage, bool fp32,
-                         hipStream_t st)
+hipError_t launch_update(const DevMesh &m, const DevState &s, double dt, const double *dtp,
+                         int stage, bool fp32, hipStream_t st)
 {
     const dim3 g = grid_for(m.nc), b(kBlock);
     if (fp32) {
         if (stage == 1)
-            hipLaunchKernelGGL((update_kernel<float, 1>), g, b, 0, st, m, s, dt);
+            hipLaunchKernelGGL((update_kernel<float, 1>), g, b, 0, st, m, s, dt, dtp);
         else
-            hipLaunchKernelGGL((update_kernel<float, 2>), g, b, 0, st, m, s, dt);
+            hipLaunchKernelGGL((update_kernel<float, 2>), g, b, 0, st, m, s, dt, dtp);
     } else {
         if (stage == 1)
-            hipLaunchKernelGGL((update_kernel<double, 1>), g, b, 0, st, m, s, dt);
+            hipLaunchKernelGGL((update_kernel<double, 1>), g, b, 0, st, m, s, dt, dtp);
         else
-            hipLaunchKernelGGL((update_kernel<double, 2>), g, b, 0, st, m, s, dt);
+            hipLaunchKernelGGL((update_kernel<double, 2>), g, b, 0, st, m, s, dt, dtp);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_dt(const DevMesh &m, const DevState &s, const Params &p, hipStream_t st)
+hipError_t launch_dt(const DevMesh &m, const DevState &s, const Params &p, double cfl,
+                     hipStream_t st)
 {
     int blocks = (m.nc + kBlock - 1) / kBlock;
     if (blocks > kRedBlocks) blocks = kRedBlocks;
     hipLaunchKernelGGL(dt_pass1, dim3(blocks), dim3(kBlock), 0, st, m, s, p);
-    hipLaunchKernelGGL(min_pass2, dim3(1), dim3(kBlock), 0, st, s, blocks);
+    hipLaunchKernelGGL(min_pass2, dim3(1), dim3(kBlock), 0, st, s, blocks, cfl);
     return hipGetLastError();
 }
 

@@ -215,6 +215,32 @@ def test_bitwise_determinism():
     np.testing.assert_array_equal(out[0][1], out[1][1])
 
 
+def test_device_time_step_matches_host_time_step():
+    """gks_step_cfl (dt kept on the device) is bitwise gks_compute_dt + gks_step."""
+    m = I.kuhn_cube_mesh(5, 2 * np.pi, 0.05, 5, True)
+    W, gW = I.cell_averages(m, I.taylor_green_field(mach=0.3))
+    cfg = G.default_config(viscous=True, mu=0.002, prandtl=0.72)
+    a, b = G.Solver(m, cfg), G.Solver(m, cfg)
+    a.init(W, gW)
+    b.init(W, gW)
+    for _ in range(3):
+        dt = a.compute_dt(0.5)
+        a.step(dt)
+        b.step_cfl(0.5)
+        assert b.last_dt() == dt
+    Wa, gWa = a.read_state()
+    Wb, gWb = b.read_state()
+    np.testing.assert_array_equal(Wa, Wb)
+    np.testing.assert_array_equal(gWa, gWb)
+    b.stage(1, dt)
+    with pytest.raises(G.GksError) as e:
+        b.step_cfl(0.5)  # a stage 1 is pending
+    assert e.value.status == G.GKS_E_ORDER
+    with pytest.raises(G.GksError) as e:
+        a.step_cfl(float("nan"))
+    assert e.value.status == G.GKS_E_INVAL
+
+
 def test_device_pointers_match_host_pointers():
     import torch
     m = I.kuhn_cube_mesh(4, 1.0, 0.1, 6, True)
