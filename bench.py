@@ -52,6 +52,50 @@ BYTES_PER_UNIT = {
 UNIT = {"slopes": "cell", "reconstruct": "cell", "flux_stage1": "face", "flux_stage2": "face",
         "update_stage1": "cell", "update_stage2": "cell", "dt": "cell"}
 
+# rocprofv3 names of each timed kernel (FP64, FP32-bulk) of this workload
+# (viscous, Pr != 1)
+PROFILE_NAMES = {
+    "slopes": ("gks::slopes_kernel<double>", "gks::slopes_kernel<float>"),
+    "reconstruct": ("gks::reconstruct_kernel<double>", "gks::reconstruct_kernel<float>"),
+    "flux_stage1": ("gks::flux_kernel<double, 0, true, true>", "gks::flux_kernel<float, 0, true, true>"),
+    "flux_stage2": ("gks::flux_kernel<double, 1, true, true>", "gks::flux_kernel<float, 1, true, true>"),
+    "update_stage1": ("gks::update_kernel<double, 1>", "gks::update_kernel<float, 1>"),
+    "update_stage2": ("gks::update_kernel<double, 2>", "gks::update_kernel<float, 2>"),
+    "dt": ("gks::dt_pass1", None),  # one kernel serves both forms
+}
+# the kernel sources whose digest the committed counter summary records
+KERNEL_SOURCES = ("paper_2102_01366_amd/csrc/gks_kernels.hip", "paper_2102_01366_amd/csrc/gks_flux.h",
+                  "paper_2102_01366_amd/csrc/gks_internal.h")
+COUNTERS = os.path.join(ROOT, "profiles", "taylor_green_196608_counters.md")
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of the FP64 kernel `key` on the 196,608-cell mesh,
+    from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by
+    the copy-kernel calibration it states); None when that summary was taken
+    on other kernel sources."""
+    try:
+        with open(COUNTERS) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    if f"`{kernel_digest()}`" not in text:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 6 and cells[1] == f"{key} (fp64)":
+            return float(cells[5].replace(",", ""))
+    return None
+
 
 def I_cell_volumes(mesh):
     import numpy as np
@@ -143,14 +187,15 @@ def main():
         kernels[k] = entry
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     d = kernels[dom]
+    traffic = measured_traffic(dom) if args.n == 32 else None
     if dom.startswith("flux"):
         roof = {"kernel": dom, "bound": "alu", "achieved": d["fp64_TFLOPs"],
                 "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": d["fp64_TFLOPs"] / FP64_VECTOR_TFLOPS, "traffic": None,
+                "frac": d["fp64_TFLOPs"] / FP64_VECTOR_TFLOPS, "traffic": traffic,
                 "work_per_launch": f"{flops_face:.0f} FP64 ops/face x {nf} faces"}
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": d["hbm_GBs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": d["hbm_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                "unit": "GB/s", "frac": d["hbm_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
                 "work_per_launch": f"{BYTES_PER_UNIT[dom]} B/{UNIT[dom]} x {units[UNIT[dom]]}"}
 
     value = nc * 2 * args.steps / elapsed
