@@ -185,6 +185,29 @@ gks_status gks_timing_read(gks_ctx *ctx, double ms[GKS_NKERNELS], int64_t counts
  * routine on the host with a counting scalar.  Host only. */
 gks_status gks_flux_op_count(const gks_config *cfg, double counts[4]);
 
+/* Derivative checks of the flux routines, run on the host (no device work).
+ * Each evaluates the flux with a forward-mode dual number (the exact
+ * Jacobian-vector product J v) and its hand-written reverse (the
+ * vector-Jacobian product J^T ybar) on the same inputs, for tests.
+ *
+ * gks_flux_point_check: the time-dependent distribution at one interface point
+ * in the face frame (Sec. 2.2, eq. 2nd-flux).  x[40] = (W_l[5], dW_l/dx_d[3][5],
+ * W_r[5], dW_r/dx_d[3][5]); y[20] = (F(dt)[5], F(dt/2)[5], W(0)[5], W(dt)[5]).
+ * Outputs y, jv = J v, xbar = J^T ybar.
+ *
+ * gks_flux_face_check: the terms of one Gauss point of a face (eq.
+ * linear-system), acc[20] = (F, dF/dt, W(0), W(dt)) x |Gamma|/3, as functions of
+ * the two cells' coefficients coef[100] (owner [5][10], then neighbour [5][10],
+ * as gks_debug_reconstruct orders them).  geo[10] = (unit normal[3], area,
+ * Gauss point minus owner centroid[3], owner centroid minus neighbour
+ * centroid[3]).  Outputs acc, jv = J v, coefbar = J^T accbar.
+ * GKS_E_INVAL on a null pointer or dt <= 0. */
+gks_status gks_flux_point_check(const gks_config *cfg, double dt, const double x[40], const double v[40],
+                                const double ybar[20], double y[20], double jv[20], double xbar[40]);
+gks_status gks_flux_face_check(const gks_config *cfg, double dt, const double geo[10], const double coef[100],
+                               const double v[100], const double accbar[20], double acc[20], double jv[20],
+                               double coefbar[100]);
+
 /* Message of the last failure on this context (never NULL). */
 const char *gks_last_error(const gks_ctx *ctx);
 /* Name of a status code (never NULL). */

@@ -38,7 +38,8 @@ EXPORTS = ("gks_default_config", "gks_create", "gks_destroy", "gks_set_stream",
            "gks_compute_dt", "gks_stage", "gks_step", "gks_step_cfl", "gks_last_dt",
            "gks_read_state",
            "gks_conservation_sums", "gks_debug_reconstruct", "gks_debug_face_terms",
-           "gks_timing_enable", "gks_timing_read", "gks_flux_op_count", "gks_last_error",
+           "gks_timing_enable", "gks_timing_read", "gks_flux_op_count", "gks_flux_point_check",
+           "gks_flux_face_check", "gks_last_error",
            "gks_strerror")
 
 KERNELS = ("slopes", "reconstruct", "flux_stage1", "flux_stage2", "update_stage1",
@@ -104,6 +105,8 @@ def load_library(path: str = LIB_PATH):
         "gks_timing_enable": (S, [P, I32]),
         "gks_timing_read": (S, [P, P, P, I32]),
         "gks_flux_op_count": (S, [P, P]),
+        "gks_flux_point_check": (S, [P, D, P, P, P, P, P, P]),
+        "gks_flux_face_check": (S, [P, D, P, P, P, P, P, P, P]),
         "gks_last_error": (ctypes.c_char_p, [P]),
         "gks_strerror": (ctypes.c_char_p, [S]),
     }
@@ -144,6 +147,32 @@ def flux_op_count(config: Config | None = None) -> dict:
     d = {"add": out[0], "mul": out[1], "div": out[2], "special": out[3]}
     d["total"] = sum(out)
     return d
+
+
+def flux_point_check(config: Config, dt: float, x, v, ybar):
+    """Host check of the interface-point flux: (y, J v, J^T ybar), see gks.h."""
+    L = load_library()
+    x, v, yb = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, v, ybar))
+    assert x.shape == (40,) and v.shape == (40,) and yb.shape == (20,)
+    y, jv, xb = np.zeros(20), np.zeros(20), np.zeros(40)
+    st = L.gks_flux_point_check(ctypes.byref(config), float(dt), _ptr(x), _ptr(v), _ptr(yb),
+                                _ptr(y), _ptr(jv), _ptr(xb))
+    if st != GKS_OK:
+        raise GksError(st, "gks_flux_point_check failed")
+    return y, jv, xb
+
+
+def flux_face_check(config: Config, dt: float, geo, coef, v, accbar):
+    """Host check of one Gauss point's face terms: (acc, J v, J^T accbar), see gks.h."""
+    L = load_library()
+    geo, coef, v, ab = (np.ascontiguousarray(a, dtype=np.float64) for a in (geo, coef, v, accbar))
+    assert geo.shape == (10,) and coef.shape == (100,) and v.shape == (100,) and ab.shape == (20,)
+    acc, jv, cb = np.zeros(20), np.zeros(20), np.zeros(100)
+    st = L.gks_flux_face_check(ctypes.byref(config), float(dt), _ptr(geo), _ptr(coef), _ptr(v), _ptr(ab),
+                               _ptr(acc), _ptr(jv), _ptr(cb))
+    if st != GKS_OK:
+        raise GksError(st, "gks_flux_face_check failed")
+    return acc, jv, cb
 
 
 def _ptr(a) -> int:

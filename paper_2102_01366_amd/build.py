@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgks.so")
 SOURCES = [os.path.join(CSRC, "gks_kernels.hip"), os.path.join(CSRC, "gks_api.cpp"),
-           os.path.join(CSRC, "gks_opcount.cpp")]
+           os.path.join(CSRC, "gks_opcount.cpp"), os.path.join(CSRC, "gks_check.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for all device code.

@@ -13,6 +13,7 @@
 // neighbouring memory.
 #include "../../include/gks.h"
 #include "gks_internal.h"
+#include "gks_params.h"
 
 #include <algorithm>
 #include <climits>
@@ -314,23 +315,7 @@ gks_status gks_create(const gks_config *cfg, gks_ctx **out)
     gks_ctx *c = new (std::nothrow) gks_ctx();
     if (!c) return GKS_E_NOMEM;
     c->cfg = *cfg;
-    gks::Params &p = c->par;
-    p.gamma = cfg->gamma;
-    p.K = (5.0 - 3.0 * cfg->gamma) / (cfg->gamma - 1.0);
-    p.mu = cfg->mu;
-    p.prandtl = cfg->prandtl;
-    p.eps_tau = cfg->eps_tau;
-    p.c_tau = cfg->c_tau;
-    p.eps_weno = cfg->eps_weno;
-    const double s2 = cfg->lw2[0] + cfg->lw2[1] + cfg->lw2[2];
-    const double s1 = cfg->lw1[0] + cfg->lw1[1];
-    p.g22 = cfg->lw2[0] / s2;
-    p.g12 = cfg->lw2[1] / s2;
-    p.g02 = cfg->lw2[2] / s2;
-    p.g11 = cfg->lw1[0] / s1;
-    p.g01 = cfg->lw1[1] / s1;
-    p.viscous = cfg->viscous;
-    p.nonlinear = cfg->nonlinear;
+    c->par = gks::params_from_config(cfg);
     c->fp32 = cfg->precision == GKS_FP32_BULK;
     *out = c;
     return GKS_OK;

@@ -1,0 +1,158 @@
+// Host-side derivative checks of the flux routines.  The templated flux of
+// gks_flux.h is evaluated with a forward-mode dual number (an exact
+// Jacobian-vector product), beside the hand-written reverse of
+// gks_flux_adj.h (a vector-Jacobian product), on the same inputs; a test
+// compares <J v, ybar> with <v, J^T ybar> and J v with finite differences.
+#include "../../include/gks.h"
+#include "gks_flux_adj.h"
+#include "gks_params.h"
+
+#include <cmath>
+
+namespace {
+
+// value and one directional derivative
+struct Dual {
+    double v, d;
+    Dual() : v(0.0), d(0.0) {}
+    Dual(double x) : v(x), d(0.0) {}
+    Dual(double x, double y) : v(x), d(y) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) { return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual &operator+=(Dual &a, Dual b) { a = a + b; return a; }
+inline Dual &operator-=(Dual &a, Dual b) { a = a - b; return a; }
+inline Dual &operator*=(Dual &a, Dual b) { a = a * b; return a; }
+inline bool operator==(Dual a, Dual b) { return a.v == b.v; }
+inline bool operator!=(Dual a, Dual b) { return a.v != b.v; }
+inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
+inline bool operator>(Dual a, Dual b) { return a.v > b.v; }
+inline Dual exp(Dual a) { const double e = std::exp(a.v); return Dual(e, a.d * e); }
+inline Dual sqrt(Dual a) { const double s = std::sqrt(a.v); return Dual(s, a.d / (2.0 * s)); }
+// d erfc(x)/dx = -2/sqrt(pi) exp(-x^2)
+inline Dual erfc(Dual a) { return Dual(std::erfc(a.v), -a.d * 1.1283791670955126 * std::exp(-a.v * a.v)); }
+// sign(0) = 0, as in the reverse
+inline Dual fabs(Dual a) { return a.v > 0.0 ? a : (a.v < 0.0 ? -a : Dual(0.0, 0.0)); }
+
+template <typename R>
+struct ArrCoef {
+    const R *c;  // [5][10]
+    R operator()(int q, int k) const { return c[10 * q + k]; }
+};
+
+template <bool VISC, bool PRFIX>
+void point_check(const gks::Params &p, double dt, const double x[40], const double v[40], const double yb[20],
+                 double y[20], double jv[20], double xb[40])
+{
+    Dual wl[5], gl[3][5], wr[5], gr[3][5];
+    for (int q = 0; q < 5; ++q) {
+        wl[q] = Dual(x[q], v[q]);
+        wr[q] = Dual(x[20 + q], v[20 + q]);
+        for (int d = 0; d < 3; ++d) {
+            gl[d][q] = Dual(x[5 + 5 * d + q], v[5 + 5 * d + q]);
+            gr[d][q] = Dual(x[25 + 5 * d + q], v[25 + 5 * d + q]);
+        }
+    }
+    Dual Fo[2][5], Wo[2][5];
+    gks::gks_point<Dual, VISC, PRFIX>(p, Dual(dt), wl, gl, wr, gr, Fo, Wo);
+    for (int k = 0; k < 2; ++k)
+        for (int q = 0; q < 5; ++q) {
+            y[5 * k + q] = Fo[k][q].v;
+            jv[5 * k + q] = Fo[k][q].d;
+            y[10 + 5 * k + q] = Wo[k][q].v;
+            jv[10 + 5 * k + q] = Wo[k][q].d;
+        }
+    double dwl[5], dgl[3][5], dwr[5], dgr[3][5], Fob[2][5], Wob[2][5];
+    for (int q = 0; q < 5; ++q) {
+        dwl[q] = x[q];
+        dwr[q] = x[20 + q];
+        for (int d = 0; d < 3; ++d) {
+            dgl[d][q] = x[5 + 5 * d + q];
+            dgr[d][q] = x[25 + 5 * d + q];
+        }
+        for (int k = 0; k < 2; ++k) {
+            Fob[k][q] = yb[5 * k + q];
+            Wob[k][q] = yb[10 + 5 * k + q];
+        }
+    }
+    double wlb[5] = {0}, glb[3][5] = {{0}}, wrb[5] = {0}, grb[3][5] = {{0}};
+    gks::gks_point_vjp<double, VISC, PRFIX>(p, dt, dwl, dgl, dwr, dgr, Fob, Wob, wlb, glb, wrb, grb);
+    for (int q = 0; q < 5; ++q) {
+        xb[q] = wlb[q];
+        xb[20 + q] = wrb[q];
+        for (int d = 0; d < 3; ++d) {
+            xb[5 + 5 * d + q] = glb[d][q];
+            xb[25 + 5 * d + q] = grb[d][q];
+        }
+    }
+}
+
+template <bool VISC, bool PRFIX>
+void face_check(const gks::Params &p, double dt, const double geo[10], const double coef[100],
+                const double v[100], const double ab[20], double acc[20], double jv[20], double cb[100])
+{
+    Dual nrm[3], r[3], dv[3], cd[100];
+    for (int d = 0; d < 3; ++d) {
+        nrm[d] = Dual(geo[d]);
+        r[d] = Dual(geo[4 + d]);
+        dv[d] = Dual(geo[7 + d]);
+    }
+    for (int k = 0; k < 100; ++k) cd[k] = Dual(coef[k], v[k]);
+    Dual t[4][5];
+    gks::gauss_point_terms<Dual, VISC, PRFIX>(p, Dual(dt), nrm, Dual(geo[3]), r, dv, ArrCoef<Dual>{cd},
+                                              ArrCoef<Dual>{cd + 50}, t);
+    for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < 5; ++q) {
+            acc[5 * a + q] = t[a][q].v;
+            jv[5 * a + q] = t[a][q].d;
+        }
+    double nn[3], rr[3], dd[3], accb[4][5], cbl[5][10] = {{0}}, cbr[5][10] = {{0}};
+    for (int d = 0; d < 3; ++d) {
+        nn[d] = geo[d];
+        rr[d] = geo[4 + d];
+        dd[d] = geo[7 + d];
+    }
+    for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < 5; ++q) accb[a][q] = ab[5 * a + q];
+    gks::gauss_point_terms_vjp<double, VISC, PRFIX>(p, dt, nn, geo[3], rr, dd, ArrCoef<double>{coef},
+                                                    ArrCoef<double>{coef + 50}, accb, cbl, cbr);
+    for (int q = 0; q < 5; ++q)
+        for (int k = 0; k < 10; ++k) {
+            cb[10 * q + k] = cbl[q][k];
+            cb[50 + 10 * q + k] = cbr[q][k];
+        }
+}
+
+}  // namespace
+
+extern "C" gks_status gks_flux_point_check(const gks_config *cfg, double dt, const double x[40],
+                                           const double v[40], const double ybar[20], double y[20],
+                                           double jv[20], double xbar[40])
+{
+    if (!cfg || !x || !v || !ybar || !y || !jv || !xbar || !(dt > 0.0)) return GKS_E_INVAL;
+    const gks::Params p = gks::params_from_config(cfg);
+    const bool visc = p.viscous != 0, prfix = p.prandtl != 1.0;
+    if (visc && prfix) point_check<true, true>(p, dt, x, v, ybar, y, jv, xbar);
+    else if (visc) point_check<true, false>(p, dt, x, v, ybar, y, jv, xbar);
+    else if (prfix) point_check<false, true>(p, dt, x, v, ybar, y, jv, xbar);
+    else point_check<false, false>(p, dt, x, v, ybar, y, jv, xbar);
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_flux_face_check(const gks_config *cfg, double dt, const double geo[10],
+                                          const double coef[100], const double v[100],
+                                          const double accbar[20], double acc[20], double jv[20],
+                                          double coefbar[100])
+{
+    if (!cfg || !geo || !coef || !v || !accbar || !acc || !jv || !coefbar || !(dt > 0.0)) return GKS_E_INVAL;
+    const gks::Params p = gks::params_from_config(cfg);
+    const bool visc = p.viscous != 0, prfix = p.prandtl != 1.0;
+    if (visc && prfix) face_check<true, true>(p, dt, geo, coef, v, accbar, acc, jv, coefbar);
+    else if (visc) face_check<true, false>(p, dt, geo, coef, v, accbar, acc, jv, coefbar);
+    else if (prfix) face_check<false, true>(p, dt, geo, coef, v, accbar, acc, jv, coefbar);
+    else face_check<false, false>(p, dt, geo, coef, v, accbar, acc, jv, coefbar);
+    return GKS_OK;
+}

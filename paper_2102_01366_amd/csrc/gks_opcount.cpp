@@ -5,6 +5,7 @@
 // the branches the configuration selects (viscous slopes, Prandtl number).
 #include "../../include/gks.h"
 #include "gks_flux.h"
+#include "gks_params.h"
 
 #include <cmath>
 #include <cstdint>
@@ -49,15 +50,7 @@ struct HostCoef {
 extern "C" gks_status gks_flux_op_count(const gks_config *cfg, double counts[4])
 {
     if (!cfg || !counts) return GKS_E_INVAL;
-    gks::Params p{};
-    p.gamma = cfg->gamma;
-    p.K = (5.0 - 3.0 * cfg->gamma) / (cfg->gamma - 1.0);
-    p.mu = cfg->mu;
-    p.prandtl = cfg->prandtl;
-    p.eps_tau = cfg->eps_tau;
-    p.c_tau = cfg->c_tau;
-    p.viscous = cfg->viscous;
-    p.nonlinear = cfg->nonlinear;
+    const gks::Params p = gks::params_from_config(cfg);
     // a generic face: unit normal away from the coordinate axes, two
     // different physical states with gradients
     double cl[50], cr[50];
