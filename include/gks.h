@@ -141,6 +141,33 @@ gks_status gks_step(gks_ctx *ctx, double dt);
 gks_status gks_step_cfl(gks_ctx *ctx, double cfl);
 /* The time step of the last gks_step_cfl or gks_compute_dt (blocking). */
 gks_status gks_last_dt(gks_ctx *ctx, double *dt);
+/* Discrete adjoint (hand-written reverse of the forward kernels; not part of
+ * the paper, which has no adjoint).
+ *
+ * gks_adjoint_workspace_bytes / gks_bind_adjoint_workspace: a second device
+ * buffer (256-byte aligned, caller-owned, kept alive until gks_destroy) for
+ * the adjoint's recomputed forward quantities and adjoint arrays, about 5 KB
+ * per cell in FP64.  Bind after gks_bind_workspace.
+ *
+ * gks_step_adjoint: the transpose of the Jacobian of one step of eq. s2o4
+ * with the time step dt held fixed (dt is not differentiated).  Given the
+ * state before the step (W_n[5][n], gW_n[15][n]) and the adjoints of the
+ * state after it (Wbar_np1, gWbar_np1), writes the adjoints of the state
+ * before it (Wbar_n, gWbar_n).  All six are DEVICE pointers in the caller's
+ * cell order, component-major as in gks_init; the outputs may alias the
+ * inputs.  Stage 1 and stage 2's reconstruction are recomputed from W_n; the
+ * reconstruction is differentiated as implemented (the WENO weights with
+ * d|x|/dx = sign(x), sign(0) = 0, and x^(4/3) -> (4/3) x^(1/3); the
+ * positivity fallback as taken).  Asynchronous on the context's stream; it
+ * leaves the context's own state untouched.  GKS_E_STATE without an adjoint
+ * workspace, GKS_E_INVAL on a null pointer or a dt that is not positive and
+ * finite. */
+gks_status gks_adjoint_workspace_bytes(const gks_ctx *ctx, size_t *bytes);
+gks_status gks_bind_adjoint_workspace(gks_ctx *ctx, void *device_ptr, size_t bytes);
+gks_status gks_step_adjoint(gks_ctx *ctx, double dt, const double *W_n, const double *gW_n,
+                            const double *Wbar_np1, const double *gWbar_np1, double *Wbar_n,
+                            double *gWbar_n);
+
 /* Copy the state out (blocking when on_device == 0).  Reports a pending
  * non-physical flag as GKS_E_NONPHYSICAL. */
 gks_status gks_read_state(gks_ctx *ctx, double *W, double *gW, int32_t on_device);
@@ -207,6 +234,15 @@ gks_status gks_flux_point_check(const gks_config *cfg, double dt, const double x
 gks_status gks_flux_face_check(const gks_config *cfg, double dt, const double geo[10], const double coef[100],
                                const double v[100], const double accbar[20], double acc[20], double jv[20],
                                double coefbar[100]);
+/* The same check for the nonlinear combination of reconstruction step 2
+ * (Secs. 4.2-4.3) of one cell and component: x[25] = (Q0, the fit
+ * (g, H)[9], the cell's step-1 slopes[3], its four neighbours' slopes[4][3]);
+ * geo[8] = (centroid second moments / |Omega| [6], |Omega|^(2/3),
+ * |Omega|^(4/3)); bit a of has_mask set when neighbour a exists.  r[10] =
+ * the coefficients (c0, G, H).  Outputs r, jv = J v, xbar = J^T rbar. */
+gks_status gks_weno_check(const gks_config *cfg, const double geo[8], int32_t has_mask, const double x[25],
+                          const double v[25], const double rbar[10], double r[10], double jv[10],
+                          double xbar[25]);
 
 /* Message of the last failure on this context (never NULL). */
 const char *gks_last_error(const gks_ctx *ctx);

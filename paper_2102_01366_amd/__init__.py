@@ -36,10 +36,11 @@ GKS_FP32_BULK = 1
 EXPORTS = ("gks_default_config", "gks_create", "gks_destroy", "gks_set_stream",
            "gks_mesh_upload", "gks_workspace_bytes", "gks_bind_workspace", "gks_init",
            "gks_compute_dt", "gks_stage", "gks_step", "gks_step_cfl", "gks_last_dt",
+           "gks_adjoint_workspace_bytes", "gks_bind_adjoint_workspace", "gks_step_adjoint",
            "gks_read_state",
            "gks_conservation_sums", "gks_debug_reconstruct", "gks_debug_face_terms",
            "gks_timing_enable", "gks_timing_read", "gks_flux_op_count", "gks_flux_point_check",
-           "gks_flux_face_check", "gks_last_error",
+           "gks_flux_face_check", "gks_weno_check", "gks_last_error",
            "gks_strerror")
 
 KERNELS = ("slopes", "reconstruct", "flux_stage1", "flux_stage2", "update_stage1",
@@ -97,6 +98,9 @@ def load_library(path: str = LIB_PATH):
         "gks_stage": (S, [P, I32, D]),
         "gks_step": (S, [P, D]),
         "gks_step_cfl": (S, [P, D]),
+        "gks_adjoint_workspace_bytes": (S, [P, P]),
+        "gks_bind_adjoint_workspace": (S, [P, P, ctypes.c_size_t]),
+        "gks_step_adjoint": (S, [P, D, P, P, P, P, P, P]),
         "gks_last_dt": (S, [P, P]),
         "gks_read_state": (S, [P, P, P, I32]),
         "gks_conservation_sums": (S, [P, P]),
@@ -107,6 +111,7 @@ def load_library(path: str = LIB_PATH):
         "gks_flux_op_count": (S, [P, P]),
         "gks_flux_point_check": (S, [P, D, P, P, P, P, P, P]),
         "gks_flux_face_check": (S, [P, D, P, P, P, P, P, P, P]),
+        "gks_weno_check": (S, [P, P, I32, P, P, P, P, P, P]),
         "gks_last_error": (ctypes.c_char_p, [P]),
         "gks_strerror": (ctypes.c_char_p, [S]),
     }
@@ -173,6 +178,19 @@ def flux_face_check(config: Config, dt: float, geo, coef, v, accbar):
     if st != GKS_OK:
         raise GksError(st, "gks_flux_face_check failed")
     return acc, jv, cb
+
+
+def weno_check(config: Config, geo, has_mask: int, x, v, rbar):
+    """Host check of the step-2 nonlinear combination: (r, J v, J^T rbar), see gks.h."""
+    L = load_library()
+    geo, x, v, rb = (np.ascontiguousarray(a, dtype=np.float64) for a in (geo, x, v, rbar))
+    assert geo.shape == (8,) and x.shape == (25,) and v.shape == (25,) and rb.shape == (10,)
+    r, jv, xb = np.zeros(10), np.zeros(10), np.zeros(25)
+    st = L.gks_weno_check(ctypes.byref(config), _ptr(geo), int(has_mask), _ptr(x), _ptr(v), _ptr(rb),
+                          _ptr(r), _ptr(jv), _ptr(xb))
+    if st != GKS_OK:
+        raise GksError(st, "gks_weno_check failed")
+    return r, jv, xb
 
 
 def _ptr(a) -> int:
@@ -252,6 +270,34 @@ class Solver:
             raise ValueError("W must be [5, n_cell] and gW [15, n_cell]")
         self._check(self.L.gks_init(self._h, ctypes.c_void_p(_ptr(W)), ctypes.c_void_p(_ptr(gW)),
                                     1 if on_dev else 0), "init")
+
+    def bind_adjoint(self):
+        """Allocate and bind the adjoint workspace (once)."""
+        if getattr(self, "adjoint_workspace", None) is not None:
+            return
+        nbytes = ctypes.c_size_t()
+        self._check(self.L.gks_adjoint_workspace_bytes(self._h, ctypes.byref(nbytes)), "adjoint_workspace_bytes")
+        self.adjoint_workspace = self._torch.empty(int(nbytes.value), dtype=self._torch.uint8, device=self.device)
+        self._check(self.L.gks_bind_adjoint_workspace(self._h, ctypes.c_void_p(self.adjoint_workspace.data_ptr()),
+                                                      int(nbytes.value)), "bind_adjoint_workspace")
+
+    def step_adjoint(self, dt: float, W, gW, Wbar, gWbar):
+        """Adjoints of (W, gW) before a step of size dt, given the state (W, gW)
+        before it and the adjoints (Wbar, gWbar) of the state after it (CUDA
+        float64 tensors [5, n] and [15, n]).  Returns new tensors."""
+        t = self._torch
+        self.bind_adjoint()
+        args = []
+        for a, rows in ((W, 5), (gW, 15), (Wbar, 5), (gWbar, 15)):
+            if not self._dev(a) or tuple(a.shape) != (rows, self.nc):
+                raise ValueError("step_adjoint takes CUDA tensors [5, n] and [15, n]")
+            args.append(a.contiguous().to(t.float64))
+        Wo = t.empty((5, self.nc), dtype=t.float64, device=self.device)
+        Go = t.empty((15, self.nc), dtype=t.float64, device=self.device)
+        self._check(self.L.gks_step_adjoint(self._h, float(dt), *(ctypes.c_void_p(a.data_ptr()) for a in args),
+                                            ctypes.c_void_p(Wo.data_ptr()), ctypes.c_void_p(Go.data_ptr())),
+                    "step_adjoint")
+        return Wo, Go
 
     def compute_dt(self, cfl: float) -> float:
         dt = ctypes.c_double()

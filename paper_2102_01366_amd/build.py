@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgks.so")
-SOURCES = [os.path.join(CSRC, "gks_kernels.hip"), os.path.join(CSRC, "gks_api.cpp"),
+SOURCES = [os.path.join(CSRC, "gks_kernels.hip"), os.path.join(CSRC, "gks_adjoint.hip"), os.path.join(CSRC, "gks_api.cpp"),
            os.path.join(CSRC, "gks_opcount.cpp"), os.path.join(CSRC, "gks_check.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -38,7 +38,7 @@ struct gks_ctx {
     int nc = 0, nf = 0;
     bool fp32 = false;              // FP32-bulk form
     std::vector<int> cperm, fperm;  // internal -> caller
-    std::vector<int> nbr, cface, fcell;
+    std::vector<int> nbr, cface, fcell, bslot;
     std::vector<double> M1, M2, geoR, geoD, fgeo, fnrm;
     // workspace
     bool bound = false;
@@ -47,6 +47,14 @@ struct gks_ctx {
     DevMesh dm{};
     DevState ds{};
     int *d_cperm = nullptr, *d_fperm = nullptr;
+    // adjoint workspace (gks_bind_adjoint_workspace)
+    bool adj_bound = false;
+    struct Adj {
+        double *Wchk, *Gchk, *Ws, *Gs, *Wn, *Ln, *Ltn, *Wb1, *Gb1, *Wbs, *Gbs, *Wbn, *Gbn;
+        void *slopes1, *slopes2, *coef1, *coef2, *FF, *FT, *FW0, *FWs;
+        int *flag1, *flag2, *nonphys;
+        double *CB, *own_w, *own_s, *nb_w, *nb_g, *nb_s, *nb_w1, *Wtmp, *red;
+    } adj{};
     double *staging = nullptr;
     int *istaging = nullptr;
     bool have_state = false;
@@ -209,7 +217,7 @@ struct Layout {
 enum Slot {
     S_NBR, S_CFACE, S_M1, S_M2, S_GEOR, S_GEOD, S_FCELL, S_FGEO, S_FNRM, S_W, S_GW, S_WN, S_LN, S_LTN,
     S_SLOPES, S_COEF, S_FLAG, S_FF, S_FT, S_FW0, S_FWS, S_RED, S_NONPHYS, S_CPERM, S_FPERM,
-    S_STAGING, S_ISTAGING, S_COUNT
+    S_STAGING, S_ISTAGING, S_BSLOT, S_COUNT
 };
 
 // bs: bytes of a bulk element (8 in FP64, 4 in FP32-bulk)
@@ -223,7 +231,7 @@ Layout make_layout(size_t nc, size_t nf, size_t bs)
         5 * nc * 8, 15 * nc * 8, 5 * nc * 8, 5 * nc * 8, 5 * nc * 8, 15 * nc * bs, 50 * nc * bs,
         nc * sizeof(int), 5 * nf * bs, 5 * nf * bs, 5 * nf * bs, 5 * nf * bs,
         (8 + 5 * (size_t)gks::kRedBlocks) * 8, 64, nc * sizeof(int), nf * sizeof(int),
-        std::max(50 * nc, 20 * nf) * 8, nc * sizeof(int)};
+        std::max(50 * nc, 20 * nf) * 8, nc * sizeof(int), 4 * nc * sizeof(int)};
     Layout L;
     size_t o = 0;
     for (int k = 0; k < S_COUNT; ++k) {
@@ -604,6 +612,21 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
     c->nf = nf;
     c->cperm.swap(cperm);
     c->fperm.swap(fperm);
+    // back slots: slot b of neighbour j = nbr[a][i] is the same face as slot a of i
+    std::vector<int> bslot(4 * (size_t)nc, -1);
+    for (int ii = 0; ii < nc; ++ii)
+        for (int a = 0; a < 4; ++a) {
+            const int j = nbr[(size_t)a * nc + ii];
+            if (j < 0) continue;
+            const int f = cface[(size_t)a * nc + ii] >> 1;
+            for (int b = 0; b < 4; ++b)
+                if ((cface[(size_t)b * nc + j] >> 1) == f) {
+                    bslot[(size_t)a * nc + ii] = b;
+                    break;
+                }
+            if (bslot[(size_t)a * nc + ii] < 0) return fail(c, GKS_E_MESH, "inconsistent face-cell adjacency");
+        }
+    c->bslot.swap(bslot);
     c->nbr.swap(nbr);
     c->cface.swap(cface);
     c->fcell.swap(fcell);
@@ -648,6 +671,7 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     dm.fcell = (const int *)P(S_FCELL);
     dm.fgeo = P(S_FGEO);
     dm.fnrm = (const double *)P(S_FNRM);
+    dm.bslot = (const int *)P(S_BSLOT);
     ds.W = (double *)P(S_W);
     ds.gW = (double *)P(S_GW);
     ds.Wn = (double *)P(S_WN);
@@ -689,6 +713,7 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     HIP_TRY(c, up((void *)dm.fcell, c->fcell.data(), 2 * nf * sizeof(int)));
     HIP_TRY(c, up_bulk(dm.fgeo, c->fgeo));
     HIP_TRY(c, up((void *)dm.fnrm, c->fnrm.data(), 3 * nf * 8));
+    HIP_TRY(c, up((void *)dm.bslot, c->bslot.data(), 4 * nc * sizeof(int)));
     HIP_TRY(c, up(c->d_cperm, c->cperm.data(), nc * sizeof(int)));
     HIP_TRY(c, up(c->d_fperm, c->fperm.data(), nf * sizeof(int)));
     HIP_TRY(c, gks::launch_fill_int(ds.nonphys, 0, st));
@@ -697,6 +722,7 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     std::vector<int>().swap(c->nbr);
     std::vector<int>().swap(c->cface);
     std::vector<int>().swap(c->fcell);
+    std::vector<int>().swap(c->bslot);
     std::vector<double>().swap(c->M1);
     std::vector<double>().swap(c->M2);
     std::vector<double>().swap(c->geoR);
@@ -840,6 +866,181 @@ gks_status gks_last_dt(gks_ctx *c, double *dt)
     st = read_nonphys(c, false);
     if (st) return st;
     *dt = v;
+    return GKS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Discrete adjoint of one step
+
+namespace {
+
+// slots of the adjoint workspace; bulk arrays take bs bytes per element
+enum AdjSlot {
+    A_WCHK, A_GCHK, A_WS, A_GS, A_WN, A_LN, A_LTN, A_WB1, A_GB1, A_WBS, A_GBS, A_WBN, A_GBN,
+    A_SLOPES1, A_SLOPES2, A_COEF1, A_COEF2, A_FF, A_FT, A_FW0, A_FWS, A_FLAG1, A_FLAG2, A_NONPHYS,
+    A_CB, A_OWNW, A_OWNS, A_NBW, A_NBG, A_NBS, A_NBW1, A_WTMP, A_RED, A_COUNT
+};
+
+Layout make_adj_layout(size_t nc, size_t nf, size_t bs)
+{
+    const size_t d5 = 5 * nc * 8, d15 = 15 * nc * 8;
+    const size_t sz[A_COUNT] = {
+        d5, d15, d5, d15, d5, d5, d5, d5, d15, d5, d15, d5, d15,
+        15 * nc * bs, 15 * nc * bs, 50 * nc * bs, 50 * nc * bs,
+        5 * nf * bs, 5 * nf * bs, 5 * nf * bs, 5 * nf * bs,
+        nc * sizeof(int), nc * sizeof(int), 64,
+        100 * nf * 8, d5, d15, 4 * d5, 4 * d15, 4 * d15, 4 * d5, d5,
+        (8 + 5 * (size_t)gks::kRedBlocks) * 8};
+    Layout L;
+    size_t o = 0;
+    for (int k = 0; k < A_COUNT; ++k) {
+        L.off[k] = o;
+        o += (sz[k] + 255) & ~size_t(255);
+    }
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+gks_status gks_adjoint_workspace_bytes(const gks_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return GKS_E_INVAL;
+    if (!c->have_mesh) return GKS_E_STATE;
+    *bytes = make_adj_layout(c->nc, c->nf, c->fp32 ? 4 : 8).total;
+    return GKS_OK;
+}
+
+gks_status gks_bind_adjoint_workspace(gks_ctx *c, void *dev, size_t bytes)
+{
+    if (!c || !dev) return GKS_E_INVAL;
+    if (!c->bound) return fail(c, GKS_E_STATE, "bind the forward workspace first");
+    if (c->adj_bound) return fail(c, GKS_E_STATE, "adjoint workspace already bound");
+    if (((uintptr_t)dev) & 255) return fail(c, GKS_E_INVAL, "workspace must be 256-byte aligned");
+    const Layout L = make_adj_layout(c->nc, c->nf, c->fp32 ? 4 : 8);
+    if (bytes < L.total) return fail(c, GKS_E_NOMEM, "adjoint workspace too small");
+    char *w = (char *)dev;
+    auto P = [&](int k) { return (void *)(w + L.off[k]); };
+    gks_ctx::Adj &a = c->adj;
+    a.Wchk = (double *)P(A_WCHK);
+    a.Gchk = (double *)P(A_GCHK);
+    a.Ws = (double *)P(A_WS);
+    a.Gs = (double *)P(A_GS);
+    a.Wn = (double *)P(A_WN);
+    a.Ln = (double *)P(A_LN);
+    a.Ltn = (double *)P(A_LTN);
+    a.Wb1 = (double *)P(A_WB1);
+    a.Gb1 = (double *)P(A_GB1);
+    a.Wbs = (double *)P(A_WBS);
+    a.Gbs = (double *)P(A_GBS);
+    a.Wbn = (double *)P(A_WBN);
+    a.Gbn = (double *)P(A_GBN);
+    a.slopes1 = P(A_SLOPES1);
+    a.slopes2 = P(A_SLOPES2);
+    a.coef1 = P(A_COEF1);
+    a.coef2 = P(A_COEF2);
+    a.FF = P(A_FF);
+    a.FT = P(A_FT);
+    a.FW0 = P(A_FW0);
+    a.FWs = P(A_FWS);
+    a.flag1 = (int *)P(A_FLAG1);
+    a.flag2 = (int *)P(A_FLAG2);
+    a.nonphys = (int *)P(A_NONPHYS);
+    a.CB = (double *)P(A_CB);
+    a.own_w = (double *)P(A_OWNW);
+    a.own_s = (double *)P(A_OWNS);
+    a.nb_w = (double *)P(A_NBW);
+    a.nb_g = (double *)P(A_NBG);
+    a.nb_s = (double *)P(A_NBS);
+    a.nb_w1 = (double *)P(A_NBW1);
+    a.Wtmp = (double *)P(A_WTMP);
+    a.red = (double *)P(A_RED);
+    HIP_TRY(c, gks::launch_fill_int(a.nonphys, 0, c->stream));
+    c->adj_bound = true;
+    return GKS_OK;
+}
+
+gks_status gks_step_adjoint(gks_ctx *c, double dt, const double *W_n, const double *gW_n,
+                            const double *Wbar_np1, const double *gWbar_np1, double *Wbar_n,
+                            double *gWbar_n)
+{
+    if (!c) return GKS_E_INVAL;
+    gks_status st = ready(c, false);
+    if (st) return st;
+    if (!c->adj_bound) return fail(c, GKS_E_STATE, "no adjoint workspace bound");
+    if (!W_n || !gW_n || !Wbar_np1 || !gWbar_np1 || !Wbar_n || !gWbar_n)
+        return fail(c, GKS_E_INVAL, "null pointer");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, GKS_E_INVAL, "dt must be positive and finite");
+    const hipStream_t s = c->stream;
+    const int nc = c->nc;
+    const bool f32 = c->fp32;
+    gks_ctx::Adj &a = c->adj;
+    const DevMesh &dm = c->dm;
+    // caller order -> internal order
+    HIP_TRY(c, gks::launch_permute_rows(a.Wchk, W_n, c->d_cperm, nc, 5, 0, false, s));
+    HIP_TRY(c, gks::launch_permute_rows(a.Gchk, gW_n, c->d_cperm, nc, 15, 0, false, s));
+    HIP_TRY(c, gks::launch_permute_rows(a.Ws, W_n, c->d_cperm, nc, 5, 0, false, s));
+    HIP_TRY(c, gks::launch_permute_rows(a.Gs, gW_n, c->d_cperm, nc, 15, 0, false, s));
+    HIP_TRY(c, gks::launch_permute_rows(a.Wb1, Wbar_np1, c->d_cperm, nc, 5, 0, false, s));
+    HIP_TRY(c, gks::launch_permute_rows(a.Gb1, gWbar_np1, c->d_cperm, nc, 15, 0, false, s));
+    // forward recomputation of stage 1 (W*, grad W* into Ws, Gs) and of
+    // stage 2's reconstruction, on the adjoint workspace
+    DevState f1 = c->ds;
+    f1.W = a.Ws;
+    f1.gW = a.Gs;
+    f1.Wn = a.Wn;
+    f1.Ln = a.Ln;
+    f1.Ltn = a.Ltn;
+    f1.slopes = a.slopes1;
+    f1.coef = a.coef1;
+    f1.flag = a.flag1;
+    f1.FF = a.FF;
+    f1.FT = a.FT;
+    f1.FW0 = a.FW0;
+    f1.FWs = a.FWs;
+    f1.red = a.red;
+    f1.nonphys = a.nonphys;
+    HIP_TRY(c, gks::launch_slopes(dm, f1, f32, s));
+    HIP_TRY(c, gks::launch_reconstruct(dm, f1, c->par, f32, s));
+    HIP_TRY(c, gks::launch_flux(dm, f1, c->par, dt, nullptr, gks::FLUX_STAGE1, f32, s));
+    HIP_TRY(c, gks::launch_update(dm, f1, dt, nullptr, 1, f32, s));
+    DevState f2 = f1;
+    f2.slopes = a.slopes2;
+    f2.coef = a.coef2;
+    f2.flag = a.flag2;
+    HIP_TRY(c, gks::launch_slopes(dm, f2, f32, s));
+    HIP_TRY(c, gks::launch_reconstruct(dm, f2, c->par, f32, s));
+    // stage 2 in reverse: W^{n+1}, grad W^{n+1} -> W*, grad W*
+    gks::AdjRecon r{};
+    r.CB = a.CB;
+    r.own_w = a.own_w;
+    r.own_s = a.own_s;
+    r.nb_w = a.nb_w;
+    r.nb_g = a.nb_g;
+    r.nb_s = a.nb_s;
+    r.nb_w1 = a.nb_w1;
+    r.Wtmp = a.Wtmp;
+    r.bslot = dm.bslot;
+    gks::AdjFlux fx{a.coef2, a.Wb1, a.Gb1, nullptr, nullptr, a.CB};
+    HIP_TRY(c, gks::launch_flux_vjp(dm, fx, c->par, dt, gks::FLUX_ADJ_STAGE2, f32, s));
+    r.W = a.Ws;
+    r.G = a.Gs;
+    r.slopes = a.slopes2;
+    r.flag = a.flag2;
+    HIP_TRY(c, gks::launch_recon_vjp(dm, r, c->par, f32, s));
+    HIP_TRY(c, gks::launch_recon_gather(dm, r, f32, a.Gbs, a.Wbs, nullptr, nullptr, s));
+    // stage 1 in reverse: -> W^n, grad W^n (W^n also enters both updates directly)
+    fx = gks::AdjFlux{a.coef1, a.Wb1, a.Gb1, a.Wbs, a.Gbs, a.CB};
+    HIP_TRY(c, gks::launch_flux_vjp(dm, fx, c->par, dt, gks::FLUX_ADJ_STAGE1, f32, s));
+    r.W = a.Wchk;
+    r.G = a.Gchk;
+    r.slopes = a.slopes1;
+    r.flag = a.flag1;
+    HIP_TRY(c, gks::launch_recon_vjp(dm, r, c->par, f32, s));
+    HIP_TRY(c, gks::launch_recon_gather(dm, r, f32, a.Gbn, a.Wbn, a.Wb1, a.Wbs, s));
+    // internal order -> caller order
+    HIP_TRY(c, gks::launch_permute_rows(Wbar_n, a.Wbn, c->d_cperm, nc, 5, 1, false, s));
+    HIP_TRY(c, gks::launch_permute_rows(gWbar_n, a.Gbn, c->d_cperm, nc, 15, 1, false, s));
     return GKS_OK;
 }
 

@@ -6,6 +6,7 @@
 #include "../../include/gks.h"
 #include "gks_flux_adj.h"
 #include "gks_params.h"
+#include "gks_recon_adj.h"
 
 #include <cmath>
 
@@ -36,6 +37,12 @@ inline Dual sqrt(Dual a) { const double s = std::sqrt(a.v); return Dual(s, a.d /
 inline Dual erfc(Dual a) { return Dual(std::erfc(a.v), -a.d * 1.1283791670955126 * std::exp(-a.v * a.v)); }
 // sign(0) = 0, as in the reverse
 inline Dual fabs(Dual a) { return a.v > 0.0 ? a : (a.v < 0.0 ? -a : Dual(0.0, 0.0)); }
+// x^e for a constant exponent e
+inline Dual pow(Dual a, Dual e)
+{
+    const double v = std::pow(a.v, e.v);
+    return Dual(v, a.v > 0.0 ? e.v * std::pow(a.v, e.v - 1.0) * a.d : 0.0);
+}
 
 template <typename R>
 struct ArrCoef {
@@ -154,5 +161,46 @@ extern "C" gks_status gks_flux_face_check(const gks_config *cfg, double dt, cons
     else if (visc) face_check<true, false>(p, dt, geo, coef, v, accbar, acc, jv, coefbar);
     else if (prfix) face_check<false, true>(p, dt, geo, coef, v, accbar, acc, jv, coefbar);
     else face_check<false, false>(p, dt, geo, coef, v, accbar, acc, jv, coefbar);
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_weno_check(const gks_config *cfg, const double geo[8], int32_t has_mask,
+                                     const double x[25], const double v[25], const double rbar[10],
+                                     double r[10], double jv[10], double xbar[25])
+{
+    if (!cfg || !geo || !x || !v || !rbar || !r || !jv || !xbar) return GKS_E_INVAL;
+    const gks::Params p = gks::params_from_config(cfg);
+    bool has[4];
+    for (int s = 0; s < 4; ++s) has[s] = (has_mask >> s) & 1;
+    // forward with duals
+    Dual Q0(x[0], v[0]), c[9], C[6], b[3], sn[4][3];
+    for (int k = 0; k < 9; ++k) c[k] = Dual(x[1 + k], v[1 + k]);
+    for (int d = 0; d < 3; ++d) b[d] = Dual(x[10 + d], v[10 + d]);
+    for (int s = 0; s < 4; ++s)
+        for (int d = 0; d < 3; ++d) sn[s][d] = Dual(x[13 + 3 * s + d], v[13 + 3 * s + d]);
+    for (int k = 0; k < 6; ++k) C[k] = Dual(geo[k]);
+    gks::WenoFwd<Dual> fd;
+    Dual Rq[10];
+    gks::weno_forward<Dual>(p, Q0, c, C, Dual(geo[6]), Dual(geo[7]), b, sn, has, fd, Rq);
+    for (int k = 0; k < 10; ++k) {
+        r[k] = Rq[k].v;
+        jv[k] = Rq[k].d;
+    }
+    // reverse in double
+    double cq[9], Cq[6], bq[3], snq[4][3], Rd[10];
+    for (int k = 0; k < 9; ++k) cq[k] = x[1 + k];
+    for (int d = 0; d < 3; ++d) bq[d] = x[10 + d];
+    for (int s = 0; s < 4; ++s)
+        for (int d = 0; d < 3; ++d) snq[s][d] = x[13 + 3 * s + d];
+    for (int k = 0; k < 6; ++k) Cq[k] = geo[k];
+    gks::WenoFwd<double> f;
+    gks::weno_forward<double>(p, x[0], cq, Cq, geo[6], geo[7], bq, snq, has, f, Rd);
+    double Q0b, cb[9], bb[3], snb[4][3];
+    gks::weno_reverse<double>(p, cq, Cq, geo[6], geo[7], bq, snq, has, f, rbar, Q0b, cb, bb, snb);
+    xbar[0] = Q0b;
+    for (int k = 0; k < 9; ++k) xbar[1 + k] = cb[k];
+    for (int d = 0; d < 3; ++d) xbar[10 + d] = bb[d];
+    for (int s = 0; s < 4; ++s)
+        for (int d = 0; d < 3; ++d) xbar[13 + 3 * s + d] = snb[s][d];
     return GKS_OK;
 }

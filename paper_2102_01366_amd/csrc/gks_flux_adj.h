@@ -795,12 +795,11 @@ GKS_HD void gks_point_vjp(const Params &p, R dt, const R wl[5], const R gl[3][5]
     primitive_rev(wr, K, gRb, wrb);
 }
 
-// Reverse of eval_local: adjoints of the rotated point state w and gradient g
-// to the cell's coefficients cb[5][10] (added).
+// Reverse of the rotation in eval_local: adjoints of the rotated point state
+// w and gradient g (face frame) to the unrotated W[5] and G[5][3] (set).
 template <typename R>
-GKS_HD void eval_local_rev(const R r[3], const R T[3][3], const R wb[5], const R gb[3][5], R cb[5][10])
+GKS_HD void point_adjoint_global(const R T[3][3], const R wb[5], const R gb[3][5], R Wb[5], R Gb[5][3])
 {
-    R Wb[5], Gb[5][3];
     Wb[0] = wb[0];
     Wb[4] = wb[4];
 #pragma unroll
@@ -821,19 +820,38 @@ GKS_HD void eval_local_rev(const R r[3], const R T[3][3], const R wb[5], const R
 #pragma unroll
             for (int d = 0; d < 3; ++d) Gb[q][d] += T[j][d] * dWb[q];
     }
+}
+
+// Reverse of the polynomial evaluation at offset r for one component:
+// adjoints of its value w and gradient G[3] to its ten coefficients (set).
+template <typename R>
+GKS_HD void coef_adjoint(const R r[3], R w, const R G[3], R cb[10])
+{
+    cb[0] = w;
+    cb[1] = w * r[0] + G[0];
+    cb[2] = w * r[1] + G[1];
+    cb[3] = w * r[2] + G[2];
+    cb[4] = R(0.5) * w * r[0] * r[0] + G[0] * r[0];
+    cb[5] = R(0.5) * w * r[1] * r[1] + G[1] * r[1];
+    cb[6] = R(0.5) * w * r[2] * r[2] + G[2] * r[2];
+    cb[7] = w * r[0] * r[1] + G[0] * r[1] + G[1] * r[0];
+    cb[8] = w * r[0] * r[2] + G[0] * r[2] + G[2] * r[0];
+    cb[9] = w * r[1] * r[2] + G[1] * r[2] + G[2] * r[1];
+}
+
+// Reverse of eval_local: adjoints of the rotated point state w and gradient g
+// to the cell's coefficients cb[5][10] (added).
+template <typename R>
+GKS_HD void eval_local_rev(const R r[3], const R T[3][3], const R wb[5], const R gb[3][5], R cb[5][10])
+{
+    R Wb[5], Gb[5][3];
+    point_adjoint_global(T, wb, gb, Wb, Gb);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        const R w = Wb[q], *G = Gb[q];
-        cb[q][0] += w;
-        cb[q][1] += w * r[0] + G[0];
-        cb[q][2] += w * r[1] + G[1];
-        cb[q][3] += w * r[2] + G[2];
-        cb[q][4] += R(0.5) * w * r[0] * r[0] + G[0] * r[0];
-        cb[q][5] += R(0.5) * w * r[1] * r[1] + G[1] * r[1];
-        cb[q][6] += R(0.5) * w * r[2] * r[2] + G[2] * r[2];
-        cb[q][7] += w * r[0] * r[1] + G[0] * r[1] + G[1] * r[0];
-        cb[q][8] += w * r[0] * r[2] + G[0] * r[2] + G[2] * r[0];
-        cb[q][9] += w * r[1] * r[2] + G[1] * r[2] + G[2] * r[1];
+        R t[10];
+        coef_adjoint(r, Wb[q], Gb[q], t);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) cb[q][k] += t[k];
     }
 }
 
@@ -847,22 +865,26 @@ GKS_HD void to_global_rev(const R T[3][3], const R goutb[5], R lb[5])
     for (int b = 0; b < 3; ++b) lb[1 + b] = T[b][0] * goutb[1] + T[b][1] * goutb[2] + T[b][2] * goutb[3];
 }
 
-// Vector-Jacobian product of gauss_point_terms with respect to the two
-// cells' coefficients: accb = adjoint of acc[4][5]; adds to cbl, cbr.
+// Vector-Jacobian product of gauss_point_terms down to the unrotated point
+// values: accb = adjoint of acc[4][5]; sets the adjoints of both sides' point
+// state Wb[2][5] and gradient Gb[2][5][3] (global frame) and the two offsets
+// r[2][3] at which the cells' polynomials are evaluated.
 template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR>
-GKS_HD void gauss_point_terms_vjp(const Params &p, R dt, const R nrm[3], R area, const R r[3], const R dv[3],
-                                  const CoefL &cl, const CoefR &cr, const R accb[4][5], R cbl[5][10],
-                                  R cbr[5][10])
+GKS_HD void gauss_point_vjp_point(const Params &p, R dt, const R nrm[3], R area, const R r[3], const R dv[3],
+                                  const CoefL &cl, const CoefR &cr, const R accb[4][5], R Wb[2][5],
+                                  R Gb[2][5][3], R off[2][3])
 {
     const R w = area * R(1.0 / 3.0);
     R T[3][3];
     rotation(nrm, T);
-    R rr[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) rr[d] = r[d] + dv[d];
+    for (int d = 0; d < 3; ++d) {
+        off[0][d] = r[d];
+        off[1][d] = r[d] + dv[d];
+    }
     R wl[5], gl[3][5], wr[5], gr[3][5];
-    eval_local(cl, r, T, wl, gl);
-    eval_local(cr, rr, T, wr, gr);
+    eval_local(cl, off[0], T, wl, gl);
+    eval_local(cr, off[1], T, wr, gr);
     const R idt = R(1) / dt;
     // acc0 = w (4 Fh - F1)/dt, acc1 = 4 w (F1 - 2 Fh)/dt^2, acc2 = w W0, acc3 = w W1
     R gF1[5], gFh[5], gW0[5], gW1[5];
@@ -886,8 +908,29 @@ GKS_HD void gauss_point_terms_vjp(const Params &p, R dt, const R nrm[3], R area,
         for (int d = 0; d < 3; ++d) glb[d][q] = grb[d][q] = R(0);
     }
     gks_point_vjp<R, VISC, PRFIX>(p, dt, wl, gl, wr, gr, Fob, Wob, wlb, glb, wrb, grb);
-    eval_local_rev(r, T, wlb, glb, cbl);
-    eval_local_rev(rr, T, wrb, grb, cbr);
+    point_adjoint_global(T, wlb, glb, Wb[0], Gb[0]);
+    point_adjoint_global(T, wrb, grb, Wb[1], Gb[1]);
+}
+
+// Vector-Jacobian product of gauss_point_terms with respect to the two
+// cells' coefficients: accb = adjoint of acc[4][5]; adds to cbl, cbr.
+template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR>
+GKS_HD void gauss_point_terms_vjp(const Params &p, R dt, const R nrm[3], R area, const R r[3], const R dv[3],
+                                  const CoefL &cl, const CoefR &cr, const R accb[4][5], R cbl[5][10],
+                                  R cbr[5][10])
+{
+    R Wb[2][5], Gb[2][5][3], off[2][3];
+    gauss_point_vjp_point<R, VISC, PRFIX>(p, dt, nrm, area, r, dv, cl, cr, accb, Wb, Gb, off);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        R t[10];
+        coef_adjoint(off[0], Wb[0][q], Gb[0][q], t);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) cbl[q][k] += t[k];
+        coef_adjoint(off[1], Wb[1][q], Gb[1][q], t);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) cbr[q][k] += t[k];
+    }
 }
 
 #undef GKS_HD

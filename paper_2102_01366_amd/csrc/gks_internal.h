@@ -63,6 +63,7 @@ struct DevMesh {
     const int *fcell;   // [2][nf] owner, neighbour (-1 on a wall)
     const void *fgeo;   // [NFGEO][nf]
     const double *fnrm; // [3][nf] unit normal in FP64 (the Gauss sums of the cell update)
+    const int *bslot;   // [4][nc] slot of neighbour a whose face is the cell's slot a (-1 on a wall)
 };
 
 // Device view of the state and per-stage scratch.
@@ -118,6 +119,49 @@ __host__ __device__ inline size_t m2_index(int row, int i)
     return ((size_t)(i / kM2Tile) * kM2Rows + row) * kM2Tile + (size_t)(i % kM2Tile);
 }
 inline size_t m2_padded_cells(size_t nc) { return (nc + kM2Tile - 1) / kM2Tile * kM2Tile; }
+
+// ---------------------------------------------------------------------------
+// Discrete adjoint of one step (gks_adjoint.hip).  Adjoint arrays are FP64 in
+// internal order.
+
+// Flux stage of the adjoint: the adjoint of the face terms of a stage is
+// formed from the cells' adjoints (the transpose of the cell update), and the
+// flux's vector-Jacobian product is written per face side as the adjoint of
+// that side's cell coefficients.
+struct AdjFlux {
+    const void *coef;           // [50][nc] the stage's reconstruction (bulk type)
+    const double *Wb1, *Gb1;    // adjoint of W^{n+1}, grad W^{n+1}
+    const double *Wbs, *Gbs;    // adjoint of W*, grad W* (stage 1 only)
+    double *CB;                 // [2][50][nf] out: coefficient adjoints of owner / neighbour
+};
+
+// Reconstruction stage of the adjoint: the stage's input state and step-1
+// slopes, the coefficient adjoints per face side, and the per-cell results.
+struct AdjRecon {
+    const double *W, *G;        // the stage's input state
+    const void *slopes;         // [15][nc] its step-1 slopes (bulk type)
+    const int *flag;            // [nc] positivity fallback taken
+    const double *CB;           // [2][50][nf]
+    double *own_w, *own_s;      // [5][nc], [15][nc] adjoints of the cell's own W and slopes
+    double *nb_w, *nb_g, *nb_s; // [4][5][nc], [4][15][nc], [4][15][nc] adjoints of
+                                // neighbour a's W, grad W and slopes
+    double *nb_w1;              // [4][5][nc] neighbour a's W through the step-1 slopes
+    double *Wtmp;               // [5][nc]
+    const int *bslot;           // [4][nc] slot of neighbour a that points back at the cell
+};
+
+enum FluxAdjMode { FLUX_ADJ_STAGE1 = 1, FLUX_ADJ_STAGE2 = 2 };
+
+hipError_t launch_flux_vjp(const DevMesh &m, const AdjFlux &a, const Params &p, double dt, int mode,
+                           bool fp32, hipStream_t st);
+// adjoints of the reconstruction's inputs: own / neighbour terms
+hipError_t launch_recon_vjp(const DevMesh &m, const AdjRecon &a, const Params &p, bool fp32,
+                            hipStream_t st);
+// gathers the neighbour terms (fixed slot order) and applies the reverse of the
+// step-1 slopes: Gout = adjoint of the stage's input gradient (complete); then
+// Wout = adjoint of its input W + X1 + X2 (X1, X2 may be null)
+hipError_t launch_recon_gather(const DevMesh &m, const AdjRecon &a, bool fp32, double *Gout,
+                               double *Wout, const double *X1, const double *X2, hipStream_t st);
 
 // block size for the one-thread-per-item kernels
 constexpr int kBlock = 256;

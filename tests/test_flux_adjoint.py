@@ -83,3 +83,27 @@ def test_bad_arguments():
     cfg = G.default_config()
     with pytest.raises(G.GksError):
         G.flux_point_check(cfg, 0.0, np.ones(40), np.ones(40), np.ones(20))
+
+
+@pytest.mark.parametrize("nonlinear", [True, False])
+def test_weno_reverse_is_the_transpose(nonlinear):
+    """The nonlinear combination of reconstruction step 2 (indicators,
+    weights, R) against its reverse, including cells with missing
+    neighbours."""
+    rng = np.random.default_rng(14)
+    cfg = G.default_config(nonlinear=nonlinear)
+    for t in range(120):
+        A = 0.1 * rng.standard_normal((3, 3))
+        Cm = A @ A.T
+        geo = np.array([Cm[0, 0], Cm[1, 1], Cm[2, 2], Cm[0, 1], Cm[0, 2], Cm[1, 2], 0.7, 0.49])
+        x = 0.1 * rng.standard_normal(25)
+        x[0] = 1.0
+        mask = 15 if t % 3 else int(rng.integers(1, 16))
+        v, rb = rng.standard_normal(25), rng.standard_normal(10)
+        r, jv, xb = G.weno_check(cfg, geo, mask, x, v, rb)
+        a, b = jv @ rb, v @ xb
+        assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
+        h = 1e-7
+        rp = G.weno_check(cfg, geo, mask, x + h * v, v, rb)[0]
+        rm = G.weno_check(cfg, geo, mask, x - h * v, v, rb)[0]
+        assert np.abs((rp - rm) / (2 * h) - jv).max() <= 1e-5 * np.abs(jv).max()

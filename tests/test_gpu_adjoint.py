@@ -1,0 +1,202 @@
+"""The discrete adjoint (gks_step_adjoint and the autograd rollout) on the GPU.
+
+The adjoint is the transpose of the Jacobian of the scheme as implemented,
+with the time steps held fixed.  It is checked against central finite
+differences of the forward map (GPU) and of the FP64 CPU oracle, along
+seeded random directions whose components are scaled by the RMS of each
+row of the state.
+
+Two parts of the scheme are not differentiable everywhere: the collision-time
+jump C |p_l - p_r| / (p_l + p_r) dt and the absolute values inside the WENO
+indicators.  The adjoint takes sign(x) at the base point (sign(0) = 0); a
+finite difference whose step straddles such a kink measures a secant
+instead.  The tight checks therefore switch the jump term off (c_tau = 0),
+and take a step of 1e-7 where the WENO weights are active, so that no kink
+lies within the step; with smooth weights (eps_weno = 1) and the jump term
+off, the step map is smooth and the checks use 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2102_01366_amd as G
+from paper_2102_01366_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+def _tgv(n=4, mach=0.3, jitter=0.1, seed=3, length=2 * math.pi):
+    m = I.kuhn_cube_mesh(n, length, jitter, seed, True)
+    W, gW = I.cell_averages(m, I.taylor_green_field(mach=mach, ell=length / (2 * math.pi)))
+    return m, W, gW
+
+
+def _dirs(W, gW, gen):
+    """A random direction, each row scaled by its RMS (gradients: + 1e-3)."""
+    sW = torch.from_numpy(np.sqrt((W ** 2).mean(axis=1, keepdims=True))).to(DEV)
+    sG = torch.from_numpy(np.sqrt((gW ** 2).mean(axis=1, keepdims=True)) + 1e-3).to(DEV)
+    vW = torch.randn(W.shape, generator=gen, dtype=torch.float64, device="cpu").to(DEV) * sW
+    vG = torch.randn(gW.shape, generator=gen, dtype=torch.float64, device="cpu").to(DEV) * sG
+    return vW, vG
+
+
+def _one_step_check(cfg_kw, eps, tol, ndir=3, seed=0):
+    m, W, gW = _tgv()
+    s = G.Solver(m, G.default_config(**cfg_kw))
+    Wt, Gt = torch.from_numpy(W).to(DEV), torch.from_numpy(gW).to(DEV)
+    s.init(Wt, Gt)
+    dt = s.compute_dt(0.5)
+
+    def F(Wx, Gx):
+        s.init(Wx, Gx)
+        s.step(dt)
+        return s.read_state(device=True)
+
+    gen = torch.Generator().manual_seed(seed)
+    for _ in range(ndir):
+        vW, vG = _dirs(W, gW, gen)
+        bW = torch.randn(W.shape, generator=gen, dtype=torch.float64).to(DEV)
+        bG = torch.randn(gW.shape, generator=gen, dtype=torch.float64).to(DEV)
+        Wp, Gp = F(Wt + eps * vW, Gt + eps * vG)
+        Wm, Gm = F(Wt - eps * vW, Gt - eps * vG)
+        lhs = (((Wp - Wm) * bW).sum() + ((Gp - Gm) * bG).sum()).item() / (2 * eps)
+        aW, aG = s.step_adjoint(dt, Wt, Gt, bW, bG)
+        rhs = ((aW * vW).sum() + (aG * vG).sum()).item()
+        assert abs(lhs - rhs) <= tol * abs(rhs), (cfg_kw, lhs, rhs)
+
+
+@pytest.mark.parametrize("cfg_kw", [
+    dict(viscous=True, mu=0.01, prandtl=0.72, c_tau=0.0, eps_weno=1.0),
+    dict(viscous=True, mu=0.01, prandtl=0.72, c_tau=0.0, nonlinear=False),
+    dict(c_tau=0.0, nonlinear=False),
+    dict(c_tau=0.0, eps_weno=1.0, prandtl=0.72),
+], ids=["ns_smooth_weights", "ns_linear", "euler_linear", "euler_prandtl_smooth_weights"])
+def test_step_adjoint_smooth(cfg_kw):
+    _one_step_check(cfg_kw, eps=1e-6, tol=1e-6)
+
+
+@pytest.mark.parametrize("cfg_kw", [
+    dict(viscous=True, mu=0.01, prandtl=0.72, c_tau=0.0),
+    dict(c_tau=0.0),
+], ids=["ns_weno", "euler_weno"])
+def test_step_adjoint_weno(cfg_kw):
+    _one_step_check(cfg_kw, eps=1e-7, tol=1e-5)
+
+
+def _ke(W, vol):
+    """J = sum_i |Omega_i| |rho U|^2 / (2 rho): kinetic energy."""
+    return (vol * 0.5 * (W[1] ** 2 + W[2] ** 2 + W[3] ** 2) / W[0]).sum()
+
+
+def _volumes(m):
+    v = m.xyz[m.tet]
+    return np.abs(np.linalg.det(v[:, 1:] - v[:, :1])) / 6.0
+
+
+def test_rollout_gradient_matches_finite_differences():
+    """dJ/d(W0, gW0) through 10 steps with autograd, against central
+    differences of the same 10-step map with the same time steps."""
+    from paper_2102_01366_amd.autograd import rollout, time_steps
+    m, W, gW = _tgv(n=4, mach=0.3)
+    s = G.Solver(m, G.default_config(viscous=True, mu=0.01, prandtl=0.72, c_tau=0.0, eps_weno=1.0))
+    vol = torch.from_numpy(_volumes(m)).to(DEV)
+    W0, G0 = torch.from_numpy(W).to(DEV), torch.from_numpy(gW).to(DEV)
+    dts = time_steps(s, W0, G0, 0.5, 10)
+    Wr, Gr = W0.clone().requires_grad_(True), G0.clone().requires_grad_(True)
+    WN, GN = rollout(s, Wr, Gr, dts)
+    J = _ke(WN, vol)
+    J.backward()
+    gen = torch.Generator().manual_seed(5)
+    for _ in range(3):
+        vW, vG = _dirs(W, gW, gen)
+        eps = 1e-6
+        with torch.no_grad():
+            Jp = _ke(rollout(s, W0 + eps * vW, G0 + eps * vG, dts)[0], vol).item()
+            Jm = _ke(rollout(s, W0 - eps * vW, G0 - eps * vG, dts)[0], vol).item()
+        fd = (Jp - Jm) / (2 * eps)
+        ad = ((Wr.grad * vW).sum() + (Gr.grad * vG).sum()).item()
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
+
+
+def test_adjoint_matches_oracle_finite_differences():
+    """The FP64 CPU reference gradient: central differences of the oracle's
+    3-step map against the GPU adjoint, on a 162-cell mesh."""
+    import oracle
+    m, W, gW = _tgv(n=3, mach=0.3, seed=4)
+    kw = dict(viscous=True, mu=0.01, prandtl=0.72, c_tau=0.0)
+    orc = oracle.Oracle(m, oracle.make_config(**kw))
+    s = G.Solver(m, G.default_config(**kw))
+    dts, Wo, gWo = [], W, gW
+    for _ in range(3):
+        dt = orc.compute_dt(Wo, 0.5)
+        Wo, gWo = orc.step(dt, Wo, gWo)
+        dts.append(dt)
+    vol = _volumes(m)
+
+    def J_oracle(Wx, Gx):
+        for dt in dts:
+            Wx, Gx = orc.step(dt, Wx, Gx)
+        return float((vol * 0.5 * (Wx[1] ** 2 + Wx[2] ** 2 + Wx[3] ** 2) / Wx[0]).sum())
+
+    from paper_2102_01366_amd.autograd import rollout
+    Wr = torch.from_numpy(W).to(DEV).requires_grad_(True)
+    Gr = torch.from_numpy(gW).to(DEV).requires_grad_(True)
+    WN, _ = rollout(s, Wr, Gr, dts)
+    _ke(WN, torch.from_numpy(vol).to(DEV)).backward()
+    rng = np.random.default_rng(9)
+    sW = np.sqrt((W ** 2).mean(axis=1, keepdims=True))
+    sG = np.sqrt((gW ** 2).mean(axis=1, keepdims=True)) + 1e-3
+    for _ in range(2):
+        vW, vG = rng.standard_normal(W.shape) * sW, rng.standard_normal(gW.shape) * sG
+        eps = 1e-7
+        fd = (J_oracle(W + eps * vW, gW + eps * vG) - J_oracle(W - eps * vW, gW - eps * vG)) / (2 * eps)
+        ad = float((Wr.grad.cpu().numpy() * vW).sum() + (Gr.grad.cpu().numpy() * vG).sum())
+        assert abs(fd - ad) <= 1e-5 * abs(ad), (fd, ad)
+
+
+def test_adjoint_is_bitwise_reproducible_and_leaves_state():
+    m, W, gW = _tgv()
+    s = G.Solver(m, G.default_config(viscous=True, mu=0.01, prandtl=0.72))
+    Wt, Gt = torch.from_numpy(W).to(DEV), torch.from_numpy(gW).to(DEV)
+    s.init(Wt, Gt)
+    dt = s.compute_dt(0.5)
+    gen = torch.Generator().manual_seed(2)
+    bW = torch.randn(W.shape, generator=gen, dtype=torch.float64).to(DEV)
+    bG = torch.randn(gW.shape, generator=gen, dtype=torch.float64).to(DEV)
+    a1 = s.step_adjoint(dt, Wt, Gt, bW, bG)
+    a2 = s.step_adjoint(dt, Wt, Gt, bW, bG)
+    assert torch.equal(a1[0], a2[0]) and torch.equal(a1[1], a2[1])
+    Ws, Gs = s.read_state(device=True)
+    assert torch.equal(Ws, Wt) and torch.equal(Gs, Gt)
+
+
+def test_fp32_bulk_adjoint_close_to_fp64():
+    m, W, gW = _tgv(n=5, mach=0.3, jitter=0.05, seed=6)
+    kw = dict(viscous=True, mu=0.01, prandtl=0.72)
+    out = []
+    for prec in (G.GKS_FP64, G.GKS_FP32_BULK):
+        s = G.Solver(m, G.default_config(precision=prec, **kw))
+        Wt, Gt = torch.from_numpy(W).to(DEV), torch.from_numpy(gW).to(DEV)
+        s.init(Wt, Gt)
+        dt = 0.02
+        gen = torch.Generator().manual_seed(3)
+        bW = torch.randn(W.shape, generator=gen, dtype=torch.float64).to(DEV)
+        bG = torch.randn(gW.shape, generator=gen, dtype=torch.float64).to(DEV)
+        out.append(s.step_adjoint(dt, Wt, Gt, bW, bG))
+    for a, b in zip(out[0], out[1]):
+        assert (a - b).abs().max().item() <= 1e-3 * a.abs().max().item()
+
+
+def test_adjoint_errors():
+    m, W, gW = _tgv(n=2)
+    s = G.Solver(m, G.default_config())
+    Wt, Gt = torch.from_numpy(W).to(DEV), torch.from_numpy(gW).to(DEV)
+    with pytest.raises(G.GksError) as e:
+        s.step_adjoint(-1.0, Wt, Gt, Wt, Gt)
+    assert e.value.status == G.GKS_E_INVAL
+    with pytest.raises(ValueError):
+        s.step_adjoint(0.01, Wt[:4], Gt, Wt, Gt)
