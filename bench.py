@@ -11,7 +11,9 @@ timed region starts.
 
 Prints one JSON line: cell-stage-updates/s, the roofline of the dominant
 kernel (per-kernel durations from HIP events on the library's stream inside
-the timed region) and the FP64 CPU oracle timed on a bounded sample.
+the timed region), the FP32-bulk form's throughput and error, the
+differentiation form (adjoint / forward time and its finite-difference
+check) and the FP64 CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -121,6 +123,66 @@ def cpu_baseline(mesh, W, gW, cfg_kw, steps):
                       f"{el:.1f} s on {threads} OpenMP threads"}
 
 
+def adjoint_leg(G, I, mesh, W, gW, cfg_kw, nsteps, ndir, precision):
+    """Differentiation form on the same mesh: J = kinetic energy after
+    `nsteps` CFL steps (time steps of an undifferentiated run, then fixed);
+    dJ/d(W0, grad W0) by the discrete adjoint through the autograd rollout.
+    Times one forward pass of plain steps and the adjoint pass, and checks
+    the gradient against central differences along `ndir` seeded directions
+    (rows scaled by their RMS, step 1e-6)."""
+    import numpy as np
+    import torch
+    from paper_2102_01366_amd.autograd import rollout, time_steps
+    dev = "cuda:0"
+    s = G.Solver(mesh, G.default_config(precision=precision, **cfg_kw), device=dev)
+    vol = torch.from_numpy(I_cell_volumes(mesh)).to(dev)
+    W0, G0 = torch.from_numpy(W).to(dev), torch.from_numpy(gW).to(dev)
+    dts = time_steps(s, W0, G0, 0.5, nsteps)
+
+    def ke(Wx):
+        return (vol * 0.5 * (Wx[1] ** 2 + Wx[2] ** 2 + Wx[3] ** 2) / Wx[0]).sum()
+
+    s.init(W0, G0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for dt in dts:
+        s.step(dt)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    Wr, Gr = W0.clone().requires_grad_(True), G0.clone().requires_grad_(True)
+    J = ke(rollout(s, Wr, Gr, dts)[0])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t1
+    out = {"steps": nsteps, "objective": "kinetic energy sum |Omega| |rho U|^2 / (2 rho) at the final time",
+           "forward_ms_per_step": t_fwd / nsteps * 1e3, "adjoint_ms_per_step": t_adj / nsteps * 1e3,
+           "adjoint_over_forward": t_adj / t_fwd,
+           "checkpoint_bytes": nsteps * 20 * 8 * mesh.n_cell}
+    if ndir:
+        gen = torch.Generator().manual_seed(4)
+        sW = torch.from_numpy(np.sqrt((W ** 2).mean(axis=1, keepdims=True))).to(dev)
+        sG = torch.from_numpy(np.sqrt((gW ** 2).mean(axis=1, keepdims=True)) + 1e-3).to(dev)
+        # the jump term |p_l - p_r| and the WENO indicators' |.| are kinks: a
+        # difference whose step straddles one measures a secant, so the check
+        # is reported at two steps
+        errs = {1e-6: [], 1e-7: []}
+        for _ in range(ndir):
+            vW = torch.randn(W.shape, generator=gen, dtype=torch.float64).to(dev) * sW
+            vG = torch.randn(gW.shape, generator=gen, dtype=torch.float64).to(dev) * sG
+            ad = ((Wr.grad * vW).sum() + (Gr.grad * vG).sum()).item()
+            for eps in errs:
+                with torch.no_grad():
+                    Jp = ke(rollout(s, W0 + eps * vW, G0 + eps * vG, dts)[0]).item()
+                    Jm = ke(rollout(s, W0 - eps * vW, G0 - eps * vG, dts)[0]).item()
+                errs[eps].append(abs((Jp - Jm) / (2 * eps) - ad) / abs(ad))
+        out.update({"fd_directions": ndir,
+                    "fd": [{"eps": eps, "max_rel_err": max(e), "median_rel_err": float(np.median(e))}
+                           for eps, e in errs.items()]})
+    return out, (Wr.grad.detach(), Gr.grad.detach())
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +192,9 @@ def main():
     ap.add_argument("--cpu-baseline-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk leg")
+    ap.add_argument("--adjoint-steps", type=int, default=50,
+                    help="steps of the differentiation leg (0 skips it)")
+    ap.add_argument("--adjoint-directions", type=int, default=16)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a 256 MiB fill (writes 256 MiB) and a 256 MiB elementwise add "
                          "(reads and writes 256 MiB): known byte counts that calibrate rocprofv3 "
@@ -249,6 +314,17 @@ def main():
         "kernels": kernels,
     }
     out["fp32_bulk"] = fp32
+    if args.adjoint_steps > 0:
+        adj, g64 = adjoint_leg(G, I, mesh, W, gW, cfg_kw, args.adjoint_steps, args.adjoint_directions,
+                               G.GKS_FP64)
+        adj32, g32 = adjoint_leg(G, I, mesh, W, gW, cfg_kw, args.adjoint_steps, 0, G.GKS_FP32_BULK)
+        adj["fp32_bulk"] = {k: adj32[k] for k in ("forward_ms_per_step", "adjoint_ms_per_step",
+                                                  "adjoint_over_forward")}
+        adj["fp32_bulk"]["gradient_rel_diff_vs_fp64"] = max(
+            float((a - b).abs().max() / a.abs().max()) for a, b in zip(g64, g32))
+        out["adjoint"] = adj
+    else:
+        out["adjoint"] = None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, W, gW, cfg_kw, args.cpu_baseline_steps)
     else:
