@@ -83,7 +83,7 @@ def _load():
         for name in ("or_geometry",):
             getattr(L, name).argtypes = [P, P, P, P, P]
         L.or_face_geometry.argtypes = [P, P, P, P]
-        L.or_slopes.argtypes = [P, P, P]
+        L.or_slopes.argtypes = [P, P, P, P]
         L.or_reconstruct.argtypes = [P, P, P, P, P, P]
         L.or_face_terms.argtypes = [P, P, P, D, P]
         L.or_stage.argtypes = [P, ctypes.c_int, D, P, P]
@@ -150,10 +150,11 @@ class Oracle:
         _load().or_face_geometry(self._h, _p(area), _p(nrm), _p(gp))
         return area, nrm, gp
 
-    def slopes(self, W):
+    def slopes(self, W, gW=None):
         W = _f64(W)
+        g = _f64(gW) if gW is not None else None
         b = np.empty((15, self.nc))
-        _load().or_slopes(self._h, _p(W), _p(b))
+        _load().or_slopes(self._h, _p(W), _p(g) if g is not None else None, _p(b))
         return b
 
     def reconstruct(self, W, gW, with_p2=False):

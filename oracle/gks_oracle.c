@@ -18,6 +18,11 @@
  *   - two-stage fourth-order time stepping and Gauss-theorem gradient update
  *     (Secs. 2.3 and 3).
  *
+ * Walls (face_cell[2f+1] = -1) are slip walls (Sec. 4.4): cells next to them
+ * use one-sided reconstructions (the own averaged gradient, and a linear
+ * least-squares fit in step 2, where fewer than three neighbours remain) and
+ * the flux sees the mirror image of the interior state as ghost.
+ *
  * Loops over cells and faces may run under OpenMP; every output element is
  * written by exactly one iteration, and all sums run in a fixed serial
  * order, so results do not depend on the thread count.
@@ -370,7 +375,10 @@ static void neighbour_vertices(const or_ctx *c, int64_t i, int a, double v[4][3]
 /* averages of the von Neumann neighbours                                   */
 /* ======================================================================== */
 
-static void slopes_cell(const or_ctx *c, int64_t i, const double *W, double b[NC][3])
+/* Boundary cells (Sec. 4.4, reconstruction for the boundary cells): with
+ * fewer than three neighbours the cell's own averaged gradient serves as the
+ * slopes; a singular least-squares matrix gives P^1 = P^0 (zero slopes). */
+static void slopes_cell(const or_ctx *c, int64_t i, const double *W, const double *gW, double b[NC][3])
 {
     int64_t n = c->nc;
     double h = cbrt(c->vol[i]);
@@ -400,7 +408,12 @@ static void slopes_cell(const or_ctx *c, int64_t i, const double *W, double b[NC
             for (int k = 0; k < nn; ++k) t += D[k][r] * (W[q * n + mm[k]] - W[q * n + i]);
             B[r * NC + q] = t;
         }
-    if (nn < 3 || gepp(3, NC, A, B) != 0) {
+    if (nn < 3) {
+        for (int q = 0; q < NC; ++q)
+            for (int d = 0; d < 3; ++d) b[q][d] = gW ? gW[(3 * q + d) * n + i] : 0.0;
+        return;
+    }
+    if (gepp(3, NC, A, B) != 0) {
         for (int q = 0; q < NC; ++q)
             for (int d = 0; d < 3; ++d) b[q][d] = 0.0;
         return;
@@ -409,13 +422,13 @@ static void slopes_cell(const or_ctx *c, int64_t i, const double *W, double b[NC
         for (int d = 0; d < 3; ++d) b[q][d] = B[d * NC + q] / h; /* back to physical units */
 }
 
-int or_slopes(or_ctx *c, const double *W, double *b)
+int or_slopes(or_ctx *c, const double *W, const double *gW, double *b)
 {
     int64_t n = c->nc;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double s[NC][3];
-        slopes_cell(c, i, W, s);
+        slopes_cell(c, i, W, gW, s);
         for (int q = 0; q < NC; ++q)
             for (int d = 0; d < 3; ++d) b[(3 * q + d) * n + i] = s[q][d];
     }
@@ -530,15 +543,42 @@ static void p2_cell(const or_ctx *c, int64_t i, const double *W, const double *g
         for (int r = 0; r < 9; ++r) K[(9 + s) * N + r] = E[s][r];
         for (int q = 0; q < NC; ++q) B[(9 + s) * NC + q] = e[s][q];
     }
-    int rc = gepp(N, NC, K, B);
+    int rc = ne >= 3 ? gepp(N, NC, K, B) : -1;
+    if (rc != 0) {
+        /* boundary cells with fewer than three neighbours, or a singular
+         * system (Sec. 4.4): the first-order polynomial fitted to the same
+         * data (neighbour averages and averaged derivatives) by least squares,
+         * normal equations on the three linear coefficients */
+        double A3[9], B3[3 * NC];
+        memset(A3, 0, sizeof(A3));
+        memset(B3, 0, sizeof(B3));
+        for (int r = 0; r < 3; ++r) {
+            for (int s2 = 0; s2 < 3; ++s2) {
+                double t = 0.0;
+                for (int k = 0; k < ne; ++k) t += E[k][r] * E[k][s2];
+                for (int k = 0; k < na; ++k) t += A[k][r] * A[k][s2];
+                A3[3 * r + s2] = t;
+            }
+            for (int q = 0; q < NC; ++q) {
+                double t = 0.0;
+                for (int k = 0; k < ne; ++k) t += E[k][r] * e[k][q];
+                for (int k = 0; k < na; ++k) t += A[k][r] * bb[k][q];
+                B3[r * NC + q] = t;
+            }
+        }
+        int rc3 = (ne + na) >= 3 ? gepp(3, NC, A3, B3) : -1;
+        for (int q = 0; q < NC; ++q) {
+            qpoly_t *p = &P2[q];
+            memset(p, 0, sizeof(*p));
+            p->c0 = W[q * n + i];
+            if (rc3 == 0)
+                for (int d = 0; d < 3; ++d) p->G[d] = B3[d * NC + q] / h;
+        }
+        return;
+    }
     for (int q = 0; q < NC; ++q) {
         qpoly_t *p = &P2[q];
         double Q0 = W[q * n + i];
-        if (rc != 0) {
-            memset(p, 0, sizeof(*p));
-            p->c0 = Q0;
-            continue;
-        }
         double ak[9];
         for (int k = 0; k < 9; ++k) ak[k] = B[k * NC + q];
         /* P^2(y) = Q0 + sum_k a_k (y^k - <y^k>_0); back to physical r = h y */
@@ -692,7 +732,7 @@ int or_reconstruct(or_ctx *c, const double *W, const double *gW, double *coef, i
                    double *p2coef)
 {
     int64_t n = c->nc;
-    or_slopes(c, W, c->slopes);
+    or_slopes(c, W, gW, c->slopes);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         qpoly_t R[NC], P2[NC];
@@ -1173,6 +1213,38 @@ static void quad_from_coef(const double *coef, int64_t n, int64_t i, int q, qpol
     for (int k = 0; k < 6; ++k) p->H[k] = o[(4 + k) * n];
 }
 
+/* Slip wall (Sec. 4.4, ghost states): the ghost is the mirror image of the
+ * interior solution in the wall plane.  With the reflection P = I - 2 n n^T
+ * (P = P^T = P^-1): density and energy W_g(x) = W(P x), momentum
+ * m_g(x) = P m(P x); at a point of the wall (P x = x) this gives the ghost
+ * value, and by the chain rule grad s_g = P grad s for the scalars and
+ * J_g = P J P for the momentum Jacobian J_ab = dm_a/dx_b. */
+static void mirror_ghost(const double n[3], const double W[5], const double gW[15], double Wg[5],
+                         double gWg[15])
+{
+    double P[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) P[a][b] = (a == b ? 1.0 : 0.0) - 2.0 * n[a] * n[b];
+    Wg[0] = W[0];
+    Wg[4] = W[4];
+    for (int a = 0; a < 3; ++a) {
+        Wg[1 + a] = 0.0;
+        for (int b = 0; b < 3; ++b) Wg[1 + a] += P[a][b] * W[1 + b];
+    }
+    for (int q = 0; q < 5; q += 4)
+        for (int a = 0; a < 3; ++a) {
+            gWg[3 * q + a] = 0.0;
+            for (int b = 0; b < 3; ++b) gWg[3 * q + a] += P[a][b] * gW[3 * q + b];
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double t = 0.0;
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) t += P[a][k] * gW[3 * (1 + k) + l] * P[l][b];
+            gWg[3 * (1 + a) + b] = t;
+        }
+}
+
 static int face_terms(or_ctx *c, const double *coef, double dt, double *out)
 {
     int64_t n = c->nc, nf = c->nf;
@@ -1200,7 +1272,7 @@ static int face_terms(or_ctx *c, const double *coef, double dt, double *out)
                     quad_grad(&p, rr, gWr + 3 * k);
                 }
             }
-            if (R < 0) { err |= 1; continue; } /* walls: not in this oracle yet */
+            if (R < 0) mirror_ghost(c->fnorm[f], Wl, gWl, Wr, gWr);
             double o[20];
             if (gks_point(&c->cfg, c->fnorm[f], Wl, gWl, Wr, gWr, dt, o)) { err |= 1; continue; }
             /* eq. linear-system: F = (4 F(dt/2) - F(dt)) / dt,

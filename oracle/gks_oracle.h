@@ -52,8 +52,10 @@ int or_geometry(const or_ctx *ctx, double *vol, double *cen, double *mom2, doubl
  * Gauss points [3 points][3][nf]. */
 int or_face_geometry(const or_ctx *ctx, double *area, double *normal, double *gp);
 
-/* Reconstruction step 1: slopes b[15][n] (component c, direction d at 3c+d). */
-int or_slopes(or_ctx *ctx, const double *W, double *b);
+/* Reconstruction step 1: slopes b[15][n] (component c, direction d at 3c+d).
+ * A cell with fewer than three neighbours (at walls) takes its own averaged
+ * gradient gW (zero if gW is NULL). */
+int or_slopes(or_ctx *ctx, const double *W, const double *gW, double *b);
 /* Reconstruction step 2: final polynomial R(x) = c0 + G.r + 1/2 r^T H r about
  * the centroid, coef[50][n] = per component (c0, Gx, Gy, Gz, Hxx, Hyy, Hzz,
  * Hxy, Hxz, Hyz); flag[n] = 1 where the positivity fallback fired.

@@ -68,8 +68,12 @@ __global__ __launch_bounds__(kFluxThreadsA) void flux_vjp_kernel(DevMesh m, AdjF
 #pragma unroll
         for (int d = 0; d < 3; ++d) off[sd][d] = R(0);
     if (live) {
-        const int L = m.fcell[f], Rc = m.fcell[nf + f];
-        const double iL = m.geoD[(size_t)G_INVVOL * n + L], iR = m.geoD[(size_t)G_INVVOL * n + Rc];
+        const int L = m.fcell[f], Rc0 = m.fcell[nf + f];
+        const bool wall = Rc0 < 0;
+        // a wall face has only its owner: the neighbour terms below vanish
+        const int Rc = wall ? L : Rc0;
+        const double iL = m.geoD[(size_t)G_INVVOL * n + L];
+        const double iR = wall ? 0.0 : m.geoD[(size_t)G_INVVOL * n + Rc];
         double nn[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) nn[d] = m.fnrm[(size_t)d * nf + f];
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(kFluxThreadsA) void flux_vjp_kernel(DevMesh m, AdjF
         const R area = fg[(size_t)F_AREA * nf + f];
         const R *coef = static_cast<const R *>(a.coef);
         gauss_point_vjp_point<R, VISC, PRFIX>(p, dt, nrm, area, r, dv, CoefView<R>{coef, n, L},
-                                              CoefView<R>{coef, n, Rc}, accb, Wb, Gb, off);
+                                              CoefView<R>{coef, n, Rc}, accb, Wb, Gb, off, wall);
     }
     // per side and component: the ten coefficient adjoints, summed over the
     // face's three Gauss points in order onto its first lane
@@ -296,7 +300,12 @@ __global__ __launch_bounds__(kBlock) void recon_gather1_kernel(DevMesh m, AdjRec
         }
 #pragma unroll
         for (int d = 0; d < 3; ++d) Gout[(size_t)(3 * q + d) * n + j] = G[d];
-        // slopes b_d = sum_s M1[4d+s] (Q_s - Q_0) over the neighbours present
+        // a cell with fewer than three neighbours took its own averaged gradient
+        // as slopes; otherwise b_d = sum_s M1[4d+s] (Q_s - Q_0) over the
+        // neighbours present (M1 is zero for this cell in the first case)
+        if (m.bmode[j])
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Gout[(size_t)(3 * q + d) * n + j] += S[d];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const double dqb = M[s] * S[0] + M[4 + s] * S[1] + M[8 + s] * S[2];

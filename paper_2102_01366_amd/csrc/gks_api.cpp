@@ -38,7 +38,7 @@ struct gks_ctx {
     int nc = 0, nf = 0;
     bool fp32 = false;              // FP32-bulk form
     std::vector<int> cperm, fperm;  // internal -> caller
-    std::vector<int> nbr, cface, fcell, bslot;
+    std::vector<int> nbr, cface, fcell, bslot, bmode;
     std::vector<double> M1, M2, geoR, geoD, fgeo, fnrm;
     // workspace
     bool bound = false;
@@ -217,7 +217,7 @@ struct Layout {
 enum Slot {
     S_NBR, S_CFACE, S_M1, S_M2, S_GEOR, S_GEOD, S_FCELL, S_FGEO, S_FNRM, S_W, S_GW, S_WN, S_LN, S_LTN,
     S_SLOPES, S_COEF, S_FLAG, S_FF, S_FT, S_FW0, S_FWS, S_RED, S_NONPHYS, S_CPERM, S_FPERM,
-    S_STAGING, S_ISTAGING, S_BSLOT, S_COUNT
+    S_STAGING, S_ISTAGING, S_BSLOT, S_BMODE, S_COUNT
 };
 
 // bs: bytes of a bulk element (8 in FP64, 4 in FP32-bulk)
@@ -231,7 +231,7 @@ Layout make_layout(size_t nc, size_t nf, size_t bs)
         5 * nc * 8, 15 * nc * 8, 5 * nc * 8, 5 * nc * 8, 5 * nc * 8, 15 * nc * bs, 50 * nc * bs,
         nc * sizeof(int), 5 * nf * bs, 5 * nf * bs, 5 * nf * bs, 5 * nf * bs,
         (8 + 5 * (size_t)gks::kRedBlocks) * 8, 64, nc * sizeof(int), nf * sizeof(int),
-        std::max(50 * nc, 20 * nf) * 8, nc * sizeof(int), 4 * nc * sizeof(int)};
+        std::max(50 * nc, 20 * nf) * 8, nc * sizeof(int), 4 * nc * sizeof(int), nc * sizeof(int)};
     Layout L;
     size_t o = 0;
     for (int k = 0; k < S_COUNT; ++k) {
@@ -375,11 +375,11 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
         const int64_t L = m->face_cell[2 * (size_t)f], R = m->face_cell[2 * (size_t)f + 1];
         const int tag = m->face_tag[f];
         if (L < 0 || L >= nc || R >= nc || R == L) return fail(c, GKS_E_MESH, "bad face_cell entry");
-        if (R < 0 || tag == GKS_FACE_SLIP)
-            return fail(c, GKS_E_MESH, "wall faces are not supported by this build");
-        if (tag != GKS_FACE_INTERIOR && tag != GKS_FACE_PERIODIC)
+        if (tag != GKS_FACE_INTERIOR && tag != GKS_FACE_PERIODIC && tag != GKS_FACE_SLIP)
             return fail(c, GKS_E_MESH, "unknown face tag");
-        for (int s = 0; s < 2; ++s) {
+        if ((R < 0) != (tag == GKS_FACE_SLIP))
+            return fail(c, GKS_E_MESH, "a wall face needs face_cell[2f+1] = -1 and the slip tag");
+        for (int s = 0; s < (R < 0 ? 1 : 2); ++s) {
             const int cell = (int)(s == 0 ? L : R);
             if (nslots[cell] >= 4) return fail(c, GKS_E_MESH, "a cell has more than four faces");
             slot_face[4 * (size_t)cell + nslots[cell]] = f;
@@ -414,7 +414,10 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
     for (int i = 0; i < nc; ++i) cinv[cperm[i]] = i;
     std::vector<int> fkey(nf);
     for (int f = 0; f < nf; ++f)
-        fkey[f] = std::min(cinv[m->face_cell[2 * (size_t)f]], cinv[m->face_cell[2 * (size_t)f + 1]]);
+    {
+        const int64_t L = m->face_cell[2 * (size_t)f], R = m->face_cell[2 * (size_t)f + 1];
+        fkey[f] = R < 0 ? cinv[L] : std::min(cinv[L], cinv[R]);
+    }
     std::vector<int> fperm(nf), finv(nf);
     std::iota(fperm.begin(), fperm.end(), 0);
     std::stable_sort(fperm.begin(), fperm.end(), [&](int a, int b) { return fkey[a] < fkey[b]; });
@@ -462,15 +465,15 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
                 fgeo[(size_t)(gks::F_RL + 3 * k + d) * nf + j] = gp[k][d] - cen[3 * L + d];
         for (int d = 0; d < 3; ++d)
             fgeo[(size_t)(gks::F_D + d) * nf + j] =
-                cen[3 * L + d] - (cen[3 * R + d] + m->face_shift[3 * (size_t)f + d]);
+                R < 0 ? 0.0 : cen[3 * L + d] - (cen[3 * R + d] + m->face_shift[3 * (size_t)f + d]);
         fcell[j] = cinv[L];
-        fcell[(size_t)nf + j] = cinv[R];
+        fcell[(size_t)nf + j] = R < 0 ? -1 : cinv[R];
     }
 
     // --- cells: geometry rows, neighbours, operators (internal order) ----
     std::vector<double> geoR((size_t)gks::NGEO_R * nc), geoD((size_t)gks::NGEO_D * nc);
     std::vector<double> M1(12 * (size_t)nc), M2(gks::kM2Rows * gks::m2_padded_cells(nc), 0.0);
-    std::vector<int> nbr(4 * (size_t)nc), cface(4 * (size_t)nc);
+    std::vector<int> nbr(4 * (size_t)nc), cface(4 * (size_t)nc), bmode(nc, 0);
     for (int ii = 0; ii < nc; ++ii) {
         const int i = cperm[ii];
         const double V = vol[i];
@@ -494,8 +497,13 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
             const double sgn = side == 0 ? 1.0 : -1.0;
             sumA += farea[f];
             for (int d = 0; d < 3; ++d) closure[d] += sgn * farea[f] * fnrm[3 * (size_t)f + d];
-            nbr[(size_t)a * nc + ii] = cinv[other];
+            nbr[(size_t)a * nc + ii] = other < 0 ? -1 : cinv[other];
             cface[(size_t)a * nc + ii] = 2 * finv[f] + side;
+            if (other < 0) {
+                for (int d = 0; d < 3; ++d) delta[a][d] = 0.0;
+                for (int k = 0; k < 6; ++k) Cm[a][k] = 0.0;
+                continue;
+            }
             // neighbour centroid next to this cell
             for (int d = 0; d < 3; ++d) {
                 const double off = side == 0 ? m->face_shift[3 * (size_t)f + d] : -m->face_shift[3 * (size_t)f + d];
@@ -525,86 +533,125 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
         for (int a = 0; a < 4; ++a)
             for (int d = 0; d < 3; ++d) g[(size_t)(gks::G_RV + 3 * a + d) * nc + ii] = rv[a][d];
 
-        // step 1: least squares of the 4 neighbour averages, D b' = dQ, D = delta / h
-        double D[12], Dp[12];
+        // the neighbours present (a cell at a wall has fewer than four)
+        int pres[4], np = 0;
         for (int a = 0; a < 4; ++a)
-            for (int d = 0; d < 3; ++d) D[3 * a + d] = delta[a][d] / h;
-        if (!pseudo_inverse(4, 3, D, Dp)) return fail(c, GKS_E_MESH, "singular step-1 stencil");
-        for (int d = 0; d < 3; ++d)
-            for (int a = 0; a < 4; ++a) M1[(size_t)(4 * d + a) * nc + ii] = Dp[4 * d + a] / h;
+            if (nbr[(size_t)a * nc + ii] >= 0) pres[np++] = a;
+
+        // step 1: least squares of the neighbour averages, D b' = dQ, D = delta / h;
+        // fewer than three neighbours: the cell's own averaged gradient (bmode);
+        // a singular stencil: zero slopes
+        if (np >= 3) {
+            double D[12], Dp[12];
+            for (int k = 0; k < np; ++k)
+                for (int d = 0; d < 3; ++d) D[3 * k + d] = delta[pres[k]][d] / h;
+            if (pseudo_inverse(np, 3, D, Dp))
+                for (int d = 0; d < 3; ++d)
+                    for (int k = 0; k < np; ++k) M1[(size_t)(4 * d + pres[k]) * nc + ii] = Dp[d * np + k] / h;
+        } else {
+            bmode[ii] = 1;
+        }
 
         // step 2: constrained least squares in y = (x - c) / h for the 9
-        // coefficients of the basis y^k - <y^k>_0
+        // coefficients of the basis y^k - <y^k>_0: equality rows E (neighbour
+        // averages), least-squares rows A (neighbour averaged derivatives)
         double E[4][9], A[12][9];
-        for (int a = 0; a < 4; ++a) {
+        for (int k = 0; k < np; ++k) {
+            const int a = pres[k];
             double dl[3];
             for (int d = 0; d < 3; ++d) dl[d] = delta[a][d] / h;
-            for (int d = 0; d < 3; ++d) E[a][d] = dl[d];
-            for (int k = 0; k < 6; ++k)
-                E[a][3 + k] = dl[QA[k]] * dl[QB[k]] + (Cm[a][k] - C[k]) / (h * h);
+            for (int d = 0; d < 3; ++d) E[k][d] = dl[d];
+            for (int t = 0; t < 6; ++t)
+                E[k][3 + t] = dl[QA[t]] * dl[QB[t]] + (Cm[a][t] - C[t]) / (h * h);
             for (int j = 0; j < 3; ++j) {
-                double *row = A[3 * a + j];
+                double *row = A[3 * k + j];
                 for (int d = 0; d < 3; ++d) row[d] = j == d ? 1.0 : 0.0;
-                for (int k = 0; k < 6; ++k) {
-                    const int p = QA[k], q = QB[k];
+                for (int t = 0; t < 6; ++t) {
+                    const int p = QA[t], q = QB[t];
                     double v = 0.0;
                     if (j == p) v += dl[q];
                     if (j == q) v += dl[p];
-                    row[3 + k] = v;
+                    row[3 + t] = v;
                 }
             }
         }
-        // null-space method: E^T = Q [R; 0]; a = Q1 R^{-T} e + Q2 z, z = (A Q2)^+ (b - A Q1 R^{-T} e)
-        double Et[9 * 4], Q[81];
-        for (int r = 0; r < 9; ++r)
-            for (int a = 0; a < 4; ++a) Et[r * 4 + a] = E[a][r];
-        householder_qr(9, 4, Et, Q);
-        double Y[9 * 4];  // Q1 R^{-T}
-        {
-            double Rinv_t[16];  // R^{-T} I
-            for (int r = 0; r < 4; ++r)
-                for (int s = 0; s < 4; ++s) Rinv_t[r * 4 + s] = r == s ? 1.0 : 0.0;
-            if (!lower_solve_transposed(4, Et, 4, Rinv_t, 4))
-                return fail(c, GKS_E_MESH, "singular step-2 constraints");
-            for (int r = 0; r < 9; ++r)
-                for (int s = 0; s < 4; ++s) {
-                    double t = 0.0;
-                    for (int k = 0; k < 4; ++k) t += Q[r * 9 + k] * Rinv_t[k * 4 + s];
-                    Y[r * 4 + s] = t;
-                }
-        }
-        double AQ2[12 * 5], AQ2p[5 * 12];
-        for (int r = 0; r < 12; ++r)
-            for (int s = 0; s < 5; ++s) {
-                double t = 0.0;
-                for (int k = 0; k < 9; ++k) t += A[r][k] * Q[k * 9 + 4 + s];
-                AQ2[r * 5 + s] = t;
-            }
-        if (!pseudo_inverse(12, 5, AQ2, AQ2p)) return fail(c, GKS_E_MESH, "singular step-2 stencil");
-        double Mb[9 * 12], Me[9 * 4];
-        for (int r = 0; r < 9; ++r)
-            for (int s = 0; s < 12; ++s) {
-                double t = 0.0;
-                for (int k = 0; k < 5; ++k) t += Q[r * 9 + 4 + k] * AQ2p[k * 12 + s];
-                Mb[r * 12 + s] = t;
-            }
-        for (int r = 0; r < 9; ++r)
-            for (int s = 0; s < 4; ++s) {
-                double t = 0.0;
-                for (int k = 0; k < 12; ++k) {
-                    double ay = 0.0;
-                    for (int l = 0; l < 9; ++l) ay += A[k][l] * Y[l * 4 + s];
-                    t += Mb[r * 12 + k] * ay;
-                }
-                Me[r * 4 + s] = Y[r * 4 + s] - t;
-            }
         // physical outputs: g = a_lin / h; H_pp = 2 a / h^2; H_pq = a / h^2; inputs e, h * dQ/dx
         const double osc[9] = {1 / h, 1 / h, 1 / h, 2 / (h * h), 2 / (h * h), 2 / (h * h),
                                1 / (h * h), 1 / (h * h), 1 / (h * h)};
-        for (int r = 0; r < 9; ++r) {
-            for (int s = 0; s < 4; ++s) M2[gks::m2_index(16 * r + s, ii)] = osc[r] * Me[r * 4 + s];
-            for (int s = 0; s < 12; ++s)
-                M2[gks::m2_index(16 * r + 4 + s, ii)] = osc[r] * h * Mb[r * 12 + s];
+        bool fitted = false;
+        if (np >= 3) {
+            // null-space method: E^T = Q [R; 0]; a = Q1 R^{-T} e + Q2 z,
+            // z = (A Q2)^+ (b - A Q1 R^{-T} e)
+            const int nz = 9 - np, na = 3 * np;
+            double Et[9 * 4], Q[81];
+            for (int r = 0; r < 9; ++r)
+                for (int k = 0; k < np; ++k) Et[r * np + k] = E[k][r];
+            householder_qr(9, np, Et, Q);
+            double Rinv_t[16];
+            for (int r = 0; r < np; ++r)
+                for (int t = 0; t < np; ++t) Rinv_t[r * np + t] = r == t ? 1.0 : 0.0;
+            double AQ2[12 * 6], AQ2p[6 * 12];
+            if (lower_solve_transposed(np, Et, np, Rinv_t, np)) {
+                double Y[9 * 4];  // Q1 R^{-T}
+                for (int r = 0; r < 9; ++r)
+                    for (int t = 0; t < np; ++t) {
+                        double v = 0.0;
+                        for (int k = 0; k < np; ++k) v += Q[r * 9 + k] * Rinv_t[k * np + t];
+                        Y[r * np + t] = v;
+                    }
+                for (int r = 0; r < na; ++r)
+                    for (int t = 0; t < nz; ++t) {
+                        double v = 0.0;
+                        for (int k = 0; k < 9; ++k) v += A[r][k] * Q[k * 9 + np + t];
+                        AQ2[r * nz + t] = v;
+                    }
+                if (pseudo_inverse(na, nz, AQ2, AQ2p)) {
+                    double Mb[9 * 12], Me[9 * 4];
+                    for (int r = 0; r < 9; ++r)
+                        for (int t = 0; t < na; ++t) {
+                            double v = 0.0;
+                            for (int k = 0; k < nz; ++k) v += Q[r * 9 + np + k] * AQ2p[k * na + t];
+                            Mb[r * na + t] = v;
+                        }
+                    for (int r = 0; r < 9; ++r)
+                        for (int t = 0; t < np; ++t) {
+                            double v = 0.0;
+                            for (int k = 0; k < na; ++k) {
+                                double ay = 0.0;
+                                for (int l = 0; l < 9; ++l) ay += A[k][l] * Y[l * np + t];
+                                v += Mb[r * na + k] * ay;
+                            }
+                            Me[r * np + t] = Y[r * np + t] - v;
+                        }
+                    for (int r = 0; r < 9; ++r)
+                        for (int k = 0; k < np; ++k) {
+                            const int a = pres[k];
+                            M2[gks::m2_index(16 * r + a, ii)] = osc[r] * Me[r * np + k];
+                            for (int j = 0; j < 3; ++j)
+                                M2[gks::m2_index(16 * r + 4 + 3 * a + j, ii)] = osc[r] * h * Mb[r * na + 3 * k + j];
+                        }
+                    fitted = true;
+                }
+            }
+        }
+        if (!fitted && np > 0) {
+            // fewer than three neighbours or a singular system (boundary cells,
+            // Sec. 4.4): the linear polynomial fitted to the same data in the
+            // least-squares sense; H = 0
+            const int nr = 4 * np;
+            double Lr[16 * 3], Lp[3 * 16];
+            for (int k = 0; k < np; ++k)
+                for (int d = 0; d < 3; ++d) Lr[3 * k + d] = E[k][d];
+            for (int r = 0; r < 3 * np; ++r)
+                for (int d = 0; d < 3; ++d) Lr[3 * (np + r) + d] = A[r][d];
+            if (pseudo_inverse(nr, 3, Lr, Lp))
+                for (int d = 0; d < 3; ++d)
+                    for (int k = 0; k < np; ++k) {
+                        const int a = pres[k];
+                        M2[gks::m2_index(16 * d + a, ii)] = osc[d] * Lp[d * nr + k];
+                        for (int j = 0; j < 3; ++j)
+                            M2[gks::m2_index(16 * d + 4 + 3 * a + j, ii)] = osc[d] * h * Lp[d * nr + np + 3 * k + j];
+                    }
         }
     }
 
@@ -627,6 +674,7 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
             if (bslot[(size_t)a * nc + ii] < 0) return fail(c, GKS_E_MESH, "inconsistent face-cell adjacency");
         }
     c->bslot.swap(bslot);
+    c->bmode.swap(bmode);
     c->nbr.swap(nbr);
     c->cface.swap(cface);
     c->fcell.swap(fcell);
@@ -672,6 +720,7 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     dm.fgeo = P(S_FGEO);
     dm.fnrm = (const double *)P(S_FNRM);
     dm.bslot = (const int *)P(S_BSLOT);
+    dm.bmode = (const int *)P(S_BMODE);
     ds.W = (double *)P(S_W);
     ds.gW = (double *)P(S_GW);
     ds.Wn = (double *)P(S_WN);
@@ -714,6 +763,7 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     HIP_TRY(c, up_bulk(dm.fgeo, c->fgeo));
     HIP_TRY(c, up((void *)dm.fnrm, c->fnrm.data(), 3 * nf * 8));
     HIP_TRY(c, up((void *)dm.bslot, c->bslot.data(), 4 * nc * sizeof(int)));
+    HIP_TRY(c, up((void *)dm.bmode, c->bmode.data(), nc * sizeof(int)));
     HIP_TRY(c, up(c->d_cperm, c->cperm.data(), nc * sizeof(int)));
     HIP_TRY(c, up(c->d_fperm, c->fperm.data(), nf * sizeof(int)));
     HIP_TRY(c, gks::launch_fill_int(ds.nonphys, 0, st));
@@ -723,6 +773,7 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     std::vector<int>().swap(c->cface);
     std::vector<int>().swap(c->fcell);
     std::vector<int>().swap(c->bslot);
+    std::vector<int>().swap(c->bmode);
     std::vector<double>().swap(c->M1);
     std::vector<double>().swap(c->M2);
     std::vector<double>().swap(c->geoR);

@@ -482,13 +482,31 @@ GKS_HD void to_global(const R T[3][3], const R l[5], R gout[5])
     for (int a = 0; a < 3; ++a) gout[1 + a] = T[0][a] * l[1] + T[1][a] * l[2] + T[2][a] * l[3];
 }
 
+// Ghost state of a slip wall in the face frame (Sec. 4.4): the normal
+// momentum is reversed; the normal derivatives are reversed except that of
+// the normal momentum; of the tangential derivatives only the normal
+// momentum's are reversed.  The map is its own inverse and its own transpose.
+template <typename R>
+GKS_HD void slip_ghost(const R w[5], const R g[3][5], R wg[5], R gg[3][5])
+{
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        wg[q] = q == 1 ? -w[q] : w[q];
+        gg[0][q] = q == 1 ? g[0][q] : -g[0][q];
+        gg[1][q] = q == 1 ? -g[1][q] : g[1][q];
+        gg[2][q] = q == 1 ? -g[2][q] : g[2][q];
+    }
+}
+
 // Terms of one Gauss point k of a face, weighted by w_k |Gamma| = |Gamma|/3:
 // acc[0] = F_k, acc[1] = dF_k/dt (eq. linear-system), acc[2] = W_k(0),
 // acc[3] = W_k(dt), all in the global frame.  r: the Gauss point relative to
 // the owner centroid; dv: owner centroid minus the neighbour's (translated).
+// On a wall face (no neighbour; cr is not evaluated) the right state is the
+// slip-wall ghost of the left one.
 template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR>
 GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, const R r[3], const R dv[3],
-                              const CoefL &cl, const CoefR &cr, R acc[4][5])
+                              const CoefL &cl, const CoefR &cr, R acc[4][5], bool wall = false)
 {
     const R w = area * R(1.0 / 3.0);
     R T[3][3];
@@ -498,7 +516,10 @@ GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, con
     for (int d = 0; d < 3; ++d) rr[d] = r[d] + dv[d];
     R wl[5], gl[3][5], wr[5], gr[3][5];
     eval_local(cl, r, T, wl, gl);
-    eval_local(cr, rr, T, wr, gr);
+    if (wall)
+        slip_ghost(wl, gl, wr, gr);
+    else
+        eval_local(cr, rr, T, wr, gr);
     R Fo[2][5], Wo[2][5];
     gks_point<R, VISC, PRFIX>(p, dt, wl, gl, wr, gr, Fo, Wo);
     R F1[5], Fh[5], W0[5], W1[5];
@@ -519,7 +540,7 @@ GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, con
 // All terms of one face: the sum over its three Gauss points, in order.
 template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR>
 GKS_HD void face_terms(const Params &p, R dt, const R nrm[3], R area, const R rl[3][3], const R dv[3],
-                       const CoefL &cl, const CoefR &cr, R acc[4][5])
+                       const CoefL &cl, const CoefR &cr, R acc[4][5], bool wall = false)
 {
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -527,7 +548,7 @@ GKS_HD void face_terms(const Params &p, R dt, const R nrm[3], R area, const R rl
         for (int q = 0; q < 5; ++q) acc[a][q] = R(0);
     for (int k = 0; k < 3; ++k) {
         R t[4][5];
-        gauss_point_terms<R, VISC, PRFIX>(p, dt, nrm, area, rl[k], dv, cl, cr, t);
+        gauss_point_terms<R, VISC, PRFIX>(p, dt, nrm, area, rl[k], dv, cl, cr, t, wall);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll

@@ -872,7 +872,7 @@ GKS_HD void to_global_rev(const R T[3][3], const R goutb[5], R lb[5])
 template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR>
 GKS_HD void gauss_point_vjp_point(const Params &p, R dt, const R nrm[3], R area, const R r[3], const R dv[3],
                                   const CoefL &cl, const CoefR &cr, const R accb[4][5], R Wb[2][5],
-                                  R Gb[2][5][3], R off[2][3])
+                                  R Gb[2][5][3], R off[2][3], bool wall = false)
 {
     const R w = area * R(1.0 / 3.0);
     R T[3][3];
@@ -884,7 +884,10 @@ GKS_HD void gauss_point_vjp_point(const Params &p, R dt, const R nrm[3], R area,
     }
     R wl[5], gl[3][5], wr[5], gr[3][5];
     eval_local(cl, off[0], T, wl, gl);
-    eval_local(cr, off[1], T, wr, gr);
+    if (wall)
+        slip_ghost(wl, gl, wr, gr);
+    else
+        eval_local(cr, off[1], T, wr, gr);
     const R idt = R(1) / dt;
     // acc0 = w (4 Fh - F1)/dt, acc1 = 4 w (F1 - 2 Fh)/dt^2, acc2 = w W0, acc3 = w W1
     R gF1[5], gFh[5], gW0[5], gW1[5];
@@ -908,6 +911,21 @@ GKS_HD void gauss_point_vjp_point(const Params &p, R dt, const R nrm[3], R area,
         for (int d = 0; d < 3; ++d) glb[d][q] = grb[d][q] = R(0);
     }
     gks_point_vjp<R, VISC, PRFIX>(p, dt, wl, gl, wr, gr, Fob, Wob, wlb, glb, wrb, grb);
+    if (wall) {
+        // the ghost is a linear function of the left state; its transpose is itself
+        R wg[5], gg[3][5];
+        slip_ghost(wrb, grb, wg, gg);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            wlb[q] += wg[q];
+            wrb[q] = R(0);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                glb[d][q] += gg[d][q];
+                grb[d][q] = R(0);
+            }
+        }
+    }
     point_adjoint_global(T, wlb, glb, Wb[0], Gb[0]);
     point_adjoint_global(T, wrb, grb, Wb[1], Gb[1]);
 }

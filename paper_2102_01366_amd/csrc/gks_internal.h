@@ -64,6 +64,7 @@ struct DevMesh {
     const void *fgeo;   // [NFGEO][nf]
     const double *fnrm; // [3][nf] unit normal in FP64 (the Gauss sums of the cell update)
     const int *bslot;   // [4][nc] slot of neighbour a whose face is the cell's slot a (-1 on a wall)
+    const int *bmode;   // [nc] 1: fewer than three neighbours, step-1 slopes = own averaged gradient
 };
 
 // Device view of the state and per-stage scratch.

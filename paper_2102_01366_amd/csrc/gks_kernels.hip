@@ -53,6 +53,12 @@ __global__ __launch_bounds__(kBlock) void slopes_kernel(DevMesh m, DevState s)
     int nbc[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) nbc[a] = nb[a] >= 0 ? nb[a] : i;
+    if (m.bmode[i]) {
+        // fewer than three neighbours (at walls): the own averaged gradient
+#pragma unroll
+        for (int k = 0; k < 15; ++k) slopes[(size_t)k * n + i] = R(s.gW[(size_t)k * n + i]);
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         const double Q0 = s.W[(size_t)q * n + i];
@@ -389,8 +395,9 @@ __global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(
             r[d] = fg[(size_t)(F_RL + 3 * k + d) * nf + f];
         }
         const R area = fg[(size_t)F_AREA * nf + f];
+        const bool wall = Rc < 0;
         gauss_point_terms<R, VISC, PRFIX>(p, dt, nrm, area, r, dv, DevCoef<R>{coef, n, L},
-                                          DevCoef<R>{coef, n, Rc}, acc);
+                                          DevCoef<R>{coef, n, wall ? L : Rc}, acc, wall);
     } else {
 #pragma unroll
         for (int a = 0; a < 4; ++a)

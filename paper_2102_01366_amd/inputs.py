@@ -300,3 +300,106 @@ def conservative_to_primitive(W: np.ndarray, gamma: float):
     u = W[1:4] / rho
     p = (gamma - 1.0) * (W[4] - 0.5 * rho * np.sum(u * u, axis=0))
     return rho, u, p
+
+
+def box_vortex_field(gamma: float = 1.4, amp: float = 0.2, p0: float = 1.0, bump: float = 0.3,
+                     length: float = 1.0):
+    """A smooth state in the box [0, L]^3 with slip walls: the swirl
+    U = amp (sin(pi x/L) cos(pi y/L), -cos(pi x/L) sin(pi y/L), 0), which has no
+    normal velocity on the walls, rho = 1 + bump/2 exp(-|x - c|^2 / (0.05 L^2)),
+    p = p0 (1 + bump exp(-|x - c|^2 / (0.05 L^2))), c the centre."""
+    k = np.pi / length
+    s2 = 0.05 * length * length
+
+    def f(X):
+        x, y, z = X[..., 0], X[..., 1], X[..., 2]
+        dx, dy, dz = x - 0.5 * length, y - 0.5 * length, z - 0.5 * length
+        G = np.exp(-(dx * dx + dy * dy + dz * dz) / s2)
+        dG = [-2.0 * dx / s2 * G, -2.0 * dy / s2 * G, -2.0 * dz / s2 * G]
+        rho = 1.0 + 0.5 * bump * G
+        drho = [0.5 * bump * g for g in dG]
+        p = p0 * (1.0 + bump * G)
+        dp = [p0 * bump * g for g in dG]
+        u = amp * np.sin(k * x) * np.cos(k * y)
+        v = -amp * np.cos(k * x) * np.sin(k * y)
+        w = np.zeros_like(x)
+        du = [amp * k * np.cos(k * x) * np.cos(k * y), -amp * k * np.sin(k * x) * np.sin(k * y), 0 * x]
+        dv = [amp * k * np.sin(k * x) * np.sin(k * y), -amp * k * np.cos(k * x) * np.cos(k * y), 0 * x]
+        dw = [0 * x, 0 * x, 0 * x]
+        q = 0.5 * (u * u + v * v + w * w)
+        dq = [u * du[d] + v * dv[d] + w * dw[d] for d in range(3)]
+        E = p / (gamma - 1.0) + rho * q
+        Q = np.stack([rho, rho * u, rho * v, rho * w, E])
+        dQ = np.stack([
+            np.stack(drho),
+            np.stack([drho[d] * u + rho * du[d] for d in range(3)]),
+            np.stack([drho[d] * v + rho * dv[d] for d in range(3)]),
+            np.stack([drho[d] * w + rho * dw[d] for d in range(3)]),
+            np.stack([dp[d] / (gamma - 1.0) + drho[d] * q + rho * dq[d] for d in range(3)]),
+        ])
+        return Q, dQ
+
+    return f
+
+
+def _refined_centroids(levels: int) -> np.ndarray:
+    """Barycentric coordinates of the centroids of the 8^levels tetrahedra of
+    `levels` regular refinements of a tetrahedron (four corner tetrahedra and
+    the central octahedron cut along one diagonal into four); the children of
+    a regular refinement have equal volumes."""
+    tets = [np.eye(4)]
+    for _ in range(levels):
+        out = []
+        for t in tets:
+            v = t
+            m = {(a, b): 0.5 * (v[a] + v[b]) for a in range(4) for b in range(a + 1, 4)}
+            e = lambda a, b: m[(min(a, b), max(a, b))]
+            out += [np.stack([v[0], e(0, 1), e(0, 2), e(0, 3)]),
+                    np.stack([e(0, 1), v[1], e(1, 2), e(1, 3)]),
+                    np.stack([e(0, 2), e(1, 2), v[2], e(2, 3)]),
+                    np.stack([e(0, 3), e(1, 3), e(2, 3), v[3]])]
+            # octahedron (midpoints of the six edges) cut along e(0,2)-e(1,3)
+            a, b = e(0, 2), e(1, 3)
+            ring = [e(0, 1), e(1, 2), e(2, 3), e(0, 3)]
+            for k in range(4):
+                out.append(np.stack([a, b, ring[k], ring[(k + 1) % 4]]))
+        tets = out
+    return np.stack([t.mean(axis=0) for t in tets])  # [8^levels, 4]
+
+
+def blast_cell_averages(mesh: TetMesh, gamma: float = 1.4, radius: float = 0.1, center=(0.5, 0.5, 0.5),
+                        inside=(1.0, 10.0), outside=(1.0, 0.1), levels: int = 3, chunk: int = 16384):
+    """The spherical blast: gas at rest, (rho, p) = inside for |x - c| < radius
+    and outside elsewhere.  Cell averages from the volume fraction of each
+    cell inside the sphere, counted on its 8^levels equal sub-tetrahedra by
+    their centroids; averaged gradients by the divergence theorem, the sum
+    over the cell's faces of |Gamma| n times the three-point face rule applied
+    to point values of the step.  Returns W[5, n], gW[15, n]."""
+    c = np.asarray(center, dtype=np.float64)
+    Win = np.array([inside[0], 0.0, 0.0, 0.0, inside[1] / (gamma - 1.0)])
+    Wout = np.array([outside[0], 0.0, 0.0, 0.0, outside[1] / (gamma - 1.0)])
+    bary = _refined_centroids(levels)
+    nc = mesh.n_cell
+    frac = np.empty(nc)
+    v_all = mesh.xyz[mesh.tet]
+    for s in range(0, nc, chunk):
+        v = v_all[s:s + chunk]
+        X = np.matmul(bary[None], v - c)  # sub-tetrahedron centroids relative to c
+        frac[s:s + chunk] = (np.einsum("ckd,ckd->ck", X, X) < radius * radius).mean(axis=1)
+    W = np.outer(Win, frac) + np.outer(Wout, 1.0 - frac)
+    # divergence theorem with the face rule at (1/6,1/6), (2/3,1/6), (1/6,2/3)
+    gp = np.array([[2 / 3, 1 / 6, 1 / 6], [1 / 6, 2 / 3, 1 / 6], [1 / 6, 1 / 6, 2 / 3]])
+    vol = np.abs(np.linalg.det(v_all[:, 1:] - v_all[:, :1])) / 6.0
+    cen = v_all.mean(axis=1)
+    acc = np.zeros((nc, 3, 5))
+    for a in range(4):
+        fv = v_all[:, [b for b in range(4) if b != a]]  # [nc, 3, 3]
+        an = 0.5 * np.cross(fv[:, 1] - fv[:, 0], fv[:, 2] - fv[:, 0])  # area * normal
+        out = np.sign(np.einsum("cd,cd->c", an, fv[:, 0] - cen))
+        an *= out[:, None]
+        P = np.matmul(gp[None], fv)  # [nc, 3 points, 3]
+        ins = (np.sum((P - c) ** 2, axis=2) < radius * radius).astype(np.float64)
+        Wp = ins[:, :, None] * Win + (1.0 - ins[:, :, None]) * Wout  # [nc, 3, 5]
+        acc += an[:, :, None] * Wp.mean(axis=1)[:, None, :]
+    gW = (acc / vol[:, None, None]).transpose(2, 1, 0).reshape(15, nc)
+    return W, gW

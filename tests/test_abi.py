@@ -133,9 +133,17 @@ def test_mesh_rejections(lib):
     tag[0] = 9
     assert _upload(lib, m, face_tag=tag)[0] == G.GKS_E_MESH
     assert st in (0, G.GKS_E_MESH)
-    # walls are not supported by this build
+    # slip walls are accepted; a wall face must carry the slip tag and no neighbour
     mw = I.kuhn_cube_mesh(2, 1.0, 0.1, 5, False)
-    assert _upload(lib, mw)[0] == G.GKS_E_MESH
+    assert _upload(lib, mw)[0] == 0
+    wall = int(np.nonzero(mw.face_tag == I.FACE_SLIP)[0][0])
+    tag = mw.face_tag.copy()
+    tag[wall] = I.FACE_INTERIOR
+    assert _upload(lib, mw, face_tag=tag)[0] == G.GKS_E_MESH
+    inner = int(np.nonzero(mw.face_tag == I.FACE_INTERIOR)[0][0])
+    tag = mw.face_tag.copy()
+    tag[inner] = I.FACE_SLIP
+    assert _upload(lib, mw, face_tag=tag)[0] == G.GKS_E_MESH
 
 
 def test_empty_mesh_rejected(lib):
