@@ -13,7 +13,8 @@ Prints one JSON line: cell-stage-updates/s, the roofline of the dominant
 kernel (per-kernel durations from HIP events on the library's stream inside
 the timed region), the FP32-bulk form's throughput and error, the
 differentiation form (adjoint / forward time and its finite-difference
-check) and the FP64 CPU oracle timed on a bounded sample.
+check), the walled blast workload (1.57M cells, slip walls) and the FP64
+CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -183,6 +184,58 @@ def adjoint_leg(G, I, mesh, W, gW, cfg_kw, nsteps, ndir, precision):
     return out, (Wr.grad.detach(), Gr.grad.detach())
 
 
+def blast_leg(G, I, n, steps, warmup):
+    """Shock-robustness workload with reflective walls: the spherical blast
+    (rho 1, p 10 inside r < 0.1, p 0.1 outside, at rest) in the unit cube,
+    n^3 hexahedra x 6 Kuhn tetrahedra, 10% jitter (seed 2), six slip walls,
+    Euler, third-order WENO, CFL 0.5; FP64 and FP32-bulk."""
+    import numpy as np
+    import torch
+    mesh = I.kuhn_cube_mesh(n, 1.0, 0.1, 2, False)
+    W, gW = I.blast_cell_averages(mesh)
+    vol = I_cell_volumes(mesh)
+    out = {"workload": f"spherical blast in the unit cube, {n}^3 hexes x 6 Kuhn tets "
+                       f"({mesh.n_cell} cells, {mesh.n_face} faces), 10% jitter, slip walls, Euler, CFL 0.5",
+           "cells": mesh.n_cell, "faces": mesh.n_face, "steps": steps}
+    res = {}
+    for name, prec in (("fp64", G.GKS_FP64), ("fp32_bulk", G.GKS_FP32_BULK)):
+        s = G.Solver(mesh, G.default_config(precision=prec), device="cuda:0")
+        s.init(W, gW)
+        sums0 = s.conservation_sums()
+        for _ in range(warmup):
+            s.step_cfl(0.5)
+        s.timing_read(reset=True)
+        s.timing_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.step_cfl(0.5)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s.timing_enable(False)
+        kt = s.timing_read(reset=True)
+        Wf, _ = s.read_state()
+        sums1 = s.conservation_sums()
+        flag = s.debug_reconstruct()[2]
+        units = {"cell": mesh.n_cell, "face": mesh.n_face}
+        kern = {}
+        for k, (ms, cnt) in kt.items():
+            if cnt:
+                kern[k] = {"avg_ms": ms / cnt}
+                if prec == G.GKS_FP64:
+                    kern[k]["hbm_GBs"] = BYTES_PER_UNIT[k] * units[UNIT[k]] / (ms / cnt * 1e-3) / 1e9
+        res[name] = (Wf, {"value": mesh.n_cell * 2 * steps / el, "unit": "cell-stage-updates/s",
+                          "ms_per_step": el / steps * 1e3,
+                          "mass_energy_drift": float(max(abs(sums1[q] - sums0[q]) / abs(sums0[q]) for q in (0, 4))),
+                          "fallback_cells": int(flag.sum()), "kernels": kern})
+    out["fp64"] = res["fp64"][1]
+    out["fp32_bulk"] = res["fp32_bulk"][1]
+    W64, W32 = res["fp64"][0], res["fp32_bulk"][0]
+    out["fp32_bulk"]["l1_density_vs_fp64"] = float(np.sum(vol * np.abs(W32[0] - W64[0])) / np.sum(vol * W64[0]))
+    out["fp32_bulk"]["speedup_vs_fp64"] = out["fp32_bulk"]["value"] / out["fp64"]["value"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +248,9 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=50,
                     help="steps of the differentiation leg (0 skips it)")
     ap.add_argument("--adjoint-directions", type=int, default=16)
+    ap.add_argument("--blast-n", type=int, default=64,
+                    help="hexahedra per side of the walled blast leg (0 skips it)")
+    ap.add_argument("--blast-steps", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a 256 MiB fill (writes 256 MiB) and a 256 MiB elementwise add "
                          "(reads and writes 256 MiB): known byte counts that calibrate rocprofv3 "
@@ -325,6 +381,7 @@ def main():
         out["adjoint"] = adj
     else:
         out["adjoint"] = None
+    out["blast_walls"] = blast_leg(G, I, args.blast_n, args.blast_steps, 2) if args.blast_n > 0 else None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, W, gW, cfg_kw, args.cpu_baseline_steps)
     else:
