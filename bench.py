@@ -60,8 +60,8 @@ UNIT = {"slopes": "cell", "reconstruct": "cell", "flux_stage1": "face", "flux_st
 PROFILE_NAMES = {
     "slopes": ("gks::slopes_kernel<double>", "gks::slopes_kernel<float>"),
     "reconstruct": ("gks::reconstruct_kernel<double>", "gks::reconstruct_kernel<float>"),
-    "flux_stage1": ("gks::flux_kernel<double, 0, true, true>", "gks::flux_kernel<float, 0, true, true>"),
-    "flux_stage2": ("gks::flux_kernel<double, 1, true, true>", "gks::flux_kernel<float, 1, true, true>"),
+    "flux_stage1": ("gks::flux_kernel<double, 0, true, true, false>", "gks::flux_kernel<float, 0, true, true, false>"),
+    "flux_stage2": ("gks::flux_kernel<double, 1, true, true, false>", "gks::flux_kernel<float, 1, true, true, false>"),
     "update_stage1": ("gks::update_kernel<double, 1>", "gks::update_kernel<float, 1>"),
     "update_stage2": ("gks::update_kernel<double, 2>", "gks::update_kernel<float, 2>"),
     "dt": ("gks::dt_pass1", None),  # one kernel serves both forms

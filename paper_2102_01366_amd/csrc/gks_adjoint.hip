@@ -45,15 +45,16 @@ constexpr int kFluxThreadsA = 256;
 constexpr int kFacesPerWaveA = 21;
 constexpr int kFacesPerBlockA = kFacesPerWaveA * (kFluxThreadsA / 64);
 
-template <typename R, int MODE, bool VISC, bool PRFIX>
+template <typename R, int MODE, bool VISC, bool PRFIX, bool WALL>
 __global__ __launch_bounds__(kFluxThreadsA) void flux_vjp_kernel(DevMesh m, AdjFlux a, Params p, double dt_)
 {
     const int nf = m.nf, n = m.nc;
     const R dt = R(dt_);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane / 3, k = lane - 3 * slot;
-    const int f = xcd_block_a() * kFacesPerBlockA + wave * kFacesPerWaveA + slot;
-    const bool live = slot < kFacesPerWaveA && f < nf;
+    const int f0 = WALL ? m.nfi : 0, f1 = WALL ? nf : m.nfi;
+    const int f = f0 + xcd_block_a() * kFacesPerBlockA + wave * kFacesPerWaveA + slot;
+    const bool live = slot < kFacesPerWaveA && f < f1;
     R Wb[2][5], Gb[2][5][3], off[2][3];
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd)
@@ -68,12 +69,10 @@ __global__ __launch_bounds__(kFluxThreadsA) void flux_vjp_kernel(DevMesh m, AdjF
 #pragma unroll
         for (int d = 0; d < 3; ++d) off[sd][d] = R(0);
     if (live) {
-        const int L = m.fcell[f], Rc0 = m.fcell[nf + f];
-        const bool wall = Rc0 < 0;
         // a wall face has only its owner: the neighbour terms below vanish
-        const int Rc = wall ? L : Rc0;
+        const int L = m.fcell[f], Rc = WALL ? L : m.fcell[nf + f];
         const double iL = m.geoD[(size_t)G_INVVOL * n + L];
-        const double iR = wall ? 0.0 : m.geoD[(size_t)G_INVVOL * n + Rc];
+        const double iR = WALL ? 0.0 : m.geoD[(size_t)G_INVVOL * n + Rc];
         double nn[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) nn[d] = m.fnrm[(size_t)d * nf + f];
@@ -118,7 +117,7 @@ __global__ __launch_bounds__(kFluxThreadsA) void flux_vjp_kernel(DevMesh m, AdjF
         const R area = fg[(size_t)F_AREA * nf + f];
         const R *coef = static_cast<const R *>(a.coef);
         gauss_point_vjp_point<R, VISC, PRFIX>(p, dt, nrm, area, r, dv, CoefView<R>{coef, n, L},
-                                              CoefView<R>{coef, n, Rc}, accb, Wb, Gb, off, wall);
+                                              CoefView<R>{coef, n, Rc}, accb, Wb, Gb, off, WALL);
     }
     // per side and component: the ten coefficient adjoints, summed over the
     // face's three Gauss points in order onto its first lane
@@ -141,19 +140,28 @@ __global__ __launch_bounds__(kFluxThreadsA) void flux_vjp_kernel(DevMesh m, AdjF
         }
 }
 
+template <typename R, int MODE, bool WALL>
+void launch_flux_vjp_part(const DevMesh &m, const AdjFlux &a, const Params &p, double dt, hipStream_t st)
+{
+    const int nfaces = WALL ? m.nf - m.nfi : m.nfi;
+    if (nfaces <= 0) return;
+    const dim3 grid((unsigned)((nfaces + kFacesPerBlockA - 1) / kFacesPerBlockA)), block(kFluxThreadsA);
+    const bool visc = p.viscous != 0, prfix = p.prandtl != 1.0;
+    if (visc && prfix)
+        hipLaunchKernelGGL((flux_vjp_kernel<R, MODE, true, true, WALL>), grid, block, 0, st, m, a, p, dt);
+    else if (visc)
+        hipLaunchKernelGGL((flux_vjp_kernel<R, MODE, true, false, WALL>), grid, block, 0, st, m, a, p, dt);
+    else if (prfix)
+        hipLaunchKernelGGL((flux_vjp_kernel<R, MODE, false, true, WALL>), grid, block, 0, st, m, a, p, dt);
+    else
+        hipLaunchKernelGGL((flux_vjp_kernel<R, MODE, false, false, WALL>), grid, block, 0, st, m, a, p, dt);
+}
+
 template <typename R, int MODE>
 void launch_flux_vjp_mode(const DevMesh &m, const AdjFlux &a, const Params &p, double dt, hipStream_t st)
 {
-    const dim3 grid((unsigned)((m.nf + kFacesPerBlockA - 1) / kFacesPerBlockA)), block(kFluxThreadsA);
-    const bool visc = p.viscous != 0, prfix = p.prandtl != 1.0;
-    if (visc && prfix)
-        hipLaunchKernelGGL((flux_vjp_kernel<R, MODE, true, true>), grid, block, 0, st, m, a, p, dt);
-    else if (visc)
-        hipLaunchKernelGGL((flux_vjp_kernel<R, MODE, true, false>), grid, block, 0, st, m, a, p, dt);
-    else if (prfix)
-        hipLaunchKernelGGL((flux_vjp_kernel<R, MODE, false, true>), grid, block, 0, st, m, a, p, dt);
-    else
-        hipLaunchKernelGGL((flux_vjp_kernel<R, MODE, false, false>), grid, block, 0, st, m, a, p, dt);
+    launch_flux_vjp_part<R, MODE, false>(m, a, p, dt, st);
+    launch_flux_vjp_part<R, MODE, true>(m, a, p, dt, st);
 }
 
 // ===========================================================================

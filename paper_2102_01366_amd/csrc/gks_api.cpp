@@ -35,7 +35,7 @@ struct gks_ctx {
     bool device_failed = false;
     // mesh, prepared on the host in device layout
     bool have_mesh = false;
-    int nc = 0, nf = 0;
+    int nc = 0, nf = 0, nfi = 0;  // nfi: interior faces (internal ids below it)
     bool fp32 = false;              // FP32-bulk form
     std::vector<int> cperm, fperm;  // internal -> caller
     std::vector<int> nbr, cface, fcell, bslot, bmode;
@@ -415,8 +415,10 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
     std::vector<int> fkey(nf);
     for (int f = 0; f < nf; ++f)
     {
+        // interior faces by their lower internal cell; wall faces after all of
+        // them (by owner), so that the flux runs them as a launch of their own
         const int64_t L = m->face_cell[2 * (size_t)f], R = m->face_cell[2 * (size_t)f + 1];
-        fkey[f] = R < 0 ? cinv[L] : std::min(cinv[L], cinv[R]);
+        fkey[f] = R < 0 ? nc + cinv[L] : std::min(cinv[L], cinv[R]);
     }
     std::vector<int> fperm(nf), finv(nf);
     std::iota(fperm.begin(), fperm.end(), 0);
@@ -655,8 +657,11 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
         }
     }
 
+    int nwall = 0;
+    for (int f = 0; f < nf; ++f) nwall += m->face_cell[2 * (size_t)f + 1] < 0 ? 1 : 0;
     c->nc = nc;
     c->nf = nf;
+    c->nfi = nf - nwall;
     c->cperm.swap(cperm);
     c->fperm.swap(fperm);
     // back slots: slot b of neighbour j = nbr[a][i] is the same face as slot a of i
@@ -710,6 +715,7 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     DevState &ds = c->ds;
     dm.nc = c->nc;
     dm.nf = c->nf;
+    dm.nfi = c->nfi;
     dm.nbr = (const int *)P(S_NBR);
     dm.cface = (const int *)P(S_CFACE);
     dm.M1 = P(S_M1);

@@ -53,6 +53,7 @@ enum FaceRow {
 // Device view of the mesh (all pointers into the caller's workspace).
 struct DevMesh {
     int nc, nf;
+    int nfi;            // faces [0, nfi) are interior, [nfi, nf) walls
     const int *nbr;     // [4][nc] neighbour internal id, -1 on a wall
     const int *cface;   // [4][nc] 2 * face + side (side 1: the cell is the face's neighbour)
     const void *M1;     // [12][nc] slopes b_d = sum_m M1[4d+m] (Q_m - Q_0)

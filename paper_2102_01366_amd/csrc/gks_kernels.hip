@@ -370,7 +370,9 @@ constexpr int kFluxThreads = 256;
 constexpr int kFacesPerWave = 21;
 constexpr int kFacesPerBlock = kFacesPerWave * (kFluxThreads / 64);
 
-template <typename R, int MODE, bool VISC, bool PRFIX>
+// WALL: the launch over the wall faces [nfi, nf) (slip-wall ghost on the
+// right), else over the interior faces [0, nfi).
+template <typename R, int MODE, bool VISC, bool PRFIX, bool WALL>
 __global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(DevMesh m, DevState s, Params p, double dt_,
                                                                              const double *dtp)
 {
@@ -381,8 +383,9 @@ __global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(
       *FWs = static_cast<R *>(s.FWs);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane / 3, k = lane - 3 * slot;
-    const int f = xcd_block() * kFacesPerBlock + wave * kFacesPerWave + slot;
-    const bool live = slot < kFacesPerWave && f < nf;
+    const int f0 = WALL ? m.nfi : 0, f1 = WALL ? nf : m.nfi;
+    const int f = f0 + xcd_block() * kFacesPerBlock + wave * kFacesPerWave + slot;
+    const bool live = slot < kFacesPerWave && f < f1;
     R acc[4][5];
     if (live) {
         const int L = m.fcell[f], Rc = m.fcell[nf + f];
@@ -395,9 +398,8 @@ __global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(
             r[d] = fg[(size_t)(F_RL + 3 * k + d) * nf + f];
         }
         const R area = fg[(size_t)F_AREA * nf + f];
-        const bool wall = Rc < 0;
         gauss_point_terms<R, VISC, PRFIX>(p, dt, nrm, area, r, dv, DevCoef<R>{coef, n, L},
-                                          DevCoef<R>{coef, n, wall ? L : Rc}, acc, wall);
+                                          DevCoef<R>{coef, n, WALL ? L : Rc}, acc, WALL);
     } else {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -434,20 +436,30 @@ __global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(
     }
 }
 
+template <typename R, int MODE, bool WALL>
+static void launch_flux_part(const DevMesh &m, const DevState &s, const Params &p, double dt,
+                             const double *dtp, hipStream_t st)
+{
+    const int nfaces = WALL ? m.nf - m.nfi : m.nfi;
+    if (nfaces <= 0) return;
+    const dim3 grid((unsigned)((nfaces + kFacesPerBlock - 1) / kFacesPerBlock)), block(kFluxThreads);
+    const bool visc = p.viscous != 0, prfix = p.prandtl != 1.0;
+    if (visc && prfix)
+        hipLaunchKernelGGL((flux_kernel<R, MODE, true, true, WALL>), grid, block, 0, st, m, s, p, dt, dtp);
+    else if (visc)
+        hipLaunchKernelGGL((flux_kernel<R, MODE, true, false, WALL>), grid, block, 0, st, m, s, p, dt, dtp);
+    else if (prfix)
+        hipLaunchKernelGGL((flux_kernel<R, MODE, false, true, WALL>), grid, block, 0, st, m, s, p, dt, dtp);
+    else
+        hipLaunchKernelGGL((flux_kernel<R, MODE, false, false, WALL>), grid, block, 0, st, m, s, p, dt, dtp);
+}
+
 template <typename R, int MODE>
 static void launch_flux_mode(const DevMesh &m, const DevState &s, const Params &p, double dt,
                              const double *dtp, hipStream_t st)
 {
-    const dim3 grid((unsigned)((m.nf + kFacesPerBlock - 1) / kFacesPerBlock)), block(kFluxThreads);
-    const bool visc = p.viscous != 0, prfix = p.prandtl != 1.0;
-    if (visc && prfix)
-        hipLaunchKernelGGL((flux_kernel<R, MODE, true, true>), grid, block, 0, st, m, s, p, dt, dtp);
-    else if (visc)
-        hipLaunchKernelGGL((flux_kernel<R, MODE, true, false>), grid, block, 0, st, m, s, p, dt, dtp);
-    else if (prfix)
-        hipLaunchKernelGGL((flux_kernel<R, MODE, false, true>), grid, block, 0, st, m, s, p, dt, dtp);
-    else
-        hipLaunchKernelGGL((flux_kernel<R, MODE, false, false>), grid, block, 0, st, m, s, p, dt, dtp);
+    launch_flux_part<R, MODE, false>(m, s, p, dt, dtp, st);
+    launch_flux_part<R, MODE, true>(m, s, p, dt, dtp, st);
 }
 
 // ===========================================================================
