@@ -76,7 +76,8 @@ typedef struct {
     int32_t viscous;  /* 0: Euler, tau = 0; 1: Navier-Stokes, tau = mu / p */
     int32_t nonlinear;/* 1: multi-resolution WENO weights; 0: linear (R = P^2) */
     int32_t precision;/* GKS_FP64 or GKS_FP32_BULK */
-    int32_t reserved; /* must be 0 */
+    int32_t order;    /* 3: third-order scheme (default); 2: second-order scheme, R from P^1 and
+                         P^0 only (eq. final_weno_expression-2nd) */
 } gks_config;
 
 /* Fill cfg with the paper's defaults: gamma 1.4, Euler, Pr 1, eps_tau 0.01,

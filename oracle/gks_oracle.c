@@ -635,17 +635,80 @@ static int cell_face_points(const or_ctx *c, int64_t i, double r[12][3])
     return k;
 }
 
+/* eq. p0-non-linear-weight: the two-step indicator of P^0 for component q,
+ * from the neighbours' step-1 slopes */
+static double beta0_two_step(const or_ctx *c, int64_t i, const double *slopes, int q)
+{
+    const or_config *cf = &c->cfg;
+    int64_t n = c->nc;
+    double vol23 = pow(c->vol[i], 2.0 / 3.0), eps = cf->eps_weno;
+    double b0[4];
+    int nb = 0;
+    for (int a = 0; a < 4; ++a) {
+        int64_t m = c->nbr[i][a];
+        if (m < 0) continue;
+        double s = 0;
+        for (int d = 0; d < 3; ++d) {
+            double v = slopes[(3 * q + d) * n + m];
+            s += v * v;
+        }
+        b0[nb++] = vol23 * s;
+    }
+    double beta0 = 0.0;
+    if (nb > 0) {
+        double sum = 0.0;
+        int npair = 0;
+        for (int j = 0; j < nb; ++j)
+            for (int k = 0; k < j; ++k) { sum += fabs(b0[j] - b0[k]); ++npair; }
+        double sigma1 = npair ? pow(sum / npair, 4.0 / 3.0) : 0.0;
+        double w[4], ws = 0.0;
+        for (int j = 0; j < nb; ++j) { w[j] = 1.0 + sigma1 / (eps + b0[j]); ws += w[j]; }
+        for (int j = 0; j < nb; ++j) beta0 += (w[j] / ws) * b0[j];
+    }
+    return beta0;
+}
+
+static int positivity_fallback(const or_ctx *c, int64_t i, const double *W, qpoly_t R[NC]);
+
+/* Second-order scheme (eq. final_weno_expression-2nd): R = w11 p1 + w01 p0
+ * with p1 = (P^1 - g01 P^0) / g11, p0 = P^0, sigma = |beta1 - beta0|^(4/3) */
+static int reconstruct_cell_2nd(const or_ctx *c, int64_t i, const double *W, const double *slopes,
+                                qpoly_t R[NC])
+{
+    const or_config *cf = &c->cfg;
+    int64_t n = c->nc;
+    const double g11 = cf->lw1[0], g01 = cf->lw1[1], eps = cf->eps_weno;
+    for (int q = 0; q < NC; ++q) {
+        qpoly_t P0;
+        memset(&P0, 0, sizeof(P0));
+        P0.c0 = W[q * n + i];
+        qpoly_t P1 = P0;
+        for (int d = 0; d < 3; ++d) P1.G[d] = slopes[(3 * q + d) * n + i];
+        if (!cf->nonlinear) { R[q] = P1; continue; }
+        double beta1 = smoothness(c, i, &P1, 1);
+        double beta0 = beta0_two_step(c, i, slopes, q);
+        double sigma = pow(fabs(beta1 - beta0), 4.0 / 3.0);
+        double w1 = g11 * (1.0 + pow(sigma / (eps + beta1), 2.0));
+        double w0 = g01 * (1.0 + pow(sigma / (eps + beta0), 2.0));
+        double ws = w0 + w1;
+        w0 /= ws; w1 /= ws;
+        qpoly_t p1 = quad_lin(1.0 / g11, &P1, -g01 / g11, &P0);
+        R[q] = quad_lin(w1, &p1, w0, &P0);
+    }
+    return positivity_fallback(c, i, W, R);
+}
+
 /* Secs. 4.2-4.3: multi-resolution WENO with the two-step indicator for P^0 */
 static int reconstruct_cell(const or_ctx *c, int64_t i, const double *W, const double *gW,
                             const double *slopes, qpoly_t R[NC], qpoly_t *p2out)
 {
     const or_config *cf = &c->cfg;
     int64_t n = c->nc;
+    if (cf->order == 2) return reconstruct_cell_2nd(c, i, W, slopes, R);
     qpoly_t P2[NC];
     p2_cell(c, i, W, gW, P2);
     if (p2out)
         for (int q = 0; q < NC; ++q) p2out[q] = P2[q];
-    double vol23 = pow(c->vol[i], 2.0 / 3.0);
     const double g22 = cf->lw2[0], g12 = cf->lw2[1], g02 = cf->lw2[2];
     const double g11 = cf->lw1[0], g01 = cf->lw1[1];
     const double eps = cf->eps_weno;
@@ -661,29 +724,7 @@ static int reconstruct_cell(const or_ctx *c, int64_t i, const double *W, const d
         double beta1 = smoothness(c, i, &P1, 1);
         double beta2 = smoothness(c, i, &P2[q], 2);
         /* eq. p0-non-linear-weight: indicator of P^0 from the neighbours' slopes */
-        double b0[4];
-        int nb = 0;
-        for (int a = 0; a < 4; ++a) {
-            int64_t m = c->nbr[i][a];
-            if (m < 0) continue;
-            double s = 0;
-            for (int d = 0; d < 3; ++d) {
-                double v = slopes[(3 * q + d) * n + m];
-                s += v * v;
-            }
-            b0[nb++] = vol23 * s;
-        }
-        double beta0 = 0.0;
-        if (nb > 0) {
-            double sum = 0.0;
-            int npair = 0;
-            for (int j = 0; j < nb; ++j)
-                for (int k = 0; k < j; ++k) { sum += fabs(b0[j] - b0[k]); ++npair; }
-            double sigma1 = npair ? pow(sum / npair, 4.0 / 3.0) : 0.0;
-            double w[4], ws = 0.0;
-            for (int j = 0; j < nb; ++j) { w[j] = 1.0 + sigma1 / (eps + b0[j]); ws += w[j]; }
-            for (int j = 0; j < nb; ++j) beta0 += (w[j] / ws) * b0[j];
-        }
+        double beta0 = beta0_two_step(c, i, slopes, q);
         /* global indicator and nonlinear weights (eq. non-linear-weight) */
         double sigma = pow(0.5 * (fabs(beta2 - beta1) + fabs(beta2 - beta0)), 4.0 / 3.0);
         double w2 = g22 * (1.0 + pow(sigma / (eps + beta2), 2.0));
@@ -699,8 +740,15 @@ static int reconstruct_cell(const or_ctx *c, int64_t i, const double *W, const d
         qpoly_t s = quad_lin(w2, &p2, w1, &p1);
         R[q] = quad_lin(1.0, &s, w0, &p0);
     }
-    /* positivity of density and pressure at the cell's face Gauss points;
-     * otherwise the first-order (constant) reconstruction */
+    return positivity_fallback(c, i, W, R);
+}
+
+/* positivity of density and pressure at the cell's face Gauss points;
+ * otherwise the first-order (constant) reconstruction */
+static int positivity_fallback(const or_ctx *c, int64_t i, const double *W, qpoly_t R[NC])
+{
+    const or_config *cf = &c->cfg;
+    int64_t n = c->nc;
     double r[12][3];
     int np = cell_face_points(c, i, r);
     int bad = 0;
@@ -736,6 +784,7 @@ int or_reconstruct(or_ctx *c, const double *W, const double *gW, double *coef, i
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         qpoly_t R[NC], P2[NC];
+        memset(P2, 0, sizeof(P2)); /* the second-order scheme has no P^2 */
         int bad = reconstruct_cell(c, i, W, gW, c->slopes, R, P2);
         for (int q = 0; q < NC; ++q) {
             pack_quad(&R[q], coef, n, i, q);

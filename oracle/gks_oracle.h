@@ -33,6 +33,8 @@ typedef struct {
     double lw1[2];    /* linear weights gamma_{1,1}, gamma_{0,1} (sum 1) */
     int32_t viscous;  /* 0: Euler (tau = 0); 1: Navier-Stokes (tau = mu / p) */
     int32_t nonlinear;/* 1: multi-resolution WENO weights; 0: R = P^2 (linear) */
+    int32_t order;    /* 3: third-order (P^2, eq. final_weno_expression-3rd); 2: second-order
+                         (P^1 and P^0 only, eq. final_weno_expression-2nd) */
 } or_config;
 
 typedef struct or_ctx or_ctx;

@@ -59,7 +59,7 @@ class Config(ctypes.Structure):
                 ("c_tau", ctypes.c_double), ("eps_weno", ctypes.c_double),
                 ("lw2", ctypes.c_double * 3), ("lw1", ctypes.c_double * 2),
                 ("viscous", ctypes.c_int32), ("nonlinear", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
 class _Mesh(ctypes.Structure):

@@ -53,7 +53,7 @@ struct gks_ctx {
         double *Wchk, *Gchk, *Ws, *Gs, *Wn, *Ln, *Ltn, *Wb1, *Gb1, *Wbs, *Gbs, *Wbn, *Gbn;
         void *slopes1, *slopes2, *coef1, *coef2, *FF, *FT, *FW0, *FWs;
         int *flag1, *flag2, *nonphys;
-        double *CB, *own_w, *own_s, *nb_w, *nb_g, *nb_s, *nb_w1, *Wtmp, *red;
+        double *CB, *own_w, *own_s, *nb_w, *nb_g, *nb_s, *nb_w1, *Wtmp, *red, *EQ, *SB;
     } adj{};
     double *staging = nullptr;
     int *istaging = nullptr;
@@ -258,7 +258,7 @@ bool config_ok(const gks_config *c, std::string &why)
     if (c->viscous != 0 && c->viscous != 1) { why = "viscous must be 0 or 1"; return false; }
     if (c->nonlinear != 0 && c->nonlinear != 1) { why = "nonlinear must be 0 or 1"; return false; }
     if (c->precision != GKS_FP64 && c->precision != GKS_FP32_BULK) { why = "unknown precision"; return false; }
-    if (c->reserved != 0) { why = "reserved must be 0"; return false; }
+    if (c->order != 2 && c->order != 3) { why = "order must be 2 or 3"; return false; }
     return true;
 }
 
@@ -312,6 +312,7 @@ void gks_default_config(gks_config *cfg)
     cfg->viscous = 0;
     cfg->nonlinear = 1;
     cfg->precision = GKS_FP64;
+    cfg->order = 3;
 }
 
 gks_status gks_create(const gks_config *cfg, gks_ctx **out)
@@ -935,7 +936,7 @@ namespace {
 enum AdjSlot {
     A_WCHK, A_GCHK, A_WS, A_GS, A_WN, A_LN, A_LTN, A_WB1, A_GB1, A_WBS, A_GBS, A_WBN, A_GBN,
     A_SLOPES1, A_SLOPES2, A_COEF1, A_COEF2, A_FF, A_FT, A_FW0, A_FWS, A_FLAG1, A_FLAG2, A_NONPHYS,
-    A_CB, A_OWNW, A_OWNS, A_NBW, A_NBG, A_NBS, A_NBW1, A_WTMP, A_RED, A_COUNT
+    A_CB, A_OWNW, A_OWNS, A_NBW, A_NBG, A_NBS, A_NBW1, A_WTMP, A_RED, A_EQ, A_SB, A_COUNT
 };
 
 Layout make_adj_layout(size_t nc, size_t nf, size_t bs)
@@ -947,7 +948,7 @@ Layout make_adj_layout(size_t nc, size_t nf, size_t bs)
         5 * nf * bs, 5 * nf * bs, 5 * nf * bs, 5 * nf * bs,
         nc * sizeof(int), nc * sizeof(int), 64,
         100 * nf * 8, d5, d15, 4 * d5, 4 * d15, 4 * d15, 4 * d5, d5,
-        (8 + 5 * (size_t)gks::kRedBlocks) * 8};
+        (8 + 5 * (size_t)gks::kRedBlocks) * 8, 32 * 3 * nf * 8, 35 * 6 * nf * 8};
     Layout L;
     size_t o = 0;
     for (int k = 0; k < A_COUNT; ++k) {
@@ -1012,6 +1013,8 @@ gks_status gks_bind_adjoint_workspace(gks_ctx *c, void *dev, size_t bytes)
     a.nb_w1 = (double *)P(A_NBW1);
     a.Wtmp = (double *)P(A_WTMP);
     a.red = (double *)P(A_RED);
+    a.EQ = (double *)P(A_EQ);
+    a.SB = (double *)P(A_SB);
     HIP_TRY(c, gks::launch_fill_int(a.nonphys, 0, c->stream));
     c->adj_bound = true;
     return GKS_OK;
@@ -1078,7 +1081,7 @@ gks_status gks_step_adjoint(gks_ctx *c, double dt, const double *W_n, const doub
     r.nb_w1 = a.nb_w1;
     r.Wtmp = a.Wtmp;
     r.bslot = dm.bslot;
-    gks::AdjFlux fx{a.coef2, a.Wb1, a.Gb1, nullptr, nullptr, a.CB};
+    gks::AdjFlux fx{a.coef2, a.Wb1, a.Gb1, nullptr, nullptr, a.CB, a.EQ, a.SB};
     HIP_TRY(c, gks::launch_flux_vjp(dm, fx, c->par, dt, gks::FLUX_ADJ_STAGE2, f32, s));
     r.W = a.Ws;
     r.G = a.Gs;
@@ -1087,7 +1090,7 @@ gks_status gks_step_adjoint(gks_ctx *c, double dt, const double *W_n, const doub
     HIP_TRY(c, gks::launch_recon_vjp(dm, r, c->par, f32, s));
     HIP_TRY(c, gks::launch_recon_gather(dm, r, f32, a.Gbs, a.Wbs, nullptr, nullptr, s));
     // stage 1 in reverse: -> W^n, grad W^n (W^n also enters both updates directly)
-    fx = gks::AdjFlux{a.coef1, a.Wb1, a.Gb1, a.Wbs, a.Gbs, a.CB};
+    fx = gks::AdjFlux{a.coef1, a.Wb1, a.Gb1, a.Wbs, a.Gbs, a.CB, a.EQ, a.SB};
     HIP_TRY(c, gks::launch_flux_vjp(dm, fx, c->par, dt, gks::FLUX_ADJ_STAGE1, f32, s));
     r.W = a.Wchk;
     r.G = a.Gchk;

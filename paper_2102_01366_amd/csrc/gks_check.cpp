@@ -179,8 +179,31 @@ extern "C" gks_status gks_weno_check(const gks_config *cfg, const double geo[8],
     for (int s = 0; s < 4; ++s)
         for (int d = 0; d < 3; ++d) sn[s][d] = Dual(x[13 + 3 * s + d], v[13 + 3 * s + d]);
     for (int k = 0; k < 6; ++k) C[k] = Dual(geo[k]);
-    gks::WenoFwd<Dual> fd;
     Dual Rq[10];
+    if (p.order == 2) {
+        // the second-order combination: x[1..9] (the fit) does not enter
+        gks::Weno2Fwd<Dual> f2;
+        gks::weno2_forward<Dual>(p, Q0, Dual(geo[6]), b, sn, has, f2, Rq);
+        double bq[3], snq[4][3], Rd[10];
+        for (int d = 0; d < 3; ++d) bq[d] = x[10 + d];
+        for (int s = 0; s < 4; ++s)
+            for (int d = 0; d < 3; ++d) snq[s][d] = x[13 + 3 * s + d];
+        gks::Weno2Fwd<double> f;
+        gks::weno2_forward<double>(p, x[0], geo[6], bq, snq, has, f, Rd);
+        double Q0b, bb[3], snb[4][3];
+        gks::weno2_reverse<double>(p, geo[6], bq, snq, has, f, rbar, Q0b, bb, snb);
+        for (int k = 0; k < 10; ++k) {
+            r[k] = Rq[k].v;
+            jv[k] = Rq[k].d;
+        }
+        xbar[0] = Q0b;
+        for (int k = 0; k < 9; ++k) xbar[1 + k] = 0.0;
+        for (int d = 0; d < 3; ++d) xbar[10 + d] = bb[d];
+        for (int s = 0; s < 4; ++s)
+            for (int d = 0; d < 3; ++d) xbar[13 + 3 * s + d] = snb[s][d];
+        return GKS_OK;
+    }
+    gks::WenoFwd<Dual> fd;
     gks::weno_forward<Dual>(p, Q0, c, C, Dual(geo[6]), Dual(geo[7]), b, sn, has, fd, Rq);
     for (int k = 0; k < 10; ++k) {
         r[k] = Rq[k].v;

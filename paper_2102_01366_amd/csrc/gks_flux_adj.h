@@ -579,45 +579,91 @@ GKS_HD void side_terms_rev(const Params &p, const Prim<R> &g, R m0, R m1, const 
     gb.rho += rhob;
 }
 
-// Vector-Jacobian product of gks_point: given the adjoints Fob, Wob of its
-// outputs, adds the adjoints of wl, gl, wr, gr.
-template <typename R, bool VISC, bool PRFIX>
-GKS_HD void gks_point_vjp(const Params &p, R dt, const R wl[5], const R gl[3][5], const R wr[5],
-                          const R gr[3][5], const R Fob[2][5], const R Wob[2][5], R wlb[5], R glb[3][5],
-                          R wrb[5], R grb[3][5])
+// The reverse of gks_point in four parts, so that a kernel can hold one
+// part's working set at a time:
+//   point_forward      the forward quantities that depend on the two point
+//                      states only (primitive variables, half-line seeds, W^c,
+//                      collision times, time coefficients);
+//   eq_reverse         the equilibrium part's reverse, which also yields the
+//                      adjoint of g^c_x (the kinetic slopes' contribution);
+//   side_reverse       one kinetic side's reverse;
+//   common_reverse     the reverse of the point_forward quantities.
+template <typename R>
+struct PointFwd {
+    Prim<R> gL, gR, gC;
+    R l0, l1, r0, r1, el, er;
+    R Wc[5], Uc[3];
+    R pl, pr, pc, z, tau, taun;
+    TimeCoef<R> tc;
+};
+
+template <typename R, bool VISC>
+GKS_HD void point_forward(const Params &p, R dt, const R wl[5], const R wr[5], PointFwd<R> &P)
 {
     const R K = R(p.K);
-    // ---- forward (as gks_point)
-    const Prim<R> gL = primitive(wl, K), gR = primitive(wr, K);
-    const R sl = sqrt(gL.lam), el = exp(-gL.lam * gL.U * gL.U) / (R(2) * sqrt(R(M_PI) * gL.lam));
-    const R l0 = R(0.5) * erfc(-sl * gL.U), l1 = gL.U * l0 + el;
-    const R sr = sqrt(gR.lam), er = exp(-gR.lam * gR.U * gR.U) / (R(2) * sqrt(R(M_PI) * gR.lam));
-    const R r0 = R(0.5) * erfc(sr * gR.U), r1 = gR.U * r0 - er;
+    P.gL = primitive(wl, K);
+    P.gR = primitive(wr, K);
+    const Prim<R> &gL = P.gL, &gR = P.gR;
+    const R sl = sqrt(gL.lam), sr = sqrt(gR.lam);
+    P.el = exp(-gL.lam * gL.U * gL.U) / (R(2) * sqrt(R(M_PI) * gL.lam));
+    P.er = exp(-gR.lam * gR.U * gR.U) / (R(2) * sqrt(R(M_PI) * gR.lam));
+    P.l0 = R(0.5) * erfc(-sl * gL.U);
+    P.l1 = gL.U * P.l0 + P.el;
+    P.r0 = R(0.5) * erfc(sr * gR.U);
+    P.r1 = gR.U * P.r0 - P.er;
     const R hl = R(0.5) / gL.lam, hr = R(0.5) / gR.lam;
-    const R l2 = gL.U * l1 + hl * l0, r2 = gR.U * r1 + hr * r0;
+    const R l2 = gL.U * P.l1 + hl * P.l0, r2 = gR.U * P.r1 + hr * P.r0;
     const R tl = gL.V * gL.V + gL.W * gL.W + (R(2) + K) * hl;
     const R tr = gR.V * gR.V + gR.W * gR.W + (R(2) + K) * hr;
-    R Wc[5];
-    Wc[0] = gL.rho * l0 + gR.rho * r0;
-    Wc[1] = gL.rho * l1 + gR.rho * r1;
-    Wc[2] = gL.rho * (gL.V * l0) + gR.rho * (gR.V * r0);
-    Wc[3] = gL.rho * (gL.W * l0) + gR.rho * (gR.W * r0);
-    Wc[4] = gL.rho * (R(0.5) * (l2 + l0 * tl)) + gR.rho * (R(0.5) * (r2 + r0 * tr));
-    const Prim<R> gC = primitive(Wc, K);
-    const R Uc[3] = {gC.U, gC.V, gC.W};
-    const R pl = gL.rho * R(0.5) / gL.lam, pr = gR.rho * R(0.5) / gR.lam, pc = gC.rho * R(0.5) / gC.lam;
-    const R z = (pl - pr) / (pl + pr);
-    const R jump = R(p.c_tau) * fabs(z) * dt;
-    R tau, taun;
+    P.Wc[0] = gL.rho * P.l0 + gR.rho * P.r0;
+    P.Wc[1] = gL.rho * P.l1 + gR.rho * P.r1;
+    P.Wc[2] = gL.rho * (gL.V * P.l0) + gR.rho * (gR.V * P.r0);
+    P.Wc[3] = gL.rho * (gL.W * P.l0) + gR.rho * (gR.W * P.r0);
+    P.Wc[4] = gL.rho * (R(0.5) * (l2 + P.l0 * tl)) + gR.rho * (R(0.5) * (r2 + P.r0 * tr));
+    P.gC = primitive(P.Wc, K);
+    P.Uc[0] = P.gC.U;
+    P.Uc[1] = P.gC.V;
+    P.Uc[2] = P.gC.W;
+    P.pl = gL.rho * R(0.5) / gL.lam;
+    P.pr = gR.rho * R(0.5) / gR.lam;
+    P.pc = P.gC.rho * R(0.5) / P.gC.lam;
+    P.z = (P.pl - P.pr) / (P.pl + P.pr);
+    const R jump = R(p.c_tau) * fabs(P.z) * dt;
     if (VISC) {
-        tau = R(p.mu) / pc;
-        taun = tau + jump;
+        P.tau = R(p.mu) / P.pc;
+        P.taun = P.tau + jump;
     } else {
-        tau = R(0);
-        taun = R(p.eps_tau) * dt + jump;
+        P.tau = R(0);
+        P.taun = R(p.eps_tau) * dt + jump;
     }
-    TimeCoef<R> tc;
-    time_coefficients<R, VISC>(tau, taun, dt, tc);
+    time_coefficients<R, VISC>(P.tau, P.taun, dt, P.tc);
+}
+
+// adjoints produced by the equilibrium part
+template <typename R>
+struct EqAdj {
+    R gcb[3][5];            // g^c_x (from both sides' slopes)
+    PrimB<R> gCb;           // primitive variables of W^c (partial)
+    R cF0b[3], cF1b[3], cWb[3];  // equilibrium time coefficients
+    R Ucb[3];
+};
+
+// adjoints produced by one kinetic side
+template <typename R>
+struct SideAdj {
+    PrimB<R> gb;            // the side's primitive variables (partial)
+    R m0b, m1b;             // its half-line seeds
+    R grb[3][5];            // its point gradient (face frame)
+    R cF0b[3], cF1b[3], cWb[3], taub;  // kinetic time coefficients, tau (in W(0))
+    R Ucb[3];
+};
+
+template <typename R, bool VISC, bool PRFIX>
+GKS_HD void eq_reverse(const Params &p, const PointFwd<R> &P, const R gl[3][5], const R gr[3][5],
+                       const R Fob[2][5], const R Wob[2][5], EqAdj<R> &E)
+{
+    const R K = R(p.K);
+    const Prim<R> &gC = P.gC;
     R gc[3][5];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -625,15 +671,14 @@ GKS_HD void gks_point_vjp(const Params &p, R dt, const R wl[5], const R gl[3][5]
         for (int q = 0; q < 5; ++q) gc[d][q] = R(0);
     {
         SideFwd<R> S;
-        side_forward<R, VISC>(p, gL, l0, l1, gl, S, gc);
-        side_forward<R, VISC>(p, gR, r0, r1, gr, S, gc);
+        side_forward<R, VISC>(p, P.gL, P.l0, P.l1, gl, S, gc);
+        side_forward<R, VISC>(p, P.gR, P.r0, P.r1, gr, S, gc);
     }
-    // equilibrium part
     Tab<R> TC;
     gauss_moments<7>(gC.U, gC.lam, TC.u);
     vw_tables(gC, K, TC);
     const R irc = R(1) / gC.rho;
-    R ac[3][5], V1[5] = {R(0), R(0), R(0), R(0), R(0)}, F[3][5], V[3][5];
+    R ac[3][5], F[3][5], V[3][5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) F[1][q] = V[1][q] = F[2][q] = V[2][q] = R(0);
 #pragma unroll
@@ -653,26 +698,18 @@ GKS_HD void gks_point_vjp(const Params &p, R dt, const R wl[5], const R gl[3][5]
             contract<1, 0, 1>(TC, ac[d], R(1), F[1]);
         }
     }
-#pragma unroll
-    for (int q = 0; q < 5; ++q) V1[q] = V[1][q];
     R nB[5], Ac[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) nB[q] = -V1[q];
+    for (int q = 0; q < 5; ++q) nB[q] = -V[1][q];
     micro_slope(gC, K, nB, Ac);
     contract<1, 0, 0>(TC, Ac, R(1), F[2]);
     contract<0, 0, 0>(TC, Ac, R(1), V[2]);
     psi_mom<1, 0, 0>(TC, F[0]);
     psi_mom<0, 0, 0>(TC, V[0]);
 
-    // ---- reverse
-    PrimB<R> gLb, gRb, gCb;
-    zero(gLb);
-    zero(gRb);
-    zero(gCb);
-    TimeCoefB<R> tcb;
-    zero(tcb);
-    R Ucb[3] = {R(0), R(0), R(0)};
-    // equilibrium part
+    zero(E.gCb);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) E.cF0b[k] = E.cF1b[k] = E.cWb[k] = E.Ucb[k] = R(0);
     R Fb[3][5], Vb[3][5];
 #pragma unroll
     for (int j = 0; j < 3; ++j)
@@ -681,8 +718,8 @@ GKS_HD void gks_point_vjp(const Params &p, R dt, const R wl[5], const R gl[3][5]
     {
         const R cW0[3] = {R(0), R(0), R(0)};
         R cW0b[3] = {R(0), R(0), R(0)};
-        add_part_rev<R, PRFIX>(p, gC.rho, tc.cF[0], tc.cF[1], cW0, tc.cW, F, V, Uc, Fob, Wob, gCb.rho,
-                               tcb.cF[0], tcb.cF[1], cW0b, tcb.cW, Fb, Vb, Ucb);
+        add_part_rev<R, PRFIX>(p, gC.rho, P.tc.cF[0], P.tc.cF[1], cW0, P.tc.cW, F, V, P.Uc, Fob, Wob, E.gCb.rho,
+                               E.cF0b, E.cF1b, cW0b, E.cWb, Fb, Vb, E.Ucb);
     }
     TabB<R> TCb;
     zero(TCb);
@@ -693,11 +730,10 @@ GKS_HD void gks_point_vjp(const Params &p, R dt, const R wl[5], const R gl[3][5]
         R Acb[5] = {R(0), R(0), R(0), R(0), R(0)}, nBb[5] = {R(0), R(0), R(0), R(0), R(0)};
         contract_rev<0, 0, 0>(TC, Ac, R(1), Vb[2], TCb, Acb, dummy);
         contract_rev<1, 0, 0>(TC, Ac, R(1), Fb[2], TCb, Acb, dummy);
-        micro_slope_rev(gC, K, nB, Acb, gCb, nBb);
+        micro_slope_rev(gC, K, nB, Acb, E.gCb, nBb);
 #pragma unroll
         for (int q = 0; q < 5; ++q) Vb[1][q] -= nBb[q];
     }
-    R gcb[3][5];
     R ircb = R(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -715,84 +751,161 @@ GKS_HD void gks_point_vjp(const Params &p, R dt, const R wl[5], const R gl[3][5]
         R b[5], bb[5] = {R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
         for (int q = 0; q < 5; ++q) b[q] = gc[d][q] * irc;
-        micro_slope_rev(gC, K, b, ab, gCb, bb);
+        micro_slope_rev(gC, K, b, ab, E.gCb, bb);
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            gcb[d][q] = bb[q] * irc;
+            E.gcb[d][q] = bb[q] * irc;
             ircb += bb[q] * gc[d][q];
         }
     }
-    gCb.rho -= ircb * irc * irc;
-    vw_tables_rev(gC, K, TC, TCb, gCb);
-    gauss_moments_rev<7>(gC.U, gC.lam, TC.u, TCb.u, gCb.U, gCb.lam);
-    // kinetic parts of both sides
-    R l0b = R(0), l1b = R(0), r0b = R(0), r1b = R(0);
-    side_terms_rev<R, VISC, PRFIX>(p, gR, r0, r1, gr, tc, Uc, gcb, Fob, Wob, gRb, r0b, r1b, grb, tcb, Ucb);
-    side_terms_rev<R, VISC, PRFIX>(p, gL, l0, l1, gl, tc, Uc, gcb, Fob, Wob, gLb, l0b, l1b, glb, tcb, Ucb);
-    gCb.U += Ucb[0];
-    gCb.V += Ucb[1];
-    gCb.W += Ucb[2];
+    E.gCb.rho -= ircb * irc * irc;
+    vw_tables_rev(gC, K, TC, TCb, E.gCb);
+    gauss_moments_rev<7>(gC.U, gC.lam, TC.u, TCb.u, E.gCb.U, E.gCb.lam);
+}
+
+template <typename R, bool VISC, bool PRFIX>
+GKS_HD void side_reverse(const Params &p, const PointFwd<R> &P, bool right, const R g[3][5], const R gcb[3][5],
+                         const R Fob[2][5], const R Wob[2][5], SideAdj<R> &A)
+{
+    TimeCoefB<R> tcb;
+    zero(tcb);
+    zero(A.gb);
+    A.m0b = A.m1b = R(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) A.grb[d][q] = R(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) A.Ucb[k] = R(0);
+    side_terms_rev<R, VISC, PRFIX>(p, right ? P.gR : P.gL, right ? P.r0 : P.l0, right ? P.r1 : P.l1, g, P.tc,
+                                   P.Uc, gcb, Fob, Wob, A.gb, A.m0b, A.m1b, A.grb, tcb, A.Ucb);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        A.cF0b[k] = tcb.cF[0][3 + k];
+        A.cF1b[k] = tcb.cF[1][3 + k];
+        A.cWb[k] = tcb.cW[3 + k];
+    }
+    A.taub = tcb.tau;
+}
+
+// Completes the reverse: sets wlb, wrb (the adjoints of the point states).
+template <typename R, bool VISC>
+GKS_HD void common_reverse(const Params &p, R dt, const R wl[5], const R wr[5], const PointFwd<R> &P,
+                           const EqAdj<R> &E, const SideAdj<R> &SL, const SideAdj<R> &SR, R wlb[5], R wrb[5])
+{
+    const R K = R(p.K);
+    const Prim<R> &gL = P.gL, &gR = P.gR, &gC = P.gC;
+    TimeCoefB<R> tcb;
+    zero(tcb);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        tcb.cF[0][k] = E.cF0b[k];
+        tcb.cF[1][k] = E.cF1b[k];
+        tcb.cW[k] = E.cWb[k];
+        tcb.cF[0][3 + k] = SL.cF0b[k] + SR.cF0b[k];
+        tcb.cF[1][3 + k] = SL.cF1b[k] + SR.cF1b[k];
+        tcb.cW[3 + k] = SL.cWb[k] + SR.cWb[k];
+    }
+    tcb.tau = SL.taub + SR.taub;
+    PrimB<R> gLb = SL.gb, gRb = SR.gb, gCb = E.gCb;
+    R l0b = SL.m0b, l1b = SL.m1b, r0b = SR.m0b, r1b = SR.m1b;
+    gCb.U += E.Ucb[0] + SL.Ucb[0] + SR.Ucb[0];
+    gCb.V += E.Ucb[1] + SL.Ucb[1] + SR.Ucb[1];
+    gCb.W += E.Ucb[2] + SL.Ucb[2] + SR.Ucb[2];
     // collision times
     R taub = R(0), taunb = R(0);
-    time_coefficients_rev<R, VISC>(tau, taun, dt, tcb, taub, taunb);
+    time_coefficients_rev<R, VISC>(P.tau, P.taun, dt, tcb, taub, taunb);
     R jumpb, pcb = R(0);
     if (VISC) {
         taub += taunb;
         jumpb = taunb;
-        pcb -= taub * tau / pc;
+        pcb -= taub * P.tau / P.pc;
     } else {
         jumpb = taunb;
     }
-    const R zb = jumpb * R(p.c_tau) * dt * sign_of(z);
-    const R sp = pl + pr;
-    const R plb = zb * R(2) * pr / (sp * sp), prb = -zb * R(2) * pl / (sp * sp);
+    const R zb = jumpb * R(p.c_tau) * dt * sign_of(P.z);
+    const R sp = P.pl + P.pr;
+    const R plb = zb * R(2) * P.pr / (sp * sp), prb = -zb * R(2) * P.pl / (sp * sp);
     gLb.rho += plb * R(0.5) / gL.lam;
-    gLb.lam -= plb * pl / gL.lam;
+    gLb.lam -= plb * P.pl / gL.lam;
     gRb.rho += prb * R(0.5) / gR.lam;
-    gRb.lam -= prb * pr / gR.lam;
+    gRb.lam -= prb * P.pr / gR.lam;
     gCb.rho += pcb * R(0.5) / gC.lam;
-    gCb.lam -= pcb * pc / gC.lam;
-    // W^c = primitive^-1 ...: reverse of gC = primitive(Wc)
+    gCb.lam -= pcb * P.pc / gC.lam;
+    // gC = primitive(Wc)
     R Wcb[5] = {R(0), R(0), R(0), R(0), R(0)};
-    primitive_rev(Wc, K, gCb, Wcb);
-    // reverse of the kinetic weighting, one side at a time
+    primitive_rev(P.Wc, K, gCb, Wcb);
+    // the kinetic weighting, one side at a time: rho, V, W, seeds m0, m1,
+    // m2 = U m1 + h m0, t = V^2 + W^2 + (2+K) h
+    const R s4 = R(0.5) * Wcb[4];
     {
-        // left: rho, V, W, seeds l0, l1, l2 = U l1 + h l0, t = V^2 + W^2 + (2+K) h
-        const R s4 = R(0.5) * Wcb[4];
-        gLb.rho += Wcb[0] * l0 + Wcb[1] * l1 + Wcb[2] * gL.V * l0 + Wcb[3] * gL.W * l0 + s4 * (l2 + l0 * tl);
-        const R l2b = gL.rho * s4, tlb = gL.rho * s4 * l0;
+        const R hl = R(0.5) / gL.lam, l2 = gL.U * P.l1 + hl * P.l0;
+        const R tl = gL.V * gL.V + gL.W * gL.W + (R(2) + K) * hl;
+        gLb.rho += Wcb[0] * P.l0 + Wcb[1] * P.l1 + Wcb[2] * gL.V * P.l0 + Wcb[3] * gL.W * P.l0 + s4 * (l2 + P.l0 * tl);
+        const R l2b = gL.rho * s4, tlb = gL.rho * s4 * P.l0;
         l0b += gL.rho * (Wcb[0] + Wcb[2] * gL.V + Wcb[3] * gL.W + s4 * tl);
         l1b += gL.rho * Wcb[1];
-        gLb.V += gL.rho * Wcb[2] * l0 + R(2) * gL.V * tlb;
-        gLb.W += gL.rho * Wcb[3] * l0 + R(2) * gL.W * tlb;
-        gLb.U += l2b * l1;
+        gLb.V += gL.rho * Wcb[2] * P.l0 + R(2) * gL.V * tlb;
+        gLb.W += gL.rho * Wcb[3] * P.l0 + R(2) * gL.W * tlb;
+        gLb.U += l2b * P.l1;
         l1b += l2b * gL.U;
         l0b += l2b * hl;
-        const R hlb = l2b * l0 + (R(2) + K) * tlb;
+        const R hlb = l2b * P.l0 + (R(2) + K) * tlb;
         gLb.lam -= hlb * hl / gL.lam;
     }
     {
-        const R s4 = R(0.5) * Wcb[4];
-        gRb.rho += Wcb[0] * r0 + Wcb[1] * r1 + Wcb[2] * gR.V * r0 + Wcb[3] * gR.W * r0 + s4 * (r2 + r0 * tr);
-        const R r2b = gR.rho * s4, trb = gR.rho * s4 * r0;
+        const R hr = R(0.5) / gR.lam, r2 = gR.U * P.r1 + hr * P.r0;
+        const R tr = gR.V * gR.V + gR.W * gR.W + (R(2) + K) * hr;
+        gRb.rho += Wcb[0] * P.r0 + Wcb[1] * P.r1 + Wcb[2] * gR.V * P.r0 + Wcb[3] * gR.W * P.r0 + s4 * (r2 + P.r0 * tr);
+        const R r2b = gR.rho * s4, trb = gR.rho * s4 * P.r0;
         r0b += gR.rho * (Wcb[0] + Wcb[2] * gR.V + Wcb[3] * gR.W + s4 * tr);
         r1b += gR.rho * Wcb[1];
-        gRb.V += gR.rho * Wcb[2] * r0 + R(2) * gR.V * trb;
-        gRb.W += gR.rho * Wcb[3] * r0 + R(2) * gR.W * trb;
-        gRb.U += r2b * r1;
+        gRb.V += gR.rho * Wcb[2] * P.r0 + R(2) * gR.V * trb;
+        gRb.W += gR.rho * Wcb[3] * P.r0 + R(2) * gR.W * trb;
+        gRb.U += r2b * P.r1;
         r1b += r2b * gR.U;
         r0b += r2b * hr;
-        const R hrb = r2b * r0 + (R(2) + K) * trb;
+        const R hrb = r2b * P.r0 + (R(2) + K) * trb;
         gRb.lam -= hrb * hr / gR.lam;
     }
     // half-line seeds: d l0/dU = 2 lam e, d l0/dlam = U e, d l1/dU = l0,
     // d l1/dlam = -e/(2 lam); the right side with the signs of u < 0
-    gLb.U += l0b * R(2) * gL.lam * el + l1b * l0;
-    gLb.lam += l0b * gL.U * el - l1b * el / (R(2) * gL.lam);
-    gRb.U += -r0b * R(2) * gR.lam * er + r1b * r0;
-    gRb.lam += -r0b * gR.U * er + r1b * er / (R(2) * gR.lam);
+    gLb.U += l0b * R(2) * gL.lam * P.el + l1b * P.l0;
+    gLb.lam += l0b * gL.U * P.el - l1b * P.el / (R(2) * gL.lam);
+    gRb.U += -r0b * R(2) * gR.lam * P.er + r1b * P.r0;
+    gRb.lam += -r0b * gR.U * P.er + r1b * P.er / (R(2) * gR.lam);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) wlb[q] = wrb[q] = R(0);
     primitive_rev(wl, K, gLb, wlb);
     primitive_rev(wr, K, gRb, wrb);
+}
+
+// Vector-Jacobian product of gks_point: given the adjoints Fob, Wob of its
+// outputs, adds the adjoints of wl, gl, wr, gr (the four parts in sequence).
+template <typename R, bool VISC, bool PRFIX>
+GKS_HD void gks_point_vjp(const Params &p, R dt, const R wl[5], const R gl[3][5], const R wr[5],
+                          const R gr[3][5], const R Fob[2][5], const R Wob[2][5], R wlb[5], R glb[3][5],
+                          R wrb[5], R grb[3][5])
+{
+    PointFwd<R> P;
+    point_forward<R, VISC>(p, dt, wl, wr, P);
+    EqAdj<R> E;
+    eq_reverse<R, VISC, PRFIX>(p, P, gl, gr, Fob, Wob, E);
+    SideAdj<R> SL, SR;
+    side_reverse<R, VISC, PRFIX>(p, P, true, gr, E.gcb, Fob, Wob, SR);
+    side_reverse<R, VISC, PRFIX>(p, P, false, gl, E.gcb, Fob, Wob, SL);
+    R a[5], b[5];
+    common_reverse<R, VISC>(p, dt, wl, wr, P, E, SL, SR, a, b);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        wlb[q] += a[q];
+        wrb[q] += b[q];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            glb[d][q] += SL.grb[d][q];
+            grb[d][q] += SR.grb[d][q];
+        }
+    }
 }
 
 // Reverse of the rotation in eval_local: adjoints of the rotated point state

@@ -21,6 +21,7 @@ struct Params {
     double gamma, K, mu, prandtl, eps_tau, c_tau, eps_weno;
     double g22, g12, g02, g11, g01;
     int viscous, nonlinear;
+    int order;  // 3 or 2
 };
 
 // Rows of DevMesh::geoR ([NGEO_R][nc], bulk precision): what the
@@ -135,6 +136,8 @@ struct AdjFlux {
     const double *Wb1, *Gb1;    // adjoint of W^{n+1}, grad W^{n+1}
     const double *Wbs, *Gbs;    // adjoint of W*, grad W* (stage 1 only)
     double *CB;                 // [2][50][nf] out: coefficient adjoints of owner / neighbour
+    double *EQ;                 // [32][3 nf] per Gauss point: the equilibrium part's adjoints
+    double *SB;                 // [35][2 x 3 nf] per Gauss point and side: a kinetic side's adjoints
 };
 
 // Reconstruction stage of the adjoint: the stage's input state and step-1
@@ -158,7 +161,7 @@ hipError_t launch_flux_vjp(const DevMesh &m, const AdjFlux &a, const Params &p, 
                            bool fp32, hipStream_t st);
 // adjoints of the reconstruction's inputs: own / neighbour terms
 hipError_t launch_recon_vjp(const DevMesh &m, const AdjRecon &a, const Params &p, bool fp32,
-                            hipStream_t st);
+                            hipStream_t st);  // either order
 // gathers the neighbour terms (fixed slot order) and applies the reverse of the
 // step-1 slopes: Gout = adjoint of the stage's input gradient (complete); then
 // Wout = adjoint of its input W + X1 + X2 (X1, X2 may be null)

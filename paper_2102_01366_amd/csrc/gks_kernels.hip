@@ -8,6 +8,8 @@
 // per-cell operators are small matrix-vector products used once per stage.
 #include "gks_flux.h"
 #include "gks_internal.h"
+#include "gks_m2stage.h"
+#include "gks_recon_adj.h"
 
 #include <cmath>
 
@@ -97,39 +99,6 @@ __device__ __forceinline__ R pow43(R x) { return pow(x, R(4.0 / 3.0)); }
 // current one is used).  The coefficients then meet in LDS for the cell-wide
 // positivity check: wavefront a evaluates the three Gauss points of the face
 // opposite vertex a, wavefront 4 checks the cell average.
-constexpr int kRecCells = kM2Tile;
-constexpr int kRecThreads = 5 * kRecCells;
-constexpr int kM2Chunk = 48;                 // three output rows of 16 operator rows
-constexpr int kM2Chunks = kM2Rows / kM2Chunk;
-static_assert(kM2Chunk * kM2Chunks == kM2Rows && kM2Chunk % 16 == 0, "M2 chunking");
-
-// one chunk of a tile as 16-byte vectors, spread over the block
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-template <typename R>
-struct M2Chunk {
-    static constexpr int kVec = kM2Chunk * kRecCells * (int)sizeof(R) / 16;
-    static constexpr int kPer = (kVec + kRecThreads - 1) / kRecThreads;
-    u32x4 v[kPer];
-    __device__ __forceinline__ void load(const R *tile, int chunk)
-    {
-        const u32x4 *src = reinterpret_cast<const u32x4 *>(tile + (size_t)chunk * kM2Chunk * kRecCells);
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const int t = threadIdx.x + j * kRecThreads;
-            if (t < kVec) v[j] = src[t];
-        }
-    }
-    __device__ __forceinline__ void store(R *lds) const
-    {
-        u32x4 *dst = reinterpret_cast<u32x4 *>(lds);
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const int t = threadIdx.x + j * kRecThreads;
-            if (t < kVec) dst[t] = v[j];
-        }
-    }
-};
-
 template <typename R>
 __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, DevState s, Params p)
 {
@@ -345,6 +314,80 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
             coef[(size_t)(10 * q + k) * n + i] = anybad ? (k == 0 ? R(sQ0[q][l]) : R(0)) : sR[q][k][l];
         if (q == 0) s.flag[i] = anybad ? 1 : 0;
     }
+}
+
+// ===========================================================================
+// A2, second-order scheme (eq. final_weno_expression-2nd): R = Q0 + alpha
+// (P^1 - Q0) per component (weno2_forward), then the same positivity check at
+// the cell's 12 face Gauss points.  No step-2 fit; one thread per cell.
+// ===========================================================================
+template <typename R>
+__global__ __launch_bounds__(kBlock) void reconstruct2_kernel(DevMesh m, DevState s, Params p)
+{
+    const int i = xcd_gid();
+    const int n = m.nc;
+    if (i >= n) return;
+    const R *geo = static_cast<const R *>(m.geoR);
+    const R *slopes = static_cast<const R *>(s.slopes);
+    R *coef = static_cast<R *>(s.coef);
+    int nb[4];
+    bool has[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        nb[a] = m.nbr[a * n + i];
+        has[a] = nb[a] >= 0;
+    }
+    const R vol23 = geo[(size_t)G_VOL23 * n + i];
+    double Q0[5];
+    R G[5][3];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        Q0[q] = s.W[(size_t)q * n + i];
+        R b[3], sn[4][3], Rq[10];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            b[d] = slopes[(size_t)(3 * q + d) * n + i];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) sn[a][d] = has[a] ? slopes[(size_t)(3 * q + d) * n + nb[a]] : R(0);
+        }
+        Weno2Fwd<R> f;
+        weno2_forward<R>(p, R(Q0[q]), vol23, b, sn, has, f, Rq);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) G[q][d] = Rq[1 + d];
+    }
+    // Gauss points of the face opposite vertex a: r_k / 2 - r_a / 6, k != a
+    R rv[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) rv[a][d] = geo[(size_t)(G_RV + 3 * a + d) * n + i];
+    bool bad = false;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k == a) continue;
+            R r[3], v[5];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) r[d] = R(0.5) * rv[k][d] - rv[a][d] / R(6);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) v[q] = R(Q0[q]) + G[q][0] * r[0] + G[q][1] * r[1] + G[q][2] * r[2];
+            const R pr = R(p.gamma - 1.0) * (v[4] - R(0.5) * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
+            if (!(v[0] > R(0)) || !(pr > R(0))) bad = true;
+        }
+    {
+        const double pr = (p.gamma - 1.0) * (Q0[4] - 0.5 * (Q0[1] * Q0[1] + Q0[2] * Q0[2] + Q0[3] * Q0[3]) / Q0[0]);
+        if (!(Q0[0] > 0.0) || !(pr > 0.0)) *s.nonphys = 1;
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        coef[(size_t)(10 * q) * n + i] = R(Q0[q]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) coef[(size_t)(10 * q + 1 + d) * n + i] = bad ? R(0) : G[q][d];
+#pragma unroll
+        for (int k = 4; k < 10; ++k) coef[(size_t)(10 * q + k) * n + i] = R(0);
+    }
+    s.flag[i] = bad ? 1 : 0;
 }
 
 // ===========================================================================
@@ -672,6 +715,14 @@ hipError_t launch_slopes(const DevMesh &m, const DevState &s, bool fp32, hipStre
 hipError_t launch_reconstruct(const DevMesh &m, const DevState &s, const Params &p, bool fp32,
                               hipStream_t st)
 {
+    if (p.order == 2) {
+        const dim3 g = grid_for(m.nc), b(kBlock);
+        if (fp32)
+            hipLaunchKernelGGL(reconstruct2_kernel<float>, g, b, 0, st, m, s, p);
+        else
+            hipLaunchKernelGGL(reconstruct2_kernel<double>, g, b, 0, st, m, s, p);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)((m.nc + kRecCells - 1) / kRecCells)), block(kRecThreads);
     if (fp32)
         hipLaunchKernelGGL(reconstruct_kernel<float>, grid, block, 0, st, m, s, p);

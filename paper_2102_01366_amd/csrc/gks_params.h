@@ -26,6 +26,7 @@ inline Params params_from_config(const gks_config *cfg)
     p.g01 = cfg->lw1[1] / s1;
     p.viscous = cfg->viscous;
     p.nonlinear = cfg->nonlinear;
+    p.order = cfg->order;
     return p;
 }
 

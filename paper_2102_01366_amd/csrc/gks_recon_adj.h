@@ -228,6 +228,141 @@ GKS_HD void weno_reverse(const Params &p, const R c[9], const R C[6], R vol23, R
     cb[8] -= C[5] * corrb;
 }
 
+
+// ---------------------------------------------------------------------------
+// Second-order scheme (eq. final_weno_expression-2nd): R = w11 p1 + w01 p0,
+// p1 = (P^1 - g01 P^0) / g11, p0 = P^0, with sigma = |beta1 - beta0|^(4/3) and
+// beta0 the two-step indicator.  Both polynomials have the cell mean Q0, so
+// R = Q0 + alpha (P^1 - Q0) with alpha = w11 / g11: ten coefficients
+// (Q0, alpha b, 0 ... 0).
+template <typename R>
+struct Weno2Fwd {
+    R beta0, beta1, b0[4], S, sig1, w0v[4], ws0, X, r0, r1, ws, w1n, alpha;
+    int np, nn;
+};
+
+template <typename R>
+GKS_HD void weno2_forward(const Params &p, R Q0, R vol23, const R b[3], const R sn[4][3], const bool has[4],
+                          Weno2Fwd<R> &f, R Rq[10])
+{
+    const R eps = R(p.eps_weno), g11 = R(p.g11), g01 = R(p.g01);
+#pragma unroll
+    for (int k = 4; k < 10; ++k) Rq[k] = R(0);
+    Rq[0] = Q0;
+    if (!p.nonlinear) {
+        f.alpha = R(1);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Rq[1 + d] = b[d];
+        return;
+    }
+    f.beta1 = vol23 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        f.b0[s] = has[s] ? vol23 * (sn[s][0] * sn[s][0] + sn[s][1] * sn[s][1] + sn[s][2] * sn[s][2]) : R(0);
+    f.S = R(0);
+    f.np = 0;
+    f.nn = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        f.nn += has[j] ? 1 : 0;
+#pragma unroll
+        for (int k = 0; k < j; ++k)
+            if (has[j] && has[k]) {
+                f.S += fabs(f.b0[j] - f.b0[k]);
+                ++f.np;
+            }
+    }
+    f.sig1 = R(0);
+    f.ws0 = R(0);
+    f.beta0 = R(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) f.w0v[j] = R(0);
+    if (f.nn > 0) {
+        f.sig1 = f.np ? R(pow(f.S / R(f.np), R(4.0 / 3.0))) : R(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            f.w0v[j] = has[j] ? R(1) + f.sig1 / (eps + f.b0[j]) : R(0);
+            if (has[j]) f.ws0 += f.w0v[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (has[j]) f.beta0 += (f.w0v[j] / f.ws0) * f.b0[j];
+    }
+    f.X = fabs(f.beta1 - f.beta0);
+    const R sig = R(pow(f.X, R(4.0 / 3.0)));
+    f.r1 = sig / (eps + f.beta1);
+    f.r0 = sig / (eps + f.beta0);
+    const R w1 = g11 * (R(1) + f.r1 * f.r1), w0 = g01 * (R(1) + f.r0 * f.r0);
+    f.ws = w0 + w1;
+    f.w1n = w1 / f.ws;
+    f.alpha = f.w1n / g11;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Rq[1 + d] = f.alpha * b[d];
+}
+
+template <typename R>
+GKS_HD void weno2_reverse(const Params &p, R vol23, const R b[3], const R sn[4][3], const bool has[4],
+                          const Weno2Fwd<R> &f, const R Rqb[10], R &Q0b, R bb[3], R snb[4][3])
+{
+    const R eps = R(p.eps_weno), g11 = R(p.g11), g01 = R(p.g01);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) snb[s][d] = R(0);
+    Q0b = Rqb[0];
+    R alphab = R(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        bb[d] = f.alpha * Rqb[1 + d];
+        alphab += Rqb[1 + d] * b[d];
+    }
+    if (!p.nonlinear) return;
+    const R w1nb = alphab / g11;
+    const R wsb = -w1nb * f.w1n / f.ws;
+    const R w1b = w1nb / f.ws + wsb, w0b = wsb;
+    const R r1b = w1b * g11 * R(2) * f.r1, r0b = w0b * g01 * R(2) * f.r0;
+    const R sigb = r1b / (eps + f.beta1) + r0b / (eps + f.beta0);
+    R beta1b = -r1b * f.r1 / (eps + f.beta1);
+    R beta0b = -r0b * f.r0 / (eps + f.beta0);
+    const R Xb = sigb * R(4.0 / 3.0) * cbrt_pos(f.X);
+    const R s10 = sign_r(f.beta1 - f.beta0);
+    beta1b += Xb * s10;
+    beta0b -= Xb * s10;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) bb[d] += R(2) * vol23 * b[d] * beta1b;
+    R b0b[4] = {R(0), R(0), R(0), R(0)};
+    if (f.nn > 0) {
+        const R ws0b = -beta0b * f.beta0 / f.ws0;
+        R sig1b = R(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (has[j]) {
+                b0b[j] += beta0b * f.w0v[j] / f.ws0;
+                const R wjb = beta0b * f.b0[j] / f.ws0 + ws0b;
+                const R e = eps + f.b0[j];
+                sig1b += wjb / e;
+                b0b[j] -= wjb * f.sig1 / (e * e);
+            }
+        if (f.np > 0) {
+            const R Sb = sig1b * R(4.0 / 3.0) * cbrt_pos(f.S / R(f.np)) / R(f.np);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int k = 0; k < j; ++k)
+                    if (has[j] && has[k]) {
+                        const R sj = sign_r(f.b0[j] - f.b0[k]);
+                        b0b[j] += Sb * sj;
+                        b0b[k] -= Sb * sj;
+                    }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        if (has[s])
+#pragma unroll
+            for (int d = 0; d < 3; ++d) snb[s][d] = R(2) * vol23 * sn[s][d] * b0b[s];
+}
+
 #undef GKS_HD
 
 }  // namespace gks

@@ -43,7 +43,7 @@ def _create(lib, cfg):
 @pytest.mark.parametrize("field,value", [("gamma", 1.0), ("gamma", 0.5), ("mu", -1.0),
                                          ("prandtl", 0.0), ("eps_weno", 0.0),
                                          ("viscous", 2), ("nonlinear", -1), ("precision", 7),
-                                         ("reserved", 1)])
+                                         ("order", 4)])
 def test_create_rejects_bad_config(lib, field, value):
     cfg = G.default_config()
     setattr(cfg, field, value)

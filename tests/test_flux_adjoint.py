@@ -85,13 +85,13 @@ def test_bad_arguments():
         G.flux_point_check(cfg, 0.0, np.ones(40), np.ones(40), np.ones(20))
 
 
-@pytest.mark.parametrize("nonlinear", [True, False])
-def test_weno_reverse_is_the_transpose(nonlinear):
+@pytest.mark.parametrize("nonlinear,order", [(True, 3), (False, 3), (True, 2), (False, 2)])
+def test_weno_reverse_is_the_transpose(nonlinear, order):
     """The nonlinear combination of reconstruction step 2 (indicators,
     weights, R) against its reverse, including cells with missing
     neighbours."""
     rng = np.random.default_rng(14)
-    cfg = G.default_config(nonlinear=nonlinear)
+    cfg = G.default_config(nonlinear=nonlinear, order=order)
     for t in range(120):
         A = 0.1 * rng.standard_normal((3, 3))
         Cm = A @ A.T
