@@ -13,6 +13,16 @@ namespace gks {
 
 #define GKS_HD __host__ __device__ __forceinline__
 
+// A scheduling fence between the unrolled per-direction blocks of the reverse:
+// keeps the scheduler from interleaving them, which would hold several
+// directions' temporaries at once (the device pass only).
+__host__ __device__ __forceinline__ void sched_fence()
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
 // adjoints of a Prim and of a moment table
 template <typename R>
 struct PrimB {
@@ -134,8 +144,21 @@ GKS_HD void psi_mom_rev(const Tab<R> &T, const R tb[5], TabB<R> &Tb)
 // Reverse of contract<A,B,C>: out += s <u^A v^B w^C (a.psi) psi>.  Adds the
 // adjoints of the table (Tb), of a (ab) and of s (sb).
 template <int A, int B, int C, typename R>
+GKS_HD void contract_rev_split(const Tab<R> &T, const R a[5], R s, const R outb[5], R *ub, TabB<R> &Tb,
+                               R ab[5], R &sb);
+
+template <int A, int B, int C, typename R>
 GKS_HD void contract_rev(const Tab<R> &T, const R a[5], R s, const R outb[5], TabB<R> &Tb, R ab[5],
                          R &sb)
+{
+    contract_rev_split<A, B, C>(T, a, s, outb, Tb.u, Tb, ab, sb);
+}
+
+// The same with the adjoints of the u table in ub (so that a table sharing
+// its v, w and xi entries with another can keep a u-adjoint of its own).
+template <int A, int B, int C, typename R>
+GKS_HD void contract_rev_split(const Tab<R> &T, const R a[5], R s, const R outb[5], R *ub, TabB<R> &Tb,
+                               R ab[5], R &sb)
 {
     const R *U = T.u, *V = T.v, *W = T.w;
     // forward values
@@ -231,7 +254,7 @@ GKS_HD void contract_rev(const Tab<R> &T, const R a[5], R s, const R outb[5], Ta
     Tb.xi2 += c0b * h;
     ab[4] += R(0.5) * hb;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) Tb.u[A + k] += Ub[k];
+    for (int k = 0; k < 5; ++k) ub[A + k] += Ub[k];
 #pragma unroll
     for (int i = 0; i < 5; ++i)
 #pragma unroll
@@ -472,6 +495,7 @@ GKS_HD void side_forward(const Params &p, const Prim<R> &g, R m0, R m1, const R 
             contract<0, 0, 1>(S.Th, S.a[d], R(1), S.V[1]);
             if (VISC) contract<0, 0, 1>(S.Tf, S.a[d], R(-1), S.B);
         }
+        sched_fence();
     }
     if (VISC) {
         micro_slope(g, K, S.B, S.A);
@@ -490,12 +514,14 @@ GKS_HD void side_terms_rev(const Params &p, const Prim<R> &g, R m0, R m1, const 
 {
     const R K = R(p.K);
     SideFwd<R> S;
-    R gcs[3][5];
+    {
+        R gcs[3][5];
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+        for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int q = 0; q < 5; ++q) gcs[d][q] = R(0);
-    side_forward<R, VISC>(p, g, m0, m1, gr, S, gcs);
+            for (int q = 0; q < 5; ++q) gcs[d][q] = R(0);
+        side_forward<R, VISC>(p, g, m0, m1, gr, S, gcs);
+    }
     R Fb[3][5], Vb[3][5];
 #pragma unroll
     for (int j = 0; j < 3; ++j)
@@ -507,71 +533,57 @@ GKS_HD void side_terms_rev(const Params &p, const Prim<R> &g, R m0, R m1, const 
     add_part_rev<R, PRFIX>(p, g.rho, tc.cF[0] + 3, tc.cF[1] + 3, cW0, tc.cW + 3, S.F, S.V, Uc, Fob, Wob,
                            rhob, tcb.cF[0] + 3, tcb.cF[1] + 3, cW0b, tcb.cW + 3, Fb, Vb, Ucb);
     tcb.tau -= cW0b[1] + cW0b[2];
-    TabB<R> Thb, Tfb;
+    sched_fence();
+    TabB<R> Thb;
     zero(Thb);
-    zero(Tfb);
+    // the full-line table shares v, w and xi with the half-line one: only its
+    // u entries need an adjoint of their own
+    R Tfub[7] = {R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
     R dummy = R(0);
+    psi_mom_rev<0, 0, 0>(S.Th, Vb[0], Thb);
+    psi_mom_rev<1, 0, 0>(S.Th, Fb[0], Thb);
+    R Bb[5] = {R(0), R(0), R(0), R(0), R(0)};
     if (VISC) {
-        R Ab[5] = {R(0), R(0), R(0), R(0), R(0)}, Bb[5] = {R(0), R(0), R(0), R(0), R(0)};
+        R Ab[5] = {R(0), R(0), R(0), R(0), R(0)};
         contract_rev<0, 0, 0>(S.Th, S.A, R(1), Vb[2], Thb, Ab, dummy);
         contract_rev<1, 0, 0>(S.Th, S.A, R(1), Fb[2], Thb, Ab, dummy);
         micro_slope_rev(g, K, S.B, Ab, gb, Bb);
-        // B accumulated -<u_d (a_d.psi) psi> over the full line for each d
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            R ab[5] = {R(0), R(0), R(0), R(0), R(0)};
-            if (d == 0)
-                contract_rev<1, 0, 0>(S.Tf, S.a[d], R(-1), Bb, Tfb, ab, dummy);
-            else if (d == 1)
-                contract_rev<0, 1, 0>(S.Tf, S.a[d], R(-1), Bb, Tfb, ab, dummy);
-            else
-                contract_rev<0, 0, 1>(S.Tf, S.a[d], R(-1), Bb, Tfb, ab, dummy);
-            // gcs is free now: it carries these slope adjoints to the loop below
-#pragma unroll
-            for (int q = 0; q < 5; ++q) gcs[d][q] = ab[q];
-        }
     }
+    sched_fence();
     const R ir = R(1) / g.rho;
     R irb = R(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        R ab[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) ab[q] = VISC ? gcs[d][q] : R(0);
-        if (d == 0) {
-            contract_rev<2, 0, 0>(S.Th, S.a[d], R(1), Fb[1], Thb, ab, dummy);
-            contract_rev<1, 0, 0>(S.Th, S.a[d], R(1), Vb[1], Thb, ab, dummy);
-        } else if (d == 1) {
-            contract_rev<1, 1, 0>(S.Th, S.a[d], R(1), Fb[1], Thb, ab, dummy);
-            contract_rev<0, 1, 0>(S.Th, S.a[d], R(1), Vb[1], Thb, ab, dummy);
-        } else {
-            contract_rev<1, 0, 1>(S.Th, S.a[d], R(1), Fb[1], Thb, ab, dummy);
-            contract_rev<0, 0, 1>(S.Th, S.a[d], R(1), Vb[1], Thb, ab, dummy);
-        }
-        contract_rev<0, 0, 0>(S.Th, S.a[d], g.rho, gcb[d], Thb, ab, rhob);
-        R b[5], bb[5] = {R(0), R(0), R(0), R(0), R(0)};
+        // the slopes a_d recomputed rather than kept
+        R b[5], a[5], ab[5] = {R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
         for (int q = 0; q < 5; ++q) b[q] = gr[d][q] * ir;
+        micro_slope(g, K, b, a);
+        if (d == 0) {
+            if (VISC) contract_rev_split<1, 0, 0>(S.Tf, a, R(-1), Bb, Tfub, Thb, ab, dummy);
+            contract_rev<2, 0, 0>(S.Th, a, R(1), Fb[1], Thb, ab, dummy);
+            contract_rev<1, 0, 0>(S.Th, a, R(1), Vb[1], Thb, ab, dummy);
+        } else if (d == 1) {
+            if (VISC) contract_rev_split<0, 1, 0>(S.Tf, a, R(-1), Bb, Tfub, Thb, ab, dummy);
+            contract_rev<1, 1, 0>(S.Th, a, R(1), Fb[1], Thb, ab, dummy);
+            contract_rev<0, 1, 0>(S.Th, a, R(1), Vb[1], Thb, ab, dummy);
+        } else {
+            if (VISC) contract_rev_split<0, 0, 1>(S.Tf, a, R(-1), Bb, Tfub, Thb, ab, dummy);
+            contract_rev<1, 0, 1>(S.Th, a, R(1), Fb[1], Thb, ab, dummy);
+            contract_rev<0, 0, 1>(S.Th, a, R(1), Vb[1], Thb, ab, dummy);
+        }
+        contract_rev<0, 0, 0>(S.Th, a, g.rho, gcb[d], Thb, ab, rhob);
+        R bb[5] = {R(0), R(0), R(0), R(0), R(0)};
         micro_slope_rev(g, K, b, ab, gb, bb);
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             grb[d][q] += bb[q] * ir;
             irb += bb[q] * gr[d][q];
         }
+        sched_fence();
     }
     rhob -= irb * ir * ir;
-    psi_mom_rev<0, 0, 0>(S.Th, Vb[0], Thb);
-    psi_mom_rev<1, 0, 0>(S.Th, Fb[0], Thb);
-    if (VISC) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            Thb.v[k] += Tfb.v[k];
-            Thb.w[k] += Tfb.w[k];
-        }
-        Thb.xi2 += Tfb.xi2;
-        Thb.xi4 += Tfb.xi4;
-        gauss_moments_rev<7>(g.U, g.lam, S.Tf.u, Tfb.u, gb.U, gb.lam);
-    }
+    if (VISC) gauss_moments_rev<7>(g.U, g.lam, S.Tf.u, Tfub, gb.U, gb.lam);
     vw_tables_rev(g, K, S.Th, Thb, gb);
     recursion_rev<7>(g.U, g.lam, S.Th.u, Thb.u, gb.U, gb.lam);
     m0b += Thb.u[0];
@@ -757,6 +769,7 @@ GKS_HD void eq_reverse(const Params &p, const PointFwd<R> &P, const R gl[3][5], 
             E.gcb[d][q] = bb[q] * irc;
             ircb += bb[q] * gc[d][q];
         }
+        sched_fence();
     }
     E.gCb.rho -= ircb * irc * irc;
     vw_tables_rev(gC, K, TC, TCb, E.gCb);
