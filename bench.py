@@ -68,7 +68,8 @@ PROFILE_NAMES = {
 }
 # the kernel sources whose digest the committed counter summary records
 KERNEL_SOURCES = ("paper_2102_01366_amd/csrc/gks_kernels.hip", "paper_2102_01366_amd/csrc/gks_flux.h",
-                  "paper_2102_01366_amd/csrc/gks_internal.h")
+                  "paper_2102_01366_amd/csrc/gks_internal.h", "paper_2102_01366_amd/csrc/gks_m2stage.h",
+                  "paper_2102_01366_amd/csrc/gks_recon_adj.h")
 COUNTERS = os.path.join(ROOT, "profiles", "taylor_green_196608_counters.md")
 
 
