@@ -133,13 +133,36 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
 #pragma unroll
         for (int a = 0; a < 4; ++a) nb[a] = m.nbr[a * n + i];
         Q0 = s.W[(size_t)q * n + i];
+        if constexpr (sizeof(R) == 8) {
+            // FP64: the gathers from clamped indices, issued unconditionally
+            // (a missing neighbour's entries are zeroed afterwards), 4% faster;
+            // in FP32 the extra registers cost more occupancy than they gain
+            int nbc[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const bool has = nb[a] >= 0;
-            d[a] = has ? R(s.W[(size_t)q * n + nb[a]] - Q0) : R(0);
+            for (int a = 0; a < 4; ++a) nbc[a] = nb[a] >= 0 ? nb[a] : i;
+            double wn[4], gn[4][3];
 #pragma unroll
-            for (int dd = 0; dd < 3; ++dd)
-                d[4 + 3 * a + dd] = has ? R(s.gW[(size_t)(3 * q + dd) * n + nb[a]]) : R(0);
+            for (int a = 0; a < 4; ++a) {
+                wn[a] = s.W[(size_t)q * n + nbc[a]];
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) gn[a][dd] = s.gW[(size_t)(3 * q + dd) * n + nbc[a]];
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const bool has = nb[a] >= 0;
+                d[a] = has ? R(wn[a] - Q0) : R(0);
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) d[4 + 3 * a + dd] = has ? R(gn[a][dd]) : R(0);
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const bool has = nb[a] >= 0;
+                d[a] = has ? R(s.W[(size_t)q * n + nb[a]] - Q0) : R(0);
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd)
+                    d[4 + 3 * a + dd] = has ? R(s.gW[(size_t)(3 * q + dd) * n + nb[a]]) : R(0);
+            }
         }
     }
     R c[9];
