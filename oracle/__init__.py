@@ -37,15 +37,18 @@ class Config(ctypes.Structure):
                 ("prandtl", ctypes.c_double), ("eps_tau", ctypes.c_double),
                 ("c_tau", ctypes.c_double), ("eps_weno", ctypes.c_double),
                 ("lw2", ctypes.c_double * 3), ("lw1", ctypes.c_double * 2),
-                ("viscous", ctypes.c_int32), ("nonlinear", ctypes.c_int32), ("order", ctypes.c_int32)]
+                ("viscous", ctypes.c_int32), ("nonlinear", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("flux", ctypes.c_int32)]
 
 
 def make_config(gamma=1.4, mu=0.0, prandtl=1.0, viscous=False, nonlinear=True,
                 eps_tau=0.01, c_tau=1.0, eps_weno=1e-8, lw2=(100.0, 10.0, 1.0),
-                lw1=(10.0, 1.0), K=None, order=3) -> Config:
-    """Scheme parameters; linear weights are given as ratios and normalised."""
+                lw1=(10.0, 1.0), K=None, order=3, flux=0) -> Config:
+    """Scheme parameters; linear weights are given as ratios and normalised.
+    flux: 0 for eq. 2nd-flux, 1 for the smooth-flow form eq. 2nd-smooth-flux."""
     c = Config()
     c.order = order
+    c.flux = flux
     c.gamma = gamma
     c.K = (5.0 - 3.0 * gamma) / (gamma - 1.0) if K is None else K
     c.mu = mu

@@ -18,6 +18,10 @@
  *   - two-stage fourth-order time stepping and Gauss-theorem gradient update
  *     (Secs. 2.3 and 3).
  *
+ * The flux may also take the smooth-flow form of the distribution (eq.
+ * 2nd-smooth-flux): the equilibrium g^c, with the kinetically weighted W^c
+ * and slopes of eq. new-equ-part, and no kinetic part.
+ *
  * Walls (face_cell[2f+1] = -1) are slip walls (Sec. 4.4): cells next to them
  * use one-sided reconstructions (the own averaged gradient, and a linear
  * least-squares fit in step 2, where fewer than three neighbours remain) and
@@ -1051,6 +1055,7 @@ static void part_moments(const maxw_t *g, int half, double a[3][5], const double
  * point, in the local frame. */
 typedef struct {
     double rhoc, rhol, rhor, tau, taun;
+    int smooth; /* eq. 2nd-smooth-flux: the equilibrium part alone */
     parts_t c, l, r;
 } interface_t;
 
@@ -1103,7 +1108,10 @@ static int build_interface(const or_config *cf, const double Wl[5], double gl[3]
         I->tau = 0.0;
         I->taun = cf->eps_tau * dt + jump;
     }
-    if (I->tau > 0.0) {
+    /* eq. 2nd-smooth-flux keeps tau = mu / p (0 for Euler) and drops tau_n
+     * with the kinetic part */
+    I->smooth = cf->flux == 1;
+    if (I->tau > 0.0 && !I->smooth) {
         if (solve_time_slope(&ml, al, Al) || solve_time_slope(&mr, ar, Ar)) return -1;
     }
     /* heat-flux weight (u-U^c)(|u-U^c|^2 + xi^2)/2 about the interface velocity */
@@ -1123,8 +1131,13 @@ static int build_interface(const or_config *cf, const double Wl[5], double gl[3]
     I->rhol = ml.rho;
     I->rhor = mr.rho;
     part_moments(&mc, FULL, ac, Ac, &qw, &I->c);
-    part_moments(&ml, POS, al, Al, &qw, &I->l);
-    part_moments(&mr, NEG, ar, Ar, &qw, &I->r);
+    if (I->smooth) {
+        memset(&I->l, 0, sizeof(parts_t));
+        memset(&I->r, 0, sizeof(parts_t));
+    } else {
+        part_moments(&ml, POS, al, Al, &qw, &I->l);
+        part_moments(&mr, NEG, ar, Ar, &qw, &I->r);
+    }
     return 0;
 }
 
@@ -1132,15 +1145,25 @@ static int build_interface(const or_config *cf, const double Wl[5], double gl[3]
 static void integrated_flux(const or_config *cf, const interface_t *I, double delta, double F[5])
 {
     double tau = I->tau, tn = I->taun;
-    double e = exp(-delta / tn);
-    double E1 = tn * (1.0 - e);
-    double E2 = tn * tn * (1.0 - e) - tn * delta * e;
-    double c1 = delta - E1;
-    double c2 = E2 + tau * E1 - tau * delta;
-    double c3 = 0.5 * delta * delta - tau * delta + tau * E1;
-    double c4 = E1;
-    double c5 = -(tau * E1 + E2);
-    double c6 = -tau * E1;
+    double c1, c2, c3, c4, c5, c6;
+    if (I->smooth) {
+        /* eq. 2nd-smooth-flux: g^c - tau (a^c.u + A^c) g^c + t A^c g^c,
+         * integrated over [0, delta] */
+        c1 = delta;
+        c2 = -tau * delta;
+        c3 = 0.5 * delta * delta - tau * delta;
+        c4 = c5 = c6 = 0.0;
+    } else {
+        double e = exp(-delta / tn);
+        double E1 = tn * (1.0 - e);
+        double E2 = tn * tn * (1.0 - e) - tn * delta * e;
+        c1 = delta - E1;
+        c2 = E2 + tau * E1 - tau * delta;
+        c3 = 0.5 * delta * delta - tau * delta + tau * E1;
+        c4 = E1;
+        c5 = -(tau * E1 + E2);
+        c6 = -tau * E1;
+    }
     for (int q = 0; q < 5; ++q)
         F[q] = I->rhoc * (c1 * I->c.F[0][q] + c2 * I->c.F[1][q] + c3 * I->c.F[2][q]) +
                I->rhol * (c4 * I->l.F[0][q] + c5 * I->l.F[1][q] + c6 * I->l.F[2][q]) +
@@ -1156,7 +1179,15 @@ static void integrated_flux(const or_config *cf, const interface_t *I, double de
 /* the coefficients of eq. 2nd-flux at time t (un-integrated) */
 static void point_coeffs(const interface_t *I, double t, double d[6])
 {
-    double tau = I->tau, e = exp(-t / I->taun);
+    double tau = I->tau;
+    if (I->smooth) { /* eq. 2nd-smooth-flux */
+        d[0] = 1.0;
+        d[1] = -tau;
+        d[2] = t - tau;
+        d[3] = d[4] = d[5] = 0.0;
+        return;
+    }
+    double e = exp(-t / I->taun);
     d[0] = 1.0 - e;
     d[1] = (t + tau) * e - tau;
     d[2] = t - tau + tau * e;

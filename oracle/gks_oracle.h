@@ -35,6 +35,8 @@ typedef struct {
     int32_t nonlinear;/* 1: multi-resolution WENO weights; 0: R = P^2 (linear) */
     int32_t order;    /* 3: third-order (P^2, eq. final_weno_expression-3rd); 2: second-order
                          (P^1 and P^0 only, eq. final_weno_expression-2nd) */
+    int32_t flux;     /* 0: the full distribution of eq. 2nd-flux; 1: its smooth-flow form,
+                         eq. 2nd-smooth-flux */
 } or_config;
 
 typedef struct or_ctx or_ctx;

@@ -274,3 +274,101 @@ def test_collision_limit_is_euler_flux_of_interface_state(oracle_lib):
         Wc = _half_flux(Wl, +1)[1] + _half_flux(Wr, -1)[1]
         np.testing.assert_allclose(out[2], Wc, rtol=1e-12)
         np.testing.assert_allclose(out[0] / dt, euler_flux(Wc, e1), rtol=1e-8, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# The smooth-flow form of the distribution (eq. 2nd-smooth-flux):
+# f = g^c - tau (a^c.u + A^c) g^c + t A^c g^c, with W^c and its slopes from
+# the kinetic weighting of eq. new-equ-part and tau = mu / p^c (0 for Euler).
+# Its moments are the Euler flux of W^c, plus the Chapman-Enskog
+# Navier-Stokes flux of (W^c, grad W^c), plus t times dF_Euler/dt of W^c.
+# ---------------------------------------------------------------------------
+
+def _half_state_derivative(W, G, sign, h=1e-5):
+    """d/de of the kinetically weighted half-line state along W + e G, by
+    central differences of the quadrature (the slopes of eq. new-equ-part)."""
+    return (_half_flux(W + h * G, sign)[1] - _half_flux(W - h * G, sign)[1]) / (2 * h)
+
+
+def _smooth_reference(Wc, Gc, n, mu, prandtl, delta):
+    FE = euler_flux(Wc, n)
+    Wt = euler_time_derivative(Wc, Gc)
+    FNS, qn = ns_flux(Wc, Gc, n, mu)
+    ref = delta * (FE + FNS) + 0.5 * delta ** 2 * dflux(Wc, n, Wt)
+    if prandtl != 1.0:
+        rho = Wc[0]
+        u = Wc[1:4] / rho
+        p = (GAMMA - 1) * (Wc[4] - 0.5 * rho * u @ u)
+        ut = (Wt[1:4] - u * Wt[0]) / rho
+        ref[4] += (1 / prandtl - 1) * (delta * qn + 0.5 * delta ** 2 * (K + 5) / 2 * p * (ut @ n))
+    return ref, Wt
+
+
+@pytest.mark.parametrize("viscous,prandtl", [(False, 1.0), (True, 1.0), (True, 0.72)])
+def test_smooth_flux_continuous_linear_data(oracle_lib, viscous, prandtl):
+    """Continuous data: the same closed form as the full distribution (which
+    collapses to the smooth one when g^l = g^r = g^c)."""
+    rng = np.random.default_rng(12)
+    mu = 0.03
+    cfg = oracle_lib.make_config(viscous=viscous, mu=mu, prandtl=prandtl, flux=1)
+    full = oracle_lib.make_config(viscous=viscous, mu=mu, prandtl=prandtl)
+    for trial in range(5):
+        n = random_normal(rng) if trial < 4 else np.array([-1.0, 0.0, 0.0])
+        W, G = _continuous_case(rng)
+        gW = G.reshape(15)
+        dt = 0.02
+        out = oracle_lib.point_flux(cfg, n, W, gW, W, gW, dt)
+        for k, delta in enumerate((dt, 0.5 * dt)):
+            ref, Wt = _smooth_reference(W, G, n, mu if viscous else 0.0, prandtl, delta)
+            np.testing.assert_allclose(out[k], ref, rtol=0, atol=1e-12 * delta)
+        np.testing.assert_allclose(out[2], W, rtol=1e-13)
+        np.testing.assert_allclose(out[3], W + dt * Wt, rtol=1e-12, atol=1e-14)
+        # identical sides: tau_n = tau (viscous) or no slopes of the kinetic
+        # part survive (Euler), so eq. 2nd-flux reduces to eq. 2nd-smooth-flux
+        np.testing.assert_allclose(out, oracle_lib.point_flux(full, n, W, gW, W, gW, dt),
+                                   rtol=0, atol=1e-13 * np.abs(out).max())
+
+
+@pytest.mark.parametrize("viscous", [False, True])
+def test_smooth_flux_jump_without_slopes(oracle_lib, viscous):
+    """Discontinuous constant states: the Euler flux of the kinetically
+    weighted W^c and the state W^c at all times (no slopes, so no A^c)."""
+    rng = np.random.default_rng(13)
+    cfg = oracle_lib.make_config(viscous=viscous, mu=0.02, flux=1)
+    e1 = np.array([1.0, 0, 0])
+    for _ in range(3):
+        Wl, Wr = random_state(rng), random_state(rng)
+        dt = 0.01
+        out = oracle_lib.point_flux(cfg, e1, Wl, np.zeros(15), Wr, np.zeros(15), dt)
+        Wc = _half_flux(Wl, +1)[1] + _half_flux(Wr, -1)[1]
+        np.testing.assert_allclose(out[0], dt * euler_flux(Wc, e1), rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(out[1], 0.5 * dt * euler_flux(Wc, e1), rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(out[2], Wc, rtol=1e-12)
+        np.testing.assert_allclose(out[3], Wc, rtol=1e-12)
+
+
+@pytest.mark.parametrize("viscous,prandtl", [(False, 1.0), (True, 1.0), (True, 0.72)])
+def test_smooth_flux_jump_with_slopes(oracle_lib, viscous, prandtl):
+    """Discontinuous states and gradients: the closed form at (W^c, grad W^c),
+    W^c and its slopes weighted kinetically by half-line quadrature."""
+    rng = np.random.default_rng(14)
+    mu = 0.02
+    cfg = oracle_lib.make_config(viscous=viscous, mu=mu, prandtl=prandtl, flux=1)
+    e1 = np.array([1.0, 0, 0])
+    for _ in range(2):
+        Wl, Wr = random_state(rng), random_state(rng)
+        Gl, Gr = 0.4 * rng.normal(size=(5, 3)), 0.4 * rng.normal(size=(5, 3))
+        dt = 0.01
+        out = oracle_lib.point_flux(cfg, e1, Wl, Gl.reshape(15), Wr, Gr.reshape(15), dt)
+        Wc = _half_flux(Wl, +1)[1] + _half_flux(Wr, -1)[1]
+        Gc = np.stack([_half_state_derivative(Wl, Gl[:, d], +1) + _half_state_derivative(Wr, Gr[:, d], -1)
+                       for d in range(3)], axis=1)
+        rho, u = Wc[0], Wc[1:4] / Wc[0]
+        pc = (GAMMA - 1) * (Wc[4] - 0.5 * rho * u @ u)
+        # tau = mu / p^c, so the Navier-Stokes viscosity is tau p^c = mu
+        for k, delta in enumerate((dt, 0.5 * dt)):
+            ref, Wt = _smooth_reference(Wc, Gc, e1, mu if viscous else 0.0, prandtl, delta)
+            np.testing.assert_allclose(out[k], ref, rtol=0, atol=1e-8 * delta * np.abs(ref / delta).max())
+        np.testing.assert_allclose(out[2], Wc, rtol=1e-12)
+        np.testing.assert_allclose(out[3], Wc + dt * Wt, rtol=1e-8)
+        assert pc > 0

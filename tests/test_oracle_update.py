@@ -6,6 +6,8 @@
   mesh (each face flux enters its two cells with opposite signs).
 * The time step of eq. time-step against closed-form tetrahedron geometry.
 * Stage sequencing of the two-stage fourth-order step.
+* The same with the smooth-flow flux of eq. 2nd-smooth-flux where it applies
+  (free stream, conservation, convergence).
 * Third-order convergence of the density on the smooth sine-wave advection
   against exact cell averages of the translated profile (the paper's Tables
   1-2 show order ~3; magnitudes depend on the mesh and are not compared).
@@ -25,10 +27,10 @@ def _uniform(mesh, rho=1.2, u=(0.3, -0.2, 0.5), p=0.9, gamma=1.4):
     return W, np.zeros((15, mesh.n_cell))
 
 
-@pytest.mark.parametrize("viscous", [False, True])
-def test_free_stream_preservation(oracle_lib, viscous):
+@pytest.mark.parametrize("viscous,flux", [(False, 0), (True, 0), (True, 1)])
+def test_free_stream_preservation(oracle_lib, viscous, flux):
     m = I.kuhn_cube_mesh(4, 1.0, 0.15, 21, True)
-    orc = oracle_lib.Oracle(m, oracle_lib.make_config(viscous=viscous, mu=0.01,
+    orc = oracle_lib.Oracle(m, oracle_lib.make_config(viscous=viscous, mu=0.01, flux=flux,
                                                       prandtl=0.72 if viscous else 1))
     W0, gW0 = _uniform(m)
     W, gW = W0, gW0
@@ -42,9 +44,10 @@ def test_free_stream_preservation(oracle_lib, viscous):
     assert np.abs(gW).max() < 1e-13 * scale
 
 
-def test_exact_conservation(oracle_lib):
+@pytest.mark.parametrize("flux", [0, 1])
+def test_exact_conservation(oracle_lib, flux):
     m = I.kuhn_cube_mesh(4, 2 * np.pi, 0.1, 22, True)
-    orc = oracle_lib.Oracle(m, oracle_lib.make_config(viscous=True, mu=0.05, prandtl=0.72))
+    orc = oracle_lib.Oracle(m, oracle_lib.make_config(viscous=True, mu=0.05, prandtl=0.72, flux=flux))
     W, gW = I.cell_averages(m, I.taylor_green_field(mach=0.3))
     rng = np.random.default_rng(0)
     W = W * (1 + 0.02 * rng.standard_normal(W.shape))
@@ -92,9 +95,10 @@ def test_stage_sequence(oracle_lib):
     np.testing.assert_array_equal(gW2, gW3)
 
 
-@pytest.mark.parametrize("nonlinear", [False, True])
-def test_third_order_convergence(oracle_lib, nonlinear):
-    cfg = oracle_lib.make_config(nonlinear=nonlinear)
+@pytest.mark.parametrize("nonlinear,flux", [(False, 0), (True, 0), (True, 1)],
+                         ids=["linear", "weno", "weno_smooth_flux"])
+def test_third_order_convergence(oracle_lib, nonlinear, flux):
+    cfg = oracle_lib.make_config(nonlinear=nonlinear, flux=flux)
     T = 0.02
     errs, gerrs = [], []
     for N in (4, 8, 16):
