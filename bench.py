@@ -61,14 +61,17 @@ UNIT = {"slopes": "cell", "reconstruct": "cell", "flux_stage1": "face", "flux_st
 PROFILE_NAMES = {
     "slopes": ("gks::slopes_kernel<double>", "gks::slopes_kernel<float>"),
     "reconstruct": ("gks::reconstruct_kernel<double>", "gks::reconstruct_kernel<float>"),
-    "flux_stage1": ("gks::flux_kernel<double, 0, true, true, false>", "gks::flux_kernel<float, 0, true, true, false>"),
-    "flux_stage2": ("gks::flux_kernel<double, 1, true, true, false>", "gks::flux_kernel<float, 1, true, true, false>"),
+    "flux_stage1": ("gks::flux_kernel<double, 0, true, true, false, false>",
+                    "gks::flux_kernel<float, 0, true, true, false, false>"),
+    "flux_stage2": ("gks::flux_kernel<double, 1, true, true, false, false>",
+                    "gks::flux_kernel<float, 1, true, true, false, false>"),
     "update_stage1": ("gks::update_kernel<double, 1>", "gks::update_kernel<float, 1>"),
     "update_stage2": ("gks::update_kernel<double, 2>", "gks::update_kernel<float, 2>"),
     "dt": ("gks::dt_pass1", None),  # one kernel serves both forms
 }
 # the kernel sources whose digest the committed counter summary records
 KERNEL_SOURCES = ("paper_2102_01366_amd/csrc/gks_kernels.hip", "paper_2102_01366_amd/csrc/gks_flux.h",
+                  "paper_2102_01366_amd/csrc/gks_flux_kernel.h", "paper_2102_01366_amd/csrc/gks_device.h",
                   "paper_2102_01366_amd/csrc/gks_internal.h", "paper_2102_01366_amd/csrc/gks_m2stage.h",
                   "paper_2102_01366_amd/csrc/gks_recon_adj.h")
 COUNTERS = os.path.join(ROOT, "profiles", "taylor_green_196608_counters.md")

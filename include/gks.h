@@ -60,6 +60,11 @@ typedef int32_t gks_status;
 #define GKS_FACE_PERIODIC 1 /* neighbour lies across a periodic seam (face_shift != 0) */
 #define GKS_FACE_SLIP 2     /* inviscid wall: mirror ghost state (Sec. 4.4) */
 
+/* distributions of the gas-kinetic flux */
+#define GKS_FLUX_FULL 0   /* eq. 2nd-flux: equilibrium and kinetic parts, collision times tau, tau_n */
+#define GKS_FLUX_SMOOTH 1 /* eq. 2nd-smooth-flux: the equilibrium part alone, g^c - tau (a^c.u + A^c) g^c
+                             + t A^c g^c, with W^c and its slopes of eq. new-equ-part; for smooth flows */
+
 /* precision forms */
 #define GKS_FP64 0
 #define GKS_FP32_BULK 1 /* reconstruction and flux arithmetic in FP32, state in FP64 */
@@ -78,10 +83,12 @@ typedef struct {
     int32_t precision;/* GKS_FP64 or GKS_FP32_BULK */
     int32_t order;    /* 3: third-order scheme (default); 2: second-order scheme, R from P^1 and
                          P^0 only (eq. final_weno_expression-2nd) */
+    int32_t flux;     /* GKS_FLUX_FULL (default) or GKS_FLUX_SMOOTH */
 } gks_config;
 
 /* Fill cfg with the paper's defaults: gamma 1.4, Euler, Pr 1, eps_tau 0.01,
- * C 1, eps_weno 1e-8, weights 100:10:1 and 10:1, nonlinear, FP64. */
+ * C 1, eps_weno 1e-8, weights 100:10:1 and 10:1, nonlinear, FP64, third order,
+ * full flux distribution. */
 void gks_default_config(gks_config *cfg);
 
 /* Tetrahedral mesh, host arrays.  face_vert lists the face's vertices as seen

@@ -31,6 +31,8 @@ GKS_E_NOMEM = -7
 
 GKS_FP64 = 0
 GKS_FP32_BULK = 1
+GKS_FLUX_FULL = 0    # eq. 2nd-flux
+GKS_FLUX_SMOOTH = 1  # eq. 2nd-smooth-flux
 
 # names of every function the C interface declares (include/gks.h)
 EXPORTS = ("gks_default_config", "gks_create", "gks_destroy", "gks_set_stream",
@@ -59,7 +61,8 @@ class Config(ctypes.Structure):
                 ("c_tau", ctypes.c_double), ("eps_weno", ctypes.c_double),
                 ("lw2", ctypes.c_double * 3), ("lw1", ctypes.c_double * 2),
                 ("viscous", ctypes.c_int32), ("nonlinear", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("order", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("flux", ctypes.c_int32)]
 
 
 class _Mesh(ctypes.Structure):
@@ -129,7 +132,10 @@ def default_config(**kw) -> Config:
     L = load_library()
     c = Config()
     L.gks_default_config(ctypes.byref(c))
+    names = {f[0] for f in Config._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown configuration field {k!r}")
         if k in ("lw2", "lw1"):
             arr = getattr(c, k)
             for i, x in enumerate(v):

@@ -1,5 +1,8 @@
 """Build libgks.so (HIP, gfx950) in-tree with hipcc.
 
+Each translation unit is compiled to an object under _build/ in parallel,
+then the objects are linked into libgks.so next to this file.
+
 Usage: python -m paper_2102_01366_amd.build [--verbose]
 """
 from __future__ import annotations
@@ -7,33 +10,48 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
+OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgks.so")
-SOURCES = [os.path.join(CSRC, "gks_kernels.hip"), os.path.join(CSRC, "gks_adjoint.hip"), os.path.join(CSRC, "gks_api.cpp"),
-           os.path.join(CSRC, "gks_opcount.cpp"), os.path.join(CSRC, "gks_check.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in (
+    "gks_adjoint_flux_f64.hip", "gks_adjoint_flux_f32.hip", "gks_flux_f64.hip", "gks_flux_f32.hip",
+    "gks_adjoint.hip", "gks_kernels.hip", "gks_check.cpp", "gks_api.cpp", "gks_opcount.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for all device code.
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-I" + os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *extra, "-o", tmp, *SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
-    out = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
-                    if "packed-fp32-ops" not in l)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({r.returncode}):\n{out}")
-    if verbose and out.strip():
-        print(out)
+    out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
+    return r.returncode, out
+
+
+def build(verbose: bool = False, extra=(), jobs: int | None = None) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    objs = [os.path.join(OBJ, os.path.basename(s) + ".o") for s in SOURCES]
+    cmds = [[HIPCC, *FLAGS, *extra, "-c", s, "-o", o] for s, o in zip(SOURCES, objs)]
+    jobs = jobs or min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(_run, cmds))
+    for cmd, (rc, out) in zip(cmds, results):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        if rc != 0:
+            raise RuntimeError(f"hipcc failed ({rc}) on {cmd[-3]}:\n{out}")
+        if verbose and out.strip():
+            print(out)
+    tmp = LIB + ".tmp"
+    rc, out = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
+    if rc != 0:
+        raise RuntimeError(f"link failed ({rc}):\n{out}")
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,0 +1,7 @@
+// Adjoint of the flux stage instantiated for the float bulk type.
+#include "gks_flux_vjp.h"
+
+namespace gks {
+template hipError_t launch_flux_vjp_t<float>(const DevMesh &, const AdjFlux &, const Params &, double, int,
+                                          hipStream_t);
+}  // namespace gks

@@ -259,6 +259,7 @@ bool config_ok(const gks_config *c, std::string &why)
     if (c->nonlinear != 0 && c->nonlinear != 1) { why = "nonlinear must be 0 or 1"; return false; }
     if (c->precision != GKS_FP64 && c->precision != GKS_FP32_BULK) { why = "unknown precision"; return false; }
     if (c->order != 2 && c->order != 3) { why = "order must be 2 or 3"; return false; }
+    if (c->flux != GKS_FLUX_FULL && c->flux != GKS_FLUX_SMOOTH) { why = "unknown flux"; return false; }
     return true;
 }
 
@@ -313,6 +314,7 @@ void gks_default_config(gks_config *cfg)
     cfg->nonlinear = 1;
     cfg->precision = GKS_FP64;
     cfg->order = 3;
+    cfg->flux = GKS_FLUX_FULL;
 }
 
 gks_status gks_create(const gks_config *cfg, gks_ctx **out)
@@ -948,7 +950,7 @@ Layout make_adj_layout(size_t nc, size_t nf, size_t bs)
         5 * nf * bs, 5 * nf * bs, 5 * nf * bs, 5 * nf * bs,
         nc * sizeof(int), nc * sizeof(int), 64,
         100 * nf * 8, d5, d15, 4 * d5, 4 * d15, 4 * d15, 4 * d5, d5,
-        (8 + 5 * (size_t)gks::kRedBlocks) * 8, 32 * 3 * nf * 8, 35 * 6 * nf * 8};
+        (8 + 5 * (size_t)gks::kRedBlocks) * 8, gks::kEqRec * 3 * nf * 8, gks::kSideRec * 6 * nf * 8};
     Layout L;
     size_t o = 0;
     for (int k = 0; k < A_COUNT; ++k) {

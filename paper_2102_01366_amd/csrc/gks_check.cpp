@@ -9,6 +9,7 @@
 #include "gks_recon_adj.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace {
 
@@ -50,7 +51,7 @@ struct ArrCoef {
     R operator()(int q, int k) const { return c[10 * q + k]; }
 };
 
-template <bool VISC, bool PRFIX>
+template <bool VISC, bool PRFIX, bool SMOOTH>
 void point_check(const gks::Params &p, double dt, const double x[40], const double v[40], const double yb[20],
                  double y[20], double jv[20], double xb[40])
 {
@@ -64,7 +65,7 @@ void point_check(const gks::Params &p, double dt, const double x[40], const doub
         }
     }
     Dual Fo[2][5], Wo[2][5];
-    gks::gks_point<Dual, VISC, PRFIX>(p, Dual(dt), wl, gl, wr, gr, Fo, Wo);
+    gks::gks_point<Dual, VISC, PRFIX, SMOOTH>(p, Dual(dt), wl, gl, wr, gr, Fo, Wo);
     for (int k = 0; k < 2; ++k)
         for (int q = 0; q < 5; ++q) {
             y[5 * k + q] = Fo[k][q].v;
@@ -86,7 +87,7 @@ void point_check(const gks::Params &p, double dt, const double x[40], const doub
         }
     }
     double wlb[5] = {0}, glb[3][5] = {{0}}, wrb[5] = {0}, grb[3][5] = {{0}};
-    gks::gks_point_vjp<double, VISC, PRFIX>(p, dt, dwl, dgl, dwr, dgr, Fob, Wob, wlb, glb, wrb, grb);
+    gks::gks_point_vjp<double, VISC, PRFIX, SMOOTH>(p, dt, dwl, dgl, dwr, dgr, Fob, Wob, wlb, glb, wrb, grb);
     for (int q = 0; q < 5; ++q) {
         xb[q] = wlb[q];
         xb[20 + q] = wrb[q];
@@ -97,7 +98,7 @@ void point_check(const gks::Params &p, double dt, const double x[40], const doub
     }
 }
 
-template <bool VISC, bool PRFIX>
+template <bool VISC, bool PRFIX, bool SMOOTH>
 void face_check(const gks::Params &p, double dt, const double geo[10], const double coef[100],
                 const double v[100], const double ab[20], double acc[20], double jv[20], double cb[100])
 {
@@ -109,8 +110,8 @@ void face_check(const gks::Params &p, double dt, const double geo[10], const dou
     }
     for (int k = 0; k < 100; ++k) cd[k] = Dual(coef[k], v[k]);
     Dual t[4][5];
-    gks::gauss_point_terms<Dual, VISC, PRFIX>(p, Dual(dt), nrm, Dual(geo[3]), r, dv, ArrCoef<Dual>{cd},
-                                              ArrCoef<Dual>{cd + 50}, t);
+    gks::gauss_point_terms<Dual, VISC, PRFIX, ArrCoef<Dual>, ArrCoef<Dual>, SMOOTH>(
+        p, Dual(dt), nrm, Dual(geo[3]), r, dv, ArrCoef<Dual>{cd}, ArrCoef<Dual>{cd + 50}, t);
     for (int a = 0; a < 4; ++a)
         for (int q = 0; q < 5; ++q) {
             acc[5 * a + q] = t[a][q].v;
@@ -124,13 +125,26 @@ void face_check(const gks::Params &p, double dt, const double geo[10], const dou
     }
     for (int a = 0; a < 4; ++a)
         for (int q = 0; q < 5; ++q) accb[a][q] = ab[5 * a + q];
-    gks::gauss_point_terms_vjp<double, VISC, PRFIX>(p, dt, nn, geo[3], rr, dd, ArrCoef<double>{coef},
-                                                    ArrCoef<double>{coef + 50}, accb, cbl, cbr);
+    gks::gauss_point_terms_vjp<double, VISC, PRFIX, ArrCoef<double>, ArrCoef<double>, SMOOTH>(
+        p, dt, nn, geo[3], rr, dd, ArrCoef<double>{coef}, ArrCoef<double>{coef + 50}, accb, cbl, cbr);
     for (int q = 0; q < 5; ++q)
         for (int k = 0; k < 10; ++k) {
             cb[10 * q + k] = cbl[q][k];
             cb[50 + 10 * q + k] = cbr[q][k];
         }
+}
+
+// calls f(VISC, PRFIX, SMOOTH) with the flags as std::integral_constant values
+template <bool SMOOTH, typename F>
+void dispatch_visc_prfix(bool visc, bool prfix, F &&f)
+{
+    using T = std::true_type;
+    using N = std::false_type;
+    using S = std::integral_constant<bool, SMOOTH>;
+    if (visc && prfix) f(T{}, T{}, S{});
+    else if (visc) f(T{}, N{}, S{});
+    else if (prfix) f(N{}, T{}, S{});
+    else f(N{}, N{}, S{});
 }
 
 }  // namespace
@@ -142,10 +156,14 @@ extern "C" gks_status gks_flux_point_check(const gks_config *cfg, double dt, con
     if (!cfg || !x || !v || !ybar || !y || !jv || !xbar || !(dt > 0.0)) return GKS_E_INVAL;
     const gks::Params p = gks::params_from_config(cfg);
     const bool visc = p.viscous != 0, prfix = p.prandtl != 1.0;
-    if (visc && prfix) point_check<true, true>(p, dt, x, v, ybar, y, jv, xbar);
-    else if (visc) point_check<true, false>(p, dt, x, v, ybar, y, jv, xbar);
-    else if (prfix) point_check<false, true>(p, dt, x, v, ybar, y, jv, xbar);
-    else point_check<false, false>(p, dt, x, v, ybar, y, jv, xbar);
+    if (p.flux == gks::FLUX_KIND_SMOOTH)
+        dispatch_visc_prfix<true>(visc, prfix, [&](auto v_, auto f_, auto s_) {
+            point_check<decltype(v_)::value, decltype(f_)::value, decltype(s_)::value>(p, dt, x, v, ybar, y, jv, xbar);
+        });
+    else
+        dispatch_visc_prfix<false>(visc, prfix, [&](auto v_, auto f_, auto s_) {
+            point_check<decltype(v_)::value, decltype(f_)::value, decltype(s_)::value>(p, dt, x, v, ybar, y, jv, xbar);
+        });
     return GKS_OK;
 }
 
@@ -157,10 +175,14 @@ extern "C" gks_status gks_flux_face_check(const gks_config *cfg, double dt, cons
     if (!cfg || !geo || !coef || !v || !accbar || !acc || !jv || !coefbar || !(dt > 0.0)) return GKS_E_INVAL;
     const gks::Params p = gks::params_from_config(cfg);
     const bool visc = p.viscous != 0, prfix = p.prandtl != 1.0;
-    if (visc && prfix) face_check<true, true>(p, dt, geo, coef, v, accbar, acc, jv, coefbar);
-    else if (visc) face_check<true, false>(p, dt, geo, coef, v, accbar, acc, jv, coefbar);
-    else if (prfix) face_check<false, true>(p, dt, geo, coef, v, accbar, acc, jv, coefbar);
-    else face_check<false, false>(p, dt, geo, coef, v, accbar, acc, jv, coefbar);
+    auto run = [&](auto v_, auto f_, auto s_) {
+        face_check<decltype(v_)::value, decltype(f_)::value, decltype(s_)::value>(p, dt, geo, coef, v, accbar, acc,
+                                                                                  jv, coefbar);
+    };
+    if (p.flux == gks::FLUX_KIND_SMOOTH)
+        dispatch_visc_prfix<true>(visc, prfix, run);
+    else
+        dispatch_visc_prfix<false>(visc, prfix, run);
     return GKS_OK;
 }
 

@@ -215,6 +215,28 @@ GKS_HD void time_coefficients(R tau, R taun, R dt, TimeCoef<R> &tc)
     }
 }
 
+// The coefficients of eq. 2nd-smooth-flux in the same slots: the
+// equilibrium part 1, -tau, t - tau (the limit tau_n -> 0 of eq. 2nd-flux
+// with tau kept) and no kinetic part.  At t = 0 the equilibrium part is
+// (1, -tau, -tau).
+template <typename R>
+GKS_HD void time_coefficients_smooth(R tau, R dt, TimeCoef<R> &tc)
+{
+    tc.tau = tau;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const R del = k == 0 ? dt : R(0.5) * dt;
+        tc.cF[k][0] = del;
+        tc.cF[k][1] = -tau * del;
+        tc.cF[k][2] = R(0.5) * del * del - tau * del;
+        tc.cF[k][3] = tc.cF[k][4] = tc.cF[k][5] = R(0);
+    }
+    tc.cW[0] = R(1);
+    tc.cW[1] = -tau;
+    tc.cW[2] = dt - tau;
+    tc.cW[3] = tc.cW[4] = tc.cW[5] = R(0);
+}
+
 // Adds the part a, b, c of eq. 2nd-flux with moment vectors F_j = <u psi Y_j>,
 // V_j = <psi Y_j> (Y_0 = 1, Y_1 = slopes term, Y_2 = time-slope term) to the
 // time integrals Fo, the point values Wo (t = 0, dt), and, with the Prandtl
@@ -241,8 +263,9 @@ GKS_HD void add_part(const Params &p, R rho, const R *cF0, const R *cF1, const R
 
 // Kinetic part of one side (u > 0 for the left state, u < 0 for the right),
 // given its half-line seeds <1>, <u>: the slopes' contribution to the
-// interface gradients gc, and the side's terms of eq. 2nd-flux.
-template <typename R, bool VISC, bool PRFIX>
+// interface gradients gc, and the side's terms of eq. 2nd-flux (none with
+// the smooth-flow distribution, SMOOTH).
+template <typename R, bool VISC, bool PRFIX, bool SMOOTH = false>
 GKS_HD void side_terms(const Params &p, const Prim<R> &g, R m0, R m1, const R gr[3][5],
                        const TimeCoef<R> &tc, const R Uc[3], R gc[3][5], R Fo[2][5], R Wo[2][5])
 {
@@ -256,6 +279,18 @@ GKS_HD void side_terms(const Params &p, const Prim<R> &g, R m0, R m1, const R gr
         for (int k = 0; k + 2 < 7; ++k) Th.u[k + 2] = g.U * Th.u[k + 1] + R(k + 1) * h * Th.u[k];
     }
     vw_tables(g, K, Th);
+    if constexpr (SMOOTH) {
+        const R ir = R(1) / g.rho;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            R b[5], a[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) b[q] = gr[d][q] * ir;
+            micro_slope(g, K, b, a);
+            contract<0, 0, 0>(Th, a, g.rho, gc[d]);
+        }
+        return;
+    }
     R F[3][5], V[3][5];
     psi_mom<1, 0, 0>(Th, F[0]);
     psi_mom<0, 0, 0>(Th, V[0]);
@@ -308,10 +343,11 @@ GKS_HD void side_terms(const Params &p, const Prim<R> &g, R m0, R m1, const R gr
     add_part<R, PRFIX>(p, g.rho, tc.cF[0] + 3, tc.cF[1] + 3, cW0, tc.cW + 3, F, V, Uc, Fo, Wo);
 }
 
-// Time-dependent distribution of eq. 2nd-flux at one interface point, face
-// frame.  Outputs: Fo[0] = F(dt), Fo[1] = F(dt/2) (time integrals of the
-// flux), Wo[0] = W(0), Wo[1] = W(dt).
-template <typename R, bool VISC, bool PRFIX>
+// Time-dependent distribution of eq. 2nd-flux (SMOOTH: of eq.
+// 2nd-smooth-flux) at one interface point, face frame.  Outputs: Fo[0] =
+// F(dt), Fo[1] = F(dt/2) (time integrals of the flux), Wo[0] = W(0), Wo[1] =
+// W(dt).
+template <typename R, bool VISC, bool PRFIX, bool SMOOTH = false>
 GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], const R wr[5],
                       const R gr[3][5], R Fo[2][5], R Wo[2][5])
 {
@@ -344,17 +380,21 @@ GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], co
     const R Uc[3] = {gC.U, gC.V, gC.W};
     // collision times (Sec. 2.2)
     const R pl = gL.rho * R(0.5) / gL.lam, pr = gR.rho * R(0.5) / gR.lam, pc = gC.rho * R(0.5) / gC.lam;
-    const R jump = R(p.c_tau) * fabs((pl - pr) / (pl + pr)) * dt;
-    R tau, taun;
-    if (VISC) {
-        tau = R(p.mu) / pc;
-        taun = tau + jump;
-    } else {
-        tau = R(0);
-        taun = R(p.eps_tau) * dt + jump;
-    }
     TimeCoef<R> tc;
-    time_coefficients<R, VISC>(tau, taun, dt, tc);
+    if constexpr (SMOOTH) {
+        time_coefficients_smooth<R>(VISC ? R(p.mu) / pc : R(0), dt, tc);
+    } else {
+        const R jump = R(p.c_tau) * fabs((pl - pr) / (pl + pr)) * dt;
+        R tau, taun;
+        if (VISC) {
+            tau = R(p.mu) / pc;
+            taun = tau + jump;
+        } else {
+            tau = R(0);
+            taun = R(p.eps_tau) * dt + jump;
+        }
+        time_coefficients<R, VISC>(tau, taun, dt, tc);
+    }
 #pragma unroll
     for (int k = 0; k < 2; ++k)
 #pragma unroll
@@ -364,8 +404,8 @@ GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], co
     for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int q = 0; q < 5; ++q) gc[d][q] = R(0);
-    side_terms<R, VISC, PRFIX>(p, gL, l0, l1, gl, tc, Uc, gc, Fo, Wo);
-    side_terms<R, VISC, PRFIX>(p, gR, r0, r1, gr, tc, Uc, gc, Fo, Wo);
+    side_terms<R, VISC, PRFIX, SMOOTH>(p, gL, l0, l1, gl, tc, Uc, gc, Fo, Wo);
+    side_terms<R, VISC, PRFIX, SMOOTH>(p, gR, r0, r1, gr, tc, Uc, gc, Fo, Wo);
     // equilibrium part: g^c with slopes a^c (from g^c_x) and A^c
     Tab<R> TC;
     gauss_moments<7>(gC.U, gC.lam, TC.u);
@@ -401,7 +441,7 @@ GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], co
     }
     psi_mom<1, 0, 0>(TC, F[0]);
     psi_mom<0, 0, 0>(TC, V[0]);
-    const R cW0[3] = {R(0), R(0), R(0)};
+    const R cW0[3] = {SMOOTH ? R(1) : R(0), SMOOTH ? -tc.tau : R(0), SMOOTH ? -tc.tau : R(0)};
     add_part<R, PRFIX>(p, gC.rho, tc.cF[0], tc.cF[1], cW0, tc.cW, F, V, Uc, Fo, Wo);
 }
 
@@ -504,7 +544,7 @@ GKS_HD void slip_ghost(const R w[5], const R g[3][5], R wg[5], R gg[3][5])
 // the owner centroid; dv: owner centroid minus the neighbour's (translated).
 // On a wall face (no neighbour; cr is not evaluated) the right state is the
 // slip-wall ghost of the left one.
-template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR>
+template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR, bool SMOOTH = false>
 GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, const R r[3], const R dv[3],
                               const CoefL &cl, const CoefR &cr, R acc[4][5], bool wall = false)
 {
@@ -521,7 +561,7 @@ GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, con
     else
         eval_local(cr, rr, T, wr, gr);
     R Fo[2][5], Wo[2][5];
-    gks_point<R, VISC, PRFIX>(p, dt, wl, gl, wr, gr, Fo, Wo);
+    gks_point<R, VISC, PRFIX, SMOOTH>(p, dt, wl, gl, wr, gr, Fo, Wo);
     R F1[5], Fh[5], W0[5], W1[5];
     to_global(T, Fo[0], F1);
     to_global(T, Fo[1], Fh);
@@ -538,7 +578,7 @@ GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, con
 }
 
 // All terms of one face: the sum over its three Gauss points, in order.
-template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR>
+template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR, bool SMOOTH = false>
 GKS_HD void face_terms(const Params &p, R dt, const R nrm[3], R area, const R rl[3][3], const R dv[3],
                        const CoefL &cl, const CoefR &cr, R acc[4][5], bool wall = false)
 {
@@ -548,7 +588,7 @@ GKS_HD void face_terms(const Params &p, R dt, const R nrm[3], R area, const R rl
         for (int q = 0; q < 5; ++q) acc[a][q] = R(0);
     for (int k = 0; k < 3; ++k) {
         R t[4][5];
-        gauss_point_terms<R, VISC, PRFIX>(p, dt, nrm, area, rl[k], dv, cl, cr, t, wall);
+        gauss_point_terms<R, VISC, PRFIX, CoefL, CoefR, SMOOTH>(p, dt, nrm, area, rl[k], dv, cl, cr, t, wall);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll

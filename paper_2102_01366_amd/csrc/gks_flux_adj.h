@@ -447,7 +447,8 @@ struct SideFwd {
 
 // The direction-d contractions of side_terms: F[1] += <u u_d (a.psi) psi>,
 // V[1] += <u_d (a.psi) psi>, B -= <u_d (a.psi) psi> over the full line.
-template <typename R, bool VISC>
+// SMOOTH (eq. 2nd-smooth-flux): only the tables and the share of g^c_x.
+template <typename R, bool VISC, bool SMOOTH = false>
 GKS_HD void side_forward(const Params &p, const Prim<R> &g, R m0, R m1, const R gr[3][5], SideFwd<R> &S,
                          R gc[3][5])
 {
@@ -460,6 +461,18 @@ GKS_HD void side_forward(const Params &p, const Prim<R> &g, R m0, R m1, const R 
         for (int k = 0; k + 2 < 7; ++k) S.Th.u[k + 2] = g.U * S.Th.u[k + 1] + R(k + 1) * h * S.Th.u[k];
     }
     vw_tables(g, K, S.Th);
+    if constexpr (SMOOTH) {
+        const R ir = R(1) / g.rho;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            R b[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) b[q] = gr[d][q] * ir;
+            micro_slope(g, K, b, S.a[d]);
+            contract<0, 0, 0>(S.Th, S.a[d], g.rho, gc[d]);
+        }
+        return;
+    }
     psi_mom<1, 0, 0>(S.Th, S.F[0]);
     psi_mom<0, 0, 0>(S.Th, S.V[0]);
 #pragma unroll
@@ -505,8 +518,9 @@ GKS_HD void side_forward(const Params &p, const Prim<R> &g, R m0, R m1, const R 
 }
 
 // Reverse of side_terms.  gcb: adjoint of the side's share of g^c_x (from the
-// equilibrium part).  Adds to gb, m0b, m1b, grb, tcb, Ucb.
-template <typename R, bool VISC, bool PRFIX>
+// equilibrium part).  Adds to gb, m0b, m1b, grb, tcb, Ucb.  SMOOTH: the side
+// enters only through that share.
+template <typename R, bool VISC, bool PRFIX, bool SMOOTH = false>
 GKS_HD void side_terms_rev(const Params &p, const Prim<R> &g, R m0, R m1, const R gr[3][5],
                            const TimeCoef<R> &tc, const R Uc[3], const R gcb[3][5], const R Fob[2][5],
                            const R Wob[2][5], PrimB<R> &gb, R &m0b, R &m1b, R grb[3][5],
@@ -520,7 +534,7 @@ GKS_HD void side_terms_rev(const Params &p, const Prim<R> &g, R m0, R m1, const 
         for (int d = 0; d < 3; ++d)
 #pragma unroll
             for (int q = 0; q < 5; ++q) gcs[d][q] = R(0);
-        side_forward<R, VISC>(p, g, m0, m1, gr, S, gcs);
+        side_forward<R, VISC, SMOOTH>(p, g, m0, m1, gr, S, gcs);
     }
     R Fb[3][5], Vb[3][5];
 #pragma unroll
@@ -528,11 +542,13 @@ GKS_HD void side_terms_rev(const Params &p, const Prim<R> &g, R m0, R m1, const 
 #pragma unroll
         for (int q = 0; q < 5; ++q) Fb[j][q] = Vb[j][q] = R(0);
     R rhob = R(0);
-    R cW0b[3] = {R(0), R(0), R(0)};
-    const R cW0[3] = {R(1), -tc.tau, -tc.tau};
-    add_part_rev<R, PRFIX>(p, g.rho, tc.cF[0] + 3, tc.cF[1] + 3, cW0, tc.cW + 3, S.F, S.V, Uc, Fob, Wob,
-                           rhob, tcb.cF[0] + 3, tcb.cF[1] + 3, cW0b, tcb.cW + 3, Fb, Vb, Ucb);
-    tcb.tau -= cW0b[1] + cW0b[2];
+    if constexpr (!SMOOTH) {
+        R cW0b[3] = {R(0), R(0), R(0)};
+        const R cW0[3] = {R(1), -tc.tau, -tc.tau};
+        add_part_rev<R, PRFIX>(p, g.rho, tc.cF[0] + 3, tc.cF[1] + 3, cW0, tc.cW + 3, S.F, S.V, Uc, Fob, Wob,
+                               rhob, tcb.cF[0] + 3, tcb.cF[1] + 3, cW0b, tcb.cW + 3, Fb, Vb, Ucb);
+        tcb.tau -= cW0b[1] + cW0b[2];
+    }
     sched_fence();
     TabB<R> Thb;
     zero(Thb);
@@ -540,10 +556,13 @@ GKS_HD void side_terms_rev(const Params &p, const Prim<R> &g, R m0, R m1, const 
     // u entries need an adjoint of their own
     R Tfub[7] = {R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
     R dummy = R(0);
-    psi_mom_rev<0, 0, 0>(S.Th, Vb[0], Thb);
-    psi_mom_rev<1, 0, 0>(S.Th, Fb[0], Thb);
+    if constexpr (!SMOOTH) {
+        psi_mom_rev<0, 0, 0>(S.Th, Vb[0], Thb);
+        psi_mom_rev<1, 0, 0>(S.Th, Fb[0], Thb);
+    }
+    constexpr bool KIN_VISC = VISC && !SMOOTH;
     R Bb[5] = {R(0), R(0), R(0), R(0), R(0)};
-    if (VISC) {
+    if (KIN_VISC) {
         R Ab[5] = {R(0), R(0), R(0), R(0), R(0)};
         contract_rev<0, 0, 0>(S.Th, S.A, R(1), Vb[2], Thb, Ab, dummy);
         contract_rev<1, 0, 0>(S.Th, S.A, R(1), Fb[2], Thb, Ab, dummy);
@@ -559,18 +578,20 @@ GKS_HD void side_terms_rev(const Params &p, const Prim<R> &g, R m0, R m1, const 
 #pragma unroll
         for (int q = 0; q < 5; ++q) b[q] = gr[d][q] * ir;
         micro_slope(g, K, b, a);
-        if (d == 0) {
-            if (VISC) contract_rev_split<1, 0, 0>(S.Tf, a, R(-1), Bb, Tfub, Thb, ab, dummy);
-            contract_rev<2, 0, 0>(S.Th, a, R(1), Fb[1], Thb, ab, dummy);
-            contract_rev<1, 0, 0>(S.Th, a, R(1), Vb[1], Thb, ab, dummy);
-        } else if (d == 1) {
-            if (VISC) contract_rev_split<0, 1, 0>(S.Tf, a, R(-1), Bb, Tfub, Thb, ab, dummy);
-            contract_rev<1, 1, 0>(S.Th, a, R(1), Fb[1], Thb, ab, dummy);
-            contract_rev<0, 1, 0>(S.Th, a, R(1), Vb[1], Thb, ab, dummy);
-        } else {
-            if (VISC) contract_rev_split<0, 0, 1>(S.Tf, a, R(-1), Bb, Tfub, Thb, ab, dummy);
-            contract_rev<1, 0, 1>(S.Th, a, R(1), Fb[1], Thb, ab, dummy);
-            contract_rev<0, 0, 1>(S.Th, a, R(1), Vb[1], Thb, ab, dummy);
+        if constexpr (!SMOOTH) {
+            if (d == 0) {
+                if (KIN_VISC) contract_rev_split<1, 0, 0>(S.Tf, a, R(-1), Bb, Tfub, Thb, ab, dummy);
+                contract_rev<2, 0, 0>(S.Th, a, R(1), Fb[1], Thb, ab, dummy);
+                contract_rev<1, 0, 0>(S.Th, a, R(1), Vb[1], Thb, ab, dummy);
+            } else if (d == 1) {
+                if (KIN_VISC) contract_rev_split<0, 1, 0>(S.Tf, a, R(-1), Bb, Tfub, Thb, ab, dummy);
+                contract_rev<1, 1, 0>(S.Th, a, R(1), Fb[1], Thb, ab, dummy);
+                contract_rev<0, 1, 0>(S.Th, a, R(1), Vb[1], Thb, ab, dummy);
+            } else {
+                if (KIN_VISC) contract_rev_split<0, 0, 1>(S.Tf, a, R(-1), Bb, Tfub, Thb, ab, dummy);
+                contract_rev<1, 0, 1>(S.Th, a, R(1), Fb[1], Thb, ab, dummy);
+                contract_rev<0, 0, 1>(S.Th, a, R(1), Vb[1], Thb, ab, dummy);
+            }
         }
         contract_rev<0, 0, 0>(S.Th, a, g.rho, gcb[d], Thb, ab, rhob);
         R bb[5] = {R(0), R(0), R(0), R(0), R(0)};
@@ -583,7 +604,7 @@ GKS_HD void side_terms_rev(const Params &p, const Prim<R> &g, R m0, R m1, const 
         sched_fence();
     }
     rhob -= irb * ir * ir;
-    if (VISC) gauss_moments_rev<7>(g.U, g.lam, S.Tf.u, Tfub, gb.U, gb.lam);
+    if (KIN_VISC) gauss_moments_rev<7>(g.U, g.lam, S.Tf.u, Tfub, gb.U, gb.lam);
     vw_tables_rev(g, K, S.Th, Thb, gb);
     recursion_rev<7>(g.U, g.lam, S.Th.u, Thb.u, gb.U, gb.lam);
     m0b += Thb.u[0];
@@ -609,7 +630,7 @@ struct PointFwd {
     TimeCoef<R> tc;
 };
 
-template <typename R, bool VISC>
+template <typename R, bool VISC, bool SMOOTH = false>
 GKS_HD void point_forward(const Params &p, R dt, const R wl[5], const R wr[5], PointFwd<R> &P)
 {
     const R K = R(p.K);
@@ -640,6 +661,12 @@ GKS_HD void point_forward(const Params &p, R dt, const R wl[5], const R wr[5], P
     P.pr = gR.rho * R(0.5) / gR.lam;
     P.pc = P.gC.rho * R(0.5) / P.gC.lam;
     P.z = (P.pl - P.pr) / (P.pl + P.pr);
+    if constexpr (SMOOTH) {
+        P.tau = VISC ? R(p.mu) / P.pc : R(0);
+        P.taun = R(0);  // not used by eq. 2nd-smooth-flux
+        time_coefficients_smooth<R>(P.tau, dt, P.tc);
+        return;
+    }
     const R jump = R(p.c_tau) * fabs(P.z) * dt;
     if (VISC) {
         P.tau = R(p.mu) / P.pc;
@@ -658,6 +685,7 @@ struct EqAdj {
     PrimB<R> gCb;           // primitive variables of W^c (partial)
     R cF0b[3], cF1b[3], cWb[3];  // equilibrium time coefficients
     R Ucb[3];
+    R taub;                 // tau through the equilibrium part's W(0) (eq. 2nd-smooth-flux only)
 };
 
 // adjoints produced by one kinetic side
@@ -670,7 +698,7 @@ struct SideAdj {
     R Ucb[3];
 };
 
-template <typename R, bool VISC, bool PRFIX>
+template <typename R, bool VISC, bool PRFIX, bool SMOOTH = false>
 GKS_HD void eq_reverse(const Params &p, const PointFwd<R> &P, const R gl[3][5], const R gr[3][5],
                        const R Fob[2][5], const R Wob[2][5], EqAdj<R> &E)
 {
@@ -683,8 +711,8 @@ GKS_HD void eq_reverse(const Params &p, const PointFwd<R> &P, const R gl[3][5], 
         for (int q = 0; q < 5; ++q) gc[d][q] = R(0);
     {
         SideFwd<R> S;
-        side_forward<R, VISC>(p, P.gL, P.l0, P.l1, gl, S, gc);
-        side_forward<R, VISC>(p, P.gR, P.r0, P.r1, gr, S, gc);
+        side_forward<R, VISC, SMOOTH>(p, P.gL, P.l0, P.l1, gl, S, gc);
+        side_forward<R, VISC, SMOOTH>(p, P.gR, P.r0, P.r1, gr, S, gc);
     }
     Tab<R> TC;
     gauss_moments<7>(gC.U, gC.lam, TC.u);
@@ -728,10 +756,12 @@ GKS_HD void eq_reverse(const Params &p, const PointFwd<R> &P, const R gl[3][5], 
 #pragma unroll
         for (int q = 0; q < 5; ++q) Fb[j][q] = Vb[j][q] = R(0);
     {
-        const R cW0[3] = {R(0), R(0), R(0)};
+        const R t0 = SMOOTH ? -P.tc.tau : R(0);
+        const R cW0[3] = {SMOOTH ? R(1) : R(0), t0, t0};
         R cW0b[3] = {R(0), R(0), R(0)};
         add_part_rev<R, PRFIX>(p, gC.rho, P.tc.cF[0], P.tc.cF[1], cW0, P.tc.cW, F, V, P.Uc, Fob, Wob, E.gCb.rho,
                                E.cF0b, E.cF1b, cW0b, E.cWb, Fb, Vb, E.Ucb);
+        E.taub = SMOOTH ? -(cW0b[1] + cW0b[2]) : R(0);
     }
     TabB<R> TCb;
     zero(TCb);
@@ -776,7 +806,7 @@ GKS_HD void eq_reverse(const Params &p, const PointFwd<R> &P, const R gl[3][5], 
     gauss_moments_rev<7>(gC.U, gC.lam, TC.u, TCb.u, E.gCb.U, E.gCb.lam);
 }
 
-template <typename R, bool VISC, bool PRFIX>
+template <typename R, bool VISC, bool PRFIX, bool SMOOTH = false>
 GKS_HD void side_reverse(const Params &p, const PointFwd<R> &P, bool right, const R g[3][5], const R gcb[3][5],
                          const R Fob[2][5], const R Wob[2][5], SideAdj<R> &A)
 {
@@ -790,7 +820,7 @@ GKS_HD void side_reverse(const Params &p, const PointFwd<R> &P, bool right, cons
         for (int q = 0; q < 5; ++q) A.grb[d][q] = R(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) A.Ucb[k] = R(0);
-    side_terms_rev<R, VISC, PRFIX>(p, right ? P.gR : P.gL, right ? P.r0 : P.l0, right ? P.r1 : P.l1, g, P.tc,
+    side_terms_rev<R, VISC, PRFIX, SMOOTH>(p, right ? P.gR : P.gL, right ? P.r0 : P.l0, right ? P.r1 : P.l1, g, P.tc,
                                    P.Uc, gcb, Fob, Wob, A.gb, A.m0b, A.m1b, A.grb, tcb, A.Ucb);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -802,7 +832,7 @@ GKS_HD void side_reverse(const Params &p, const PointFwd<R> &P, bool right, cons
 }
 
 // Completes the reverse: sets wlb, wrb (the adjoints of the point states).
-template <typename R, bool VISC>
+template <typename R, bool VISC, bool SMOOTH = false>
 GKS_HD void common_reverse(const Params &p, R dt, const R wl[5], const R wr[5], const PointFwd<R> &P,
                            const EqAdj<R> &E, const SideAdj<R> &SL, const SideAdj<R> &SR, R wlb[5], R wrb[5])
 {
@@ -826,23 +856,36 @@ GKS_HD void common_reverse(const Params &p, R dt, const R wl[5], const R wr[5], 
     gCb.V += E.Ucb[1] + SL.Ucb[1] + SR.Ucb[1];
     gCb.W += E.Ucb[2] + SL.Ucb[2] + SR.Ucb[2];
     // collision times
-    R taub = R(0), taunb = R(0);
-    time_coefficients_rev<R, VISC>(P.tau, P.taun, dt, tcb, taub, taunb);
-    R jumpb, pcb = R(0);
-    if (VISC) {
-        taub += taunb;
-        jumpb = taunb;
-        pcb -= taub * P.tau / P.pc;
+    R pcb = R(0);
+    if constexpr (SMOOTH) {
+        // the coefficients of eq. 2nd-smooth-flux are linear in tau
+        R taub = E.taub;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const R del = k == 0 ? dt : R(0.5) * dt;
+            taub -= del * (tcb.cF[k][1] + tcb.cF[k][2]);
+        }
+        taub -= tcb.cW[1] + tcb.cW[2];
+        if (VISC) pcb -= taub * P.tau / P.pc;
     } else {
-        jumpb = taunb;
+        R taub = R(0), taunb = R(0);
+        time_coefficients_rev<R, VISC>(P.tau, P.taun, dt, tcb, taub, taunb);
+        R jumpb;
+        if (VISC) {
+            taub += taunb;
+            jumpb = taunb;
+            pcb -= taub * P.tau / P.pc;
+        } else {
+            jumpb = taunb;
+        }
+        const R zb = jumpb * R(p.c_tau) * dt * sign_of(P.z);
+        const R sp = P.pl + P.pr;
+        const R plb = zb * R(2) * P.pr / (sp * sp), prb = -zb * R(2) * P.pl / (sp * sp);
+        gLb.rho += plb * R(0.5) / gL.lam;
+        gLb.lam -= plb * P.pl / gL.lam;
+        gRb.rho += prb * R(0.5) / gR.lam;
+        gRb.lam -= prb * P.pr / gR.lam;
     }
-    const R zb = jumpb * R(p.c_tau) * dt * sign_of(P.z);
-    const R sp = P.pl + P.pr;
-    const R plb = zb * R(2) * P.pr / (sp * sp), prb = -zb * R(2) * P.pl / (sp * sp);
-    gLb.rho += plb * R(0.5) / gL.lam;
-    gLb.lam -= plb * P.pl / gL.lam;
-    gRb.rho += prb * R(0.5) / gR.lam;
-    gRb.lam -= prb * P.pr / gR.lam;
     gCb.rho += pcb * R(0.5) / gC.lam;
     gCb.lam -= pcb * P.pc / gC.lam;
     // gC = primitive(Wc)
@@ -895,20 +938,20 @@ GKS_HD void common_reverse(const Params &p, R dt, const R wl[5], const R wr[5], 
 
 // Vector-Jacobian product of gks_point: given the adjoints Fob, Wob of its
 // outputs, adds the adjoints of wl, gl, wr, gr (the four parts in sequence).
-template <typename R, bool VISC, bool PRFIX>
+template <typename R, bool VISC, bool PRFIX, bool SMOOTH = false>
 GKS_HD void gks_point_vjp(const Params &p, R dt, const R wl[5], const R gl[3][5], const R wr[5],
                           const R gr[3][5], const R Fob[2][5], const R Wob[2][5], R wlb[5], R glb[3][5],
                           R wrb[5], R grb[3][5])
 {
     PointFwd<R> P;
-    point_forward<R, VISC>(p, dt, wl, wr, P);
+    point_forward<R, VISC, SMOOTH>(p, dt, wl, wr, P);
     EqAdj<R> E;
-    eq_reverse<R, VISC, PRFIX>(p, P, gl, gr, Fob, Wob, E);
+    eq_reverse<R, VISC, PRFIX, SMOOTH>(p, P, gl, gr, Fob, Wob, E);
     SideAdj<R> SL, SR;
-    side_reverse<R, VISC, PRFIX>(p, P, true, gr, E.gcb, Fob, Wob, SR);
-    side_reverse<R, VISC, PRFIX>(p, P, false, gl, E.gcb, Fob, Wob, SL);
+    side_reverse<R, VISC, PRFIX, SMOOTH>(p, P, true, gr, E.gcb, Fob, Wob, SR);
+    side_reverse<R, VISC, PRFIX, SMOOTH>(p, P, false, gl, E.gcb, Fob, Wob, SL);
     R a[5], b[5];
-    common_reverse<R, VISC>(p, dt, wl, wr, P, E, SL, SR, a, b);
+    common_reverse<R, VISC, SMOOTH>(p, dt, wl, wr, P, E, SL, SR, a, b);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         wlb[q] += a[q];
@@ -995,7 +1038,7 @@ GKS_HD void to_global_rev(const R T[3][3], const R goutb[5], R lb[5])
 // values: accb = adjoint of acc[4][5]; sets the adjoints of both sides' point
 // state Wb[2][5] and gradient Gb[2][5][3] (global frame) and the two offsets
 // r[2][3] at which the cells' polynomials are evaluated.
-template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR>
+template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR, bool SMOOTH = false>
 GKS_HD void gauss_point_vjp_point(const Params &p, R dt, const R nrm[3], R area, const R r[3], const R dv[3],
                                   const CoefL &cl, const CoefR &cr, const R accb[4][5], R Wb[2][5],
                                   R Gb[2][5][3], R off[2][3], bool wall = false)
@@ -1036,7 +1079,7 @@ GKS_HD void gauss_point_vjp_point(const Params &p, R dt, const R nrm[3], R area,
 #pragma unroll
         for (int d = 0; d < 3; ++d) glb[d][q] = grb[d][q] = R(0);
     }
-    gks_point_vjp<R, VISC, PRFIX>(p, dt, wl, gl, wr, gr, Fob, Wob, wlb, glb, wrb, grb);
+    gks_point_vjp<R, VISC, PRFIX, SMOOTH>(p, dt, wl, gl, wr, gr, Fob, Wob, wlb, glb, wrb, grb);
     if (wall) {
         // the ghost is a linear function of the left state; its transpose is itself
         R wg[5], gg[3][5];
@@ -1058,13 +1101,13 @@ GKS_HD void gauss_point_vjp_point(const Params &p, R dt, const R nrm[3], R area,
 
 // Vector-Jacobian product of gauss_point_terms with respect to the two
 // cells' coefficients: accb = adjoint of acc[4][5]; adds to cbl, cbr.
-template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR>
+template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR, bool SMOOTH = false>
 GKS_HD void gauss_point_terms_vjp(const Params &p, R dt, const R nrm[3], R area, const R r[3], const R dv[3],
                                   const CoefL &cl, const CoefR &cr, const R accb[4][5], R cbl[5][10],
                                   R cbr[5][10])
 {
     R Wb[2][5], Gb[2][5][3], off[2][3];
-    gauss_point_vjp_point<R, VISC, PRFIX>(p, dt, nrm, area, r, dv, cl, cr, accb, Wb, Gb, off);
+    gauss_point_vjp_point<R, VISC, PRFIX, CoefL, CoefR, SMOOTH>(p, dt, nrm, area, r, dv, cl, cr, accb, Wb, Gb, off);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         R t[10];

@@ -1,0 +1,7 @@
+// Kernel B (gas-kinetic flux) instantiated for the double bulk type.
+#include "gks_flux_kernel.h"
+
+namespace gks {
+template hipError_t launch_flux_t<double>(const DevMesh &, const DevState &, const Params &, double, const double *,
+                                      int, hipStream_t);
+}  // namespace gks

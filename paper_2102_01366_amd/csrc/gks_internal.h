@@ -1,5 +1,5 @@
 // Internal definitions shared by the host side of libgks (gks_api.cpp) and
-// its HIP kernels (gks_kernels.hip).  Not part of the public interface.
+// its HIP kernels (gks_kernels.hip, gks_flux_*.hip, gks_adjoint*.hip).  Not part of the public interface.
 //
 // Two precision forms share one layout: in FP64 every bulk array holds
 // doubles; in FP32-bulk the per-stage bulk arrays (least-squares operators,
@@ -22,7 +22,11 @@ struct Params {
     double g22, g12, g02, g11, g01;
     int viscous, nonlinear;
     int order;  // 3 or 2
+    int flux;   // FLUX_KIND_FULL or FLUX_KIND_SMOOTH
 };
+
+// distribution of the flux: eq. 2nd-flux, or its smooth-flow form eq. 2nd-smooth-flux
+enum FluxKind { FLUX_KIND_FULL = 0, FLUX_KIND_SMOOTH = 1 };
 
 // Rows of DevMesh::geoR ([NGEO_R][nc], bulk precision): what the
 // reconstruction reads.
@@ -95,6 +99,10 @@ hipError_t launch_flux(const DevMesh &m, const DevState &s, const Params &p, dou
                        const double *dtp, int mode, bool fp32, hipStream_t st);
 hipError_t launch_update(const DevMesh &m, const DevState &s, double dt, const double *dtp,
                          int stage, bool fp32, hipStream_t st);
+// the flux launcher of one bulk type (gks_flux_f64.hip, gks_flux_f32.hip)
+template <typename R>
+hipError_t launch_flux_t(const DevMesh &m, const DevState &s, const Params &p, double dt, const double *dtp,
+                         int mode, hipStream_t st);
 // dt: writes the min over cells of the CFL bound (without the CFL factor) to
 // s.red[0] and cfl times it, the time step, to s.red[kRedDt]
 hipError_t launch_dt(const DevMesh &m, const DevState &s, const Params &p, double cfl,
@@ -136,8 +144,8 @@ struct AdjFlux {
     const double *Wb1, *Gb1;    // adjoint of W^{n+1}, grad W^{n+1}
     const double *Wbs, *Gbs;    // adjoint of W*, grad W* (stage 1 only)
     double *CB;                 // [2][50][nf] out: coefficient adjoints of owner / neighbour
-    double *EQ;                 // [32][3 nf] per Gauss point: the equilibrium part's adjoints
-    double *SB;                 // [35][2 x 3 nf] per Gauss point and side: a kinetic side's adjoints
+    double *EQ;                 // [kEqRec][3 nf] per Gauss point: the equilibrium part's adjoints
+    double *SB;                 // [kSideRec][2 x 3 nf] per Gauss point and side: a kinetic side's adjoints
 };
 
 // Reconstruction stage of the adjoint: the stage's input state and step-1
@@ -156,9 +164,18 @@ struct AdjRecon {
 };
 
 enum FluxAdjMode { FLUX_ADJ_STAGE1 = 1, FLUX_ADJ_STAGE2 = 2 };
+constexpr int kEqRec = 33;    // values of an AdjFlux::EQ record (per Gauss point)
+constexpr int kSideRec = 35;  // values of an AdjFlux::SB record (per Gauss point and side)
 
-hipError_t launch_flux_vjp(const DevMesh &m, const AdjFlux &a, const Params &p, double dt, int mode,
-                           bool fp32, hipStream_t st);
+// the flux stage's adjoint for one bulk type (gks_adjoint_flux_f64.hip, _f32.hip)
+template <typename R>
+hipError_t launch_flux_vjp_t(const DevMesh &m, const AdjFlux &a, const Params &p, double dt, int mode,
+                             hipStream_t st);
+inline hipError_t launch_flux_vjp(const DevMesh &m, const AdjFlux &a, const Params &p, double dt, int mode,
+                                  bool fp32, hipStream_t st)
+{
+    return fp32 ? launch_flux_vjp_t<float>(m, a, p, dt, mode, st) : launch_flux_vjp_t<double>(m, a, p, dt, mode, st);
+}
 // adjoints of the reconstruction's inputs: own / neighbour terms
 hipError_t launch_recon_vjp(const DevMesh &m, const AdjRecon &a, const Params &p, bool fp32,
                             hipStream_t st);  // either order

@@ -6,7 +6,7 @@
 // element is written by exactly one thread; the cell update gathers its four
 // faces in a fixed order, so results are bitwise reproducible.  No MFMA: the
 // per-cell operators are small matrix-vector products used once per stage.
-#include "gks_flux.h"
+#include "gks_device.h"
 #include "gks_internal.h"
 #include "gks_m2stage.h"
 #include "gks_recon_adj.h"
@@ -15,21 +15,6 @@
 
 namespace gks {
 
-__device__ __forceinline__ int gid() { return blockIdx.x * blockDim.x + threadIdx.x; }
-
-// Workgroups go to the chip's 8 XCDs round-robin (workgroup b to XCD b mod 8),
-// and each XCD has its own L2.  The kernels that gather neighbours renumber
-// their workgroups so that each XCD takes one contiguous range of cells or
-// faces: ranges adjacent in the space-filling order, whose neighbour gathers
-// then hit the L2 that loaded them.  A bijection of [0, gridDim.x).
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_block()
-{
-    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
-    const int q = nb / kXcds, r = nb % kXcds, x = b % kXcds, k = b / kXcds;
-    return x * q + (x < r ? x : r) + k;
-}
-__device__ __forceinline__ int xcd_gid() { return xcd_block() * blockDim.x + threadIdx.x; }
 
 // ===========================================================================
 // A1: reconstruction step 1 (Sec. 4.3) -- P^1 slopes b = M1 (Q_m - Q_0)
@@ -414,121 +399,6 @@ __global__ __launch_bounds__(kBlock) void reconstruct2_kernel(DevMesh m, DevStat
 }
 
 // ===========================================================================
-// B: gas-kinetic flux (Sec. 2.2) at the three Gauss points of each face
-// ===========================================================================
-template <typename R>
-struct DevCoef {
-    const R *coef;
-    int n, cell;
-    __device__ __forceinline__ R operator()(int q, int k) const
-    {
-        return coef[(size_t)(10 * q + k) * n + cell];
-    }
-};
-
-// Three lanes per face, one per Gauss point: 21 faces per wavefront (lane 63
-// idle).  The lanes of a face are summed in Gauss-point order by shuffles and
-// the first lane writes the face.
-constexpr int kFluxThreads = 256;
-#ifndef GKS_FLUX_MIN_WAVES
-#define GKS_FLUX_MIN_WAVES 1
-#endif
-constexpr int kFacesPerWave = 21;
-constexpr int kFacesPerBlock = kFacesPerWave * (kFluxThreads / 64);
-
-// WALL: the launch over the wall faces [nfi, nf) (slip-wall ghost on the
-// right), else over the interior faces [0, nfi).
-template <typename R, int MODE, bool VISC, bool PRFIX, bool WALL>
-__global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(DevMesh m, DevState s, Params p, double dt_,
-                                                                             const double *dtp)
-{
-    const int nf = m.nf, n = m.nc;
-    const R dt = R(dtp ? *dtp : dt_);
-    const R *coef = static_cast<const R *>(s.coef);
-    R *FF = static_cast<R *>(s.FF), *FT = static_cast<R *>(s.FT), *FW0 = static_cast<R *>(s.FW0),
-      *FWs = static_cast<R *>(s.FWs);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int slot = lane / 3, k = lane - 3 * slot;
-    const int f0 = WALL ? m.nfi : 0, f1 = WALL ? nf : m.nfi;
-    const int f = f0 + xcd_block() * kFacesPerBlock + wave * kFacesPerWave + slot;
-    const bool live = slot < kFacesPerWave && f < f1;
-    R acc[4][5];
-    if (live) {
-        const int L = m.fcell[f], Rc = m.fcell[nf + f];
-        const R *fg = static_cast<const R *>(m.fgeo);
-        R nrm[3], dv[3], r[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            nrm[d] = fg[(size_t)(F_N + d) * nf + f];
-            dv[d] = fg[(size_t)(F_D + d) * nf + f];
-            r[d] = fg[(size_t)(F_RL + 3 * k + d) * nf + f];
-        }
-        const R area = fg[(size_t)F_AREA * nf + f];
-        gauss_point_terms<R, VISC, PRFIX>(p, dt, nrm, area, r, dv, DevCoef<R>{coef, n, L},
-                                          DevCoef<R>{coef, n, WALL ? L : Rc}, acc, WALL);
-    } else {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int q = 0; q < 5; ++q) acc[a][q] = R(0);
-    }
-    // sum the three Gauss points of each face onto its first lane
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            const R v1 = __shfl_down(acc[a][q], 1, 64);
-            const R v2 = __shfl_down(acc[a][q], 2, 64);
-            acc[a][q] = (acc[a][q] + v1) + v2;
-        }
-    if (!live || k != 0) return;
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        const size_t o = (size_t)q * nf + f;
-        if (MODE == FLUX_STAGE1) {
-            FF[o] = acc[0][q];
-            FT[o] = acc[1][q];
-            FW0[o] = acc[2][q];
-            FWs[o] = R(0.5) * (acc[2][q] + acc[3][q]);
-        } else if (MODE == FLUX_STAGE2) {
-            FT[o] = acc[1][q];
-            FWs[o] = acc[3][q] - acc[2][q];
-        } else {
-            FF[o] = acc[0][q];
-            FT[o] = acc[1][q];
-            FW0[o] = acc[2][q];
-            FWs[o] = acc[3][q];
-        }
-    }
-}
-
-template <typename R, int MODE, bool WALL>
-static void launch_flux_part(const DevMesh &m, const DevState &s, const Params &p, double dt,
-                             const double *dtp, hipStream_t st)
-{
-    const int nfaces = WALL ? m.nf - m.nfi : m.nfi;
-    if (nfaces <= 0) return;
-    const dim3 grid((unsigned)((nfaces + kFacesPerBlock - 1) / kFacesPerBlock)), block(kFluxThreads);
-    const bool visc = p.viscous != 0, prfix = p.prandtl != 1.0;
-    if (visc && prfix)
-        hipLaunchKernelGGL((flux_kernel<R, MODE, true, true, WALL>), grid, block, 0, st, m, s, p, dt, dtp);
-    else if (visc)
-        hipLaunchKernelGGL((flux_kernel<R, MODE, true, false, WALL>), grid, block, 0, st, m, s, p, dt, dtp);
-    else if (prfix)
-        hipLaunchKernelGGL((flux_kernel<R, MODE, false, true, WALL>), grid, block, 0, st, m, s, p, dt, dtp);
-    else
-        hipLaunchKernelGGL((flux_kernel<R, MODE, false, false, WALL>), grid, block, 0, st, m, s, p, dt, dtp);
-}
-
-template <typename R, int MODE>
-static void launch_flux_mode(const DevMesh &m, const DevState &s, const Params &p, double dt,
-                             const double *dtp, hipStream_t st)
-{
-    launch_flux_part<R, MODE, false>(m, s, p, dt, dtp, st);
-    launch_flux_part<R, MODE, true>(m, s, p, dt, dtp, st);
-}
-
-// ===========================================================================
 // C: cell update (eqs. flux-operator, s2o4, gauss-formula, step-du)
 // ===========================================================================
 template <typename R, int STAGE>
@@ -754,26 +624,10 @@ hipError_t launch_reconstruct(const DevMesh &m, const DevState &s, const Params 
     return hipGetLastError();
 }
 
-template <typename R>
-static void launch_flux_r(const DevMesh &m, const DevState &s, const Params &p, double dt,
-                          const double *dtp, int mode, hipStream_t st)
-{
-    if (mode == FLUX_STAGE1)
-        launch_flux_mode<R, FLUX_STAGE1>(m, s, p, dt, dtp, st);
-    else if (mode == FLUX_STAGE2)
-        launch_flux_mode<R, FLUX_STAGE2>(m, s, p, dt, dtp, st);
-    else
-        launch_flux_mode<R, FLUX_DEBUG>(m, s, p, dt, dtp, st);
-}
-
 hipError_t launch_flux(const DevMesh &m, const DevState &s, const Params &p, double dt,
                        const double *dtp, int mode, bool fp32, hipStream_t st)
 {
-    if (fp32)
-        launch_flux_r<float>(m, s, p, dt, dtp, mode, st);
-    else
-        launch_flux_r<double>(m, s, p, dt, dtp, mode, st);
-    return hipGetLastError();
+    return fp32 ? launch_flux_t<float>(m, s, p, dt, dtp, mode, st) : launch_flux_t<double>(m, s, p, dt, dtp, mode, st);
 }
 
 hipError_t launch_update(const DevMesh &m, const DevState &s, double dt, const double *dtp,

@@ -69,14 +69,19 @@ extern "C" gks_status gks_flux_op_count(const gks_config *cfg, double counts[4])
     Cnt acc[4][5];
     tally = Tally{};
     const HostCoef L{cl}, R{cr};
+    const bool sm = p.flux == gks::FLUX_KIND_SMOOTH;
     if (p.viscous && p.prandtl != 1.0)
-        gks::face_terms<Cnt, true, true>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc);
+        sm ? gks::face_terms<Cnt, true, true, HostCoef, HostCoef, true>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc)
+           : gks::face_terms<Cnt, true, true>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc);
     else if (p.viscous)
-        gks::face_terms<Cnt, true, false>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc);
+        sm ? gks::face_terms<Cnt, true, false, HostCoef, HostCoef, true>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc)
+           : gks::face_terms<Cnt, true, false>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc);
     else if (p.prandtl != 1.0)
-        gks::face_terms<Cnt, false, true>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc);
+        sm ? gks::face_terms<Cnt, false, true, HostCoef, HostCoef, true>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc)
+           : gks::face_terms<Cnt, false, true>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc);
     else
-        gks::face_terms<Cnt, false, false>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc);
+        sm ? gks::face_terms<Cnt, false, false, HostCoef, HostCoef, true>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc)
+           : gks::face_terms<Cnt, false, false>(p, Cnt(1e-3), nrm, Cnt(0.01), rl, dv, L, R, acc);
     counts[0] = (double)tally.add;
     counts[1] = (double)tally.mul;
     counts[2] = (double)tally.div;

@@ -27,6 +27,7 @@ inline Params params_from_config(const gks_config *cfg)
     p.viscous = cfg->viscous;
     p.nonlinear = cfg->nonlinear;
     p.order = cfg->order;
+    p.flux = cfg->flux;
     return p;
 }
 

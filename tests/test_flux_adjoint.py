@@ -23,10 +23,11 @@ def _state(rng):
     return np.array([rho, *(rho * U), p / 0.4 + 0.5 * rho * U @ U])
 
 
+@pytest.mark.parametrize("flux", [G.GKS_FLUX_FULL, G.GKS_FLUX_SMOOTH], ids=["full", "smooth"])
 @pytest.mark.parametrize("visc,pr", VARIANTS)
-def test_point_reverse_is_the_transpose(visc, pr):
+def test_point_reverse_is_the_transpose(visc, pr, flux):
     rng = np.random.default_rng(11)
-    cfg = G.default_config(viscous=visc, mu=0.01, prandtl=pr)
+    cfg = G.default_config(viscous=visc, mu=0.01, prandtl=pr, flux=flux)
     for _ in range(25):
         x = np.concatenate([_state(rng), 0.3 * rng.standard_normal(15),
                             _state(rng), 0.3 * rng.standard_normal(15)])
@@ -40,12 +41,13 @@ def test_point_reverse_is_the_transpose(visc, pr):
         assert np.abs((yp - ym) / (2 * h) - jv).max() <= 1e-7 * np.abs(jv).max()
 
 
+@pytest.mark.parametrize("flux", [G.GKS_FLUX_FULL, G.GKS_FLUX_SMOOTH], ids=["full", "smooth"])
 @pytest.mark.parametrize("visc,pr", [(False, 1.0), (True, 0.72)])
-def test_face_reverse_is_the_transpose(visc, pr):
+def test_face_reverse_is_the_transpose(visc, pr, flux):
     """Through the face frame (including the n1 = -1 frame) and the
     evaluation of both cells' polynomials at the Gauss point."""
     rng = np.random.default_rng(12)
-    cfg = G.default_config(viscous=visc, mu=0.01, prandtl=pr)
+    cfg = G.default_config(viscous=visc, mu=0.01, prandtl=pr, flux=flux)
     for t in range(20):
         n = rng.standard_normal(3)
         n = np.array([-1.0, 0.0, 0.0]) if t == 0 else n / np.linalg.norm(n)
@@ -65,6 +67,25 @@ def test_face_reverse_is_the_transpose(visc, pr):
         ap = G.flux_face_check(cfg, 0.01, geo, coef + h * v, v, ab)[0]
         am = G.flux_face_check(cfg, 0.01, geo, coef - h * v, v, ab)[0]
         assert np.abs((ap - am) / (2 * h) - jv).max() <= 1e-6 * np.abs(jv).max()
+
+
+@pytest.mark.parametrize("flux", [0, 1], ids=["full", "smooth"])
+@pytest.mark.parametrize("visc,pr", VARIANTS)
+def test_point_flux_matches_oracle(oracle_lib, visc, pr, flux):
+    """The library's flux arithmetic (evaluated on the host in FP64) against
+    the oracle's at one interface point; with the normal e1 the face frame is
+    the global one."""
+    rng = np.random.default_rng(15)
+    cfg = G.default_config(viscous=visc, mu=0.01, prandtl=pr, flux=flux)
+    ocfg = oracle_lib.make_config(viscous=visc, mu=0.01, prandtl=pr, flux=flux)
+    e1 = np.array([1.0, 0.0, 0.0])
+    for _ in range(10):
+        wl, wr = _state(rng), _state(rng)
+        gl, gr = 0.3 * rng.standard_normal((3, 5)), 0.3 * rng.standard_normal((3, 5))
+        x = np.concatenate([wl, gl.reshape(15), wr, gr.reshape(15)])
+        y = G.flux_point_check(cfg, 0.01, x, np.zeros(40), np.zeros(20))[0].reshape(4, 5)
+        ref = oracle_lib.point_flux(ocfg, e1, wl, gl.T.reshape(15), wr, gr.T.reshape(15), 0.01)
+        np.testing.assert_allclose(y, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
 
 
 def test_jump_term_differentiated_as_sign():

@@ -1,0 +1,136 @@
+"""The smooth-flow distribution of eq. 2nd-smooth-flux on the GPU.
+
+The flux kernel's smooth form (the equilibrium part alone, with the
+kinetically weighted W^c and slopes of eq. new-equ-part and tau = mu / p^c)
+against the oracle's, to the normwise 1e-12 bar of test_gpu_parity.py:
+face terms and two steps stage by stage, on periodic and walled meshes,
+Euler and Navier-Stokes; the FP32-bulk form against FP64; and the discrete
+adjoint of a step against central differences.  Without the pressure-jump
+term the smooth form has no kink of its own, so with smooth WENO weights
+(eps_weno = 1) the step map is smooth.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2102_01366_amd as G
+from paper_2102_01366_amd import inputs as I
+
+from test_gpu_parity import FACE_GROUPS, GW_GROUPS, W_GROUPS, assert_parity, gradient_floors
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _case(name):
+    if name == "tgv_ns_ragged":
+        m = I.kuhn_cube_mesh(5, 2 * np.pi, 0.05, 1, True)  # 750 cells
+        W, gW = I.cell_averages(m, I.taylor_green_field(mach=0.3))
+        return m, dict(viscous=True, mu=0.01, prandtl=0.72), W, gW
+    if name == "sine_euler":
+        m = I.kuhn_cube_mesh(4, 1.0, 0.1, 0, True)
+        W, gW = I.cell_averages(m, I.sine_wave_field())
+        return m, dict(), W, gW
+    if name == "walls_ns":
+        m = I.kuhn_cube_mesh(4, 1.0, 0.1, 2, False)
+        W, gW = I.cell_averages(m, I.box_vortex_field(amp=0.3))
+        return m, dict(viscous=True, mu=0.005, prandtl=0.72), W, gW
+    if name == "sine_order2":
+        m = I.kuhn_cube_mesh(4, 1.0, 0.1, 5, True)
+        W, gW = I.cell_averages(m, I.sine_wave_field())
+        return m, dict(order=2), W, gW
+    raise KeyError(name)
+
+
+CASES = ["tgv_ns_ragged", "sine_euler", "walls_ns", "sine_order2"]
+
+
+def _pair(name, **extra):
+    m, kw, W, gW = _case(name)
+    kw = dict(kw, flux=1, **extra)
+    return m, G.Solver(m, G.default_config(**kw)), oracle.Oracle(m, oracle.make_config(**kw)), W, gW
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_smooth_face_terms(name):
+    m, s, orc, W, gW = _pair(name)
+    s.init(W, gW)
+    dt = orc.compute_dt(W, 0.5)
+    assert_parity(s.debug_face_terms(dt), orc.face_terms(W, gW, dt), FACE_GROUPS, "face terms")
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_smooth_steps(name):
+    m, s, orc, W, gW = _pair(name)
+    s.init(W, gW)
+    Wo, gWo = W, gW
+    for step in range(2):
+        dt = orc.compute_dt(Wo, 0.5)
+        for stage in (1, 2):
+            s.stage(stage, dt)
+            Wo, gWo = orc.stage(stage, dt, Wo, gWo)
+            Wg, gWg = s.read_state()
+            assert_parity(Wg, Wo, W_GROUPS, f"W step {step} stage {stage}")
+            assert_parity(gWg, gWo, GW_GROUPS, f"gW step {step} stage {stage}",
+                          floors=gradient_floors(Wo, orc))
+    ref = orc.conservation_sums(Wo)
+    if name != "walls_ns":  # slip walls exchange momentum with the fluid
+        assert np.abs(s.conservation_sums() - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_smooth_differs_from_full():
+    """The two distributions are different schemes: on the same data their
+    face terms differ well above round-off."""
+    m, kw, W, gW = _case("tgv_ns_ragged")
+    dt = 0.01
+    out = []
+    for flux in (0, 1):
+        s = G.Solver(m, G.default_config(flux=flux, **kw))
+        s.init(W, gW)
+        out.append(s.debug_face_terms(dt))
+    assert np.abs(out[0] - out[1]).max() > 1e-8 * np.abs(out[0]).max()
+
+
+def test_smooth_fp32_bulk_close_to_fp64():
+    m, kw, W, gW = _case("tgv_ns_ragged")
+    res = []
+    for prec in (G.GKS_FP64, G.GKS_FP32_BULK):
+        s = G.Solver(m, G.default_config(flux=1, precision=prec, **kw))
+        s.init(W, gW)
+        for _ in range(3):
+            s.step(0.02)
+        res.append(s.read_state()[0])
+    for g in W_GROUPS:
+        assert np.abs(res[1][g] - res[0][g]).max() <= 1e-5 * np.abs(res[0][g]).max()
+
+
+@pytest.mark.parametrize("weno", [False, True], ids=["smooth_weights", "weno"])
+def test_smooth_adjoint_matches_finite_differences(weno):
+    m, kw, W, gW = _case("tgv_ns_ragged")
+    cfg = dict(kw, flux=1) if weno else dict(kw, flux=1, eps_weno=1.0)
+    eps, tol = (1e-7, 1e-5) if weno else (1e-6, 1e-6)
+    s = G.Solver(m, G.default_config(**cfg))
+    Wt, Gt = torch.from_numpy(W).cuda(), torch.from_numpy(gW).cuda()
+    s.init(Wt, Gt)
+    dt = s.compute_dt(0.5)
+
+    def F(Wx, Gx):
+        s.init(Wx, Gx)
+        s.step(dt)
+        return s.read_state(device=True)
+
+    gen = torch.Generator().manual_seed(21)
+    sW = torch.from_numpy(np.sqrt((W ** 2).mean(axis=1, keepdims=True))).cuda()
+    sG = torch.from_numpy(np.sqrt((gW ** 2).mean(axis=1, keepdims=True)) + 1e-3).cuda()
+    for _ in range(3):
+        vW = torch.randn(W.shape, generator=gen, dtype=torch.float64).cuda() * sW
+        vG = torch.randn(gW.shape, generator=gen, dtype=torch.float64).cuda() * sG
+        bW = torch.randn(W.shape, generator=gen, dtype=torch.float64).cuda()
+        bG = torch.randn(gW.shape, generator=gen, dtype=torch.float64).cuda()
+        Wp, Gp = F(Wt + eps * vW, Gt + eps * vG)
+        Wm, Gm = F(Wt - eps * vW, Gt - eps * vG)
+        lhs = (((Wp - Wm) * bW).sum() + ((Gp - Gm) * bG).sum()).item() / (2 * eps)
+        aW, aG = s.step_adjoint(dt, Wt, Gt, bW, bG)
+        rhs = ((aW * vW).sum() + (aG * vG).sum()).item()
+        assert abs(lhs - rhs) <= tol * abs(rhs), (lhs, rhs)
