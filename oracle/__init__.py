@@ -38,17 +38,18 @@ class Config(ctypes.Structure):
                 ("c_tau", ctypes.c_double), ("eps_weno", ctypes.c_double),
                 ("lw2", ctypes.c_double * 3), ("lw1", ctypes.c_double * 2),
                 ("viscous", ctypes.c_int32), ("nonlinear", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("flux", ctypes.c_int32)]
+                ("flux", ctypes.c_int32), ("wall_T", ctypes.c_double)]
 
 
 def make_config(gamma=1.4, mu=0.0, prandtl=1.0, viscous=False, nonlinear=True,
                 eps_tau=0.01, c_tau=1.0, eps_weno=1e-8, lw2=(100.0, 10.0, 1.0),
-                lw1=(10.0, 1.0), K=None, order=3, flux=0) -> Config:
+                lw1=(10.0, 1.0), K=None, order=3, flux=0, wall_T=1.0) -> Config:
     """Scheme parameters; linear weights are given as ratios and normalised.
     flux: 0 for eq. 2nd-flux, 1 for the smooth-flow form eq. 2nd-smooth-flux."""
     c = Config()
     c.order = order
     c.flux = flux
+    c.wall_T = wall_T
     c.gamma = gamma
     c.K = (5.0 - 3.0 * gamma) / (gamma - 1.0) if K is None else K
     c.mu = mu
@@ -80,7 +81,8 @@ def _load():
         D = ctypes.c_double
         I64 = ctypes.c_int64
         L.or_create.restype = P
-        L.or_create.argtypes = [ctypes.POINTER(Config), I64, P, I64, P, I64, P, P, P, P]
+        L.or_create.argtypes = [ctypes.POINTER(Config), I64, P, I64, P, I64, P, P, P, P, P]
+        L.or_wall_ghost.argtypes = [ctypes.POINTER(Config), ctypes.c_int32, P, P, P, P, P, P]
         L.or_destroy.argtypes = [P]
         L.or_set_threads.argtypes = [ctypes.c_int]
         L.or_set_threads.restype = ctypes.c_int
@@ -130,9 +132,11 @@ class Oracle:
                       np.ascontiguousarray(mesh.face_cell, np.int64),
                       np.ascontiguousarray(mesh.face_tag, np.int32),
                       np.ascontiguousarray(mesh.face_shift, np.float64)]
-        xyz, tet, fv, fc, ft, fs = self._keep
+        wu = getattr(mesh, "face_wall_u", None)
+        self._keep.append(None if wu is None else np.ascontiguousarray(wu, np.float64))
+        xyz, tet, fv, fc, ft, fs, fw = self._keep
         self._h = L.or_create(ctypes.byref(cfg), mesh.n_vert, _p(xyz), self.nc, _p(tet),
-                              self.nf, _p(fv), _p(fc), _p(ft), _p(fs))
+                              self.nf, _p(fv), _p(fc), _p(ft), _p(fs), None if fw is None else _p(fw))
         if not self._h:
             raise ValueError("oracle rejected the mesh")
 
@@ -201,6 +205,17 @@ class Oracle:
         out = np.empty(5)
         _load().or_conservation_sums(self._h, _p(W), _p(out))
         return out
+
+
+def wall_ghost(cfg: Config, tag, n, uw, W, gW):
+    """Ghost state (W, gW[15], component c direction d at 3c+d) of a wall
+    point: tag 2 slip, 3 no-slip adiabatic, 4 no-slip isothermal."""
+    Wg, gWg = np.empty(5), np.empty(15)
+    rc = _load().or_wall_ghost(ctypes.byref(cfg), int(tag), _p(_f64(n)), _p(_f64(uw)), _p(_f64(W)),
+                               _p(_f64(gW)), _p(Wg), _p(gWg))
+    if rc != 0:
+        raise ValueError("unknown wall tag")
+    return Wg, gWg
 
 
 def point_flux(cfg: Config, n, Wl, gWl, Wr, gWr, dt):

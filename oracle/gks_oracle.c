@@ -53,6 +53,10 @@
 #endif
 
 #define NC 5 /* conservative components */
+/* wall face tags (a wall face has no neighbour) */
+#define TAG_SLIP 2
+#define TAG_NOSLIP_ADIABATIC 3
+#define TAG_NOSLIP_ISOTHERMAL 4
 
 /* ======================================================================== */
 /* small dense linear algebra                                               */
@@ -191,6 +195,7 @@ struct or_ctx {
     double (*noff)[4][3]; /* translation that brings the neighbour next to the cell */
     int64_t (*fcell)[2];
     int32_t *ftag;
+    double (*fwu)[3];     /* velocity of a no-slip wall face (global frame) */
     double (*fshift)[3];
     double *farea;
     double (*fnorm)[3];
@@ -219,7 +224,7 @@ void or_destroy(or_ctx *c)
 {
     if (!c) return;
     free(c->cv); free(c->vol); free(c->cen); free(c->m2); free(c->dr);
-    free(c->nbr); free(c->cface); free(c->noff); free(c->fcell); free(c->ftag);
+    free(c->nbr); free(c->cface); free(c->noff); free(c->fcell); free(c->ftag); free(c->fwu);
     free(c->fshift); free(c->farea); free(c->fnorm); free(c->fgp);
     free(c->Wn); free(c->Ln); free(c->Ltn); free(c->FW0);
     free(c->slopes); free(c->coef); free(c->fterm); free(c->flag);
@@ -229,7 +234,7 @@ void or_destroy(or_ctx *c)
 or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
                   int64_t n_cell, const int64_t *tet, int64_t n_face,
                   const int64_t *face_vert, const int64_t *face_cell,
-                  const int32_t *face_tag, const double *face_shift)
+                  const int32_t *face_tag, const double *face_shift, const double *face_wall_u)
 {
     if (!cfg || n_cell <= 0 || n_face <= 0 || n_vert <= 0) return NULL;
     or_ctx *c = (or_ctx *)xcalloc(1, sizeof(or_ctx));
@@ -247,6 +252,7 @@ or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
     c->noff = xcalloc(nc, sizeof(*c->noff));
     c->fcell = xcalloc(nf, sizeof(*c->fcell));
     c->ftag = xcalloc(nf, sizeof(int32_t));
+    c->fwu = xcalloc(nf, sizeof(*c->fwu));
     c->fshift = xcalloc(nf, sizeof(*c->fshift));
     c->farea = xcalloc(nf, sizeof(double));
     c->fnorm = xcalloc(nf, sizeof(*c->fnorm));
@@ -286,6 +292,9 @@ or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
         c->fcell[f][0] = L;
         c->fcell[f][1] = R;
         c->ftag[f] = face_tag[f];
+        if (R < 0 && face_tag[f] != TAG_SLIP && face_tag[f] != TAG_NOSLIP_ADIABATIC &&
+            face_tag[f] != TAG_NOSLIP_ISOTHERMAL) { free(sumarea); or_destroy(c); return NULL; }
+        for (int d = 0; d < 3; ++d) c->fwu[f][d] = face_wall_u ? face_wall_u[3 * f + d] : 0.0;
         for (int d = 0; d < 3; ++d) c->fshift[f][d] = face_shift[3 * f + d];
         double x[3][3];
         for (int a = 0; a < 3; ++a)
@@ -379,9 +388,36 @@ static void neighbour_vertices(const or_ctx *c, int64_t i, int a, double v[4][3]
 /* averages of the von Neumann neighbours                                   */
 /* ======================================================================== */
 
+/* No-slip walls (Sec. 4.4): the velocity is prescribed on both kinds, the
+ * temperature too on isothermal walls, so momentum is constrained at every
+ * no-slip face and the energy at the isothermal ones; the density never. */
+static int face_constrains(const or_ctx *c, int64_t f, int q)
+{
+    if (c->fcell[f][1] >= 0) return 0;
+    int t = c->ftag[f];
+    if (t != TAG_NOSLIP_ADIABATIC && t != TAG_NOSLIP_ISOTHERMAL) return 0;
+    if (q >= 1 && q <= 3) return 1;
+    return q == 4 && t == TAG_NOSLIP_ISOTHERMAL;
+}
+
+/* the prescribed value of component q at a point of wall face f, from the
+ * density reconstructed there: rho U_wall, or rho (|U_wall|^2 / 2 +
+ * T_wall / (gamma - 1)) with T = p / rho */
+static double wall_value(const or_ctx *c, int64_t f, int q, double rho)
+{
+    const double *u = c->fwu[f];
+    if (q <= 3) return rho * u[q - 1];
+    return rho * (0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) + c->cfg.wall_T / (c->cfg.gamma - 1.0));
+}
+
 /* Boundary cells (Sec. 4.4, reconstruction for the boundary cells): with
  * fewer than three neighbours the cell's own averaged gradient serves as the
- * slopes; a singular least-squares matrix gives P^1 = P^0 (zero slopes). */
+ * slopes; a singular least-squares matrix gives P^1 = P^0 (zero slopes).
+ * Components constrained at no-slip faces (density first, then momentum and
+ * energy from the reconstructed density) are fitted by constrained least
+ * squares with one equality row at each constrained face's centre, if the
+ * neighbours and constraints number at least three and the constraints at
+ * most three. */
 static void slopes_cell(const or_ctx *c, int64_t i, const double *W, const double *gW, double b[NC][3])
 {
     int64_t n = c->nc;
@@ -412,18 +448,55 @@ static void slopes_cell(const or_ctx *c, int64_t i, const double *W, const doubl
             for (int k = 0; k < nn; ++k) t += D[k][r] * (W[q * n + mm[k]] - W[q * n + i]);
             B[r * NC + q] = t;
         }
+    double A0[9];
+    memcpy(A0, A, sizeof(A));
     if (nn < 3) {
         for (int q = 0; q < NC; ++q)
             for (int d = 0; d < 3; ++d) b[q][d] = gW ? gW[(3 * q + d) * n + i] : 0.0;
-        return;
-    }
-    if (gepp(3, NC, A, B) != 0) {
+    } else if (gepp(3, NC, A, B) != 0) {
         for (int q = 0; q < NC; ++q)
             for (int d = 0; d < 3; ++d) b[q][d] = 0.0;
-        return;
+    } else {
+        for (int q = 0; q < NC; ++q)
+            for (int d = 0; d < 3; ++d) b[q][d] = B[d * NC + q] / h; /* back to physical units */
     }
-    for (int q = 0; q < NC; ++q)
-        for (int d = 0; d < 3; ++d) b[q][d] = B[d * NC + q] / h; /* back to physical units */
+    /* no-slip walls: the constrained components, after the density */
+    for (int q = 1; q < NC; ++q) {
+        int64_t fl[4];
+        int ncon = 0;
+        for (int a = 0; a < 4; ++a)
+            if (face_constrains(c, c->cface[i][a], q)) fl[ncon++] = c->cface[i][a];
+        if (ncon == 0 || ncon > 3) continue; /* more than three: the plain fit above */
+        if (nn + ncon < 3) {
+            for (int d = 0; d < 3; ++d) b[q][d] = gW ? gW[(3 * q + d) * n + i] : 0.0;
+            continue;
+        }
+        /* KKT system [D^T D  C^T; C  0] [b'; lambda] = [D^T (Q_m - Q_0); e] */
+        int N = 3 + ncon;
+        double K[36], R[6];
+        memset(K, 0, sizeof(K));
+        for (int r = 0; r < 3; ++r) {
+            for (int s2 = 0; s2 < 3; ++s2) K[r * N + s2] = A0[3 * r + s2];
+            double t = 0;
+            for (int k = 0; k < nn; ++k) t += D[k][r] * (W[q * n + mm[k]] - W[q * n + i]);
+            R[r] = t;
+        }
+        for (int j = 0; j < ncon; ++j) {
+            int64_t f = fl[j];
+            double x[3], rho = W[i];
+            for (int d = 0; d < 3; ++d) {
+                x[d] = (c->fgp[f][0][d] + c->fgp[f][1][d] + c->fgp[f][2][d]) / 3.0 - c->cen[i][d];
+                rho += b[0][d] * x[d];
+            }
+            for (int r = 0; r < 3; ++r) K[r * N + 3 + j] = K[(3 + j) * N + r] = x[r] / h;
+            R[3 + j] = wall_value(c, f, q, rho) - W[q * n + i];
+        }
+        if (gepp(N, 1, K, R) != 0) {
+            for (int d = 0; d < 3; ++d) b[q][d] = 0.0;
+        } else {
+            for (int d = 0; d < 3; ++d) b[q][d] = R[d] / h;
+        }
+    }
 }
 
 int or_slopes(or_ctx *c, const double *W, const double *gW, double *b)
@@ -488,19 +561,16 @@ static double mono_lookup(const double mono[10], int ex, int ey, int ez)
     return mono[9];
 }
 
-/* Constrained least squares for P^2 (eqs. large-stenci-condition-1/2):
- * equality rows reproduce the neighbour averages, least-squares rows the
- * neighbour averaged derivatives; the cell's own averaged derivative is not
- * used.  Solved through the KKT system.  Returns per component the
- * polynomial about the centroid. */
-static void p2_cell(const or_ctx *c, int64_t i, const double *W, const double *gW,
-                    qpoly_t P2[NC])
+/* Rows of the step-2 fit of cell i (eqs. large-stenci-condition-1/2), in
+ * y = (x - c_0) / h for the basis y^k - <y^k>_0: E and e, the neighbour
+ * averages (E[.][k] = <y^k>_m - <y^k>_0, e = Q_m - Q_0 per component); A and
+ * bb, the neighbour averaged derivatives (bb = h dQ_m/dx_j). */
+static void p2_rows(const or_ctx *c, int64_t i, const double *W, const double *gW, double mono0[10],
+                    double E[4][9], double e[4][NC], double A[12][9], double bb[12][NC], int *ne_, int *na_)
 {
     int64_t n = c->nc;
     double h = cbrt(c->vol[i]);
-    double mono0[10];
     tet_avg_monomials(c->cv[i], c->cen[i], h, mono0);
-    double E[4][9], e[4][NC], A[12][9], bb[12][NC];
     int ne = 0, na = 0;
     for (int a = 0; a < 4; ++a) {
         int64_t m = c->nbr[i][a];
@@ -525,6 +595,63 @@ static void p2_cell(const or_ctx *c, int64_t i, const double *W, const double *g
             ++na;
         }
     }
+    *ne_ = ne;
+    *na_ = na;
+}
+
+/* The first-order polynomial fitted to the step-2 data (neighbour averages
+ * and averaged derivatives) by least squares, normal equations on the three
+ * linear coefficients: the fallback of Sec. 4.4 for component q. */
+static void p2_linear(double E[4][9], double e[4][NC], double A[12][9], double bb[12][NC], int ne, int na,
+                      double h, double Q0, int q, qpoly_t *p)
+{
+    double A3[9], B3[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int s2 = 0; s2 < 3; ++s2) {
+            double t = 0.0;
+            for (int k = 0; k < ne; ++k) t += E[k][r] * E[k][s2];
+            for (int k = 0; k < na; ++k) t += A[k][r] * A[k][s2];
+            A3[3 * r + s2] = t;
+        }
+        double t = 0.0;
+        for (int k = 0; k < ne; ++k) t += E[k][r] * e[k][q];
+        for (int k = 0; k < na; ++k) t += A[k][r] * bb[k][q];
+        B3[r] = t;
+    }
+    int rc3 = (ne + na) >= 3 ? gepp(3, 1, A3, B3) : -1;
+    memset(p, 0, sizeof(*p));
+    p->c0 = Q0;
+    if (rc3 == 0)
+        for (int d = 0; d < 3; ++d) p->G[d] = B3[d] / h;
+}
+
+/* P^2(y) = Q0 + sum_k a_k (y^k - <y^k>_0), back to physical r = h y */
+static void p2_from_basis(const double ak[9], const double mono0[10], double h, double Q0, qpoly_t *p)
+{
+    p->c0 = Q0;
+    for (int k = 3; k < 9; ++k) p->c0 -= ak[k] * mono_lookup(mono0, KEXP[k][0], KEXP[k][1], KEXP[k][2]);
+    for (int d = 0; d < 3; ++d) p->G[d] = ak[d] / h;
+    p->H[0] = 2.0 * ak[3] / (h * h);
+    p->H[1] = 2.0 * ak[4] / (h * h);
+    p->H[2] = 2.0 * ak[5] / (h * h);
+    p->H[3] = ak[6] / (h * h);
+    p->H[4] = ak[7] / (h * h);
+    p->H[5] = ak[8] / (h * h);
+}
+
+/* Constrained least squares for P^2 (eqs. large-stenci-condition-1/2):
+ * equality rows reproduce the neighbour averages, least-squares rows the
+ * neighbour averaged derivatives; the cell's own averaged derivative is not
+ * used.  Solved through the KKT system.  Returns per component the
+ * polynomial about the centroid. */
+static void p2_cell(const or_ctx *c, int64_t i, const double *W, const double *gW,
+                    qpoly_t P2[NC])
+{
+    int64_t n = c->nc;
+    double h = cbrt(c->vol[i]);
+    double mono0[10], E[4][9], e[4][NC], A[12][9], bb[12][NC];
+    int ne, na;
+    p2_rows(c, i, W, gW, mono0, E, e, A, bb, &ne, &na);
     /* KKT: [A^T A  E^T; E  0] [a; lambda] = [A^T b; e] */
     int N = 9 + ne;
     double K[13 * 13], B[13 * NC];
@@ -548,55 +675,86 @@ static void p2_cell(const or_ctx *c, int64_t i, const double *W, const double *g
         for (int q = 0; q < NC; ++q) B[(9 + s) * NC + q] = e[s][q];
     }
     int rc = ne >= 3 ? gepp(N, NC, K, B) : -1;
-    if (rc != 0) {
-        /* boundary cells with fewer than three neighbours, or a singular
-         * system (Sec. 4.4): the first-order polynomial fitted to the same
-         * data (neighbour averages and averaged derivatives) by least squares,
-         * normal equations on the three linear coefficients */
-        double A3[9], B3[3 * NC];
-        memset(A3, 0, sizeof(A3));
-        memset(B3, 0, sizeof(B3));
-        for (int r = 0; r < 3; ++r) {
-            for (int s2 = 0; s2 < 3; ++s2) {
-                double t = 0.0;
-                for (int k = 0; k < ne; ++k) t += E[k][r] * E[k][s2];
-                for (int k = 0; k < na; ++k) t += A[k][r] * A[k][s2];
-                A3[3 * r + s2] = t;
-            }
-            for (int q = 0; q < NC; ++q) {
-                double t = 0.0;
-                for (int k = 0; k < ne; ++k) t += E[k][r] * e[k][q];
-                for (int k = 0; k < na; ++k) t += A[k][r] * bb[k][q];
-                B3[r * NC + q] = t;
-            }
-        }
-        int rc3 = (ne + na) >= 3 ? gepp(3, NC, A3, B3) : -1;
-        for (int q = 0; q < NC; ++q) {
-            qpoly_t *p = &P2[q];
-            memset(p, 0, sizeof(*p));
-            p->c0 = W[q * n + i];
-            if (rc3 == 0)
-                for (int d = 0; d < 3; ++d) p->G[d] = B3[d * NC + q] / h;
-        }
-        return;
-    }
     for (int q = 0; q < NC; ++q) {
-        qpoly_t *p = &P2[q];
-        double Q0 = W[q * n + i];
+        if (rc != 0) {
+            /* boundary cells with fewer than three neighbours, or a singular
+             * system (Sec. 4.4): the linear least-squares fallback */
+            p2_linear(E, e, A, bb, ne, na, h, W[q * n + i], q, &P2[q]);
+            continue;
+        }
         double ak[9];
         for (int k = 0; k < 9; ++k) ak[k] = B[k * NC + q];
-        /* P^2(y) = Q0 + sum_k a_k (y^k - <y^k>_0); back to physical r = h y */
-        p->c0 = Q0;
-        for (int k = 3; k < 9; ++k)
-            p->c0 -= ak[k] * mono_lookup(mono0, KEXP[k][0], KEXP[k][1], KEXP[k][2]);
-        for (int d = 0; d < 3; ++d) p->G[d] = ak[d] / h;
-        p->H[0] = 2.0 * ak[3] / (h * h);
-        p->H[1] = 2.0 * ak[4] / (h * h);
-        p->H[2] = 2.0 * ak[5] / (h * h);
-        p->H[3] = ak[6] / (h * h);
-        p->H[4] = ak[7] / (h * h);
-        p->H[5] = ak[8] / (h * h);
+        memset(&P2[q], 0, sizeof(qpoly_t));
+        p2_from_basis(ak, mono0, h, W[q * n + i], &P2[q]);
     }
+}
+
+/* Sec. 4.4, step 2, component q of a cell with no-slip faces that constrain
+ * it: weighted constrained least squares whose equality rows are the wall
+ * values at the Gauss points of those faces (three per face), from the
+ * cell's reconstructed density Rrho there, and whose least-squares rows are
+ * all the neighbour data (averages and averaged derivatives).  With more
+ * than nine constraints, fewer than nine data and constraints together, or a
+ * singular system: the linear least-squares fallback.  P is left unchanged
+ * when no face constrains q. */
+static void p2_wall(const or_ctx *c, int64_t i, const double *W, const double *gW, int q,
+                    const qpoly_t *Rrho, qpoly_t *P)
+{
+    int64_t n = c->nc;
+    int64_t fl[4];
+    int nfc = 0;
+    for (int a = 0; a < 4; ++a)
+        if (face_constrains(c, c->cface[i][a], q)) fl[nfc++] = c->cface[i][a];
+    if (nfc == 0) return;
+    double h = cbrt(c->vol[i]), Q0 = W[q * n + i];
+    double mono0[10], E[4][9], e[4][NC], A[12][9], bb[12][NC];
+    int ne, na;
+    p2_rows(c, i, W, gW, mono0, E, e, A, bb, &ne, &na);
+    int ng = 3 * nfc;
+    if (ng > 9 || 4 * ne + ng < 9) {
+        p2_linear(E, e, A, bb, ne, na, h, Q0, q, P);
+        return;
+    }
+    int N = 9 + ng;
+    double K[18 * 18], B[18];
+    memset(K, 0, sizeof(K));
+    for (int r = 0; r < 9; ++r) {
+        for (int s2 = 0; s2 < 9; ++s2) {
+            double t = 0.0;
+            for (int k = 0; k < ne; ++k) t += E[k][r] * E[k][s2];
+            for (int k = 0; k < na; ++k) t += A[k][r] * A[k][s2];
+            K[r * N + s2] = t;
+        }
+        double t = 0.0;
+        for (int k = 0; k < ne; ++k) t += E[k][r] * e[k][q];
+        for (int k = 0; k < na; ++k) t += A[k][r] * bb[k][q];
+        B[r] = t;
+    }
+    for (int j = 0; j < nfc; ++j) {
+        int64_t f = fl[j];
+        for (int g = 0; g < 3; ++g) {
+            int row = 9 + 3 * j + g;
+            double x[3], y[3];
+            for (int d = 0; d < 3; ++d) {
+                x[d] = c->fgp[f][g][d] - c->cen[i][d];
+                y[d] = x[d] / h;
+            }
+            for (int k = 0; k < 9; ++k) {
+                double v = 1.0;
+                for (int d = 0; d < 3; ++d)
+                    for (int t = 0; t < KEXP[k][d]; ++t) v *= y[d];
+                v -= mono_lookup(mono0, KEXP[k][0], KEXP[k][1], KEXP[k][2]);
+                K[k * N + row] = K[row * N + k] = v;
+            }
+            B[row] = wall_value(c, f, q, quad_eval(Rrho, x)) - Q0;
+        }
+    }
+    if (gepp(N, 1, K, B) != 0) {
+        p2_linear(E, e, A, bb, ne, na, h, Q0, q, P);
+        return;
+    }
+    memset(P, 0, sizeof(*P));
+    p2_from_basis(B, mono0, h, Q0, P);
 }
 
 /* eq. smooth-indicator for a polynomial about the centroid of cell i, with
@@ -711,8 +869,6 @@ static int reconstruct_cell(const or_ctx *c, int64_t i, const double *W, const d
     if (cf->order == 2) return reconstruct_cell_2nd(c, i, W, slopes, R);
     qpoly_t P2[NC];
     p2_cell(c, i, W, gW, P2);
-    if (p2out)
-        for (int q = 0; q < NC; ++q) p2out[q] = P2[q];
     const double g22 = cf->lw2[0], g12 = cf->lw2[1], g02 = cf->lw2[2];
     const double g11 = cf->lw1[0], g01 = cf->lw1[1];
     const double eps = cf->eps_weno;
@@ -723,6 +879,9 @@ static int reconstruct_cell(const or_ctx *c, int64_t i, const double *W, const d
         P0.c0 = Q0;
         qpoly_t P1 = P0;
         for (int d = 0; d < 3; ++d) P1.G[d] = slopes[(3 * q + d) * n + i];
+        /* no-slip walls: momentum and energy from the reconstructed density */
+        if (q > 0) p2_wall(c, i, W, gW, q, &R[0], &P2[q]);
+        if (p2out) p2out[q] = P2[q];
         if (!cf->nonlinear) { R[q] = P2[q]; continue; }
         /* indicators of P^1 and P^2 */
         double beta1 = smoothness(c, i, &P1, 1);
@@ -1325,6 +1484,51 @@ static void mirror_ghost(const double n[3], const double W[5], const double gW[1
         }
 }
 
+/* No-slip wall ghost (Sec. 4.4).  The interior point state is mapped to
+ * primitive variables with the paper's chain rule (T = p / rho); the ghost
+ * reflects it through the wall point: velocity 2 U_wall - U with unchanged
+ * derivatives, the same pressure with reversed derivatives, and the same
+ * temperature with reversed derivatives (adiabatic) or 2 T_wall - T with
+ * unchanged derivatives (isothermal); then back to conservative variables by
+ * the same chain rule.  At rest on an adiabatic wall this is the paper's
+ * (rho, -rho U, rho E) with unchanged momentum derivatives and reversed
+ * density and energy derivatives. */
+static void noslip_ghost(const or_config *cf, int iso, const double uw[3], const double W[5],
+                         const double gW[15], double Wg[5], double gWg[15])
+{
+    double g1 = cf->gamma - 1.0;
+    double rho = W[0], U[3], Q = 0.0;
+    for (int d = 0; d < 3; ++d) { U[d] = W[1 + d] / rho; Q += 0.5 * U[d] * U[d]; }
+    double p = g1 * (W[4] - rho * Q), T = p / rho;
+    double Ug[3], Qg = 0.0;
+    for (int d = 0; d < 3; ++d) { Ug[d] = 2.0 * uw[d] - U[d]; Qg += 0.5 * Ug[d] * Ug[d]; }
+    double Tg = iso ? 2.0 * cf->wall_T - T : T, pg = p, rhog = pg / Tg;
+    Wg[0] = rhog;
+    for (int d = 0; d < 3; ++d) Wg[1 + d] = rhog * Ug[d];
+    Wg[4] = rhog * Qg + pg / g1;
+    for (int j = 0; j < 3; ++j) { /* derivatives along axis j */
+        double drho = gW[j], dU[3], dQ = 0.0;
+        for (int d = 0; d < 3; ++d) { dU[d] = (gW[3 * (1 + d) + j] - drho * U[d]) / rho; dQ += U[d] * dU[d]; }
+        double dp = g1 * (gW[12 + j] - drho * Q - rho * dQ);
+        double dT = (dp - drho * T) / rho;
+        double dTg = iso ? dT : -dT, dpg = -dp, dQg = 0.0;
+        double drhog = (dpg - dTg * rhog) / Tg;
+        gWg[j] = drhog;
+        for (int d = 0; d < 3; ++d) { gWg[3 * (1 + d) + j] = drhog * Ug[d] + rhog * dU[d]; dQg += Ug[d] * dU[d]; }
+        gWg[12 + j] = drhog * Qg + rhog * dQg + dpg / g1;
+    }
+}
+
+int or_wall_ghost(const or_config *cf, int32_t tag, const double n[3], const double uw[3], const double W[5],
+                  const double gW[15], double Wg[5], double gWg[15])
+{
+    if (tag == TAG_SLIP) mirror_ghost(n, W, gW, Wg, gWg);
+    else if (tag == TAG_NOSLIP_ADIABATIC || tag == TAG_NOSLIP_ISOTHERMAL)
+        noslip_ghost(cf, tag == TAG_NOSLIP_ISOTHERMAL, uw, W, gW, Wg, gWg);
+    else return -1;
+    return 0;
+}
+
 static int face_terms(or_ctx *c, const double *coef, double dt, double *out)
 {
     int64_t n = c->nc, nf = c->nf;
@@ -1352,7 +1556,8 @@ static int face_terms(or_ctx *c, const double *coef, double dt, double *out)
                     quad_grad(&p, rr, gWr + 3 * k);
                 }
             }
-            if (R < 0) mirror_ghost(c->fnorm[f], Wl, gWl, Wr, gWr);
+            if (R < 0)
+                or_wall_ghost(&c->cfg, c->ftag[f], c->fnorm[f], c->fwu[f], Wl, gWl, Wr, gWr);
             double o[20];
             if (gks_point(&c->cfg, c->fnorm[f], Wl, gWl, Wr, gWr, dt, o)) { err |= 1; continue; }
             /* eq. linear-system: F = (4 F(dt/2) - F(dt)) / dt,

@@ -37,15 +37,19 @@ typedef struct {
                          (P^1 and P^0 only, eq. final_weno_expression-2nd) */
     int32_t flux;     /* 0: the full distribution of eq. 2nd-flux; 1: its smooth-flow form,
                          eq. 2nd-smooth-flux */
+    double wall_T;    /* temperature p / rho of isothermal no-slip walls */
 } or_config;
 
 typedef struct or_ctx or_ctx;
 
-/* Build the oracle's mesh and geometry.  Returns NULL on a malformed mesh. */
+/* Build the oracle's mesh and geometry.  Wall faces (face_cell[2f+1] = -1)
+ * carry tag 2 (slip), 3 (no-slip adiabatic) or 4 (no-slip isothermal);
+ * face_wall_u[3f..3f+2] is a no-slip face's wall velocity (NULL: walls at
+ * rest).  Returns NULL on a malformed mesh. */
 or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
                   int64_t n_cell, const int64_t *tet, int64_t n_face,
                   const int64_t *face_vert, const int64_t *face_cell,
-                  const int32_t *face_tag, const double *face_shift);
+                  const int32_t *face_tag, const double *face_shift, const double *face_wall_u);
 void or_destroy(or_ctx *ctx);
 int or_set_threads(int n);
 
@@ -56,9 +60,15 @@ int or_geometry(const or_ctx *ctx, double *vol, double *cen, double *mom2, doubl
  * Gauss points [3 points][3][nf]. */
 int or_face_geometry(const or_ctx *ctx, double *area, double *normal, double *gp);
 
+/* The ghost state of a wall point (tag 2, 3 or 4; n the outward unit normal,
+ * uw the wall velocity), global frame. */
+int or_wall_ghost(const or_config *cfg, int32_t tag, const double n[3], const double uw[3], const double W[5],
+                  const double gW[15], double Wg[5], double gWg[15]);
+
 /* Reconstruction step 1: slopes b[15][n] (component c, direction d at 3c+d).
  * A cell with fewer than three neighbours (at walls) takes its own averaged
- * gradient gW (zero if gW is NULL). */
+ * gradient gW (zero if gW is NULL); components constrained at no-slip faces
+ * take the constrained fit. */
 int or_slopes(or_ctx *ctx, const double *W, const double *gW, double *b);
 /* Reconstruction step 2: final polynomial R(x) = c0 + G.r + 1/2 r^T H r about
  * the centroid, coef[50][n] = per component (c0, Gx, Gy, Gz, Hxx, Hyy, Hzz,

@@ -16,6 +16,7 @@ Array conventions (the library's C-ABI uses the same ones):
 * ``face_tag``   int32   [n_face]      FACE_* below
 * ``face_shift`` float64 [n_face, 3]   translation that carries the neighbour's
   geometry into the owner's frame (non-zero only across a periodic seam)
+* ``face_wall_u`` float64 [n_face, 3]  velocity of a no-slip wall face (optional)
 
 Cell fields are component-major: ``W[5, n_cell]`` holds (rho, rho u, rho v,
 rho w, rho E) and ``gW[15, n_cell]`` holds the cell-averaged gradient, with
@@ -31,6 +32,8 @@ import numpy as np
 FACE_INTERIOR = 0
 FACE_PERIODIC = 1
 FACE_SLIP = 2
+FACE_NOSLIP_ADIABATIC = 3
+FACE_NOSLIP_ISOTHERMAL = 4
 
 
 @dataclass
@@ -44,6 +47,7 @@ class TetMesh:
     length: float
     n: int
     periodic: bool
+    face_wall_u: np.ndarray | None = None  # [n_face, 3] velocity of no-slip wall faces (None: at rest)
 
     @property
     def n_cell(self) -> int:
@@ -180,6 +184,31 @@ def kuhn_cube_mesh(n: int, length: float = 1.0, jitter: float = 0.1, seed: int =
                    face_tag=np.ascontiguousarray(face_tag[fo]),
                    face_shift=np.ascontiguousarray(face_shift[fo]),
                    length=float(length), n=int(n), periodic=bool(periodic))
+
+
+def with_walls(mesh: TetMesh, tags: dict, velocity: dict | None = None) -> TetMesh:
+    """The walled cube mesh with its six sides retagged: ``tags`` maps a side
+    name ("x0", "x1", "y0", "y1", "z0", "z1": the plane x = 0, x = length,
+    ...) to a FACE_* wall tag (sides not named stay slip walls); ``velocity``
+    maps a side to its wall velocity (3 components; others at rest).  A side
+    is found from the mean of its face's vertices."""
+    if mesh.periodic:
+        raise ValueError("a periodic mesh has no walls")
+    wall = mesh.face_cell[:, 1] < 0
+    cen = mesh.xyz[mesh.face_vert].mean(axis=1)
+    tag = mesh.face_tag.copy()
+    wu = np.zeros((mesh.n_face, 3))
+    tol = 1e-9 * mesh.length
+    for name in set(tags) | set(velocity or {}):
+        axis, end = "xyz".index(name[0]), float(name[1]) * mesh.length
+        on = wall & (np.abs(cen[:, axis] - end) < tol)
+        if name in tags:
+            tag[on] = tags[name]
+        if velocity and name in velocity:
+            wu[on] = np.asarray(velocity[name], np.float64)
+    return TetMesh(xyz=mesh.xyz, tet=mesh.tet, face_vert=mesh.face_vert, face_cell=mesh.face_cell,
+                   face_tag=np.ascontiguousarray(tag), face_shift=mesh.face_shift, length=mesh.length,
+                   n=mesh.n, periodic=False, face_wall_u=np.ascontiguousarray(wu))
 
 
 # ----------------------------------------------------------------------------
