@@ -39,6 +39,12 @@ struct gks_ctx {
     bool fp32 = false;              // FP32-bulk form
     std::vector<int> cperm, fperm;  // internal -> caller
     std::vector<int> nbr, cface, fcell, bslot, bmode;
+    // no-slip walls: wall faces' tags and velocities (internal wall order),
+    // wall cells, their modes and operators (host copies until bound)
+    int nwc = 0;
+    bool noslip = false;
+    std::vector<int> wtag, wcell, wmode;
+    std::vector<double> wvel, wop;
     std::vector<double> M1, M2, geoR, geoD, fgeo, fnrm;
     // workspace
     bool bound = false;
@@ -174,6 +180,42 @@ bool pseudo_inverse(int m, int n, const double *A, double *Ap)
     return true;
 }
 
+// A X = I for a square n x n matrix (row-major, destroyed) by Gauss-Jordan
+// elimination with partial pivoting; Ainv n x n.  False if a pivot vanishes.
+bool invert(int n, double *A, double *Ainv)
+{
+    for (int r = 0; r < n; ++r)
+        for (int t = 0; t < n; ++t) Ainv[r * n + t] = r == t ? 1.0 : 0.0;
+    double scale = 0.0;
+    for (int k = 0; k < n * n; ++k) scale = std::max(scale, std::fabs(A[k]));
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (std::fabs(A[r * n + col]) > std::fabs(A[piv * n + col])) piv = r;
+        if (!(std::fabs(A[piv * n + col]) > 1e-13 * scale)) return false;
+        if (piv != col)
+            for (int t = 0; t < n; ++t) {
+                std::swap(A[piv * n + t], A[col * n + t]);
+                std::swap(Ainv[piv * n + t], Ainv[col * n + t]);
+            }
+        const double ip = 1.0 / A[col * n + col];
+        for (int t = 0; t < n; ++t) {
+            A[col * n + t] *= ip;
+            Ainv[col * n + t] *= ip;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            const double fct = A[r * n + col];
+            if (fct == 0.0) continue;
+            for (int t = 0; t < n; ++t) {
+                A[r * n + t] -= fct * A[col * n + t];
+                Ainv[r * n + t] -= fct * Ainv[col * n + t];
+            }
+        }
+    }
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // geometry helpers
 // ---------------------------------------------------------------------------
@@ -217,11 +259,12 @@ struct Layout {
 enum Slot {
     S_NBR, S_CFACE, S_M1, S_M2, S_GEOR, S_GEOD, S_FCELL, S_FGEO, S_FNRM, S_W, S_GW, S_WN, S_LN, S_LTN,
     S_SLOPES, S_COEF, S_FLAG, S_FF, S_FT, S_FW0, S_FWS, S_RED, S_NONPHYS, S_CPERM, S_FPERM,
-    S_STAGING, S_ISTAGING, S_BSLOT, S_BMODE, S_COUNT
+    S_STAGING, S_ISTAGING, S_BSLOT, S_BMODE, S_WTAG, S_WVEL, S_WCELL, S_WMODE, S_WOP, S_COUNT
 };
 
-// bs: bytes of a bulk element (8 in FP64, 4 in FP32-bulk)
-Layout make_layout(size_t nc, size_t nf, size_t bs)
+// bs: bytes of a bulk element (8 in FP64, 4 in FP32-bulk); nwf wall faces,
+// nwc no-slip wall cells
+Layout make_layout(size_t nc, size_t nf, size_t bs, size_t nwf, size_t nwc)
 {
     const size_t sz[S_COUNT] = {
         4 * nc * sizeof(int), 4 * nc * sizeof(int), 12 * nc * bs,
@@ -231,7 +274,8 @@ Layout make_layout(size_t nc, size_t nf, size_t bs)
         5 * nc * 8, 15 * nc * 8, 5 * nc * 8, 5 * nc * 8, 5 * nc * 8, 15 * nc * bs, 50 * nc * bs,
         nc * sizeof(int), 5 * nf * bs, 5 * nf * bs, 5 * nf * bs, 5 * nf * bs,
         (8 + 5 * (size_t)gks::kRedBlocks) * 8, 64, nc * sizeof(int), nf * sizeof(int),
-        std::max(50 * nc, 20 * nf) * 8, nc * sizeof(int), 4 * nc * sizeof(int), nc * sizeof(int)};
+        std::max(50 * nc, 20 * nf) * 8, nc * sizeof(int), 4 * nc * sizeof(int), nc * sizeof(int),
+        nwf * sizeof(int), 3 * nwf * bs, nwc * sizeof(int), 4 * nwc * sizeof(int), (size_t)gks::kWallRows * nwc * bs};
     Layout L;
     size_t o = 0;
     for (int k = 0; k < S_COUNT; ++k) {
@@ -260,10 +304,28 @@ bool config_ok(const gks_config *c, std::string &why)
     if (c->precision != GKS_FP64 && c->precision != GKS_FP32_BULK) { why = "unknown precision"; return false; }
     if (c->order != 2 && c->order != 3) { why = "order must be 2 or 3"; return false; }
     if (c->flux != GKS_FLUX_FULL && c->flux != GKS_FLUX_SMOOTH) { why = "unknown flux"; return false; }
+    if (!(c->wall_T > 0.0) || !std::isfinite(c->wall_T)) { why = "wall_T must be positive"; return false; }
     return true;
 }
 
 }  // namespace
+
+// Reconstruction steps 1 and 2 (Secs. 4.1-4.4): every cell, then the
+// constrained fits of the no-slip wall cells.
+static hipError_t slopes_step(const gks::DevMesh &m, const gks::DevState &s, const gks::Params &p, bool fp32,
+                              hipStream_t st)
+{
+    hipError_t e = gks::launch_slopes(m, s, fp32, st);
+    if (e == hipSuccess && m.nwc > 0) e = gks::launch_wall_slopes(m, s, p, fp32, st);
+    return e;
+}
+static hipError_t reconstruct_step(const gks::DevMesh &m, const gks::DevState &s, const gks::Params &p, bool fp32,
+                                   hipStream_t st)
+{
+    hipError_t e = gks::launch_reconstruct(m, s, p, fp32, st);
+    if (e == hipSuccess && m.nwc > 0) e = gks::launch_wall_reconstruct(m, s, p, fp32, st);
+    return e;
+}
 
 // Record an event on the context's stream when timing is on.
 static gks_status mark(gks_ctx *c)
@@ -315,6 +377,7 @@ void gks_default_config(gks_config *cfg)
     cfg->precision = GKS_FP64;
     cfg->order = 3;
     cfg->flux = GKS_FLUX_FULL;
+    cfg->wall_T = 1.0;
 }
 
 gks_status gks_create(const gks_config *cfg, gks_ctx **out)
@@ -351,6 +414,9 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
     if (m->n_cell > INT_MAX / 64 || m->n_face > INT_MAX / 64)
         return fail(c, GKS_E_INVAL, "mesh too large for 32-bit indexing");
     const int nc = (int)m->n_cell, nf = (int)m->n_face;
+    c->wcell.clear();
+    c->wmode.clear();
+    c->wop.clear();
 
     // --- cells: vertices, volume, centroid -------------------------------
     std::vector<double> cen(3 * (size_t)nc), vol(nc);
@@ -378,10 +444,17 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
         const int64_t L = m->face_cell[2 * (size_t)f], R = m->face_cell[2 * (size_t)f + 1];
         const int tag = m->face_tag[f];
         if (L < 0 || L >= nc || R >= nc || R == L) return fail(c, GKS_E_MESH, "bad face_cell entry");
-        if (tag != GKS_FACE_INTERIOR && tag != GKS_FACE_PERIODIC && tag != GKS_FACE_SLIP)
+        if (tag != GKS_FACE_INTERIOR && tag != GKS_FACE_PERIODIC && tag != GKS_FACE_SLIP &&
+            tag != GKS_FACE_NOSLIP_ADIABATIC && tag != GKS_FACE_NOSLIP_ISOTHERMAL)
             return fail(c, GKS_E_MESH, "unknown face tag");
-        if ((R < 0) != (tag == GKS_FACE_SLIP))
-            return fail(c, GKS_E_MESH, "a wall face needs face_cell[2f+1] = -1 and the slip tag");
+        const bool wall_tag = tag == GKS_FACE_SLIP || tag == GKS_FACE_NOSLIP_ADIABATIC ||
+                              tag == GKS_FACE_NOSLIP_ISOTHERMAL;
+        if ((R < 0) != wall_tag)
+            return fail(c, GKS_E_MESH, "a wall face needs face_cell[2f+1] = -1 and a wall tag");
+        if (m->face_wall_u)
+            for (int d = 0; d < 3; ++d)
+                if (!std::isfinite(m->face_wall_u[3 * (size_t)f + d]))
+                    return fail(c, GKS_E_MESH, "face_wall_u is not finite");
         for (int s = 0; s < (R < 0 ? 1 : 2); ++s) {
             const int cell = (int)(s == 0 ? L : R);
             if (nslots[cell] >= 4) return fail(c, GKS_E_MESH, "a cell has more than four faces");
@@ -639,10 +712,10 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
                 }
             }
         }
-        if (!fitted && np > 0) {
-            // fewer than three neighbours or a singular system (boundary cells,
-            // Sec. 4.4): the linear polynomial fitted to the same data in the
-            // least-squares sense; H = 0
+        // the linear polynomial fitted to the step-2 data in the least-squares
+        // sense (H = 0), as rows of a (g, H) operator on d
+        auto linear_fallback = [&](auto put) {
+            if (np == 0) return;
             const int nr = 4 * np;
             double Lr[16 * 3], Lp[3 * 16];
             for (int k = 0; k < np; ++k)
@@ -653,15 +726,145 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
                 for (int d = 0; d < 3; ++d)
                     for (int k = 0; k < np; ++k) {
                         const int a = pres[k];
-                        M2[gks::m2_index(16 * d + a, ii)] = osc[d] * Lp[d * nr + k];
-                        for (int j = 0; j < 3; ++j)
-                            M2[gks::m2_index(16 * d + 4 + 3 * a + j, ii)] = osc[d] * h * Lp[d * nr + np + 3 * k + j];
+                        put(16 * d + a, osc[d] * Lp[d * nr + k]);
+                        for (int j = 0; j < 3; ++j) put(16 * d + 4 + 3 * a + j, osc[d] * h * Lp[d * nr + np + 3 * k + j]);
                     }
+        };
+        if (!fitted) {
+            // fewer than three neighbours or a singular system (boundary cells,
+            // Sec. 4.4)
+            linear_fallback([&](int row, double v) { M2[gks::m2_index(row, ii)] = v; });
+        }
+
+        // no-slip walls (Sec. 4.4): constrained fits of the momentum set (every
+        // no-slip face) and the energy set (isothermal faces)
+        int ws_slot[2][4], ws_n[2] = {0, 0};
+        for (int a = 0; a < 4; ++a) {
+            if (nbr[(size_t)a * nc + ii] >= 0) continue;
+            const int t = m->face_tag[slot_face[4 * (size_t)i + a]];
+            if (t == GKS_FACE_NOSLIP_ADIABATIC || t == GKS_FACE_NOSLIP_ISOTHERMAL) ws_slot[0][ws_n[0]++] = a;
+            if (t == GKS_FACE_NOSLIP_ISOTHERMAL) ws_slot[1][ws_n[1]++] = a;
+        }
+        if (ws_n[0] > 0) {
+            const size_t w = c->wcell.size();
+            c->wcell.push_back(ii);
+            c->wmode.resize(4 * (w + 1), gks::WM_KEEP);
+            c->wop.resize(gks::kWallRows * (w + 1), 0.0);
+            double *op = &c->wop[gks::kWallRows * w];
+            for (int set = 0; set < 2; ++set) {
+                const int ns = ws_n[set];
+                double *o = op + set * gks::WR_SET;
+                // constraint points: face centres (step 1), Gauss points (step 2)
+                double xc[3][3] = {}, xg[9][3] = {}, uf[3][3] = {};
+                for (int j = 0; j < ns && j < 3; ++j) {
+                    const int f = slot_face[4 * (size_t)i + ws_slot[set][j]], jj = finv[f];
+                    for (int d = 0; d < 3; ++d) {
+                        uf[j][d] = m->face_wall_u ? m->face_wall_u[3 * (size_t)f + d] : 0.0;
+                        for (int k = 0; k < 3; ++k) {
+                            xg[3 * j + k][d] = fgeo[(size_t)(gks::F_RL + 3 * k + d) * nf + jj];
+                            xc[j][d] += xg[3 * j + k][d] / 3.0;
+                        }
+                    }
+                }
+                for (int j = 0; j < 3; ++j)
+                    for (int d = 0; d < 3; ++d) {
+                        o[gks::WR_X1 + 3 * j + d] = xc[j][d];
+                        o[gks::WR_U1 + 3 * j + d] = uf[j][d];
+                        for (int k = 0; k < 3; ++k) {
+                            o[gks::WR_X2 + 3 * (3 * j + k) + d] = xg[3 * j + k][d];
+                            o[gks::WR_U2 + 3 * (3 * j + k) + d] = uf[j][d];
+                        }
+                    }
+                // step 1: least squares on the neighbour averages with one
+                // equality row per face centre: [D^T D  C^T; C  0]
+                int &mode1 = c->wmode[4 * w + set];
+                if (ns == 0 || ns > 3) {
+                    mode1 = gks::WM_KEEP;
+                } else if (np + ns < 3) {
+                    mode1 = gks::WM_OWN;
+                } else {
+                    mode1 = gks::WM_FIT;
+                    const int N = 3 + ns;
+                    double K[36] = {}, Ki[36];
+                    for (int r = 0; r < 3; ++r)
+                        for (int t = 0; t < 3; ++t)
+                            for (int k = 0; k < np; ++k) K[r * N + t] += delta[pres[k]][r] * delta[pres[k]][t] / (h * h);
+                    for (int j = 0; j < ns; ++j)
+                        for (int r = 0; r < 3; ++r) K[r * N + 3 + j] = K[(3 + j) * N + r] = xc[j][r] / h;
+                    if (invert(N, K, Ki)) {
+                        for (int d = 0; d < 3; ++d) {
+                            for (int k = 0; k < np; ++k) {
+                                double v = 0.0;
+                                for (int r = 0; r < 3; ++r) v += Ki[d * N + r] * delta[pres[k]][r] / h;
+                                o[gks::WR_K1N + 4 * d + pres[k]] = v / h;
+                            }
+                            for (int j = 0; j < ns; ++j) o[gks::WR_K1C + 3 * d + j] = Ki[d * N + 3 + j] / h;
+                        }
+                    }
+                }
+                // step 2: least squares on the neighbour averages and averaged
+                // derivatives with one equality row per wall Gauss point
+                int &mode2 = c->wmode[4 * w + 2 + set];
+                const int ng = 3 * ns;
+                if (ns == 0) {
+                    mode2 = gks::WM_KEEP;
+                    continue;
+                }
+                mode2 = gks::WM_FIT;
+                bool ok = false;
+                if (ng <= 9 && 4 * np + ng >= 9) {
+                    const int N = 9 + ng;
+                    double K[18 * 18] = {}, Ki[18 * 18];
+                    for (int r = 0; r < 9; ++r)
+                        for (int t = 0; t < 9; ++t) {
+                            double v = 0.0;
+                            for (int k = 0; k < np; ++k) v += E[k][r] * E[k][t];
+                            for (int l = 0; l < 3 * np; ++l) v += A[l][r] * A[l][t];
+                            K[r * N + t] = v;
+                        }
+                    for (int g = 0; g < ng; ++g) {
+                        double y[3], row[9];
+                        for (int d = 0; d < 3; ++d) y[d] = xg[g][d] / h;
+                        for (int d = 0; d < 3; ++d) row[d] = y[d];
+                        for (int t = 0; t < 6; ++t) row[3 + t] = y[QA[t]] * y[QB[t]] - C[t] / (h * h);
+                        for (int r = 0; r < 9; ++r) K[r * N + 9 + g] = K[(9 + g) * N + r] = row[r];
+                    }
+                    if (invert(N, K, Ki)) {
+                        ok = true;
+                        for (int r = 0; r < 9; ++r) {
+                            for (int k = 0; k < np; ++k) {
+                                const int a = pres[k];
+                                double v = 0.0;
+                                for (int t = 0; t < 9; ++t) v += Ki[r * N + t] * E[k][t];
+                                o[gks::WR_K2N + 16 * r + a] = osc[r] * v;
+                                for (int j = 0; j < 3; ++j) {
+                                    double u = 0.0;
+                                    for (int t = 0; t < 9; ++t) u += Ki[r * N + t] * A[3 * k + j][t];
+                                    o[gks::WR_K2N + 16 * r + 4 + 3 * a + j] = osc[r] * h * u;
+                                }
+                            }
+                            for (int g = 0; g < ng; ++g) o[gks::WR_K2C + 9 * r + g] = osc[r] * Ki[r * N + 9 + g];
+                        }
+                    }
+                }
+                if (!ok) linear_fallback([&](int row, double v) { o[gks::WR_K2N + row] = v; });
+            }
         }
     }
 
     int nwall = 0;
     for (int f = 0; f < nf; ++f) nwall += m->face_cell[2 * (size_t)f + 1] < 0 ? 1 : 0;
+    c->wtag.assign(nwall, gks::WALL_SLIP);
+    c->wvel.assign(3 * (size_t)nwall, 0.0);
+    c->noslip = false;
+    for (int j = nf - nwall; j < nf; ++j) {
+        const int f = fperm[j], k = j - (nf - nwall);
+        c->wtag[k] = m->face_tag[f];
+        c->noslip = c->noslip || m->face_tag[f] != GKS_FACE_SLIP;
+        for (int d = 0; d < 3; ++d)
+            c->wvel[(size_t)d * nwall + k] = m->face_wall_u ? m->face_wall_u[3 * (size_t)f + d] : 0.0;
+    }
+    c->nwc = (int)c->wcell.size();
     c->nc = nc;
     c->nf = nf;
     c->nfi = nf - nwall;
@@ -700,7 +903,7 @@ gks_status gks_workspace_bytes(const gks_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return GKS_E_INVAL;
     if (!c->have_mesh) return GKS_E_STATE;
-    *bytes = make_layout(c->nc, c->nf, c->fp32 ? 4 : 8).total;
+    *bytes = make_layout(c->nc, c->nf, c->fp32 ? 4 : 8, c->nf - c->nfi, c->nwc).total;
     return GKS_OK;
 }
 
@@ -710,7 +913,7 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     if (!c->have_mesh) return fail(c, GKS_E_STATE, "no mesh uploaded");
     if (c->bound) return fail(c, GKS_E_STATE, "workspace already bound");
     if (((uintptr_t)dev) & 255) return fail(c, GKS_E_INVAL, "workspace must be 256-byte aligned");
-    const Layout L = make_layout(c->nc, c->nf, c->fp32 ? 4 : 8);
+    const Layout L = make_layout(c->nc, c->nf, c->fp32 ? 4 : 8, c->nf - c->nfi, c->nwc);
     if (bytes < L.total) return fail(c, GKS_E_NOMEM, "workspace too small");
     char *w = (char *)dev;
     auto P = [&](int slot) { return (void *)(w + L.off[slot]); };
@@ -730,6 +933,12 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     dm.fnrm = (const double *)P(S_FNRM);
     dm.bslot = (const int *)P(S_BSLOT);
     dm.bmode = (const int *)P(S_BMODE);
+    dm.wtag = (const int *)P(S_WTAG);
+    dm.wvel = P(S_WVEL);
+    dm.nwc = c->nwc;
+    dm.wcell = (const int *)P(S_WCELL);
+    dm.wmode = (const int *)P(S_WMODE);
+    dm.wop = P(S_WOP);
     ds.W = (double *)P(S_W);
     ds.gW = (double *)P(S_GW);
     ds.Wn = (double *)P(S_WN);
@@ -773,6 +982,24 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     HIP_TRY(c, up((void *)dm.fnrm, c->fnrm.data(), 3 * nf * 8));
     HIP_TRY(c, up((void *)dm.bslot, c->bslot.data(), 4 * nc * sizeof(int)));
     HIP_TRY(c, up((void *)dm.bmode, c->bmode.data(), nc * sizeof(int)));
+    if (!c->wtag.empty()) {
+        HIP_TRY(c, up((void *)dm.wtag, c->wtag.data(), c->wtag.size() * sizeof(int)));
+        HIP_TRY(c, up_bulk(dm.wvel, c->wvel));
+    }
+    if (c->nwc > 0) {
+        // operators per wall cell on the host, [kWallRows][nwc] on the device
+        std::vector<double> wt((size_t)gks::kWallRows * c->nwc);
+        for (int w = 0; w < c->nwc; ++w)
+            for (int r = 0; r < gks::kWallRows; ++r)
+                wt[(size_t)r * c->nwc + w] = c->wop[(size_t)gks::kWallRows * w + r];
+        std::vector<int> wm(4 * (size_t)c->nwc);
+        for (int w = 0; w < c->nwc; ++w)
+            for (int k = 0; k < 4; ++k) wm[(size_t)k * c->nwc + w] = c->wmode[4 * (size_t)w + k];
+        HIP_TRY(c, up((void *)dm.wcell, c->wcell.data(), c->nwc * sizeof(int)));
+        HIP_TRY(c, up((void *)dm.wmode, wm.data(), wm.size() * sizeof(int)));
+        HIP_TRY(c, up_bulk(dm.wop, wt));
+        HIP_TRY(c, hipStreamSynchronize(st));
+    }
     HIP_TRY(c, up(c->d_cperm, c->cperm.data(), nc * sizeof(int)));
     HIP_TRY(c, up(c->d_fperm, c->fperm.data(), nf * sizeof(int)));
     HIP_TRY(c, gks::launch_fill_int(ds.nonphys, 0, st));
@@ -783,6 +1010,11 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     std::vector<int>().swap(c->fcell);
     std::vector<int>().swap(c->bslot);
     std::vector<int>().swap(c->bmode);
+    std::vector<int>().swap(c->wtag);
+    std::vector<int>().swap(c->wcell);
+    std::vector<int>().swap(c->wmode);
+    std::vector<double>().swap(c->wvel);
+    std::vector<double>().swap(c->wop);
     std::vector<double>().swap(c->M1);
     std::vector<double>().swap(c->M2);
     std::vector<double>().swap(c->geoR);
@@ -863,8 +1095,8 @@ static gks_status stage_impl(gks_ctx *c, int stage, double dt, const double *dtp
 {
     gks_status st;
     const hipStream_t s = c->stream;
-    if ((st = timed(c, GKS_K_SLOPES, [&] { return gks::launch_slopes(c->dm, c->ds, c->fp32, s); }))) return st;
-    if ((st = timed(c, GKS_K_RECON, [&] { return gks::launch_reconstruct(c->dm, c->ds, c->par, c->fp32, s); })))
+    if ((st = timed(c, GKS_K_SLOPES, [&] { return slopes_step(c->dm, c->ds, c->par, c->fp32, s); }))) return st;
+    if ((st = timed(c, GKS_K_RECON, [&] { return reconstruct_step(c->dm, c->ds, c->par, c->fp32, s); })))
         return st;
     const int mode = stage == 1 ? gks::FLUX_STAGE1 : gks::FLUX_STAGE2;
     if ((st = timed(c, stage == 1 ? GKS_K_FLUX1 : GKS_K_FLUX2, [&] {
@@ -1033,6 +1265,7 @@ gks_status gks_step_adjoint(gks_ctx *c, double dt, const double *W_n, const doub
     if (!W_n || !gW_n || !Wbar_np1 || !gWbar_np1 || !Wbar_n || !gWbar_n)
         return fail(c, GKS_E_INVAL, "null pointer");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, GKS_E_INVAL, "dt must be positive and finite");
+    if (c->noslip) return fail(c, GKS_E_INVAL, "the adjoint does not cover no-slip walls");
     const hipStream_t s = c->stream;
     const int nc = c->nc;
     const bool f32 = c->fp32;
@@ -1062,16 +1295,16 @@ gks_status gks_step_adjoint(gks_ctx *c, double dt, const double *W_n, const doub
     f1.FWs = a.FWs;
     f1.red = a.red;
     f1.nonphys = a.nonphys;
-    HIP_TRY(c, gks::launch_slopes(dm, f1, f32, s));
-    HIP_TRY(c, gks::launch_reconstruct(dm, f1, c->par, f32, s));
+    HIP_TRY(c, slopes_step(dm, f1, c->par, f32, s));
+    HIP_TRY(c, reconstruct_step(dm, f1, c->par, f32, s));
     HIP_TRY(c, gks::launch_flux(dm, f1, c->par, dt, nullptr, gks::FLUX_STAGE1, f32, s));
     HIP_TRY(c, gks::launch_update(dm, f1, dt, nullptr, 1, f32, s));
     DevState f2 = f1;
     f2.slopes = a.slopes2;
     f2.coef = a.coef2;
     f2.flag = a.flag2;
-    HIP_TRY(c, gks::launch_slopes(dm, f2, f32, s));
-    HIP_TRY(c, gks::launch_reconstruct(dm, f2, c->par, f32, s));
+    HIP_TRY(c, slopes_step(dm, f2, c->par, f32, s));
+    HIP_TRY(c, reconstruct_step(dm, f2, c->par, f32, s));
     // stage 2 in reverse: W^{n+1}, grad W^{n+1} -> W*, grad W*
     gks::AdjRecon r{};
     r.CB = a.CB;
@@ -1161,8 +1394,8 @@ gks_status gks_debug_reconstruct(gks_ctx *c, double *slopes, double *coef, int32
     gks_status st = ready(c, true);
     if (st) return st;
     const hipStream_t s = c->stream;
-    HIP_TRY(c, gks::launch_slopes(c->dm, c->ds, c->fp32, s));
-    HIP_TRY(c, gks::launch_reconstruct(c->dm, c->ds, c->par, c->fp32, s));
+    HIP_TRY(c, slopes_step(c->dm, c->ds, c->par, c->fp32, s));
+    HIP_TRY(c, reconstruct_step(c->dm, c->ds, c->par, c->fp32, s));
     if (slopes && (st = export_rows(c, slopes, c->ds.slopes, c->d_cperm, c->nc, 15, on_device))) return st;
     if (coef && (st = export_rows(c, coef, c->ds.coef, c->d_cperm, c->nc, 50, on_device))) return st;
     if (flag) {
@@ -1184,8 +1417,8 @@ gks_status gks_debug_face_terms(gks_ctx *c, double dt, double *out, int32_t on_d
     if (st) return st;
     if (!out || !(dt > 0.0)) return fail(c, GKS_E_INVAL, "null output or non-positive dt");
     const hipStream_t s = c->stream;
-    HIP_TRY(c, gks::launch_slopes(c->dm, c->ds, c->fp32, s));
-    HIP_TRY(c, gks::launch_reconstruct(c->dm, c->ds, c->par, c->fp32, s));
+    HIP_TRY(c, slopes_step(c->dm, c->ds, c->par, c->fp32, s));
+    HIP_TRY(c, reconstruct_step(c->dm, c->ds, c->par, c->fp32, s));
     HIP_TRY(c, gks::launch_flux(c->dm, c->ds, c->par, dt, nullptr, gks::FLUX_DEBUG, c->fp32, s));
     c->stage1_done = false;  // the face buffers of a pending stage 1 are overwritten
     const int nf = c->nf;

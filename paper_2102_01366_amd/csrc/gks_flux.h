@@ -538,15 +538,73 @@ GKS_HD void slip_ghost(const R w[5], const R g[3][5], R wg[5], R gg[3][5])
     }
 }
 
+// Ghost state of a no-slip wall in the face frame (Sec. 4.4): the interior
+// point state reflected through the wall point in primitive variables (T =
+// p / rho): velocity 2 U_wall - U with unchanged derivatives, the same
+// pressure with reversed derivatives, temperature T with reversed
+// derivatives (adiabatic) or 2 T_wall - T with unchanged ones (isothermal);
+// derivatives converted with the paper's chain rule.  uw is the wall
+// velocity in the face frame; g[j][q] the derivative along axis j.
+template <typename R>
+GKS_HD void noslip_ghost(bool iso, R gamma, R Tw, const R uw[3], const R w[5], const R g[3][5], R wg[5],
+                         R gg[3][5])
+{
+    const R g1 = gamma - R(1), rho = w[0], ir = R(1) / rho;
+    R U[3], Ug[3], Q = R(0), Qg = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        U[a] = w[1 + a] * ir;
+        Ug[a] = R(2) * uw[a] - U[a];
+        Q += R(0.5) * U[a] * U[a];
+        Qg += R(0.5) * Ug[a] * Ug[a];
+    }
+    const R p = g1 * (w[4] - rho * Q), T = p * ir;
+    const R Tg = iso ? R(2) * Tw - T : T, rhog = p / Tg;
+    wg[0] = rhog;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) wg[1 + a] = rhog * Ug[a];
+    wg[4] = rhog * Qg + p / g1;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const R dr = g[j][0];
+        R dU[3], dQ = R(0), dQg = R(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            dU[a] = (g[j][1 + a] - dr * U[a]) * ir;
+            dQ += U[a] * dU[a];
+            dQg += Ug[a] * dU[a];
+        }
+        const R dp = g1 * (g[j][4] - dr * Q - rho * dQ);
+        const R dT = (dp - dr * T) * ir;
+        const R dTg = iso ? dT : -dT;
+        const R drg = (-dp - dTg * rhog) / Tg;
+        gg[j][0] = drg;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gg[j][1 + a] = drg * Ug[a] + rhog * dU[a];
+        gg[j][4] = drg * Qg + rhog * dQg - dp / g1;
+    }
+}
+
+// Boundary data of a wall face for the flux: its WallTag (2 slip, 3 no-slip
+// adiabatic, 4 no-slip isothermal) and, on a no-slip wall, its velocity in
+// the global frame.
+template <typename R>
+struct WallBC {
+    int tag;
+    R u[3];
+};
+
 // Terms of one Gauss point k of a face, weighted by w_k |Gamma| = |Gamma|/3:
 // acc[0] = F_k, acc[1] = dF_k/dt (eq. linear-system), acc[2] = W_k(0),
 // acc[3] = W_k(dt), all in the global frame.  r: the Gauss point relative to
 // the owner centroid; dv: owner centroid minus the neighbour's (translated).
 // On a wall face (no neighbour; cr is not evaluated) the right state is the
-// slip-wall ghost of the left one.
+// ghost of the left one: the slip-wall mirror, or the no-slip reflection
+// when bc says so.
 template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR, bool SMOOTH = false>
 GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, const R r[3], const R dv[3],
-                              const CoefL &cl, const CoefR &cr, R acc[4][5], bool wall = false)
+                              const CoefL &cl, const CoefR &cr, R acc[4][5], bool wall = false,
+                              const WallBC<R> *bc = nullptr)
 {
     const R w = area * R(1.0 / 3.0);
     R T[3][3];
@@ -556,10 +614,16 @@ GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, con
     for (int d = 0; d < 3; ++d) rr[d] = r[d] + dv[d];
     R wl[5], gl[3][5], wr[5], gr[3][5];
     eval_local(cl, r, T, wl, gl);
-    if (wall)
+    if (wall && bc && bc->tag != WALL_SLIP) {
+        R uw[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) uw[a] = T[a][0] * bc->u[0] + T[a][1] * bc->u[1] + T[a][2] * bc->u[2];
+        noslip_ghost(bc->tag == WALL_ISOTHERMAL, R(p.gamma), R(p.wall_T), uw, wl, gl, wr, gr);
+    } else if (wall) {
         slip_ghost(wl, gl, wr, gr);
-    else
+    } else {
         eval_local(cr, rr, T, wr, gr);
+    }
     R Fo[2][5], Wo[2][5];
     gks_point<R, VISC, PRFIX, SMOOTH>(p, dt, wl, gl, wr, gr, Fo, Wo);
     R F1[5], Fh[5], W0[5], W1[5];

@@ -30,8 +30,8 @@ constexpr int kFluxThreads = 256;
 constexpr int kFacesPerWave = 21;
 constexpr int kFacesPerBlock = kFacesPerWave * (kFluxThreads / 64);
 
-// WALL: the launch over the wall faces [nfi, nf) (slip-wall ghost on the
-// right), else over the interior faces [0, nfi).  SMOOTH: eq. 2nd-smooth-flux.
+// WALL: the launch over the wall faces [nfi, nf) (a ghost on the right, as
+// the face's wall tag says), else over the interior faces [0, nfi).  SMOOTH: eq. 2nd-smooth-flux.
 template <typename R, int MODE, bool VISC, bool PRFIX, bool WALL, bool SMOOTH>
 __global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(DevMesh m, DevState s, Params p, double dt_,
                                                                              const double *dtp)
@@ -58,8 +58,15 @@ __global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(
             r[d] = fg[(size_t)(F_RL + 3 * k + d) * nf + f];
         }
         const R area = fg[(size_t)F_AREA * nf + f];
+        WallBC<R> bc{WALL_SLIP, {R(0), R(0), R(0)}};
+        if (WALL) {
+            const int w = f - m.nfi, nw = nf - m.nfi;
+            bc.tag = m.wtag[w];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) bc.u[d] = static_cast<const R *>(m.wvel)[(size_t)d * nw + w];
+        }
         gauss_point_terms<R, VISC, PRFIX, DevCoef<R>, DevCoef<R>, SMOOTH>(
-            p, dt, nrm, area, r, dv, DevCoef<R>{coef, n, L}, DevCoef<R>{coef, n, WALL ? L : Rc}, acc, WALL);
+            p, dt, nrm, area, r, dv, DevCoef<R>{coef, n, L}, DevCoef<R>{coef, n, WALL ? L : Rc}, acc, WALL, &bc);
     } else {
 #pragma unroll
         for (int a = 0; a < 4; ++a)

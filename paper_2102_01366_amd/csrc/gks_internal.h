@@ -23,6 +23,7 @@ struct Params {
     int viscous, nonlinear;
     int order;  // 3 or 2
     int flux;   // FLUX_KIND_FULL or FLUX_KIND_SMOOTH
+    double wall_T;  // p / rho of isothermal no-slip walls
 };
 
 // distribution of the flux: eq. 2nd-flux, or its smooth-flow form eq. 2nd-smooth-flux
@@ -55,6 +56,38 @@ enum FaceRow {
     NFGEO = 16
 };
 
+// No-slip walls (Sec. 4.4).  A cell with at least one no-slip face (a wall
+// cell) has two constraint sets: momentum, constrained at every no-slip face,
+// and energy, constrained at the isothermal ones.  Per set, rows of
+// DevMesh::wop ([kWallRows][nwc], bulk precision):
+//   step 1: b_d = sum_a K1N[4d+a] (Q_a - Q_0) + sum_j K1C[3d+j] (c_j - Q_0)
+//           over the face centres j (X1, relative to the centroid; U1 their
+//           wall velocity);
+//   step 2: (g, H)_r = sum_k K2N[16r+k] d_k + sum_g K2C[9r+g] (c_g - Q_0)
+//           over the faces' Gauss points g (X2, U2), d as for M2;
+// c = rho U_wall (momentum) or rho (|U_wall|^2/2 + T_wall/(gamma-1)) (energy)
+// from the density reconstructed at the point.  Unused constraint columns are
+// zero.  DevMesh::wmode ([4][nwc]): step 1 momentum, step 1 energy, step 2
+// momentum, step 2 energy, each a WallMode.
+enum WallRow {
+    WR_K1N = 0,
+    WR_K1C = 12,
+    WR_X1 = 21,
+    WR_U1 = 30,
+    WR_K2N = 39,
+    WR_K2C = 183,
+    WR_X2 = 264,
+    WR_U2 = 291,
+    WR_SET = 318
+};
+constexpr int kWallRows = 2 * WR_SET;
+enum WallMode {
+    WM_KEEP = 0,  // no constraint: the unconstrained result stands
+    WM_OWN = 1,   // step 1 with fewer than three neighbours and constraints: own averaged gradient
+    WM_FIT = 2    // the operators above (a fallback is an operator without K1C / K2C)
+};
+enum WallTag { WALL_SLIP = 2, WALL_ADIABATIC = 3, WALL_ISOTHERMAL = 4 };
+
 // Device view of the mesh (all pointers into the caller's workspace).
 struct DevMesh {
     int nc, nf;
@@ -71,6 +104,12 @@ struct DevMesh {
     const double *fnrm; // [3][nf] unit normal in FP64 (the Gauss sums of the cell update)
     const int *bslot;   // [4][nc] slot of neighbour a whose face is the cell's slot a (-1 on a wall)
     const int *bmode;   // [nc] 1: fewer than three neighbours, step-1 slopes = own averaged gradient
+    const int *wtag;    // [nf - nfi] WallTag of wall face nfi + k
+    const void *wvel;   // [3][nf - nfi] wall velocity (global frame)
+    int nwc;            // wall cells (cells with a no-slip face)
+    const int *wcell;   // [nwc] their internal ids
+    const int *wmode;   // [4][nwc]
+    const void *wop;    // [kWallRows][nwc]
 };
 
 // Device view of the state and per-stage scratch.
@@ -103,6 +142,11 @@ hipError_t launch_update(const DevMesh &m, const DevState &s, double dt, const d
 template <typename R>
 hipError_t launch_flux_t(const DevMesh &m, const DevState &s, const Params &p, double dt, const double *dtp,
                          int mode, hipStream_t st);
+// no-slip wall cells: the constrained step-1 slopes (after launch_slopes) and
+// the step-2 reconstruction of the wall cells (after launch_reconstruct)
+hipError_t launch_wall_slopes(const DevMesh &m, const DevState &s, const Params &p, bool fp32, hipStream_t st);
+hipError_t launch_wall_reconstruct(const DevMesh &m, const DevState &s, const Params &p, bool fp32,
+                                   hipStream_t st);
 // dt: writes the min over cells of the CFL bound (without the CFL factor) to
 // s.red[0] and cfl times it, the time step, to s.red[kRedDt]
 hipError_t launch_dt(const DevMesh &m, const DevState &s, const Params &p, double cfl,

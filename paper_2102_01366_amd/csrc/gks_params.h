@@ -28,6 +28,7 @@ inline Params params_from_config(const gks_config *cfg)
     p.nonlinear = cfg->nonlinear;
     p.order = cfg->order;
     p.flux = cfg->flux;
+    p.wall_T = cfg->wall_T;
     return p;
 }
 

@@ -43,7 +43,7 @@ def _create(lib, cfg):
 @pytest.mark.parametrize("field,value", [("gamma", 1.0), ("gamma", 0.5), ("mu", -1.0),
                                          ("prandtl", 0.0), ("eps_weno", 0.0),
                                          ("viscous", 2), ("nonlinear", -1), ("precision", 7),
-                                         ("order", 4)])
+                                         ("order", 4), ("flux", 2), ("wall_T", 0.0), ("wall_T", -1.0)])
 def test_create_rejects_bad_config(lib, field, value):
     cfg = G.default_config()
     setattr(cfg, field, value)
@@ -58,7 +58,7 @@ def test_create_rejects_bad_weights(lib):
     assert _create(lib, cfg)[0] == G.GKS_E_INVAL
 
 
-def _upload(lib, mesh, **override):
+def _upload(lib, mesh, wall_u=None, **override):
     arrays = dict(xyz=mesh.xyz, tet=mesh.tet, face_vert=mesh.face_vert, face_cell=mesh.face_cell,
                   face_tag=mesh.face_tag, face_shift=mesh.face_shift)
     arrays.update(override)
@@ -68,9 +68,10 @@ def _upload(lib, mesh, **override):
             np.ascontiguousarray(arrays["face_cell"], np.int64),
             np.ascontiguousarray(arrays["face_tag"], np.int32),
             np.ascontiguousarray(arrays["face_shift"], np.float64)]
+    wu = None if wall_u is None else np.ascontiguousarray(wall_u, np.float64)
     m = G._Mesh(keep[0].shape[0], keep[0].ctypes.data, keep[1].shape[0], keep[1].ctypes.data,
                 keep[2].shape[0], keep[2].ctypes.data, keep[3].ctypes.data, keep[4].ctypes.data,
-                keep[5].ctypes.data)
+                keep[5].ctypes.data, None if wu is None else wu.ctypes.data)
     st, h = _create(lib, G.default_config())
     assert st == 0
     try:
@@ -144,6 +145,28 @@ def test_mesh_rejections(lib):
     tag = mw.face_tag.copy()
     tag[inner] = I.FACE_SLIP
     assert _upload(lib, mw, face_tag=tag)[0] == G.GKS_E_MESH
+
+
+def test_noslip_walls_accepted(lib):
+    """No-slip tags on wall faces, with or without wall velocities; the
+    workspace grows by the wall cells' operators; a no-slip tag on an interior
+    face and a non-finite wall velocity are rejected."""
+    mw = I.kuhn_cube_mesh(3, 1.0, 0.1, 5, False)
+    base = _upload(lib, mw)
+    assert base[0] == 0
+    m2 = I.with_walls(mw, {"x0": I.FACE_NOSLIP_ADIABATIC, "y1": I.FACE_NOSLIP_ISOTHERMAL},
+                      {"y1": (0.3, 0.0, 0.0)})
+    st, st2, nbytes, msg, _, _ = _upload(lib, m2, wall_u=m2.face_wall_u, face_tag=m2.face_tag)
+    assert st == 0 and st2 == 0, msg
+    assert nbytes > base[2]
+    assert _upload(lib, m2, face_tag=m2.face_tag)[0] == 0  # walls at rest
+    inner = int(np.nonzero(mw.face_tag == I.FACE_INTERIOR)[0][0])
+    tag = m2.face_tag.copy()
+    tag[inner] = I.FACE_NOSLIP_ISOTHERMAL
+    assert _upload(lib, m2, face_tag=tag)[0] == G.GKS_E_MESH
+    wu = m2.face_wall_u.copy()
+    wu[0, 1] = np.nan
+    assert _upload(lib, m2, wall_u=wu, face_tag=m2.face_tag)[0] == G.GKS_E_MESH
 
 
 def test_empty_mesh_rejected(lib):

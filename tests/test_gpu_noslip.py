@@ -1,0 +1,132 @@
+"""No-slip adiabatic and isothermal walls (Sec. 4.4) on the GPU against the
+oracle, to the normwise 1e-12 bar of test_gpu_parity.py.
+
+Meshes: the unit cube with jittered interior vertices, sides retagged as
+no-slip adiabatic or isothermal walls (some moving); so wall cells with one,
+two and three wall faces, constrained momentum and energy, and the
+fallbacks all occur.  Fields: the swirl with a pressure bump, whose
+tangential velocity is non-zero on the walls, so the constraints act.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2102_01366_amd as G
+from paper_2102_01366_amd import inputs as I
+
+from test_gpu_parity import COEF_GROUPS, FACE_GROUPS, GW_GROUPS, W_GROUPS, assert_parity, gradient_floors
+
+pytestmark = pytest.mark.gpu
+
+ADIA, ISO = I.FACE_NOSLIP_ADIABATIC, I.FACE_NOSLIP_ISOTHERMAL
+SIDES = ("x0", "x1", "y0", "y1", "z0", "z1")
+
+
+def _case(name):
+    if name == "adiabatic_ns":
+        m = I.with_walls(I.kuhn_cube_mesh(4, 1.0, 0.1, 2, False), {s: ADIA for s in SIDES})
+        W, gW = I.cell_averages(m, I.box_vortex_field(amp=0.3))
+        return m, dict(viscous=True, mu=0.01, prandtl=0.72), W, gW
+    if name == "cavity_isothermal_ragged":
+        # lid-driven: every side isothermal, the lid y = 1 moving along x
+        m = I.with_walls(I.kuhn_cube_mesh(5, 1.0, 0.1, 3, False), {s: ISO for s in SIDES},
+                         {"y1": (0.15, 0.0, 0.0)})
+        W, gW = I.cell_averages(m, I.box_vortex_field(amp=0.1, bump=0.1))
+        return m, dict(viscous=True, mu=0.005, prandtl=0.72, wall_T=0.95), W, gW
+    if name == "cavity_smooth_flux":
+        m = I.with_walls(I.kuhn_cube_mesh(4, 1.0, 0.1, 7, False), {s: ISO for s in SIDES},
+                         {"y1": (0.15, 0.0, 0.0)})
+        W, gW = I.cell_averages(m, I.box_vortex_field(amp=0.1, bump=0.1))
+        return m, dict(viscous=True, mu=0.005, prandtl=1.0, wall_T=1.0, flux=1), W, gW
+    if name == "mixed_euler":
+        m = I.with_walls(I.kuhn_cube_mesh(4, 1.0, 0.1, 4, False), {"x0": ADIA, "y1": ISO},
+                         {"y1": (0.0, 0.0, 0.2), "x0": (0.0, 0.1, 0.0)})
+        W, gW = I.cell_averages(m, I.box_vortex_field(amp=0.3))
+        return m, dict(wall_T=1.1), W, gW
+    if name == "order2_isothermal":
+        m = I.with_walls(I.kuhn_cube_mesh(4, 1.0, 0.1, 6, False), {s: ISO for s in SIDES})
+        W, gW = I.cell_averages(m, I.box_vortex_field(amp=0.3))
+        return m, dict(viscous=True, mu=0.01, prandtl=0.72, order=2), W, gW
+    raise KeyError(name)
+
+
+CASES = ["adiabatic_ns", "cavity_isothermal_ragged", "cavity_smooth_flux", "mixed_euler", "order2_isothermal"]
+
+
+def _pair(name):
+    m, kw, W, gW = _case(name)
+    return m, G.Solver(m, G.default_config(**kw)), oracle.Oracle(m, oracle.make_config(**kw)), W, gW
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_noslip_reconstruction(name):
+    m, s, orc, W, gW = _pair(name)
+    s.init(W, gW)
+    b, coef, flag = s.debug_reconstruct()
+    co, fo = orc.reconstruct(W, gW)
+    assert_parity(b, orc.slopes(W, gW), GW_GROUPS, "slopes")
+    assert_parity(coef, co, COEF_GROUPS, "coef")
+    np.testing.assert_array_equal(flag, fo)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_noslip_face_terms(name):
+    m, s, orc, W, gW = _pair(name)
+    s.init(W, gW)
+    dt = orc.compute_dt(W, 0.5)
+    assert_parity(s.debug_face_terms(dt), orc.face_terms(W, gW, dt), FACE_GROUPS, "face terms")
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_noslip_steps(name):
+    m, s, orc, W, gW = _pair(name)
+    s.init(W, gW)
+    Wo, gWo = W, gW
+    for step in range(2):
+        dt = orc.compute_dt(Wo, 0.5)
+        for stage in (1, 2):
+            s.stage(stage, dt)
+            Wo, gWo = orc.stage(stage, dt, Wo, gWo)
+            Wg, gWg = s.read_state()
+            assert_parity(Wg, Wo, W_GROUPS, f"W step {step} stage {stage}")
+            assert_parity(gWg, gWo, GW_GROUPS, f"gW step {step} stage {stage}",
+                          floors=gradient_floors(Wo, orc))
+
+
+@pytest.mark.parametrize("tag", [ADIA, ISO], ids=["adiabatic", "isothermal"])
+def test_gas_at_rest_stays_at_rest_on_gpu(tag):
+    Tw = 1.0 / 1.4
+    m = I.with_walls(I.kuhn_cube_mesh(4, 1.0, 0.1, 5, False), {s: tag for s in SIDES})
+    s = G.Solver(m, G.default_config(viscous=True, mu=0.01, prandtl=0.72, wall_T=Tw))
+    W = np.zeros((5, m.n_cell))
+    W[0] = 1.0
+    W[4] = Tw / 0.4
+    s.init(W, np.zeros((15, m.n_cell)))
+    dt = s.compute_dt(0.5)
+    for _ in range(3):
+        s.step(dt)
+    Wg, _ = s.read_state()
+    assert np.abs(Wg - W).max() < 1e-13
+
+
+def test_noslip_fp32_bulk_close_to_fp64():
+    m, kw, W, gW = _case("cavity_isothermal_ragged")
+    res = []
+    for prec in (G.GKS_FP64, G.GKS_FP32_BULK):
+        s = G.Solver(m, G.default_config(precision=prec, **kw))
+        s.init(W, gW)
+        for _ in range(3):
+            s.step(0.005)
+        res.append(s.read_state()[0])
+    for g in W_GROUPS:
+        assert np.abs(res[1][g] - res[0][g]).max() <= 1e-5 * np.abs(res[0][g]).max()
+
+
+def test_noslip_adjoint_is_rejected():
+    torch = pytest.importorskip("torch")
+    m, kw, W, gW = _case("adiabatic_ns")
+    s = G.Solver(m, G.default_config(**kw))
+    Wt, Gt = torch.from_numpy(W).cuda(), torch.from_numpy(gW).cuda()
+    with pytest.raises(G.GksError) as e:
+        s.step_adjoint(0.001, Wt, Gt, Wt, Gt)
+    assert e.value.status == G.GKS_E_INVAL
