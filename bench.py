@@ -14,8 +14,9 @@ region, the roofline of the dominant kernel (per-kernel durations from HIP
 events that the library records on its stream around each kernel, over the
 same number of steps right after the timed region), the FP32-bulk form's throughput and error, the
 differentiation form (adjoint / forward time and its finite-difference
-check), the walled blast workload (1.57M cells, slip walls) and the FP64
-CPU oracle timed on a bounded sample.
+check), the walled blast workload (1.57M cells, slip walls), the lid-driven
+cavity (no-slip isothermal walls, smooth-flow flux) and the FP64 CPU oracle
+timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -254,6 +255,51 @@ def blast_leg(G, I, n, steps, warmup):
     return out
 
 
+def cavity_leg(G, I, n, steps, warmup):
+    """No-slip walls and the smooth-flow flux: the lid-driven cavity of the
+    paper's Sec. 5 set-up -- unit cube, n^3 hexahedra x 6 Kuhn tetrahedra,
+    uniform (no jitter), six isothermal no-slip walls at T = p/rho = 1/gamma,
+    the lid y = 1 moving at 0.15 along x (Ma 0.15), gamma 5/3, Re 1000 on
+    the lid speed and side, gas initially at rest (rho 1, p 1/gamma), linear
+    reconstruction weights, eq. 2nd-smooth-flux, CFL 0.5; FP64 and
+    FP32-bulk."""
+    import numpy as np
+    import torch
+    gamma, ulid = 5.0 / 3.0, 0.15
+    sides = ("x0", "x1", "y0", "y1", "z0", "z1")
+    mesh = I.with_walls(I.kuhn_cube_mesh(n, 1.0, 0.0, 0, False), {s: I.FACE_NOSLIP_ISOTHERMAL for s in sides},
+                        {"y1": (ulid, 0.0, 0.0)})
+    W = np.zeros((5, mesh.n_cell))
+    W[0] = 1.0
+    W[4] = (1.0 / gamma) / (gamma - 1.0)
+    gW = np.zeros((15, mesh.n_cell))
+    kw = dict(gamma=gamma, viscous=True, mu=ulid / 1000.0, prandtl=1.0, nonlinear=False, flux=G.GKS_FLUX_SMOOTH,
+              wall_T=1.0 / gamma)
+    nwall_cells = int(np.unique(mesh.face_cell[mesh.face_cell[:, 1] < 0, 0]).size)
+    out = {"workload": f"lid-driven cavity, {n}^3 hexes x 6 Kuhn tets ({mesh.n_cell} cells, {mesh.n_face} faces, "
+                       f"{nwall_cells} wall cells), uniform, isothermal no-slip walls, lid Ma 0.15, gamma 5/3, "
+                       f"Re 1000, linear weights, smooth-flow flux, CFL 0.5",
+           "cells": mesh.n_cell, "faces": mesh.n_face, "wall_cells": nwall_cells, "steps": steps}
+    for name, prec in (("fp64", G.GKS_FP64), ("fp32_bulk", G.GKS_FP32_BULK)):
+        s = G.Solver(mesh, G.default_config(precision=prec, **kw), device="cuda:0")
+        s.init(W, gW)
+        for _ in range(warmup):
+            s.step_cfl(0.5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.step_cfl(0.5)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        Wf, _ = s.read_state()
+        kt, _ = timed_kernels(s, steps)
+        out[name] = {"value": mesh.n_cell * 2 * steps / el, "unit": "cell-stage-updates/s",
+                     "ms_per_step": el / steps * 1e3,
+                     "max_speed_over_lid": float(np.abs(Wf[1:4] / Wf[0]).max() / ulid),
+                     "kernels_ms": {k: ms / cnt for k, (ms, cnt) in kt.items() if cnt}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +312,9 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=50,
                     help="steps of the differentiation leg (0 skips it)")
     ap.add_argument("--adjoint-directions", type=int, default=16)
+    ap.add_argument("--cavity-n", type=int, default=32,
+                    help="hexahedra per side of the lid-driven cavity leg (0 skips it)")
+    ap.add_argument("--cavity-steps", type=int, default=20)
     ap.add_argument("--blast-n", type=int, default=64,
                     help="hexahedra per side of the walled blast leg (0 skips it)")
     ap.add_argument("--blast-steps", type=int, default=20)
@@ -397,6 +446,7 @@ def main():
     else:
         out["adjoint"] = None
     out["blast_walls"] = blast_leg(G, I, args.blast_n, args.blast_steps, 2) if args.blast_n > 0 else None
+    out["cavity_noslip"] = cavity_leg(G, I, args.cavity_n, args.cavity_steps, 2) if args.cavity_n > 0 else None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, W, gW, cfg_kw, args.cpu_baseline_steps)
     else:

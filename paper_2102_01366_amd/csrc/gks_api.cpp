@@ -751,6 +751,7 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
             c->wmode.resize(4 * (w + 1), gks::WM_KEEP);
             c->wop.resize(gks::kWallRows * (w + 1), 0.0);
             double *op = &c->wop[gks::kWallRows * w];
+            for (int r = 0; r < gks::kM2Rows; ++r) op[gks::WR_M2 + r] = M2[gks::m2_index(r, ii)];
             for (int set = 0; set < 2; ++set) {
                 const int ns = ws_n[set];
                 double *o = op + set * gks::WR_SET;

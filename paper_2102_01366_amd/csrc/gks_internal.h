@@ -80,7 +80,10 @@ enum WallRow {
     WR_U2 = 291,
     WR_SET = 318
 };
-constexpr int kWallRows = 2 * WR_SET;
+// after the two sets: the cell's unconstrained step-2 operator (the 144 rows
+// of M2), so that the wall kernel reads every operator coalesced
+constexpr int WR_M2 = 2 * WR_SET;
+constexpr int kWallRows = WR_M2 + 144;
 enum WallMode {
     WM_KEEP = 0,  // no constraint: the unconstrained result stands
     WM_OWN = 1,   // step 1 with fewer than three neighbours and constraints: own averaged gradient

@@ -420,160 +420,188 @@ __device__ __forceinline__ R quad_value(const R c[10], const R r[3])
            c[8] * r[0] * r[2] + c[9] * r[1] * r[2];
 }
 
-constexpr int kWallBlock = 64;
+constexpr int kWallBlock = 256;
 
 // step 1: b = K1N (Q_a - Q_0) + K1C (c_j - Q_0), c_j at the face centres from
-// the cell's step-1 density P^1
+// the cell's step-1 density P^1; one thread per (wall cell, component 1-4)
 template <typename R>
 __global__ __launch_bounds__(kWallBlock) void wall_slopes_kernel(DevMesh m, DevState s, Params p)
 {
-    const int w = gid(), nw = m.nwc, n = m.nc;
-    if (w >= nw) return;
+    const int t = gid(), nw = m.nwc, n = m.nc;
+    if (t >= 4 * nw) return;
+    const int q = 1 + t / nw, w = t - (q - 1) * nw;
     const int i = m.wcell[w];
+    const int set = q < 4 ? 0 : 1, base = set * WR_SET;
+    const int mode = m.wmode[(size_t)set * nw + w];
+    if (mode == WM_KEEP) return;
     const R *op = static_cast<const R *>(m.wop);
     R *slopes = static_cast<R *>(s.slopes);
-    int nb[4];
+    if (mode == WM_OWN) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) nb[a] = m.nbr[a * n + i];
+        for (int d = 0; d < 3; ++d) slopes[(size_t)(3 * q + d) * n + i] = R(s.gW[(size_t)(3 * q + d) * n + i]);
+        return;
+    }
     const R rho0 = R(s.W[i]);
     R br[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) br[d] = slopes[(size_t)d * n + i];
-    for (int q = 1; q < 5; ++q) {
-        const int set = q < 4 ? 0 : 1, base = set * WR_SET;
-        const int mode = m.wmode[(size_t)set * nw + w];
-        if (mode == WM_KEEP) continue;
-        if (mode == WM_OWN) {
+    for (int d = 0; d < 3; ++d) br[d] = slopes[(size_t)d * n + i];  // the density's (never constrained)
+    const double Q0 = s.W[(size_t)q * n + i];
+    R dq[4], ec[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) slopes[(size_t)(3 * q + d) * n + i] = R(s.gW[(size_t)(3 * q + d) * n + i]);
-            continue;
-        }
-        const double Q0 = s.W[(size_t)q * n + i];
-        R dq[4], ec[3];
+    for (int a = 0; a < 4; ++a) {
+        const int nb = m.nbr[a * n + i];
+        dq[a] = nb >= 0 ? R(s.W[(size_t)q * n + nb] - Q0) : R(0);
+    }
 #pragma unroll
-        for (int a = 0; a < 4; ++a) dq[a] = nb[a] >= 0 ? R(s.W[(size_t)q * n + nb[a]] - Q0) : R(0);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            R x[3], u[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                x[d] = op[(size_t)(base + WR_X1 + 3 * j + d) * nw + w];
-                u[d] = op[(size_t)(base + WR_U1 + 3 * j + d) * nw + w];
-            }
-            const R rho = rho0 + br[0] * x[0] + br[1] * x[1] + br[2] * x[2];
-            ec[j] = wall_value(q, rho, u, R(p.gamma), R(p.wall_T)) - R(Q0);
-        }
+    for (int j = 0; j < 3; ++j) {
+        R x[3], u[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            R b = R(0);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) b += op[(size_t)(base + WR_K1N + 4 * d + a) * nw + w] * dq[a];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) b += op[(size_t)(base + WR_K1C + 3 * d + j) * nw + w] * ec[j];
-            slopes[(size_t)(3 * q + d) * n + i] = b;
+            x[d] = op[(size_t)(base + WR_X1 + 3 * j + d) * nw + w];
+            u[d] = op[(size_t)(base + WR_U1 + 3 * j + d) * nw + w];
         }
+        const R rho = rho0 + br[0] * x[0] + br[1] * x[1] + br[2] * x[2];
+        ec[j] = wall_value(q, rho, u, R(p.gamma), R(p.wall_T)) - R(Q0);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        R b = R(0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) b += op[(size_t)(base + WR_K1N + 4 * d + a) * nw + w] * dq[a];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) b += op[(size_t)(base + WR_K1C + 3 * d + j) * nw + w] * ec[j];
+        slopes[(size_t)(3 * q + d) * n + i] = b;
     }
 }
 
-// step 2: the whole reconstruction of a wall cell again, component by
-// component in order (the density first): P^2 from M2, or for a constrained
+// step 2: the whole reconstruction of the wall cells again, laid out as the
+// ordinary kernel -- a block of kRecCells wall cells with one wavefront per
+// component -- so that the density, finished first, reaches the constrained
+// components through LDS: P^2 from the copied M2 rows, or for a constrained
 // component K2N d + K2C (c_g - Q_0) with c_g at the wall Gauss points from the
 // reconstructed density; the same weights; the positivity check over all five
 template <typename R>
-__global__ __launch_bounds__(kWallBlock) void wall_reconstruct_kernel(DevMesh m, DevState s, Params p)
+__global__ __launch_bounds__(kRecThreads) void wall_reconstruct_kernel(DevMesh m, DevState s, Params p)
 {
-    const int w = gid(), nw = m.nwc, n = m.nc;
-    if (w >= nw) return;
-    const int i = m.wcell[w];
+    __shared__ R sR[5][10][kRecCells];
+    __shared__ int sBad[5][kRecCells];
+    const int nw = m.nwc, n = m.nc;
+    const int q = threadIdx.x / kRecCells, l = threadIdx.x % kRecCells;
+    const int w = blockIdx.x * kRecCells + l;
+    const bool live = w < nw;
+    const int i = live ? m.wcell[w] : 0;
     const R *op = static_cast<const R *>(m.wop);
-    const R *M2 = static_cast<const R *>(m.M2);
     const R *geo = static_cast<const R *>(m.geoR);
     const R *slopes = static_cast<const R *>(s.slopes);
     R *coef = static_cast<R *>(s.coef);
-    int nb[4];
-    bool has[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        nb[a] = m.nbr[a * n + i];
-        has[a] = nb[a] >= 0;
-    }
-    const R vol23 = geo[(size_t)G_VOL23 * n + i], vol43 = geo[(size_t)G_VOL43 * n + i];
-    R C[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) C[k] = geo[(size_t)(G_C + k) * n + i];
-    R Rall[5][10];
-    for (int q = 0; q < 5; ++q) {
-        const double Q0 = s.W[(size_t)q * n + i];
-        R d[16];
+    const int set = q < 4 ? 0 : 1, base = set * WR_SET;
+    const int mode = (q == 0 || !live) ? WM_KEEP : m.wmode[(size_t)(2 + set) * nw + w];
+    double Q0 = 0.0;
+    R d[16], c[9], Rq[10];
+    if (live) {
+        Q0 = s.W[(size_t)q * n + i];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            d[a] = has[a] ? R(s.W[(size_t)q * n + nb[a]] - Q0) : R(0);
+            const int nb = m.nbr[a * n + i];
+            d[a] = nb >= 0 ? R(s.W[(size_t)q * n + nb] - Q0) : R(0);
 #pragma unroll
-            for (int dd = 0; dd < 3; ++dd) d[4 + 3 * a + dd] = has[a] ? R(s.gW[(size_t)(3 * q + dd) * n + nb[a]]) : R(0);
+            for (int dd = 0; dd < 3; ++dd) d[4 + 3 * a + dd] = nb >= 0 ? R(s.gW[(size_t)(3 * q + dd) * n + nb]) : R(0);
         }
-        const int set = q < 4 ? 0 : 1, base = set * WR_SET;
-        const int mode = q == 0 ? WM_KEEP : m.wmode[(size_t)(2 + set) * nw + w];
-        R c[9];
-        if (mode == WM_KEEP) {
-            for (int r = 0; r < 9; ++r) {
-                R acc = R(0);
+    }
+    // P^2 of the density and of the unconstrained components (the rows of M2),
+    // then the density's final polynomial for the wall values
+    auto finish = [&]() {
+        bool has[4];
+        R b[3], sn[4][3], C[6];
 #pragma unroll
-                for (int k = 0; k < 16; ++k) acc += M2[m2_index(16 * r + k, i)] * d[k];
-                c[r] = acc;
-            }
-        } else {
-            R ec[9];
-            for (int g = 0; g < 9; ++g) {
-                R x[3], u[3];
+        for (int a = 0; a < 4; ++a) {
+            const int nb = m.nbr[a * n + i];
+            has[a] = nb >= 0;
 #pragma unroll
-                for (int dd = 0; dd < 3; ++dd) {
-                    x[dd] = op[(size_t)(base + WR_X2 + 3 * g + dd) * nw + w];
-                    u[dd] = op[(size_t)(base + WR_U2 + 3 * g + dd) * nw + w];
-                }
-                ec[g] = wall_value(q, quad_value(Rall[0], x), u, R(p.gamma), R(p.wall_T)) - R(Q0);
-            }
-            for (int r = 0; r < 9; ++r) {
-                R acc = R(0);
-#pragma unroll
-                for (int k = 0; k < 16; ++k) acc += op[(size_t)(base + WR_K2N + 16 * r + k) * nw + w] * d[k];
-#pragma unroll
-                for (int g = 0; g < 9; ++g) acc += op[(size_t)(base + WR_K2C + 9 * r + g) * nw + w] * ec[g];
-                c[r] = acc;
-            }
+            for (int dd = 0; dd < 3; ++dd) sn[a][dd] = has[a] ? slopes[(size_t)(3 * q + dd) * n + nb] : R(0);
         }
-        R b[3], sn[4][3];
 #pragma unroll
         for (int dd = 0; dd < 3; ++dd) b[dd] = slopes[(size_t)(3 * q + dd) * n + i];
 #pragma unroll
+        for (int k = 0; k < 6; ++k) C[k] = geo[(size_t)(G_C + k) * n + i];
+        WenoFwd<R> f;
+        weno_forward<R>(p, R(Q0), c, C, geo[(size_t)G_VOL23 * n + i], geo[(size_t)G_VOL43 * n + i], b, sn, has, f,
+                        Rq);
+    };
+    if (live && mode == WM_KEEP) {
+        for (int r = 0; r < 9; ++r) {
+            R acc = R(0);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) acc += op[(size_t)(WR_M2 + 16 * r + k) * nw + w] * d[k];
+            c[r] = acc;
+        }
+        finish();
+    }
+    if (live && q == 0)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) sR[0][k][l] = Rq[k];
+    __syncthreads();
+    if (live && mode != WM_KEEP) {
+        R Rr[10], ec[9];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) Rr[k] = sR[0][k][l];
+        for (int g = 0; g < 9; ++g) {
+            R x[3], u[3];
+#pragma unroll
+            for (int dd = 0; dd < 3; ++dd) {
+                x[dd] = op[(size_t)(base + WR_X2 + 3 * g + dd) * nw + w];
+                u[dd] = op[(size_t)(base + WR_U2 + 3 * g + dd) * nw + w];
+            }
+            ec[g] = wall_value(q, quad_value(Rr, x), u, R(p.gamma), R(p.wall_T)) - R(Q0);
+        }
+        for (int r = 0; r < 9; ++r) {
+            R acc = R(0);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) acc += op[(size_t)(base + WR_K2N + 16 * r + k) * nw + w] * d[k];
+#pragma unroll
+            for (int g = 0; g < 9; ++g) acc += op[(size_t)(base + WR_K2C + 9 * r + g) * nw + w] * ec[g];
+            c[r] = acc;
+        }
+        finish();
+    }
+    if (live && q > 0)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) sR[q][k][l] = Rq[k];
+    __syncthreads();
+    // positivity of density and pressure: wavefront a < 4 checks the three
+    // Gauss points of the face opposite vertex a
+    int bad = 0;
+    if (live && q < 4) {
+        R rv[4][3];
+#pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int dd = 0; dd < 3; ++dd) sn[a][dd] = has[a] ? slopes[(size_t)(3 * q + dd) * n + nb[a]] : R(0);
-        WenoFwd<R> f;
-        weno_forward<R>(p, R(Q0), c, C, vol23, vol43, b, sn, has, f, Rall[q]);
-    }
-    // positivity of density and pressure at the twelve face Gauss points
-    R rv[4][3];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int dd = 0; dd < 3; ++dd) rv[a][dd] = geo[(size_t)(G_RV + 3 * a + dd) * n + i];
-    bool bad = false;
-    for (int a = 0; a < 4; ++a)
+            for (int dd = 0; dd < 3; ++dd) rv[a][dd] = geo[(size_t)(G_RV + 3 * a + dd) * n + i];
         for (int k = 0; k < 4; ++k) {
-            if (k == a) continue;
+            if (k == q) continue;
             R r[3], v[5];
 #pragma unroll
-            for (int dd = 0; dd < 3; ++dd) r[dd] = R(0.5) * rv[k][dd] - rv[a][dd] / R(6);
+            for (int dd = 0; dd < 3; ++dd) r[dd] = R(0.5) * rv[k][dd] - rv[q][dd] / R(6);
 #pragma unroll
-            for (int q = 0; q < 5; ++q) v[q] = quad_value(Rall[q], r);
+            for (int cc = 0; cc < 5; ++cc) {
+                R cf[10];
+#pragma unroll
+                for (int kk = 0; kk < 10; ++kk) cf[kk] = sR[cc][kk][l];
+                v[cc] = quad_value(cf, r);
+            }
             const R pr = R(p.gamma - 1.0) * (v[4] - R(0.5) * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
-            if (!(v[0] > R(0)) || !(pr > R(0))) bad = true;
+            if (!(v[0] > R(0)) || !(pr > R(0))) bad = 1;
         }
-    for (int q = 0; q < 5; ++q)
+    }
+    sBad[q][l] = bad;
+    __syncthreads();
+    if (live) {
+        const bool anybad = (sBad[0][l] | sBad[1][l] | sBad[2][l] | sBad[3][l]) != 0;
 #pragma unroll
         for (int k = 0; k < 10; ++k)
-            coef[(size_t)(10 * q + k) * n + i] = bad ? (k == 0 ? R(s.W[(size_t)q * n + i]) : R(0)) : Rall[q][k];
-    s.flag[i] = bad ? 1 : 0;
+            coef[(size_t)(10 * q + k) * n + i] = anybad ? (k == 0 ? R(Q0) : R(0)) : sR[q][k][l];
+        if (q == 0) s.flag[i] = anybad ? 1 : 0;
+    }
 }
 
 // ===========================================================================
@@ -811,7 +839,7 @@ hipError_t launch_flux(const DevMesh &m, const DevState &s, const Params &p, dou
 hipError_t launch_wall_slopes(const DevMesh &m, const DevState &s, const Params &p, bool fp32, hipStream_t st)
 {
     if (m.nwc <= 0) return hipSuccess;
-    const dim3 g((unsigned)((m.nwc + kWallBlock - 1) / kWallBlock)), b(kWallBlock);
+    const dim3 g((unsigned)((4 * m.nwc + kWallBlock - 1) / kWallBlock)), b(kWallBlock);
     if (fp32)
         hipLaunchKernelGGL(wall_slopes_kernel<float>, g, b, 0, st, m, s, p);
     else
@@ -825,7 +853,7 @@ hipError_t launch_wall_reconstruct(const DevMesh &m, const DevState &s, const Pa
     // the second-order scheme has no step-2 fit: its wall cells take the
     // constrained step-1 slopes through the ordinary kernel
     if (m.nwc <= 0 || p.order == 2) return hipSuccess;
-    const dim3 g((unsigned)((m.nwc + kWallBlock - 1) / kWallBlock)), b(kWallBlock);
+    const dim3 g((unsigned)((m.nwc + kRecCells - 1) / kRecCells)), b(kRecThreads);
     if (fp32)
         hipLaunchKernelGGL(wall_reconstruct_kernel<float>, g, b, 0, st, m, s, p);
     else
