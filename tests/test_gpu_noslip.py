@@ -130,3 +130,33 @@ def test_noslip_adjoint_is_rejected():
     with pytest.raises(G.GksError) as e:
         s.step_adjoint(0.001, Wt, Gt, Wt, Gt)
     assert e.value.status == G.GKS_E_INVAL
+
+
+def test_cavity_full_size_one_step():
+    """The bench's lid-driven cavity at full size (unjittered 32^3 x 6 mesh,
+    196,608 cells, 12,096 wall cells; isothermal no-slip walls, lid Ma 0.15,
+    gamma 5/3, Re 1000, linear weights, smooth-flow flux), in the bench's
+    launch configuration: one whole step against the oracle, after the flow
+    has started (two steps from rest on both sides first)."""
+    gamma, ulid = 5.0 / 3.0, 0.15
+    m = I.with_walls(I.kuhn_cube_mesh(32, 1.0, 0.0, 0, False), {s: ISO for s in SIDES},
+                     {"y1": (ulid, 0.0, 0.0)})
+    kw = dict(gamma=gamma, viscous=True, mu=ulid / 1000.0, prandtl=1.0, nonlinear=False, flux=1,
+              wall_T=1.0 / gamma)
+    W = np.zeros((5, m.n_cell))
+    W[0] = 1.0
+    W[4] = (1.0 / gamma) / (gamma - 1.0)
+    gW = np.zeros((15, m.n_cell))
+    s = G.Solver(m, G.default_config(**kw))
+    orc = oracle.Oracle(m, oracle.make_config(**kw))
+    s.init(W, gW)
+    Wo, gWo = W, gW
+    for step in range(3):
+        dt = orc.compute_dt(Wo, 0.5)
+        assert abs(s.compute_dt(0.5) - dt) <= 1e-15 * dt
+        s.step(dt)
+        Wo, gWo = orc.step(dt, Wo, gWo)
+    Wg, gWg = s.read_state()
+    assert_parity(Wg, Wo, W_GROUPS, "W")
+    assert_parity(gWg, gWo, GW_GROUPS, "gW", floors=gradient_floors(Wo, orc))
+    assert np.abs(Wo[1]).max() > 1e-4  # the lid has set the gas moving
