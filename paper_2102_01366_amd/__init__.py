@@ -42,7 +42,7 @@ EXPORTS = ("gks_default_config", "gks_create", "gks_destroy", "gks_set_stream",
            "gks_read_state",
            "gks_conservation_sums", "gks_debug_reconstruct", "gks_debug_face_terms",
            "gks_timing_enable", "gks_timing_read", "gks_flux_op_count", "gks_flux_point_check",
-           "gks_flux_face_check", "gks_weno_check", "gks_last_error",
+           "gks_flux_face_check", "gks_weno_check", "gks_wall_ghost_check", "gks_last_error",
            "gks_strerror")
 
 KERNELS = ("slopes", "reconstruct", "flux_stage1", "flux_stage2", "update_stage1",
@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH):
         "gks_flux_point_check": (S, [P, D, P, P, P, P, P, P]),
         "gks_flux_face_check": (S, [P, D, P, P, P, P, P, P, P]),
         "gks_weno_check": (S, [P, P, I32, P, P, P, P, P, P]),
+        "gks_wall_ghost_check": (S, [P, I32, P, P, P, P, P, P, P]),
         "gks_last_error": (ctypes.c_char_p, [P]),
         "gks_strerror": (ctypes.c_char_p, [S]),
     }
@@ -197,6 +198,19 @@ def weno_check(config: Config, geo, has_mask: int, x, v, rbar):
     if st != GKS_OK:
         raise GksError(st, "gks_weno_check failed")
     return r, jv, xb
+
+
+def wall_ghost_check(config: Config, tag: int, uw, x, v, ybar):
+    """Host check of the no-slip ghost state: (y, J v, J^T ybar), see gks.h."""
+    L = load_library()
+    uw, x, v, yb = (np.ascontiguousarray(a, dtype=np.float64) for a in (uw, x, v, ybar))
+    assert uw.shape == (3,) and x.shape == (20,) and v.shape == (20,) and yb.shape == (20,)
+    y, jv, xb = np.zeros(20), np.zeros(20), np.zeros(20)
+    st = L.gks_wall_ghost_check(ctypes.byref(config), int(tag), _ptr(uw), _ptr(x), _ptr(v), _ptr(yb),
+                                _ptr(y), _ptr(jv), _ptr(xb))
+    if st != GKS_OK:
+        raise GksError(st, "gks_wall_ghost_check failed")
+    return y, jv, xb
 
 
 def _ptr(a) -> int:

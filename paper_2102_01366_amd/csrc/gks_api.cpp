@@ -259,7 +259,7 @@ struct Layout {
 enum Slot {
     S_NBR, S_CFACE, S_M1, S_M2, S_GEOR, S_GEOD, S_FCELL, S_FGEO, S_FNRM, S_W, S_GW, S_WN, S_LN, S_LTN,
     S_SLOPES, S_COEF, S_FLAG, S_FF, S_FT, S_FW0, S_FWS, S_RED, S_NONPHYS, S_CPERM, S_FPERM,
-    S_STAGING, S_ISTAGING, S_BSLOT, S_BMODE, S_WTAG, S_WVEL, S_WCELL, S_WMODE, S_WOP, S_COUNT
+    S_STAGING, S_ISTAGING, S_BSLOT, S_BMODE, S_WTAG, S_WVEL, S_WCELL, S_WMODE, S_WOP, S_WIDX, S_COUNT
 };
 
 // bs: bytes of a bulk element (8 in FP64, 4 in FP32-bulk); nwf wall faces,
@@ -275,7 +275,8 @@ Layout make_layout(size_t nc, size_t nf, size_t bs, size_t nwf, size_t nwc)
         nc * sizeof(int), 5 * nf * bs, 5 * nf * bs, 5 * nf * bs, 5 * nf * bs,
         (8 + 5 * (size_t)gks::kRedBlocks) * 8, 64, nc * sizeof(int), nf * sizeof(int),
         std::max(50 * nc, 20 * nf) * 8, nc * sizeof(int), 4 * nc * sizeof(int), nc * sizeof(int),
-        nwf * sizeof(int), 3 * nwf * bs, nwc * sizeof(int), 4 * nwc * sizeof(int), (size_t)gks::kWallRows * nwc * bs};
+        nwf * sizeof(int), 3 * nwf * bs, nwc * sizeof(int), 4 * nwc * sizeof(int), (size_t)gks::kWallRows * nwc * bs,
+        nc * sizeof(int)};
     Layout L;
     size_t o = 0;
     for (int k = 0; k < S_COUNT; ++k) {
@@ -940,6 +941,7 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     dm.wcell = (const int *)P(S_WCELL);
     dm.wmode = (const int *)P(S_WMODE);
     dm.wop = P(S_WOP);
+    dm.widx = (const int *)P(S_WIDX);
     ds.W = (double *)P(S_W);
     ds.gW = (double *)P(S_GW);
     ds.Wn = (double *)P(S_WN);
@@ -986,6 +988,13 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     if (!c->wtag.empty()) {
         HIP_TRY(c, up((void *)dm.wtag, c->wtag.data(), c->wtag.size() * sizeof(int)));
         HIP_TRY(c, up_bulk(dm.wvel, c->wvel));
+    }
+    {
+        // every cell's wall-cell index (-1 for most), read by the adjoint
+        std::vector<int> widx(nc, -1);
+        for (int w = 0; w < c->nwc; ++w) widx[c->wcell[w]] = w;
+        HIP_TRY(c, up((void *)dm.widx, widx.data(), nc * sizeof(int)));
+        HIP_TRY(c, hipStreamSynchronize(st));
     }
     if (c->nwc > 0) {
         // operators per wall cell on the host, [kWallRows][nwc] on the device
@@ -1266,7 +1275,6 @@ gks_status gks_step_adjoint(gks_ctx *c, double dt, const double *W_n, const doub
     if (!W_n || !gW_n || !Wbar_np1 || !gWbar_np1 || !Wbar_n || !gWbar_n)
         return fail(c, GKS_E_INVAL, "null pointer");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, GKS_E_INVAL, "dt must be positive and finite");
-    if (c->noslip) return fail(c, GKS_E_INVAL, "the adjoint does not cover no-slip walls");
     const hipStream_t s = c->stream;
     const int nc = c->nc;
     const bool f32 = c->fp32;
@@ -1324,7 +1332,8 @@ gks_status gks_step_adjoint(gks_ctx *c, double dt, const double *W_n, const doub
     r.slopes = a.slopes2;
     r.flag = a.flag2;
     HIP_TRY(c, gks::launch_recon_vjp(dm, r, c->par, f32, s));
-    HIP_TRY(c, gks::launch_recon_gather(dm, r, f32, a.Gbs, a.Wbs, nullptr, nullptr, s));
+    HIP_TRY(c, gks::launch_wall_recon_vjp(dm, r, c->par, f32, s));
+    HIP_TRY(c, gks::launch_recon_gather(dm, r, c->par, f32, a.Gbs, a.Wbs, nullptr, nullptr, s));
     // stage 1 in reverse: -> W^n, grad W^n (W^n also enters both updates directly)
     fx = gks::AdjFlux{a.coef1, a.Wb1, a.Gb1, a.Wbs, a.Gbs, a.CB, a.EQ, a.SB};
     HIP_TRY(c, gks::launch_flux_vjp(dm, fx, c->par, dt, gks::FLUX_ADJ_STAGE1, f32, s));
@@ -1333,7 +1342,8 @@ gks_status gks_step_adjoint(gks_ctx *c, double dt, const double *W_n, const doub
     r.slopes = a.slopes1;
     r.flag = a.flag1;
     HIP_TRY(c, gks::launch_recon_vjp(dm, r, c->par, f32, s));
-    HIP_TRY(c, gks::launch_recon_gather(dm, r, f32, a.Gbn, a.Wbn, a.Wb1, a.Wbs, s));
+    HIP_TRY(c, gks::launch_wall_recon_vjp(dm, r, c->par, f32, s));
+    HIP_TRY(c, gks::launch_recon_gather(dm, r, c->par, f32, a.Gbn, a.Wbn, a.Wb1, a.Wbs, s));
     // internal order -> caller order
     HIP_TRY(c, gks::launch_permute_rows(Wbar_n, a.Wbn, c->d_cperm, nc, 5, 1, false, s));
     HIP_TRY(c, gks::launch_permute_rows(gWbar_n, a.Gbn, c->d_cperm, nc, 15, 1, false, s));

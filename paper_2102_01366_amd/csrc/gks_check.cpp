@@ -186,6 +186,46 @@ extern "C" gks_status gks_flux_face_check(const gks_config *cfg, double dt, cons
     return GKS_OK;
 }
 
+extern "C" gks_status gks_wall_ghost_check(const gks_config *cfg, int32_t tag, const double uw[3],
+                                           const double x[20], const double v[20], const double ybar[20],
+                                           double y[20], double jv[20], double xbar[20])
+{
+    if (!cfg || !uw || !x || !v || !ybar || !y || !jv || !xbar) return GKS_E_INVAL;
+    if (tag != GKS_FACE_NOSLIP_ADIABATIC && tag != GKS_FACE_NOSLIP_ISOTHERMAL) return GKS_E_INVAL;
+    const gks::Params p = gks::params_from_config(cfg);
+    const bool iso = tag == GKS_FACE_NOSLIP_ISOTHERMAL;
+    Dual w[5], g[3][5], wg[5], gg[3][5], u[3];
+    for (int q = 0; q < 5; ++q) {
+        w[q] = Dual(x[q], v[q]);
+        for (int j = 0; j < 3; ++j) g[j][q] = Dual(x[5 + 5 * j + q], v[5 + 5 * j + q]);
+    }
+    for (int a = 0; a < 3; ++a) u[a] = Dual(uw[a]);
+    gks::noslip_ghost<Dual>(iso, Dual(p.gamma), Dual(p.wall_T), u, w, g, wg, gg);
+    for (int q = 0; q < 5; ++q) {
+        y[q] = wg[q].v;
+        jv[q] = wg[q].d;
+        for (int j = 0; j < 3; ++j) {
+            y[5 + 5 * j + q] = gg[j][q].v;
+            jv[5 + 5 * j + q] = gg[j][q].d;
+        }
+    }
+    double wd[5], gd[3][5], wgb[5], ggb[3][5], wb[5] = {0}, gbb[3][5] = {{0}};
+    for (int q = 0; q < 5; ++q) {
+        wd[q] = x[q];
+        wgb[q] = ybar[q];
+        for (int j = 0; j < 3; ++j) {
+            gd[j][q] = x[5 + 5 * j + q];
+            ggb[j][q] = ybar[5 + 5 * j + q];
+        }
+    }
+    gks::noslip_ghost_rev<double>(iso, p.gamma, p.wall_T, uw, wd, gd, wgb, ggb, wb, gbb);
+    for (int q = 0; q < 5; ++q) {
+        xbar[q] = wb[q];
+        for (int j = 0; j < 3; ++j) xbar[5 + 5 * j + q] = gbb[j][q];
+    }
+    return GKS_OK;
+}
+
 extern "C" gks_status gks_weno_check(const gks_config *cfg, const double geo[8], int32_t has_mask,
                                      const double x[25], const double v[25], const double rbar[10],
                                      double r[10], double jv[10], double xbar[25])

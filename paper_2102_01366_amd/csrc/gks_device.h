@@ -21,4 +21,44 @@ __device__ __forceinline__ int xcd_block()
 }
 __device__ __forceinline__ int xcd_gid() { return xcd_block() * blockDim.x + threadIdx.x; }
 
+// No-slip walls (Sec. 4.4): the prescribed value of component q (1-3
+// momentum, 4 energy) at a wall point is rho times this factor, rho the
+// density reconstructed there: U_wall, or |U_wall|^2/2 + T_wall/(gamma - 1)
+// with T = p / rho.
+template <typename R>
+__device__ __forceinline__ R wall_factor(int q, const R u[3], R gamma, R Tw)
+{
+    if (q <= 3) return u[q - 1];
+    return R(0.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) + Tw / (gamma - R(1));
+}
+template <typename R>
+__device__ __forceinline__ R wall_value(int q, R rho, const R u[3], R gamma, R Tw)
+{
+    return rho * wall_factor(q, u, gamma, Tw);
+}
+
+// a cell polynomial about its centroid, coefficients (c0, G, Hxx, Hyy, Hzz,
+// Hxy, Hxz, Hyz), at offset r; and the coefficients' weights at r
+template <typename R>
+__device__ __forceinline__ void quad_basis(const R r[3], R e[10])
+{
+    e[0] = R(1);
+    e[1] = r[0];
+    e[2] = r[1];
+    e[3] = r[2];
+    e[4] = R(0.5) * r[0] * r[0];
+    e[5] = R(0.5) * r[1] * r[1];
+    e[6] = R(0.5) * r[2] * r[2];
+    e[7] = r[0] * r[1];
+    e[8] = r[0] * r[2];
+    e[9] = r[1] * r[2];
+}
+template <typename R>
+__device__ __forceinline__ R quad_value(const R c[10], const R r[3])
+{
+    return c[0] + c[1] * r[0] + c[2] * r[1] + c[3] * r[2] +
+           R(0.5) * (c[4] * r[0] * r[0] + c[5] * r[1] * r[1] + c[6] * r[2] * r[2]) + c[7] * r[0] * r[1] +
+           c[8] * r[0] * r[2] + c[9] * r[1] * r[2];
+}
+
 }  // namespace gks

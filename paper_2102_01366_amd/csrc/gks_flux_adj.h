@@ -964,6 +964,153 @@ GKS_HD void gks_point_vjp(const Params &p, R dt, const R wl[5], const R gl[3][5]
     }
 }
 
+// Reverse of noslip_ghost (gks_flux.h): given the adjoints wgb, ggb of the
+// ghost state and gradient, adds the adjoints of the interior point state w
+// and gradient g.  The forward quantities are recomputed.
+template <typename R>
+GKS_HD void noslip_ghost_rev(bool iso, R gamma, R Tw, const R uw[3], const R w[5], const R g[3][5],
+                             const R wgb[5], const R ggb[3][5], R wb[5], R gb[3][5])
+{
+    const R g1 = gamma - R(1), rho = w[0], ir = R(1) / rho;
+    R U[3], Ug[3], Q = R(0), Qg = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        U[a] = w[1 + a] * ir;
+        Ug[a] = R(2) * uw[a] - U[a];
+        Q += R(0.5) * U[a] * U[a];
+        Qg += R(0.5) * Ug[a] * Ug[a];
+    }
+    const R p = g1 * (w[4] - rho * Q), T = p * ir;
+    const R Tg = iso ? R(2) * Tw - T : T, rhog = p / Tg;
+    R rhob = R(0), irb = R(0), Ub[3] = {R(0), R(0), R(0)}, Ugb[3] = {R(0), R(0), R(0)};
+    R Qb = R(0), Qgb = R(0), pb = R(0), Tb = R(0), Tgb = R(0), rhogb = R(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        // forward of axis j
+        const R dr = g[j][0];
+        R dU[3], dQ = R(0), dQg = R(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            dU[a] = (g[j][1 + a] - dr * U[a]) * ir;
+            dQ += U[a] * dU[a];
+            dQg += Ug[a] * dU[a];
+        }
+        const R dp = g1 * (g[j][4] - dr * Q - rho * dQ);
+        const R dT = (dp - dr * T) * ir;
+        const R dTg = iso ? dT : -dT;
+        const R drg = (-dp - dTg * rhog) / Tg;
+        // reverse: gg[j][0] = drg, gg[j][1+a] = drg Ug + rhog dU, gg[j][4] = drg Qg + rhog dQg - dp/g1
+        R drgb = ggb[j][0] + ggb[j][4] * Qg;
+        R dUb[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            drgb += ggb[j][1 + a] * Ug[a];
+            Ugb[a] += ggb[j][1 + a] * drg;
+            rhogb += ggb[j][1 + a] * dU[a];
+            dUb[a] = ggb[j][1 + a] * rhog;
+        }
+        Qgb += ggb[j][4] * drg;
+        rhogb += ggb[j][4] * dQg;
+        const R dQgb = ggb[j][4] * rhog;
+        R dpb = -ggb[j][4] / g1;
+        // drg = (-dp - dTg rhog) / Tg
+        dpb -= drgb / Tg;
+        const R dTgb = -drgb * rhog / Tg;
+        rhogb -= drgb * dTg / Tg;
+        Tgb -= drgb * drg / Tg;
+        const R dTb = iso ? dTgb : -dTgb;
+        // dT = (dp - dr T) ir
+        dpb += dTb * ir;
+        R drb = -dTb * T * ir;
+        Tb -= dTb * dr * ir;
+        irb += dTb * (dp - dr * T);
+        // dp = g1 (g4 - dr Q - rho dQ)
+        gb[j][4] += dpb * g1;
+        drb -= dpb * g1 * Q;
+        Qb -= dpb * g1 * dr;
+        rhob -= dpb * g1 * dQ;
+        const R dQb = -dpb * g1 * rho;
+        // dQ = sum U dU, dQg = sum Ug dU, dU = (g - dr U) ir
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Ub[a] += dQb * dU[a];
+            Ugb[a] += dQgb * dU[a];
+            const R dUt = dUb[a] + dQb * U[a] + dQgb * Ug[a];
+            gb[j][1 + a] += dUt * ir;
+            drb -= dUt * U[a] * ir;
+            Ub[a] -= dUt * dr * ir;
+            irb += dUt * (g[j][1 + a] - dr * U[a]);
+        }
+        gb[j][0] += drb;
+    }
+    // wg = (rhog, rhog Ug, rhog Qg + p/g1)
+    rhogb += wgb[0] + wgb[4] * Qg;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        rhogb += wgb[1 + a] * Ug[a];
+        Ugb[a] += wgb[1 + a] * rhog;
+    }
+    Qgb += wgb[4] * rhog;
+    pb += wgb[4] / g1;
+    // rhog = p / Tg, Tg = 2 Tw - T or T, T = p ir
+    pb += rhogb / Tg;
+    Tgb -= rhogb * rhog / Tg;
+    Tb += iso ? -Tgb : Tgb;
+    pb += Tb * ir;
+    irb += Tb * p;
+    // p = g1 (w4 - rho Q)
+    wb[4] += pb * g1;
+    rhob -= pb * g1 * Q;
+    Qb -= pb * g1 * rho;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Ugb[a] += Qgb * Ug[a];
+        Ub[a] += Qb * U[a] - Ugb[a];
+        wb[1 + a] += Ub[a] * ir;
+        irb += Ub[a] * w[1 + a];
+    }
+    rhob -= irb * ir * ir;
+    wb[0] += rhob;
+}
+
+// The wall ghost of a point and its reverse, as the flux uses them: the
+// slip mirror (its own transpose) or the no-slip reflection.
+template <typename R>
+GKS_HD void wall_ghost(const Params &p, int tag, const R T[3][3], const R u[3], const R wl[5], const R gl[3][5],
+                       R wr[5], R gr[3][5])
+{
+    if (tag == WALL_SLIP) {
+        slip_ghost(wl, gl, wr, gr);
+        return;
+    }
+    R uw[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) uw[a] = T[a][0] * u[0] + T[a][1] * u[1] + T[a][2] * u[2];
+    noslip_ghost(tag == WALL_ISOTHERMAL, R(p.gamma), R(p.wall_T), uw, wl, gl, wr, gr);
+}
+
+// wrb, grb: adjoints of the ghost; adds to wlb, glb
+template <typename R>
+GKS_HD void wall_ghost_rev(const Params &p, int tag, const R T[3][3], const R u[3], const R wl[5],
+                           const R gl[3][5], const R wrb[5], const R grb[3][5], R wlb[5], R glb[3][5])
+{
+    if (tag == WALL_SLIP) {
+        R wg[5], gg[3][5];
+        slip_ghost(wrb, grb, wg, gg);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            wlb[q] += wg[q];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) glb[d][q] += gg[d][q];
+        }
+        return;
+    }
+    R uw[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) uw[a] = T[a][0] * u[0] + T[a][1] * u[1] + T[a][2] * u[2];
+    noslip_ghost_rev(tag == WALL_ISOTHERMAL, R(p.gamma), R(p.wall_T), uw, wl, gl, wrb, grb, wlb, glb);
+}
+
 // Reverse of the rotation in eval_local: adjoints of the rotated point state
 // w and gradient g (face frame) to the unrotated W[5] and G[5][3] (set).
 template <typename R>

@@ -34,8 +34,19 @@ constexpr int kFluxThreadsA = 256;
 // (the slip ghost on a wall face) and the offsets of the polynomial
 // evaluations; with ADJ also the adjoints Fob, Wob of the point outputs,
 // formed from the cells' adjoints (the transpose of the cell update).
+// the wall tag of wall face f and its wall velocity (global frame)
+template <typename R>
+__device__ __forceinline__ int wall_bc(const DevMesh &m, int f, R u[3])
+{
+    const int w = f - m.nfi, nw = m.nf - m.nfi;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) u[d] = static_cast<const R *>(m.wvel)[(size_t)d * nw + w];
+    return m.wtag[w];
+}
+
 template <typename R, int MODE, bool WALL, bool ADJ>
-__device__ __forceinline__ void gp_setup(const DevMesh &m, const AdjFlux &a, int f, int k, double dt_, R T[3][3],
+__device__ __forceinline__ void gp_setup(const DevMesh &m, const AdjFlux &a, const Params &p, int f, int k, double dt_,
+                                         R T[3][3],
                                          R wl[5], R gl[3][5], R wr[5], R gr[3][5], R off[2][3], R Fob[2][5],
                                          R Wob[2][5])
 {
@@ -52,10 +63,13 @@ __device__ __forceinline__ void gp_setup(const DevMesh &m, const AdjFlux &a, int
     rotation(nrm, T);
     const R *coef = static_cast<const R *>(a.coef);
     eval_local(CoefView<R>{coef, n, L}, off[0], T, wl, gl);
-    if (WALL)
-        slip_ghost(wl, gl, wr, gr);
-    else
+    if (WALL) {
+        R u[3];
+        const int tag = wall_bc(m, f, u);
+        wall_ghost(p, tag, T, u, wl, gl, wr, gr);
+    } else {
         eval_local(CoefView<R>{coef, n, Rc}, off[1], T, wr, gr);
+    }
     if (!ADJ) return;
     const double iL = m.geoD[(size_t)G_INVVOL * n + L];
     const double iR = WALL ? 0.0 : m.geoD[(size_t)G_INVVOL * n + Rc];
@@ -120,7 +134,7 @@ __global__ __launch_bounds__(kFluxThreadsA) void flux_vjp_eq_kernel(DevMesh m, A
     const int f = f0 + xcd_block() * 84 + wave * 21 + slot;
     if (slot >= 21 || f >= f1) return;
     R T[3][3], wl[5], gl[3][5], wr[5], gr[3][5], off[2][3], Fob[2][5], Wob[2][5];
-    gp_setup<R, MODE, WALL, true>(m, a, f, k, dt_, T, wl, gl, wr, gr, off, Fob, Wob);
+    gp_setup<R, MODE, WALL, true>(m, a, p, f, k, dt_, T, wl, gl, wr, gr, off, Fob, Wob);
     PointFwd<R> P;
     point_forward<R, VISC, SMOOTH>(p, R(dt_), wl, wr, P);
     EqAdj<R> E;
@@ -158,7 +172,7 @@ __global__ __launch_bounds__(kFluxThreadsA) void flux_vjp_side_kernel(DevMesh m,
     const int f = f0 + xcd_block() * 40 + wave * 10 + slot;
     if (slot >= 10 || f >= f1) return;
     R T[3][3], wl[5], gl[3][5], wr[5], gr[3][5], off[2][3], Fob[2][5], Wob[2][5];
-    gp_setup<R, MODE, WALL, true>(m, a, f, k, dt_, T, wl, gl, wr, gr, off, Fob, Wob);
+    gp_setup<R, MODE, WALL, true>(m, a, p, f, k, dt_, T, wl, gl, wr, gr, off, Fob, Wob);
     PointFwd<R> P;
     point_forward<R, VISC, SMOOTH>(p, R(dt_), wl, wr, P);
     const size_t ng = 3 * (size_t)m.nf, g = 3 * (size_t)f + k;
@@ -246,7 +260,7 @@ __global__ __launch_bounds__(kFluxThreadsA) void flux_vjp_common_kernel(DevMesh 
     }
     if (live) {
         R T[3][3], wl[5], gl[3][5], wr[5], gr[3][5], Fob[2][5], Wob[2][5];
-        gp_setup<R, MODE, WALL, false>(m, a, f, k, dt_, T, wl, gl, wr, gr, off, Fob, Wob);
+        gp_setup<R, MODE, WALL, false>(m, a, p, f, k, dt_, T, wl, gl, wr, gr, off, Fob, Wob);
         PointFwd<R> P;
         point_forward<R, VISC, SMOOTH>(p, R(dt_), wl, wr, P);
         const size_t ng = 3 * (size_t)nf, g = 3 * (size_t)f + k;
@@ -272,18 +286,15 @@ __global__ __launch_bounds__(kFluxThreadsA) void flux_vjp_common_kernel(DevMesh 
         R wlb[5], wrb[5];
         common_reverse<R, VISC, SMOOTH>(p, R(dt_), wl, wr, P, E, SL, SR, wlb, wrb);
         if (WALL) {
-            // the ghost is a linear function of the left state; its transpose is itself
-            R wg[5], gg[3][5];
-            slip_ghost(wrb, SR.grb, wg, gg);
+            // the ghost is a function of the left state: its reverse
+            R u[3];
+            const int tag = wall_bc(m, f, u);
+            wall_ghost_rev(p, tag, T, u, wl, gl, wrb, SR.grb, wlb, SL.grb);
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
-                wlb[q] += wg[q];
                 wrb[q] = R(0);
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    SL.grb[d][q] += gg[d][q];
-                    SR.grb[d][q] = R(0);
-                }
+                for (int d = 0; d < 3; ++d) SR.grb[d][q] = R(0);
             }
         }
         point_adjoint_global(T, wlb, SL.grb, Wb[0], Gb[0]);

@@ -111,6 +111,7 @@ struct DevMesh {
     const void *wvel;   // [3][nf - nfi] wall velocity (global frame)
     int nwc;            // wall cells (cells with a no-slip face)
     const int *wcell;   // [nwc] their internal ids
+    const int *widx;    // [nc] wall-cell index of a cell, -1 if it has no no-slip face
     const int *wmode;   // [4][nwc]
     const void *wop;    // [kWallRows][nwc]
 };
@@ -229,8 +230,11 @@ hipError_t launch_recon_vjp(const DevMesh &m, const AdjRecon &a, const Params &p
 // gathers the neighbour terms (fixed slot order) and applies the reverse of the
 // step-1 slopes: Gout = adjoint of the stage's input gradient (complete); then
 // Wout = adjoint of its input W + X1 + X2 (X1, X2 may be null)
-hipError_t launch_recon_gather(const DevMesh &m, const AdjRecon &a, bool fp32, double *Gout,
+hipError_t launch_recon_gather(const DevMesh &m, const AdjRecon &a, const Params &p, bool fp32, double *Gout,
                                double *Wout, const double *X1, const double *X2, hipStream_t st);
+// the step-2 reverse of the no-slip wall cells (after launch_recon_vjp, which
+// it overwrites for them)
+hipError_t launch_wall_recon_vjp(const DevMesh &m, const AdjRecon &a, const Params &p, bool fp32, hipStream_t st);
 
 // block size for the one-thread-per-item kernels
 constexpr int kBlock = 256;

@@ -405,21 +405,6 @@ __global__ __launch_bounds__(kBlock) void reconstruct2_kernel(DevMesh m, DevStat
 // constrained; the wall values of the other components take the density
 // reconstructed at the constraint point.
 // ===========================================================================
-template <typename R>
-__device__ __forceinline__ R wall_value(int q, R rho, const R u[3], R gamma, R Tw)
-{
-    if (q <= 3) return rho * u[q - 1];
-    return rho * (R(0.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) + Tw / (gamma - R(1)));
-}
-
-template <typename R>
-__device__ __forceinline__ R quad_value(const R c[10], const R r[3])
-{
-    return c[0] + c[1] * r[0] + c[2] * r[1] + c[3] * r[2] +
-           R(0.5) * (c[4] * r[0] * r[0] + c[5] * r[1] * r[1] + c[6] * r[2] * r[2]) + c[7] * r[0] * r[1] +
-           c[8] * r[0] * r[2] + c[9] * r[1] * r[2];
-}
-
 constexpr int kWallBlock = 256;
 
 // step 1: b = K1N (Q_a - Q_0) + K1C (c_j - Q_0), c_j at the face centres from

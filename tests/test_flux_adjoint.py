@@ -128,3 +128,38 @@ def test_weno_reverse_is_the_transpose(nonlinear, order):
         rp = G.weno_check(cfg, geo, mask, x + h * v, v, rb)[0]
         rm = G.weno_check(cfg, geo, mask, x - h * v, v, rb)[0]
         assert np.abs((rp - rm) / (2 * h) - jv).max() <= 1e-5 * np.abs(jv).max()
+
+
+@pytest.mark.parametrize("tag", [3, 4], ids=["adiabatic", "isothermal"])
+def test_noslip_ghost_reverse_is_the_transpose(tag):
+    """The reverse of the no-slip ghost state (Sec. 4.4) against the dual-number
+    forward, and the forward derivative against central differences."""
+    rng = np.random.default_rng(16)
+    cfg = G.default_config(wall_T=0.9)
+    for _ in range(20):
+        uw = rng.uniform(-0.3, 0.3, 3)
+        x = np.concatenate([_state(rng), 0.3 * rng.standard_normal(15)])
+        v, yb = rng.standard_normal(20), rng.standard_normal(20)
+        y, jv, xb = G.wall_ghost_check(cfg, tag, uw, x, v, yb)
+        a, b = jv @ yb, v @ xb
+        assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
+        h = 1e-6
+        yp = G.wall_ghost_check(cfg, tag, uw, x + h * v, v, yb)[0]
+        ym = G.wall_ghost_check(cfg, tag, uw, x - h * v, v, yb)[0]
+        assert np.abs((yp - ym) / (2 * h) - jv).max() <= 1e-7 * np.abs(jv).max()
+
+
+def test_noslip_ghost_matches_oracle(oracle_lib):
+    """The library's ghost (face frame, normal e3 so that the frame is the
+    global one up to the axis order) against the oracle's (global frame)."""
+    rng = np.random.default_rng(17)
+    cfg = G.default_config(wall_T=0.9)
+    ocfg = oracle_lib.make_config(wall_T=0.9)
+    for tag in (3, 4):
+        for _ in range(5):
+            uw = rng.uniform(-0.3, 0.3, 3)
+            w, g = _state(rng), 0.3 * rng.standard_normal((3, 5))
+            y = G.wall_ghost_check(cfg, tag, uw, np.concatenate([w, g.reshape(15)]), np.zeros(20), np.zeros(20))[0]
+            Wg, gWg = oracle_lib.wall_ghost(ocfg, tag, np.array([1.0, 0, 0]), uw, w, g.T.reshape(15))
+            np.testing.assert_allclose(y[:5], Wg, rtol=1e-14, atol=1e-15)
+            np.testing.assert_allclose(y[5:].reshape(3, 5), gWg.reshape(5, 3).T, rtol=1e-12, atol=1e-13)
