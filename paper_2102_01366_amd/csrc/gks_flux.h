@@ -19,9 +19,11 @@ namespace gks {
 
 // Maxwellian g = rho (lam/pi)^((K+3)/2) exp(-lam(|u-U|^2 + xi^2)) of a state;
 // rho E = rho (|U|^2/2 + (K+3)/(4 lam)).
+// ir = 1/rho and ilam = 1/lam are kept so that the many quotients by rho and
+// lam below are products (FP64 division is a long instruction sequence).
 template <typename R>
 struct Prim {
-    R rho, U, V, W, lam;
+    R rho, U, V, W, lam, ir, ilam;
 };
 
 template <typename R>
@@ -29,15 +31,24 @@ GKS_HD Prim<R> primitive(const R w[5], R K)
 {
     Prim<R> g;
     g.rho = w[0];
-    const R ir = R(1) / w[0];
-    g.U = w[1] * ir;
-    g.V = w[2] * ir;
-    g.W = w[3] * ir;
+    g.ir = R(1) / w[0];
+    g.U = w[1] * g.ir;
+    g.V = w[2] * g.ir;
+    g.W = w[3] * g.ir;
     g.lam = (K + R(3)) * w[0] / (R(4) * (w[4] - R(0.5) * w[0] * (g.U * g.U + g.V * g.V + g.W * g.W)));
+    g.ilam = R(1) / g.lam;
     return g;
 }
 
-// normalised moments <c^k>, k < N, of a Gaussian of mean U and variance 1/(2 lam)
+// normalised moments <c^k>, k < N, of a Gaussian of mean U and variance h = 1/(2 lam)
+template <int N, typename R>
+GKS_HD void gauss_moments_h(R U, R h, R *m)
+{
+    m[0] = R(1);
+    m[1] = U;
+#pragma unroll
+    for (int k = 0; k + 2 < N; ++k) m[k + 2] = U * m[k + 1] + R(k + 1) * h * m[k];
+}
 template <int N, typename R>
 GKS_HD void gauss_moments(R U, R lam, R *m)
 {
@@ -77,10 +88,11 @@ struct Tab {
 template <typename R>
 GKS_HD void vw_tables(const Prim<R> &g, R K, Tab<R> &t)
 {
-    gauss_moments<6>(g.V, g.lam, t.v);
-    gauss_moments<6>(g.W, g.lam, t.w);
-    t.xi2 = K * R(0.5) / g.lam;
-    t.xi4 = K * (K + R(2)) * R(0.25) / (g.lam * g.lam);
+    const R h = R(0.5) * g.ilam;
+    gauss_moments_h<6>(g.V, h, t.v);
+    gauss_moments_h<6>(g.W, h, t.w);
+    t.xi2 = K * h;
+    t.xi4 = K * (K + R(2)) * (h * h);
 }
 
 // t[j] = <u^A v^B w^C psi_j>, psi = (1, u, v, w, (u^2+v^2+w^2+xi^2)/2)
@@ -142,10 +154,11 @@ template <typename R>
 GKS_HD void micro_slope(const Prim<R> &g, R K, const R b[5], R a[5])
 {
     const R U = g.U, V = g.V, W = g.W, lam = g.lam;
-    const R q2 = U * U + V * V + W * W + (K + R(3)) / (R(2) * lam);
+    const R q2 = U * U + V * V + W * W + (K + R(3)) * (R(0.5) * g.ilam);
     const R R1 = b[1] - U * b[0], R2 = b[2] - V * b[0], R3 = b[3] - W * b[0];
     const R R4 = R(2) * b[4] - q2 * b[0];
-    a[4] = R(4) * lam * lam / (K + R(3)) * (R4 - R(2) * U * R1 - R(2) * V * R2 - R(2) * W * R3);
+    // 4 / (K + 3) is the same quotient in every call
+    a[4] = lam * lam * (R(4) / (K + R(3))) * (R4 - R(2) * U * R1 - R(2) * V * R2 - R(2) * W * R3);
     a[1] = R(2) * lam * R1 - U * a[4];
     a[2] = R(2) * lam * R2 - V * a[4];
     a[3] = R(2) * lam * R3 - W * a[4];
@@ -177,10 +190,11 @@ template <typename R, bool VISC>
 GKS_HD void time_coefficients(R tau, R taun, R dt, TimeCoef<R> &tc)
 {
     tc.tau = tau;
+    const R itaun = R(1) / taun;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const R del = k == 0 ? dt : R(0.5) * dt;
-        const R e = exp(-del / taun);
+        const R e = exp(-del * itaun);
         const R E1 = taun * (R(1) - e);
         const R E2 = taun * taun * (R(1) - e) - taun * del * e;
         if (VISC) {
@@ -199,7 +213,7 @@ GKS_HD void time_coefficients(R tau, R taun, R dt, TimeCoef<R> &tc)
             tc.cF[k][5] = R(0);
         }
     }
-    const R et = exp(-dt / taun);
+    const R et = exp(-dt * itaun);
     tc.cW[0] = R(1) - et;
     tc.cW[3] = et;
     if (VISC) {
@@ -272,7 +286,7 @@ GKS_HD void side_terms(const Params &p, const Prim<R> &g, R m0, R m1, const R gr
     const R K = R(p.K);
     Tab<R> Th;
     {
-        const R h = R(0.5) / g.lam;
+        const R h = R(0.5) * g.ilam;
         Th.u[0] = m0;
         Th.u[1] = m1;
 #pragma unroll
@@ -280,7 +294,7 @@ GKS_HD void side_terms(const Params &p, const Prim<R> &g, R m0, R m1, const R gr
     }
     vw_tables(g, K, Th);
     if constexpr (SMOOTH) {
-        const R ir = R(1) / g.rho;
+        const R ir = g.ir;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             R b[5], a[5];
@@ -299,7 +313,7 @@ GKS_HD void side_terms(const Params &p, const Prim<R> &g, R m0, R m1, const R gr
     R B[5] = {R(0), R(0), R(0), R(0), R(0)};
     Tab<R> Tf;
     if (VISC) {
-        gauss_moments<7>(g.U, g.lam, Tf.u);
+        gauss_moments_h<7>(g.U, R(0.5) * g.ilam, Tf.u);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             Tf.v[k] = Th.v[k];
@@ -308,7 +322,7 @@ GKS_HD void side_terms(const Params &p, const Prim<R> &g, R m0, R m1, const R gr
         Tf.xi2 = Th.xi2;
         Tf.xi4 = Th.xi4;
     }
-    const R ir = R(1) / g.rho;
+    const R ir = g.ir;
     // one direction at a time: a_d, its share of g^c_{x_d}, of
     // sum_d <u u_d (a_d.psi) psi> and of sum_d <u_d (a_d.psi) psi>
 #pragma unroll
@@ -356,17 +370,20 @@ GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], co
     // half-line seeds <1> and <u> of both sides
     R l0, l1, r0, r1;
     {
-        const R sl = sqrt(gL.lam), e = exp(-gL.lam * gL.U * gL.U) / (R(2) * sqrt(R(M_PI) * gL.lam));
+        // exp(-lam U^2) / (2 sqrt(pi lam)) = exp(-lam U^2) sqrt(pi lam) / (2 pi lam)
+        const R sl = sqrt(gL.lam),
+                e = exp(-gL.lam * gL.U * gL.U) * (sqrt(R(M_PI) * gL.lam) * gL.ilam) * R(0.5 / M_PI);
         l0 = R(0.5) * erfc(-sl * gL.U);
         l1 = gL.U * l0 + e;
-        const R sr = sqrt(gR.lam), f = exp(-gR.lam * gR.U * gR.U) / (R(2) * sqrt(R(M_PI) * gR.lam));
+        const R sr = sqrt(gR.lam),
+                f = exp(-gR.lam * gR.U * gR.U) * (sqrt(R(M_PI) * gR.lam) * gR.ilam) * R(0.5 / M_PI);
         r0 = R(0.5) * erfc(sr * gR.U);
         r1 = gR.U * r0 - f;
     }
     // eq. new-equ-part: W^c = rho_l <psi>_{u>0} + rho_r <psi>_{u<0}
     R Wc[5];
     {
-        const R hl = R(0.5) / gL.lam, hr = R(0.5) / gR.lam;
+        const R hl = R(0.5) * gL.ilam, hr = R(0.5) * gR.ilam;
         const R l2 = gL.U * l1 + hl * l0, r2 = gR.U * r1 + hr * r0;
         const R tl = gL.V * gL.V + gL.W * gL.W + (R(2) + K) * hl;
         const R tr = gR.V * gR.V + gR.W * gR.W + (R(2) + K) * hr;
@@ -379,7 +396,7 @@ GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], co
     const Prim<R> gC = primitive(Wc, K);
     const R Uc[3] = {gC.U, gC.V, gC.W};
     // collision times (Sec. 2.2)
-    const R pl = gL.rho * R(0.5) / gL.lam, pr = gR.rho * R(0.5) / gR.lam, pc = gC.rho * R(0.5) / gC.lam;
+    const R pl = gL.rho * R(0.5) * gL.ilam, pr = gR.rho * R(0.5) * gR.ilam, pc = gC.rho * R(0.5) * gC.ilam;
     TimeCoef<R> tc;
     if constexpr (SMOOTH) {
         time_coefficients_smooth<R>(VISC ? R(p.mu) / pc : R(0), dt, tc);
@@ -408,12 +425,12 @@ GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], co
     side_terms<R, VISC, PRFIX, SMOOTH>(p, gR, r0, r1, gr, tc, Uc, gc, Fo, Wo);
     // equilibrium part: g^c with slopes a^c (from g^c_x) and A^c
     Tab<R> TC;
-    gauss_moments<7>(gC.U, gC.lam, TC.u);
+    gauss_moments_h<7>(gC.U, R(0.5) * gC.ilam, TC.u);
     vw_tables(gC, K, TC);
     R F[3][5], V[3][5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) F[1][q] = V[1][q] = F[2][q] = V[2][q] = R(0);
-    const R irc = R(1) / gC.rho;
+    const R irc = gC.ir;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         R b[5], a[5];
