@@ -108,7 +108,7 @@ GKS_HD void vw_tables_rev(const Prim<R> &g, R K, const Tab<R> &t, TabB<R> &tb, P
     gauss_moments_rev<6>(g.V, g.lam, t.v, vb, gb.V, gb.lam);
     gauss_moments_rev<6>(g.W, g.lam, t.w, wb, gb.W, gb.lam);
     // xi2 = K / (2 lam), xi4 = K (K+2) / (4 lam^2)
-    gb.lam -= tb.xi2 * t.xi2 / g.lam + tb.xi4 * R(2) * t.xi4 / g.lam;
+    gb.lam -= tb.xi2 * t.xi2 * g.ilam + tb.xi4 * R(2) * t.xi4 * g.ilam;
 }
 
 template <int A, int B, int C, typename R>
@@ -454,7 +454,7 @@ GKS_HD void side_forward(const Params &p, const Prim<R> &g, R m0, R m1, const R 
 {
     const R K = R(p.K);
     {
-        const R h = R(0.5) / g.lam;
+        const R h = R(0.5) * g.ilam;
         S.Th.u[0] = m0;
         S.Th.u[1] = m1;
 #pragma unroll
@@ -462,7 +462,7 @@ GKS_HD void side_forward(const Params &p, const Prim<R> &g, R m0, R m1, const R 
     }
     vw_tables(g, K, S.Th);
     if constexpr (SMOOTH) {
-        const R ir = R(1) / g.rho;
+        const R ir = g.ir;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             R b[5];
@@ -478,7 +478,7 @@ GKS_HD void side_forward(const Params &p, const Prim<R> &g, R m0, R m1, const R 
 #pragma unroll
     for (int q = 0; q < 5; ++q) S.F[1][q] = S.V[1][q] = S.F[2][q] = S.V[2][q] = S.B[q] = S.A[q] = R(0);
     if (VISC) {
-        gauss_moments<7>(g.U, g.lam, S.Tf.u);
+        gauss_moments_h<7>(g.U, R(0.5) * g.ilam, S.Tf.u);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             S.Tf.v[k] = S.Th.v[k];
@@ -487,7 +487,7 @@ GKS_HD void side_forward(const Params &p, const Prim<R> &g, R m0, R m1, const R 
         S.Tf.xi2 = S.Th.xi2;
         S.Tf.xi4 = S.Th.xi4;
     }
-    const R ir = R(1) / g.rho;
+    const R ir = g.ir;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         R b[5];
@@ -569,7 +569,7 @@ GKS_HD void side_terms_rev(const Params &p, const Prim<R> &g, R m0, R m1, const 
         micro_slope_rev(g, K, S.B, Ab, gb, Bb);
     }
     sched_fence();
-    const R ir = R(1) / g.rho;
+    const R ir = g.ir;
     R irb = R(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -638,13 +638,13 @@ GKS_HD void point_forward(const Params &p, R dt, const R wl[5], const R wr[5], P
     P.gR = primitive(wr, K);
     const Prim<R> &gL = P.gL, &gR = P.gR;
     const R sl = sqrt(gL.lam), sr = sqrt(gR.lam);
-    P.el = exp(-gL.lam * gL.U * gL.U) / (R(2) * sqrt(R(M_PI) * gL.lam));
-    P.er = exp(-gR.lam * gR.U * gR.U) / (R(2) * sqrt(R(M_PI) * gR.lam));
+    P.el = exp(-gL.lam * gL.U * gL.U) * (sqrt(R(M_PI) * gL.lam) * gL.ilam) * R(0.5 / M_PI);
+    P.er = exp(-gR.lam * gR.U * gR.U) * (sqrt(R(M_PI) * gR.lam) * gR.ilam) * R(0.5 / M_PI);
     P.l0 = R(0.5) * erfc(-sl * gL.U);
     P.l1 = gL.U * P.l0 + P.el;
     P.r0 = R(0.5) * erfc(sr * gR.U);
     P.r1 = gR.U * P.r0 - P.er;
-    const R hl = R(0.5) / gL.lam, hr = R(0.5) / gR.lam;
+    const R hl = R(0.5) * gL.ilam, hr = R(0.5) * gR.ilam;
     const R l2 = gL.U * P.l1 + hl * P.l0, r2 = gR.U * P.r1 + hr * P.r0;
     const R tl = gL.V * gL.V + gL.W * gL.W + (R(2) + K) * hl;
     const R tr = gR.V * gR.V + gR.W * gR.W + (R(2) + K) * hr;
@@ -657,8 +657,8 @@ GKS_HD void point_forward(const Params &p, R dt, const R wl[5], const R wr[5], P
     P.Uc[0] = P.gC.U;
     P.Uc[1] = P.gC.V;
     P.Uc[2] = P.gC.W;
-    P.pl = gL.rho * R(0.5) / gL.lam;
-    P.pr = gR.rho * R(0.5) / gR.lam;
+    P.pl = gL.rho * R(0.5) * gL.ilam;
+    P.pr = gR.rho * R(0.5) * gR.ilam;
     P.pc = P.gC.rho * R(0.5) / P.gC.lam;
     P.z = (P.pl - P.pr) / (P.pl + P.pr);
     if constexpr (SMOOTH) {
@@ -717,7 +717,7 @@ GKS_HD void eq_reverse(const Params &p, const PointFwd<R> &P, const R gl[3][5], 
     Tab<R> TC;
     gauss_moments<7>(gC.U, gC.lam, TC.u);
     vw_tables(gC, K, TC);
-    const R irc = R(1) / gC.rho;
+    const R irc = gC.ir;
     R ac[3][5], F[3][5], V[3][5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) F[1][q] = V[1][q] = F[2][q] = V[2][q] = R(0);
@@ -881,13 +881,13 @@ GKS_HD void common_reverse(const Params &p, R dt, const R wl[5], const R wr[5], 
         const R zb = jumpb * R(p.c_tau) * dt * sign_of(P.z);
         const R sp = P.pl + P.pr;
         const R plb = zb * R(2) * P.pr / (sp * sp), prb = -zb * R(2) * P.pl / (sp * sp);
-        gLb.rho += plb * R(0.5) / gL.lam;
-        gLb.lam -= plb * P.pl / gL.lam;
-        gRb.rho += prb * R(0.5) / gR.lam;
-        gRb.lam -= prb * P.pr / gR.lam;
+        gLb.rho += plb * R(0.5) * gL.ilam;
+        gLb.lam -= plb * P.pl * gL.ilam;
+        gRb.rho += prb * R(0.5) * gR.ilam;
+        gRb.lam -= prb * P.pr * gR.ilam;
     }
-    gCb.rho += pcb * R(0.5) / gC.lam;
-    gCb.lam -= pcb * P.pc / gC.lam;
+    gCb.rho += pcb * R(0.5) * gC.ilam;
+    gCb.lam -= pcb * P.pc * gC.ilam;
     // gC = primitive(Wc)
     R Wcb[5] = {R(0), R(0), R(0), R(0), R(0)};
     primitive_rev(P.Wc, K, gCb, Wcb);
@@ -895,7 +895,7 @@ GKS_HD void common_reverse(const Params &p, R dt, const R wl[5], const R wr[5], 
     // m2 = U m1 + h m0, t = V^2 + W^2 + (2+K) h
     const R s4 = R(0.5) * Wcb[4];
     {
-        const R hl = R(0.5) / gL.lam, l2 = gL.U * P.l1 + hl * P.l0;
+        const R hl = R(0.5) * gL.ilam, l2 = gL.U * P.l1 + hl * P.l0;
         const R tl = gL.V * gL.V + gL.W * gL.W + (R(2) + K) * hl;
         gLb.rho += Wcb[0] * P.l0 + Wcb[1] * P.l1 + Wcb[2] * gL.V * P.l0 + Wcb[3] * gL.W * P.l0 + s4 * (l2 + P.l0 * tl);
         const R l2b = gL.rho * s4, tlb = gL.rho * s4 * P.l0;
@@ -907,10 +907,10 @@ GKS_HD void common_reverse(const Params &p, R dt, const R wl[5], const R wr[5], 
         l1b += l2b * gL.U;
         l0b += l2b * hl;
         const R hlb = l2b * P.l0 + (R(2) + K) * tlb;
-        gLb.lam -= hlb * hl / gL.lam;
+        gLb.lam -= hlb * hl * gL.ilam;
     }
     {
-        const R hr = R(0.5) / gR.lam, r2 = gR.U * P.r1 + hr * P.r0;
+        const R hr = R(0.5) * gR.ilam, r2 = gR.U * P.r1 + hr * P.r0;
         const R tr = gR.V * gR.V + gR.W * gR.W + (R(2) + K) * hr;
         gRb.rho += Wcb[0] * P.r0 + Wcb[1] * P.r1 + Wcb[2] * gR.V * P.r0 + Wcb[3] * gR.W * P.r0 + s4 * (r2 + P.r0 * tr);
         const R r2b = gR.rho * s4, trb = gR.rho * s4 * P.r0;
@@ -922,7 +922,7 @@ GKS_HD void common_reverse(const Params &p, R dt, const R wl[5], const R wr[5], 
         r1b += r2b * gR.U;
         r0b += r2b * hr;
         const R hrb = r2b * P.r0 + (R(2) + K) * trb;
-        gRb.lam -= hrb * hr / gR.lam;
+        gRb.lam -= hrb * hr * gR.ilam;
     }
     // half-line seeds: d l0/dU = 2 lam e, d l0/dlam = U e, d l1/dU = l0,
     // d l1/dlam = -e/(2 lam); the right side with the signs of u < 0
