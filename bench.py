@@ -324,7 +324,7 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(the mesh would shard by cell partition with halo exchange).", file=sys.stderr)
         sys.exit(2)
 
