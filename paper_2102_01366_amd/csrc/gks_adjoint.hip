@@ -526,6 +526,12 @@ __global__ __launch_bounds__(kBlock) void recon_gather2_kernel(DevMesh m, AdjRec
 
 }  // namespace
 
+hipError_t launch_flux_vjp(const DevMesh &m, const AdjFlux &a, const Params &p, double dt, int mode, bool fp32,
+                           hipStream_t st)
+{
+    return fp32 ? launch_flux_vjp_t<float>(m, a, p, dt, mode, st) : launch_flux_vjp_t<double>(m, a, p, dt, mode, st);
+}
+
 hipError_t launch_recon_vjp(const DevMesh &m, const AdjRecon &a, const Params &p, bool fp32, hipStream_t st)
 {
     if (p.order == 2) {

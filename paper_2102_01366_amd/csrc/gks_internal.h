@@ -215,15 +215,14 @@ enum FluxAdjMode { FLUX_ADJ_STAGE1 = 1, FLUX_ADJ_STAGE2 = 2 };
 constexpr int kEqRec = 33;    // values of an AdjFlux::EQ record (per Gauss point)
 constexpr int kSideRec = 35;  // values of an AdjFlux::SB record (per Gauss point and side)
 
-// the flux stage's adjoint for one bulk type (gks_adjoint_flux_f64.hip, _f32.hip)
+// the flux stage's adjoint for one bulk type (gks_adjoint_flux_f64.hip, _f32.hip),
+// and the dispatch on the bulk type (gks_adjoint.hip, which does not see the
+// template's definition, so each type is compiled in its own unit only)
 template <typename R>
 hipError_t launch_flux_vjp_t(const DevMesh &m, const AdjFlux &a, const Params &p, double dt, int mode,
                              hipStream_t st);
-inline hipError_t launch_flux_vjp(const DevMesh &m, const AdjFlux &a, const Params &p, double dt, int mode,
-                                  bool fp32, hipStream_t st)
-{
-    return fp32 ? launch_flux_vjp_t<float>(m, a, p, dt, mode, st) : launch_flux_vjp_t<double>(m, a, p, dt, mode, st);
-}
+hipError_t launch_flux_vjp(const DevMesh &m, const AdjFlux &a, const Params &p, double dt, int mode, bool fp32,
+                           hipStream_t st);
 // adjoints of the reconstruction's inputs: own / neighbour terms
 hipError_t launch_recon_vjp(const DevMesh &m, const AdjRecon &a, const Params &p, bool fp32,
                             hipStream_t st);  // either order
