@@ -38,18 +38,22 @@ class Config(ctypes.Structure):
                 ("c_tau", ctypes.c_double), ("eps_weno", ctypes.c_double),
                 ("lw2", ctypes.c_double * 3), ("lw1", ctypes.c_double * 2),
                 ("viscous", ctypes.c_int32), ("nonlinear", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("flux", ctypes.c_int32), ("wall_T", ctypes.c_double)]
+                ("flux", ctypes.c_int32), ("wall_T", ctypes.c_double),
+                ("farfield", ctypes.c_double * 5)]
 
 
 def make_config(gamma=1.4, mu=0.0, prandtl=1.0, viscous=False, nonlinear=True,
                 eps_tau=0.01, c_tau=1.0, eps_weno=1e-8, lw2=(100.0, 10.0, 1.0),
-                lw1=(10.0, 1.0), K=None, order=3, flux=0, wall_T=1.0) -> Config:
+                lw1=(10.0, 1.0), K=None, order=3, flux=0, wall_T=1.0,
+                farfield=(1.0, 0.0, 0.0, 0.0, 2.5)) -> Config:
     """Scheme parameters; linear weights are given as ratios and normalised.
     flux: 0 for eq. 2nd-flux, 1 for the smooth-flow form eq. 2nd-smooth-flux."""
     c = Config()
     c.order = order
     c.flux = flux
     c.wall_T = wall_T
+    for q in range(5):
+        c.farfield[q] = farfield[q]
     c.gamma = gamma
     c.K = (5.0 - 3.0 * gamma) / (gamma - 1.0) if K is None else K
     c.mu = mu
@@ -209,7 +213,7 @@ class Oracle:
 
 def wall_ghost(cfg: Config, tag, n, uw, W, gW):
     """Ghost state (W, gW[15], component c direction d at 3c+d) of a wall
-    point: tag 2 slip, 3 no-slip adiabatic, 4 no-slip isothermal."""
+    point: tag 2 slip, 3 no-slip adiabatic, 4 no-slip isothermal, 5 far field."""
     Wg, gWg = np.empty(5), np.empty(15)
     rc = _load().or_wall_ghost(ctypes.byref(cfg), int(tag), _p(_f64(n)), _p(_f64(uw)), _p(_f64(W)),
                                _p(_f64(gW)), _p(Wg), _p(gWg))

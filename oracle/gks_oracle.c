@@ -57,6 +57,7 @@
 #define TAG_SLIP 2
 #define TAG_NOSLIP_ADIABATIC 3
 #define TAG_NOSLIP_ISOTHERMAL 4
+#define TAG_FARFIELD 5
 
 /* ======================================================================== */
 /* small dense linear algebra                                               */
@@ -293,7 +294,9 @@ or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
         c->fcell[f][1] = R;
         c->ftag[f] = face_tag[f];
         if (R < 0 && face_tag[f] != TAG_SLIP && face_tag[f] != TAG_NOSLIP_ADIABATIC &&
-            face_tag[f] != TAG_NOSLIP_ISOTHERMAL) { free(sumarea); or_destroy(c); return NULL; }
+            face_tag[f] != TAG_NOSLIP_ISOTHERMAL && face_tag[f] != TAG_FARFIELD) {
+            free(sumarea); or_destroy(c); return NULL;
+        }
         for (int d = 0; d < 3; ++d) c->fwu[f][d] = face_wall_u ? face_wall_u[3 * f + d] : 0.0;
         for (int d = 0; d < 3; ++d) c->fshift[f][d] = face_shift[3 * f + d];
         double x[3][3];
@@ -1519,10 +1522,63 @@ static void noslip_ghost(const or_config *cf, int iso, const double uw[3], const
     }
 }
 
+/* Far field (the Riemann invariants of the paper's external-flow cases): the
+ * locally one-dimensional characteristic state along the outward normal n.
+ * Supersonic outflow takes the interior state, supersonic inflow the free
+ * stream; otherwise the outgoing invariant u_n + 2a/(gamma-1) comes from the
+ * interior and the incoming u_n - 2a/(gamma-1) from the free stream, and the
+ * entropy p/rho^gamma and tangential velocity from the side the flow comes
+ * from.  The ghost is uniform (zero gradients). */
+static void farfield_ghost(const or_config *cf, const double n[3], const double W[5], double Wg[5],
+                           double gWg[15])
+{
+    double g = cf->gamma, g1 = g - 1.0;
+    const double *Wf = cf->farfield;
+    double ri = W[0], rf = Wf[0], Ui[3], Uf[3], ki = 0.0, kf = 0.0, uni = 0.0, unf = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        Ui[d] = W[1 + d] / ri;
+        Uf[d] = Wf[1 + d] / rf;
+        ki += 0.5 * Ui[d] * Ui[d];
+        kf += 0.5 * Uf[d] * Uf[d];
+        uni += Ui[d] * n[d];
+        unf += Uf[d] * n[d];
+    }
+    double pi = g1 * (W[4] - ri * ki), pf = g1 * (Wf[4] - rf * kf);
+    double ai = sqrt(g * pi / ri), af = sqrt(g * pf / rf);
+    for (int k = 0; k < 15; ++k) gWg[k] = 0.0;
+    if (uni >= ai) { /* supersonic outflow */
+        for (int q = 0; q < 5; ++q) Wg[q] = W[q];
+        return;
+    }
+    if (uni <= -ai) { /* supersonic inflow */
+        for (int q = 0; q < 5; ++q) Wg[q] = Wf[q];
+        return;
+    }
+    double Rp = uni + 2.0 * ai / g1, Rm = unf - 2.0 * af / g1;
+    double ub = 0.5 * (Rp + Rm), ab = 0.25 * g1 * (Rp - Rm);
+    double s, Ut[3];
+    if (ub > 0.0) {
+        s = pi / pow(ri, g);
+        for (int d = 0; d < 3; ++d) Ut[d] = Ui[d] - uni * n[d];
+    } else {
+        s = pf / pow(rf, g);
+        for (int d = 0; d < 3; ++d) Ut[d] = Uf[d] - unf * n[d];
+    }
+    double rb = pow(ab * ab / (g * s), 1.0 / g1), pb = rb * ab * ab / g, kb = 0.0;
+    Wg[0] = rb;
+    for (int d = 0; d < 3; ++d) {
+        double u = Ut[d] + ub * n[d];
+        Wg[1 + d] = rb * u;
+        kb += 0.5 * u * u;
+    }
+    Wg[4] = pb / g1 + rb * kb;
+}
+
 int or_wall_ghost(const or_config *cf, int32_t tag, const double n[3], const double uw[3], const double W[5],
                   const double gW[15], double Wg[5], double gWg[15])
 {
     if (tag == TAG_SLIP) mirror_ghost(n, W, gW, Wg, gWg);
+    else if (tag == TAG_FARFIELD) farfield_ghost(cf, n, W, Wg, gWg);
     else if (tag == TAG_NOSLIP_ADIABATIC || tag == TAG_NOSLIP_ISOTHERMAL)
         noslip_ghost(cf, tag == TAG_NOSLIP_ISOTHERMAL, uw, W, gW, Wg, gWg);
     else return -1;

@@ -38,12 +38,14 @@ typedef struct {
     int32_t flux;     /* 0: the full distribution of eq. 2nd-flux; 1: its smooth-flow form,
                          eq. 2nd-smooth-flux */
     double wall_T;    /* temperature p / rho of isothermal no-slip walls */
+    double farfield[5]; /* free-stream state (conservative) of far-field faces */
 } or_config;
 
 typedef struct or_ctx or_ctx;
 
 /* Build the oracle's mesh and geometry.  Wall faces (face_cell[2f+1] = -1)
- * carry tag 2 (slip), 3 (no-slip adiabatic) or 4 (no-slip isothermal);
+ * carry tag 2 (slip), 3 (no-slip adiabatic), 4 (no-slip isothermal) or 5
+ * (far field);
  * face_wall_u[3f..3f+2] is a no-slip face's wall velocity (NULL: walls at
  * rest).  Returns NULL on a malformed mesh. */
 or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
@@ -60,8 +62,8 @@ int or_geometry(const or_ctx *ctx, double *vol, double *cen, double *mom2, doubl
  * Gauss points [3 points][3][nf]. */
 int or_face_geometry(const or_ctx *ctx, double *area, double *normal, double *gp);
 
-/* The ghost state of a wall point (tag 2, 3 or 4; n the outward unit normal,
- * uw the wall velocity), global frame. */
+/* The ghost state of a wall point (tag 2, 3, 4 or 5; n the outward unit
+ * normal, uw the wall velocity), global frame. */
 int or_wall_ghost(const or_config *cfg, int32_t tag, const double n[3], const double uw[3], const double W[5],
                   const double gW[15], double Wg[5], double gWg[15]);
 

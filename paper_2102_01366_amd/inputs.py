@@ -34,6 +34,7 @@ FACE_PERIODIC = 1
 FACE_SLIP = 2
 FACE_NOSLIP_ADIABATIC = 3
 FACE_NOSLIP_ISOTHERMAL = 4
+FACE_FARFIELD = 5
 
 
 @dataclass
