@@ -15,8 +15,9 @@ events that the library records on its stream around each kernel, over the
 same number of steps right after the timed region), the FP32-bulk form's throughput and error, the
 differentiation form (adjoint / forward time and its finite-difference
 check), the walled blast workload (1.57M cells, slip walls), the lid-driven
-cavity (no-slip isothermal walls, smooth-flow flux) and the FP64 CPU oracle
-timed on a bounded sample.
+cavity (no-slip isothermal walls, smooth-flow flux), flow past a sphere on a
+cubed-sphere shell (1.77M cells, slip wall and far field) and the FP64 CPU
+oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -300,6 +301,44 @@ def cavity_leg(G, I, n, steps, warmup):
     return out
 
 
+def sphere_leg(G, I, n, layers, steps, warmup):
+    """The curved-wall workload's mesh with straight faces: inviscid Mach 0.3
+    flow past the unit sphere on a cubed-sphere shell (6 panels of n x n
+    cells, `layers` radial layers stretched by 1.08 out to r = 20, each
+    hexahedron split into 6 tetrahedra), slip wall on the sphere, far field
+    by Riemann invariants, impulsive start from the free stream rho = 1,
+    U = (0.3, 0, 0), p = 1/gamma, third-order WENO, CFL 0.5; FP64 and
+    FP32-bulk."""
+    import numpy as np
+    import torch
+    gamma = 1.4
+    mesh = I.cubed_sphere_shell(n, layers, r_out=20.0, ratio=1.08)
+    W, gW = I.uniform_state(mesh, 1.0, (0.3, 0.0, 0.0), 1.0 / gamma, gamma)
+    free = tuple(W[:, 0])
+    out = {"workload": f"Mach 0.3 past the unit sphere, cubed-sphere shell 6 x {n}^2 x {layers} layers "
+                       f"x 6 tets ({mesh.n_cell} cells, {mesh.n_face} faces), straight faces, slip wall, "
+                       f"Riemann-invariant far field at r = 20, Euler, CFL 0.5",
+           "cells": mesh.n_cell, "faces": mesh.n_face, "steps": steps}
+    for name, prec in (("fp64", G.GKS_FP64), ("fp32_bulk", G.GKS_FP32_BULK)):
+        s = G.Solver(mesh, G.default_config(precision=prec, farfield=free), device="cuda:0")
+        s.init(W, gW)
+        for _ in range(warmup):
+            s.step_cfl(0.5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.step_cfl(0.5)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        Wf, _ = s.read_state()
+        assert np.isfinite(Wf).all()
+        kt, _ = timed_kernels(s, steps)
+        out[name] = {"value": mesh.n_cell * 2 * steps / el, "unit": "cell-stage-updates/s",
+                     "ms_per_step": el / steps * 1e3,
+                     "kernels_ms": {k: ms / cnt for k, (ms, cnt) in kt.items() if cnt}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,6 +354,10 @@ def main():
     ap.add_argument("--cavity-n", type=int, default=32,
                     help="hexahedra per side of the lid-driven cavity leg (0 skips it)")
     ap.add_argument("--cavity-steps", type=int, default=20)
+    ap.add_argument("--sphere-n", type=int, default=32,
+                    help="cells per panel side of the sphere leg (0 skips it)")
+    ap.add_argument("--sphere-layers", type=int, default=48)
+    ap.add_argument("--sphere-steps", type=int, default=4)
     ap.add_argument("--blast-n", type=int, default=64,
                     help="hexahedra per side of the walled blast leg (0 skips it)")
     ap.add_argument("--blast-steps", type=int, default=20)
@@ -447,6 +490,8 @@ def main():
         out["adjoint"] = None
     out["blast_walls"] = blast_leg(G, I, args.blast_n, args.blast_steps, 2) if args.blast_n > 0 else None
     out["cavity_noslip"] = cavity_leg(G, I, args.cavity_n, args.cavity_steps, 2) if args.cavity_n > 0 else None
+    out["sphere_farfield"] = (sphere_leg(G, I, args.sphere_n, args.sphere_layers, args.sphere_steps, 1)
+                              if args.sphere_n > 0 else None)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, W, gW, cfg_kw, args.cpu_baseline_steps)
     else:

@@ -61,6 +61,7 @@ typedef int32_t gks_status;
 #define GKS_FACE_SLIP 2     /* inviscid wall: mirror ghost state (Sec. 4.4) */
 #define GKS_FACE_NOSLIP_ADIABATIC 3  /* no-slip wall at the face's wall velocity, no heat flux (Sec. 4.4) */
 #define GKS_FACE_NOSLIP_ISOTHERMAL 4 /* no-slip wall at the wall velocity and temperature wall_T (Sec. 4.4) */
+#define GKS_FACE_FARFIELD 5 /* far field: characteristic (Riemann-invariant) state against the free stream farfield */
 
 /* distributions of the gas-kinetic flux */
 #define GKS_FLUX_FULL 0   /* eq. 2nd-flux: equilibrium and kinetic parts, collision times tau, tau_n */
@@ -87,19 +88,21 @@ typedef struct {
                          P^0 only (eq. final_weno_expression-2nd) */
     int32_t flux;     /* GKS_FLUX_FULL (default) or GKS_FLUX_SMOOTH */
     double wall_T;    /* temperature of isothermal no-slip walls as p / rho (> 0; default 1) */
+    double farfield[5]; /* free stream of far-field faces, conservative (rho, rho u, rho v, rho w, rho E);
+                           default (1, 0, 0, 0, 2.5) */
 } gks_config;
 
 /* Fill cfg with the paper's defaults: gamma 1.4, Euler, Pr 1, eps_tau 0.01,
  * C 1, eps_weno 1e-8, weights 100:10:1 and 10:1, nonlinear, FP64, third order,
- * full flux distribution, wall_T 1. */
+ * full flux distribution, wall_T 1, far-field state (1, 0, 0, 0, 2.5). */
 void gks_default_config(gks_config *cfg);
 
 /* Tetrahedral mesh, host arrays.  face_vert lists the face's vertices as seen
  * from the owner face_cell[2f]; face_cell[2f+1] is the neighbour or -1 on a
  * wall.  face_shift[3f..3f+2] is the translation that carries the
  * neighbour's geometry into the owner's frame (periodic seams; else 0).
- * A wall face is tagged GKS_FACE_SLIP, GKS_FACE_NOSLIP_ADIABATIC or
- * GKS_FACE_NOSLIP_ISOTHERMAL; face_wall_u[3f..3f+2] is the velocity of a
+ * A boundary face is tagged GKS_FACE_SLIP, GKS_FACE_NOSLIP_ADIABATIC,
+ * GKS_FACE_NOSLIP_ISOTHERMAL or GKS_FACE_FARFIELD; face_wall_u[3f..3f+2] is the velocity of a
  * no-slip wall face (global frame; NULL: every wall at rest). */
 typedef struct {
     int64_t n_vert;
@@ -176,7 +179,8 @@ gks_status gks_last_dt(gks_ctx *ctx, double *dt);
  * positivity fallback as taken).  Asynchronous on the context's stream; it
  * leaves the context's own state untouched.  GKS_E_STATE without an adjoint
  * workspace, GKS_E_INVAL on a null pointer or a dt that is not positive and
- * finite.  No-slip walls are differentiated too: the constrained wall fits
+ * finite, or on a mesh with far-field faces (their characteristic state has no
+ * reverse here).  No-slip walls are differentiated: the constrained wall fits
  * (through the density they take their wall values from) and the reflected
  * ghost state. */
 gks_status gks_adjoint_workspace_bytes(const gks_ctx *ctx, size_t *bytes);

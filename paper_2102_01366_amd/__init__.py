@@ -62,7 +62,8 @@ class Config(ctypes.Structure):
                 ("lw2", ctypes.c_double * 3), ("lw1", ctypes.c_double * 2),
                 ("viscous", ctypes.c_int32), ("nonlinear", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("flux", ctypes.c_int32), ("wall_T", ctypes.c_double)]
+                ("flux", ctypes.c_int32), ("wall_T", ctypes.c_double),
+                ("farfield", ctypes.c_double * 5)]
 
 
 class _Mesh(ctypes.Structure):
@@ -137,7 +138,7 @@ def default_config(**kw) -> Config:
     for k, v in kw.items():
         if k not in names:
             raise TypeError(f"unknown configuration field {k!r}")
-        if k in ("lw2", "lw1"):
+        if k in ("lw2", "lw1", "farfield"):
             arr = getattr(c, k)
             for i, x in enumerate(v):
                 arr[i] = float(x)

@@ -42,7 +42,7 @@ struct gks_ctx {
     // no-slip walls: wall faces' tags and velocities (internal wall order),
     // wall cells, their modes and operators (host copies until bound)
     int nwc = 0;
-    bool noslip = false;
+    bool farfield = false;  // the mesh has far-field faces (no adjoint)
     std::vector<int> wtag, wcell, wmode;
     std::vector<double> wvel, wop;
     std::vector<double> M1, M2, geoR, geoD, fgeo, fnrm;
@@ -306,6 +306,14 @@ bool config_ok(const gks_config *c, std::string &why)
     if (c->order != 2 && c->order != 3) { why = "order must be 2 or 3"; return false; }
     if (c->flux != GKS_FLUX_FULL && c->flux != GKS_FLUX_SMOOTH) { why = "unknown flux"; return false; }
     if (!(c->wall_T > 0.0) || !std::isfinite(c->wall_T)) { why = "wall_T must be positive"; return false; }
+    {
+        const double *w = c->farfield;
+        const double r = w[0], k = r > 0.0 ? 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / r : 0.0;
+        if (!(r > 0.0) || !((c->gamma - 1.0) * (w[4] - k) > 0.0) || !std::isfinite(w[4])) {
+            why = "the far-field state must have rho > 0 and p > 0";
+            return false;
+        }
+    }
     return true;
 }
 
@@ -379,6 +387,8 @@ void gks_default_config(gks_config *cfg)
     cfg->order = 3;
     cfg->flux = GKS_FLUX_FULL;
     cfg->wall_T = 1.0;
+    cfg->farfield[0] = 1.0;
+    cfg->farfield[4] = 2.5;
 }
 
 gks_status gks_create(const gks_config *cfg, gks_ctx **out)
@@ -446,10 +456,10 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
         const int tag = m->face_tag[f];
         if (L < 0 || L >= nc || R >= nc || R == L) return fail(c, GKS_E_MESH, "bad face_cell entry");
         if (tag != GKS_FACE_INTERIOR && tag != GKS_FACE_PERIODIC && tag != GKS_FACE_SLIP &&
-            tag != GKS_FACE_NOSLIP_ADIABATIC && tag != GKS_FACE_NOSLIP_ISOTHERMAL)
+            tag != GKS_FACE_NOSLIP_ADIABATIC && tag != GKS_FACE_NOSLIP_ISOTHERMAL && tag != GKS_FACE_FARFIELD)
             return fail(c, GKS_E_MESH, "unknown face tag");
         const bool wall_tag = tag == GKS_FACE_SLIP || tag == GKS_FACE_NOSLIP_ADIABATIC ||
-                              tag == GKS_FACE_NOSLIP_ISOTHERMAL;
+                              tag == GKS_FACE_NOSLIP_ISOTHERMAL || tag == GKS_FACE_FARFIELD;
         if ((R < 0) != wall_tag)
             return fail(c, GKS_E_MESH, "a wall face needs face_cell[2f+1] = -1 and a wall tag");
         if (m->face_wall_u)
@@ -858,11 +868,11 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
     for (int f = 0; f < nf; ++f) nwall += m->face_cell[2 * (size_t)f + 1] < 0 ? 1 : 0;
     c->wtag.assign(nwall, gks::WALL_SLIP);
     c->wvel.assign(3 * (size_t)nwall, 0.0);
-    c->noslip = false;
+    c->farfield = false;
     for (int j = nf - nwall; j < nf; ++j) {
         const int f = fperm[j], k = j - (nf - nwall);
         c->wtag[k] = m->face_tag[f];
-        c->noslip = c->noslip || m->face_tag[f] != GKS_FACE_SLIP;
+        c->farfield = c->farfield || m->face_tag[f] == GKS_FACE_FARFIELD;
         for (int d = 0; d < 3; ++d)
             c->wvel[(size_t)d * nwall + k] = m->face_wall_u ? m->face_wall_u[3 * (size_t)f + d] : 0.0;
     }
@@ -1275,6 +1285,7 @@ gks_status gks_step_adjoint(gks_ctx *c, double dt, const double *W_n, const doub
     if (!W_n || !gW_n || !Wbar_np1 || !gWbar_np1 || !Wbar_n || !gWbar_n)
         return fail(c, GKS_E_INVAL, "null pointer");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, GKS_E_INVAL, "dt must be positive and finite");
+    if (c->farfield) return fail(c, GKS_E_INVAL, "the adjoint does not cover far-field faces");
     const hipStream_t s = c->stream;
     const int nc = c->nc;
     const bool f32 = c->fp32;

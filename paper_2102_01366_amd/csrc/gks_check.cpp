@@ -32,6 +32,8 @@ inline bool operator==(Dual a, Dual b) { return a.v == b.v; }
 inline bool operator!=(Dual a, Dual b) { return a.v != b.v; }
 inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
 inline bool operator>(Dual a, Dual b) { return a.v > b.v; }
+inline bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
+inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
 inline Dual exp(Dual a) { const double e = std::exp(a.v); return Dual(e, a.d * e); }
 inline Dual sqrt(Dual a) { const double s = std::sqrt(a.v); return Dual(s, a.d / (2.0 * s)); }
 // d erfc(x)/dx = -2/sqrt(pi) exp(-x^2)

@@ -602,9 +602,53 @@ GKS_HD void noslip_ghost(bool iso, R gamma, R Tw, const R uw[3], const R w[5], c
     }
 }
 
+// Far field in the face frame (normal e1, out of the domain): the locally
+// one-dimensional characteristic state against the free stream wf (face
+// frame).  Supersonic outflow: the interior state; supersonic inflow: the
+// free stream; otherwise the outgoing invariant u_n + 2a/(gamma-1) from the
+// interior, the incoming u_n - 2a/(gamma-1) from the free stream, entropy
+// p/rho^gamma and tangential velocity from the upwind side.  Zero gradients.
+template <typename R>
+GKS_HD void farfield_ghost(R gamma, const R wf[5], const R w[5], R wg[5], R gg[3][5])
+{
+    const R g1 = gamma - R(1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) gg[j][q] = R(0);
+    const R ri = w[0], rf = wf[0];
+    R Ui[3], Uf[3], ki = R(0), kf = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Ui[a] = w[1 + a] / ri;
+        Uf[a] = wf[1 + a] / rf;
+        ki += R(0.5) * Ui[a] * Ui[a];
+        kf += R(0.5) * Uf[a] * Uf[a];
+    }
+    const R pi = g1 * (w[4] - ri * ki), pf = g1 * (wf[4] - rf * kf);
+    const R ai = sqrt(gamma * pi / ri), af = sqrt(gamma * pf / rf);
+    if (Ui[0] >= ai || Ui[0] <= -ai) {
+        const R *src = Ui[0] >= ai ? w : wf;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) wg[q] = src[q];
+        return;
+    }
+    const R Rp = Ui[0] + R(2) * ai / g1, Rm = Uf[0] - R(2) * af / g1;
+    const R ub = R(0.5) * (Rp + Rm), ab = R(0.25) * g1 * (Rp - Rm);
+    const bool out = ub > R(0);
+    const R s = out ? pi / pow(ri, gamma) : pf / pow(rf, gamma);
+    const R rb = pow(ab * ab / (gamma * s), R(1) / g1), pb = rb * ab * ab / gamma;
+    const R ut1 = out ? Ui[1] : Uf[1], ut2 = out ? Ui[2] : Uf[2];
+    wg[0] = rb;
+    wg[1] = rb * ub;
+    wg[2] = rb * ut1;
+    wg[3] = rb * ut2;
+    wg[4] = pb / g1 + R(0.5) * rb * (ub * ub + ut1 * ut1 + ut2 * ut2);
+}
+
 // Boundary data of a wall face for the flux: its WallTag (2 slip, 3 no-slip
-// adiabatic, 4 no-slip isothermal) and, on a no-slip wall, its velocity in
-// the global frame.
+// adiabatic, 4 no-slip isothermal, 5 far field) and, on a no-slip wall, its
+// velocity in the global frame.
 template <typename R>
 struct WallBC {
     int tag;
@@ -631,7 +675,15 @@ GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, con
     for (int d = 0; d < 3; ++d) rr[d] = r[d] + dv[d];
     R wl[5], gl[3][5], wr[5], gr[3][5];
     eval_local(cl, r, T, wl, gl);
-    if (wall && bc && bc->tag != WALL_SLIP) {
+    if (wall && bc && bc->tag == WALL_FARFIELD) {
+        R wf[5];
+        wf[0] = R(p.farfield[0]);
+        wf[4] = R(p.farfield[4]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            wf[1 + a] = T[a][0] * R(p.farfield[1]) + T[a][1] * R(p.farfield[2]) + T[a][2] * R(p.farfield[3]);
+        farfield_ghost(R(p.gamma), wf, wl, wr, gr);
+    } else if (wall && bc && bc->tag != WALL_SLIP) {
         R uw[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) uw[a] = T[a][0] * bc->u[0] + T[a][1] * bc->u[1] + T[a][2] * bc->u[2];

@@ -1083,6 +1083,16 @@ GKS_HD void wall_ghost(const Params &p, int tag, const R T[3][3], const R u[3], 
         slip_ghost(wl, gl, wr, gr);
         return;
     }
+    if (tag == WALL_FARFIELD) {  // forward only: the adjoint rejects far-field meshes
+        R wf[5];
+        wf[0] = R(p.farfield[0]);
+        wf[4] = R(p.farfield[4]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            wf[1 + a] = T[a][0] * R(p.farfield[1]) + T[a][1] * R(p.farfield[2]) + T[a][2] * R(p.farfield[3]);
+        farfield_ghost(R(p.gamma), wf, wl, wr, gr);
+        return;
+    }
     R uw[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) uw[a] = T[a][0] * u[0] + T[a][1] * u[1] + T[a][2] * u[2];

@@ -24,6 +24,7 @@ struct Params {
     int order;  // 3 or 2
     int flux;   // FLUX_KIND_FULL or FLUX_KIND_SMOOTH
     double wall_T;  // p / rho of isothermal no-slip walls
+    double farfield[5];  // free stream of far-field faces (conservative)
 };
 
 // distribution of the flux: eq. 2nd-flux, or its smooth-flow form eq. 2nd-smooth-flux
@@ -89,7 +90,7 @@ enum WallMode {
     WM_OWN = 1,   // step 1 with fewer than three neighbours and constraints: own averaged gradient
     WM_FIT = 2    // the operators above (a fallback is an operator without K1C / K2C)
 };
-enum WallTag { WALL_SLIP = 2, WALL_ADIABATIC = 3, WALL_ISOTHERMAL = 4 };
+enum WallTag { WALL_SLIP = 2, WALL_ADIABATIC = 3, WALL_ISOTHERMAL = 4, WALL_FARFIELD = 5 };
 
 // Device view of the mesh (all pointers into the caller's workspace).
 struct DevMesh {

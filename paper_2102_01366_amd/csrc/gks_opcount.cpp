@@ -35,6 +35,9 @@ inline bool operator==(Cnt a, Cnt b) { return a.v == b.v; }
 inline bool operator!=(Cnt a, Cnt b) { return a.v != b.v; }
 inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
 inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
+inline bool operator<=(Cnt a, Cnt b) { return a.v <= b.v; }
+inline bool operator>=(Cnt a, Cnt b) { return a.v >= b.v; }
+inline Cnt pow(Cnt a, Cnt b) { ++tally.special; return Cnt(std::pow(a.v, b.v)); }
 inline Cnt exp(Cnt a) { ++tally.special; return Cnt(std::exp(a.v)); }
 inline Cnt erfc(Cnt a) { ++tally.special; return Cnt(std::erfc(a.v)); }
 inline Cnt sqrt(Cnt a) { ++tally.special; return Cnt(std::sqrt(a.v)); }

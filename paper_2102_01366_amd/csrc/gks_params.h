@@ -29,6 +29,7 @@ inline Params params_from_config(const gks_config *cfg)
     p.order = cfg->order;
     p.flux = cfg->flux;
     p.wall_T = cfg->wall_T;
+    for (int q = 0; q < 5; ++q) p.farfield[q] = cfg->farfield[q];
     return p;
 }
 

@@ -187,6 +187,118 @@ def kuhn_cube_mesh(n: int, length: float = 1.0, jitter: float = 0.1, seed: int =
                    length=float(length), n=int(n), periodic=bool(periodic))
 
 
+def _match_faces(tet: np.ndarray):
+    """All faces of the tetrahedra matched by their sorted vertex triples:
+    (face_vert as seen from the owner, face_cell with -1 for a boundary face)."""
+    local = np.array([[1, 2, 3], [0, 2, 3], [0, 1, 3], [0, 1, 2]])
+    fv = tet[:, local].reshape(-1, 3)
+    owner = np.repeat(np.arange(tet.shape[0]), 4)
+    key = np.sort(fv, axis=1)
+    _, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
+    inv = inv.ravel()
+    if cnt.max() > 2:
+        raise ValueError("a face is shared by more than two cells")
+    order = np.argsort(inv, kind="stable")
+    first = np.ones(inv.size, bool)
+    first[1:] = inv[order][1:] != inv[order][:-1]
+    own_idx = order[first]                      # first occurrence of every face
+    nbr = -np.ones(own_idx.size, np.int64)
+    second = order[~first]                      # the second occurrence, if any
+    pos = np.searchsorted(inv[own_idx], inv[second])
+    nbr[pos] = owner[second]
+    return fv[own_idx], np.stack([owner[own_idx], nbr], axis=1)
+
+
+def cubed_sphere_shell(n: int, layers: int, r_out: float = 20.0, ratio: float = 1.08) -> TetMesh:
+    """Shell 1 <= r <= r_out around the unit sphere: the cube surface cut into
+    6 panels of n x n cells (n even), mapped to the sphere equiangularly
+    (lattice point p with |p|_inf = n/2 goes to the direction tan(pi/4 p/(n/2))),
+    and `layers` radial layers whose thickness grows geometrically by `ratio`.
+    Each hexahedron is split into two prisms along the surface diagonal
+    through its smallest vertex id, each prism into three tetrahedra by the
+    minimum-vertex-id rule, so the split conforms across cells and panel
+    seams.  Faces on r = 1 are slip walls, on r = r_out far field."""
+    if n < 2 or n % 2:
+        raise ValueError("n must be even and >= 2")
+    m = n // 2
+    g = np.arange(-m, m + 1)
+    P = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    on = np.abs(P).max(axis=1) == m
+    S = P[on]                                   # the cube-surface lattice, 6 n^2 + 2 points
+    lookup = -np.ones((n + 1,) * 3, np.int64)
+    lookup[S[:, 0] + m, S[:, 1] + m, S[:, 2] + m] = np.arange(S.shape[0])
+    d = np.tan(np.pi / 4 * S / m)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    # radii: r_0 = 1, thicknesses h0 ratio^k summing to r_out - 1
+    h0 = (r_out - 1.0) * (ratio - 1.0) / (ratio ** layers - 1.0) if ratio != 1.0 else (r_out - 1.0) / layers
+    r = np.concatenate([[1.0], 1.0 + np.cumsum(h0 * ratio ** np.arange(layers))])
+    r[-1] = r_out
+    ns = S.shape[0]
+    xyz = (r[:, None, None] * d[None, :, :]).reshape(-1, 3)
+    # surface quads of the six panels, corners in cyclic order
+    quads = []
+    for axis in range(3):
+        for sign in (-1, 1):
+            u, v = [a for a in range(3) if a != axis]
+            ii, jj = np.meshgrid(np.arange(-m, m), np.arange(-m, m), indexing="ij")
+            ii, jj = ii.ravel(), jj.ravel()
+            corners = []
+            for du, dv in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                q = np.zeros((ii.size, 3), np.int64)
+                q[:, axis] = sign * m
+                q[:, u] = ii + du
+                q[:, v] = jj + dv
+                corners.append(lookup[q[:, 0] + m, q[:, 1] + m, q[:, 2] + m])
+            quads.append(np.stack(corners, axis=1))
+    quads = np.concatenate(quads)               # [6 n^2, 4]
+    # two triangles per quad along the diagonal through its smallest id
+    k0 = np.argmin(quads, axis=1)
+    rot = np.stack([quads[np.arange(quads.shape[0]), (k0 + t) % 4] for t in range(4)], axis=1)
+    tris = np.concatenate([rot[:, [0, 1, 2]], rot[:, [0, 2, 3]]])
+    # prisms of every layer: bottom (a, b, c) at layer k, top at k + 1
+    kk = np.arange(layers)
+    bot = (tris[None, :, :] + (kk * ns)[:, None, None]).reshape(-1, 3)
+    pr = np.concatenate([bot, bot + ns], axis=1)  # [n_prism, 6]: (a, b, c, a', b', c')
+    # minimum-vertex-id rule: bring the smallest id to position 0 (reflecting
+    # top and bottom if it is on top, then rotating), split the quad opposite it
+    imin = np.argmin(pr, axis=1)
+    top = imin >= 3
+    pr = np.where(top[:, None], pr[:, [3, 4, 5, 0, 1, 2]], pr)
+    i0 = imin % 3
+    idx = np.stack([(i0 + t) % 3 for t in range(3)], axis=1)
+    ar = np.arange(pr.shape[0])[:, None]
+    pr = np.concatenate([pr[ar, idx], pr[ar, idx + 3]], axis=1)
+    v0, v1, v2, v3, v4, v5 = pr.T
+    diag15 = np.minimum(v1, v5) < np.minimum(v2, v4)
+    t1 = np.where(diag15[:, None], np.stack([v0, v1, v2, v5], 1), np.stack([v0, v1, v2, v4], 1))
+    t2 = np.where(diag15[:, None], np.stack([v0, v1, v5, v4], 1), np.stack([v0, v4, v2, v5], 1))
+    t3 = np.stack([v0, v4, v5, v3], 1)
+    tet = np.concatenate([t1, t2, t3])
+    # positive orientation
+    e = xyz[tet[:, 1:]] - xyz[tet[:, :1]]
+    neg = np.linalg.det(e) < 0
+    tet[neg] = tet[neg][:, [0, 2, 1, 3]]
+    face_vert, face_cell = _match_faces(tet)
+    wall = face_cell[:, 1] < 0
+    rad = np.linalg.norm(xyz[face_vert].mean(axis=1), axis=1)
+    tag = np.where(wall, np.where(rad < 0.5 * (1.0 + r_out), FACE_SLIP, FACE_FARFIELD), FACE_INTERIOR)
+    fo = np.lexsort((face_cell[:, 1], face_cell[:, 0]))
+    return TetMesh(xyz=np.ascontiguousarray(xyz), tet=np.ascontiguousarray(tet),
+                   face_vert=np.ascontiguousarray(face_vert[fo]), face_cell=np.ascontiguousarray(face_cell[fo]),
+                   face_tag=np.ascontiguousarray(tag[fo].astype(np.int32)),
+                   face_shift=np.zeros((face_vert.shape[0], 3)), length=float(r_out), n=int(n), periodic=False)
+
+
+def uniform_state(mesh: TetMesh, rho: float, U, p: float, gamma: float = 1.4):
+    """A uniform state (W, grad W = 0)."""
+    U = np.asarray(U, np.float64)
+    W = np.empty((5, mesh.n_cell))
+    W[0] = rho
+    W[1:4] = rho * U[:, None]
+    W[4] = p / (gamma - 1.0) + 0.5 * rho * (U @ U)
+    return W, np.zeros((15, mesh.n_cell))
+
+
 def with_walls(mesh: TetMesh, tags: dict, velocity: dict | None = None) -> TetMesh:
     """The walled cube mesh with its six sides retagged: ``tags`` maps a side
     name ("x0", "x1", "y0", "y1", "z0", "z1": the plane x = 0, x = length,

@@ -169,6 +169,23 @@ def test_noslip_walls_accepted(lib):
     assert _upload(lib, m2, wall_u=wu, face_tag=m2.face_tag)[0] == G.GKS_E_MESH
 
 
+def test_far_field_state_checked(lib):
+    cfg = G.default_config()
+    cfg.farfield[0] = 0.0
+    assert _create(lib, cfg)[0] == G.GKS_E_INVAL
+    cfg = G.default_config()
+    cfg.farfield[4] = 0.1  # p < 0 with the momentum below
+    cfg.farfield[1] = 1.0
+    assert _create(lib, cfg)[0] == G.GKS_E_INVAL
+
+
+def test_sphere_shell_with_far_field_accepted(lib):
+    m = I.cubed_sphere_shell(4, 3, r_out=3.0, ratio=1.2)
+    st, st2, nbytes, msg, _, _ = _upload(lib, m)
+    assert st == 0 and st2 == 0, msg
+    assert set(np.unique(m.face_tag)) == {I.FACE_INTERIOR, I.FACE_SLIP, I.FACE_FARFIELD}
+
+
 def test_empty_mesh_rejected(lib):
     st, h = _create(lib, G.default_config())
     m = G._Mesh(0, None, 0, None, 0, None, None, None, None)
