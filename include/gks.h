@@ -179,10 +179,10 @@ gks_status gks_last_dt(gks_ctx *ctx, double *dt);
  * positivity fallback as taken).  Asynchronous on the context's stream; it
  * leaves the context's own state untouched.  GKS_E_STATE without an adjoint
  * workspace, GKS_E_INVAL on a null pointer or a dt that is not positive and
- * finite, or on a mesh with far-field faces (their characteristic state has no
- * reverse here).  No-slip walls are differentiated: the constrained wall fits
- * (through the density they take their wall values from) and the reflected
- * ghost state. */
+ * finite.  Every boundary kind is differentiated: the slip mirror, the
+ * no-slip walls (the constrained wall fits, through the density they take
+ * their wall values from, and the reflected ghost state) and the far-field
+ * state (its branch as taken, the free stream held constant). */
 gks_status gks_adjoint_workspace_bytes(const gks_ctx *ctx, size_t *bytes);
 gks_status gks_bind_adjoint_workspace(gks_ctx *ctx, void *device_ptr, size_t bytes);
 gks_status gks_step_adjoint(gks_ctx *ctx, double dt, const double *W_n, const double *gW_n,
@@ -264,11 +264,12 @@ gks_status gks_flux_face_check(const gks_config *cfg, double dt, const double ge
 gks_status gks_weno_check(const gks_config *cfg, const double geo[8], int32_t has_mask, const double x[25],
                           const double v[25], const double rbar[10], double r[10], double jv[10],
                           double xbar[25]);
-/* The same check for the no-slip ghost state of a wall point (Sec. 4.4), in
- * the face frame: tag GKS_FACE_NOSLIP_ADIABATIC or _ISOTHERMAL, uw the wall
- * velocity (face frame); x[20] = (interior W[5], its derivatives along the
- * three axes [3][5]); y[20] the ghost in the same layout.  Outputs y, jv = J v,
- * xbar = J^T ybar.  GKS_E_INVAL for another tag. */
+/* The same check for the ghost state of a boundary point, in the face frame
+ * (normal e1): tag GKS_FACE_NOSLIP_ADIABATIC or _ISOTHERMAL (Sec. 4.4; uw the
+ * wall velocity, face frame) or GKS_FACE_FARFIELD (the free stream cfg->farfield,
+ * taken as given in the face frame); x[20] = (interior W[5], its derivatives
+ * along the three axes [3][5]); y[20] the ghost in the same layout.  Outputs
+ * y, jv = J v, xbar = J^T ybar.  GKS_E_INVAL for another tag. */
 gks_status gks_wall_ghost_check(const gks_config *cfg, int32_t tag, const double uw[3], const double x[20],
                                 const double v[20], const double ybar[20], double y[20], double jv[20],
                                 double xbar[20]);

@@ -1285,7 +1285,6 @@ gks_status gks_step_adjoint(gks_ctx *c, double dt, const double *W_n, const doub
     if (!W_n || !gW_n || !Wbar_np1 || !gWbar_np1 || !Wbar_n || !gWbar_n)
         return fail(c, GKS_E_INVAL, "null pointer");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, GKS_E_INVAL, "dt must be positive and finite");
-    if (c->farfield) return fail(c, GKS_E_INVAL, "the adjoint does not cover far-field faces");
     const hipStream_t s = c->stream;
     const int nc = c->nc;
     const bool f32 = c->fp32;

@@ -193,16 +193,21 @@ extern "C" gks_status gks_wall_ghost_check(const gks_config *cfg, int32_t tag, c
                                            double y[20], double jv[20], double xbar[20])
 {
     if (!cfg || !uw || !x || !v || !ybar || !y || !jv || !xbar) return GKS_E_INVAL;
-    if (tag != GKS_FACE_NOSLIP_ADIABATIC && tag != GKS_FACE_NOSLIP_ISOTHERMAL) return GKS_E_INVAL;
+    if (tag != GKS_FACE_NOSLIP_ADIABATIC && tag != GKS_FACE_NOSLIP_ISOTHERMAL && tag != GKS_FACE_FARFIELD)
+        return GKS_E_INVAL;
     const gks::Params p = gks::params_from_config(cfg);
-    const bool iso = tag == GKS_FACE_NOSLIP_ISOTHERMAL;
-    Dual w[5], g[3][5], wg[5], gg[3][5], u[3];
+    const bool iso = tag == GKS_FACE_NOSLIP_ISOTHERMAL, far = tag == GKS_FACE_FARFIELD;
+    Dual w[5], g[3][5], wg[5], gg[3][5], u[3], wf[5];
     for (int q = 0; q < 5; ++q) {
         w[q] = Dual(x[q], v[q]);
+        wf[q] = Dual(p.farfield[q]);
         for (int j = 0; j < 3; ++j) g[j][q] = Dual(x[5 + 5 * j + q], v[5 + 5 * j + q]);
     }
     for (int a = 0; a < 3; ++a) u[a] = Dual(uw[a]);
-    gks::noslip_ghost<Dual>(iso, Dual(p.gamma), Dual(p.wall_T), u, w, g, wg, gg);
+    if (far)
+        gks::farfield_ghost<Dual>(Dual(p.gamma), wf, w, wg, gg);
+    else
+        gks::noslip_ghost<Dual>(iso, Dual(p.gamma), Dual(p.wall_T), u, w, g, wg, gg);
     for (int q = 0; q < 5; ++q) {
         y[q] = wg[q].v;
         jv[q] = wg[q].d;
@@ -220,7 +225,10 @@ extern "C" gks_status gks_wall_ghost_check(const gks_config *cfg, int32_t tag, c
             ggb[j][q] = ybar[5 + 5 * j + q];
         }
     }
-    gks::noslip_ghost_rev<double>(iso, p.gamma, p.wall_T, uw, wd, gd, wgb, ggb, wb, gbb);
+    if (far)
+        gks::farfield_ghost_rev<double>(p.gamma, p.farfield, wd, wgb, wb);
+    else
+        gks::noslip_ghost_rev<double>(iso, p.gamma, p.wall_T, uw, wd, gd, wgb, ggb, wb, gbb);
     for (int q = 0; q < 5; ++q) {
         xbar[q] = wb[q];
         for (int j = 0; j < 3; ++j) xbar[5 + 5 * j + q] = gbb[j][q];

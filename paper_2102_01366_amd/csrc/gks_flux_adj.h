@@ -1073,8 +1073,79 @@ GKS_HD void noslip_ghost_rev(bool iso, R gamma, R Tw, const R uw[3], const R w[5
     wb[0] += rhob;
 }
 
+// Reverse of farfield_ghost (gks_flux.h): adds to wb the adjoint of the
+// interior point state (the ghost has no gradients, so gb gets nothing).
+// Differentiated as implemented: the branch taken, the free stream constant.
+template <typename R>
+GKS_HD void farfield_ghost_rev(R gamma, const R wf[5], const R w[5], const R wgb[5], R wb[5])
+{
+    const R g1 = gamma - R(1);
+    const R ri = w[0], rf = wf[0];
+    R Ui[3], Uf[3], ki = R(0), kf = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Ui[a] = w[1 + a] / ri;
+        Uf[a] = wf[1 + a] / rf;
+        ki += R(0.5) * Ui[a] * Ui[a];
+        kf += R(0.5) * Uf[a] * Uf[a];
+    }
+    const R pi = g1 * (w[4] - ri * ki), pf = g1 * (wf[4] - rf * kf);
+    const R ai = sqrt(gamma * pi / ri), af = sqrt(gamma * pf / rf);
+    if (Ui[0] >= ai) {  // supersonic outflow: the ghost is the interior state
+#pragma unroll
+        for (int q = 0; q < 5; ++q) wb[q] += wgb[q];
+        return;
+    }
+    if (Ui[0] <= -ai) return;  // supersonic inflow: the free stream
+    const R Rp = Ui[0] + R(2) * ai / g1, Rm = Uf[0] - R(2) * af / g1;
+    const R ub = R(0.5) * (Rp + Rm), ab = R(0.25) * g1 * (Rp - Rm);
+    const bool out = ub > R(0);
+    const R s = out ? pi / pow(ri, gamma) : pf / pow(rf, gamma);
+    const R X = ab * ab / (gamma * s);
+    const R rb = pow(X, R(1) / g1), pb = rb * ab * ab / gamma;
+    const R ut1 = out ? Ui[1] : Uf[1], ut2 = out ? Ui[2] : Uf[2];
+    // wg = (rb, rb ub, rb ut1, rb ut2, pb/g1 + rb (ub^2 + ut1^2 + ut2^2)/2)
+    const R k2 = R(0.5) * (ub * ub + ut1 * ut1 + ut2 * ut2);
+    R rbb = wgb[0] + wgb[1] * ub + wgb[2] * ut1 + wgb[3] * ut2 + wgb[4] * k2;
+    R ubb = wgb[1] * rb + wgb[4] * rb * ub;
+    const R ut1b = wgb[2] * rb + wgb[4] * rb * ut1, ut2b = wgb[3] * rb + wgb[4] * rb * ut2;
+    const R pbb = wgb[4] / g1;
+    // pb = rb ab^2 / gamma, rb = X^(1/g1), X = ab^2 / (gamma s)
+    rbb += pbb * ab * ab / gamma;
+    R abb = pbb * R(2) * rb * ab / gamma;
+    const R Xb = rbb * rb / (g1 * X);
+    abb += Xb * R(2) * ab / (gamma * s);
+    const R sb = -Xb * X / s;
+    // ab = g1 (Rp - Rm) / 4, ub = (Rp + Rm) / 2; Rm is the free stream's
+    const R Rpb = R(0.25) * g1 * abb + R(0.5) * ubb;
+    R Uib[3] = {Rpb, R(0), R(0)};
+    R aib = R(2) * Rpb / g1, pib = R(0), rib = R(0);
+    if (out) {
+        // s = pi ri^-gamma, ut = Ui[1], Ui[2]
+        const R rg = pow(ri, gamma);
+        pib += sb / rg;
+        rib -= gamma * sb * s / ri;
+        Uib[1] += ut1b;
+        Uib[2] += ut2b;
+    }
+    // ai = sqrt(gamma pi / ri)
+    pib += aib * gamma / (R(2) * ai * ri);
+    rib -= aib * ai / (R(2) * ri);
+    // pi = g1 (w4 - ri ki), ki = |Ui|^2 / 2, Ui = w[1+a] / ri
+    wb[4] += g1 * pib;
+    rib -= g1 * pib * ki;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Uib[a] -= g1 * pib * ri * Ui[a];
+        wb[1 + a] += Uib[a] / ri;
+        rib -= Uib[a] * Ui[a] / ri;
+    }
+    wb[0] += rib;
+}
+
 // The wall ghost of a point and its reverse, as the flux uses them: the
-// slip mirror (its own transpose) or the no-slip reflection.
+// slip mirror (its own transpose), the far-field state or the no-slip
+// reflection.
 template <typename R>
 GKS_HD void wall_ghost(const Params &p, int tag, const R T[3][3], const R u[3], const R wl[5], const R gl[3][5],
                        R wr[5], R gr[3][5])
@@ -1083,7 +1154,7 @@ GKS_HD void wall_ghost(const Params &p, int tag, const R T[3][3], const R u[3], 
         slip_ghost(wl, gl, wr, gr);
         return;
     }
-    if (tag == WALL_FARFIELD) {  // forward only: the adjoint rejects far-field meshes
+    if (tag == WALL_FARFIELD) {
         R wf[5];
         wf[0] = R(p.farfield[0]);
         wf[4] = R(p.farfield[4]);
@@ -1113,6 +1184,16 @@ GKS_HD void wall_ghost_rev(const Params &p, int tag, const R T[3][3], const R u[
 #pragma unroll
             for (int d = 0; d < 3; ++d) glb[d][q] += gg[d][q];
         }
+        return;
+    }
+    if (tag == WALL_FARFIELD) {
+        R wf[5];
+        wf[0] = R(p.farfield[0]);
+        wf[4] = R(p.farfield[4]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            wf[1 + a] = T[a][0] * R(p.farfield[1]) + T[a][1] * R(p.farfield[2]) + T[a][2] * R(p.farfield[3]);
+        farfield_ghost_rev(R(p.gamma), wf, wl, wrb, wlb);
         return;
     }
     R uw[3];

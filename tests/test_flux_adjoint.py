@@ -163,3 +163,44 @@ def test_noslip_ghost_matches_oracle(oracle_lib):
             Wg, gWg = oracle_lib.wall_ghost(ocfg, tag, np.array([1.0, 0, 0]), uw, w, g.T.reshape(15))
             np.testing.assert_allclose(y[:5], Wg, rtol=1e-14, atol=1e-15)
             np.testing.assert_allclose(y[5:].reshape(3, 5), gWg.reshape(5, 3).T, rtol=1e-12, atol=1e-13)
+
+
+def _far_states(rng):
+    """Interior states about the free stream (1, 0.3, 0, 0, p = 1/1.4):
+    subsonic in- and outflow along e1, and supersonic both ways."""
+    out = []
+    for un in (0.3, -0.4, 1.6, -1.7):
+        rho = rng.uniform(0.9, 1.1)
+        U = np.array([un, rng.uniform(-0.2, 0.2), rng.uniform(-0.2, 0.2)])
+        p = rng.uniform(0.6, 0.8)
+        out.append(np.array([rho, *(rho * U), p / 0.4 + 0.5 * rho * U @ U]))
+    return out
+
+
+def test_far_field_ghost_reverse_is_the_transpose():
+    rng = np.random.default_rng(18)
+    free = (1.0, 0.3, 0.0, 0.0, (1 / 1.4) / 0.4 + 0.045)
+    cfg = G.default_config(farfield=free)
+    for _ in range(5):
+        for w in _far_states(rng):
+            x = np.concatenate([w, 0.3 * rng.standard_normal(15)])
+            v, yb = rng.standard_normal(20), rng.standard_normal(20)
+            y, jv, xb = G.wall_ghost_check(cfg, 5, np.zeros(3), x, v, yb)
+            a, b = jv @ yb, v @ xb
+            assert abs(a - b) <= 1e-12 * max(abs(a), abs(b), 1e-300)
+            h = 1e-6
+            yp = G.wall_ghost_check(cfg, 5, np.zeros(3), x + h * v, v, yb)[0]
+            ym = G.wall_ghost_check(cfg, 5, np.zeros(3), x - h * v, v, yb)[0]
+            assert np.abs((yp - ym) / (2 * h) - jv).max() <= 1e-7 * max(np.abs(jv).max(), 1e-12)
+
+
+def test_far_field_ghost_matches_oracle(oracle_lib):
+    rng = np.random.default_rng(19)
+    free = (1.0, 0.3, 0.0, 0.0, (1 / 1.4) / 0.4 + 0.045)
+    cfg = G.default_config(farfield=free)
+    ocfg = oracle_lib.make_config(farfield=free)
+    for w in _far_states(rng):
+        y = G.wall_ghost_check(cfg, 5, np.zeros(3), np.concatenate([w, np.zeros(15)]), np.zeros(20), np.zeros(20))[0]
+        Wg, gWg = oracle_lib.wall_ghost(ocfg, 5, np.array([1.0, 0, 0]), np.zeros(3), w, np.zeros(15))
+        np.testing.assert_allclose(y[:5], Wg, rtol=1e-13, atol=1e-15)
+        assert np.all(y[5:] == 0.0) and np.all(gWg == 0.0)
