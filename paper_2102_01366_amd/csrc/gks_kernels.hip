@@ -76,21 +76,44 @@ __global__ __launch_bounds__(kBlock) void slopes_kernel(DevMesh m, DevState s)
 template <typename R>
 __device__ __forceinline__ R pow43(R x) { return pow(x, R(4.0 / 3.0)); }
 
+// step-1 slopes of component q of cell i (b) and of its four neighbours (sn),
+// a missing neighbour read from the cell itself (its entries are not used)
+template <typename R>
+__device__ __forceinline__ void load_slopes(const R *slopes, int n, int q, int i, const int nb[4], R b[3],
+                                            R sn[4][3])
+{
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) b[dd] = slopes[(size_t)(3 * q + dd) * n + i];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int j = nb[a] >= 0 ? nb[a] : i;
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) sn[a][dd] = slopes[(size_t)(3 * q + dd) * n + j];
+    }
+}
+
 // One block reconstructs one tile of kRecCells cells with one wavefront per
 // conservative component: thread (q, l) fits component q of cell l, so each
 // thread holds a single component's stencil and coefficients.  The tile's
 // operators M2 are streamed once through LDS in kM2Chunk-row chunks shared by
-// the five wavefronts (the next chunk is prefetched into registers while the
-// current one is used).  The coefficients then meet in LDS for the cell-wide
-// positivity check: wavefront a evaluates the three Gauss points of the face
-// opposite vertex a, wavefront 4 checks the cell average.
+// the five wavefronts, ahead in registers.  Loads are issued as early as
+// their addresses are known, so that a block waits on few round trips to
+// memory: the first chunks and the tile's 20 geometry rows (staged once in
+// LDS for all five wavefronts) at entry, the neighbour gathers next.  The
+// coefficients then meet in LDS for the cell-wide positivity check: wavefront
+// a evaluates the three Gauss points of the face opposite vertex a, wavefront
+// 4 checks the cell average.
+// at most 128 VGPRs: four wavefronts per SIMD, three blocks per CU
 template <typename R>
-__global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, DevState s, Params p)
+__global__ __launch_bounds__(kRecThreads, 4) void reconstruct_kernel(DevMesh m, DevState s, Params p)
 {
     // the operator chunks and, after the fit, the coefficients share one buffer
     constexpr int kBuf = 5 * 10 * kRecCells > kM2Chunk * kRecCells ? 5 * 10 * kRecCells
                                                                    : kM2Chunk * kRecCells;
+    constexpr int kGeoRows = G_RV + 12;  // |Omega|^(2/3), |Omega|^(4/3), C, vertex offsets
+    constexpr int kGeoPer = (kGeoRows * kRecCells + kRecThreads - 1) / kRecThreads;
     __shared__ __align__(16) R sBuf[kBuf];
+    __shared__ R sGeo[kGeoRows][kRecCells];
     __shared__ double sQ0[5][kRecCells];
     __shared__ int sBad[5][kRecCells];
     R (*sR)[10][kRecCells] = reinterpret_cast<R (*)[10][kRecCells]>(sBuf);
@@ -106,8 +129,21 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
     R *coef = static_cast<R *>(s.coef);
     const R eps = R(p.eps_weno), g22 = R(p.g22), g12 = R(p.g12), g02 = R(p.g02), g11 = R(p.g11);
 
-    M2Chunk<R> pre;
-    pre.load(tile, 0);
+    // FP64: chunk t of the operators lives in slot t & 1 (two chunks ahead)
+    // and the step-1 slopes load with the second chunk; FP32 keeps one
+    // chunk ahead and loads them after the fit, where the registers saved
+    // hold more blocks per CU than the earlier loads would gain
+    constexpr bool kAhead = sizeof(R) == 8 && kM2Chunks > 1;
+    M2Chunk<R> slot[kAhead ? 2 : 1];
+    slot[0].load(tile, 0);
+    if constexpr (kAhead) slot[1].load(tile, 1);
+    // the tile's geometry rows, spread over the block (row-major, coalesced)
+    R gv[kGeoPer];
+#pragma unroll
+    for (int j = 0; j < kGeoPer; ++j) {
+        const int e = threadIdx.x + j * kRecThreads, row = e / kRecCells, cell = tb * kRecCells + e % kRecCells;
+        gv[j] = (e < kGeoRows * kRecCells && cell < n) ? geo[(size_t)row * n + cell] : R(0);
+    }
 
     int nb[4] = {-1, -1, -1, -1};
     double Q0 = 0.0;
@@ -151,12 +187,30 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
         }
     }
     R c[9];
+    // step-1 slopes: the cell's (beta_1, the P^1 part of R), the neighbours' (beta_0)
+    R b[3] = {R(0), R(0), R(0)}, sn[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) sn[a][dd] = R(0);
 #pragma unroll
     for (int t = 0; t < kM2Chunks; ++t) {
         if (t > 0) __syncthreads();  // the previous chunk has been used
-        pre.store(sBuf);
+        slot[kAhead ? t & 1 : 0].store(sBuf);
+        if (t == 0) {
+#pragma unroll
+            for (int j = 0; j < kGeoPer; ++j) {
+                const int e = threadIdx.x + j * kRecThreads;
+                if (e < kGeoRows * kRecCells) sGeo[e / kRecCells][e % kRecCells] = gv[j];
+            }
+        }
         __syncthreads();
-        if (t + 1 < kM2Chunks) pre.load(tile, t + 1);
+        if constexpr (kAhead) {
+            if (t + 2 < kM2Chunks) slot[t & 1].load(tile, t + 2);
+            if (t == 1 && live && p.nonlinear) load_slopes(slopes, n, q, i, nb, b, sn);
+        } else {
+            if (t + 1 < kM2Chunks) slot[0].load(tile, t + 1);
+        }
 #pragma unroll
         for (int rr = 0; rr < kM2Chunk / 16; ++rr) {
             R acc = R(0);
@@ -169,13 +223,16 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
         }
     }
     __syncthreads();  // sBuf now holds the coefficients
+    if constexpr (!kAhead) {
+        if (live && p.nonlinear) load_slopes(slopes, n, q, i, nb, b, sn);
+    }
 
     if (live) {
-        const R vol23 = geo[(size_t)G_VOL23 * n + i];
-        const R vol43 = geo[(size_t)G_VOL43 * n + i];
+        const R vol23 = sGeo[G_VOL23][l];
+        const R vol43 = sGeo[G_VOL43][l];
         R C[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) C[k] = geo[(size_t)(G_C + k) * n + i];
+        for (int k = 0; k < 6; ++k) C[k] = sGeo[G_C + k][l];
         // P^2 about the centroid: its value at the centroid, c0 = Q0 + corr,
         // keeps the mean
         const R corr = -(R(0.5) * (c[3] * C[0] + c[4] * C[1] + c[5] * C[2]) +
@@ -186,9 +243,6 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
 #pragma unroll
             for (int k = 0; k < 9; ++k) Rq[1 + k] = c[k];
         } else {
-            R b[3];
-#pragma unroll
-            for (int dd = 0; dd < 3; ++dd) b[dd] = slopes[(size_t)(3 * q + dd) * n + i];
             // beta_1 = |Omega|^(2/3) |b|^2
             const R beta1 = vol23 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
             // beta_2 = |Omega|^(2/3) (|g|^2 + tr(H C H)) + |Omega|^(4/3) sum of the six H^2
@@ -218,10 +272,7 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
                 R ss = R(0);
                 if (hv[a]) {
 #pragma unroll
-                    for (int dd = 0; dd < 3; ++dd) {
-                        const R v = slopes[(size_t)(3 * q + dd) * n + nb[a]];
-                        ss += v * v;
-                    }
+                    for (int dd = 0; dd < 3; ++dd) ss += sn[a][dd] * sn[a][dd];
                 }
                 b0[a] = vol23 * ss;
             }
@@ -283,7 +334,7 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(DevMesh m, Dev
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int dd = 0; dd < 3; ++dd) rv[a][dd] = geo[(size_t)(G_RV + 3 * a + dd) * n + i];
+                for (int dd = 0; dd < 3; ++dd) rv[a][dd] = sGeo[G_RV + 3 * a + dd][l];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (k == q) continue;
