@@ -22,8 +22,14 @@ struct DevCoef {
 
 // Three lanes per face, one per Gauss point: 21 faces per wavefront (lane 63
 // idle).  The lanes of a face are summed in Gauss-point order by shuffles and
-// the first lane writes the face.
-constexpr int kFluxThreads = 256;
+// the first lane writes the face.  The kernel holds one wavefront per SIMD
+// (its registers), so a block is one wavefront: each SIMD takes the next
+// block as soon as its own wavefront ends, instead of waiting for the
+// slowest wavefront of a wider block.
+#ifndef GKS_FLUX_THREADS
+#define GKS_FLUX_THREADS 64
+#endif
+constexpr int kFluxThreads = GKS_FLUX_THREADS;
 #ifndef GKS_FLUX_MIN_WAVES
 #define GKS_FLUX_MIN_WAVES 1
 #endif

@@ -28,7 +28,16 @@ struct CoefView {
 //            W(0) of stage 1 + (W(dt) - W(0)) of stage 2;
 //   stage 1: W* = W^n + dt/2 L^n + dt^2/8 L_t^n, grad W* from (W(0) + W(dt))/2.
 // ===========================================================================
-constexpr int kFluxThreadsA = 256;
+// One wavefront per block, as in the forward flux kernel: these kernels hold
+// one or two wavefronts per SIMD, and a SIMD then takes the next block as
+// soon as its own wavefront ends.  Per wavefront: 21 faces x 3 Gauss points
+// (eq, common), 10 faces x 3 Gauss points x 2 sides (side).
+#ifndef GKS_FLUX_THREADS_ADJ
+#define GKS_FLUX_THREADS_ADJ 64
+#endif
+constexpr int kFluxThreadsA = GKS_FLUX_THREADS_ADJ;
+constexpr int kWavesA = kFluxThreadsA / 64;
+constexpr int kFaces3A = 21 * kWavesA, kFaces6A = 10 * kWavesA;
 
 // Per Gauss point k of face f: the face frame, both sides' point states in it
 // (the slip ghost on a wall face) and the offsets of the polynomial
@@ -131,7 +140,7 @@ __global__ __launch_bounds__(kFluxThreadsA) void flux_vjp_eq_kernel(DevMesh m, A
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane / 3, k = lane - 3 * slot;
     const int f0 = WALL ? m.nfi : 0, f1 = WALL ? m.nf : m.nfi;
-    const int f = f0 + xcd_block() * 84 + wave * 21 + slot;
+    const int f = f0 + xcd_block() * kFaces3A + wave * 21 + slot;
     if (slot >= 21 || f >= f1) return;
     R T[3][3], wl[5], gl[3][5], wr[5], gr[3][5], off[2][3], Fob[2][5], Wob[2][5];
     gp_setup<R, MODE, WALL, true>(m, a, p, f, k, dt_, T, wl, gl, wr, gr, off, Fob, Wob);
@@ -169,7 +178,7 @@ __global__ __launch_bounds__(kFluxThreadsA) void flux_vjp_side_kernel(DevMesh m,
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane / 6, k = (lane - 6 * slot) >> 1, side = lane & 1;
     const int f0 = WALL ? m.nfi : 0, f1 = WALL ? m.nf : m.nfi;
-    const int f = f0 + xcd_block() * 40 + wave * 10 + slot;
+    const int f = f0 + xcd_block() * kFaces6A + wave * 10 + slot;
     if (slot >= 10 || f >= f1) return;
     R T[3][3], wl[5], gl[3][5], wr[5], gr[3][5], off[2][3], Fob[2][5], Wob[2][5];
     gp_setup<R, MODE, WALL, true>(m, a, p, f, k, dt_, T, wl, gl, wr, gr, off, Fob, Wob);
@@ -244,7 +253,7 @@ __global__ __launch_bounds__(kFluxThreadsA) void flux_vjp_common_kernel(DevMesh 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane / 3, k = lane - 3 * slot;
     const int f0 = WALL ? m.nfi : 0, f1 = WALL ? nf : m.nfi;
-    const int f = f0 + xcd_block() * 84 + wave * 21 + slot;
+    const int f = f0 + xcd_block() * kFaces3A + wave * 21 + slot;
     const bool live = slot < 21 && f < f1;
     R Wb[2][5], Gb[2][5][3], off[2][3];
 #pragma unroll
@@ -325,7 +334,7 @@ void launch_flux_vjp_parts(const DevMesh &m, const AdjFlux &a, const Params &p, 
     const int nfaces = WALL ? m.nf - m.nfi : m.nfi;
     if (nfaces <= 0) return;
     const dim3 block(kFluxThreadsA);
-    const dim3 g3((unsigned)((nfaces + 83) / 84)), g6((unsigned)((nfaces + 39) / 40));
+    const dim3 g3((unsigned)((nfaces + kFaces3A - 1) / kFaces3A)), g6((unsigned)((nfaces + kFaces6A - 1) / kFaces6A));
     hipLaunchKernelGGL((flux_vjp_eq_kernel<R, MODE, VISC, PRFIX, WALL, SMOOTH>), g3, block, 0, st, m, a, p, dt);
     hipLaunchKernelGGL((flux_vjp_side_kernel<R, MODE, VISC, PRFIX, WALL, SMOOTH>), g6, block, 0, st, m, a, p, dt);
     hipLaunchKernelGGL((flux_vjp_common_kernel<R, MODE, VISC, PRFIX, WALL, SMOOTH>), g3, block, 0, st, m, a, p, dt);
