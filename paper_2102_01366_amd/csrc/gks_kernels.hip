@@ -96,16 +96,19 @@ __device__ __forceinline__ void load_slopes(const R *slopes, int n, int q, int i
 // conservative component: thread (q, l) fits component q of cell l, so each
 // thread holds a single component's stencil and coefficients.  The tile's
 // operators M2 are streamed once through LDS in kM2Chunk-row chunks shared by
-// the five wavefronts, ahead in registers.  Loads are issued as early as
-// their addresses are known, so that a block waits on few round trips to
-// memory: the first chunks and the tile's 20 geometry rows (staged once in
-// LDS for all five wavefronts) at entry, the neighbour gathers next.  The
+// the five wavefronts, the next chunk prefetched into registers while the
+// current one is used.  The tile's 20 geometry rows are loaded with the first
+// chunk and staged once in LDS for all five wavefronts.  The
 // coefficients then meet in LDS for the cell-wide positivity check: wavefront
 // a evaluates the three Gauss points of the face opposite vertex a, wavefront
 // 4 checks the cell average.
-// at most 128 VGPRs: four wavefronts per SIMD, three blocks per CU
+// at most 96 VGPRs (FP64): five wavefronts per SIMD, four blocks per CU,
+// which the 39.7 KB of LDS per block still allows
+#ifndef GKS_REC_MIN_WAVES
+#define GKS_REC_MIN_WAVES 5
+#endif
 template <typename R>
-__global__ __launch_bounds__(kRecThreads, 4) void reconstruct_kernel(DevMesh m, DevState s, Params p)
+__global__ __launch_bounds__(kRecThreads, GKS_REC_MIN_WAVES) void reconstruct_kernel(DevMesh m, DevState s, Params p)
 {
     // the operator chunks and, after the fit, the coefficients share one buffer
     constexpr int kBuf = 5 * 10 * kRecCells > kM2Chunk * kRecCells ? 5 * 10 * kRecCells
@@ -129,14 +132,10 @@ __global__ __launch_bounds__(kRecThreads, 4) void reconstruct_kernel(DevMesh m, 
     R *coef = static_cast<R *>(s.coef);
     const R eps = R(p.eps_weno), g22 = R(p.g22), g12 = R(p.g12), g02 = R(p.g02), g11 = R(p.g11);
 
-    // FP64: chunk t of the operators lives in slot t & 1 (two chunks ahead)
-    // and the step-1 slopes load with the second chunk; FP32 keeps one
-    // chunk ahead and loads them after the fit, where the registers saved
-    // hold more blocks per CU than the earlier loads would gain
-    constexpr bool kAhead = sizeof(R) == 8 && kM2Chunks > 1;
-    M2Chunk<R> slot[kAhead ? 2 : 1];
-    slot[0].load(tile, 0);
-    if constexpr (kAhead) slot[1].load(tile, 1);
+    // one operator chunk ahead in registers (two would cost the fifth
+    // wavefront per SIMD, which hides more)
+    M2Chunk<R> pre;
+    pre.load(tile, 0);
     // the tile's geometry rows, spread over the block (row-major, coalesced)
     R gv[kGeoPer];
 #pragma unroll
@@ -196,7 +195,7 @@ __global__ __launch_bounds__(kRecThreads, 4) void reconstruct_kernel(DevMesh m, 
 #pragma unroll
     for (int t = 0; t < kM2Chunks; ++t) {
         if (t > 0) __syncthreads();  // the previous chunk has been used
-        slot[kAhead ? t & 1 : 0].store(sBuf);
+        pre.store(sBuf);
         if (t == 0) {
 #pragma unroll
             for (int j = 0; j < kGeoPer; ++j) {
@@ -205,12 +204,7 @@ __global__ __launch_bounds__(kRecThreads, 4) void reconstruct_kernel(DevMesh m, 
             }
         }
         __syncthreads();
-        if constexpr (kAhead) {
-            if (t + 2 < kM2Chunks) slot[t & 1].load(tile, t + 2);
-            if (t == 1 && live && p.nonlinear) load_slopes(slopes, n, q, i, nb, b, sn);
-        } else {
-            if (t + 1 < kM2Chunks) slot[0].load(tile, t + 1);
-        }
+        if (t + 1 < kM2Chunks) pre.load(tile, t + 1);
 #pragma unroll
         for (int rr = 0; rr < kM2Chunk / 16; ++rr) {
             R acc = R(0);
@@ -223,9 +217,7 @@ __global__ __launch_bounds__(kRecThreads, 4) void reconstruct_kernel(DevMesh m, 
         }
     }
     __syncthreads();  // sBuf now holds the coefficients
-    if constexpr (!kAhead) {
-        if (live && p.nonlinear) load_slopes(slopes, n, q, i, nb, b, sn);
-    }
+    if (live && p.nonlinear) load_slopes(slopes, n, q, i, nb, b, sn);
 
     if (live) {
         const R vol23 = sGeo[G_VOL23][l];
