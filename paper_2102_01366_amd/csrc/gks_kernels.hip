@@ -322,30 +322,35 @@ __global__ __launch_bounds__(kRecThreads, GKS_REC_MIN_WAVES) void reconstruct_ke
     if (live) {
         if (q < 4) {
             // Gauss points of the face opposite vertex q: r_k / 2 - r_q / 6, k != q
-            R rv[4][3];
+            // (the vertex offsets read from LDS at the wavefront's own rows);
+            // each component's polynomial is read once and evaluated at all three
+            R rq6[3], r[3][3], v[3][5];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int dd = 0; dd < 3; ++dd) rq6[dd] = sGeo[G_RV + 3 * q + dd][l] / R(6);
 #pragma unroll
-                for (int dd = 0; dd < 3; ++dd) rv[a][dd] = sGeo[G_RV + 3 * a + dd][l];
+            for (int j = 0; j < 3; ++j) {
+                const int k = j + (j >= q ? 1 : 0);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (k == q) continue;
-                R r[3];
+                for (int dd = 0; dd < 3; ++dd) r[j][dd] = R(0.5) * sGeo[G_RV + 3 * k + dd][l] - rq6[dd];
+            }
 #pragma unroll
-                for (int dd = 0; dd < 3; ++dd) r[dd] = R(0.5) * rv[k][dd] - rv[q][dd] / R(6);
-                R v[5];
+            for (int c = 0; c < 5; ++c) {
+                R cf[10];
 #pragma unroll
-                for (int c = 0; c < 5; ++c) {
-                    R cf[10];
+                for (int kk = 0; kk < 10; ++kk) cf[kk] = sR[c][kk][l];
 #pragma unroll
-                    for (int kk = 0; kk < 10; ++kk) cf[kk] = sR[c][kk][l];
-                    v[c] = cf[0] + cf[1] * r[0] + cf[2] * r[1] + cf[3] * r[2] +
-                           R(0.5) * (cf[4] * r[0] * r[0] + cf[5] * r[1] * r[1] + cf[6] * r[2] * r[2]) +
-                           cf[7] * r[0] * r[1] + cf[8] * r[0] * r[2] + cf[9] * r[1] * r[2];
+                for (int j = 0; j < 3; ++j) {
+                    const R *x = r[j];
+                    v[j][c] = cf[0] + cf[1] * x[0] + cf[2] * x[1] + cf[3] * x[2] +
+                              R(0.5) * (cf[4] * x[0] * x[0] + cf[5] * x[1] * x[1] + cf[6] * x[2] * x[2]) +
+                              cf[7] * x[0] * x[1] + cf[8] * x[0] * x[2] + cf[9] * x[1] * x[2];
                 }
+            }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
                 const R pr = R(p.gamma - 1.0) *
-                             (v[4] - R(0.5) * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
-                if (!(v[0] > R(0)) || !(pr > R(0))) bad = 1;
+                             (v[j][4] - R(0.5) * (v[j][1] * v[j][1] + v[j][2] * v[j][2] + v[j][3] * v[j][3]) / v[j][0]);
+                if (!(v[j][0] > R(0)) || !(pr > R(0))) bad = 1;
             }
         } else {
             // a non-physical cell average cannot be repaired by the fallback
