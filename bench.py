@@ -157,6 +157,11 @@ def adjoint_leg(G, I, mesh, W, gW, cfg_kw, nsteps, ndir, precision):
         s.step(dt)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
+    # one step forward and back first, so that loading the reverse kernels and
+    # allocating the adjoint workspace fall outside the timed pass
+    Ww, Gw = W0.clone().requires_grad_(True), G0.clone().requires_grad_(True)
+    ke(rollout(s, Ww, Gw, dts[:1])[0]).backward()
+    del Ww, Gw
     Wr, Gr = W0.clone().requires_grad_(True), G0.clone().requires_grad_(True)
     J = ke(rollout(s, Wr, Gr, dts)[0])
     torch.cuda.synchronize()
