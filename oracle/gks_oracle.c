@@ -22,10 +22,25 @@
  * 2nd-smooth-flux): the equilibrium g^c, with the kinetically weighted W^c
  * and slopes of eq. new-equ-part, and no kinetic part.
  *
- * Walls (face_cell[2f+1] = -1) are slip walls (Sec. 4.4): cells next to them
- * use one-sided reconstructions (the own averaged gradient, and a linear
- * least-squares fit in step 2, where fewer than three neighbours remain) and
- * the flux sees the mirror image of the interior state as ghost.
+ * Walls (face_cell[2f+1] = -1) carry a tag (Sec. 4.4).  Next to any wall,
+ * cells use one-sided reconstructions (the own averaged gradient, and a
+ * linear least-squares fit in step 2, where fewer than three neighbours
+ * remain).  Slip walls (tag 2): the flux sees the mirror image of the
+ * interior state as ghost.  No-slip adiabatic (3) and isothermal (4) walls:
+ * the momentum (and at isothermal walls the energy) of the adjacent cells'
+ * reconstructions is constrained to the wall values in both steps, and the
+ * ghost is the reflected state.  Far field (5): the locally one-dimensional
+ * Riemann-invariant state against the free stream, with zero gradients.
+ *
+ * Pins (the tests/test_oracle_*.py suites, no GPU): quadrature exactness,
+ * reconstruction exactness on polynomials and the paper's convergence orders,
+ * Maxwellian moments against closed forms, the flux against the Euler and
+ * Navier-Stokes fluxes of smooth states, conservation, free-stream
+ * preservation, the walls' constraints and ghost symmetries.  Parity
+ * unpinned: the Prandtl correction beyond continuous linear data (pinned
+ * there against the Chapman-Enskog heat flux), and the magnitudes of the
+ * nonlinear-weight errors (their orders and the exactness are pinned; the
+ * paper's tabulated magnitudes are not reproduced).
  *
  * Loops over cells and faces may run under OpenMP; every output element is
  * written by exactly one iteration, and all sums run in a fixed serial
