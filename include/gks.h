@@ -210,6 +210,13 @@ gks_status gks_debug_reconstruct(gks_ctx *ctx, double *slopes, double *coef, int
  * |Gamma| sum_k w_k of (F_k (5), dF_k/dt (5), W_k(0) (5), W_k(dt) (5)) in the
  * global frame, normal outward from the owner.  Blocking. */
 gks_status gks_debug_face_terms(gks_ctx *ctx, double dt, double *out, int32_t on_device);
+/* The same launch with the flux rows before the linear-in-time fit of eq.
+ * linear-system: out[20][n_face] = |Gamma| sum_k w_k of (F_k(dt) (5),
+ * F_k(dt/2) (5), W_k(0) (5), W_k(dt) (5)), F_k(delta) the time integral over
+ * [0, delta] of the flux of eq. 2nd-flux (Sec. 2.2).  Comparing these
+ * un-cancelled integrals bounds the fitted dF/dt = 4 (F(dt) - 2 F(dt/2)) /
+ * dt^2, a difference of nearly equal terms.  Blocking. */
+gks_status gks_debug_flux_integrals(gks_ctx *ctx, double dt, double *out, int32_t on_device);
 
 /* Per-kernel timing for measurement: while enabled, every kernel launch of
  * the context is bracketed by HIP events on its stream.  gks_timing_read

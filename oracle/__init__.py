@@ -8,6 +8,13 @@ the benchmark's CPU-baseline leg may import this package.
 ``build()`` compiles ``libgks_oracle.so`` next to this file with gcc
 (``-O2``, OpenMP, no fast-math); ``Oracle`` wraps a mesh and exposes the
 per-kernel and per-step entry points as numpy functions.
+
+``build()`` also compiles the tangent build ``libgks_oracle_tangent.so``: the
+same source compiled as C++ over the forward-mode dual numbers of
+``or_dual.hpp`` (value plus 16 directional derivatives).  ``TangentOracle``
+runs its steps and returns exact Jacobian-vector products of the step map
+(time steps held fixed), and counts how often a kink of the scheme lies
+within a given distance along each direction.
 """
 from __future__ import annotations
 
@@ -20,6 +27,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gks_oracle.c")
 _LIB = os.path.join(_HERE, "libgks_oracle.so")
+_TLIB = os.path.join(_HERE, "libgks_oracle_tangent.so")
+_DUAL = os.path.join(_HERE, "or_dual.hpp")
+# the tangent build keeps ~3 MB of dual-number polynomials on each OpenMP
+# thread's stack; libgomp reads this when the first OpenMP library loads
+os.environ.setdefault("OMP_STACKSIZE", "64M")
 
 
 def build(force: bool = True) -> str:
@@ -29,6 +41,13 @@ def build(force: bool = True) -> str:
                "-ffp-contract=off", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_DUAL))
+    if force or not os.path.exists(_TLIB) or os.path.getmtime(_TLIB) < newest:
+        cmd = ["g++", "-O2", "-x", "c++", "-std=gnu++17", "-DOR_TANGENT", "-fopenmp", "-fPIC", "-shared",
+               "-ffp-contract=off", "-Wall", "-Wno-class-memaccess", "-Wl,-Bsymbolic", "-o", _TLIB + ".tmp",
+               _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_TLIB + ".tmp", _TLIB)
     return _LIB
 
 
@@ -39,16 +58,19 @@ class Config(ctypes.Structure):
                 ("lw2", ctypes.c_double * 3), ("lw1", ctypes.c_double * 2),
                 ("viscous", ctypes.c_int32), ("nonlinear", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("flux", ctypes.c_int32), ("wall_T", ctypes.c_double),
-                ("farfield", ctypes.c_double * 5)]
+                ("farfield", ctypes.c_double * 5), ("weno_reading", ctypes.c_int32)]
 
 
 def make_config(gamma=1.4, mu=0.0, prandtl=1.0, viscous=False, nonlinear=True,
                 eps_tau=0.01, c_tau=1.0, eps_weno=1e-8, lw2=(100.0, 10.0, 1.0),
                 lw1=(10.0, 1.0), K=None, order=3, flux=0, wall_T=1.0,
-                farfield=(1.0, 0.0, 0.0, 0.0, 2.5)) -> Config:
+                farfield=(1.0, 0.0, 0.0, 0.0, 2.5), weno_reading=0) -> Config:
     """Scheme parameters; linear weights are given as ratios and normalised.
-    flux: 0 for eq. 2nd-flux, 1 for the smooth-flow form eq. 2nd-smooth-flux."""
+    flux: 0 for eq. 2nd-flux, 1 for the smooth-flow form eq. 2nd-smooth-flux.
+    weno_reading: 0, or bits of READ_* selecting alternative readings of the
+    nonlinear weights (only for comparisons with the paper's Tables 2-3)."""
     c = Config()
+    c.weno_reading = weno_reading
     c.order = order
     c.flux = flux
     c.wall_T = wall_T
@@ -71,6 +93,9 @@ def make_config(gamma=1.4, mu=0.0, prandtl=1.0, viscous=False, nonlinear=True,
     c.nonlinear = 1 if nonlinear else 0
     return c
 
+
+# alternative readings of the nonlinear weights (gks_oracle.h, OR_READ_*)
+READ_POW1, READ_POW1ST2, READ_B0VOL, READ_MIXED2, READ_BETA_LOWER, READ_SIGMA1 = 1, 2, 4, 8, 16, 32
 
 _lib = None
 
@@ -96,6 +121,8 @@ def _load():
         L.or_slopes.argtypes = [P, P, P, P]
         L.or_reconstruct.argtypes = [P, P, P, P, P, P]
         L.or_face_terms.argtypes = [P, P, P, D, P]
+        L.or_face_integrals.argtypes = [P, P, P, D, P]
+        L.or_last_face_terms.argtypes = [P, P]
         L.or_stage.argtypes = [P, ctypes.c_int, D, P, P]
         L.or_step.argtypes = [P, D, P, P]
         L.or_compute_dt.argtypes = [P, P, D]
@@ -186,6 +213,48 @@ class Oracle:
             raise RuntimeError("oracle face terms failed")
         return out
 
+    def face_integrals(self, W, gW, dt):
+        """[20, nf]: |Gamma| sum_k w_k of F_k(dt), F_k(dt/2), W_k(0), W_k(dt)."""
+        W, gW = _f64(W), _f64(gW)
+        out = np.empty((20, self.nf))
+        rc = _load().or_face_integrals(self._h, _p(W), _p(gW), float(dt), _p(out))
+        if rc:
+            raise RuntimeError("oracle face integrals failed")
+        return out
+
+    def last_face_terms(self):
+        """[20, nf]: the face terms (as face_terms) of the last stage run."""
+        out = np.empty((20, self.nf))
+        _load().or_last_face_terms(self._h, _p(out))
+        return out
+
+    def gradient_bound(self, stage, ft1=None):
+        """Per cell, component and direction, the sum of the magnitudes of the
+        terms of the Gauss-theorem gradient (eq. gauss-formula) of the last
+        stage run, (1/|Omega_i|) sum over the cell's faces of |W_f| |n_d|
+        (interface values weighted by |Gamma|): stage 1 sums (W_k(0) +
+        W_k(dt)) / 2, stage 2 sums W1_k(0) + W2_k(dt) - W2_k(0), ft1 the face
+        terms of stage 1.  The momentum components share one bound (the face
+        frame mixes them).  Two correct FP64 evaluations of the gradient
+        differ by rounding relative to this bound, not to the gradient."""
+        ft = self.last_face_terms()
+        if stage == 1:
+            a = 0.5 * (np.abs(ft[10:15]) + np.abs(ft[15:20]))
+        else:
+            a = np.abs(ft1[10:15]) + np.abs(ft[15:20]) + np.abs(ft[10:15])
+        a[1:4] = a[1:4].sum(axis=0)
+        vol = self.geometry()[0]
+        nrm = np.abs(self.face_geometry()[1])
+        fc = self._keep[3].reshape(-1, 2)
+        B = np.zeros((15, self.nc))
+        for side in (0, 1):
+            cells = fc[:, side]
+            ok = cells >= 0
+            for q in range(5):
+                for d in range(3):
+                    B[3 * q + d] += np.bincount(cells[ok], weights=a[q, ok] * nrm[d, ok], minlength=self.nc)
+        return B / vol
+
     def stage(self, stage, dt, W, gW):
         W, gW = _f64(W).copy(), _f64(gW).copy()
         rc = _load().or_stage(self._h, int(stage), float(dt), _p(W), _p(gW))
@@ -262,3 +331,92 @@ def face_rule():
     p, w = np.empty(6), np.empty(3)
     _load().or_face_rule(_p(p), _p(w))
     return p.reshape(3, 2), w
+
+
+_tlib = None
+
+
+def _load_tangent():
+    global _tlib
+    if _tlib is None:
+        if not os.path.exists(_TLIB):
+            build(force=False)
+        L = ctypes.CDLL(_TLIB)
+        P = ctypes.c_void_p
+        D = ctypes.c_double
+        I64 = ctypes.c_int64
+        L.or_create.restype = P
+        L.or_create.argtypes = [ctypes.POINTER(Config), I64, P, I64, P, I64, P, P, P, P, P]
+        L.or_destroy.argtypes = [P]
+        L.or_step.argtypes = [P, D, P, P]
+        L.or_tangent_ndir.restype = ctypes.c_int
+        L.or_tangent_set_kink_eps.argtypes = [D]
+        L.or_tangent_kinks.argtypes = [P, ctypes.c_int]
+        _tlib = L
+    return _tlib
+
+
+class TangentOracle:
+    """The oracle's tangent build bound to one mesh and configuration.
+
+    States are arrays of shape (rows, n_cell, 1 + ndir): the value, then its
+    derivatives along ``ndir`` directions.  ``step`` advances them by one
+    step of the scheme with the time step held fixed, so the derivative part
+    of the result is the exact Jacobian-vector product of the step map."""
+
+    def __init__(self, mesh, cfg: Config):
+        L = _load_tangent()
+        self.cfg = cfg
+        self.nc = mesh.n_cell
+        self.ndir = L.or_tangent_ndir()
+        self._keep = [np.ascontiguousarray(mesh.xyz, np.float64),
+                      np.ascontiguousarray(mesh.tet, np.int64),
+                      np.ascontiguousarray(mesh.face_vert, np.int64),
+                      np.ascontiguousarray(mesh.face_cell, np.int64),
+                      np.ascontiguousarray(mesh.face_tag, np.int32),
+                      np.ascontiguousarray(mesh.face_shift, np.float64)]
+        wu = getattr(mesh, "face_wall_u", None)
+        self._keep.append(None if wu is None else np.ascontiguousarray(wu, np.float64))
+        xyz, tet, fv, fc, ft, fs, fw = self._keep
+        self._h = L.or_create(ctypes.byref(cfg), mesh.n_vert, _p(xyz), self.nc, _p(tet),
+                              mesh.n_face, _p(fv), _p(fc), _p(ft), _p(fs), None if fw is None else _p(fw))
+        if not self._h:
+            raise ValueError("oracle rejected the mesh")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _tlib is not None:
+            _tlib.or_destroy(h)
+            self._h = None
+
+    def pack(self, X, dX):
+        """value X[rows][n] and derivatives dX[ndir][rows][n] -> dual array"""
+        out = np.empty(X.shape + (1 + self.ndir,))
+        out[..., 0] = X
+        out[..., 1:] = np.moveaxis(np.asarray(dX, np.float64), 0, -1)
+        return out
+
+    @staticmethod
+    def unpack(Xd):
+        """dual array -> value [rows][n], derivatives [ndir][rows][n]"""
+        return Xd[..., 0].copy(), np.ascontiguousarray(np.moveaxis(Xd[..., 1:], -1, 0))
+
+    def step(self, dt, Wd, gWd):
+        Wd = np.ascontiguousarray(Wd, np.float64).copy()
+        gWd = np.ascontiguousarray(gWd, np.float64).copy()
+        assert Wd.shape == (5, self.nc, 1 + self.ndir) and gWd.shape == (15, self.nc, 1 + self.ndir)
+        rc = _tlib.or_step(self._h, float(dt), _p(Wd), _p(gWd))
+        if rc:
+            raise RuntimeError(f"tangent oracle step failed ({rc})")
+        return Wd, gWd
+
+    @staticmethod
+    def set_kink_eps(eps):
+        _load_tangent().or_tangent_set_kink_eps(float(eps))
+
+    def kinks(self, reset=True):
+        """counts [2][ndir]: jump-term and WENO-indicator kinks within the
+        set distance along each direction, since the last reset"""
+        out = np.zeros(2 * self.ndir, np.int64)
+        _tlib.or_tangent_kinks(_p(out), 1 if reset else 0)
+        return out.reshape(2, self.ndir)

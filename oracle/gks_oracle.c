@@ -58,6 +58,36 @@
  * a correction of the time-integrated energy flux by (1/Pr - 1) times the
  * time-integrated heat flux of the interface distribution about U^c.
  */
+/* The arithmetic type of everything that depends on the state: double, or
+ * in the tangent build (compiled as C++ with OR_TANGENT) a forward-mode dual
+ * number that also carries directional derivatives.  Geometry stays double. */
+#ifdef OR_TANGENT
+#include "or_dual.hpp"
+typedef or_dual real;
+#define OR_REAL or_dual
+#define OR_VALUE(x) ((x).v)
+/* Non-differentiable points of the scheme: the collision-time jump (site 0)
+ * and the absolute values in the WENO indicators (site 1).  The tangent
+ * build counts, per direction k, the evaluations whose argument x lies
+ * within the kink distance of zero, |x| < eps |dx/dv_k|: a central
+ * difference of step eps along v_k straddles such a kink. */
+static double or_kink_eps = 0.0;
+static long or_kinks[2][OR_NDIR];
+static or_dual or_kink_abs(const or_dual &x, int site)
+{
+    for (int k = 0; k < OR_NDIR; ++k)
+        if (std::fabs(x.v) < or_kink_eps * std::fabs(x.d[k])) {
+#pragma omp atomic
+            or_kinks[site][k] += 1;
+        }
+    return fabs(x);
+}
+#define OR_KINK_ABS(x, site) or_kink_abs((x), (site))
+#else
+typedef double real;
+#define OR_VALUE(x) (x)
+#define OR_KINK_ABS(x, site) fabs(x)
+#endif
 #include "gks_oracle.h"
 
 #include <math.h>
@@ -81,22 +111,22 @@
 /* Solve A X = B by Gaussian elimination with partial pivoting.  A is n x n
  * (row-major, destroyed), B is n x m (row-major, overwritten by X).
  * Returns 0, or -1 if a pivot is exactly zero. */
-static int gepp(int n, int m, double *A, double *B)
+static int gepp(int n, int m, real *A, real *B)
 {
     for (int k = 0; k < n; ++k) {
         int p = k;
-        double best = fabs(A[k * n + k]);
+        real best = fabs(A[k * n + k]);
         for (int i = k + 1; i < n; ++i) {
-            double v = fabs(A[i * n + k]);
+            real v = fabs(A[i * n + k]);
             if (v > best) { best = v; p = i; }
         }
         if (best == 0.0) return -1;
         if (p != k) {
-            for (int j = 0; j < n; ++j) { double t = A[k*n+j]; A[k*n+j] = A[p*n+j]; A[p*n+j] = t; }
-            for (int j = 0; j < m; ++j) { double t = B[k*m+j]; B[k*m+j] = B[p*m+j]; B[p*m+j] = t; }
+            for (int j = 0; j < n; ++j) { real t = A[k*n+j]; A[k*n+j] = A[p*n+j]; A[p*n+j] = t; }
+            for (int j = 0; j < m; ++j) { real t = B[k*m+j]; B[k*m+j] = B[p*m+j]; B[p*m+j] = t; }
         }
         for (int i = k + 1; i < n; ++i) {
-            double f = A[i * n + k] / A[k * n + k];
+            real f = A[i * n + k] / A[k * n + k];
             if (f == 0.0) continue;
             for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
             for (int j = 0; j < m; ++j) B[i * m + j] -= f * B[k * m + j];
@@ -104,7 +134,7 @@ static int gepp(int n, int m, double *A, double *B)
     }
     for (int k = n - 1; k >= 0; --k) {
         for (int j = 0; j < m; ++j) {
-            double s = B[k * m + j];
+            real s = B[k * m + j];
             for (int i = k + 1; i < n; ++i) s -= A[k * n + i] * B[i * m + j];
             B[k * m + j] = s / A[k * n + k];
         }
@@ -217,8 +247,8 @@ struct or_ctx {
     double (*fnorm)[3];
     double (*fgp)[3][3];  /* Gauss points, owner frame */
     /* stage storage */
-    double *Wn, *Ln, *Ltn, *FW0; /* W^n [5][nc], L(W^n), dL/dt(W^n), stage-1 W_k(0) sums [5][nf] */
-    double *slopes, *coef, *fterm;
+    real *Wn, *Ln, *Ltn, *FW0; /* W^n [5][nc], L(W^n), dL/dt(W^n), stage-1 W_k(0) sums [5][nf] */
+    real *slopes, *coef, *fterm;
     int32_t *flag;
     int have_stage1;
 };
@@ -258,29 +288,29 @@ or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
     c->nc = n_cell;
     c->nf = n_face;
     int64_t nc = n_cell, nf = n_face;
-    c->cv = xcalloc(nc, sizeof(*c->cv));
-    c->vol = xcalloc(nc, sizeof(double));
-    c->cen = xcalloc(nc, sizeof(*c->cen));
-    c->m2 = xcalloc(nc, sizeof(*c->m2));
-    c->dr = xcalloc(nc, sizeof(double));
-    c->nbr = xcalloc(nc, sizeof(*c->nbr));
-    c->cface = xcalloc(nc, sizeof(*c->cface));
-    c->noff = xcalloc(nc, sizeof(*c->noff));
-    c->fcell = xcalloc(nf, sizeof(*c->fcell));
-    c->ftag = xcalloc(nf, sizeof(int32_t));
-    c->fwu = xcalloc(nf, sizeof(*c->fwu));
-    c->fshift = xcalloc(nf, sizeof(*c->fshift));
-    c->farea = xcalloc(nf, sizeof(double));
-    c->fnorm = xcalloc(nf, sizeof(*c->fnorm));
-    c->fgp = xcalloc(nf, sizeof(*c->fgp));
-    c->Wn = xcalloc(5 * nc, sizeof(double));
-    c->Ln = xcalloc(5 * nc, sizeof(double));
-    c->Ltn = xcalloc(5 * nc, sizeof(double));
-    c->FW0 = xcalloc(5 * nf, sizeof(double));
-    c->slopes = xcalloc(15 * nc, sizeof(double));
-    c->coef = xcalloc(50 * nc, sizeof(double));
-    c->fterm = xcalloc(20 * nf, sizeof(double));
-    c->flag = xcalloc(nc, sizeof(int32_t));
+    c->cv = (__typeof__(c->cv))xcalloc(nc, sizeof(*c->cv));
+    c->vol = (__typeof__(c->vol))xcalloc(nc, sizeof(double));
+    c->cen = (__typeof__(c->cen))xcalloc(nc, sizeof(*c->cen));
+    c->m2 = (__typeof__(c->m2))xcalloc(nc, sizeof(*c->m2));
+    c->dr = (__typeof__(c->dr))xcalloc(nc, sizeof(double));
+    c->nbr = (__typeof__(c->nbr))xcalloc(nc, sizeof(*c->nbr));
+    c->cface = (__typeof__(c->cface))xcalloc(nc, sizeof(*c->cface));
+    c->noff = (__typeof__(c->noff))xcalloc(nc, sizeof(*c->noff));
+    c->fcell = (__typeof__(c->fcell))xcalloc(nf, sizeof(*c->fcell));
+    c->ftag = (__typeof__(c->ftag))xcalloc(nf, sizeof(int32_t));
+    c->fwu = (__typeof__(c->fwu))xcalloc(nf, sizeof(*c->fwu));
+    c->fshift = (__typeof__(c->fshift))xcalloc(nf, sizeof(*c->fshift));
+    c->farea = (__typeof__(c->farea))xcalloc(nf, sizeof(double));
+    c->fnorm = (__typeof__(c->fnorm))xcalloc(nf, sizeof(*c->fnorm));
+    c->fgp = (__typeof__(c->fgp))xcalloc(nf, sizeof(*c->fgp));
+    c->Wn = (real *)xcalloc(5 * nc, sizeof(real));
+    c->Ln = (real *)xcalloc(5 * nc, sizeof(real));
+    c->Ltn = (real *)xcalloc(5 * nc, sizeof(real));
+    c->FW0 = (real *)xcalloc(5 * nf, sizeof(real));
+    c->slopes = (real *)xcalloc(15 * nc, sizeof(real));
+    c->coef = (real *)xcalloc(50 * nc, sizeof(real));
+    c->fterm = (real *)xcalloc(20 * nf, sizeof(real));
+    c->flag = (__typeof__(c->flag))xcalloc(nc, sizeof(int32_t));
 
     /* cells: |Omega| = |J| / 6, centroid and second moments by the 5-point rule */
     for (int64_t i = 0; i < nc; ++i) {
@@ -301,7 +331,7 @@ or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
     }
 
     /* faces: area, owner-outward unit normal and the three Gauss points */
-    double *sumarea = xcalloc(nc, sizeof(double));
+    double *sumarea = (double *)xcalloc(nc, sizeof(double));
     for (int64_t f = 0; f < nf; ++f) {
         int64_t L = face_cell[2 * f], R = face_cell[2 * f + 1];
         if (L < 0 || L >= nc || R >= nc) { free(sumarea); or_destroy(c); return NULL; }
@@ -421,7 +451,7 @@ static int face_constrains(const or_ctx *c, int64_t f, int q)
 /* the prescribed value of component q at a point of wall face f, from the
  * density reconstructed there: rho U_wall, or rho (|U_wall|^2 / 2 +
  * T_wall / (gamma - 1)) with T = p / rho */
-static double wall_value(const or_ctx *c, int64_t f, int q, double rho)
+static real wall_value(const or_ctx *c, int64_t f, int q, real rho)
 {
     const double *u = c->fwu[f];
     if (q <= 3) return rho * u[q - 1];
@@ -436,11 +466,11 @@ static double wall_value(const or_ctx *c, int64_t f, int q, double rho)
  * squares with one equality row at each constrained face's centre, if the
  * neighbours and constraints number at least three and the constraints at
  * most three. */
-static void slopes_cell(const or_ctx *c, int64_t i, const double *W, const double *gW, double b[NC][3])
+static void slopes_cell(const or_ctx *c, int64_t i, const real *W, const real *gW, real b[NC][3])
 {
     int64_t n = c->nc;
     double h = cbrt(c->vol[i]);
-    double D[4][3];
+    real D[4][3];
     int nn = 0;
     int64_t mm[4];
     for (int a = 0; a < 4; ++a) {
@@ -453,20 +483,20 @@ static void slopes_cell(const or_ctx *c, int64_t i, const double *W, const doubl
         mm[nn++] = c->nbr[i][a];
     }
     /* normal equations (D^T D) b' = D^T (Q_m - Q_0) for all components */
-    double A[9], B[3 * NC];
+    real A[9], B[3 * NC];
     for (int r = 0; r < 3; ++r)
         for (int s = 0; s < 3; ++s) {
-            double t = 0;
+            real t = 0;
             for (int k = 0; k < nn; ++k) t += D[k][r] * D[k][s];
             A[3 * r + s] = t;
         }
     for (int r = 0; r < 3; ++r)
         for (int q = 0; q < NC; ++q) {
-            double t = 0;
+            real t = 0;
             for (int k = 0; k < nn; ++k) t += D[k][r] * (W[q * n + mm[k]] - W[q * n + i]);
             B[r * NC + q] = t;
         }
-    double A0[9];
+    real A0[9];
     memcpy(A0, A, sizeof(A));
     if (nn < 3) {
         for (int q = 0; q < NC; ++q)
@@ -491,17 +521,17 @@ static void slopes_cell(const or_ctx *c, int64_t i, const double *W, const doubl
         }
         /* KKT system [D^T D  C^T; C  0] [b'; lambda] = [D^T (Q_m - Q_0); e] */
         int N = 3 + ncon;
-        double K[36], R[6];
+        real K[36], R[6];
         memset(K, 0, sizeof(K));
         for (int r = 0; r < 3; ++r) {
             for (int s2 = 0; s2 < 3; ++s2) K[r * N + s2] = A0[3 * r + s2];
-            double t = 0;
+            real t = 0;
             for (int k = 0; k < nn; ++k) t += D[k][r] * (W[q * n + mm[k]] - W[q * n + i]);
             R[r] = t;
         }
         for (int j = 0; j < ncon; ++j) {
             int64_t f = fl[j];
-            double x[3], rho = W[i];
+            real x[3], rho = W[i];
             for (int d = 0; d < 3; ++d) {
                 x[d] = (c->fgp[f][0][d] + c->fgp[f][1][d] + c->fgp[f][2][d]) / 3.0 - c->cen[i][d];
                 rho += b[0][d] * x[d];
@@ -517,12 +547,12 @@ static void slopes_cell(const or_ctx *c, int64_t i, const double *W, const doubl
     }
 }
 
-int or_slopes(or_ctx *c, const double *W, const double *gW, double *b)
+int or_slopes(or_ctx *c, const real *W, const real *gW, real *b)
 {
     int64_t n = c->nc;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double s[NC][3];
+        real s[NC][3];
         slopes_cell(c, i, W, gW, s);
         for (int q = 0; q < NC; ++q)
             for (int d = 0; d < 3; ++d) b[(3 * q + d) * n + i] = s[q][d];
@@ -536,23 +566,23 @@ int or_slopes(or_ctx *c, const double *W, const double *gW, double *b)
 
 /* polynomial about the centroid: value c0, gradient G, Hessian H
  * (xx,yy,zz,xy,xz,yz) -- P(r) = c0 + G.r + 1/2 r^T H r */
-typedef struct { double c0, G[3], H[6]; } qpoly_t;
+typedef struct { real c0, G[3], H[6]; } qpoly_t;
 
-static double quad_eval(const qpoly_t *p, const double r[3])
+static real quad_eval(const qpoly_t *p, const double r[3])
 {
     return p->c0 + p->G[0] * r[0] + p->G[1] * r[1] + p->G[2] * r[2] +
            0.5 * (p->H[0] * r[0] * r[0] + p->H[1] * r[1] * r[1] + p->H[2] * r[2] * r[2]) +
            p->H[3] * r[0] * r[1] + p->H[4] * r[0] * r[2] + p->H[5] * r[1] * r[2];
 }
 
-static void quad_grad(const qpoly_t *p, const double r[3], double g[3])
+static void quad_grad(const qpoly_t *p, const double r[3], real g[3])
 {
     g[0] = p->G[0] + p->H[0] * r[0] + p->H[3] * r[1] + p->H[4] * r[2];
     g[1] = p->G[1] + p->H[3] * r[0] + p->H[1] * r[1] + p->H[5] * r[2];
     g[2] = p->G[2] + p->H[4] * r[0] + p->H[5] * r[1] + p->H[2] * r[2];
 }
 
-static qpoly_t quad_lin(double a, const qpoly_t *p, double b, const qpoly_t *q)
+static qpoly_t quad_lin(real a, const qpoly_t *p, real b, const qpoly_t *q)
 {
     qpoly_t r;
     r.c0 = a * p->c0 + b * q->c0;
@@ -583,8 +613,8 @@ static double mono_lookup(const double mono[10], int ex, int ey, int ez)
  * y = (x - c_0) / h for the basis y^k - <y^k>_0: E and e, the neighbour
  * averages (E[.][k] = <y^k>_m - <y^k>_0, e = Q_m - Q_0 per component); A and
  * bb, the neighbour averaged derivatives (bb = h dQ_m/dx_j). */
-static void p2_rows(const or_ctx *c, int64_t i, const double *W, const double *gW, double mono0[10],
-                    double E[4][9], double e[4][NC], double A[12][9], double bb[12][NC], int *ne_, int *na_)
+static void p2_rows(const or_ctx *c, int64_t i, const real *W, const real *gW, double mono0[10],
+                    double E[4][9], real e[4][NC], double A[12][9], real bb[12][NC], int *ne_, int *na_)
 {
     int64_t n = c->nc;
     double h = cbrt(c->vol[i]);
@@ -620,18 +650,18 @@ static void p2_rows(const or_ctx *c, int64_t i, const double *W, const double *g
 /* The first-order polynomial fitted to the step-2 data (neighbour averages
  * and averaged derivatives) by least squares, normal equations on the three
  * linear coefficients: the fallback of Sec. 4.4 for component q. */
-static void p2_linear(double E[4][9], double e[4][NC], double A[12][9], double bb[12][NC], int ne, int na,
-                      double h, double Q0, int q, qpoly_t *p)
+static void p2_linear(double E[4][9], real e[4][NC], double A[12][9], real bb[12][NC], int ne, int na,
+                      double h, real Q0, int q, qpoly_t *p)
 {
-    double A3[9], B3[3];
+    real A3[9], B3[3];
     for (int r = 0; r < 3; ++r) {
         for (int s2 = 0; s2 < 3; ++s2) {
-            double t = 0.0;
+            real t = 0.0;
             for (int k = 0; k < ne; ++k) t += E[k][r] * E[k][s2];
             for (int k = 0; k < na; ++k) t += A[k][r] * A[k][s2];
             A3[3 * r + s2] = t;
         }
-        double t = 0.0;
+        real t = 0.0;
         for (int k = 0; k < ne; ++k) t += E[k][r] * e[k][q];
         for (int k = 0; k < na; ++k) t += A[k][r] * bb[k][q];
         B3[r] = t;
@@ -644,7 +674,7 @@ static void p2_linear(double E[4][9], double e[4][NC], double A[12][9], double b
 }
 
 /* P^2(y) = Q0 + sum_k a_k (y^k - <y^k>_0), back to physical r = h y */
-static void p2_from_basis(const double ak[9], const double mono0[10], double h, double Q0, qpoly_t *p)
+static void p2_from_basis(const real ak[9], const double mono0[10], double h, real Q0, qpoly_t *p)
 {
     p->c0 = Q0;
     for (int k = 3; k < 9; ++k) p->c0 -= ak[k] * mono_lookup(mono0, KEXP[k][0], KEXP[k][1], KEXP[k][2]);
@@ -662,28 +692,29 @@ static void p2_from_basis(const double ak[9], const double mono0[10], double h, 
  * neighbour averaged derivatives; the cell's own averaged derivative is not
  * used.  Solved through the KKT system.  Returns per component the
  * polynomial about the centroid. */
-static void p2_cell(const or_ctx *c, int64_t i, const double *W, const double *gW,
+static void p2_cell(const or_ctx *c, int64_t i, const real *W, const real *gW,
                     qpoly_t P2[NC])
 {
     int64_t n = c->nc;
     double h = cbrt(c->vol[i]);
-    double mono0[10], E[4][9], e[4][NC], A[12][9], bb[12][NC];
+    double mono0[10], E[4][9], A[12][9];
+    real e[4][NC], bb[12][NC];
     int ne, na;
     p2_rows(c, i, W, gW, mono0, E, e, A, bb, &ne, &na);
     /* KKT: [A^T A  E^T; E  0] [a; lambda] = [A^T b; e] */
     int N = 9 + ne;
-    double K[13 * 13], B[13 * NC];
+    real K[13 * 13], B[13 * NC];
     memset(K, 0, sizeof(K));
     memset(B, 0, sizeof(B));
     for (int r = 0; r < 9; ++r) {
         for (int s = 0; s < 9; ++s) {
-            double t = 0;
+            real t = 0;
             for (int k = 0; k < na; ++k) t += A[k][r] * A[k][s];
             K[r * N + s] = t;
         }
         for (int s = 0; s < ne; ++s) K[r * N + 9 + s] = E[s][r];
         for (int q = 0; q < NC; ++q) {
-            double t = 0;
+            real t = 0;
             for (int k = 0; k < na; ++k) t += A[k][r] * bb[k][q];
             B[r * NC + q] = t;
         }
@@ -700,7 +731,7 @@ static void p2_cell(const or_ctx *c, int64_t i, const double *W, const double *g
             p2_linear(E, e, A, bb, ne, na, h, W[q * n + i], q, &P2[q]);
             continue;
         }
-        double ak[9];
+        real ak[9];
         for (int k = 0; k < 9; ++k) ak[k] = B[k * NC + q];
         memset(&P2[q], 0, sizeof(qpoly_t));
         p2_from_basis(ak, mono0, h, W[q * n + i], &P2[q]);
@@ -715,7 +746,7 @@ static void p2_cell(const or_ctx *c, int64_t i, const double *W, const double *g
  * than nine constraints, fewer than nine data and constraints together, or a
  * singular system: the linear least-squares fallback.  P is left unchanged
  * when no face constrains q. */
-static void p2_wall(const or_ctx *c, int64_t i, const double *W, const double *gW, int q,
+static void p2_wall(const or_ctx *c, int64_t i, const real *W, const real *gW, int q,
                     const qpoly_t *Rrho, qpoly_t *P)
 {
     int64_t n = c->nc;
@@ -724,8 +755,10 @@ static void p2_wall(const or_ctx *c, int64_t i, const double *W, const double *g
     for (int a = 0; a < 4; ++a)
         if (face_constrains(c, c->cface[i][a], q)) fl[nfc++] = c->cface[i][a];
     if (nfc == 0) return;
-    double h = cbrt(c->vol[i]), Q0 = W[q * n + i];
-    double mono0[10], E[4][9], e[4][NC], A[12][9], bb[12][NC];
+    double h = cbrt(c->vol[i]);
+    real Q0 = W[q * n + i];
+    double mono0[10], E[4][9], A[12][9];
+    real e[4][NC], bb[12][NC];
     int ne, na;
     p2_rows(c, i, W, gW, mono0, E, e, A, bb, &ne, &na);
     int ng = 3 * nfc;
@@ -734,16 +767,16 @@ static void p2_wall(const or_ctx *c, int64_t i, const double *W, const double *g
         return;
     }
     int N = 9 + ng;
-    double K[18 * 18], B[18];
+    real K[18 * 18], B[18];
     memset(K, 0, sizeof(K));
     for (int r = 0; r < 9; ++r) {
         for (int s2 = 0; s2 < 9; ++s2) {
-            double t = 0.0;
+            real t = 0.0;
             for (int k = 0; k < ne; ++k) t += E[k][r] * E[k][s2];
             for (int k = 0; k < na; ++k) t += A[k][r] * A[k][s2];
             K[r * N + s2] = t;
         }
-        double t = 0.0;
+        real t = 0.0;
         for (int k = 0; k < ne; ++k) t += E[k][r] * e[k][q];
         for (int k = 0; k < na; ++k) t += A[k][r] * bb[k][q];
         B[r] = t;
@@ -758,7 +791,7 @@ static void p2_wall(const or_ctx *c, int64_t i, const double *W, const double *g
                 y[d] = x[d] / h;
             }
             for (int k = 0; k < 9; ++k) {
-                double v = 1.0;
+                real v = 1.0;
                 for (int d = 0; d < 3; ++d)
                     for (int t = 0; t < KEXP[k][d]; ++t) v *= y[d];
                 v -= mono_lookup(mono0, KEXP[k][0], KEXP[k][1], KEXP[k][2]);
@@ -778,12 +811,13 @@ static void p2_wall(const or_ctx *c, int64_t i, const double *W, const double *g
 /* eq. smooth-indicator for a polynomial about the centroid of cell i, with
  * derivatives up to order r; the integrals use the five-point rule (exact
  * for the quadratic integrands that occur here). */
-static double smoothness(const or_ctx *c, int64_t i, const qpoly_t *p, int r)
+static real smoothness(const or_ctx *c, int64_t i, const qpoly_t *p, int r)
 {
-    double vol = c->vol[i];
-    double s1 = 0.0, wsum = 0.0;
+    real vol = c->vol[i];
+    real s1 = 0.0, wsum = 0.0;
     for (int q = 0; q < 5; ++q) {
-        double X[3], rr[3], g[3];
+        double X[3], rr[3];
+        real g[3];
         tet_map(c->cv[i], VQ_PTS[q], X);
         for (int d = 0; d < 3; ++d) rr[d] = X[d] - c->cen[i][d];
         quad_grad(p, rr, g);
@@ -791,10 +825,12 @@ static double smoothness(const or_ctx *c, int64_t i, const qpoly_t *p, int r)
         wsum += VQ_W[q];
     }
     /* integral over Omega = |Omega| * average */
-    double beta = pow(vol, 2.0 / 3.0 - 1.0) * vol * (s1 / wsum);
+    real beta = pow(vol, 2.0 / 3.0 - 1.0) * vol * (s1 / wsum);
     if (r >= 2) {
-        double s2 = 0.0;
+        real s2 = 0.0;
         for (int k = 0; k < 6; ++k) s2 += p->H[k] * p->H[k];
+        if (c->cfg.weno_reading & OR_READ_MIXED2)
+            for (int k = 3; k < 6; ++k) s2 += p->H[k] * p->H[k];
         beta += pow(vol, 4.0 / 3.0 - 1.0) * vol * s2;
     }
     return beta;
@@ -817,47 +853,56 @@ static int cell_face_points(const or_ctx *c, int64_t i, double r[12][3])
 
 /* eq. p0-non-linear-weight: the two-step indicator of P^0 for component q,
  * from the neighbours' step-1 slopes */
-static double beta0_two_step(const or_ctx *c, int64_t i, const double *slopes, int q)
+static real beta0_two_step(const or_ctx *c, int64_t i, const real *slopes, int q)
 {
     const or_config *cf = &c->cfg;
     int64_t n = c->nc;
-    double vol23 = pow(c->vol[i], 2.0 / 3.0), eps = cf->eps_weno;
-    double b0[4];
+    real vol23 = pow(c->vol[i], 2.0 / 3.0), eps = cf->eps_weno;
+    real b0[4];
     int nb = 0;
     for (int a = 0; a < 4; ++a) {
         int64_t m = c->nbr[i][a];
         if (m < 0) continue;
-        double s = 0;
+        real s = 0;
         for (int d = 0; d < 3; ++d) {
-            double v = slopes[(3 * q + d) * n + m];
+            real v = slopes[(3 * q + d) * n + m];
             s += v * v;
         }
-        b0[nb++] = vol23 * s;
+        b0[nb++] = ((cf->weno_reading & OR_READ_B0VOL) ? c->vol[i] : vol23) * s;
     }
-    double beta0 = 0.0;
+    real beta0 = 0.0;
     if (nb > 0) {
-        double sum = 0.0;
+        real sum = 0.0;
         int npair = 0;
         for (int j = 0; j < nb; ++j)
-            for (int k = 0; k < j; ++k) { sum += fabs(b0[j] - b0[k]); ++npair; }
-        double sigma1 = npair ? pow(sum / npair, 4.0 / 3.0) : 0.0;
-        double w[4], ws = 0.0;
-        for (int j = 0; j < nb; ++j) { w[j] = 1.0 + sigma1 / (eps + b0[j]); ws += w[j]; }
+            for (int k = 0; k < j; ++k) { sum += OR_KINK_ABS(b0[j] - b0[k], 1); ++npair; }
+        real sigma1 = npair ? pow(sum / npair, 4.0 / 3.0) : 0.0;
+        real w[4], ws = 0.0;
+        for (int j = 0; j < nb; ++j) {
+            real r = sigma1 / (eps + b0[j]);
+            w[j] = 1.0 + ((cf->weno_reading & OR_READ_POW1ST2) ? r * r : r);
+            ws += w[j];
+        }
         for (int j = 0; j < nb; ++j) beta0 += (w[j] / ws) * b0[j];
     }
     return beta0;
 }
 
-static int positivity_fallback(const or_ctx *c, int64_t i, const double *W, qpoly_t R[NC]);
+static int positivity_fallback(const or_ctx *c, int64_t i, const real *W, qpoly_t R[NC]);
+
+/* (sigma / (eps + beta))^2 of eq. non-linear-weight (the first power under
+ * the alternative reading OR_READ_POW1) */
+static real wpow(real r, int reading) { return (reading & OR_READ_POW1) ? r : r * r; }
 
 /* Second-order scheme (eq. final_weno_expression-2nd): R = w11 p1 + w01 p0
  * with p1 = (P^1 - g01 P^0) / g11, p0 = P^0, sigma = |beta1 - beta0|^(4/3) */
-static int reconstruct_cell_2nd(const or_ctx *c, int64_t i, const double *W, const double *slopes,
+static int reconstruct_cell_2nd(const or_ctx *c, int64_t i, const real *W, const real *slopes,
                                 qpoly_t R[NC])
 {
     const or_config *cf = &c->cfg;
     int64_t n = c->nc;
     const double g11 = cf->lw1[0], g01 = cf->lw1[1], eps = cf->eps_weno;
+    const int rd = cf->weno_reading;
     for (int q = 0; q < NC; ++q) {
         qpoly_t P0;
         memset(&P0, 0, sizeof(P0));
@@ -865,22 +910,22 @@ static int reconstruct_cell_2nd(const or_ctx *c, int64_t i, const double *W, con
         qpoly_t P1 = P0;
         for (int d = 0; d < 3; ++d) P1.G[d] = slopes[(3 * q + d) * n + i];
         if (!cf->nonlinear) { R[q] = P1; continue; }
-        double beta1 = smoothness(c, i, &P1, 1);
-        double beta0 = beta0_two_step(c, i, slopes, q);
-        double sigma = pow(fabs(beta1 - beta0), 4.0 / 3.0);
-        double w1 = g11 * (1.0 + pow(sigma / (eps + beta1), 2.0));
-        double w0 = g01 * (1.0 + pow(sigma / (eps + beta0), 2.0));
-        double ws = w0 + w1;
-        w0 /= ws; w1 /= ws;
         qpoly_t p1 = quad_lin(1.0 / g11, &P1, -g01 / g11, &P0);
+        real beta1 = smoothness(c, i, (rd & OR_READ_BETA_LOWER) ? &p1 : &P1, 1);
+        real beta0 = beta0_two_step(c, i, slopes, q);
+        real sigma = pow(OR_KINK_ABS(beta1 - beta0, 1), (rd & OR_READ_SIGMA1) ? 1.0 : 4.0 / 3.0);
+        real w1 = g11 * (1.0 + wpow(sigma / (eps + beta1), rd));
+        real w0 = g01 * (1.0 + wpow(sigma / (eps + beta0), rd));
+        real ws = w0 + w1;
+        w0 /= ws; w1 /= ws;
         R[q] = quad_lin(w1, &p1, w0, &P0);
     }
     return positivity_fallback(c, i, W, R);
 }
 
 /* Secs. 4.2-4.3: multi-resolution WENO with the two-step indicator for P^0 */
-static int reconstruct_cell(const or_ctx *c, int64_t i, const double *W, const double *gW,
-                            const double *slopes, qpoly_t R[NC], qpoly_t *p2out)
+static int reconstruct_cell(const or_ctx *c, int64_t i, const real *W, const real *gW,
+                            const real *slopes, qpoly_t R[NC], qpoly_t *p2out)
 {
     const or_config *cf = &c->cfg;
     int64_t n = c->nc;
@@ -890,8 +935,9 @@ static int reconstruct_cell(const or_ctx *c, int64_t i, const double *W, const d
     const double g22 = cf->lw2[0], g12 = cf->lw2[1], g02 = cf->lw2[2];
     const double g11 = cf->lw1[0], g01 = cf->lw1[1];
     const double eps = cf->eps_weno;
+    const int rd = cf->weno_reading;
     for (int q = 0; q < NC; ++q) {
-        double Q0 = W[q * n + i];
+        real Q0 = W[q * n + i];
         qpoly_t P0;
         memset(&P0, 0, sizeof(P0));
         P0.c0 = Q0;
@@ -901,23 +947,26 @@ static int reconstruct_cell(const or_ctx *c, int64_t i, const double *W, const d
         if (q > 0) p2_wall(c, i, W, gW, q, &R[0], &P2[q]);
         if (p2out) p2out[q] = P2[q];
         if (!cf->nonlinear) { R[q] = P2[q]; continue; }
-        /* indicators of P^1 and P^2 */
-        double beta1 = smoothness(c, i, &P1, 1);
-        double beta2 = smoothness(c, i, &P2[q], 2);
-        /* eq. p0-non-linear-weight: indicator of P^0 from the neighbours' slopes */
-        double beta0 = beta0_two_step(c, i, slopes, q);
-        /* global indicator and nonlinear weights (eq. non-linear-weight) */
-        double sigma = pow(0.5 * (fabs(beta2 - beta1) + fabs(beta2 - beta0)), 4.0 / 3.0);
-        double w2 = g22 * (1.0 + pow(sigma / (eps + beta2), 2.0));
-        double w1 = g12 * (1.0 + pow(sigma / (eps + beta1), 2.0));
-        double w0 = g02 * (1.0 + pow(sigma / (eps + beta0), 2.0));
-        double ws = w0 + w1 + w2;
-        w0 /= ws; w1 /= ws; w2 /= ws;
-        /* the three hierarchical polynomials and their weighted sum */
+        /* the three hierarchical polynomials */
         qpoly_t p0 = P0;
         qpoly_t p1 = quad_lin(1.0 / g11, &P1, -g01 / g11, &P0);
         qpoly_t t = quad_lin(1.0 / g22, &P2[q], -g12 / g22, &p1);
         qpoly_t p2 = quad_lin(1.0, &t, -g02 / g22, &p0);
+        /* indicators of P^1 and P^2 */
+        int lower = rd & OR_READ_BETA_LOWER;
+        real beta1 = smoothness(c, i, lower ? &p1 : &P1, 1);
+        real beta2 = smoothness(c, i, lower ? &p2 : &P2[q], 2);
+        /* eq. p0-non-linear-weight: indicator of P^0 from the neighbours' slopes */
+        real beta0 = beta0_two_step(c, i, slopes, q);
+        /* global indicator and nonlinear weights (eq. non-linear-weight) */
+        real sigma = pow(0.5 * (OR_KINK_ABS(beta2 - beta1, 1) + OR_KINK_ABS(beta2 - beta0, 1)),
+                           (rd & OR_READ_SIGMA1) ? 1.0 : 4.0 / 3.0);
+        real w2 = g22 * (1.0 + wpow(sigma / (eps + beta2), rd));
+        real w1 = g12 * (1.0 + wpow(sigma / (eps + beta1), rd));
+        real w0 = g02 * (1.0 + wpow(sigma / (eps + beta0), rd));
+        real ws = w0 + w1 + w2;
+        w0 /= ws; w1 /= ws; w2 /= ws;
+        /* their weighted sum */
         qpoly_t s = quad_lin(w2, &p2, w1, &p1);
         R[q] = quad_lin(1.0, &s, w0, &p0);
     }
@@ -926,7 +975,7 @@ static int reconstruct_cell(const or_ctx *c, int64_t i, const double *W, const d
 
 /* positivity of density and pressure at the cell's face Gauss points;
  * otherwise the first-order (constant) reconstruction */
-static int positivity_fallback(const or_ctx *c, int64_t i, const double *W, qpoly_t R[NC])
+static int positivity_fallback(const or_ctx *c, int64_t i, const real *W, qpoly_t R[NC])
 {
     const or_config *cf = &c->cfg;
     int64_t n = c->nc;
@@ -934,10 +983,10 @@ static int positivity_fallback(const or_ctx *c, int64_t i, const double *W, qpol
     int np = cell_face_points(c, i, r);
     int bad = 0;
     for (int k = 0; k < np && !bad; ++k) {
-        double v[NC];
+        real v[NC];
         for (int q = 0; q < NC; ++q) v[q] = quad_eval(&R[q], r[k]);
-        double rho = v[0];
-        double pr = (cf->gamma - 1.0) * (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho);
+        real rho = v[0];
+        real pr = (cf->gamma - 1.0) * (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho);
         if (!(rho > 0.0) || !(pr > 0.0)) bad = 1;
     }
     if (bad) {
@@ -949,16 +998,16 @@ static int positivity_fallback(const or_ctx *c, int64_t i, const double *W, qpol
     return bad;
 }
 
-static void pack_quad(const qpoly_t *p, double *out, int64_t n, int64_t i, int q)
+static void pack_quad(const qpoly_t *p, real *out, int64_t n, int64_t i, int q)
 {
-    double *o = out + (size_t)(10 * q) * n + i;
+    real *o = out + (size_t)(10 * q) * n + i;
     o[0] = p->c0;
     for (int d = 0; d < 3; ++d) o[(1 + d) * n] = p->G[d];
     for (int k = 0; k < 6; ++k) o[(4 + k) * n] = p->H[k];
 }
 
-int or_reconstruct(or_ctx *c, const double *W, const double *gW, double *coef, int32_t *flag,
-                   double *p2coef)
+int or_reconstruct(or_ctx *c, const real *W, const real *gW, real *coef, int32_t *flag,
+                   real *p2coef)
 {
     int64_t n = c->nc;
     or_slopes(c, W, gW, c->slopes);
@@ -984,11 +1033,11 @@ int or_reconstruct(or_ctx *c, const double *W, const double *gW, double *coef, i
  * unsimplified list of monomials c u^e0 v^e1 w^e2 (xi^2)^e3. */
 #define MAXMONO 1024
 #define NMOM 12
-typedef struct { double c; int e[4]; } mono_t;
+typedef struct { real c; int e[4]; } mono_t;
 typedef struct { int n; mono_t m[MAXMONO]; } poly_t;
 
 static void poly_zero(poly_t *p) { p->n = 0; }
-static void poly_term(poly_t *p, double c, int eu, int ev, int ew, int ex)
+static void poly_term(poly_t *p, real c, int eu, int ev, int ew, int ex)
 {
     if (p->n >= MAXMONO) abort();
     mono_t *t = &p->m[p->n++];
@@ -1003,7 +1052,7 @@ static void poly_mul(const poly_t *a, const poly_t *b, poly_t *out)
                       a->m[i].e[1] + b->m[j].e[1], a->m[i].e[2] + b->m[j].e[2],
                       a->m[i].e[3] + b->m[j].e[3]);
 }
-static void poly_add_to(poly_t *acc, const poly_t *p, double s)
+static void poly_add_to(poly_t *acc, const poly_t *p, real s)
 {
     for (int i = 0; i < p->n; ++i)
         poly_term(acc, s * p->m[i].c, p->m[i].e[0], p->m[i].e[1], p->m[i].e[2], p->m[i].e[3]);
@@ -1024,7 +1073,7 @@ static void poly_psi(int j, poly_t *p)
     }
 }
 /* s = s_j psi_j */
-static void poly_slope(const double s[5], poly_t *p)
+static void poly_slope(const real s[5], poly_t *p)
 {
     poly_zero(p);
     for (int j = 0; j < 5; ++j) {
@@ -1043,38 +1092,38 @@ static void poly_velocity(int d, poly_t *p) /* u_d */
  * determined from W by eq. get-glr: rho E = rho (|U|^2/2 + (K+3)/(4 lam)).
  * Moments are normalised by rho. */
 typedef struct {
-    double rho, U, V, Wv, lam;
-    double mu[NMOM], mup[NMOM], mun[NMOM], mv[NMOM], mw[NMOM], mx[4];
+    real rho, U, V, Wv, lam;
+    real mu[NMOM], mup[NMOM], mun[NMOM], mv[NMOM], mw[NMOM], mx[4];
 } maxw_t;
 
 enum { FULL = 0, POS = 1, NEG = 2 };
 
-static void full_moments(double U, double lam, double *m)
+static void full_moments(real U, real lam, real *m)
 {
     m[0] = 1.0;
     m[1] = U;
     for (int k = 0; k + 2 < NMOM; ++k) m[k + 2] = U * m[k + 1] + (k + 1) / (2.0 * lam) * m[k];
 }
 
-static int maxwellian(const or_config *cf, const double W[5], maxw_t *g)
+static int maxwellian(const or_config *cf, const real W[5], maxw_t *g)
 {
-    double K = cf->K;
+    real K = cf->K;
     g->rho = W[0];
     if (!(g->rho > 0.0)) return -1;
     g->U = W[1] / W[0];
     g->V = W[2] / W[0];
     g->Wv = W[3] / W[0];
-    double ein = W[4] / W[0] - 0.5 * (g->U * g->U + g->V * g->V + g->Wv * g->Wv);
+    real ein = W[4] / W[0] - 0.5 * (g->U * g->U + g->V * g->V + g->Wv * g->Wv);
     if (!(ein > 0.0)) return -1;
     g->lam = (K + 3.0) / (4.0 * ein);
-    double lam = g->lam;
+    real lam = g->lam;
     full_moments(g->U, lam, g->mu);
     full_moments(g->V, lam, g->mv);
     full_moments(g->Wv, lam, g->mw);
     /* half spaces: <u^0>_{u>0} = erfc(-sqrt(lam) U)/2,
      * <u^1>_{u>0} = U <u^0>_{u>0} + exp(-lam U^2) / (2 sqrt(pi lam)); the
      * same three-term recursion as the full moments holds above order 1 */
-    double sl = sqrt(lam), ex = exp(-lam * g->U * g->U) / (2.0 * sqrt(M_PI * lam));
+    real sl = sqrt(lam), ex = exp(-lam * g->U * g->U) / (2.0 * sqrt(M_PI * lam));
     g->mup[0] = 0.5 * erfc(-sl * g->U);
     g->mup[1] = g->U * g->mup[0] + ex;
     g->mun[0] = 0.5 * erfc(sl * g->U);
@@ -1093,10 +1142,10 @@ static int maxwellian(const or_config *cf, const double W[5], maxw_t *g)
 
 /* normalised moment of a polynomial: integral of p g over the chosen half of
  * u, divided by rho */
-static double moment(const poly_t *p, const maxw_t *g, int half)
+static real moment(const poly_t *p, const maxw_t *g, int half)
 {
-    const double *mu = half == POS ? g->mup : (half == NEG ? g->mun : g->mu);
-    double s = 0.0;
+    const real *mu = half == POS ? g->mup : (half == NEG ? g->mun : g->mu);
+    real s = 0.0;
     for (int i = 0; i < p->n; ++i) {
         const mono_t *t = &p->m[i];
         if (t->e[0] >= NMOM || t->e[1] >= NMOM || t->e[2] >= NMOM || t->e[3] > 3) abort();
@@ -1106,7 +1155,7 @@ static double moment(const poly_t *p, const maxw_t *g, int half)
 }
 
 /* vector of moments <X psi_j>, j = 0..4 */
-static void moment_psi(const poly_t *X, const maxw_t *g, int half, double out[5])
+static void moment_psi(const poly_t *X, const maxw_t *g, int half, real out[5])
 {
     for (int j = 0; j < 5; ++j) {
         poly_t psi, t;
@@ -1117,9 +1166,9 @@ static void moment_psi(const poly_t *X, const maxw_t *g, int half, double out[5]
 }
 
 /* eq. co: solve <psi psi^T> s = rhs (normalised by rho) for the slope s */
-static int solve_slope(const maxw_t *g, const double rhs[5], double s[5])
+static int solve_slope(const maxw_t *g, const real rhs[5], real s[5])
 {
-    double M[25], B[5];
+    real M[25], B[5];
     for (int j = 0; j < 5; ++j)
         for (int k = 0; k < 5; ++k) {
             poly_t a, b, t;
@@ -1135,15 +1184,15 @@ static int solve_slope(const maxw_t *g, const double rhs[5], double s[5])
 }
 
 /* A from the compatibility condition <A + a_x u + a_y v + a_z w> = 0 */
-static int solve_time_slope(const maxw_t *g, double a[3][5], double A[5])
+static int solve_time_slope(const maxw_t *g, real a[3][5], real A[5])
 {
-    double rhs[5] = {0, 0, 0, 0, 0};
+    real rhs[5] = {0, 0, 0, 0, 0};
     for (int d = 0; d < 3; ++d) {
         poly_t sp, ud, t;
         poly_slope(a[d], &sp);
         poly_velocity(d, &ud);
         poly_mul(&ud, &sp, &t);
-        double m[5];
+        real m[5];
         moment_psi(&t, g, FULL, m);
         for (int j = 0; j < 5; ++j) rhs[j] -= m[j];
     }
@@ -1167,14 +1216,14 @@ static void rotation(const double n[3], double T[3][3])
 
 /* state and gradient into the local frame: W~ = T W; derivative along local
  * axis j is sum_i T_ji d/dx_i, then T on the components */
-static void to_local(const double T[3][3], const double W[5], const double gW[15],
-                     double Wl[5], double gl[3][5])
+static void to_local(const double T[3][3], const real W[5], const real gW[15],
+                     real Wl[5], real gl[3][5])
 {
     Wl[0] = W[0];
     Wl[4] = W[4];
     for (int r = 0; r < 3; ++r) Wl[1 + r] = T[r][0] * W[1] + T[r][1] * W[2] + T[r][2] * W[3];
     for (int j = 0; j < 3; ++j) {
-        double dW[5];
+        real dW[5];
         for (int q = 0; q < 5; ++q)
             dW[q] = T[j][0] * gW[3 * q + 0] + T[j][1] * gW[3 * q + 1] + T[j][2] * gW[3 * q + 2];
         gl[j][0] = dW[0];
@@ -1184,7 +1233,7 @@ static void to_local(const double T[3][3], const double W[5], const double gW[15
 }
 
 /* back to the global frame with T^{-1} = T^T */
-static void to_global(const double T[3][3], const double Fl[5], double F[5])
+static void to_global(const double T[3][3], const real Fl[5], real F[5])
 {
     F[0] = Fl[0];
     F[4] = Fl[4];
@@ -1195,9 +1244,9 @@ static void to_global(const double T[3][3], const double Fl[5], double F[5])
  *   F0 = <u psi>, F1 = sum_d <u u_d (a_d.psi) psi>, F2 = <u (A.psi) psi>,
  *   V0 = <psi>,   V1 = sum_d <u_d (a_d.psi) psi>,   V2 = <(A.psi) psi>,
  *   Q0..Q2 = the same with the heat-flux weight in place of u psi. */
-typedef struct { double F[3][5], V[3][5], Q[3]; } parts_t;
+typedef struct { real F[3][5], V[3][5], Q[3]; } parts_t;
 
-static void part_moments(const maxw_t *g, int half, double a[3][5], const double A[5],
+static void part_moments(const maxw_t *g, int half, real a[3][5], const real A[5],
                          const poly_t *qw, parts_t *P)
 {
     poly_t one, u, sumF, sumV, As, t, tt;
@@ -1231,30 +1280,30 @@ static void part_moments(const maxw_t *g, int half, double a[3][5], const double
 /* Everything the time-dependent distribution of eq. 2nd-flux needs at one
  * point, in the local frame. */
 typedef struct {
-    double rhoc, rhol, rhor, tau, taun;
+    real rhoc, rhol, rhor, tau, taun;
     int smooth; /* eq. 2nd-smooth-flux: the equilibrium part alone */
     parts_t c, l, r;
 } interface_t;
 
-static int build_interface(const or_config *cf, const double Wl[5], double gl[3][5],
-                           const double Wr[5], double gr[3][5], double dt, interface_t *I)
+static int build_interface(const or_config *cf, const real Wl[5], real gl[3][5],
+                           const real Wr[5], real gr[3][5], double dt, interface_t *I)
 {
     maxw_t ml, mr, mc;
     if (maxwellian(cf, Wl, &ml) || maxwellian(cf, Wr, &mr)) return -1;
     /* microscopic slopes of both sides, eq. co */
-    double al[3][5], ar[3][5];
+    real al[3][5], ar[3][5];
     for (int d = 0; d < 3; ++d) {
-        double bl[5], br[5];
+        real bl[5], br[5];
         for (int q = 0; q < 5; ++q) { bl[q] = gl[d][q] / ml.rho; br[q] = gr[d][q] / mr.rho; }
         if (solve_slope(&ml, bl, al[d]) || solve_slope(&mr, br, ar[d])) return -1;
     }
     /* eq. new-equ-part: kinetic weighting of the equilibrium and its slopes */
-    double Wc[5], gc[3][5];
+    real Wc[5], gc[3][5];
     {
         poly_t one;
         poly_zero(&one);
         poly_term(&one, 1.0, 0, 0, 0, 0);
-        double mp[5], mn[5];
+        real mp[5], mn[5];
         moment_psi(&one, &ml, POS, mp);
         moment_psi(&one, &mr, NEG, mn);
         for (int q = 0; q < 5; ++q) Wc[q] = ml.rho * mp[q] + mr.rho * mn[q];
@@ -1268,16 +1317,16 @@ static int build_interface(const or_config *cf, const double Wl[5], double gl[3]
         }
     }
     if (maxwellian(cf, Wc, &mc)) return -1;
-    double ac[3][5], Ac[5], Al[5] = {0, 0, 0, 0, 0}, Ar[5] = {0, 0, 0, 0, 0};
+    real ac[3][5], Ac[5], Al[5] = {0, 0, 0, 0, 0}, Ar[5] = {0, 0, 0, 0, 0};
     for (int d = 0; d < 3; ++d) {
-        double b[5];
+        real b[5];
         for (int q = 0; q < 5; ++q) b[q] = gc[d][q] / mc.rho;
         if (solve_slope(&mc, b, ac[d])) return -1;
     }
     if (solve_time_slope(&mc, ac, Ac)) return -1;
     /* collision times (Sec. 2.2) */
-    double pl = ml.rho / (2.0 * ml.lam), pr = mr.rho / (2.0 * mr.lam), pc = mc.rho / (2.0 * mc.lam);
-    double jump = cf->c_tau * fabs((pl - pr) / (pl + pr)) * dt;
+    real pl = ml.rho / (2.0 * ml.lam), pr = mr.rho / (2.0 * mr.lam), pc = mc.rho / (2.0 * mc.lam);
+    real jump = cf->c_tau * OR_KINK_ABS((pl - pr) / (pl + pr), 0) * dt;
     if (cf->viscous) {
         I->tau = cf->mu / pc;
         I->taun = cf->mu / pc + jump;
@@ -1319,10 +1368,10 @@ static int build_interface(const or_config *cf, const double Wl[5], double gl[3]
 }
 
 /* time integral over [0, delta] of eq. 2nd-flux taken against u psi */
-static void integrated_flux(const or_config *cf, const interface_t *I, double delta, double F[5])
+static void integrated_flux(const or_config *cf, const interface_t *I, double delta, real F[5])
 {
-    double tau = I->tau, tn = I->taun;
-    double c1, c2, c3, c4, c5, c6;
+    real tau = I->tau, tn = I->taun;
+    real c1, c2, c3, c4, c5, c6;
     if (I->smooth) {
         /* eq. 2nd-smooth-flux: g^c - tau (a^c.u + A^c) g^c + t A^c g^c,
          * integrated over [0, delta] */
@@ -1331,9 +1380,9 @@ static void integrated_flux(const or_config *cf, const interface_t *I, double de
         c3 = 0.5 * delta * delta - tau * delta;
         c4 = c5 = c6 = 0.0;
     } else {
-        double e = exp(-delta / tn);
-        double E1 = tn * (1.0 - e);
-        double E2 = tn * tn * (1.0 - e) - tn * delta * e;
+        real e = exp(-delta / tn);
+        real E1 = tn * (1.0 - e);
+        real E2 = tn * tn * (1.0 - e) - tn * delta * e;
         c1 = delta - E1;
         c2 = E2 + tau * E1 - tau * delta;
         c3 = 0.5 * delta * delta - tau * delta + tau * E1;
@@ -1346,7 +1395,7 @@ static void integrated_flux(const or_config *cf, const interface_t *I, double de
                I->rhol * (c4 * I->l.F[0][q] + c5 * I->l.F[1][q] + c6 * I->l.F[2][q]) +
                I->rhor * (c4 * I->r.F[0][q] + c5 * I->r.F[1][q] + c6 * I->r.F[2][q]);
     if (cf->prandtl != 1.0) {
-        double qh = I->rhoc * (c1 * I->c.Q[0] + c2 * I->c.Q[1] + c3 * I->c.Q[2]) +
+        real qh = I->rhoc * (c1 * I->c.Q[0] + c2 * I->c.Q[1] + c3 * I->c.Q[2]) +
                     I->rhol * (c4 * I->l.Q[0] + c5 * I->l.Q[1] + c6 * I->l.Q[2]) +
                     I->rhor * (c4 * I->r.Q[0] + c5 * I->r.Q[1] + c6 * I->r.Q[2]);
         F[4] += (1.0 / cf->prandtl - 1.0) * qh;
@@ -1354,9 +1403,9 @@ static void integrated_flux(const or_config *cf, const interface_t *I, double de
 }
 
 /* the coefficients of eq. 2nd-flux at time t (un-integrated) */
-static void point_coeffs(const interface_t *I, double t, double d[6])
+static void point_coeffs(const interface_t *I, double t, real d[6])
 {
-    double tau = I->tau;
+    real tau = I->tau;
     if (I->smooth) { /* eq. 2nd-smooth-flux */
         d[0] = 1.0;
         d[1] = -tau;
@@ -1364,7 +1413,7 @@ static void point_coeffs(const interface_t *I, double t, double d[6])
         d[3] = d[4] = d[5] = 0.0;
         return;
     }
-    double e = exp(-t / I->taun);
+    real e = exp(-t / I->taun);
     d[0] = 1.0 - e;
     d[1] = (t + tau) * e - tau;
     d[2] = t - tau + tau * e;
@@ -1374,9 +1423,9 @@ static void point_coeffs(const interface_t *I, double t, double d[6])
 }
 
 /* eq. point-interface: conservative variables of the distribution at time t */
-static void point_state(const interface_t *I, double t, double Wt[5])
+static void point_state(const interface_t *I, double t, real Wt[5])
 {
-    double d[6];
+    real d[6];
     point_coeffs(I, t, d);
     for (int q = 0; q < 5; ++q)
         Wt[q] = I->rhoc * (d[0] * I->c.V[0][q] + d[1] * I->c.V[1][q] + d[2] * I->c.V[2][q]) +
@@ -1384,16 +1433,16 @@ static void point_state(const interface_t *I, double t, double Wt[5])
                 I->rhor * (d[3] * I->r.V[0][q] + d[4] * I->r.V[1][q] + d[5] * I->r.V[2][q]);
 }
 
-static void point_flux_density(const or_config *cf, const interface_t *I, double t, double F[5])
+static void point_flux_density(const or_config *cf, const interface_t *I, double t, real F[5])
 {
-    double d[6];
+    real d[6];
     point_coeffs(I, t, d);
     for (int q = 0; q < 5; ++q)
         F[q] = I->rhoc * (d[0] * I->c.F[0][q] + d[1] * I->c.F[1][q] + d[2] * I->c.F[2][q]) +
                I->rhol * (d[3] * I->l.F[0][q] + d[4] * I->l.F[1][q] + d[5] * I->l.F[2][q]) +
                I->rhor * (d[3] * I->r.F[0][q] + d[4] * I->r.F[1][q] + d[5] * I->r.F[2][q]);
     if (cf->prandtl != 1.0) {
-        double qh = I->rhoc * (d[0] * I->c.Q[0] + d[1] * I->c.Q[1] + d[2] * I->c.Q[2]) +
+        real qh = I->rhoc * (d[0] * I->c.Q[0] + d[1] * I->c.Q[1] + d[2] * I->c.Q[2]) +
                     I->rhol * (d[3] * I->l.Q[0] + d[4] * I->l.Q[1] + d[5] * I->l.Q[2]) +
                     I->rhor * (d[3] * I->r.Q[0] + d[4] * I->r.Q[1] + d[5] * I->r.Q[2]);
         F[4] += (1.0 / cf->prandtl - 1.0) * qh;
@@ -1402,17 +1451,18 @@ static void point_flux_density(const or_config *cf, const interface_t *I, double
 
 /* gas-kinetic solver at one point in the global frame; out[20] =
  * F(dt), F(dt/2), W(0), W(dt) */
-static int gks_point(const or_config *cf, const double n[3], const double Wl[5],
-                     const double gWl[15], const double Wr[5], const double gWr[15],
-                     double dt, double out[20])
+static int gks_point(const or_config *cf, const double n[3], const real Wl[5],
+                     const real gWl[15], const real Wr[5], const real gWr[15],
+                     double dt, real out[20])
 {
-    double T[3][3], wl[5], wr[5], gl[3][5], gr[3][5];
+    double T[3][3];
+    real wl[5], wr[5], gl[3][5], gr[3][5];
     rotation(n, T);
     to_local(T, Wl, gWl, wl, gl);
     to_local(T, Wr, gWr, wr, gr);
     interface_t I;
     if (build_interface(cf, wl, gl, wr, gr, dt, &I)) return -1;
-    double loc[4][5];
+    real loc[4][5];
     integrated_flux(cf, &I, dt, loc[0]);
     integrated_flux(cf, &I, 0.5 * dt, loc[1]);
     point_state(&I, 0.0, loc[2]);
@@ -1421,18 +1471,19 @@ static int gks_point(const or_config *cf, const double n[3], const double Wl[5],
     return 0;
 }
 
-int or_point_flux(const or_config *cf, const double n[3], const double Wl[5],
-                  const double gWl[15], const double Wr[5], const double gWr[15], double dt,
-                  double out[20])
+int or_point_flux(const or_config *cf, const double n[3], const real Wl[5],
+                  const real gWl[15], const real Wr[5], const real gWr[15], double dt,
+                  real out[20])
 {
     return gks_point(cf, n, Wl, gWl, Wr, gWr, dt, out);
 }
 
-int or_point_flux_density(const or_config *cf, const double n[3], const double Wl[5],
-                          const double gWl[15], const double Wr[5], const double gWr[15],
-                          double dt, double t, double out[5])
+int or_point_flux_density(const or_config *cf, const double n[3], const real Wl[5],
+                          const real gWl[15], const real Wr[5], const real gWr[15],
+                          double dt, double t, real out[5])
 {
-    double T[3][3], wl[5], wr[5], gl[3][5], gr[3][5], loc[5];
+    double T[3][3];
+    real wl[5], wr[5], gl[3][5], gr[3][5], loc[5];
     rotation(n, T);
     to_local(T, Wl, gWl, wl, gl);
     to_local(T, Wr, gWr, wr, gr);
@@ -1443,7 +1494,7 @@ int or_point_flux_density(const or_config *cf, const double n[3], const double W
     return 0;
 }
 
-int or_maxwell_moments(const or_config *cf, const double W[5], double out[54])
+int or_maxwell_moments(const or_config *cf, const real W[5], real out[54])
 {
     maxw_t g;
     if (maxwellian(cf, W, &g)) return -1;
@@ -1462,9 +1513,9 @@ int or_maxwell_moments(const or_config *cf, const double W[5], double out[54])
 /* face terms and the two-stage update (Secs. 2.1, 2.3, 3)                  */
 /* ======================================================================== */
 
-static void quad_from_coef(const double *coef, int64_t n, int64_t i, int q, qpoly_t *p)
+static void quad_from_coef(const real *coef, int64_t n, int64_t i, int q, qpoly_t *p)
 {
-    const double *o = coef + (size_t)(10 * q) * n + i;
+    const real *o = coef + (size_t)(10 * q) * n + i;
     p->c0 = o[0];
     for (int d = 0; d < 3; ++d) p->G[d] = o[(1 + d) * n];
     for (int k = 0; k < 6; ++k) p->H[k] = o[(4 + k) * n];
@@ -1476,10 +1527,10 @@ static void quad_from_coef(const double *coef, int64_t n, int64_t i, int q, qpol
  * m_g(x) = P m(P x); at a point of the wall (P x = x) this gives the ghost
  * value, and by the chain rule grad s_g = P grad s for the scalars and
  * J_g = P J P for the momentum Jacobian J_ab = dm_a/dx_b. */
-static void mirror_ghost(const double n[3], const double W[5], const double gW[15], double Wg[5],
-                         double gWg[15])
+static void mirror_ghost(const double n[3], const real W[5], const real gW[15], real Wg[5],
+                         real gWg[15])
 {
-    double P[3][3];
+    real P[3][3];
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) P[a][b] = (a == b ? 1.0 : 0.0) - 2.0 * n[a] * n[b];
     Wg[0] = W[0];
@@ -1495,7 +1546,7 @@ static void mirror_ghost(const double n[3], const double W[5], const double gW[1
         }
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
-            double t = 0.0;
+            real t = 0.0;
             for (int k = 0; k < 3; ++k)
                 for (int l = 0; l < 3; ++l) t += P[a][k] * gW[3 * (1 + k) + l] * P[l][b];
             gWg[3 * (1 + a) + b] = t;
@@ -1511,26 +1562,26 @@ static void mirror_ghost(const double n[3], const double W[5], const double gW[1
  * the same chain rule.  At rest on an adiabatic wall this is the paper's
  * (rho, -rho U, rho E) with unchanged momentum derivatives and reversed
  * density and energy derivatives. */
-static void noslip_ghost(const or_config *cf, int iso, const double uw[3], const double W[5],
-                         const double gW[15], double Wg[5], double gWg[15])
+static void noslip_ghost(const or_config *cf, int iso, const double uw[3], const real W[5],
+                         const real gW[15], real Wg[5], real gWg[15])
 {
-    double g1 = cf->gamma - 1.0;
-    double rho = W[0], U[3], Q = 0.0;
+    real g1 = cf->gamma - 1.0;
+    real rho = W[0], U[3], Q = 0.0;
     for (int d = 0; d < 3; ++d) { U[d] = W[1 + d] / rho; Q += 0.5 * U[d] * U[d]; }
-    double p = g1 * (W[4] - rho * Q), T = p / rho;
-    double Ug[3], Qg = 0.0;
+    real p = g1 * (W[4] - rho * Q), T = p / rho;
+    real Ug[3], Qg = 0.0;
     for (int d = 0; d < 3; ++d) { Ug[d] = 2.0 * uw[d] - U[d]; Qg += 0.5 * Ug[d] * Ug[d]; }
-    double Tg = iso ? 2.0 * cf->wall_T - T : T, pg = p, rhog = pg / Tg;
+    real Tg = iso ? 2.0 * cf->wall_T - T : T, pg = p, rhog = pg / Tg;
     Wg[0] = rhog;
     for (int d = 0; d < 3; ++d) Wg[1 + d] = rhog * Ug[d];
     Wg[4] = rhog * Qg + pg / g1;
     for (int j = 0; j < 3; ++j) { /* derivatives along axis j */
-        double drho = gW[j], dU[3], dQ = 0.0;
+        real drho = gW[j], dU[3], dQ = 0.0;
         for (int d = 0; d < 3; ++d) { dU[d] = (gW[3 * (1 + d) + j] - drho * U[d]) / rho; dQ += U[d] * dU[d]; }
-        double dp = g1 * (gW[12 + j] - drho * Q - rho * dQ);
-        double dT = (dp - drho * T) / rho;
-        double dTg = iso ? dT : -dT, dpg = -dp, dQg = 0.0;
-        double drhog = (dpg - dTg * rhog) / Tg;
+        real dp = g1 * (gW[12 + j] - drho * Q - rho * dQ);
+        real dT = (dp - drho * T) / rho;
+        real dTg = iso ? dT : -dT, dpg = -dp, dQg = 0.0;
+        real drhog = (dpg - dTg * rhog) / Tg;
         gWg[j] = drhog;
         for (int d = 0; d < 3; ++d) { gWg[3 * (1 + d) + j] = drhog * Ug[d] + rhog * dU[d]; dQg += Ug[d] * dU[d]; }
         gWg[12 + j] = drhog * Qg + rhog * dQg + dpg / g1;
@@ -1544,12 +1595,12 @@ static void noslip_ghost(const or_config *cf, int iso, const double uw[3], const
  * interior and the incoming u_n - 2a/(gamma-1) from the free stream, and the
  * entropy p/rho^gamma and tangential velocity from the side the flow comes
  * from.  The ghost is uniform (zero gradients). */
-static void farfield_ghost(const or_config *cf, const double n[3], const double W[5], double Wg[5],
-                           double gWg[15])
+static void farfield_ghost(const or_config *cf, const double n[3], const real W[5], real Wg[5],
+                           real gWg[15])
 {
     double g = cf->gamma, g1 = g - 1.0;
     const double *Wf = cf->farfield;
-    double ri = W[0], rf = Wf[0], Ui[3], Uf[3], ki = 0.0, kf = 0.0, uni = 0.0, unf = 0.0;
+    real ri = W[0], rf = Wf[0], Ui[3], Uf[3], ki = 0.0, kf = 0.0, uni = 0.0, unf = 0.0;
     for (int d = 0; d < 3; ++d) {
         Ui[d] = W[1 + d] / ri;
         Uf[d] = Wf[1 + d] / rf;
@@ -1558,8 +1609,8 @@ static void farfield_ghost(const or_config *cf, const double n[3], const double 
         uni += Ui[d] * n[d];
         unf += Uf[d] * n[d];
     }
-    double pi = g1 * (W[4] - ri * ki), pf = g1 * (Wf[4] - rf * kf);
-    double ai = sqrt(g * pi / ri), af = sqrt(g * pf / rf);
+    real pi = g1 * (W[4] - ri * ki), pf = g1 * (Wf[4] - rf * kf);
+    real ai = sqrt(g * pi / ri), af = sqrt(g * pf / rf);
     for (int k = 0; k < 15; ++k) gWg[k] = 0.0;
     if (uni >= ai) { /* supersonic outflow */
         for (int q = 0; q < 5; ++q) Wg[q] = W[q];
@@ -1569,9 +1620,9 @@ static void farfield_ghost(const or_config *cf, const double n[3], const double 
         for (int q = 0; q < 5; ++q) Wg[q] = Wf[q];
         return;
     }
-    double Rp = uni + 2.0 * ai / g1, Rm = unf - 2.0 * af / g1;
-    double ub = 0.5 * (Rp + Rm), ab = 0.25 * g1 * (Rp - Rm);
-    double s, Ut[3];
+    real Rp = uni + 2.0 * ai / g1, Rm = unf - 2.0 * af / g1;
+    real ub = 0.5 * (Rp + Rm), ab = 0.25 * g1 * (Rp - Rm);
+    real s, Ut[3];
     if (ub > 0.0) {
         s = pi / pow(ri, g);
         for (int d = 0; d < 3; ++d) Ut[d] = Ui[d] - uni * n[d];
@@ -1579,18 +1630,18 @@ static void farfield_ghost(const or_config *cf, const double n[3], const double 
         s = pf / pow(rf, g);
         for (int d = 0; d < 3; ++d) Ut[d] = Uf[d] - unf * n[d];
     }
-    double rb = pow(ab * ab / (g * s), 1.0 / g1), pb = rb * ab * ab / g, kb = 0.0;
+    real rb = pow(ab * ab / (g * s), 1.0 / g1), pb = rb * ab * ab / g, kb = 0.0;
     Wg[0] = rb;
     for (int d = 0; d < 3; ++d) {
-        double u = Ut[d] + ub * n[d];
+        real u = Ut[d] + ub * n[d];
         Wg[1 + d] = rb * u;
         kb += 0.5 * u * u;
     }
     Wg[4] = pb / g1 + rb * kb;
 }
 
-int or_wall_ghost(const or_config *cf, int32_t tag, const double n[3], const double uw[3], const double W[5],
-                  const double gW[15], double Wg[5], double gWg[15])
+int or_wall_ghost(const or_config *cf, int32_t tag, const double n[3], const double uw[3], const real W[5],
+                  const real gW[15], real Wg[5], real gWg[15])
 {
     if (tag == TAG_SLIP) mirror_ghost(n, W, gW, Wg, gWg);
     else if (tag == TAG_FARFIELD) farfield_ghost(cf, n, W, Wg, gWg);
@@ -1600,14 +1651,14 @@ int or_wall_ghost(const or_config *cf, int32_t tag, const double n[3], const dou
     return 0;
 }
 
-static int face_terms(or_ctx *c, const double *coef, double dt, double *out)
+static int face_terms(or_ctx *c, const real *coef, double dt, real *out, int raw)
 {
     int64_t n = c->nc, nf = c->nf;
     int err = 0;
 #pragma omp parallel for schedule(static) reduction(| : err)
     for (int64_t f = 0; f < nf; ++f) {
         int64_t L = c->fcell[f][0], R = c->fcell[f][1];
-        double acc[20];
+        real acc[20];
         for (int k = 0; k < 20; ++k) acc[k] = 0.0;
         for (int q = 0; q < 3; ++q) {
             double rl[3], rr[3];
@@ -1615,7 +1666,7 @@ static int face_terms(or_ctx *c, const double *coef, double dt, double *out)
                 rl[d] = c->fgp[f][q][d] - c->cen[L][d];
                 rr[d] = c->fgp[f][q][d] - c->fshift[f][d] - (R >= 0 ? c->cen[R][d] : 0.0);
             }
-            double Wl[5], gWl[15], Wr[5], gWr[15];
+            real Wl[5], gWl[15], Wr[5], gWr[15];
             for (int k = 0; k < 5; ++k) {
                 qpoly_t p;
                 quad_from_coef(coef, n, L, k, &p);
@@ -1629,14 +1680,19 @@ static int face_terms(or_ctx *c, const double *coef, double dt, double *out)
             }
             if (R < 0)
                 or_wall_ghost(&c->cfg, c->ftag[f], c->fnorm[f], c->fwu[f], Wl, gWl, Wr, gWr);
-            double o[20];
+            real o[20];
             if (gks_point(&c->cfg, c->fnorm[f], Wl, gWl, Wr, gWr, dt, o)) { err |= 1; continue; }
             /* eq. linear-system: F = (4 F(dt/2) - F(dt)) / dt,
              * dF/dt = 4 (F(dt) - 2 F(dt/2)) / dt^2 */
-            double w = FQ_W[q] * c->farea[f];
+            real w = FQ_W[q] * c->farea[f];
             for (int k = 0; k < 5; ++k) {
-                acc[k] += w * (4.0 * o[5 + k] - o[k]) / dt;
-                acc[5 + k] += w * 4.0 * (o[k] - 2.0 * o[5 + k]) / (dt * dt);
+                if (raw) { /* the time integrals themselves */
+                    acc[k] += w * o[k];
+                    acc[5 + k] += w * o[5 + k];
+                } else {
+                    acc[k] += w * (4.0 * o[5 + k] - o[k]) / dt;
+                    acc[5 + k] += w * 4.0 * (o[k] - 2.0 * o[5 + k]) / (dt * dt);
+                }
                 acc[10 + k] += w * o[10 + k];
                 acc[15 + k] += w * o[15 + k];
             }
@@ -1646,28 +1702,34 @@ static int face_terms(or_ctx *c, const double *coef, double dt, double *out)
     return err ? -1 : 0;
 }
 
-int or_face_terms(or_ctx *c, const double *W, const double *gW, double dt, double *out)
+int or_face_terms(or_ctx *c, const real *W, const real *gW, double dt, real *out)
 {
     or_reconstruct(c, W, gW, c->coef, c->flag, NULL);
-    return face_terms(c, c->coef, dt, out);
+    return face_terms(c, c->coef, dt, out, 0);
+}
+
+int or_face_integrals(or_ctx *c, const real *W, const real *gW, double dt, real *out)
+{
+    or_reconstruct(c, W, gW, c->coef, c->flag, NULL);
+    return face_terms(c, c->coef, dt, out, 1);
 }
 
 /* eq. flux-operator for every cell, gathered in serial face order:
  * L = -(1/|Omega|) sum (+-) |Gamma| sum_k w_k F_k, same for dL/dt, and the
  * Gauss-theorem gradient (eq. gauss-formula) of interface values Wf[5][nf] */
-static void gather(const or_ctx *c, const double *ft, const double *Wf, double *L, double *Lt,
-                   double *grad)
+static void gather(const or_ctx *c, const real *ft, const real *Wf, real *L, real *Lt,
+                   real *grad)
 {
     int64_t n = c->nc, nf = c->nf;
-    if (L) memset(L, 0, sizeof(double) * 5 * n);
-    if (Lt) memset(Lt, 0, sizeof(double) * 5 * n);
-    if (grad) memset(grad, 0, sizeof(double) * 15 * n);
+    if (L) memset(L, 0, sizeof(real) * 5 * n);
+    if (Lt) memset(Lt, 0, sizeof(real) * 5 * n);
+    if (grad) memset(grad, 0, sizeof(real) * 15 * n);
     for (int64_t f = 0; f < nf; ++f) {
         int64_t side[2] = {c->fcell[f][0], c->fcell[f][1]};
         for (int s = 0; s < 2; ++s) {
             int64_t i = side[s];
             if (i < 0) continue;
-            double sg = s == 0 ? 1.0 : -1.0;
+            real sg = s == 0 ? 1.0 : -1.0;
             for (int q = 0; q < 5; ++q) {
                 if (L) L[q * n + i] -= sg * ft[(size_t)q * nf + f];
                 if (Lt) Lt[q * n + i] -= sg * ft[(size_t)(5 + q) * nf + f];
@@ -1678,7 +1740,7 @@ static void gather(const or_ctx *c, const double *ft, const double *Wf, double *
         }
     }
     for (int64_t i = 0; i < n; ++i) {
-        double iv = 1.0 / c->vol[i];
+        real iv = 1.0 / c->vol[i];
         for (int q = 0; q < 5; ++q) {
             if (L) L[q * n + i] *= iv;
             if (Lt) Lt[q * n + i] *= iv;
@@ -1687,22 +1749,22 @@ static void gather(const or_ctx *c, const double *ft, const double *Wf, double *
     }
 }
 
-int or_stage(or_ctx *c, int stage, double dt, double *W, double *gW)
+int or_stage(or_ctx *c, int stage, double dt, real *W, real *gW)
 {
     int64_t n = c->nc, nf = c->nf;
     if (stage != 1 && stage != 2) return -1;
     if (stage == 2 && !c->have_stage1) return -1;
     or_reconstruct(c, W, gW, c->coef, c->flag, NULL);
-    if (face_terms(c, c->coef, dt, c->fterm)) return -2;
-    double *Wf = (double *)malloc(sizeof(double) * 5 * nf);
-    double *L = (double *)malloc(sizeof(double) * 5 * n);
-    double *Lt = (double *)malloc(sizeof(double) * 5 * n);
+    if (face_terms(c, c->coef, dt, c->fterm, 0)) return -2;
+    real *Wf = (real *)malloc(sizeof(real) * 5 * nf);
+    real *L = (real *)malloc(sizeof(real) * 5 * n);
+    real *Lt = (real *)malloc(sizeof(real) * 5 * n);
     if (stage == 1) {
         /* eq. step-du with a linear-in-time f: f* = (f(0) + f(dt)) / 2 */
         for (int64_t f = 0; f < nf; ++f)
             for (int q = 0; q < 5; ++q) {
-                double w0 = c->fterm[(size_t)(10 + q) * nf + f];
-                double w1 = c->fterm[(size_t)(15 + q) * nf + f];
+                real w0 = c->fterm[(size_t)(10 + q) * nf + f];
+                real w1 = c->fterm[(size_t)(15 + q) * nf + f];
                 c->FW0[(size_t)q * nf + f] = w0;
                 Wf[(size_t)q * nf + f] = 0.5 * (w0 + w1);
             }
@@ -1732,7 +1794,13 @@ int or_stage(or_ctx *c, int stage, double dt, double *W, double *gW)
     return 0;
 }
 
-int or_step(or_ctx *c, double dt, double *W, double *gW)
+int or_last_face_terms(const or_ctx *c, real *out)
+{
+    memcpy(out, c->fterm, sizeof(real) * 20 * (size_t)c->nf);
+    return 0;
+}
+
+int or_step(or_ctx *c, double dt, real *W, real *gW)
 {
     int rc = or_stage(c, 1, dt, W, gW);
     if (rc) return rc;
@@ -1740,32 +1808,47 @@ int or_step(or_ctx *c, double dt, double *W, double *gW)
 }
 
 /* eq. time-step */
-double or_compute_dt(const or_ctx *c, const double *W, double cfl)
+double or_compute_dt(const or_ctx *c, const real *W, double cfl)
 {
     int64_t n = c->nc;
     const or_config *cf = &c->cfg;
-    double best = INFINITY;
+    real best = INFINITY;
     for (int64_t i = 0; i < n; ++i) {
-        double rho = W[i], u = W[n + i] / rho, v = W[2 * n + i] / rho, w = W[3 * n + i] / rho;
-        double p = (cf->gamma - 1.0) * (W[4 * n + i] - 0.5 * rho * (u * u + v * v + w * w));
-        double a = sqrt(cf->gamma * p / rho);
-        double s = c->dr[i] / (sqrt(u * u + v * v + w * w) + a);
+        real rho = W[i], u = W[n + i] / rho, v = W[2 * n + i] / rho, w = W[3 * n + i] / rho;
+        real p = (cf->gamma - 1.0) * (W[4 * n + i] - 0.5 * rho * (u * u + v * v + w * w));
+        real a = sqrt(cf->gamma * p / rho);
+        real s = c->dr[i] / (sqrt(u * u + v * v + w * w) + a);
         if (s < best) best = s;
         if (cf->viscous && cf->mu > 0.0) {
-            double nu = cf->mu / rho;
-            double sv = c->dr[i] * c->dr[i] / (3.0 * nu);
+            real nu = cf->mu / rho;
+            real sv = c->dr[i] * c->dr[i] / (3.0 * nu);
             if (sv < best) best = sv;
         }
     }
-    return cfl * best;
+    return cfl * OR_VALUE(best);
 }
 
-void or_conservation_sums(const or_ctx *c, const double *W, double out[5])
+void or_conservation_sums(const or_ctx *c, const real *W, real out[5])
 {
     int64_t n = c->nc;
     for (int q = 0; q < 5; ++q) {
-        double s = 0.0;
+        real s = 0.0;
         for (int64_t i = 0; i < n; ++i) s += c->vol[i] * W[q * n + i];
         out[q] = s;
     }
 }
+
+#ifdef OR_TANGENT
+/* tangent build only: the kink distance eps, and the counts per site and
+ * direction since the last reset (out[2][OR_NDIR]) */
+extern "C" int or_tangent_ndir(void) { return OR_NDIR; }
+extern "C" void or_tangent_set_kink_eps(double eps) { or_kink_eps = eps; }
+extern "C" void or_tangent_kinks(long *out, int reset)
+{
+    for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < OR_NDIR; ++k) {
+            out[s * OR_NDIR + k] = or_kinks[s][k];
+            if (reset) or_kinks[s][k] = 0;
+        }
+}
+#endif

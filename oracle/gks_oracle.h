@@ -17,6 +17,12 @@
 
 #include <stdint.h>
 
+/* arithmetic type of state arrays: double (the tangent build of the oracle
+ * defines it as its dual type) */
+#ifndef OR_REAL
+#define OR_REAL double
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -39,7 +45,18 @@ typedef struct {
                          eq. 2nd-smooth-flux */
     double wall_T;    /* temperature p / rho of isothermal no-slip walls */
     double farfield[5]; /* free-stream state (conservative) of far-field faces */
+    int32_t weno_reading; /* 0: the readings the library follows.  Other bits select alternative
+                             readings of Secs. 4.2-4.3, used only to compare against the paper's
+                             Tables 2-3: OR_READ_* below */
 } or_config;
+
+/* alternative readings of the nonlinear weights (bits of or_config.weno_reading) */
+#define OR_READ_POW1 1      /* power 1 instead of 2 in omega_{m,n} (eq. non-linear-weight) */
+#define OR_READ_POW1ST2 2   /* power 2 instead of 1 in omega^{1st}_j (eq. p0-non-linear-weight) */
+#define OR_READ_B0VOL 4     /* |Delta_0| in beta_{0,j} read as the volume |Omega_0| instead of |Omega_0|^(2/3) */
+#define OR_READ_MIXED2 8    /* mixed second derivatives counted twice in beta_2 (eq. smooth-indicator) */
+#define OR_READ_BETA_LOWER 16 /* beta_1, beta_2 of the hierarchical p_1, p_2 instead of P^1, P^2 */
+#define OR_READ_SIGMA1 32   /* sigma without the power 4/3 */
 
 typedef struct or_ctx or_ctx;
 
@@ -64,46 +81,51 @@ int or_face_geometry(const or_ctx *ctx, double *area, double *normal, double *gp
 
 /* The ghost state of a wall point (tag 2, 3, 4 or 5; n the outward unit
  * normal, uw the wall velocity), global frame. */
-int or_wall_ghost(const or_config *cfg, int32_t tag, const double n[3], const double uw[3], const double W[5],
-                  const double gW[15], double Wg[5], double gWg[15]);
+int or_wall_ghost(const or_config *cfg, int32_t tag, const double n[3], const double uw[3], const OR_REAL W[5],
+                  const OR_REAL gW[15], OR_REAL Wg[5], OR_REAL gWg[15]);
 
 /* Reconstruction step 1: slopes b[15][n] (component c, direction d at 3c+d).
  * A cell with fewer than three neighbours (at walls) takes its own averaged
  * gradient gW (zero if gW is NULL); components constrained at no-slip faces
  * take the constrained fit. */
-int or_slopes(or_ctx *ctx, const double *W, const double *gW, double *b);
+int or_slopes(or_ctx *ctx, const OR_REAL *W, const OR_REAL *gW, OR_REAL *b);
 /* Reconstruction step 2: final polynomial R(x) = c0 + G.r + 1/2 r^T H r about
  * the centroid, coef[50][n] = per component (c0, Gx, Gy, Gz, Hxx, Hyy, Hzz,
  * Hxy, Hxz, Hyz); flag[n] = 1 where the positivity fallback fired.
  * p2coef (optional, same layout) receives the linear P^2 fit. */
-int or_reconstruct(or_ctx *ctx, const double *W, const double *gW, double *coef,
-                   int32_t *flag, double *p2coef);
+int or_reconstruct(or_ctx *ctx, const OR_REAL *W, const OR_REAL *gW, OR_REAL *coef,
+                   int32_t *flag, OR_REAL *p2coef);
 /* Face terms for a state (W, gW) and step dt: out[20][nf] =
  * |Gamma| sum_k w_k of (F_k (5), dF_k/dt (5), W_k(0) (5), W_k(dt) (5)),
  * in the global frame, normal outward from the owner. */
-int or_face_terms(or_ctx *ctx, const double *W, const double *gW, double dt, double *out);
+int or_face_terms(or_ctx *ctx, const OR_REAL *W, const OR_REAL *gW, double dt, OR_REAL *out);
+/* The same with the time integrals before the fit of eq. linear-system:
+ * out[20][nf] = |Gamma| sum_k w_k of (F_k(dt), F_k(dt/2), W_k(0), W_k(dt)). */
+int or_face_integrals(or_ctx *ctx, const OR_REAL *W, const OR_REAL *gW, double dt, OR_REAL *out);
 
 /* One stage of the two-stage fourth-order step, in place on (W, gW).
  * Stage 1 expects W^n and leaves W*; stage 2 expects W* and leaves W^{n+1}. */
-int or_stage(or_ctx *ctx, int stage, double dt, double *W, double *gW);
-int or_step(or_ctx *ctx, double dt, double *W, double *gW);
-double or_compute_dt(const or_ctx *ctx, const double *W, double cfl);
-void or_conservation_sums(const or_ctx *ctx, const double *W, double out[5]);
+int or_stage(or_ctx *ctx, int stage, double dt, OR_REAL *W, OR_REAL *gW);
+int or_step(or_ctx *ctx, double dt, OR_REAL *W, OR_REAL *gW);
+/* The face terms (layout of or_face_terms) of the last or_stage call. */
+int or_last_face_terms(const or_ctx *ctx, OR_REAL *out);
+double or_compute_dt(const or_ctx *ctx, const OR_REAL *W, double cfl);
+void or_conservation_sums(const or_ctx *ctx, const OR_REAL *W, OR_REAL out[5]);
 
 /* Gas-kinetic solver at one interface point, global frame.  n: unit normal,
  * Wl/Wr: states, gWl/gWr[15] gradients (3c+d).  out[20] = F(dt), F(dt/2)
  * (time integrals of the flux density), W(0), W(dt). */
-int or_point_flux(const or_config *cfg, const double n[3], const double Wl[5],
-                  const double gWl[15], const double Wr[5], const double gWr[15],
-                  double dt, double out[20]);
+int or_point_flux(const or_config *cfg, const double n[3], const OR_REAL Wl[5],
+                  const OR_REAL gWl[15], const OR_REAL Wr[5], const OR_REAL gWr[15],
+                  double dt, OR_REAL out[20]);
 /* Flux density F(t) (not integrated) at the same point, out[5]. */
-int or_point_flux_density(const or_config *cfg, const double n[3], const double Wl[5],
-                          const double gWl[15], const double Wr[5], const double gWr[15],
-                          double dt, double t, double out[5]);
+int or_point_flux_density(const or_config *cfg, const double n[3], const OR_REAL Wl[5],
+                          const OR_REAL gWl[15], const OR_REAL Wr[5], const OR_REAL gWr[15],
+                          double dt, double t, OR_REAL out[5]);
 /* Normalised velocity moments of the Maxwellian of W (local frame as given):
  * out[0..9] <u^k>, out[10..19] <u^k>_{u>0}, out[20..29] <u^k>_{u<0},
  * out[30..39] <v^k>, out[40..49] <w^k>, out[50..53] <xi^{2k}>. */
-int or_maxwell_moments(const or_config *cfg, const double W[5], double out[54]);
+int or_maxwell_moments(const or_config *cfg, const OR_REAL W[5], OR_REAL out[54]);
 /* Five-point volume rule and three-point face rule, as used (reference
  * elements): points[5][3] weights[5]; points[3][2] weights[3]. */
 void or_volume_rule(double pts[15], double w[5]);

@@ -40,7 +40,7 @@ EXPORTS = ("gks_default_config", "gks_create", "gks_destroy", "gks_set_stream",
            "gks_compute_dt", "gks_stage", "gks_step", "gks_step_cfl", "gks_last_dt",
            "gks_adjoint_workspace_bytes", "gks_bind_adjoint_workspace", "gks_step_adjoint",
            "gks_read_state",
-           "gks_conservation_sums", "gks_debug_reconstruct", "gks_debug_face_terms",
+           "gks_conservation_sums", "gks_debug_reconstruct", "gks_debug_face_terms", "gks_debug_flux_integrals",
            "gks_timing_enable", "gks_timing_read", "gks_flux_op_count", "gks_flux_point_check",
            "gks_flux_face_check", "gks_weno_check", "gks_wall_ghost_check", "gks_last_error",
            "gks_strerror")
@@ -110,6 +110,7 @@ def load_library(path: str = LIB_PATH):
         "gks_conservation_sums": (S, [P, P]),
         "gks_debug_reconstruct": (S, [P, P, P, P, I32]),
         "gks_debug_face_terms": (S, [P, D, P, I32]),
+        "gks_debug_flux_integrals": (S, [P, D, P, I32]),
         "gks_timing_enable": (S, [P, I32]),
         "gks_timing_read": (S, [P, P, P, I32]),
         "gks_flux_op_count": (S, [P, P]),
@@ -280,6 +281,23 @@ class Solver:
     def _dev(self, a):
         return (not isinstance(a, np.ndarray)) and a.is_cuda
 
+    def _enter(self):
+        """Device inputs were produced on torch's current stream: the
+        library's stream waits for it before its work is enqueued."""
+        cur = self._torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+        return cur
+
+    def _leave(self, cur, tensors):
+        """The library's work on device tensors is enqueued on its own stream:
+        the caching allocator keeps them until that work ends, and torch's
+        current stream waits for it before the tensors are used there."""
+        if cur != self.stream:
+            for t in tensors:
+                t.record_stream(self.stream)
+            cur.wait_stream(self.stream)
+
     # -- the C interface -----------------------------------------------------
     def init(self, W, gW):
         """W[5, n], gW[15, n]: float64 numpy arrays or CUDA tensors."""
@@ -292,8 +310,11 @@ class Solver:
             gW = np.ascontiguousarray(gW, np.float64)
         if tuple(W.shape) != (5, self.nc) or tuple(gW.shape) != (15, self.nc):
             raise ValueError("W must be [5, n_cell] and gW [15, n_cell]")
+        cur = self._enter() if on_dev else None
         self._check(self.L.gks_init(self._h, ctypes.c_void_p(_ptr(W)), ctypes.c_void_p(_ptr(gW)),
                                     1 if on_dev else 0), "init")
+        if on_dev:
+            self._leave(cur, (W, gW))
 
     def bind_adjoint(self):
         """Allocate and bind the adjoint workspace (once)."""
@@ -318,9 +339,11 @@ class Solver:
             args.append(a.contiguous().to(t.float64))
         Wo = t.empty((5, self.nc), dtype=t.float64, device=self.device)
         Go = t.empty((15, self.nc), dtype=t.float64, device=self.device)
+        cur = self._enter()
         self._check(self.L.gks_step_adjoint(self._h, float(dt), *(ctypes.c_void_p(a.data_ptr()) for a in args),
                                             ctypes.c_void_p(Wo.data_ptr()), ctypes.c_void_p(Go.data_ptr())),
                     "step_adjoint")
+        self._leave(cur, args + [Wo, Go])
         return Wo, Go
 
     def compute_dt(self, cfl: float) -> float:
@@ -351,9 +374,12 @@ class Solver:
         else:
             W = np.empty((5, self.nc))
             gW = np.empty((15, self.nc))
+        cur = self._enter() if device else None
         self._check(self.L.gks_read_state(self._h, ctypes.c_void_p(_ptr(W)),
                                           ctypes.c_void_p(_ptr(gW)), 1 if device else 0),
                     "read_state")
+        if device:
+            self._leave(cur, (W, gW))
         return W, gW
 
     def conservation_sums(self):
@@ -389,4 +415,12 @@ class Solver:
         self._check(self.L.gks_debug_face_terms(self._h, float(dt),
                                                 ctypes.c_void_p(out.ctypes.data), 0),
                     "debug_face_terms")
+        return out
+
+    def debug_flux_integrals(self, dt: float):
+        """[20, n_face]: |Gamma| sum_k w_k of F_k(dt), F_k(dt/2), W_k(0), W_k(dt)."""
+        out = np.empty((20, self.nf))
+        self._check(self.L.gks_debug_flux_integrals(self._h, float(dt),
+                                                    ctypes.c_void_p(out.ctypes.data), 0),
+                    "debug_flux_integrals")
         return out

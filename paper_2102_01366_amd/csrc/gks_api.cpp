@@ -1432,7 +1432,7 @@ gks_status gks_debug_reconstruct(gks_ctx *c, double *slopes, double *coef, int32
     return GKS_OK;
 }
 
-gks_status gks_debug_face_terms(gks_ctx *c, double dt, double *out, int32_t on_device)
+static gks_status debug_faces(gks_ctx *c, double dt, double *out, int32_t on_device, int mode)
 {
     gks_status st = ready(c, true);
     if (st) return st;
@@ -1440,7 +1440,7 @@ gks_status gks_debug_face_terms(gks_ctx *c, double dt, double *out, int32_t on_d
     const hipStream_t s = c->stream;
     HIP_TRY(c, slopes_step(c->dm, c->ds, c->par, c->fp32, s));
     HIP_TRY(c, reconstruct_step(c->dm, c->ds, c->par, c->fp32, s));
-    HIP_TRY(c, gks::launch_flux(c->dm, c->ds, c->par, dt, nullptr, gks::FLUX_DEBUG, c->fp32, s));
+    HIP_TRY(c, gks::launch_flux(c->dm, c->ds, c->par, dt, nullptr, mode, c->fp32, s));
     c->stage1_done = false;  // the face buffers of a pending stage 1 are overwritten
     const int nf = c->nf;
     const void *src[4] = {c->ds.FF, c->ds.FT, c->ds.FW0, c->ds.FWs};
@@ -1450,6 +1450,16 @@ gks_status gks_debug_face_terms(gks_ctx *c, double dt, double *out, int32_t on_d
     }
     HIP_TRY(c, hipStreamSynchronize(s));
     return GKS_OK;
+}
+
+gks_status gks_debug_face_terms(gks_ctx *c, double dt, double *out, int32_t on_device)
+{
+    return debug_faces(c, dt, out, on_device, gks::FLUX_DEBUG);
+}
+
+gks_status gks_debug_flux_integrals(gks_ctx *c, double dt, double *out, int32_t on_device)
+{
+    return debug_faces(c, dt, out, on_device, gks::FLUX_DEBUG_RAW);
 }
 
 gks_status gks_timing_enable(gks_ctx *c, int32_t on)

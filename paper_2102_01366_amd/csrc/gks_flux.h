@@ -665,7 +665,7 @@ struct WallBC {
 template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR, bool SMOOTH = false>
 GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, const R r[3], const R dv[3],
                               const CoefL &cl, const CoefR &cr, R acc[4][5], bool wall = false,
-                              const WallBC<R> *bc = nullptr)
+                              const WallBC<R> *bc = nullptr, bool raw = false)
 {
     const R w = area * R(1.0 / 3.0);
     R T[3][3];
@@ -703,8 +703,13 @@ GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, con
     const R idt = R(1) / dt;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        acc[0][q] = w * (R(4) * Fh[q] - F1[q]) * idt;
-        acc[1][q] = w * R(4) * (F1[q] - R(2) * Fh[q]) * (idt * idt);
+        if (raw) {  // the time integrals F(dt), F(dt/2) themselves, before the fit
+            acc[0][q] = w * F1[q];
+            acc[1][q] = w * Fh[q];
+        } else {
+            acc[0][q] = w * (R(4) * Fh[q] - F1[q]) * idt;
+            acc[1][q] = w * R(4) * (F1[q] - R(2) * Fh[q]) * (idt * idt);
+        }
         acc[2][q] = w * W0[q];
         acc[3][q] = w * W1[q];
     }

@@ -38,9 +38,11 @@ constexpr int kFacesPerBlock = kFacesPerWave * (kFluxThreads / 64);
 
 // WALL: the launch over the wall faces [nfi, nf) (a ghost on the right, as
 // the face's wall tag says), else over the interior faces [0, nfi).  SMOOTH: eq. 2nd-smooth-flux.
+// raw (debug launches only): write |Gamma| sum_k w_k F_k(dt) and F_k(dt/2)
+// instead of the fitted flux and its time derivative.
 template <typename R, int MODE, bool VISC, bool PRFIX, bool WALL, bool SMOOTH>
 __global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(DevMesh m, DevState s, Params p, double dt_,
-                                                                             const double *dtp)
+                                                                             const double *dtp, int raw)
 {
     const int nf = m.nf, n = m.nc;
     const R dt = R(dtp ? *dtp : dt_);
@@ -72,7 +74,8 @@ __global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(
             for (int d = 0; d < 3; ++d) bc.u[d] = static_cast<const R *>(m.wvel)[(size_t)d * nw + w];
         }
         gauss_point_terms<R, VISC, PRFIX, DevCoef<R>, DevCoef<R>, SMOOTH>(
-            p, dt, nrm, area, r, dv, DevCoef<R>{coef, n, L}, DevCoef<R>{coef, n, WALL ? L : Rc}, acc, WALL, &bc);
+            p, dt, nrm, area, r, dv, DevCoef<R>{coef, n, L}, DevCoef<R>{coef, n, WALL ? L : Rc}, acc, WALL, &bc,
+            MODE == FLUX_DEBUG && raw != 0);
     } else {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -111,28 +114,28 @@ __global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(
 
 template <typename R, int MODE, bool WALL, bool SMOOTH>
 void launch_flux_part(const DevMesh &m, const DevState &s, const Params &p, double dt, const double *dtp,
-                      hipStream_t st)
+                      int raw, hipStream_t st)
 {
     const int nfaces = WALL ? m.nf - m.nfi : m.nfi;
     if (nfaces <= 0) return;
     const dim3 grid((unsigned)((nfaces + kFacesPerBlock - 1) / kFacesPerBlock)), block(kFluxThreads);
     const bool visc = p.viscous != 0, prfix = p.prandtl != 1.0;
     if (visc && prfix)
-        hipLaunchKernelGGL((flux_kernel<R, MODE, true, true, WALL, SMOOTH>), grid, block, 0, st, m, s, p, dt, dtp);
+        hipLaunchKernelGGL((flux_kernel<R, MODE, true, true, WALL, SMOOTH>), grid, block, 0, st, m, s, p, dt, dtp, raw);
     else if (visc)
-        hipLaunchKernelGGL((flux_kernel<R, MODE, true, false, WALL, SMOOTH>), grid, block, 0, st, m, s, p, dt, dtp);
+        hipLaunchKernelGGL((flux_kernel<R, MODE, true, false, WALL, SMOOTH>), grid, block, 0, st, m, s, p, dt, dtp, raw);
     else if (prfix)
-        hipLaunchKernelGGL((flux_kernel<R, MODE, false, true, WALL, SMOOTH>), grid, block, 0, st, m, s, p, dt, dtp);
+        hipLaunchKernelGGL((flux_kernel<R, MODE, false, true, WALL, SMOOTH>), grid, block, 0, st, m, s, p, dt, dtp, raw);
     else
-        hipLaunchKernelGGL((flux_kernel<R, MODE, false, false, WALL, SMOOTH>), grid, block, 0, st, m, s, p, dt, dtp);
+        hipLaunchKernelGGL((flux_kernel<R, MODE, false, false, WALL, SMOOTH>), grid, block, 0, st, m, s, p, dt, dtp, raw);
 }
 
 template <typename R, int MODE, bool SMOOTH>
 void launch_flux_mode(const DevMesh &m, const DevState &s, const Params &p, double dt, const double *dtp,
-                      hipStream_t st)
+                      int raw, hipStream_t st)
 {
-    launch_flux_part<R, MODE, false, SMOOTH>(m, s, p, dt, dtp, st);
-    launch_flux_part<R, MODE, true, SMOOTH>(m, s, p, dt, dtp, st);
+    launch_flux_part<R, MODE, false, SMOOTH>(m, s, p, dt, dtp, raw, st);
+    launch_flux_part<R, MODE, true, SMOOTH>(m, s, p, dt, dtp, raw, st);
 }
 
 template <typename R, bool SMOOTH>
@@ -140,11 +143,11 @@ void launch_flux_kind(const DevMesh &m, const DevState &s, const Params &p, doub
                       int mode, hipStream_t st)
 {
     if (mode == FLUX_STAGE1)
-        launch_flux_mode<R, FLUX_STAGE1, SMOOTH>(m, s, p, dt, dtp, st);
+        launch_flux_mode<R, FLUX_STAGE1, SMOOTH>(m, s, p, dt, dtp, 0, st);
     else if (mode == FLUX_STAGE2)
-        launch_flux_mode<R, FLUX_STAGE2, SMOOTH>(m, s, p, dt, dtp, st);
+        launch_flux_mode<R, FLUX_STAGE2, SMOOTH>(m, s, p, dt, dtp, 0, st);
     else
-        launch_flux_mode<R, FLUX_DEBUG, SMOOTH>(m, s, p, dt, dtp, st);
+        launch_flux_mode<R, FLUX_DEBUG, SMOOTH>(m, s, p, dt, dtp, mode == FLUX_DEBUG_RAW, st);
 }
 
 template <typename R>

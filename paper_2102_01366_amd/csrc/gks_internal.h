@@ -130,7 +130,9 @@ struct DevState {
     int *nonphys;           // [1] set when a cell average is non-physical
 };
 
-enum FluxMode { FLUX_STAGE1 = 0, FLUX_STAGE2 = 1, FLUX_DEBUG = 2 };
+// FLUX_DEBUG writes all four face terms; FLUX_DEBUG_RAW the same with the
+// un-fitted time integrals F(dt), F(dt/2) in place of F and dF/dt
+enum FluxMode { FLUX_STAGE1 = 0, FLUX_STAGE2 = 1, FLUX_DEBUG = 2, FLUX_DEBUG_RAW = 3 };
 
 // kernel launchers (gks_kernels.hip); fp32 selects the FP32-bulk form;
 // each returns the hipError_t of the launch

@@ -418,6 +418,28 @@ def taylor_green_field(gamma: float = 1.4, mach: float = 0.1, u0: float = 1.0,
     return f
 
 
+def bump_stream_field(gamma: float = 1.4, speed: float = 0.3, center=(2.0, 0.0, 0.0), width: float = 0.3):
+    """Uniform stream rho = 1, U = (speed, 0, 0), p = 1/gamma with a smooth
+    density and pressure bump exp(-|x - c|^2 / width) (rho + 0.1 b, p + 0.05 b)
+    around c: a disturbed free stream for flows past the sphere."""
+    c = np.asarray(center, np.float64)
+
+    def f(X):
+        x, y, z = X[..., 0] - c[0], X[..., 1] - c[1], X[..., 2] - c[2]
+        b = np.exp(-(x * x + y * y + z * z) / width)
+        db = [-2.0 * r / width * b for r in (x, y, z)]
+        rho = 1.0 + 0.1 * b
+        p = 1.0 / gamma + 0.05 * b
+        u = speed * np.ones_like(x)
+        zero = np.zeros_like(x)
+        Q = np.stack([rho, rho * u, zero, zero, p / (gamma - 1) + 0.5 * rho * u * u])
+        dQ = np.stack([np.stack([0.1 * g for g in db]), np.stack([0.1 * g * speed for g in db]),
+                       np.stack([zero] * 3), np.stack([zero] * 3),
+                       np.stack([0.05 * g / (gamma - 1) + 0.5 * speed * speed * 0.1 * g for g in db])])
+        return Q, dQ
+    return f
+
+
 def cell_averages(mesh: TetMesh, field, npts: int = 6, chunk: int = 65536):
     """Exact (to quadrature) cell averages of a field and of its gradient.
 
@@ -545,3 +567,19 @@ def blast_cell_averages(mesh: TetMesh, gamma: float = 1.4, radius: float = 0.1, 
         acc += an[:, :, None] * Wp.mean(axis=1)[:, None, :]
     gW = (acc / vol[:, None, None]).transpose(2, 1, 0).reshape(15, nc)
     return W, gW
+
+
+def rms_directions(W: np.ndarray, gW: np.ndarray, ndir: int, seed: int):
+    """`ndir` seeded Gaussian directions in the space of (W, gW), each row
+    scaled by the RMS of that row of the state (gradient rows: plus 1e-3, so
+    that a row that vanishes still moves).  Returns dW[ndir][5][n],
+    dgW[ndir][15][n]."""
+    rng = np.random.default_rng(seed)
+    sW = np.sqrt((W ** 2).mean(axis=1, keepdims=True))
+    sG = np.sqrt((gW ** 2).mean(axis=1, keepdims=True)) + 1e-3
+    dW = np.empty((ndir,) + W.shape)
+    dG = np.empty((ndir,) + gW.shape)
+    for k in range(ndir):
+        dW[k] = rng.standard_normal(W.shape) * sW
+        dG[k] = rng.standard_normal(gW.shape) * sG
+    return dW, dG

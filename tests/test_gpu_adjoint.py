@@ -15,7 +15,9 @@ and take a step of 1e-7 where the WENO weights are active, so that no kink
 lies within the step; with smooth weights (eps_weno = 1) and the jump term
 off, the step map is smooth and the checks use 1e-6.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -156,6 +158,42 @@ def test_adjoint_matches_oracle_finite_differences():
         fd = (J_oracle(W + eps * vW, gW + eps * vG) - J_oracle(W - eps * vW, gW - eps * vG)) / (2 * eps)
         ad = float((Wr.grad.cpu().numpy() * vW).sum() + (Gr.grad.cpu().numpy() * vG).sum())
         assert abs(fd - ad) <= 1e-5 * abs(ad), (fd, ad)
+
+
+TANGENT_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adjoint_tangent_c0.json")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_adjoint_matches_tangent_oracle(precision):
+    """The FP64 CPU reference gradient: directional derivatives dJ.v_k of the
+    oracle's tangent build (forward-mode dual numbers, exact up to rounding;
+    golden/adjoint_tangent_c0.json, written by golden/adjoint_tangent.py from
+    the oracle alone) on the 3,072-cell unit cube, Taylor-Green vortex of
+    period 1, Re 1600, 50 steps with the paper's default collision-time jump
+    and WENO weights (kinks active), 16 RMS-scaled directions.  The GPU's
+    adjoint gradient through the autograd rollout, with the oracle's time
+    steps, agrees to 1e-8 relative in FP64; the FP32-bulk form to 1e-3."""
+    from paper_2102_01366_amd.autograd import rollout
+    gold = json.load(open(TANGENT_GOLDEN))
+    ell = 1.0 / (2.0 * math.pi)
+    m = I.kuhn_cube_mesh(8, 1.0, 0.1, 0, True)
+    W, gW = I.cell_averages(m, I.taylor_green_field(mach=0.1, ell=ell))
+    prec = G.GKS_FP64 if precision == "fp64" else G.GKS_FP32_BULK
+    s = G.Solver(m, G.default_config(precision=prec, **gold["config"]))
+    vol = torch.from_numpy(_volumes(m)).to(DEV)
+    Wr = torch.from_numpy(W).to(DEV).requires_grad_(True)
+    Gr = torch.from_numpy(gW).to(DEV).requires_grad_(True)
+    J = _ke(rollout(s, Wr, Gr, gold["dts"])[0], vol)
+    J.backward()
+    tol_J, tol = (1e-12, 1e-8) if precision == "fp64" else (1e-6, 1e-3)
+    assert abs(J.item() - gold["J"]) <= tol_J * abs(gold["J"]), (J.item(), gold["J"])
+    dW, dG = I.rms_directions(W, gW, gold["ndir"], gold["direction_seed"])
+    gWn, gGn = Wr.grad.cpu().numpy(), Gr.grad.cpu().numpy()
+    errs = []
+    for k, ref in enumerate(gold["jvp"]):
+        ad = float((gWn * dW[k]).sum() + (gGn * dG[k]).sum())
+        errs.append(abs(ad - ref) / abs(ref))
+    assert max(errs) <= tol, errs
 
 
 def test_adjoint_is_bitwise_reproducible_and_leaves_state():

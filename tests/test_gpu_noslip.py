@@ -16,7 +16,7 @@ import oracle
 import paper_2102_01366_amd as G
 from paper_2102_01366_amd import inputs as I
 
-from test_gpu_parity import COEF_GROUPS, FACE_GROUPS, face_floors, GW_GROUPS, W_GROUPS, assert_parity, gradient_floors
+from test_gpu_parity import COEF_GROUPS, GW_GROUPS, W_GROUPS, assert_parity, check_face_terms, check_steps
 
 pytestmark = pytest.mark.gpu
 
@@ -75,25 +75,13 @@ def test_noslip_reconstruction(name):
 def test_noslip_face_terms(name):
     m, s, orc, W, gW = _pair(name)
     s.init(W, gW)
-    dt = orc.compute_dt(W, 0.5)
-    ref = orc.face_terms(W, gW, dt)
-    assert_parity(s.debug_face_terms(dt), ref, FACE_GROUPS, "face terms", floors=face_floors(ref, dt))
+    check_face_terms(s, orc, W, gW, orc.compute_dt(W, 0.5))
 
 
 @pytest.mark.parametrize("name", CASES)
 def test_noslip_steps(name):
     m, s, orc, W, gW = _pair(name)
-    s.init(W, gW)
-    Wo, gWo = W, gW
-    for step in range(2):
-        dt = orc.compute_dt(Wo, 0.5)
-        for stage in (1, 2):
-            s.stage(stage, dt)
-            Wo, gWo = orc.stage(stage, dt, Wo, gWo)
-            Wg, gWg = s.read_state()
-            assert_parity(Wg, Wo, W_GROUPS, f"W step {step} stage {stage}")
-            assert_parity(gWg, gWo, GW_GROUPS, f"gW step {step} stage {stage}",
-                          floors=gradient_floors(Wo, orc))
+    check_steps(m, s, orc, W, gW, check_dt=False)
 
 
 @pytest.mark.parametrize("tag", [ADIA, ISO], ids=["adiabatic", "isothermal"])
@@ -199,14 +187,5 @@ def test_cavity_full_size_one_step():
     gW = np.zeros((15, m.n_cell))
     s = G.Solver(m, G.default_config(**kw))
     orc = oracle.Oracle(m, oracle.make_config(**kw))
-    s.init(W, gW)
-    Wo, gWo = W, gW
-    for step in range(3):
-        dt = orc.compute_dt(Wo, 0.5)
-        assert abs(s.compute_dt(0.5) - dt) <= 1e-15 * dt
-        s.step(dt)
-        Wo, gWo = orc.step(dt, Wo, gWo)
-    Wg, gWg = s.read_state()
-    assert_parity(Wg, Wo, W_GROUPS, "W")
-    assert_parity(gWg, gWo, GW_GROUPS, "gW", floors=gradient_floors(Wo, orc))
+    Wo, gWo = check_steps(m, s, orc, W, gW, nsteps=3, by_stage=False)
     assert np.abs(Wo[1]).max() > 1e-4  # the lid has set the gas moving

@@ -8,7 +8,7 @@ import oracle
 import paper_2102_01366_amd as G
 from paper_2102_01366_amd import inputs as I
 
-from test_gpu_parity import COEF_GROUPS, FACE_GROUPS, face_floors, GW_GROUPS, MU_TGV, W_GROUPS, assert_parity, gradient_floors
+from test_gpu_parity import COEF_GROUPS, MU_TGV, assert_parity, check_face_terms, check_steps
 
 pytestmark = pytest.mark.gpu
 
@@ -42,18 +42,8 @@ def test_order2_parity(name):
     co, fo = orc.reconstruct(W, gW)
     assert_parity(coef, co, COEF_GROUPS, "coef")
     np.testing.assert_array_equal(flag, fo)
-    dt = orc.compute_dt(W, 0.5)
-    ref = orc.face_terms(W, gW, dt)
-    assert_parity(s.debug_face_terms(dt), ref, FACE_GROUPS, "face terms", floors=face_floors(ref, dt))
-    s.init(W, gW)
-    Wo, gWo = W, gW
-    for step in range(2):
-        dt = orc.compute_dt(Wo, 0.5)
-        s.step(dt)
-        Wo, gWo = orc.step(dt, Wo, gWo)
-        Wg, gWg = s.read_state()
-        assert_parity(Wg, Wo, W_GROUPS, f"W step {step}")
-        assert_parity(gWg, gWo, GW_GROUPS, f"gW step {step}", floors=gradient_floors(Wo, orc))
+    check_face_terms(s, orc, W, gW, orc.compute_dt(W, 0.5))
+    check_steps(m, s, orc, W, gW, by_stage=False, check_dt=False)
 
 
 def test_order2_adjoint_matches_finite_differences():

@@ -16,7 +16,7 @@ import oracle
 import paper_2102_01366_amd as G
 from paper_2102_01366_amd import inputs as I
 
-from test_gpu_parity import FACE_GROUPS, face_floors, GW_GROUPS, W_GROUPS, assert_parity, gradient_floors
+from test_gpu_parity import W_GROUPS, GW_GROUPS, assert_parity, check_face_terms, check_steps
 
 pytestmark = pytest.mark.gpu
 
@@ -56,25 +56,13 @@ def _pair(name, **extra):
 def test_smooth_face_terms(name):
     m, s, orc, W, gW = _pair(name)
     s.init(W, gW)
-    dt = orc.compute_dt(W, 0.5)
-    ref = orc.face_terms(W, gW, dt)
-    assert_parity(s.debug_face_terms(dt), ref, FACE_GROUPS, "face terms", floors=face_floors(ref, dt))
+    check_face_terms(s, orc, W, gW, orc.compute_dt(W, 0.5))
 
 
 @pytest.mark.parametrize("name", CASES)
 def test_smooth_steps(name):
     m, s, orc, W, gW = _pair(name)
-    s.init(W, gW)
-    Wo, gWo = W, gW
-    for step in range(2):
-        dt = orc.compute_dt(Wo, 0.5)
-        for stage in (1, 2):
-            s.stage(stage, dt)
-            Wo, gWo = orc.stage(stage, dt, Wo, gWo)
-            Wg, gWg = s.read_state()
-            assert_parity(Wg, Wo, W_GROUPS, f"W step {step} stage {stage}")
-            assert_parity(gWg, gWo, GW_GROUPS, f"gW step {step} stage {stage}",
-                          floors=gradient_floors(Wo, orc))
+    check_steps(m, s, orc, W, gW, check_dt=False)
     ref = orc.conservation_sums(Wo)
     if name != "walls_ns":  # slip walls exchange momentum with the fluid
         assert np.abs(s.conservation_sums() - ref).max() <= 1e-13 * np.abs(ref).max()

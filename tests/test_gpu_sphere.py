@@ -16,7 +16,7 @@ import oracle
 import paper_2102_01366_amd as G
 from paper_2102_01366_amd import inputs as I
 
-from test_gpu_parity import COEF_GROUPS, FACE_GROUPS, face_floors, GW_GROUPS, W_GROUPS, assert_parity, gradient_floors
+from test_gpu_parity import COEF_GROUPS, GW_GROUPS, W_GROUPS, assert_parity, check_face_terms, check_steps
 
 pytestmark = pytest.mark.gpu
 
@@ -25,20 +25,7 @@ FREE = np.array([1.0, 0.3, 0.0, 0.0, (1.0 / GAMMA) / (GAMMA - 1) + 0.5 * 0.09])
 
 
 def _bump_field():
-    def f(X):
-        x, y, z = X[..., 0] - 2.0, X[..., 1], X[..., 2]
-        b = np.exp(-(x * x + y * y + z * z) / 0.3)
-        db = [-2.0 * c / 0.3 * b for c in (x, y, z)]
-        rho = 1.0 + 0.1 * b
-        p = 1.0 / GAMMA + 0.05 * b
-        u = 0.3 * np.ones_like(x)
-        zero = np.zeros_like(x)
-        Q = np.stack([rho, rho * u, zero, zero, p / (GAMMA - 1) + 0.5 * rho * u * u])
-        dQ = np.stack([np.stack([0.1 * g for g in db]), np.stack([0.1 * g * 0.3 for g in db]),
-                       np.stack([zero] * 3), np.stack([zero] * 3),
-                       np.stack([0.05 * g / (GAMMA - 1) + 0.5 * 0.09 * 0.1 * g for g in db])])
-        return Q, dQ
-    return f
+    return I.bump_stream_field(GAMMA)
 
 
 def _case(viscous=False):
@@ -69,24 +56,12 @@ def test_sphere_reconstruction(pair):
 def test_sphere_face_terms(pair):
     m, s, orc, W, gW = pair
     s.init(W, gW)
-    dt = orc.compute_dt(W, 0.5)
-    ref = orc.face_terms(W, gW, dt)
-    assert_parity(s.debug_face_terms(dt), ref, FACE_GROUPS, "face terms", floors=face_floors(ref, dt))
+    check_face_terms(s, orc, W, gW, orc.compute_dt(W, 0.5))
 
 
 def test_sphere_steps(pair):
     m, s, orc, W, gW = pair
-    s.init(W, gW)
-    Wo, gWo = W, gW
-    for step in range(2):
-        dt = orc.compute_dt(Wo, 0.5)
-        for stage in (1, 2):
-            s.stage(stage, dt)
-            Wo, gWo = orc.stage(stage, dt, Wo, gWo)
-            Wg, gWg = s.read_state()
-            assert_parity(Wg, Wo, W_GROUPS, f"W step {step} stage {stage}")
-            assert_parity(gWg, gWo, GW_GROUPS, f"gW step {step} stage {stage}",
-                          floors=gradient_floors(Wo, orc))
+    check_steps(m, s, orc, W, gW, check_dt=False)
 
 
 def test_sphere_fp32_bulk_close_to_fp64():

@@ -16,7 +16,7 @@ import oracle
 import paper_2102_01366_amd as G
 from paper_2102_01366_amd import inputs as I
 
-from test_gpu_parity import COEF_GROUPS, FACE_GROUPS, face_floors, GW_GROUPS, W_GROUPS, assert_parity, gradient_floors
+from test_gpu_parity import COEF_GROUPS, GW_GROUPS, assert_parity, check_face_terms, check_steps
 
 pytestmark = pytest.mark.gpu
 
@@ -62,24 +62,13 @@ def test_wall_reconstruction(name):
 def test_wall_face_terms(name):
     m, s, orc, W, gW = _pair(name)
     s.init(W, gW)
-    dt = orc.compute_dt(W, 0.5)
-    ref = orc.face_terms(W, gW, dt)
-    assert_parity(s.debug_face_terms(dt), ref, FACE_GROUPS, "face terms", floors=face_floors(ref, dt))
+    check_face_terms(s, orc, W, gW, orc.compute_dt(W, 0.5))
 
 
 @pytest.mark.parametrize("name", CASES)
 def test_wall_steps(name):
     m, s, orc, W, gW = _pair(name)
-    s.init(W, gW)
-    Wo, gWo = W, gW
-    for step in range(2):
-        dt = orc.compute_dt(Wo, 0.5)
-        assert abs(s.compute_dt(0.5) - dt) <= 1e-15 * dt
-        s.step(dt)
-        Wo, gWo = orc.step(dt, Wo, gWo)
-        Wg, gWg = s.read_state()
-        assert_parity(Wg, Wo, W_GROUPS, f"W step {step}")
-        assert_parity(gWg, gWo, GW_GROUPS, f"gW step {step}", floors=gradient_floors(Wo, orc))
+    check_steps(m, s, orc, W, gW, by_stage=False)
 
 
 def test_wall_conservation_on_gpu():
