@@ -172,7 +172,8 @@ def test_adjoint_matches_tangent_oracle(precision):
     period 1, Re 1600, 50 steps with the paper's default collision-time jump
     and WENO weights (kinks active), 16 RMS-scaled directions.  The GPU's
     adjoint gradient through the autograd rollout, with the oracle's time
-    steps, agrees to 1e-8 relative in FP64; the FP32-bulk form to 1e-3."""
+    steps, agrees to 1e-8 relative in FP64 (each direction); the FP32-bulk form
+    to 1e-3 of the largest directional derivative."""
     from paper_2102_01366_amd.autograd import rollout
     gold = json.load(open(TANGENT_GOLDEN))
     ell = 1.0 / (2.0 * math.pi)
@@ -189,11 +190,13 @@ def test_adjoint_matches_tangent_oracle(precision):
     assert abs(J.item() - gold["J"]) <= tol_J * abs(gold["J"]), (J.item(), gold["J"])
     dW, dG = I.rms_directions(W, gW, gold["ndir"], gold["direction_seed"])
     gWn, gGn = Wr.grad.cpu().numpy(), Gr.grad.cpu().numpy()
-    errs = []
-    for k, ref in enumerate(gold["jvp"]):
-        ad = float((gWn * dW[k]).sum() + (gGn * dG[k]).sum())
-        errs.append(abs(ad - ref) / abs(ref))
-    assert max(errs) <= tol, errs
+    ad = np.array([float((gWn * dW[k]).sum() + (gGn * dG[k]).sum()) for k in range(gold["ndir"])])
+    ref = np.array(gold["jvp"])
+    if precision == "fp64":
+        errs = np.abs(ad - ref) / np.abs(ref)  # each direction on its own
+    else:
+        errs = np.abs(ad - ref) / np.abs(ref).max()  # FP32 rounding: against the largest
+    assert errs.max() <= tol, errs
 
 
 def test_adjoint_is_bitwise_reproducible_and_leaves_state():

@@ -62,7 +62,7 @@ def test_smooth_face_terms(name):
 @pytest.mark.parametrize("name", CASES)
 def test_smooth_steps(name):
     m, s, orc, W, gW = _pair(name)
-    check_steps(m, s, orc, W, gW, check_dt=False)
+    Wo, gWo = check_steps(m, s, orc, W, gW, check_dt=False)
     ref = orc.conservation_sums(Wo)
     if name != "walls_ns":  # slip walls exchange momentum with the fluid
         assert np.abs(s.conservation_sums() - ref).max() <= 1e-13 * np.abs(ref).max()
