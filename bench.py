@@ -1,24 +1,30 @@
 #!/usr/bin/env python3
 """Throughput of the compact third-order gas-kinetic scheme on one MI355X.
 
-Workload: the viscous Taylor-Green vortex on the periodic cube [0, 2 pi]^3,
-32^3 hexahedra each split into 6 Kuhn tetrahedra (196,608 cells), vertices
-jittered by 5% of h (seed 1), gamma 1.4, Ma 0.1, Re 1600 (mu = 1/1600),
-Pr 0.72, CFL 0.5, third-order MR-WENO.  One "step" is the whole hot path:
-the CFL time step, then both stages (slopes, MR-WENO reconstruction,
-gas-kinetic face fluxes, cell update).  The state lives in HBM before the
-timed region starts.
+Headline workload: the spherical blast with reflective walls in the unit
+cube, 64^3 hexahedra each split into 6 Kuhn tetrahedra (1,572,864 cells,
+3,170,304 faces), vertices jittered by 10% of h (seed 2), slip walls, Euler,
+gamma 1.4, (rho, p) = (1, 10) inside r < 0.1 and (1, 0.1) outside, at rest,
+third-order MR-WENO with its nonlinear weights and positivity fallback
+active, CFL 0.5, FP64.  One "step" is the whole hot path: the CFL time step,
+then both stages (slopes, MR-WENO reconstruction, gas-kinetic face fluxes,
+cell update), all on the device.  The state lives in HBM before the timed
+region starts.
 
 Prints one JSON line: cell-stage-updates/s over an uninstrumented timed
-region, the roofline of the dominant kernel (per-kernel durations from HIP
+region; the roofline of the dominant kernel (per-kernel durations from HIP
 events that the library records on its stream around each kernel, over the
-same number of steps right after the timed region), the device's measured copy bandwidth (each
-memory-bound kernel's rate is also given as a fraction of it), the FP32-bulk form's throughput and error, the
-differentiation form (adjoint / forward time and its finite-difference
-check), the walled blast workload (1.57M cells, slip walls), the lid-driven
-cavity (no-slip isothermal walls, smooth-flow flux), flow past a sphere on a
-cubed-sphere shell (1.77M cells, slip wall and far field) and the FP64 CPU
-oracle timed on a bounded sample.
+same number of steps right after the timed region; executed FP64 work and
+HBM traffic from the committed rocprofv3 counter summaries of the same
+kernel sources); the device's measured copy bandwidth; the FP32-bulk form on
+the same workload; the blast run to t = 0.2 in both precisions (density L1
+of FP32-bulk against FP64, mass and energy drift, fallback counts); the
+viscous Taylor-Green vortex (196,608 cells: throughput, kinetic-energy decay,
+FP32-bulk error); the differentiation form (adjoint / forward time, central
+differences, and the 3,072-cell check against the oracle's tangent build);
+the lid-driven cavity (no-slip isothermal walls, smooth-flow flux); flow past
+a sphere on a cubed-sphere shell (1.77M cells, slip wall and far field); and
+the FP64 CPU oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -35,6 +41,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak, TFLOP/s
+# the survey's algorithmic estimate of the flux's FP64 work per face (4-5k
+# FLOP per Gauss point, three Gauss points), beside the executed count
+FLUX_ALGORITHMIC_FLOP_PER_FACE = 13.5e3
 
 # Algorithmic HBM bytes per unit of each FP64 kernel: every array element the
 # kernel needs is counted once (neighbour gathers assumed served by caches).
@@ -59,25 +68,26 @@ BYTES_PER_UNIT = {
 UNIT = {"slopes": "cell", "reconstruct": "cell", "flux_stage1": "face", "flux_stage2": "face",
         "update_stage1": "cell", "update_stage2": "cell", "dt": "cell"}
 
-# rocprofv3 names of each timed kernel (FP64, FP32-bulk) of this workload
-# (viscous, Pr != 1)
+# rocprofv3 names of the FP64 kernels of the headline workload (Euler, slip
+# walls: interior and wall-face launches of the flux)
 PROFILE_NAMES = {
-    "slopes": ("gks::slopes_kernel<double>", "gks::slopes_kernel<float>"),
-    "reconstruct": ("gks::reconstruct_kernel<double>", "gks::reconstruct_kernel<float>"),
-    "flux_stage1": ("gks::flux_kernel<double, 0, true, true, false, false>",
-                    "gks::flux_kernel<float, 0, true, true, false, false>"),
-    "flux_stage2": ("gks::flux_kernel<double, 1, true, true, false, false>",
-                    "gks::flux_kernel<float, 1, true, true, false, false>"),
-    "update_stage1": ("gks::update_kernel<double, 1>", "gks::update_kernel<float, 1>"),
-    "update_stage2": ("gks::update_kernel<double, 2>", "gks::update_kernel<float, 2>"),
-    "dt": ("gks::dt_pass1", None),  # one kernel serves both forms
+    "slopes": ("gks::slopes_kernel<double>",),
+    "reconstruct": ("gks::reconstruct_kernel<double>",),
+    "flux_stage1": ("gks::flux_kernel<double, 0, false, false, false, false>",
+                    "gks::flux_kernel<double, 0, false, false, true, false>"),
+    "flux_stage2": ("gks::flux_kernel<double, 1, false, false, false, false>",
+                    "gks::flux_kernel<double, 1, false, false, true, false>"),
+    "update_stage1": ("gks::update_kernel<double, 1>",),
+    "update_stage2": ("gks::update_kernel<double, 2>",),
+    "dt": ("gks::dt_pass1",),
 }
-# the kernel sources whose digest the committed counter summary records
+# the kernel sources whose digest the committed counter summaries record
 KERNEL_SOURCES = ("paper_2102_01366_amd/csrc/gks_kernels.hip", "paper_2102_01366_amd/csrc/gks_flux.h",
                   "paper_2102_01366_amd/csrc/gks_flux_kernel.h", "paper_2102_01366_amd/csrc/gks_device.h",
                   "paper_2102_01366_amd/csrc/gks_internal.h", "paper_2102_01366_amd/csrc/gks_m2stage.h",
                   "paper_2102_01366_amd/csrc/gks_recon_adj.h")
-COUNTERS = os.path.join(ROOT, "profiles", "taylor_green_196608_counters.md")
+TRAFFIC = os.path.join(ROOT, "profiles", "blast_walls_1572864_counters.md")
+VALU = os.path.join(ROOT, "profiles", "blast_walls_1572864_valu_f64.md")
 
 
 def kernel_digest():
@@ -89,22 +99,25 @@ def kernel_digest():
     return h.hexdigest()
 
 
-def measured_traffic(key):
-    """HBM bytes per launch of the FP64 kernel `key` on the 196,608-cell mesh,
-    from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by
-    the copy-kernel calibration it states); None when that summary was taken
-    on other kernel sources."""
+def summary_value(path, key, column):
+    """A number from a committed rocprofv3 summary table under profiles/: the
+    row whose first cell is `key`, the column headed `column`; None when the
+    file is missing or records other kernel sources than the current ones."""
     try:
-        with open(COUNTERS) as fh:
+        with open(path) as fh:
             text = fh.read()
     except OSError:
         return None
     if f"`{kernel_digest()}`" not in text:
         return None
+    header = None
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) >= 6 and cells[1] == f"{key} (fp64)":
-            return float(cells[5].replace(",", ""))
+        if header is None and column in cells:
+            header = cells
+            continue
+        if header and len(cells) == len(header) and cells[0] == key:
+            return float(cells[header.index(column)].replace(",", ""))
     return None
 
 
@@ -114,8 +127,21 @@ def I_cell_volumes(mesh):
     return np.abs(np.linalg.det(v[:, 1:] - v[:, :1])) / 6.0
 
 
-def cpu_baseline(mesh, W, gW, cfg_kw, steps):
-    """The FP64 oracle, as it stands, on `steps` steps of the same mesh."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(I, mesh, W, gW, cfg_kw, steps, serial_n):
+    """The FP64 oracle, as it stands, on `steps` steps of the headline mesh
+    with all of the host's OpenMP threads, and on one stage of the same
+    workload at serial_n^3 x 6 cells with one thread."""
     import oracle
     oracle.build(force=False)
     threads = oracle.set_threads(0)
@@ -126,31 +152,70 @@ def cpu_baseline(mesh, W, gW, cfg_kw, steps):
     for _ in range(steps):
         Wo, gWo = orc.step(dt, Wo, gWo)
     el = time.perf_counter() - t0
-    return {"value": mesh.n_cell * 2 * steps / el, "unit": "cell-stage-updates/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"{steps} step(s) = {2 * steps} stages of the full {mesh.n_cell}-cell mesh, "
-                      f"{el:.1f} s on {threads} OpenMP threads"}
+    out = {"value": mesh.n_cell * 2 * steps / el, "unit": "cell-stage-updates/s",
+           "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"{steps} step(s) = {2 * steps} stages of the full {mesh.n_cell}-cell mesh, "
+                     f"{el:.1f} s on {threads} OpenMP threads"}
+    if serial_n > 0:
+        ms = I.kuhn_cube_mesh(serial_n, 1.0, 0.1, 2, False)
+        Ws, gWs = I.blast_cell_averages(ms)
+        so = oracle.Oracle(ms, oracle.make_config(**cfg_kw))
+        dts = so.compute_dt(Ws, 0.5)
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        so.stage(1, dts, Ws, gWs)
+        el1 = time.perf_counter() - t0
+        oracle.set_threads(threads)
+        out["serial"] = {"value": ms.n_cell / el1, "unit": "cell-stage-updates/s", "cores": 1,
+                         "sample": f"stage 1 of one step of the same workload on {serial_n}^3 x 6 = "
+                                   f"{ms.n_cell} cells, {el1:.1f} s on 1 thread"}
+    return out
 
 
 def adjoint_leg(G, I, mesh, W, gW, cfg_kw, nsteps, ndir, precision):
-    """Differentiation form on the same mesh: J = kinetic energy after
+    """Differentiation form on the Taylor-Green mesh: J = kinetic energy after
     `nsteps` CFL steps (time steps of an undifferentiated run, then fixed);
     dJ/d(W0, grad W0) by the discrete adjoint through the autograd rollout.
     Times one forward pass of plain steps and the adjoint pass, and checks
     the gradient against central differences along `ndir` seeded directions
-    (rows scaled by their RMS, step 1e-6)."""
+    (inputs.rms_directions, seed 4): in the paper's configuration (steps
+    1e-6 and 1e-7), and with the step map made smooth (no collision-time
+    jump, WENO eps = 1; step 1e-6)."""
     import numpy as np
     import torch
     from paper_2102_01366_amd.autograd import rollout, time_steps
     dev = "cuda:0"
-    s = G.Solver(mesh, G.default_config(precision=precision, **cfg_kw), device=dev)
     vol = torch.from_numpy(I_cell_volumes(mesh)).to(dev)
     W0, G0 = torch.from_numpy(W).to(dev), torch.from_numpy(gW).to(dev)
-    dts = time_steps(s, W0, G0, 0.5, nsteps)
 
     def ke(Wx):
         return (vol * 0.5 * (Wx[1] ** 2 + Wx[2] ** 2 + Wx[3] ** 2) / Wx[0]).sum()
 
+    def gradient(s, dts):
+        Wr, Gr = W0.clone().requires_grad_(True), G0.clone().requires_grad_(True)
+        J = ke(rollout(s, Wr, Gr, dts)[0])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        return Wr.grad.detach(), Gr.grad.detach(), time.perf_counter() - t1
+
+    def fd_check(s, dts, gW_, gG_, steps_eps):
+        dW, dG = I.rms_directions(W, gW, ndir, 4)
+        errs = {e: [] for e in steps_eps}
+        for k in range(ndir):
+            vW, vG = torch.from_numpy(dW[k]).to(dev), torch.from_numpy(dG[k]).to(dev)
+            ad = ((gW_ * vW).sum() + (gG_ * vG).sum()).item()
+            for eps in steps_eps:
+                with torch.no_grad():
+                    Jp = ke(rollout(s, W0 + eps * vW, G0 + eps * vG, dts)[0]).item()
+                    Jm = ke(rollout(s, W0 - eps * vW, G0 - eps * vG, dts)[0]).item()
+                errs[eps].append(abs((Jp - Jm) / (2 * eps) - ad) / abs(ad))
+        return [{"eps": eps, "max_rel_err": max(e), "median_rel_err": float(np.median(e))}
+                for eps, e in errs.items()]
+
+    s = G.Solver(mesh, G.default_config(precision=precision, **cfg_kw), device=dev)
+    dts = time_steps(s, W0, G0, 0.5, nsteps)
     s.init(W0, G0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -160,55 +225,74 @@ def adjoint_leg(G, I, mesh, W, gW, cfg_kw, nsteps, ndir, precision):
     t_fwd = time.perf_counter() - t0
     # one step forward and back first, so that loading the reverse kernels and
     # allocating the adjoint workspace fall outside the timed pass
-    Ww, Gw = W0.clone().requires_grad_(True), G0.clone().requires_grad_(True)
-    ke(rollout(s, Ww, Gw, dts[:1])[0]).backward()
-    del Ww, Gw
-    Wr, Gr = W0.clone().requires_grad_(True), G0.clone().requires_grad_(True)
-    J = ke(rollout(s, Wr, Gr, dts)[0])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    J.backward()
-    torch.cuda.synchronize()
-    t_adj = time.perf_counter() - t1
+    gradient(s, dts[:1])
+    gWa, gGa, t_adj = gradient(s, dts)
     out = {"steps": nsteps, "objective": "kinetic energy sum |Omega| |rho U|^2 / (2 rho) at the final time",
            "forward_ms_per_step": t_fwd / nsteps * 1e3, "adjoint_ms_per_step": t_adj / nsteps * 1e3,
            "adjoint_over_forward": t_adj / t_fwd,
            "checkpoint_bytes": nsteps * 20 * 8 * mesh.n_cell}
     if ndir:
-        gen = torch.Generator().manual_seed(4)
-        sW = torch.from_numpy(np.sqrt((W ** 2).mean(axis=1, keepdims=True))).to(dev)
-        sG = torch.from_numpy(np.sqrt((gW ** 2).mean(axis=1, keepdims=True)) + 1e-3).to(dev)
         # the jump term |p_l - p_r| and the WENO indicators' |.| are kinks: a
-        # difference whose step straddles one measures a secant, so the check
-        # is reported at two steps
-        errs = {1e-6: [], 1e-7: []}
-        for _ in range(ndir):
-            vW = torch.randn(W.shape, generator=gen, dtype=torch.float64).to(dev) * sW
-            vG = torch.randn(gW.shape, generator=gen, dtype=torch.float64).to(dev) * sG
-            ad = ((Wr.grad * vW).sum() + (Gr.grad * vG).sum()).item()
-            for eps in errs:
-                with torch.no_grad():
-                    Jp = ke(rollout(s, W0 + eps * vW, G0 + eps * vG, dts)[0]).item()
-                    Jm = ke(rollout(s, W0 - eps * vW, G0 - eps * vG, dts)[0]).item()
-                errs[eps].append(abs((Jp - Jm) / (2 * eps) - ad) / abs(ad))
-        out.update({"fd_directions": ndir,
-                    "fd": [{"eps": eps, "max_rel_err": max(e), "median_rel_err": float(np.median(e))}
-                           for eps, e in errs.items()]})
-    return out, (Wr.grad.detach(), Gr.grad.detach())
+        # difference whose step straddles one measures a secant
+        out["fd_directions"] = ndir
+        out["fd"] = fd_check(s, dts, gWa, gGa, (1e-6, 1e-7))
+        sm = G.Solver(mesh, G.default_config(precision=precision, **dict(cfg_kw, c_tau=0.0, eps_weno=1.0)),
+                      device=dev)
+        gWs, gGs, _ = gradient(sm, dts)
+        out["fd_smooth_map"] = {"config": "collision-time jump off (C = 0), WENO eps = 1",
+                                "checks": fd_check(sm, dts, gWs, gGs, (1e-6,))}
+    return out, (gWa, gGa)
 
 
-def timed_kernels(solver, steps):
+def tangent_reference_leg(G, I):
+    """The FP64 CPU reference gradient: the oracle's tangent build's
+    directional derivatives of the 50-step kinetic energy on the 3,072-cell
+    unit cube (tests/golden/adjoint_tangent_c0.json, written from the oracle
+    alone), against the GPU adjoint; beside them, central differences of the
+    GPU forward map along the same directions, and the oracle's count of
+    kinks within 1e-6 along each direction."""
+    import numpy as np
+    import torch
+    from paper_2102_01366_amd.autograd import rollout
+    path = os.path.join(ROOT, "tests", "golden", "adjoint_tangent_c0.json")
+    with open(path) as fh:
+        gold = json.load(fh)
+    dev = "cuda:0"
+    ell = 1.0 / (2.0 * math.pi)
+    m = I.kuhn_cube_mesh(8, 1.0, 0.1, 0, True)
+    W, gW = I.cell_averages(m, I.taylor_green_field(mach=0.1, ell=ell))
+    vol = torch.from_numpy(I_cell_volumes(m)).to(dev)
+
+    def ke(Wx):
+        return (vol * 0.5 * (Wx[1] ** 2 + Wx[2] ** 2 + Wx[3] ** 2) / Wx[0]).sum()
+
+    s = G.Solver(m, G.default_config(**gold["config"]), device=dev)
+    W0, G0 = torch.from_numpy(W).to(dev), torch.from_numpy(gW).to(dev)
+    Wr, Gr = W0.clone().requires_grad_(True), G0.clone().requires_grad_(True)
+    ke(rollout(s, Wr, Gr, gold["dts"])[0]).backward()
+    dW, dG = I.rms_directions(W, gW, gold["ndir"], gold["direction_seed"])
+    ref = np.array(gold["jvp"])
+    ad, fd = [], []
+    for k in range(gold["ndir"]):
+        vW, vG = torch.from_numpy(dW[k]).to(dev), torch.from_numpy(dG[k]).to(dev)
+        ad.append(((Wr.grad * vW).sum() + (Gr.grad * vG).sum()).item())
+        with torch.no_grad():
+            Jp = ke(rollout(s, W0 + 1e-6 * vW, G0 + 1e-6 * vG, gold["dts"])[0]).item()
+            Jm = ke(rollout(s, W0 - 1e-6 * vW, G0 - 1e-6 * vG, gold["dts"])[0]).item()
+        fd.append((Jp - Jm) / 2e-6)
+    ad, fd = np.array(ad), np.array(fd)
+    return {"workload": gold["workload"], "steps": gold["steps"], "directions": gold["ndir"],
+            "adjoint_vs_tangent_max_rel_err": float((np.abs(ad - ref) / np.abs(ref)).max()),
+            "fd_1e-6_vs_tangent_rel_err": [float(x) for x in np.abs(fd - ref) / np.abs(ref)],
+            "kinks_within_1e-6_jump": gold["kinks_jump"], "kinks_within_1e-6_weno": gold["kinks_weno"]}
+
+
+def timed_kernels(solver, steps, reseed=None):
     """Per-kernel HIP-event durations over `steps` further steps (the events
     are recorded by the library on its stream around each kernel)."""
-    import torch
     solver.timing_read(reset=True)
     solver.timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        solver.step_cfl(0.5)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el = run_steps(solver, steps, reseed)
     solver.timing_enable(False)
     return solver.timing_read(reset=True), el
 
@@ -236,65 +320,143 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
     return 2 * nbytes / (ms[len(ms) // 2] * 1e-3) / 1e9
 
 
-def blast_leg(G, I, n, steps, warmup, copy_gbs):
-    """Shock-robustness workload with reflective walls: the spherical blast
-    (rho 1, p 10 inside r < 0.1, p 0.1 outside, at rest) in the unit cube,
-    n^3 hexahedra x 6 Kuhn tetrahedra, 10% jitter (seed 2), six slip walls,
-    Euler, third-order WENO, CFL 0.5; FP64 and FP32-bulk.  On this mesh
-    (well beyond the last-level cache) the FP64 per-kernel rates are also given
-    as fractions of the HBM peak and of the measured copy bandwidth, and the
-    flux's as counted FP64 work against the FP64 vector peak."""
+# the blast becomes non-physical after about 26 steps under the paper's
+# nonlinear weights as printed, so its timed runs restart from
+# the initial state (a device-to-device copy) every RESEED steps
+RESEED = 20
+
+
+def run_steps(solver, n, reseed=None):
+    """n steps of gks_step_cfl; reseed = (W0, gW0) device tensors: restart
+    from them every RESEED steps (counted from the last restart)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n):
+        if reseed is not None and i % RESEED == 0:
+            solver.init(*reseed)
+        solver.step_cfl(0.5)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def kernel_rates(kt, units, copy_gbs, flops_face):
+    """Per-kernel average durations and rates from the HIP-event timings."""
+    out = {}
+    for k, (ms, cnt) in kt.items():
+        if cnt == 0:
+            continue
+        avg_s = ms / cnt * 1e-3
+        nbytes = BYTES_PER_UNIT[k] * units[UNIT[k]]
+        e = {"avg_ms": ms / cnt, "launches": cnt, "total_ms": ms, "bytes_per_launch": nbytes,
+             "hbm_GBs": nbytes / avg_s / 1e9}
+        if k.startswith("flux"):
+            e["fp64_flop_per_launch"] = flops_face * units["face"]
+            e["fp64_TFLOPs"] = flops_face * units["face"] / avg_s / 1e12
+            e["fp64_frac"] = e["fp64_TFLOPs"] / FP64_VECTOR_TFLOPS
+        else:
+            e["hbm_frac"] = e["hbm_GBs"] / HBM_PEAK_GBS
+            e["frac_of_copy"] = e["hbm_GBs"] / copy_gbs
+        out[k] = e
+    return out
+
+
+def blast_to_time(G, I, mesh, W, gW, t_end, compare_step=20):
+    """The blast run from rest toward t_end in FP64 and FP32-bulk (CFL 0.5,
+    the last step shortened to land on t_end), stopped where a cell average
+    becomes non-physical: steps, time reached, density L1 of FP32-bulk
+    against FP64 after `compare_step` steps; at t_end also mass and energy
+    drift and positivity-fallback cells."""
     import numpy as np
     import torch
-    mesh = I.kuhn_cube_mesh(n, 1.0, 0.1, 2, False)
-    W, gW = I.blast_cell_averages(mesh)
     vol = I_cell_volumes(mesh)
-    out = {"workload": f"spherical blast in the unit cube, {n}^3 hexes x 6 Kuhn tets "
-                       f"({mesh.n_cell} cells, {mesh.n_face} faces), 10% jitter, slip walls, Euler, CFL 0.5",
-           "cells": mesh.n_cell, "faces": mesh.n_face, "steps": steps}
     res = {}
     for name, prec in (("fp64", G.GKS_FP64), ("fp32_bulk", G.GKS_FP32_BULK)):
         s = G.Solver(mesh, G.default_config(precision=prec), device="cuda:0")
         s.init(W, gW)
-        sums0 = s.conservation_sums()
-        for _ in range(warmup):
-            s.step_cfl(0.5)
+        s0 = s.conservation_sums()
+        t, n, last_good, failed = 0.0, 0, None, False
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            s.step_cfl(0.5)
+        while t < t_end * (1 - 1e-12):
+            try:
+                dt = min(s.compute_dt(0.5), t_end - t)
+            except G.GksError:
+                failed = True  # the state of the last step is non-physical
+                break
+            if n == compare_step:
+                last_good = s.read_state()[0]
+            s.step(dt)
+            t += dt
+            n += 1
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        Wf, _ = s.read_state()
-        sums1 = s.conservation_sums()
-        kt, _ = timed_kernels(s, steps)
-        flag = s.debug_reconstruct()[2]
-        units = {"cell": mesh.n_cell, "face": mesh.n_face}
-        kern = {}
-        flops_face = G.flux_op_count(G.default_config(precision=prec))["total"]
-        for k, (ms, cnt) in kt.items():
-            if cnt:
-                kern[k] = {"avg_ms": ms / cnt}
-                if prec == G.GKS_FP64:
-                    gbs = BYTES_PER_UNIT[k] * units[UNIT[k]] / (ms / cnt * 1e-3) / 1e9
-                    kern[k]["hbm_GBs"] = gbs
-                    if k.startswith("flux"):
-                        tf = flops_face * mesh.n_face / (ms / cnt * 1e-3) / 1e12
-                        kern[k]["fp64_TFLOPs"] = tf
-                        kern[k]["fp64_frac"] = tf / FP64_VECTOR_TFLOPS
-                    else:
-                        kern[k]["hbm_frac"] = gbs / HBM_PEAK_GBS
-                        kern[k]["frac_of_copy"] = gbs / copy_gbs
-        res[name] = (Wf, {"value": mesh.n_cell * 2 * steps / el, "unit": "cell-stage-updates/s",
-                          "ms_per_step": el / steps * 1e3,
-                          "mass_energy_drift": float(max(abs(sums1[q] - sums0[q]) / abs(sums0[q]) for q in (0, 4))),
-                          "fallback_cells": int(flag.sum()), "kernels": kern})
-    out["fp64"] = res["fp64"][1]
-    out["fp32_bulk"] = res["fp32_bulk"][1]
+        r = {"steps": n, "t_reached": t, "nonphysical": failed, "wall_s": el,
+             "cell_stage_updates_per_s": mesh.n_cell * 2 * n / el}
+        if not failed:
+            s1 = s.conservation_sums()
+            r["mass_energy_drift"] = float(max(abs(s1[q] - s0[q]) / abs(s0[q]) for q in (0, 4)))
+            r["fallback_cells"] = int(s.debug_reconstruct()[2].sum())
+        res[name] = (last_good, r)
+    out = {"t_end": t_end, "fp64": res["fp64"][1], "fp32_bulk": res["fp32_bulk"][1]}
     W64, W32 = res["fp64"][0], res["fp32_bulk"][0]
-    out["fp32_bulk"]["l1_density_vs_fp64"] = float(np.sum(vol * np.abs(W32[0] - W64[0])) / np.sum(vol * W64[0]))
-    out["fp32_bulk"]["speedup_vs_fp64"] = out["fp32_bulk"]["value"] / out["fp64"]["value"]
+    if W64 is not None and W32 is not None:
+        out["fp32_bulk"]["compare_step"] = compare_step
+        out["fp32_bulk"]["l1_density_vs_fp64"] = float(np.sum(vol * np.abs(W32[0] - W64[0])) / np.sum(vol * W64[0]))
+        out["fp32_bulk"]["max_density_diff_vs_fp64"] = float(np.abs(W32[0] - W64[0]).max())
     return out
+
+
+def taylor_green_leg(G, I, n, steps, warmup, copy_gbs, ek_steps=200, ek_every=20):
+    """The viscous Taylor-Green vortex on [0, 2 pi]^3, n^3 hexahedra x 6 Kuhn
+    tetrahedra (196,608 cells at n = 32), 5% jitter (seed 1), Ma 0.1, Re 1600
+    (mu = 1/1600), Pr 0.72, CFL 0.5: FP64 and FP32-bulk throughput over
+    `steps` steps, the FP32-bulk density L1 against FP64, and the kinetic
+    energy E_k(t) = sum |Omega| |rho U|^2 / (2 rho) / (2 pi)^3 every `ek_every`
+    steps of a further FP64 run of `ek_steps` steps from the initial state."""
+    import numpy as np
+    import torch
+    cfg_kw = dict(viscous=True, mu=1.0 / 1600.0, prandtl=0.72)
+    mesh = I.kuhn_cube_mesh(n, 2 * math.pi, 0.05, 1, True)
+    W, gW = I.cell_averages(mesh, I.taylor_green_field(gamma=1.4, mach=0.1))
+    vol = I_cell_volumes(mesh)
+    out = {"workload": f"viscous Taylor-Green vortex, [0,2pi]^3 periodic, {n}^3 hexes x 6 Kuhn tets "
+                       f"({mesh.n_cell} cells, {mesh.n_face} faces), 5% jitter, Ma 0.1, Re 1600, Pr 0.72, CFL 0.5",
+           "cells": mesh.n_cell, "faces": mesh.n_face, "steps": steps}
+    finals = {}
+    for name, prec in (("fp64", G.GKS_FP64), ("fp32_bulk", G.GKS_FP32_BULK)):
+        s = G.Solver(mesh, G.default_config(precision=prec, **cfg_kw), device="cuda:0")
+        s.init(W, gW)
+        s0 = s.conservation_sums()
+        run_steps(s, warmup)
+        el = run_steps(s, steps)
+        kt, _ = timed_kernels(s, steps)
+        s1 = s.conservation_sums()
+        finals[name] = s.read_state()[0]
+        units = {"cell": mesh.n_cell, "face": mesh.n_face}
+        out[name] = {"value": mesh.n_cell * 2 * steps / el, "unit": "cell-stage-updates/s",
+                     "ms_per_step": el / steps * 1e3,
+                     "conservation_drift": float(np.max(np.abs(s1 - s0) / np.abs(s0).max())),
+                     "kernels_ms": {k: ms / c for k, (ms, c) in kt.items() if c}}
+        if prec == G.GKS_FP64:
+            # E_k(t) from the initial state
+            s.init(W, gW)
+            t, ek = 0.0, []
+            for k in range(ek_steps + 1):
+                if k % ek_every == 0:
+                    Wk, _ = s.read_state()
+                    ek.append([t, float(np.sum(vol * 0.5 * (Wk[1] ** 2 + Wk[2] ** 2 + Wk[3] ** 2) / Wk[0])
+                                        / (2 * math.pi) ** 3)])
+                if k < ek_steps:
+                    s.step_cfl(0.5)
+                    t += s.last_dt()
+            out["kinetic_energy"] = ek
+            e = np.array(ek)
+            out["dissipation_rate_last"] = float(-(e[-1, 1] - e[-2, 1]) / (e[-1, 0] - e[-2, 0]))
+    out["fp32_bulk"]["speedup_vs_fp64"] = out["fp32_bulk"]["value"] / out["fp64"]["value"]
+    out["fp32_bulk"]["l1_density_vs_fp64"] = float(
+        np.sum(vol * np.abs(finals["fp32_bulk"][0] - finals["fp64"][0])) / np.sum(vol * finals["fp64"][0]))
+    return out, (mesh, W, gW, cfg_kw)
 
 
 def cavity_leg(G, I, n, steps, warmup):
@@ -385,12 +547,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--n", type=int, default=32, help="hexahedra per side of the mesh")
+    ap.add_argument("--n", type=int, default=64, help="hexahedra per side of the headline blast mesh")
+    ap.add_argument("--t-end", type=float, default=0.2, help="end time of the blast run in both precisions "
+                                                                 "(0 skips it)")
+    ap.add_argument("--tgv-n", type=int, default=32, help="hexahedra per side of the Taylor-Green leg (0 skips it)")
     ap.add_argument("--cpu-baseline-steps", type=int, default=1)
+    ap.add_argument("--cpu-serial-n", type=int, default=32,
+                    help="mesh of the one-thread oracle leg: n^3 x 6 cells of the same workload (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk leg")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk headline leg")
     ap.add_argument("--adjoint-steps", type=int, default=50,
-                    help="steps of the differentiation leg (0 skips it)")
+                    help="steps of the differentiation leg on the Taylor-Green mesh (0 skips it)")
     ap.add_argument("--adjoint-directions", type=int, default=16)
     ap.add_argument("--cavity-n", type=int, default=32,
                     help="hexahedra per side of the lid-driven cavity leg (0 skips it)")
@@ -399,9 +566,6 @@ def main():
                     help="cells per panel side of the sphere leg (0 skips it)")
     ap.add_argument("--sphere-layers", type=int, default=48)
     ap.add_argument("--sphere-steps", type=int, default=4)
-    ap.add_argument("--blast-n", type=int, default=64,
-                    help="hexahedra per side of the walled blast leg (0 skips it)")
-    ap.add_argument("--blast-steps", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a 256 MiB fill (writes 256 MiB) and a 256 MiB elementwise add "
                          "(reads and writes 256 MiB): known byte counts that calibrate rocprofv3 "
@@ -418,88 +582,75 @@ def main():
     import paper_2102_01366_amd as G
     from paper_2102_01366_amd import inputs as I
 
-    mu = 1.0 / 1600.0
-    cfg_kw = dict(viscous=True, mu=mu, prandtl=0.72)
-    mesh = I.kuhn_cube_mesh(args.n, 2 * math.pi, 0.05, 1, True)
-    W, gW = I.cell_averages(mesh, I.taylor_green_field(gamma=1.4, mach=0.1))
-    config = G.default_config(**cfg_kw)
-    solver = G.Solver(mesh, config, device="cuda:0")
-    solver.init(W, gW)
+    mesh = I.kuhn_cube_mesh(args.n, 1.0, 0.1, 2, False)
+    W, gW = I.blast_cell_averages(mesh)
     nc, nf = mesh.n_cell, mesh.n_face
+    config = G.default_config()
+    solver = G.Solver(mesh, config, device="cuda:0")
+    seed = (torch.from_numpy(W).to("cuda:0"), torch.from_numpy(gW).to("cuda:0"))
+    solver.init(*seed)
+    sums0 = solver.conservation_sums()
+    print(f"headline: blast {nc} cells, {args.warmup} + {args.steps} steps", file=sys.stderr, flush=True)
 
     # each step: dt = CFL bound on the device, then both stages with that dt;
     # the timed region runs uninstrumented, then the same number of steps
     # runs with HIP events around every kernel for the per-kernel durations
-    for _ in range(args.warmup):
-        solver.step_cfl(0.5)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        solver.step_cfl(0.5)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    run_steps(solver, args.warmup, seed)
+    elapsed = run_steps(solver, args.steps, seed)
     Wf, _ = solver.read_state()
-    kt, el_instr = timed_kernels(solver, args.steps)
+    sums1 = solver.conservation_sums()
+    kt, el_instr = timed_kernels(solver, args.steps, seed)
     assert np.isfinite(Wf).all()
 
-    flops_face = G.flux_op_count(config)["total"]
     copy_gbs = copy_bandwidth(torch)
+    op_count = G.flux_op_count(config)["total"]
+    full = args.n == 64
+    # executed FP64 work of the flux kernel per face: rocprofv3 counts of the
+    # FP64 add, multiply, FMA (2 FLOP) and transcendental instructions of
+    # both launches per stage, times 64 lanes, over the faces
+    executed = summary_value(VALU, "flux_stage1", "executed FP64 FLOP per face") if full else None
+    flops_face = executed if executed is not None else op_count
     units = {"cell": nc, "face": nf}
-    kernels = {}
-    for k, (ms, cnt) in kt.items():
-        if cnt == 0:
-            continue
-        avg_s = ms / cnt * 1e-3
-        nbytes = BYTES_PER_UNIT[k] * units[UNIT[k]]
-        entry = {"avg_ms": ms / cnt, "launches": cnt, "total_ms": ms,
-                 "bytes_per_launch": nbytes, "hbm_GBs": nbytes / avg_s / 1e9}
-        if k.startswith("flux"):
-            entry["flops_per_launch"] = flops_face * nf
-            entry["fp64_TFLOPs"] = flops_face * nf / avg_s / 1e12
-        else:
-            entry["frac_of_copy"] = entry["hbm_GBs"] / copy_gbs
-        kernels[k] = entry
+    kernels = kernel_rates(kt, units, copy_gbs, flops_face)
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     d = kernels[dom]
-    traffic = measured_traffic(dom) if args.n == 32 else None
+    traffic = summary_value(TRAFFIC, dom, "scaled bytes per launch") if full else None
     if dom.startswith("flux"):
         roof = {"kernel": dom, "bound": "alu", "achieved": d["fp64_TFLOPs"],
                 "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": d["fp64_TFLOPs"] / FP64_VECTOR_TFLOPS, "traffic": traffic,
-                "work_per_launch": f"{flops_face:.0f} FP64 ops/face x {nf} faces"}
+                "work_source": ("executed FP64 FLOP from rocprofv3 counters (profiles/"
+                                "blast_walls_1572864_valu_f64.md)" if executed is not None else
+                                "source operation count of the flux routine (gks_flux_op_count)"),
+                "work_per_launch": f"{flops_face:.0f} FP64 FLOP/face x {nf} faces",
+                "executed_fp64_flop_per_face": executed, "algorithmic_fp64_flop_per_face":
+                FLUX_ALGORITHMIC_FLOP_PER_FACE, "source_op_count_per_face": op_count,
+                "algorithmic_frac": FLUX_ALGORITHMIC_FLOP_PER_FACE * nf / (d["avg_ms"] * 1e-3) / 1e12
+                / FP64_VECTOR_TFLOPS}
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": d["hbm_GBs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": d["hbm_GBs"] / HBM_PEAK_GBS, "frac_of_copy": d["frac_of_copy"],
-                "traffic": traffic,
-                "work_per_launch": f"{BYTES_PER_UNIT[dom]} B/{UNIT[dom]} x {units[UNIT[dom]]}"}
-
+                "traffic": traffic, "work_per_launch": f"{BYTES_PER_UNIT[dom]} B/{UNIT[dom]} x {units[UNIT[dom]]}"}
     value = nc * 2 * args.steps / elapsed
 
     fp32 = None
     if not args.no_fp32:
-        # FP32-bulk leg: the same workload, steps and time-step rule; its
-        # density L1 difference from the FP64 run and conservation drift
-        s32 = G.Solver(mesh, G.default_config(precision=G.GKS_FP32_BULK, **cfg_kw), device="cuda:0")
-        s32.init(W, gW)
-        sums0 = s32.conservation_sums()
-        for _ in range(args.warmup):
-            s32.step_cfl(0.5)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            s32.step_cfl(0.5)
-        torch.cuda.synchronize()
-        el32 = time.perf_counter() - t1
+        s32 = G.Solver(mesh, G.default_config(precision=G.GKS_FP32_BULK), device="cuda:0")
+        s32.init(*seed)
+        a0 = s32.conservation_sums()
+        run_steps(s32, args.warmup, seed)
+        el32 = run_steps(s32, args.steps, seed)
         W32, _ = s32.read_state()
-        sums1 = s32.conservation_sums()
-        kt32, _ = timed_kernels(s32, args.steps)
+        a1 = s32.conservation_sums()
+        kt32, _ = timed_kernels(s32, args.steps, seed)
         vol = I_cell_volumes(mesh)
         fp32 = {"value": nc * 2 * args.steps / el32, "unit": "cell-stage-updates/s",
                 "ms_per_step": el32 / args.steps * 1e3, "speedup_vs_fp64": elapsed / el32,
-                "l1_density_vs_fp64": float(np.sum(vol * np.abs(W32[0] - Wf[0])) / np.sum(vol * Wf[0])),
-                "conservation_drift": float(np.max(np.abs(sums1 - sums0) / np.abs(sums0).max())),
+                "l1_density_vs_fp64_same_steps": float(np.sum(vol * np.abs(W32[0] - Wf[0])) / np.sum(vol * Wf[0])),
+                "mass_energy_drift": float(max(abs(a1[q] - a0[q]) / abs(a0[q]) for q in (0, 4))),
                 "dtype": "fp32 bulk / fp64 state",
-                "kernels_ms": {k: ms / cnt for k, (ms, cnt) in kt32.items() if cnt}}
+                "kernels_ms": {k: ms / c for k, (ms, c) in kt32.items() if c}}
+        del s32
     out = {
         "metric": "cell-stage-updates/s",
         "value": value,
@@ -514,33 +665,49 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"viscous Taylor-Green vortex, [0,2pi]^3 periodic, {args.n}^3 hexes "
-                               f"x 6 Kuhn tets ({nc} cells, {nf} faces), 5% jitter, Ma 0.1, "
-                               "Re 1600, Pr 0.72, CFL 0.5, third-order MR-WENO, FP64",
+        "config": {"workload": f"spherical blast with reflective walls, unit cube, {args.n}^3 hexes x 6 Kuhn tets "
+                               f"({nc} cells, {nf} faces), 10% jitter (seed 2), slip walls, Euler, "
+                               "(rho, p) = (1, 10) inside r < 0.1 and (1, 0.1) outside, third-order MR-WENO "
+                               "with nonlinear weights and positivity fallback, CFL 0.5, FP64; the timed "
+                               f"steps restart from the initial state every {RESEED} steps",
                    "cells": nc, "faces": nf, "precision": "fp64"},
         "roofline": roof,
         "hbm_copy_GBs": copy_gbs,
         "kernels": kernels,
+        "mass_energy_drift": float(max(abs(sums1[q] - sums0[q]) / abs(sums0[q]) for q in (0, 4))),
+        "restart_every_steps": RESEED,
+        "fp32_bulk": fp32,
     }
-    out["fp32_bulk"] = fp32
-    if args.adjoint_steps > 0:
-        adj, g64 = adjoint_leg(G, I, mesh, W, gW, cfg_kw, args.adjoint_steps, args.adjoint_directions,
-                               G.GKS_FP64)
-        adj32, g32 = adjoint_leg(G, I, mesh, W, gW, cfg_kw, args.adjoint_steps, 0, G.GKS_FP32_BULK)
+    del solver
+    torch.cuda.empty_cache()
+    print("blast to t_end", file=sys.stderr, flush=True)
+    out["blast_to_t_end"] = blast_to_time(G, I, mesh, W, gW, args.t_end) if args.t_end > 0 else None
+    torch.cuda.empty_cache()
+    tgv = None
+    if args.tgv_n > 0:
+        print("taylor-green", file=sys.stderr, flush=True)
+        out["taylor_green"], tgv = taylor_green_leg(G, I, args.tgv_n, args.steps, args.warmup, copy_gbs)
+    if args.adjoint_steps > 0 and tgv is not None:
+        print("adjoint", file=sys.stderr, flush=True)
+        tm, tW, tgW, tkw = tgv
+        adj, g64 = adjoint_leg(G, I, tm, tW, tgW, tkw, args.adjoint_steps, args.adjoint_directions, G.GKS_FP64)
+        adj32, g32 = adjoint_leg(G, I, tm, tW, tgW, tkw, args.adjoint_steps, 0, G.GKS_FP32_BULK)
         adj["fp32_bulk"] = {k: adj32[k] for k in ("forward_ms_per_step", "adjoint_ms_per_step",
                                                   "adjoint_over_forward")}
         adj["fp32_bulk"]["gradient_rel_diff_vs_fp64"] = max(
             float((a - b).abs().max() / a.abs().max()) for a, b in zip(g64, g32))
+        adj["tangent_reference"] = tangent_reference_leg(G, I)
         out["adjoint"] = adj
     else:
         out["adjoint"] = None
-    out["blast_walls"] = (blast_leg(G, I, args.blast_n, args.blast_steps, 2, copy_gbs)
-                          if args.blast_n > 0 else None)
+    torch.cuda.empty_cache()
+    print("cavity, sphere", file=sys.stderr, flush=True)
     out["cavity_noslip"] = cavity_leg(G, I, args.cavity_n, args.cavity_steps, 2) if args.cavity_n > 0 else None
     out["sphere_farfield"] = (sphere_leg(G, I, args.sphere_n, args.sphere_layers, args.sphere_steps, 1)
                               if args.sphere_n > 0 else None)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh, W, gW, cfg_kw, args.cpu_baseline_steps)
+        print("cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(I, mesh, W, gW, {}, args.cpu_baseline_steps, args.cpu_serial_n)
     else:
         out["cpu_baseline"] = None
     if args.calibrate_copy:

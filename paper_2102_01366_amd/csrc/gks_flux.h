@@ -662,10 +662,12 @@ struct WallBC {
 // On a wall face (no neighbour; cr is not evaluated) the right state is the
 // ghost of the left one: the slip-wall mirror, or the no-slip reflection
 // when bc says so.
-template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR, bool SMOOTH = false>
+// RAW: write |Gamma| w_k F_k(dt), F_k(dt/2) in place of the fitted flux and
+// its time derivative (debug exports only)
+template <typename R, bool VISC, bool PRFIX, typename CoefL, typename CoefR, bool SMOOTH = false, bool RAW = false>
 GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, const R r[3], const R dv[3],
                               const CoefL &cl, const CoefR &cr, R acc[4][5], bool wall = false,
-                              const WallBC<R> *bc = nullptr, bool raw = false)
+                              const WallBC<R> *bc = nullptr)
 {
     const R w = area * R(1.0 / 3.0);
     R T[3][3];
@@ -703,7 +705,7 @@ GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, con
     const R idt = R(1) / dt;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        if (raw) {  // the time integrals F(dt), F(dt/2) themselves, before the fit
+        if (RAW) {  // the time integrals F(dt), F(dt/2) themselves, before the fit
             acc[0][q] = w * F1[q];
             acc[1][q] = w * Fh[q];
         } else {

@@ -30,9 +30,13 @@ struct DevCoef {
 #define GKS_FLUX_THREADS 64
 #endif
 constexpr int kFluxThreads = GKS_FLUX_THREADS;
-#ifndef GKS_FLUX_MIN_WAVES
-#define GKS_FLUX_MIN_WAVES 1
+// Wavefronts per SIMD the compiler must fit (registers): the Euler flux
+// (VISC false) fits two when a few registers spill; the Navier-Stokes form one
+#ifndef GKS_FLUX_EULER_WAVES
+#define GKS_FLUX_EULER_WAVES 1
 #endif
+template <bool VISC>
+constexpr int flux_min_waves() { return VISC ? 1 : GKS_FLUX_EULER_WAVES; }
 constexpr int kFacesPerWave = 21;
 constexpr int kFacesPerBlock = kFacesPerWave * (kFluxThreads / 64);
 
@@ -41,7 +45,7 @@ constexpr int kFacesPerBlock = kFacesPerWave * (kFluxThreads / 64);
 // raw (debug launches only): write |Gamma| sum_k w_k F_k(dt) and F_k(dt/2)
 // instead of the fitted flux and its time derivative.
 template <typename R, int MODE, bool VISC, bool PRFIX, bool WALL, bool SMOOTH>
-__global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(DevMesh m, DevState s, Params p, double dt_,
+__global__ __launch_bounds__(kFluxThreads, flux_min_waves<VISC>()) void flux_kernel(DevMesh m, DevState s, Params p, double dt_,
                                                                              const double *dtp, int raw)
 {
     const int nf = m.nf, n = m.nc;
@@ -73,9 +77,18 @@ __global__ __launch_bounds__(kFluxThreads, GKS_FLUX_MIN_WAVES) void flux_kernel(
 #pragma unroll
             for (int d = 0; d < 3; ++d) bc.u[d] = static_cast<const R *>(m.wvel)[(size_t)d * nw + w];
         }
-        gauss_point_terms<R, VISC, PRFIX, DevCoef<R>, DevCoef<R>, SMOOTH>(
-            p, dt, nrm, area, r, dv, DevCoef<R>{coef, n, L}, DevCoef<R>{coef, n, WALL ? L : Rc}, acc, WALL, &bc,
-            MODE == FLUX_DEBUG && raw != 0);
+        const DevCoef<R> cl{coef, n, L}, cr{coef, n, WALL ? L : Rc};
+        if constexpr (MODE == FLUX_DEBUG) {
+            if (raw)
+                gauss_point_terms<R, VISC, PRFIX, DevCoef<R>, DevCoef<R>, SMOOTH, true>(p, dt, nrm, area, r, dv, cl, cr,
+                                                                                         acc, WALL, &bc);
+            else
+                gauss_point_terms<R, VISC, PRFIX, DevCoef<R>, DevCoef<R>, SMOOTH>(p, dt, nrm, area, r, dv, cl, cr, acc,
+                                                                                  WALL, &bc);
+        } else {
+            gauss_point_terms<R, VISC, PRFIX, DevCoef<R>, DevCoef<R>, SMOOTH>(
+                p, dt, nrm, area, r, dv, DevCoef<R>{coef, n, L}, DevCoef<R>{coef, n, WALL ? L : Rc}, acc, WALL, &bc);
+        }
     } else {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
