@@ -196,6 +196,19 @@ gks_status gks_read_state(gks_ctx *ctx, double *W, double *gW, int32_t on_device
  * (blocking). */
 gks_status gks_conservation_sums(gks_ctx *ctx, double out[5]);
 
+/* For callers that cannot allocate device memory or synchronise with the
+ * host (code under HIP graph capture, tight serving loops): the sums of
+ * gks_conservation_sums written to out_device[5], a DEVICE pointer, on the
+ * context's stream without a host synchronisation and without any
+ * allocation.  The per-block partial sums live in a fixed device array of the
+ * library (2.5 MiB per device, kept until the process ends), which limits the
+ * mesh to 16,777,216 cells (GKS_E_INVAL beyond, with the limit in
+ * gks_last_error).  Every call on a device shares that array: calls that
+ * overlap on one GPU (several streams or threads) race.  Same sums as
+ * gks_conservation_sums up to rounding order (a fixed order per mesh, so
+ * bitwise reproducible).  The non-physical flag is not read here. */
+gks_status gks_conservation_sums_noalloc(gks_ctx *ctx, double *out_device);
+
 /* Intermediate results of the current state, for parity checks, in the
  * caller's order (host or device pointers as on_device says):
  *   slopes[15][n]  reconstruction step 1 (component c, direction d at 3c+d);

@@ -39,7 +39,7 @@ EXPORTS = ("gks_default_config", "gks_create", "gks_destroy", "gks_set_stream",
            "gks_mesh_upload", "gks_workspace_bytes", "gks_bind_workspace", "gks_init",
            "gks_compute_dt", "gks_stage", "gks_step", "gks_step_cfl", "gks_last_dt",
            "gks_adjoint_workspace_bytes", "gks_bind_adjoint_workspace", "gks_step_adjoint",
-           "gks_read_state",
+           "gks_read_state", "gks_conservation_sums_noalloc",
            "gks_conservation_sums", "gks_debug_reconstruct", "gks_debug_face_terms", "gks_debug_flux_integrals",
            "gks_timing_enable", "gks_timing_read", "gks_flux_op_count", "gks_flux_point_check",
            "gks_flux_face_check", "gks_weno_check", "gks_wall_ghost_check", "gks_last_error",
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH):
         "gks_last_dt": (S, [P, P]),
         "gks_read_state": (S, [P, P, P, I32]),
         "gks_conservation_sums": (S, [P, P]),
+        "gks_conservation_sums_noalloc": (S, [P, P]),
         "gks_debug_reconstruct": (S, [P, P, P, P, I32]),
         "gks_debug_face_terms": (S, [P, D, P, I32]),
         "gks_debug_flux_integrals": (S, [P, D, P, I32]),

@@ -19,7 +19,7 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgks.so")
 SOURCES = [os.path.join(CSRC, f) for f in (
     "gks_adjoint_flux_f64.hip", "gks_adjoint_flux_f32.hip", "gks_flux_f64.hip", "gks_flux_f32.hip",
-    "gks_adjoint.hip", "gks_kernels.hip", "gks_check.cpp", "gks_api.cpp", "gks_opcount.cpp")]
+    "gks_adjoint.hip", "gks_kernels.hip", "gks_noalloc.hip", "gks_check.cpp", "gks_api.cpp", "gks_opcount.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for all device code.

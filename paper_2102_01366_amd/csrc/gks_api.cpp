@@ -1394,6 +1394,19 @@ gks_status gks_conservation_sums(gks_ctx *c, double out[5])
     return GKS_OK;
 }
 
+gks_status gks_conservation_sums_noalloc(gks_ctx *c, double *out_device)
+{
+    gks_status st = ready(c, true);
+    if (st) return st;
+    if (!out_device) return fail(c, GKS_E_INVAL, "null output pointer");
+    if ((int64_t)c->nc > gks::noalloc_max_cells())
+        return fail(c, GKS_E_INVAL, "gks_conservation_sums_noalloc: " + std::to_string(c->nc) +
+                                        " cells exceed the fixed scratch of " +
+                                        std::to_string(gks::noalloc_max_cells()) + " cells");
+    HIP_TRY(c, gks::launch_sums_noalloc(c->dm, c->ds, out_device, c->stream));
+    return GKS_OK;
+}
+
 // scatter bulk rows (widened to double) to the caller's order
 static gks_status export_rows(gks_ctx *c, double *dst, const void *src, const int *perm, int n,
                               int rows, int on_device)

@@ -160,6 +160,11 @@ hipError_t launch_dt(const DevMesh &m, const DevState &s, const Params &p, doubl
                      hipStream_t st);
 // conservation sums: writes sum_i |Omega_i| W_i to s.red[0..4]
 hipError_t launch_sums(const DevMesh &m, const DevState &s, hipStream_t st);
+// conservation sums without allocation (gks_noalloc.hip): per-block partials
+// in a fixed device array, the five sums written to out (device); at most
+// noalloc_max_cells() cells (hipErrorInvalidValue beyond)
+int64_t noalloc_max_cells();
+hipError_t launch_sums_noalloc(const DevMesh &m, const DevState &s, double *out, hipStream_t st);
 // physical check of the state: sets *s.nonphys when rho <= 0 or p <= 0
 hipError_t launch_check(const DevMesh &m, const DevState &s, const Params &p, hipStream_t st);
 // dst[r][perm[i]] = src[r][i] (scatter to caller order) or dst[r][i] = src[r][perm[i]]
