@@ -357,16 +357,24 @@ GKS_HD void side_terms(const Params &p, const Prim<R> &g, R m0, R m1, const R gr
     add_part<R, PRFIX>(p, g.rho, tc.cF[0] + 3, tc.cF[1] + 3, cW0, tc.cW + 3, F, V, Uc, Fo, Wo);
 }
 
-// Time-dependent distribution of eq. 2nd-flux (SMOOTH: of eq.
-// 2nd-smooth-flux) at one interface point, face frame.  Outputs: Fo[0] =
-// F(dt), Fo[1] = F(dt/2) (time integrals of the flux), Wo[0] = W(0), Wo[1] =
-// W(dt).
-template <typename R, bool VISC, bool PRFIX, bool SMOOTH = false>
-GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], const R wr[5],
-                      const R gr[3][5], R Fo[2][5], R Wo[2][5])
+// Everything of one interface point that both kinetic sides and the
+// equilibrium part need: the two sides' primitive states and half-line seeds
+// <1>, <u>, the kinetically weighted equilibrium g^c (eq. new-equ-part) and
+// the time coefficients of its collision times.
+template <typename R>
+struct PointSetup {
+    Prim<R> gL, gR, gC;
+    R l0, l1, r0, r1;
+    TimeCoef<R> tc;
+};
+
+template <typename R, bool VISC, bool SMOOTH = false>
+GKS_HD void point_setup(const Params &p, R dt, const R wl[5], const R wr[5], PointSetup<R> &S)
 {
     const R K = R(p.K);
     const Prim<R> gL = primitive(wl, K), gR = primitive(wr, K);
+    S.gL = gL;
+    S.gR = gR;
     // half-line seeds <1> and <u> of both sides
     R l0, l1, r0, r1;
     {
@@ -380,6 +388,10 @@ GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], co
         r0 = R(0.5) * erfc(sr * gR.U);
         r1 = gR.U * r0 - f;
     }
+    S.l0 = l0;
+    S.l1 = l1;
+    S.r0 = r0;
+    S.r1 = r1;
     // eq. new-equ-part: W^c = rho_l <psi>_{u>0} + rho_r <psi>_{u<0}
     R Wc[5];
     {
@@ -394,12 +406,11 @@ GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], co
         Wc[4] = gL.rho * (R(0.5) * (l2 + l0 * tl)) + gR.rho * (R(0.5) * (r2 + r0 * tr));
     }
     const Prim<R> gC = primitive(Wc, K);
-    const R Uc[3] = {gC.U, gC.V, gC.W};
+    S.gC = gC;
     // collision times (Sec. 2.2)
     const R pl = gL.rho * R(0.5) * gL.ilam, pr = gR.rho * R(0.5) * gR.ilam, pc = gC.rho * R(0.5) * gC.ilam;
-    TimeCoef<R> tc;
     if constexpr (SMOOTH) {
-        time_coefficients_smooth<R>(VISC ? R(p.mu) / pc : R(0), dt, tc);
+        time_coefficients_smooth<R>(VISC ? R(p.mu) / pc : R(0), dt, S.tc);
     } else {
         const R jump = R(p.c_tau) * fabs((pl - pr) / (pl + pr)) * dt;
         R tau, taun;
@@ -410,20 +421,18 @@ GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], co
             tau = R(0);
             taun = R(p.eps_tau) * dt + jump;
         }
-        time_coefficients<R, VISC>(tau, taun, dt, tc);
+        time_coefficients<R, VISC>(tau, taun, dt, S.tc);
     }
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int q = 0; q < 5; ++q) Fo[k][q] = Wo[k][q] = R(0);
-    R gc[3][5];
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int q = 0; q < 5; ++q) gc[d][q] = R(0);
-    side_terms<R, VISC, PRFIX, SMOOTH>(p, gL, l0, l1, gl, tc, Uc, gc, Fo, Wo);
-    side_terms<R, VISC, PRFIX, SMOOTH>(p, gR, r0, r1, gr, tc, Uc, gc, Fo, Wo);
-    // equilibrium part: g^c with slopes a^c (from g^c_x) and A^c
+}
+
+// The equilibrium part of eq. 2nd-flux: g^c with slopes a^c (from g^c_x,
+// gc) and A^c, added to Fo and Wo.
+template <typename R, bool PRFIX, bool SMOOTH = false>
+GKS_HD void equilibrium_terms(const Params &p, const Prim<R> &gC, const TimeCoef<R> &tc, const R gc[3][5],
+                              R Fo[2][5], R Wo[2][5])
+{
+    const R K = R(p.K);
+    const R Uc[3] = {gC.U, gC.V, gC.W};
     Tab<R> TC;
     gauss_moments_h<7>(gC.U, R(0.5) * gC.ilam, TC.u);
     vw_tables(gC, K, TC);
@@ -460,6 +469,31 @@ GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], co
     psi_mom<0, 0, 0>(TC, V[0]);
     const R cW0[3] = {SMOOTH ? R(1) : R(0), SMOOTH ? -tc.tau : R(0), SMOOTH ? -tc.tau : R(0)};
     add_part<R, PRFIX>(p, gC.rho, tc.cF[0], tc.cF[1], cW0, tc.cW, F, V, Uc, Fo, Wo);
+}
+
+// Time-dependent distribution of eq. 2nd-flux (SMOOTH: of eq.
+// 2nd-smooth-flux) at one interface point, face frame.  Outputs: Fo[0] =
+// F(dt), Fo[1] = F(dt/2) (time integrals of the flux), Wo[0] = W(0), Wo[1] =
+// W(dt).
+template <typename R, bool VISC, bool PRFIX, bool SMOOTH = false>
+GKS_HD void gks_point(const Params &p, R dt, const R wl[5], const R gl[3][5], const R wr[5],
+                      const R gr[3][5], R Fo[2][5], R Wo[2][5])
+{
+    PointSetup<R> S;
+    point_setup<R, VISC, SMOOTH>(p, dt, wl, wr, S);
+    const R Uc[3] = {S.gC.U, S.gC.V, S.gC.W};
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) Fo[k][q] = Wo[k][q] = R(0);
+    R gc[3][5];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) gc[d][q] = R(0);
+    side_terms<R, VISC, PRFIX, SMOOTH>(p, S.gL, S.l0, S.l1, gl, S.tc, Uc, gc, Fo, Wo);
+    side_terms<R, VISC, PRFIX, SMOOTH>(p, S.gR, S.r0, S.r1, gr, S.tc, Uc, gc, Fo, Wo);
+    equilibrium_terms<R, PRFIX, SMOOTH>(p, S.gC, S.tc, gc, Fo, Wo);
 }
 
 // Whether the face frame uses the cancellation-free form of 1/(1 + n1).
@@ -677,6 +711,7 @@ GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, con
     for (int d = 0; d < 3; ++d) rr[d] = r[d] + dv[d];
     R wl[5], gl[3][5], wr[5], gr[3][5];
     eval_local(cl, r, T, wl, gl);
+    R Fo[2][5], Wo[2][5];
     if (wall && bc && bc->tag == WALL_FARFIELD) {
         R wf[5];
         wf[0] = R(p.farfield[0]);
@@ -695,7 +730,6 @@ GKS_HD void gauss_point_terms(const Params &p, R dt, const R nrm[3], R area, con
     } else {
         eval_local(cr, rr, T, wr, gr);
     }
-    R Fo[2][5], Wo[2][5];
     gks_point<R, VISC, PRFIX, SMOOTH>(p, dt, wl, gl, wr, gr, Fo, Wo);
     R F1[5], Fh[5], W0[5], W1[5];
     to_global(T, Fo[0], F1);
