@@ -235,14 +235,19 @@ class Oracle:
         (interface values weighted by |Gamma|): stage 1 sums (W_k(0) +
         W_k(dt)) / 2, stage 2 sums W1_k(0) + W2_k(dt) - W2_k(0), ft1 the face
         terms of stage 1.  The momentum components share one bound (the face
-        frame mixes them).  Two correct FP64 evaluations of the gradient
-        differ by rounding relative to this bound, not to the gradient."""
+        frame mixes them), which also counts the thermal momentum scale
+        sqrt(|rho| |rho E|): the interface momentum is a sum of the two
+        half-space momenta of the kinetic weighting (eq. new-equ-part), of
+        that size and opposite signs, so its rounding is relative to them even
+        where the gas is at rest.  Two correct FP64 evaluations of the
+        gradient differ by rounding relative to this bound, not to the
+        gradient."""
         ft = self.last_face_terms()
         if stage == 1:
             a = 0.5 * (np.abs(ft[10:15]) + np.abs(ft[15:20]))
         else:
             a = np.abs(ft1[10:15]) + np.abs(ft[15:20]) + np.abs(ft[10:15])
-        a[1:4] = a[1:4].sum(axis=0)
+        a[1:4] = a[1:4].sum(axis=0) + np.sqrt(a[0] * a[4])
         vol = self.geometry()[0]
         nrm = np.abs(self.face_geometry()[1])
         fc = self._keep[3].reshape(-1, 2)
