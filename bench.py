@@ -200,18 +200,25 @@ def adjoint_leg(G, I, mesh, W, gW, cfg_kw, nsteps, ndir, precision):
         torch.cuda.synchronize()
         return Wr.grad.detach(), Gr.grad.detach(), time.perf_counter() - t1
 
-    def fd_check(s, dts, gW_, gG_, steps_eps):
+    def fd_check(s, dts, gW_, gG_, steps_eps, order=2):
+        """central differences (f(e) - f(-e)) / 2e, or with order 4
+        (8 (f(e) - f(-e)) - (f(2e) - f(-2e))) / 12e, against the adjoint"""
         dW, dG = I.rms_directions(W, gW, ndir, 4)
         errs = {e: [] for e in steps_eps}
+
+        def J(vW, vG, e):
+            with torch.no_grad():
+                return ke(rollout(s, W0 + e * vW, G0 + e * vG, dts)[0]).item()
         for k in range(ndir):
             vW, vG = torch.from_numpy(dW[k]).to(dev), torch.from_numpy(dG[k]).to(dev)
             ad = ((gW_ * vW).sum() + (gG_ * vG).sum()).item()
             for eps in steps_eps:
-                with torch.no_grad():
-                    Jp = ke(rollout(s, W0 + eps * vW, G0 + eps * vG, dts)[0]).item()
-                    Jm = ke(rollout(s, W0 - eps * vW, G0 - eps * vG, dts)[0]).item()
-                errs[eps].append(abs((Jp - Jm) / (2 * eps) - ad) / abs(ad))
-        return [{"eps": eps, "max_rel_err": max(e), "median_rel_err": float(np.median(e))}
+                if order == 2:
+                    fd = (J(vW, vG, eps) - J(vW, vG, -eps)) / (2 * eps)
+                else:
+                    fd = (8 * (J(vW, vG, eps) - J(vW, vG, -eps)) - (J(vW, vG, 2 * eps) - J(vW, vG, -2 * eps))) / (12 * eps)
+                errs[eps].append(abs(fd - ad) / abs(ad))
+        return [{"eps": eps, "order": order, "max_rel_err": max(e), "median_rel_err": float(np.median(e))}
                 for eps, e in errs.items()]
 
     s = G.Solver(mesh, G.default_config(precision=precision, **cfg_kw), device=dev)
@@ -240,7 +247,7 @@ def adjoint_leg(G, I, mesh, W, gW, cfg_kw, nsteps, ndir, precision):
                       device=dev)
         gWs, gGs, _ = gradient(sm, dts)
         out["fd_smooth_map"] = {"config": "collision-time jump off (C = 0), WENO eps = 1",
-                                "checks": fd_check(sm, dts, gWs, gGs, (1e-6,))}
+                                "checks": fd_check(sm, dts, gWs, gGs, (1e-6,)) + fd_check(sm, dts, gWs, gGs, (1e-5,), 4)}
     return out, (gWa, gGa)
 
 
@@ -632,6 +639,18 @@ def main():
                 "unit": "GB/s", "frac": d["hbm_GBs"] / HBM_PEAK_GBS, "frac_of_copy": d["frac_of_copy"],
                 "traffic": traffic, "work_per_launch": f"{BYTES_PER_UNIT[dom]} B/{UNIT[dom]} x {units[UNIT[dom]]}"}
     value = nc * 2 * args.steps / elapsed
+    # the flux's own roofline (both stages' kernels), beside the dominant kernel's
+    f1 = kernels.get("flux_stage1")
+    flux_roof = None if f1 is None else {
+        "kernel": "flux_stage1", "bound": "alu", "achieved": f1["fp64_TFLOPs"], "peak": FP64_VECTOR_TFLOPS,
+        "unit": "TFLOP/s", "frac": f1["fp64_TFLOPs"] / FP64_VECTOR_TFLOPS,
+        "traffic": summary_value(TRAFFIC, "flux_stage1", "scaled bytes per launch") if full else None,
+        "work_per_launch": f"{flops_face:.0f} FP64 FLOP/face x {nf} faces",
+        "work_source": roof.get("work_source") if dom.startswith("flux") else (
+            "executed FP64 FLOP from rocprofv3 counters (profiles/blast_walls_1572864_valu_f64.md)"
+            if executed is not None else "source operation count of the flux routine (gks_flux_op_count)"),
+        "executed_fp64_flop_per_face": executed, "algorithmic_fp64_flop_per_face": FLUX_ALGORITHMIC_FLOP_PER_FACE,
+        "source_op_count_per_face": op_count}
 
     fp32 = None
     if not args.no_fp32:
@@ -672,6 +691,7 @@ def main():
                                f"steps restart from the initial state every {RESEED} steps",
                    "cells": nc, "faces": nf, "precision": "fp64"},
         "roofline": roof,
+        "flux_roofline": flux_roof,
         "hbm_copy_GBs": copy_gbs,
         "kernels": kernels,
         "mass_energy_drift": float(max(abs(sums1[q] - sums0[q]) / abs(sums0[q]) for q in (0, 4))),
