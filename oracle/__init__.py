@@ -111,6 +111,8 @@ def _load():
         I64 = ctypes.c_int64
         L.or_create.restype = P
         L.or_create.argtypes = [ctypes.POINTER(Config), I64, P, I64, P, I64, P, P, P, P, P]
+        L.or_create_quadratic.restype = P
+        L.or_create_quadratic.argtypes = [ctypes.POINTER(Config), I64, P, I64, P, I64, P, P, P, P, P, P]
         L.or_wall_ghost.argtypes = [ctypes.POINTER(Config), ctypes.c_int32, P, P, P, P, P, P]
         L.or_destroy.argtypes = [P]
         L.or_set_threads.argtypes = [ctypes.c_int]
@@ -118,6 +120,7 @@ def _load():
         for name in ("or_geometry",):
             getattr(L, name).argtypes = [P, P, P, P, P]
         L.or_face_geometry.argtypes = [P, P, P, P]
+        L.or_face_points.argtypes = [P, P, P]
         L.or_slopes.argtypes = [P, P, P, P]
         L.or_reconstruct.argtypes = [P, P, P, P, P, P]
         L.or_face_terms.argtypes = [P, P, P, D, P]
@@ -165,9 +168,12 @@ class Oracle:
                       np.ascontiguousarray(mesh.face_shift, np.float64)]
         wu = getattr(mesh, "face_wall_u", None)
         self._keep.append(None if wu is None else np.ascontiguousarray(wu, np.float64))
-        xyz, tet, fv, fc, ft, fs, fw = self._keep
-        self._h = L.or_create(ctypes.byref(cfg), mesh.n_vert, _p(xyz), self.nc, _p(tet),
-                              self.nf, _p(fv), _p(fc), _p(ft), _p(fs), None if fw is None else _p(fw))
+        tm = getattr(mesh, "tet_mid", None)
+        self._keep.append(None if tm is None else np.ascontiguousarray(tm, np.float64))
+        xyz, tet, fv, fc, ft, fs, fw, tmid = self._keep
+        self._h = L.or_create_quadratic(ctypes.byref(cfg), mesh.n_vert, _p(xyz), self.nc, _p(tet),
+                                        self.nf, _p(fv), _p(fc), _p(ft), _p(fs),
+                                        None if fw is None else _p(fw), None if tmid is None else _p(tmid))
         if not self._h:
             raise ValueError("oracle rejected the mesh")
 
@@ -188,6 +194,14 @@ class Oracle:
         area, nrm, gp = np.empty(nf), np.empty((3, nf)), np.empty((3, 3, nf))
         _load().or_face_geometry(self._h, _p(area), _p(nrm), _p(gp))
         return area, nrm, gp
+
+    def face_points(self):
+        """Per Gauss point: unit normals [3 points][3][nf] and weights [3][nf]
+        (the face area included)."""
+        nf = self.nf
+        nrm, w = np.empty((3, 3, nf)), np.empty((3, nf))
+        _load().or_face_points(self._h, _p(nrm), _p(w))
+        return nrm, w
 
     def slopes(self, W, gW=None):
         W = _f64(W)
@@ -232,7 +246,8 @@ class Oracle:
         """Per cell, component and direction, the sum of the magnitudes of the
         terms of the Gauss-theorem gradient (eq. gauss-formula) of the last
         stage run, (1/|Omega_i|) sum over the cell's faces of |W_f| |n_d|
-        (interface values weighted by |Gamma|): stage 1 sums (W_k(0) +
+        (interface values weighted by |Gamma|; on a quadratic face the largest
+        |n_d| of its Gauss points): stage 1 sums (W_k(0) +
         W_k(dt)) / 2, stage 2 sums W1_k(0) + W2_k(dt) - W2_k(0), ft1 the face
         terms of stage 1.  The momentum components share one bound (the face
         frame mixes them), which also counts the thermal momentum scale
@@ -249,7 +264,8 @@ class Oracle:
             a = np.abs(ft1[10:15]) + np.abs(ft[15:20]) + np.abs(ft[10:15])
         a[1:4] = a[1:4].sum(axis=0) + np.sqrt(a[0] * a[4])
         vol = self.geometry()[0]
-        nrm = np.abs(self.face_geometry()[1])
+        # the largest |n_d| over the face's Gauss points (one normal on a flat face)
+        nrm = np.abs(self.face_points()[0]).max(axis=0)
         fc = self._keep[3].reshape(-1, 2)
         B = np.zeros((15, self.nc))
         for side in (0, 1):
@@ -352,6 +368,8 @@ def _load_tangent():
         I64 = ctypes.c_int64
         L.or_create.restype = P
         L.or_create.argtypes = [ctypes.POINTER(Config), I64, P, I64, P, I64, P, P, P, P, P]
+        L.or_create_quadratic.restype = P
+        L.or_create_quadratic.argtypes = [ctypes.POINTER(Config), I64, P, I64, P, I64, P, P, P, P, P, P]
         L.or_destroy.argtypes = [P]
         L.or_step.argtypes = [P, D, P, P]
         L.or_tangent_ndir.restype = ctypes.c_int
@@ -382,9 +400,12 @@ class TangentOracle:
                       np.ascontiguousarray(mesh.face_shift, np.float64)]
         wu = getattr(mesh, "face_wall_u", None)
         self._keep.append(None if wu is None else np.ascontiguousarray(wu, np.float64))
-        xyz, tet, fv, fc, ft, fs, fw = self._keep
-        self._h = L.or_create(ctypes.byref(cfg), mesh.n_vert, _p(xyz), self.nc, _p(tet),
-                              mesh.n_face, _p(fv), _p(fc), _p(ft), _p(fs), None if fw is None else _p(fw))
+        tm = getattr(mesh, "tet_mid", None)
+        self._keep.append(None if tm is None else np.ascontiguousarray(tm, np.float64))
+        xyz, tet, fv, fc, ft, fs, fw, tmid = self._keep
+        self._h = L.or_create_quadratic(ctypes.byref(cfg), mesh.n_vert, _p(xyz), self.nc, _p(tet),
+                                        mesh.n_face, _p(fv), _p(fc), _p(ft), _p(fs),
+                                        None if fw is None else _p(fw), None if tmid is None else _p(tmid))
         if not self._h:
             raise ValueError("oracle rejected the mesh")
 

@@ -7,7 +7,9 @@
  *
  *   - geometry by the paper's own quadratures (Sec. 2.1 three-point face rule,
  *     Sec. 4.1 five-point volume rule, weight of the centre point read as
- *     -2/15 so that the rule integrates cubics exactly);
+ *     -2/15 so that the rule integrates cubics exactly); with quadratic
+ *     elements (or_create_quadratic) both rules run on the isoparametric
+ *     maps, each face Gauss point with its own normal and weight;
  *   - reconstruction solves the least-squares (step 1) and constrained
  *     least-squares (step 2) systems cell by cell, every stage, by Gaussian
  *     elimination with partial pivoting (Secs. 4.1-4.3);
@@ -33,6 +35,7 @@
  * Riemann-invariant state against the free stream, with zero gradients.
  *
  * Pins (the tests/test_oracle_*.py suites, no GPU): quadrature exactness,
+ * the quadratic elements' closed forms and fourth-order wall convergence,
  * reconstruction exactness on polynomials and the paper's convergence orders,
  * Maxwellian moments against closed forms, the flux against the Euler and
  * Navier-Stokes fluxes of smooth states, conservation, free-stream
@@ -224,6 +227,77 @@ static void tet_avg_monomials(const double v[4][3], const double origin[3], doub
     for (int i = 0; i < 10; ++i) out[i] = s[i] / wsum;
 }
 
+/* Sec. 4.1: the ten shape functions of the quadratic tetrahedron at
+ * xi = (xi, eta, zeta) and their derivatives; control points in the order of
+ * the shape functions: the four vertices, then the points on the edges
+ * (0,1), (1,2), (0,2), (0,3), (1,3), (2,3). */
+static void qtet_shape(const double xi[3], double N[10], double dN[10][3])
+{
+    double a = xi[0], b = xi[1], g = xi[2], L = 1.0 - a - b - g;
+    N[0] = L * (2.0 * L - 1.0);
+    N[1] = a * (2.0 * a - 1.0);
+    N[2] = b * (2.0 * b - 1.0);
+    N[3] = g * (2.0 * g - 1.0);
+    N[4] = 4.0 * a * L;
+    N[5] = 4.0 * a * b;
+    N[6] = 4.0 * b * L;
+    N[7] = 4.0 * g * L;
+    N[8] = 4.0 * g * a;
+    N[9] = 4.0 * g * b;
+    const double d[10][3] = {
+        {1.0 - 4.0 * L, 1.0 - 4.0 * L, 1.0 - 4.0 * L},
+        {4.0 * a - 1.0, 0.0, 0.0},
+        {0.0, 4.0 * b - 1.0, 0.0},
+        {0.0, 0.0, 4.0 * g - 1.0},
+        {4.0 * (L - a), -4.0 * a, -4.0 * a},
+        {4.0 * b, 4.0 * a, 0.0},
+        {-4.0 * b, 4.0 * (L - b), -4.0 * b},
+        {-4.0 * g, -4.0 * g, 4.0 * (L - g)},
+        {4.0 * g, 0.0, 4.0 * a},
+        {0.0, 4.0 * g, 4.0 * b},
+    };
+    memcpy(dN, d, sizeof(d));
+}
+
+/* The isoparametric map of a quadratic tetrahedron with control points x:
+ * X(xi), and |det dX/dxi| there (eq. base-int-change). */
+static double qtet_point(const double x[10][3], const double xi[3], double X[3])
+{
+    double N[10], dN[10][3], J[3][3] = {{0}};
+    qtet_shape(xi, N, dN);
+    for (int d = 0; d < 3; ++d) {
+        X[d] = 0.0;
+        for (int l = 0; l < 10; ++l) {
+            X[d] += N[l] * x[l][d];
+            for (int j = 0; j < 3; ++j) J[d][j] += dN[l][j] * x[l][d];
+        }
+    }
+    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                 J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    return fabs(det);
+}
+
+/* Sec. 2.1: the six shape functions of the quadratic triangle at (xi, eta)
+ * and their derivatives; control points: the three vertices, then the
+ * points on the edges (0,1), (1,2), (0,2). */
+static void qtri_shape(double xi, double eta, double N[6], double dN[6][2])
+{
+    double L = 1.0 - xi - eta;
+    N[0] = L * (2.0 * L - 1.0);
+    N[1] = xi * (2.0 * xi - 1.0);
+    N[2] = eta * (2.0 * eta - 1.0);
+    N[3] = 4.0 * xi * L;
+    N[4] = 4.0 * xi * eta;
+    N[5] = 4.0 * eta * L;
+    const double d[6][2] = {{1.0 - 4.0 * L, 1.0 - 4.0 * L}, {4.0 * xi - 1.0, 0.0}, {0.0, 4.0 * eta - 1.0},
+                            {4.0 * (L - xi), -4.0 * xi}, {4.0 * eta, 4.0 * xi}, {-4.0 * eta, 4.0 * (L - eta)}};
+    memcpy(dN, d, sizeof(d));
+}
+
+/* control-point index of the edge between local vertices a and b */
+static const int QEDGE[4][4] = {{-1, 4, 6, 7}, {4, -1, 5, 8}, {6, 5, -1, 9}, {7, 8, 9, -1}};
+
 /* ======================================================================== */
 /* mesh and geometry                                                        */
 /* ======================================================================== */
@@ -246,8 +320,14 @@ struct or_ctx {
     double *farea;
     double (*fnorm)[3];
     double (*fgp)[3][3];  /* Gauss points, owner frame */
+    double (*fpn)[3][3];  /* unit normal at each Gauss point (outward from the owner) */
+    double (*fpw)[3];     /* weight of each Gauss point: omega_m of Sec. 2.1, the area included */
+    int curved;           /* quadratic elements (control points given) */
+    double (*cx)[10][3];  /* control points of each cell (curved meshes) */
     /* stage storage */
-    real *Wn, *Ln, *Ltn, *FW0; /* W^n [5][nc], L(W^n), dL/dt(W^n), stage-1 W_k(0) sums [5][nf] */
+    real *Wn, *Ln, *Ltn;  /* W^n [5][nc], L(W^n), dL/dt(W^n) */
+    real *FG0;            /* stage 1: sum_k w_k W_k(0) n_k per face [15][nf] */
+    real *fgrad;          /* last face terms: sum_k w_k W_k(0) n_k and sum_k w_k W_k(dt) n_k [30][nf] */
     real *slopes, *coef, *fterm;
     int32_t *flag;
     int have_stage1;
@@ -271,8 +351,8 @@ void or_destroy(or_ctx *c)
     if (!c) return;
     free(c->cv); free(c->vol); free(c->cen); free(c->m2); free(c->dr);
     free(c->nbr); free(c->cface); free(c->noff); free(c->fcell); free(c->ftag); free(c->fwu);
-    free(c->fshift); free(c->farea); free(c->fnorm); free(c->fgp);
-    free(c->Wn); free(c->Ln); free(c->Ltn); free(c->FW0);
+    free(c->fshift); free(c->farea); free(c->fnorm); free(c->fgp); free(c->fpn); free(c->fpw); free(c->cx);
+    free(c->Wn); free(c->Ln); free(c->Ltn); free(c->FG0); free(c->fgrad);
     free(c->slopes); free(c->coef); free(c->fterm); free(c->flag);
     free(c);
 }
@@ -281,6 +361,16 @@ or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
                   int64_t n_cell, const int64_t *tet, int64_t n_face,
                   const int64_t *face_vert, const int64_t *face_cell,
                   const int32_t *face_tag, const double *face_shift, const double *face_wall_u)
+{
+    return or_create_quadratic(cfg, n_vert, xyz, n_cell, tet, n_face, face_vert, face_cell, face_tag,
+                               face_shift, face_wall_u, NULL);
+}
+
+or_ctx *or_create_quadratic(const or_config *cfg, int64_t n_vert, const double *xyz,
+                            int64_t n_cell, const int64_t *tet, int64_t n_face,
+                            const int64_t *face_vert, const int64_t *face_cell,
+                            const int32_t *face_tag, const double *face_shift, const double *face_wall_u,
+                            const double *tet_mid)
 {
     if (!cfg || n_cell <= 0 || n_face <= 0 || n_vert <= 0) return NULL;
     or_ctx *c = (or_ctx *)xcalloc(1, sizeof(or_ctx));
@@ -303,14 +393,19 @@ or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
     c->farea = (__typeof__(c->farea))xcalloc(nf, sizeof(double));
     c->fnorm = (__typeof__(c->fnorm))xcalloc(nf, sizeof(*c->fnorm));
     c->fgp = (__typeof__(c->fgp))xcalloc(nf, sizeof(*c->fgp));
+    c->fpn = (__typeof__(c->fpn))xcalloc(nf, sizeof(*c->fpn));
+    c->fpw = (__typeof__(c->fpw))xcalloc(nf, sizeof(*c->fpw));
     c->Wn = (real *)xcalloc(5 * nc, sizeof(real));
     c->Ln = (real *)xcalloc(5 * nc, sizeof(real));
     c->Ltn = (real *)xcalloc(5 * nc, sizeof(real));
-    c->FW0 = (real *)xcalloc(5 * nf, sizeof(real));
+    c->FG0 = (real *)xcalloc(15 * nf, sizeof(real));
+    c->fgrad = (real *)xcalloc(30 * nf, sizeof(real));
     c->slopes = (real *)xcalloc(15 * nc, sizeof(real));
     c->coef = (real *)xcalloc(50 * nc, sizeof(real));
     c->fterm = (real *)xcalloc(20 * nf, sizeof(real));
     c->flag = (__typeof__(c->flag))xcalloc(nc, sizeof(int32_t));
+    c->curved = tet_mid != NULL;
+    if (c->curved) c->cx = (__typeof__(c->cx))xcalloc(nc, sizeof(*c->cx));
 
     /* cells: |Omega| = |J| / 6, centroid and second moments by the 5-point rule */
     for (int64_t i = 0; i < nc; ++i) {
@@ -321,13 +416,41 @@ or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
         }
         double J = fabs(tet_jac(c->cv[i]));
         if (!(J > 0.0)) { or_destroy(c); return NULL; }
+        for (int a = 0; a < 4; ++a) { c->nbr[i][a] = -1; c->cface[i][a] = -1; }
+        if (c->curved) {
+            /* eq. base-int-change: |Omega|, the centroid and the second moments
+             * by the five-point rule on the isoparametric map */
+            for (int a = 0; a < 4; ++a)
+                for (int d = 0; d < 3; ++d) c->cx[i][a][d] = c->cv[i][a][d];
+            for (int e = 0; e < 6; ++e)
+                for (int d = 0; d < 3; ++d) c->cx[i][4 + e][d] = tet_mid[(6 * i + e) * 3 + d];
+            double X[5][3], w[5], V = 0.0, cen[3] = {0, 0, 0}, m2[6] = {0, 0, 0, 0, 0, 0};
+            for (int q = 0; q < 5; ++q) {
+                double dj = qtet_point(c->cx[i], VQ_PTS[q], X[q]);
+                if (!(dj > 0.0)) { or_destroy(c); return NULL; }
+                w[q] = VQ_W[q] * dj;
+                V += w[q];
+            }
+            if (!(V > 0.0)) { or_destroy(c); return NULL; }
+            for (int q = 0; q < 5; ++q)
+                for (int d = 0; d < 3; ++d) cen[d] += w[q] * X[q][d];
+            for (int d = 0; d < 3; ++d) cen[d] /= V;
+            for (int q = 0; q < 5; ++q) {
+                double r[3] = {X[q][0] - cen[0], X[q][1] - cen[1], X[q][2] - cen[2]};
+                m2[0] += w[q] * r[0] * r[0]; m2[1] += w[q] * r[1] * r[1]; m2[2] += w[q] * r[2] * r[2];
+                m2[3] += w[q] * r[0] * r[1]; m2[4] += w[q] * r[0] * r[2]; m2[5] += w[q] * r[1] * r[2];
+            }
+            c->vol[i] = V;
+            for (int d = 0; d < 3; ++d) c->cen[i][d] = cen[d];
+            for (int k = 0; k < 6; ++k) c->m2[i][k] = m2[k] / V;
+            continue;
+        }
         c->vol[i] = J / 6.0;
         double zero[3] = {0, 0, 0}, mono[10];
         tet_avg_monomials(c->cv[i], zero, 1.0, mono);
         for (int d = 0; d < 3; ++d) c->cen[i][d] = mono[1 + d];
         tet_avg_monomials(c->cv[i], c->cen[i], 1.0, mono);
         for (int k = 0; k < 6; ++k) c->m2[i][k] = mono[4 + k];
-        for (int a = 0; a < 4; ++a) { c->nbr[i][a] = -1; c->cface[i][a] = -1; }
     }
 
     /* faces: area, owner-outward unit normal and the three Gauss points */
@@ -364,6 +487,51 @@ or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
         for (int d = 0; d < 3; ++d) out += cr[d] * (c->fgp[f][0][d] - c->cen[L][d]);
         double sgn = out > 0 ? 1.0 : -1.0;
         for (int d = 0; d < 3; ++d) c->fnorm[f][d] = sgn * cr[d] / nrm;
+        for (int q = 0; q < 3; ++q) {
+            c->fpw[f][q] = FQ_W[q] * c->farea[f];
+            for (int d = 0; d < 3; ++d) c->fpn[f][q][d] = c->fnorm[f][d];
+        }
+        if (c->curved) {
+            /* Sec. 2.1, eq. flux-para-coord-gauss: the quadratic triangle through
+             * the vertices and the owner's edge points; at each Gauss point the
+             * normal X_xi x X_eta / |X_xi x X_eta| and the weight
+             * (1/2) w_m |X_xi x X_eta| */
+            double tx[6][3];
+            int loc[3];
+            for (int a = 0; a < 3; ++a) {
+                loc[a] = -1;
+                for (int k = 0; k < 4; ++k)
+                    if (tet[4 * L + k] == face_vert[3 * f + a]) loc[a] = k;
+                if (loc[a] < 0) { free(sumarea); or_destroy(c); return NULL; }
+                for (int d = 0; d < 3; ++d) tx[a][d] = x[a][d];
+            }
+            const int ep[3][2] = {{0, 1}, {1, 2}, {0, 2}};
+            for (int e = 0; e < 3; ++e)
+                for (int d = 0; d < 3; ++d) tx[3 + e][d] = c->cx[L][QEDGE[loc[ep[e][0]]][loc[ep[e][1]]]][d];
+            double area = 0.0;
+            for (int q = 0; q < 3; ++q) {
+                double N[6], dN[6][2], Xa[3] = {0, 0, 0}, Xb[3] = {0, 0, 0}, X[3] = {0, 0, 0}, cq[3];
+                qtri_shape(FQ_PTS[q][0], FQ_PTS[q][1], N, dN);
+                for (int l = 0; l < 6; ++l)
+                    for (int d = 0; d < 3; ++d) {
+                        X[d] += N[l] * tx[l][d];
+                        Xa[d] += dN[l][0] * tx[l][d];
+                        Xb[d] += dN[l][1] * tx[l][d];
+                    }
+                cq[0] = Xa[1] * Xb[2] - Xa[2] * Xb[1];
+                cq[1] = Xa[2] * Xb[0] - Xa[0] * Xb[2];
+                cq[2] = Xa[0] * Xb[1] - Xa[1] * Xb[0];
+                double jq = sqrt(cq[0] * cq[0] + cq[1] * cq[1] + cq[2] * cq[2]);
+                if (!(jq > 0.0)) { free(sumarea); or_destroy(c); return NULL; }
+                c->fpw[f][q] = 0.5 * FQ_W[q] * jq;
+                area += c->fpw[f][q];
+                for (int d = 0; d < 3; ++d) {
+                    c->fgp[f][q][d] = X[d];
+                    c->fpn[f][q][d] = sgn * cq[d] / jq;
+                }
+            }
+            c->farea[f] = area;
+        }
         sumarea[L] += c->farea[f];
         if (R >= 0) sumarea[R] += c->farea[f];
         /* neighbour slots */
@@ -411,6 +579,17 @@ int or_geometry(const or_ctx *c, double *vol, double *cen, double *mom2, double 
     return 0;
 }
 
+int or_face_points(const or_ctx *c, double *normal, double *weight)
+{
+    int64_t n = c->nf;
+    for (int64_t f = 0; f < n; ++f)
+        for (int q = 0; q < 3; ++q) {
+            if (weight) weight[q * n + f] = c->fpw[f][q];
+            for (int d = 0; d < 3 && normal; ++d) normal[(3 * q + d) * n + f] = c->fpn[f][q][d];
+        }
+    return 0;
+}
+
 int or_face_geometry(const or_ctx *c, double *area, double *normal, double *gp)
 {
     int64_t n = c->nf;
@@ -423,13 +602,42 @@ int or_face_geometry(const or_ctx *c, double *area, double *normal, double *gp)
     return 0;
 }
 
-/* vertices of neighbour slot a of cell i, translated next to cell i */
-static void neighbour_vertices(const or_ctx *c, int64_t i, int a, double v[4][3])
+/* The averages of tet_avg_monomials over cell m translated by shift; a
+ * quadratic cell by the five-point rule on its isoparametric map (eq.
+ * base-int-change), the weights times |det J|. */
+static void cell_avg_monomials(const or_ctx *c, int64_t m, const double shift[3], const double origin[3],
+                               double h, double out[10])
 {
-    int64_t m = c->nbr[i][a];
-    for (int k = 0; k < 4; ++k)
-        for (int d = 0; d < 3; ++d) v[k][d] = c->cv[m][k][d] + c->noff[i][a][d];
+    if (!c->curved) {
+        double v[4][3];
+        for (int k = 0; k < 4; ++k)
+            for (int d = 0; d < 3; ++d) v[k][d] = c->cv[m][k][d] + shift[d];
+        tet_avg_monomials(v, origin, h, out);
+        return;
+    }
+    double x[10][3], s[10] = {0}, wsum = 0.0;
+    for (int k = 0; k < 10; ++k)
+        for (int d = 0; d < 3; ++d) x[k][d] = c->cx[m][k][d] + shift[d];
+    for (int q = 0; q < 5; ++q) {
+        double X[3], y[3];
+        double w = VQ_W[q] * qtet_point(x, VQ_PTS[q], X);
+        for (int d = 0; d < 3; ++d) y[d] = (X[d] - origin[d]) / h;
+        s[0] += w;
+        s[1] += w * y[0]; s[2] += w * y[1]; s[3] += w * y[2];
+        s[4] += w * y[0] * y[0]; s[5] += w * y[1] * y[1]; s[6] += w * y[2] * y[2];
+        s[7] += w * y[0] * y[1]; s[8] += w * y[0] * y[2]; s[9] += w * y[1] * y[2];
+        wsum += w;
+    }
+    for (int k = 0; k < 10; ++k) out[k] = s[k] / wsum;
 }
+
+/* the same for neighbour slot a of cell i, translated next to cell i */
+static void neighbour_monomials(const or_ctx *c, int64_t i, int a, double h, double out[10])
+{
+    cell_avg_monomials(c, c->nbr[i][a], c->noff[i][a], c->cen[i], h, out);
+}
+
+static const double NO_SHIFT[3] = {0.0, 0.0, 0.0};
 
 /* ======================================================================== */
 /* reconstruction, step 1 (Sec. 4.3): P^1 by least squares on the cell     */
@@ -475,9 +683,8 @@ static void slopes_cell(const or_ctx *c, int64_t i, const real *W, const real *g
     int64_t mm[4];
     for (int a = 0; a < 4; ++a) {
         if (c->nbr[i][a] < 0) continue;
-        double v[4][3], mono[10];
-        neighbour_vertices(c, i, a, v);
-        tet_avg_monomials(v, c->cen[i], h, mono);
+        double mono[10];
+        neighbour_monomials(c, i, a, h, mono);
         /* row m: average over Omega_m of the linear basis y_j (zero mean on Omega_0) */
         for (int d = 0; d < 3; ++d) D[nn][d] = mono[1 + d];
         mm[nn++] = c->nbr[i][a];
@@ -618,14 +825,13 @@ static void p2_rows(const or_ctx *c, int64_t i, const real *W, const real *gW, d
 {
     int64_t n = c->nc;
     double h = cbrt(c->vol[i]);
-    tet_avg_monomials(c->cv[i], c->cen[i], h, mono0);
+    cell_avg_monomials(c, i, NO_SHIFT, c->cen[i], h, mono0);
     int ne = 0, na = 0;
     for (int a = 0; a < 4; ++a) {
         int64_t m = c->nbr[i][a];
         if (m < 0) continue;
-        double v[4][3], mono[10];
-        neighbour_vertices(c, i, a, v);
-        tet_avg_monomials(v, c->cen[i], h, mono);
+        double mono[10];
+        neighbour_monomials(c, i, a, h, mono);
         for (int k = 0; k < 9; ++k)
             E[ne][k] = mono_lookup(mono, KEXP[k][0], KEXP[k][1], KEXP[k][2]) -
                        mono_lookup(mono0, KEXP[k][0], KEXP[k][1], KEXP[k][2]);
@@ -810,19 +1016,23 @@ static void p2_wall(const or_ctx *c, int64_t i, const real *W, const real *gW, i
 
 /* eq. smooth-indicator for a polynomial about the centroid of cell i, with
  * derivatives up to order r; the integrals use the five-point rule (exact
- * for the quadratic integrands that occur here). */
+ * for the quadratic integrands that occur here on a straight cell; on a
+ * quadratic cell the rule of eq. base-int-change). */
 static real smoothness(const or_ctx *c, int64_t i, const qpoly_t *p, int r)
 {
     real vol = c->vol[i];
     real s1 = 0.0, wsum = 0.0;
     for (int q = 0; q < 5; ++q) {
-        double X[3], rr[3];
+        double X[3], rr[3], w = VQ_W[q];
         real g[3];
-        tet_map(c->cv[i], VQ_PTS[q], X);
+        if (c->curved)
+            w *= qtet_point(c->cx[i], VQ_PTS[q], X);
+        else
+            tet_map(c->cv[i], VQ_PTS[q], X);
         for (int d = 0; d < 3; ++d) rr[d] = X[d] - c->cen[i][d];
         quad_grad(p, rr, g);
-        s1 += VQ_W[q] * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-        wsum += VQ_W[q];
+        s1 += w * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        wsum += w;
     }
     /* integral over Omega = |Omega| * average */
     real beta = pow(vol, 2.0 / 3.0 - 1.0) * vol * (s1 / wsum);
@@ -1658,8 +1868,9 @@ static int face_terms(or_ctx *c, const real *coef, double dt, real *out, int raw
 #pragma omp parallel for schedule(static) reduction(| : err)
     for (int64_t f = 0; f < nf; ++f) {
         int64_t L = c->fcell[f][0], R = c->fcell[f][1];
-        real acc[20];
+        real acc[20], gacc[30];
         for (int k = 0; k < 20; ++k) acc[k] = 0.0;
+        for (int k = 0; k < 30; ++k) gacc[k] = 0.0;
         for (int q = 0; q < 3; ++q) {
             double rl[3], rr[3];
             for (int d = 0; d < 3; ++d) {
@@ -1678,13 +1889,14 @@ static int face_terms(or_ctx *c, const real *coef, double dt, real *out, int raw
                     quad_grad(&p, rr, gWr + 3 * k);
                 }
             }
+            const double *nq = c->fpn[f][q];
             if (R < 0)
-                or_wall_ghost(&c->cfg, c->ftag[f], c->fnorm[f], c->fwu[f], Wl, gWl, Wr, gWr);
+                or_wall_ghost(&c->cfg, c->ftag[f], nq, c->fwu[f], Wl, gWl, Wr, gWr);
             real o[20];
-            if (gks_point(&c->cfg, c->fnorm[f], Wl, gWl, Wr, gWr, dt, o)) { err |= 1; continue; }
+            if (gks_point(&c->cfg, nq, Wl, gWl, Wr, gWr, dt, o)) { err |= 1; continue; }
             /* eq. linear-system: F = (4 F(dt/2) - F(dt)) / dt,
              * dF/dt = 4 (F(dt) - 2 F(dt/2)) / dt^2 */
-            real w = FQ_W[q] * c->farea[f];
+            real w = c->fpw[f][q];
             for (int k = 0; k < 5; ++k) {
                 if (raw) { /* the time integrals themselves */
                     acc[k] += w * o[k];
@@ -1695,9 +1907,16 @@ static int face_terms(or_ctx *c, const real *coef, double dt, real *out, int raw
                 }
                 acc[10 + k] += w * o[10 + k];
                 acc[15 + k] += w * o[15 + k];
+                /* eq. gauss-formula: the point's share of the surface integral
+                 * of W n, at t = 0 and t = dt */
+                for (int d = 0; d < 3; ++d) {
+                    gacc[3 * k + d] += w * o[10 + k] * nq[d];
+                    gacc[15 + 3 * k + d] += w * o[15 + k] * nq[d];
+                }
             }
         }
         for (int k = 0; k < 20; ++k) out[(size_t)k * nf + f] = acc[k];
+        for (int k = 0; k < 30; ++k) c->fgrad[(size_t)k * nf + f] = gacc[k];
     }
     return err ? -1 : 0;
 }
@@ -1716,8 +1935,9 @@ int or_face_integrals(or_ctx *c, const real *W, const real *gW, double dt, real 
 
 /* eq. flux-operator for every cell, gathered in serial face order:
  * L = -(1/|Omega|) sum (+-) |Gamma| sum_k w_k F_k, same for dL/dt, and the
- * Gauss-theorem gradient (eq. gauss-formula) of interface values Wf[5][nf] */
-static void gather(const or_ctx *c, const real *ft, const real *Wf, real *L, real *Lt,
+ * Gauss-theorem gradient (eq. gauss-formula) from the faces' surface
+ * integrals of W n, Gf[15][nf] (component q, direction d at 3q+d) */
+static void gather(const or_ctx *c, const real *ft, const real *Gf, real *L, real *Lt,
                    real *grad)
 {
     int64_t n = c->nc, nf = c->nf;
@@ -1735,7 +1955,7 @@ static void gather(const or_ctx *c, const real *ft, const real *Wf, real *L, rea
                 if (Lt) Lt[q * n + i] -= sg * ft[(size_t)(5 + q) * nf + f];
                 if (grad)
                     for (int d = 0; d < 3; ++d)
-                        grad[(3 * q + d) * n + i] += sg * Wf[(size_t)q * nf + f] * c->fnorm[f][d];
+                        grad[(3 * q + d) * n + i] += sg * Gf[(size_t)(3 * q + d) * nf + f];
             }
         }
     }
@@ -1756,19 +1976,19 @@ int or_stage(or_ctx *c, int stage, double dt, real *W, real *gW)
     if (stage == 2 && !c->have_stage1) return -1;
     or_reconstruct(c, W, gW, c->coef, c->flag, NULL);
     if (face_terms(c, c->coef, dt, c->fterm, 0)) return -2;
-    real *Wf = (real *)malloc(sizeof(real) * 5 * nf);
+    real *Gf = (real *)malloc(sizeof(real) * 15 * nf);
     real *L = (real *)malloc(sizeof(real) * 5 * n);
     real *Lt = (real *)malloc(sizeof(real) * 5 * n);
     if (stage == 1) {
         /* eq. step-du with a linear-in-time f: f* = (f(0) + f(dt)) / 2 */
         for (int64_t f = 0; f < nf; ++f)
-            for (int q = 0; q < 5; ++q) {
-                real w0 = c->fterm[(size_t)(10 + q) * nf + f];
-                real w1 = c->fterm[(size_t)(15 + q) * nf + f];
-                c->FW0[(size_t)q * nf + f] = w0;
-                Wf[(size_t)q * nf + f] = 0.5 * (w0 + w1);
+            for (int k = 0; k < 15; ++k) {
+                real g0 = c->fgrad[(size_t)k * nf + f];
+                real g1 = c->fgrad[(size_t)(15 + k) * nf + f];
+                c->FG0[(size_t)k * nf + f] = g0;
+                Gf[(size_t)k * nf + f] = 0.5 * (g0 + g1);
             }
-        gather(c, c->fterm, Wf, L, Lt, gW);
+        gather(c, c->fterm, Gf, L, Lt, gW);
         /* eq. s2o4, first stage */
         for (int64_t k = 0; k < 5 * n; ++k) {
             c->Wn[k] = W[k];
@@ -1780,17 +2000,16 @@ int or_stage(or_ctx *c, int stage, double dt, real *W, real *gW)
     } else {
         /* f^{n+1} = f^n + dt f_t*, f_t* = (f*(dt) - f*(0)) / dt */
         for (int64_t f = 0; f < nf; ++f)
-            for (int q = 0; q < 5; ++q)
-                Wf[(size_t)q * nf + f] = c->FW0[(size_t)q * nf + f] +
-                                         c->fterm[(size_t)(15 + q) * nf + f] -
-                                         c->fterm[(size_t)(10 + q) * nf + f];
-        gather(c, c->fterm, Wf, L, Lt, gW);
+            for (int k = 0; k < 15; ++k)
+                Gf[(size_t)k * nf + f] = c->FG0[(size_t)k * nf + f] + c->fgrad[(size_t)(15 + k) * nf + f] -
+                                         c->fgrad[(size_t)k * nf + f];
+        gather(c, c->fterm, Gf, L, Lt, gW);
         /* eq. s2o4, second stage: only dL/dt(W*) enters */
         for (int64_t k = 0; k < 5 * n; ++k)
             W[k] = c->Wn[k] + dt * c->Ln[k] + dt * dt / 6.0 * (c->Ltn[k] + 2.0 * Lt[k]);
         c->have_stage1 = 0;
     }
-    free(Wf); free(L); free(Lt);
+    free(Gf); free(L); free(Lt);
     return 0;
 }
 

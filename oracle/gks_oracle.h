@@ -69,6 +69,18 @@ or_ctx *or_create(const or_config *cfg, int64_t n_vert, const double *xyz,
                   int64_t n_cell, const int64_t *tet, int64_t n_face,
                   const int64_t *face_vert, const int64_t *face_cell,
                   const int32_t *face_tag, const double *face_shift, const double *face_wall_u);
+/* The same mesh with quadratic elements (Sec. 2.1 quadratic triangles,
+ * Sec. 4.1 quadratic tetrahedra): tet_mid[(6 i + e) * 3 + d] is the control
+ * point on edge e of cell i, edges in the order (0,1), (1,2), (0,2), (0,3),
+ * (1,3), (2,3) of its tet[] vertices.  Volumes, centroids and moments come
+ * from the five-point rule on the isoparametric map, faces from the
+ * quadratic triangle through the owner's edge points, with a normal and a
+ * weight per Gauss point. */
+or_ctx *or_create_quadratic(const or_config *cfg, int64_t n_vert, const double *xyz,
+                            int64_t n_cell, const int64_t *tet, int64_t n_face,
+                            const int64_t *face_vert, const int64_t *face_cell,
+                            const int32_t *face_tag, const double *face_shift, const double *face_wall_u,
+                            const double *tet_mid);
 void or_destroy(or_ctx *ctx);
 int or_set_threads(int n);
 
@@ -76,8 +88,12 @@ int or_set_threads(int n);
  * [6][n] (xx,yy,zz,xy,xz,yz, divided by the volume), inscribed radius dr[n]. */
 int or_geometry(const or_ctx *ctx, double *vol, double *cen, double *mom2, double *dr);
 /* Per-face area[nf], unit normal[3][nf] (outward from the owner),
- * Gauss points [3 points][3][nf]. */
+ * Gauss points [3 points][3][nf].  On a quadratic face the area is the sum
+ * of the point weights and the normal that of the triangle of its vertices. */
 int or_face_geometry(const or_ctx *ctx, double *area, double *normal, double *gp);
+/* Per Gauss point: unit normal [3 points][3][nf] and weight [3][nf] (omega_m
+ * of eq. flux-para-coord-gauss, the face area included). */
+int or_face_points(const or_ctx *ctx, double *normal, double *weight);
 
 /* The ghost state of a wall point (tag 2, 3, 4 or 5; n the outward unit
  * normal, uw the wall velocity), global frame. */

@@ -49,6 +49,9 @@ class TetMesh:
     n: int
     periodic: bool
     face_wall_u: np.ndarray | None = None  # [n_face, 3] velocity of no-slip wall faces (None: at rest)
+    # [n_cell, 6, 3] control points of quadratic elements on the edges QEDGES
+    # of each tet (None: straight-sided tetrahedra)
+    tet_mid: np.ndarray | None = None
 
     @property
     def n_cell(self) -> int:
@@ -61,6 +64,18 @@ class TetMesh:
     @property
     def n_vert(self) -> int:
         return int(self.xyz.shape[0])
+
+
+# edges of a tetrahedron in the order of the quadratic element's shape
+# functions (Sec. 4.1): (0,1), (1,2), (0,2), (0,3), (1,3), (2,3)
+QEDGES = ((0, 1), (1, 2), (0, 2), (0, 3), (1, 3), (2, 3))
+
+
+def straight_edge_points(mesh: TetMesh) -> np.ndarray:
+    """[n_cell, 6, 3] midpoints of every tet's edges in QEDGES order: the
+    control points that make a quadratic element straight-sided."""
+    x = mesh.xyz[mesh.tet]
+    return np.ascontiguousarray(np.stack([0.5 * (x[:, a] + x[:, b]) for a, b in QEDGES], axis=1))
 
 
 def _kuhn_local_tets():
@@ -82,13 +97,19 @@ def _kuhn_local_tets():
 
 
 def kuhn_cube_mesh(n: int, length: float = 1.0, jitter: float = 0.1, seed: int = 0,
-                   periodic: bool = True) -> TetMesh:
+                   periodic: bool = True, curve: float = 0.0) -> TetMesh:
     """Cube [0, length]^3 split into n^3 hexahedra, each into 6 Kuhn tetrahedra.
 
     Vertices are displaced by iid U(-jitter h, jitter h) per axis (numpy
     ``default_rng(seed)``, PCG64), h = length / n.  On a periodic mesh every
     vertex is jittered and periodic images share one displacement.  On a
     walled mesh, boundary vertices only slide tangentially.
+
+    curve > 0 makes the elements quadratic (``tet_mid``): the control point of
+    every edge moves from the edge midpoint by iid U(-curve h, curve h) per
+    axis, drawn after the jitter from the same generator, one draw per edge
+    (periodic images of an edge share it); on a walled mesh the edges that
+    lie in a boundary plane stay straight.
     """
     if n < 1:
         raise ValueError("n must be >= 1")
@@ -179,12 +200,31 @@ def kuhn_cube_mesh(n: int, length: float = 1.0, jitter: float = 0.1, seed: int =
 
     # faces ordered by owner, then neighbour: a locality-friendly default order
     fo = np.lexsort((face_cell[:, 1], face_cell[:, 0]))
-    return TetMesh(xyz=np.ascontiguousarray(xyz), tet=np.ascontiguousarray(tet),
+    mesh = TetMesh(xyz=np.ascontiguousarray(xyz), tet=np.ascontiguousarray(tet),
                    face_vert=np.ascontiguousarray(face_vert[fo]),
                    face_cell=np.ascontiguousarray(face_cell[fo]),
                    face_tag=np.ascontiguousarray(face_tag[fo]),
                    face_shift=np.ascontiguousarray(face_shift[fo]),
                    length=float(length), n=int(n), periodic=bool(periodic))
+    if curve > 0.0:
+        # each edge by its lattice end points, translated so that the smaller
+        # coordinate per axis lies in [0, n) on a periodic mesh
+        ga = grid[tet[:, [a for a, _ in QEDGES]]]          # [nc, 6, 3]
+        gb = grid[tet[:, [b for _, b in QEDGES]]]
+        if periodic:
+            lat_e = (np.minimum(ga, gb) // n) * n
+            ga, gb = ga - lat_e, gb - lat_e
+        base = np.int64(2 * n + 3)
+        ka = (ga[..., 0] * base + ga[..., 1]) * base + ga[..., 2]
+        kb = (gb[..., 0] * base + gb[..., 1]) * base + gb[..., 2]
+        ekey = np.minimum(ka, kb) * base ** 3 + np.maximum(ka, kb)
+        uniq, inv = np.unique(ekey.ravel(), return_inverse=True)
+        delta = rng.uniform(-curve * h, curve * h, size=(uniq.size, 3))[inv].reshape(ekey.shape + (3,))
+        if not periodic:
+            flat = np.any((ga == gb) & ((ga == 0) | (ga == n)), axis=-1)
+            delta[flat] = 0.0
+        mesh.tet_mid = np.ascontiguousarray(straight_edge_points(mesh) + delta)
+    return mesh
 
 
 def _match_faces(tet: np.ndarray):
@@ -209,7 +249,8 @@ def _match_faces(tet: np.ndarray):
     return fv[own_idx], np.stack([owner[own_idx], nbr], axis=1)
 
 
-def cubed_sphere_shell(n: int, layers: int, r_out: float = 20.0, ratio: float = 1.08) -> TetMesh:
+def cubed_sphere_shell(n: int, layers: int, r_out: float = 20.0, ratio: float = 1.08,
+                       curved: bool = False) -> TetMesh:
     """Shell 1 <= r <= r_out around the unit sphere: the cube surface cut into
     6 panels of n x n cells (n even), mapped to the sphere equiangularly
     (lattice point p with |p|_inf = n/2 goes to the direction tan(pi/4 p/(n/2))),
@@ -217,7 +258,11 @@ def cubed_sphere_shell(n: int, layers: int, r_out: float = 20.0, ratio: float = 
     Each hexahedron is split into two prisms along the surface diagonal
     through its smallest vertex id, each prism into three tetrahedra by the
     minimum-vertex-id rule, so the split conforms across cells and panel
-    seams.  Faces on r = 1 are slip walls, on r = r_out far field."""
+    seams.  Faces on r = 1 are slip walls, on r = r_out far field.
+
+    curved: quadratic elements (``tet_mid``) whose edges on the wall r = 1 are
+    arcs: their control point is the edge midpoint moved radially onto the
+    sphere (Sec. 2.1); every other edge stays straight."""
     if n < 2 or n % 2:
         raise ValueError("n must be even and >= 2")
     m = n // 2
@@ -283,10 +328,17 @@ def cubed_sphere_shell(n: int, layers: int, r_out: float = 20.0, ratio: float = 
     rad = np.linalg.norm(xyz[face_vert].mean(axis=1), axis=1)
     tag = np.where(wall, np.where(rad < 0.5 * (1.0 + r_out), FACE_SLIP, FACE_FARFIELD), FACE_INTERIOR)
     fo = np.lexsort((face_cell[:, 1], face_cell[:, 0]))
-    return TetMesh(xyz=np.ascontiguousarray(xyz), tet=np.ascontiguousarray(tet),
+    mesh = TetMesh(xyz=np.ascontiguousarray(xyz), tet=np.ascontiguousarray(tet),
                    face_vert=np.ascontiguousarray(face_vert[fo]), face_cell=np.ascontiguousarray(face_cell[fo]),
                    face_tag=np.ascontiguousarray(tag[fo].astype(np.int32)),
                    face_shift=np.zeros((face_vert.shape[0], 3)), length=float(r_out), n=int(n), periodic=False)
+    if curved:
+        mid = straight_edge_points(mesh)
+        inner = np.arange(xyz.shape[0]) < ns            # the vertices of layer 0 lie on r = 1
+        on = np.stack([inner[tet[:, a]] & inner[tet[:, b]] for a, b in QEDGES], axis=1)
+        mid[on] /= np.linalg.norm(mid[on], axis=1, keepdims=True)
+        mesh.tet_mid = np.ascontiguousarray(mid)
+    return mesh
 
 
 def uniform_state(mesh: TetMesh, rho: float, U, p: float, gamma: float = 1.4):

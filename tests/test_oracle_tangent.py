@@ -4,7 +4,7 @@ adjoint, pinned to the plain oracle:
 
 * its values are bitwise those of the plain build (same source, same
   operation order), on periodic meshes, slip and no-slip walls and the far
-  field;
+  field, and with quadratic (curved) wall faces;
 * its derivatives are the limit of central differences of the plain build:
   along seeded directions (f(h) - f(-h)) / (2h) approaches them as h^2, in
   configurations where the step map is smooth (no collision-time jump,
@@ -35,6 +35,8 @@ def _cases():
     Ws, gWs = I.cell_averages(ms, I.bump_stream_field(1.4))
     free = I.uniform_state(ms, 1.0, (0.3, 0.0, 0.0), 1.0 / 1.4, 1.4)[0][:, 0]
     yield "farfield", ms, dict(farfield=tuple(free)), Ws, gWs
+    mq = I.cubed_sphere_shell(2, 2, r_out=3.0, ratio=1.3, curved=True)
+    yield "quadratic_wall", mq, dict(farfield=tuple(free)), Ws, gWs
 
 
 CASES = list(_cases())
@@ -57,7 +59,7 @@ def test_tangent_values_are_the_oracle(oracle_lib, case):
 def test_tangent_is_the_limit_of_central_differences(oracle_lib, case):
     name, m, kw, W, gW = case
     kw = dict(kw, c_tau=0.0, eps_weno=1.0)
-    if name == "farfield":
+    if name in ("farfield", "quadratic_wall"):
         # an oblique free stream: no far-field point sits exactly on the
         # switch between the upwind sides of the characteristic state
         U = (0.3, 0.1, 0.05)
