@@ -73,10 +73,10 @@ UNIT = {"slopes": "cell", "reconstruct": "cell", "flux_stage1": "face", "flux_st
 PROFILE_NAMES = {
     "slopes": ("gks::slopes_kernel<double>",),
     "reconstruct": ("gks::reconstruct_kernel<double>",),
-    "flux_stage1": ("gks::flux_kernel<double, 0, false, false, false, false>",
-                    "gks::flux_kernel<double, 0, false, false, true, false>"),
-    "flux_stage2": ("gks::flux_kernel<double, 1, false, false, false, false>",
-                    "gks::flux_kernel<double, 1, false, false, true, false>"),
+    "flux_stage1": ("gks::flux_kernel<double, 0, false, false, false, false, false>",
+                    "gks::flux_kernel<double, 0, false, false, true, false, false>"),
+    "flux_stage2": ("gks::flux_kernel<double, 1, false, false, false, false, false>",
+                    "gks::flux_kernel<double, 1, false, false, true, false, false>"),
     "update_stage1": ("gks::update_kernel<double, 1>",),
     "update_stage2": ("gks::update_kernel<double, 2>",),
     "dt": ("gks::dt_pass1",),

@@ -103,7 +103,20 @@ void gks_default_config(gks_config *cfg);
  * neighbour's geometry into the owner's frame (periodic seams; else 0).
  * A boundary face is tagged GKS_FACE_SLIP, GKS_FACE_NOSLIP_ADIABATIC,
  * GKS_FACE_NOSLIP_ISOTHERMAL or GKS_FACE_FARFIELD; face_wall_u[3f..3f+2] is the velocity of a
- * no-slip wall face (global frame; NULL: every wall at rest). */
+ * no-slip wall face (global frame; NULL: every wall at rest).
+ *
+ * Quadratic elements (Sec. 2.1 six-node triangles, Sec. 4.1 ten-node
+ * tetrahedra; curved walls and bent cells): tet_mid[(6i + e) * 3 + d] is the
+ * control point on edge e of cell i, edges in the order (0,1), (1,2), (0,2),
+ * (0,3), (1,3), (2,3) of tet[4i..4i+3].  A point within 1e-14 of the edge
+ * length of the midpoint is taken as the midpoint (a straight edge).  A cell
+ * with a bent edge takes |Omega|, centroid and moments from the five-point
+ * rule on its map (eq. base-int-change); a face with a bent edge takes the
+ * owner's control points, and each of its Gauss points its own normal and
+ * weight (eq. flux-para-coord-gauss).  GKS_E_MESH if det J <= 0 at a
+ * quadrature point or the two cells of a face disagree on its control
+ * points (after the periodic shift).  The adjoint does not cover meshes with
+ * bent edges.  NULL: straight-sided tetrahedra. */
 typedef struct {
     int64_t n_vert;
     const double *xyz;        /* [n_vert][3] */
@@ -115,6 +128,7 @@ typedef struct {
     const int32_t *face_tag;  /* [n_face] */
     const double *face_shift; /* [n_face][3] */
     const double *face_wall_u;/* [n_face][3] or NULL */
+    const double *tet_mid;    /* [n_cell][6][3] or NULL: quadratic elements (below) */
 } gks_mesh;
 
 typedef struct gks_ctx gks_ctx;

@@ -71,7 +71,8 @@ class _Mesh(ctypes.Structure):
                 ("n_cell", ctypes.c_int64), ("tet", ctypes.c_void_p),
                 ("n_face", ctypes.c_int64), ("face_vert", ctypes.c_void_p),
                 ("face_cell", ctypes.c_void_p), ("face_tag", ctypes.c_void_p),
-                ("face_shift", ctypes.c_void_p), ("face_wall_u", ctypes.c_void_p)]
+                ("face_shift", ctypes.c_void_p), ("face_wall_u", ctypes.c_void_p),
+                ("tet_mid", ctypes.c_void_p)]
 
 
 _lib = None
@@ -248,11 +249,13 @@ class Solver:
                 np.ascontiguousarray(mesh.face_tag, np.int32),
                 np.ascontiguousarray(mesh.face_shift, np.float64)]
         wu = getattr(mesh, "face_wall_u", None)
-        if wu is not None:
-            keep.append(np.ascontiguousarray(wu, np.float64))
+        tm = getattr(mesh, "tet_mid", None)
+        keep.append(None if wu is None else np.ascontiguousarray(wu, np.float64))
+        keep.append(None if tm is None else np.ascontiguousarray(tm, np.float64))
         m = _Mesh(mesh.n_vert, keep[0].ctypes.data, self.nc, keep[1].ctypes.data, self.nf,
                   keep[2].ctypes.data, keep[3].ctypes.data, keep[4].ctypes.data,
-                  keep[5].ctypes.data, keep[6].ctypes.data if wu is not None else None)
+                  keep[5].ctypes.data, keep[6].ctypes.data if wu is not None else None,
+                  keep[7].ctypes.data if tm is not None else None)
         self._check(self.L.gks_mesh_upload(self._h, ctypes.byref(m)), "mesh_upload")
         nbytes = ctypes.c_size_t()
         self._check(self.L.gks_workspace_bytes(self._h, ctypes.byref(nbytes)), "workspace_bytes")

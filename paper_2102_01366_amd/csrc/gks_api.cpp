@@ -46,6 +46,12 @@ struct gks_ctx {
     std::vector<int> wtag, wcell, wmode;
     std::vector<double> wvel, wop;
     std::vector<double> M1, M2, geoR, geoD, fgeo, fnrm;
+    // quadratic elements: faces [nfc, nf) with a normal and a weight per Gauss
+    // point (cgeo), and the ncc bent cells' face Gauss points (cpts, ccell)
+    bool curved = false;
+    int nfc = 0, ncc = 0;
+    std::vector<double> cgeo, cnrm, cpts;
+    std::vector<int> ccell;
     // workspace
     bool bound = false;
     char *ws = nullptr;
@@ -246,25 +252,152 @@ uint64_t spread_bits(uint64_t x)
     return x;
 }
 
+// ---------------------------------------------------------------------------
+// quadratic elements (Sec. 2.1 six-node triangles, Sec. 4.1 ten-node
+// tetrahedra) in barycentric form: a vertex node has the shape function
+// l (2 l - 1), an edge node 4 l_a l_b
+// ---------------------------------------------------------------------------
+
+// the tetrahedron's edges in the order of gks_mesh::tet_mid
+const int kTetEdge[6][2] = {{0, 1}, {1, 2}, {0, 2}, {0, 3}, {1, 3}, {2, 3}};
+
+int tet_edge_index(int a, int b)
+{
+    for (int e = 0; e < 6; ++e)
+        if ((kTetEdge[e][0] == a && kTetEdge[e][1] == b) || (kTetEdge[e][0] == b && kTetEdge[e][1] == a)) return e;
+    return -1;
+}
+
+// X(lambda) and det dX/d(xi, eta, zeta) of a ten-node tetrahedron, nodes
+// x[0..3] the vertices and x[4 + e] the point on edge e; lambda_0 = 1 - xi -
+// eta - zeta, lambda_k = (xi, eta, zeta)_k
+double qtet_eval(const double x[10][3], const double lam[4], double X[3])
+{
+    // d lambda_k / d xi_j
+    static const double dl[4][3] = {{-1, -1, -1}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    double J[3][3] = {};
+    for (int d = 0; d < 3; ++d) X[d] = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        const double N = lam[k] * (2.0 * lam[k] - 1.0), dN = 4.0 * lam[k] - 1.0;
+        for (int d = 0; d < 3; ++d) {
+            X[d] += N * x[k][d];
+            for (int j = 0; j < 3; ++j) J[d][j] += dN * dl[k][j] * x[k][d];
+        }
+    }
+    for (int e = 0; e < 6; ++e) {
+        const int a = kTetEdge[e][0], b = kTetEdge[e][1];
+        const double N = 4.0 * lam[a] * lam[b];
+        for (int d = 0; d < 3; ++d) {
+            X[d] += N * x[4 + e][d];
+            for (int j = 0; j < 3; ++j) J[d][j] += 4.0 * (dl[a][j] * lam[b] + lam[a] * dl[b][j]) * x[4 + e][d];
+        }
+    }
+    double c0[3];
+    cross3(J[1], J[2], c0);  // rows: det = J0 . (J1 x J2)
+    return dot3(J[0], c0);
+}
+
+// the five-point volume rule of Sec. 4.1 in barycentric form: the centre
+// (weight -2/15; the weight that makes the rule exact for cubics), and the
+// four points with one coordinate 1/2 and the others 1/6 (weight 3/40);
+// weights include the reference volume 1/6
+void volume_rule(double lam[5][4], double w[5])
+{
+    for (int k = 0; k < 4; ++k) lam[0][k] = 0.25;
+    w[0] = -2.0 / 15.0;
+    for (int q = 1; q < 5; ++q) {
+        for (int k = 0; k < 4; ++k) lam[q][k] = k == q - 1 ? 0.5 : 1.0 / 6.0;
+        w[q] = 3.0 / 40.0;
+    }
+}
+
+// |Omega|, centroid and second central moments (xx, yy, zz, xy, xz, yz,
+// divided by |Omega|) of a ten-node tetrahedron by the five-point rule on
+// its map (eq. base-int-change); false unless det J has the sign of the
+// straight element's at every point
+bool qtet_moments(const double x[10][3], double &V, double cen[3], double C[6])
+{
+    double lam[5][4], w[5], X[5][3], wj[5], e1[3], e2[3], e3[3], cr[3];
+    sub3(x[1], x[0], e1);
+    sub3(x[2], x[0], e2);
+    sub3(x[3], x[0], e3);
+    cross3(e2, e3, cr);
+    const double orient = dot3(e1, cr) > 0.0 ? 1.0 : -1.0;
+    volume_rule(lam, w);
+    V = 0.0;
+    for (int q = 0; q < 5; ++q) {
+        const double dj = orient * qtet_eval(x, lam[q], X[q]);
+        if (!(dj > 0.0)) return false;
+        wj[q] = w[q] * dj;
+        V += wj[q];
+    }
+    if (!(V > 0.0)) return false;
+    for (int d = 0; d < 3; ++d) {
+        double t = 0.0;
+        for (int q = 0; q < 5; ++q) t += wj[q] * X[q][d];
+        cen[d] = t / V;
+    }
+    static const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+    for (int k = 0; k < 6; ++k) C[k] = 0.0;
+    for (int q = 0; q < 5; ++q) {
+        double r[3];
+        sub3(X[q], cen, r);
+        for (int k = 0; k < 6; ++k) C[k] += wj[q] * r[ia[k]] * r[ib[k]];
+    }
+    for (int k = 0; k < 6; ++k) C[k] /= V;
+    return true;
+}
+
+// a six-node triangle at (xi, eta): X, and the unnormalised normal X_xi x
+// X_eta; nodes t[0..2] the vertices, t[3], t[4], t[5] the points on the
+// edges (0,1), (1,2), (0,2)
+void qtri_eval(const double t[6][3], double xi, double eta, double X[3], double cr[3])
+{
+    const double mu[3] = {1.0 - xi - eta, xi, eta};
+    static const double dm[3][2] = {{-1, -1}, {1, 0}, {0, 1}};
+    static const int edge[3][2] = {{0, 1}, {1, 2}, {0, 2}};
+    double Xa[3] = {0, 0, 0}, Xb[3] = {0, 0, 0};
+    for (int d = 0; d < 3; ++d) X[d] = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double N = mu[k] * (2.0 * mu[k] - 1.0), dN = 4.0 * mu[k] - 1.0;
+        for (int d = 0; d < 3; ++d) {
+            X[d] += N * t[k][d];
+            Xa[d] += dN * dm[k][0] * t[k][d];
+            Xb[d] += dN * dm[k][1] * t[k][d];
+        }
+    }
+    for (int e = 0; e < 3; ++e) {
+        const int a = edge[e][0], b = edge[e][1];
+        const double N = 4.0 * mu[a] * mu[b];
+        for (int d = 0; d < 3; ++d) {
+            X[d] += N * t[3 + e][d];
+            Xa[d] += 4.0 * (dm[a][0] * mu[b] + mu[a] * dm[b][0]) * t[3 + e][d];
+            Xb[d] += 4.0 * (dm[a][1] * mu[b] + mu[a] * dm[b][1]) * t[3 + e][d];
+        }
+    }
+    cross3(Xa, Xb, cr);
+}
+
 // quadratic basis of the step-2 fit, in scaled coordinates y about the
 // centroid: y_x, y_y, y_z, y_x^2, y_y^2, y_z^2, y_x y_y, y_x y_z, y_y y_z
 const int QA[6] = {0, 1, 2, 0, 0, 1};
 const int QB[6] = {0, 1, 2, 1, 2, 2};
 
 struct Layout {
-    size_t off[40];
+    size_t off[48];
     size_t total;
 };
 
 enum Slot {
     S_NBR, S_CFACE, S_M1, S_M2, S_GEOR, S_GEOD, S_FCELL, S_FGEO, S_FNRM, S_W, S_GW, S_WN, S_LN, S_LTN,
     S_SLOPES, S_COEF, S_FLAG, S_FF, S_FT, S_FW0, S_FWS, S_RED, S_NONPHYS, S_CPERM, S_FPERM,
-    S_STAGING, S_ISTAGING, S_BSLOT, S_BMODE, S_WTAG, S_WVEL, S_WCELL, S_WMODE, S_WOP, S_WIDX, S_COUNT
+    S_STAGING, S_ISTAGING, S_BSLOT, S_BMODE, S_WTAG, S_WVEL, S_WCELL, S_WMODE, S_WOP, S_WIDX,
+    S_CGEO, S_CCELL, S_CPTS, S_GC0, S_GCS, S_CNRM, S_COUNT
 };
 
 // bs: bytes of a bulk element (8 in FP64, 4 in FP32-bulk); nwf wall faces,
-// nwc no-slip wall cells
-Layout make_layout(size_t nc, size_t nf, size_t bs, size_t nwf, size_t nwc)
+// nwc no-slip wall cells, ncf quadratic-path faces, ncc bent cells
+Layout make_layout(size_t nc, size_t nf, size_t bs, size_t nwf, size_t nwc, size_t ncf, size_t ncc)
 {
     const size_t sz[S_COUNT] = {
         4 * nc * sizeof(int), 4 * nc * sizeof(int), 12 * nc * bs,
@@ -276,7 +409,8 @@ Layout make_layout(size_t nc, size_t nf, size_t bs, size_t nwf, size_t nwc)
         (8 + 5 * (size_t)gks::kRedBlocks) * 8, 64, nc * sizeof(int), nf * sizeof(int),
         std::max(50 * nc, 20 * nf) * 8, nc * sizeof(int), 4 * nc * sizeof(int), nc * sizeof(int),
         nwf * sizeof(int), 3 * nwf * bs, nwc * sizeof(int), 4 * nwc * sizeof(int), (size_t)gks::kWallRows * nwc * bs,
-        nc * sizeof(int)};
+        nc * sizeof(int), (size_t)gks::kCurvedFaceRows * ncf * bs, nc * sizeof(int),
+        (size_t)gks::kCurvedCellRows * ncc * bs, 15 * ncf * bs, 15 * ncf * bs, 9 * ncf * 8};
     Layout L;
     size_t o = 0;
     for (int k = 0; k < S_COUNT; ++k) {
@@ -449,6 +583,54 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
         for (int d = 0; d < 3; ++d) cen[3 * i + d] = 0.25 * (v[0][d] + v[1][d] + v[2][d] + v[3][d]);
     }
 
+    // second central moments / |Omega| of the straight cells: (1/20) sum_a r_a r_a^T
+    std::vector<double> cmom(6 * (size_t)nc);
+    for (int i = 0; i < nc; ++i) {
+        double C[6] = {0, 0, 0, 0, 0, 0};
+        for (int a = 0; a < 4; ++a) {
+            const int64_t id = m->tet[4 * (size_t)i + a];
+            double r[3];
+            for (int d = 0; d < 3; ++d) r[d] = m->xyz[3 * id + d] - cen[3 * (size_t)i + d];
+            for (int k = 0; k < 6; ++k) C[k] += r[QA[k]] * r[QB[k]];
+        }
+        for (int k = 0; k < 6; ++k) cmom[6 * (size_t)i + k] = C[k] / 20.0;
+    }
+
+    // --- quadratic elements (Secs. 2.1, 4.1): control points on the edges; a
+    // point within 1e-14 of its edge length of the midpoint is the midpoint
+    // (a straight edge); a cell with a bent edge takes its volume, centroid
+    // and moments from the five-point rule on its map
+    std::vector<double> cx;  // [nc][10][3]
+    std::vector<char> ecurv(m->tet_mid ? 6 * (size_t)nc : 0, 0), ccurv(nc, 0);
+    if (m->tet_mid) {
+        cx.resize(30 * (size_t)nc);
+        for (int i = 0; i < nc; ++i) {
+            double(*x)[3] = reinterpret_cast<double(*)[3]>(&cx[30 * (size_t)i]);
+            for (int a = 0; a < 4; ++a)
+                for (int d = 0; d < 3; ++d) x[a][d] = m->xyz[3 * m->tet[4 * (size_t)i + a] + d];
+            for (int e = 0; e < 6; ++e) {
+                const int a = kTetEdge[e][0], b = kTetEdge[e][1];
+                double mid[3], ed[3], dev = 0.0;
+                sub3(x[b], x[a], ed);
+                for (int d = 0; d < 3; ++d) {
+                    const double t = m->tet_mid[(6 * (size_t)i + e) * 3 + d];
+                    if (!std::isfinite(t)) return fail(c, GKS_E_MESH, "tet_mid is not finite");
+                    mid[d] = 0.5 * (x[a][d] + x[b][d]);
+                    dev = std::max(dev, std::fabs(t - mid[d]));
+                    x[4 + e][d] = t;
+                }
+                if (dev <= 1e-14 * std::sqrt(dot3(ed, ed))) {
+                    for (int d = 0; d < 3; ++d) x[4 + e][d] = mid[d];
+                } else {
+                    ecurv[6 * (size_t)i + e] = 1;
+                    ccurv[i] = 1;
+                }
+            }
+            if (ccurv[i] && !qtet_moments(x, vol[i], &cen[3 * (size_t)i], &cmom[6 * (size_t)i]))
+                return fail(c, GKS_E_MESH, "a quadratic tetrahedron has det J <= 0 at a quadrature point");
+        }
+    }
+
     // --- faces: validation, incidence in caller face order ---------------
     std::vector<int> nslots(nc, 0), slot_face(4 * (size_t)nc, -1), slot_side(4 * (size_t)nc, 0);
     for (int f = 0; f < nf; ++f) {
@@ -477,6 +659,66 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
     for (int i = 0; i < nc; ++i)
         if (nslots[i] != 4) return fail(c, GKS_E_MESH, "a cell does not have four faces");
 
+    // a face is quadratic if one of its edges is bent in its owner; the
+    // control points of its edges are the owner's and must be the
+    // neighbour's (translated by the periodic shift)
+    std::vector<char> fcurv(nf, 0);
+    std::vector<double> fctrl(m->tet_mid ? 18 * (size_t)nf : 0);  // [nf][6][3] face control points
+    if (m->tet_mid) {
+        for (int f = 0; f < nf; ++f) {
+            const int L = (int)m->face_cell[2 * (size_t)f], R = (int)m->face_cell[2 * (size_t)f + 1];
+            int loc[3];
+            for (int a = 0; a < 3; ++a) {
+                loc[a] = -1;
+                for (int k = 0; k < 4; ++k)
+                    if (m->tet[4 * (size_t)L + k] == m->face_vert[3 * (size_t)f + a]) loc[a] = k;
+                if (loc[a] < 0) return fail(c, GKS_E_MESH, "a face vertex is not a vertex of its owner");
+            }
+            double *t = &fctrl[18 * (size_t)f];
+            for (int a = 0; a < 3; ++a)
+                for (int d = 0; d < 3; ++d) t[3 * a + d] = cx[30 * (size_t)L + 3 * loc[a] + d];
+            static const int fe[3][2] = {{0, 1}, {1, 2}, {0, 2}};
+            for (int e = 0; e < 3; ++e) {
+                const int te = tet_edge_index(loc[fe[e][0]], loc[fe[e][1]]);
+                fcurv[f] |= ecurv[6 * (size_t)L + te];
+                for (int d = 0; d < 3; ++d) t[9 + 3 * e + d] = cx[30 * (size_t)L + 3 * (4 + te) + d];
+            }
+            if (R < 0) continue;
+            // the neighbour's vertices matched by position
+            int nl[3];
+            double h2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                nl[a] = -1;
+                double best = INFINITY;
+                for (int k = 0; k < 4; ++k) {
+                    double dd = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        const double u = cx[30 * (size_t)R + 3 * k + d] + m->face_shift[3 * (size_t)f + d] - t[3 * a + d];
+                        dd += u * u;
+                    }
+                    if (dd < best) { best = dd; nl[a] = k; }
+                }
+                for (int d = 0; d < 3; ++d) {
+                    const double u = t[3 * a + d] - t[3 * ((a + 1) % 3) + d];
+                    h2 = std::max(h2, u * u);
+                }
+            }
+            for (int e = 0; e < 3; ++e) {
+                const int te = tet_edge_index(nl[fe[e][0]], nl[fe[e][1]]);
+                if (te < 0) return fail(c, GKS_E_MESH, "a shared face's vertices do not match");
+                double dd = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    const double u = cx[30 * (size_t)R + 3 * (4 + te) + d] + m->face_shift[3 * (size_t)f + d] - t[9 + 3 * e + d];
+                    dd += u * u;
+                }
+                if (dd > 1e-20 * h2)
+                    return fail(c, GKS_E_MESH, "the quadratic control points of a shared face differ between its cells");
+            }
+        }
+    }
+    bool curved = false;
+    for (int f = 0; f < nf; ++f) curved = curved || fcurv[f];
+
     // --- renumbering: Morton order of centroids --------------------------
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int i = 0; i < nc; ++i)
@@ -502,20 +744,30 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
     std::vector<int> fkey(nf);
     for (int f = 0; f < nf; ++f)
     {
-        // interior faces by their lower internal cell; wall faces after all of
-        // them (by owner), so that the flux runs them as a launch of their own
+        // interior faces by their lower internal cell; on a mesh with quadratic
+        // faces those after the flat ones; wall faces after all of them (by
+        // owner), so that the flux runs each group as a launch of its own
         const int64_t L = m->face_cell[2 * (size_t)f], R = m->face_cell[2 * (size_t)f + 1];
-        fkey[f] = R < 0 ? nc + cinv[L] : std::min(cinv[L], cinv[R]);
+        fkey[f] = R < 0 ? (curved ? 2 : 1) * nc + cinv[L] : (fcurv[f] ? nc : 0) + std::min(cinv[L], cinv[R]);
     }
     std::vector<int> fperm(nf), finv(nf);
     std::iota(fperm.begin(), fperm.end(), 0);
     std::stable_sort(fperm.begin(), fperm.end(), [&](int a, int b) { return fkey[a] < fkey[b]; });
     for (int j = 0; j < nf; ++j) finv[fperm[j]] = j;
+    // faces [nfc, nf) take the quadratic path: a normal and a weight per
+    // Gauss point; on a mesh without bent edges nfc = nf
+    int nfc = nf;
+    if (curved) {
+        nfc = 0;
+        for (int f = 0; f < nf; ++f) nfc += (m->face_cell[2 * (size_t)f + 1] >= 0 && !fcurv[f]) ? 1 : 0;
+    }
+    const int ncf = nf - nfc;
 
     // --- face geometry (internal order) ----------------------------------
     std::vector<double> fgeo((size_t)gks::NFGEO * nf), fnrm64(3 * (size_t)nf);
     std::vector<int> fcell(2 * (size_t)nf);
-    std::vector<double> farea(nf), fnrm(3 * (size_t)nf);
+    std::vector<double> farea(nf), fnrm(3 * (size_t)nf), avec(3 * (size_t)nf), gpa(9 * (size_t)nf);
+    std::vector<double> cgeo((size_t)gks::kCurvedFaceRows * ncf), cnrm(9 * (size_t)ncf);
     for (int j = 0; j < nf; ++j) {
         const int f = fperm[j];
         const int L = (int)m->face_cell[2 * (size_t)f], R = (int)m->face_cell[2 * (size_t)f + 1];
@@ -548,10 +800,43 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
             fnrm[3 * (size_t)f + d] = nd;
         }
         farea[f] = 0.5 * nrm;
-        fgeo[(size_t)gks::F_AREA * nf + j] = 0.5 * nrm;
+        double pn[3][3], pa[3];  // per Gauss point: unit normal, area scale |X_xi x X_eta| / 2
+        for (int k = 0; k < 3; ++k) {
+            pa[k] = farea[f];
+            for (int d = 0; d < 3; ++d) pn[k][d] = fnrm[3 * (size_t)f + d];
+        }
+        if (fcurv[f]) {
+            // eq. flux-para-coord-gauss on the six-node triangle: weight
+            // (1/2)(1/3)|X_xi x X_eta| and normal X_xi x X_eta / |.| per point
+            const double(*t)[3] = reinterpret_cast<const double(*)[3]>(&fctrl[18 * (size_t)f]);
+            double area = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double cq[3];
+                qtri_eval(t, gpw[k][0], gpw[k][1], gp[k], cq);
+                const double jq = std::sqrt(dot3(cq, cq));
+                if (!(jq > 0.0)) return fail(c, GKS_E_MESH, "degenerate quadratic face");
+                pa[k] = 0.5 * jq;
+                area += pa[k] / 3.0;
+                for (int d = 0; d < 3; ++d) pn[k][d] = sg * cq[d] / jq;
+            }
+            farea[f] = area;
+        }
+        for (int d = 0; d < 3; ++d)
+            avec[3 * (size_t)f + d] = (pa[0] * pn[0][d] + pa[1] * pn[1][d] + pa[2] * pn[2][d]) / 3.0;
+        if (j >= nfc)
+            for (int k = 0; k < 3; ++k) {
+                for (int d = 0; d < 3; ++d) {
+                    cgeo[(size_t)(4 * k + d) * ncf + (j - nfc)] = pn[k][d];
+                    cnrm[(size_t)(3 * k + d) * ncf + (j - nfc)] = pn[k][d];
+                }
+                cgeo[(size_t)(4 * k + 3) * ncf + (j - nfc)] = pa[k];
+            }
+        fgeo[(size_t)gks::F_AREA * nf + j] = farea[f];
         for (int k = 0; k < 3; ++k)
-            for (int d = 0; d < 3; ++d)
+            for (int d = 0; d < 3; ++d) {
+                gpa[9 * (size_t)f + 3 * k + d] = gp[k][d];
                 fgeo[(size_t)(gks::F_RL + 3 * k + d) * nf + j] = gp[k][d] - cen[3 * L + d];
+            }
         for (int d = 0; d < 3; ++d)
             fgeo[(size_t)(gks::F_D + d) * nf + j] =
                 R < 0 ? 0.0 : cen[3 * L + d] - (cen[3 * R + d] + m->face_shift[3 * (size_t)f + d]);
@@ -562,7 +847,8 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
     // --- cells: geometry rows, neighbours, operators (internal order) ----
     std::vector<double> geoR((size_t)gks::NGEO_R * nc), geoD((size_t)gks::NGEO_D * nc);
     std::vector<double> M1(12 * (size_t)nc), M2(gks::kM2Rows * gks::m2_padded_cells(nc), 0.0);
-    std::vector<int> nbr(4 * (size_t)nc), cface(4 * (size_t)nc), bmode(nc, 0);
+    std::vector<int> nbr(4 * (size_t)nc), cface(4 * (size_t)nc), bmode(nc, 0), ccell(nc, -1);
+    std::vector<double> cpts_host;  // [ncc][36], transposed at binding
     for (int ii = 0; ii < nc; ++ii) {
         const int i = cperm[ii];
         const double V = vol[i];
@@ -572,11 +858,9 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
             const int64_t id = m->tet[4 * (size_t)i + a];
             for (int d = 0; d < 3; ++d) rv[a][d] = m->xyz[3 * id + d] - ci[d];
         }
-        // second moments about the centroid: (1/20) sum_a r_a r_a^T
-        double C[6] = {0, 0, 0, 0, 0, 0};
-        for (int a = 0; a < 4; ++a)
-            for (int k = 0; k < 6; ++k) C[k] += rv[a][QA[k]] * rv[a][QB[k]];
-        for (int k = 0; k < 6; ++k) C[k] /= 20.0;
+        // second moments about the centroid
+        double C[6];
+        for (int k = 0; k < 6; ++k) C[k] = cmom[6 * (size_t)i + k];
         double sumA = 0.0, closure[3] = {0, 0, 0};
         double delta[4][3], Cm[4][6];
         for (int a = 0; a < 4; ++a) {
@@ -585,7 +869,7 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
             const int other = side == 0 ? R : L;
             const double sgn = side == 0 ? 1.0 : -1.0;
             sumA += farea[f];
-            for (int d = 0; d < 3; ++d) closure[d] += sgn * farea[f] * fnrm[3 * (size_t)f + d];
+            for (int d = 0; d < 3; ++d) closure[d] += sgn * avec[3 * (size_t)f + d];
             nbr[(size_t)a * nc + ii] = other < 0 ? -1 : cinv[other];
             cface[(size_t)a * nc + ii] = 2 * finv[f] + side;
             if (other < 0) {
@@ -598,16 +882,7 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
                 const double off = side == 0 ? m->face_shift[3 * (size_t)f + d] : -m->face_shift[3 * (size_t)f + d];
                 delta[a][d] = cen[3 * (size_t)other + d] + off - ci[d];
             }
-            double ro[4][3];
-            for (int b = 0; b < 4; ++b) {
-                const int64_t id = m->tet[4 * (size_t)other + b];
-                for (int d = 0; d < 3; ++d) ro[b][d] = m->xyz[3 * id + d] - cen[3 * (size_t)other + d];
-            }
-            for (int k = 0; k < 6; ++k) {
-                double s = 0.0;
-                for (int b = 0; b < 4; ++b) s += ro[b][QA[k]] * ro[b][QB[k]];
-                Cm[a][k] = s / 20.0;
-            }
+            for (int k = 0; k < 6; ++k) Cm[a][k] = cmom[6 * (size_t)other + k];
         }
         if (std::sqrt(dot3(closure, closure)) > 1e-10 * sumA)
             return fail(c, GKS_E_MESH, "a cell surface is not closed");
@@ -621,6 +896,18 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
         for (int k = 0; k < 6; ++k) g[(size_t)(gks::G_C + k) * nc + ii] = C[k];
         for (int a = 0; a < 4; ++a)
             for (int d = 0; d < 3; ++d) g[(size_t)(gks::G_RV + 3 * a + d) * nc + ii] = rv[a][d];
+        if (ccurv[i]) {
+            // the positivity check of a quadratic cell runs at its faces' Gauss
+            // points, which its vertices no longer give
+            ccell[ii] = (int)(cpts_host.size() / gks::kCurvedCellRows);
+            for (int a = 0; a < 4; ++a) {
+                const int f = slot_face[4 * (size_t)i + a], side = slot_side[4 * (size_t)i + a];
+                for (int k = 0; k < 3; ++k)
+                    for (int d = 0; d < 3; ++d)
+                        cpts_host.push_back(gpa[9 * (size_t)f + 3 * k + d] -
+                                            (side ? m->face_shift[3 * (size_t)f + d] : 0.0) - ci[d]);
+            }
+        }
 
         // the neighbours present (a cell at a wall has fewer than four)
         int pres[4], np = 0;
@@ -907,6 +1194,13 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
     c->geoD.swap(geoD);
     c->fgeo.swap(fgeo);
     c->fnrm.swap(fnrm64);
+    c->curved = curved;
+    c->nfc = nfc;
+    c->ncc = (int)(cpts_host.size() / gks::kCurvedCellRows);
+    c->cgeo.swap(cgeo);
+    c->cnrm.swap(cnrm);
+    c->cpts.swap(cpts_host);
+    c->ccell.swap(ccell);
     c->have_mesh = true;
     return GKS_OK;
 }
@@ -915,7 +1209,7 @@ gks_status gks_workspace_bytes(const gks_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return GKS_E_INVAL;
     if (!c->have_mesh) return GKS_E_STATE;
-    *bytes = make_layout(c->nc, c->nf, c->fp32 ? 4 : 8, c->nf - c->nfi, c->nwc).total;
+    *bytes = make_layout(c->nc, c->nf, c->fp32 ? 4 : 8, c->nf - c->nfi, c->nwc, c->nf - c->nfc, c->ncc).total;
     return GKS_OK;
 }
 
@@ -925,7 +1219,7 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     if (!c->have_mesh) return fail(c, GKS_E_STATE, "no mesh uploaded");
     if (c->bound) return fail(c, GKS_E_STATE, "workspace already bound");
     if (((uintptr_t)dev) & 255) return fail(c, GKS_E_INVAL, "workspace must be 256-byte aligned");
-    const Layout L = make_layout(c->nc, c->nf, c->fp32 ? 4 : 8, c->nf - c->nfi, c->nwc);
+    const Layout L = make_layout(c->nc, c->nf, c->fp32 ? 4 : 8, c->nf - c->nfi, c->nwc, c->nf - c->nfc, c->ncc);
     if (bytes < L.total) return fail(c, GKS_E_NOMEM, "workspace too small");
     char *w = (char *)dev;
     auto P = [&](int slot) { return (void *)(w + L.off[slot]); };
@@ -952,6 +1246,12 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     dm.wmode = (const int *)P(S_WMODE);
     dm.wop = P(S_WOP);
     dm.widx = (const int *)P(S_WIDX);
+    dm.nfc = c->nfc;
+    dm.ncc = c->ncc;
+    dm.cgeo = P(S_CGEO);
+    dm.cnrm = (const double *)P(S_CNRM);
+    dm.ccell = (const int *)P(S_CCELL);
+    dm.cpts = P(S_CPTS);
     ds.W = (double *)P(S_W);
     ds.gW = (double *)P(S_GW);
     ds.Wn = (double *)P(S_WN);
@@ -964,6 +1264,8 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     ds.FT = P(S_FT);
     ds.FW0 = P(S_FW0);
     ds.FWs = P(S_FWS);
+    ds.GC0 = P(S_GC0);
+    ds.GCs = P(S_GCS);
     ds.red = (double *)P(S_RED);
     ds.nonphys = (int *)P(S_NONPHYS);
     c->d_cperm = (int *)P(S_CPERM);
@@ -1020,6 +1322,19 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
         HIP_TRY(c, up_bulk(dm.wop, wt));
         HIP_TRY(c, hipStreamSynchronize(st));
     }
+    HIP_TRY(c, up((void *)dm.ccell, c->ccell.data(), nc * sizeof(int)));
+    if (c->nf > c->nfc) {
+        HIP_TRY(c, up_bulk(dm.cgeo, c->cgeo));
+        HIP_TRY(c, up((void *)dm.cnrm, c->cnrm.data(), c->cnrm.size() * 8));
+    }
+    if (c->ncc > 0) {
+        std::vector<double> ct((size_t)gks::kCurvedCellRows * c->ncc);
+        for (int k = 0; k < c->ncc; ++k)
+            for (int r = 0; r < gks::kCurvedCellRows; ++r)
+                ct[(size_t)r * c->ncc + k] = c->cpts[(size_t)gks::kCurvedCellRows * k + r];
+        HIP_TRY(c, up_bulk(dm.cpts, ct));
+    }
+    HIP_TRY(c, hipStreamSynchronize(st));
     HIP_TRY(c, up(c->d_cperm, c->cperm.data(), nc * sizeof(int)));
     HIP_TRY(c, up(c->d_fperm, c->fperm.data(), nf * sizeof(int)));
     HIP_TRY(c, gks::launch_fill_int(ds.nonphys, 0, st));
@@ -1041,6 +1356,10 @@ gks_status gks_bind_workspace(gks_ctx *c, void *dev, size_t bytes)
     std::vector<double>().swap(c->geoD);
     std::vector<double>().swap(c->fgeo);
     std::vector<double>().swap(c->fnrm);
+    std::vector<double>().swap(c->cgeo);
+    std::vector<double>().swap(c->cnrm);
+    std::vector<double>().swap(c->cpts);
+    std::vector<int>().swap(c->ccell);
     c->ws = w;
     c->ws_bytes = bytes;
     c->bound = true;
@@ -1228,6 +1547,7 @@ gks_status gks_bind_adjoint_workspace(gks_ctx *c, void *dev, size_t bytes)
     if (!c || !dev) return GKS_E_INVAL;
     if (!c->bound) return fail(c, GKS_E_STATE, "bind the forward workspace first");
     if (c->adj_bound) return fail(c, GKS_E_STATE, "adjoint workspace already bound");
+    if (c->curved) return fail(c, GKS_E_INVAL, "the adjoint does not cover quadratic (bent) elements");
     if (((uintptr_t)dev) & 255) return fail(c, GKS_E_INVAL, "workspace must be 256-byte aligned");
     const Layout L = make_adj_layout(c->nc, c->nf, c->fp32 ? 4 : 8);
     if (bytes < L.total) return fail(c, GKS_E_NOMEM, "adjoint workspace too small");

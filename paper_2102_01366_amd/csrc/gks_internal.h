@@ -93,9 +93,23 @@ enum WallMode {
 enum WallTag { WALL_SLIP = 2, WALL_ADIABATIC = 3, WALL_ISOTHERMAL = 4, WALL_FARFIELD = 5 };
 
 // Device view of the mesh (all pointers into the caller's workspace).
+// Quadratic elements (Sec. 2.1, eq. flux-para-coord-gauss): faces [nfc, nf)
+// carry per Gauss point k a unit normal (rows 4k..4k+2 of cgeo) and the area
+// scale |X_xi x X_eta| / 2 (row 4k+3; the point's weight is a third of it);
+// a bent cell's positivity check reads its faces' Gauss points (cpts row
+// 9a + 3k + d: slot a, point k, direction d, relative to the centroid).
+constexpr int kCurvedFaceRows = 12;
+constexpr int kCurvedCellRows = 36;
+
 struct DevMesh {
     int nc, nf;
     int nfi;            // faces [0, nfi) are interior, [nfi, nf) walls
+    int nfc;            // faces [nfc, nf) take the quadratic path (nfc <= nfi, or nf without bent edges)
+    const void *cgeo;   // [kCurvedFaceRows][nf - nfc]
+    const double *cnrm; // [9][nf - nfc] the same normals in FP64 (row 3k + d), for the cell update
+    const int *ccell;   // [nc] row of a bent cell in cpts, -1 for a straight one
+    const void *cpts;   // [kCurvedCellRows][ncc]
+    int ncc;
     const int *nbr;     // [4][nc] neighbour internal id, -1 on a wall
     const int *cface;   // [4][nc] 2 * face + side (side 1: the cell is the face's neighbour)
     const void *M1;     // [12][nc] slopes b_d = sum_m M1[4d+m] (Q_m - Q_0)
@@ -126,6 +140,8 @@ struct DevState {
     int *flag;              // [nc] positivity fallback taken
     void *FF, *FT, *FW0, *FWs; // [5][nf] each: face flux, its time derivative,
                                // interface W(0) of stage 1, interface W for the gradient
+    void *GC0, *GCs;           // [15][nf - nfc] each: the quadratic faces' weighted interface values
+                               // per Gauss point, as FW0 and FWs (component q, point k at 3q+k)
     double *red;            // reduction scratch
     int *nonphys;           // [1] set when a cell average is non-physical
 };

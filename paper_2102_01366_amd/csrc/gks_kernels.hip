@@ -333,6 +333,15 @@ __global__ __launch_bounds__(kRecThreads, GKS_REC_MIN_WAVES) void reconstruct_ke
 #pragma unroll
                 for (int dd = 0; dd < 3; ++dd) r[j][dd] = R(0.5) * sGeo[G_RV + 3 * k + dd][l] - rq6[dd];
             }
+            // a bent cell: the Gauss points of its face in slot q
+            const int cc = m.ncc > 0 ? m.ccell[i] : -1;
+            if (cc >= 0) {
+                const R *cp = static_cast<const R *>(m.cpts);
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int dd = 0; dd < 3; ++dd) r[j][dd] = cp[(size_t)(9 * q + 3 * j + dd) * m.ncc + cc];
+            }
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 R cf[10];
@@ -418,6 +427,9 @@ __global__ __launch_bounds__(kBlock) void reconstruct2_kernel(DevMesh m, DevStat
 #pragma unroll
         for (int d = 0; d < 3; ++d) rv[a][d] = geo[(size_t)(G_RV + 3 * a + d) * n + i];
     bool bad = false;
+    // a bent cell: the Gauss points of its faces (slot a, point k or k - 1)
+    const int cc = m.ncc > 0 ? m.ccell[i] : -1;
+    const R *cp = static_cast<const R *>(m.cpts);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -426,6 +438,9 @@ __global__ __launch_bounds__(kBlock) void reconstruct2_kernel(DevMesh m, DevStat
             R r[3], v[5];
 #pragma unroll
             for (int d = 0; d < 3; ++d) r[d] = R(0.5) * rv[k][d] - rv[a][d] / R(6);
+            if (cc >= 0)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) r[d] = cp[(size_t)(9 * a + 3 * (k - (k > a ? 1 : 0)) + d) * m.ncc + cc];
 #pragma unroll
             for (int q = 0; q < 5; ++q) v[q] = R(Q0[q]) + G[q][0] * r[0] + G[q][1] * r[1] + G[q][2] * r[2];
             const R pr = R(p.gamma - 1.0) * (v[4] - R(0.5) * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
@@ -610,11 +625,17 @@ __global__ __launch_bounds__(kRecThreads) void wall_reconstruct_kernel(DevMesh m
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int dd = 0; dd < 3; ++dd) rv[a][dd] = geo[(size_t)(G_RV + 3 * a + dd) * n + i];
+        const int ccl = m.ncc > 0 ? m.ccell[i] : -1;
+        const R *cp = static_cast<const R *>(m.cpts);
         for (int k = 0; k < 4; ++k) {
             if (k == q) continue;
             R r[3], v[5];
 #pragma unroll
             for (int dd = 0; dd < 3; ++dd) r[dd] = R(0.5) * rv[k][dd] - rv[q][dd] / R(6);
+            // a bent cell: the Gauss points of its face in slot q
+            if (ccl >= 0)
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) r[dd] = cp[(size_t)(9 * q + 3 * (k - (k > q ? 1 : 0)) + dd) * m.ncc + ccl];
 #pragma unroll
             for (int cc = 0; cc < 5; ++cc) {
                 R cf[10];
@@ -657,17 +678,42 @@ __global__ __launch_bounds__(kBlock) void update_kernel(DevMesh m, DevState s, d
         const int code = m.cface[a * n + i];
         const int f = code >> 1;
         const double sg = (code & 1) ? -1.0 : 1.0;
-        double nrm[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) nrm[d] = m.fnrm[(size_t)d * nf + f];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             const size_t o = (size_t)q * nf + f;
             if (STAGE == 1) L[q] -= sg * double(FF[o]);
             Lt[q] -= sg * double(FT[o]);
-            const double wf = STAGE == 1 ? double(FWs[o]) : double(FW0[o]) + double(FWs[o]);
+        }
+        if (f < m.nfc) {
+            double nrm[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) G[3 * q + d] += sg * wf * nrm[d];
+            for (int d = 0; d < 3; ++d) nrm[d] = m.fnrm[(size_t)d * nf + f];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const size_t o = (size_t)q * nf + f;
+                const double wf = STAGE == 1 ? double(FWs[o]) : double(FW0[o]) + double(FWs[o]);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) G[3 * q + d] += sg * wf * nrm[d];
+            }
+        } else {
+            // a quadratic face: each Gauss point's weighted interface value
+            // times that point's own normal
+            const R *GC0 = static_cast<const R *>(s.GC0), *GCs = static_cast<const R *>(s.GCs);
+            const int nq = nf - m.nfc, fq = f - m.nfc;
+            double pn[3][3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) pn[k][d] = m.cnrm[(size_t)(3 * k + d) * nq + fq];
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const size_t o = (size_t)(3 * q + k) * nq + fq;
+                    const double wv = STAGE == 1 ? double(GCs[o]) : double(GC0[o]) + double(GCs[o]);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) G[3 * q + d] += sg * wv * pn[k][d];
+                }
         }
     }
     const double iv = m.geoD[(size_t)G_INVVOL * n + i];

@@ -373,7 +373,7 @@ def with_walls(mesh: TetMesh, tags: dict, velocity: dict | None = None) -> TetMe
             wu[on] = np.asarray(velocity[name], np.float64)
     return TetMesh(xyz=mesh.xyz, tet=mesh.tet, face_vert=mesh.face_vert, face_cell=mesh.face_cell,
                    face_tag=np.ascontiguousarray(tag), face_shift=mesh.face_shift, length=mesh.length,
-                   n=mesh.n, periodic=False, face_wall_u=np.ascontiguousarray(wu))
+                   n=mesh.n, periodic=False, face_wall_u=np.ascontiguousarray(wu), tet_mid=mesh.tet_mid)
 
 
 # ----------------------------------------------------------------------------

@@ -58,7 +58,7 @@ def test_create_rejects_bad_weights(lib):
     assert _create(lib, cfg)[0] == G.GKS_E_INVAL
 
 
-def _upload(lib, mesh, wall_u=None, **override):
+def _upload(lib, mesh, wall_u=None, tet_mid=None, **override):
     arrays = dict(xyz=mesh.xyz, tet=mesh.tet, face_vert=mesh.face_vert, face_cell=mesh.face_cell,
                   face_tag=mesh.face_tag, face_shift=mesh.face_shift)
     arrays.update(override)
@@ -69,9 +69,10 @@ def _upload(lib, mesh, wall_u=None, **override):
             np.ascontiguousarray(arrays["face_tag"], np.int32),
             np.ascontiguousarray(arrays["face_shift"], np.float64)]
     wu = None if wall_u is None else np.ascontiguousarray(wall_u, np.float64)
+    tm = None if tet_mid is None else np.ascontiguousarray(tet_mid, np.float64)
     m = G._Mesh(keep[0].shape[0], keep[0].ctypes.data, keep[1].shape[0], keep[1].ctypes.data,
                 keep[2].shape[0], keep[2].ctypes.data, keep[3].ctypes.data, keep[4].ctypes.data,
-                keep[5].ctypes.data, None if wu is None else wu.ctypes.data)
+                keep[5].ctypes.data, None if wu is None else wu.ctypes.data, None if tm is None else tm.ctypes.data)
     st, h = _create(lib, G.default_config())
     assert st == 0
     try:
@@ -184,6 +185,38 @@ def test_sphere_shell_with_far_field_accepted(lib):
     st, st2, nbytes, msg, _, _ = _upload(lib, m)
     assert st == 0 and st2 == 0, msg
     assert set(np.unique(m.face_tag)) == {I.FACE_INTERIOR, I.FACE_SLIP, I.FACE_FARFIELD}
+
+
+def test_quadratic_elements_accepted_and_checked(lib):
+    # bent interior edges on a periodic box, and the sphere with arcs on its wall
+    for m in (I.kuhn_cube_mesh(3, 1.0, 0.1, 1, True, curve=0.08),
+              I.cubed_sphere_shell(4, 3, r_out=3.0, ratio=1.2, curved=True)):
+        st, st2, nbytes, msg, _, _ = _upload(lib, m, tet_mid=m.tet_mid)
+        assert st == 0 and st2 == 0, msg
+        flat = _upload(lib, m)[2]
+        assert nbytes > flat  # the quadratic faces' per-point geometry and surface integrals
+        # straight control points: the flat mesh's workspace
+        assert _upload(lib, m, tet_mid=I.straight_edge_points(m))[2] == flat
+    m = I.kuhn_cube_mesh(3, 1.0, 0.1, 1, True, curve=0.08)
+    # the two cells of a face disagree on one of its control points
+    bad = m.tet_mid.copy()
+    bad[0, 0] += 0.01
+    st, _, _, msg, _, _ = _upload(lib, m, tet_mid=bad)
+    assert st == G.GKS_E_MESH and "control points" in msg
+    # an interior edge bent, in every cell around it, so far that det J
+    # changes sign inside the elements
+    c0 = 6 * 13  # a cell of the centre hexahedron: its edges are interior
+    a, b = m.tet[c0, 0], m.tet[c0, 1]
+    bad = m.tet_mid.copy()
+    p = 0.5 * (m.xyz[a] + m.xyz[b]) + 0.9 * (m.xyz[m.tet[c0, 2]] - m.xyz[a])
+    for e, (u, v) in enumerate(I.QEDGES):
+        hit = ((m.tet[:, u] == a) & (m.tet[:, v] == b)) | ((m.tet[:, u] == b) & (m.tet[:, v] == a))
+        bad[hit, e] = p
+    st, _, _, msg, _, _ = _upload(lib, m, tet_mid=bad)
+    assert st == G.GKS_E_MESH and "det J" in msg
+    bad = m.tet_mid.copy()
+    bad[1, 2, 0] = np.nan
+    assert _upload(lib, m, tet_mid=bad)[0] == G.GKS_E_MESH
 
 
 def test_empty_mesh_rejected(lib):

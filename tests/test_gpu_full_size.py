@@ -23,7 +23,8 @@ the normwise bar and the per-step map to the element-wise one.
   cells) out to r = 20, slip wall, Riemann-invariant far field, the free
   stream rho = 1, U = (0.3, 0, 0), p = 1/gamma disturbed by a smooth density
   and pressure bump next to the wall (inputs.bump_stream_field, centre
-  (1.5, 0, 0));
+  (1.5, 0, 0)); with straight faces, and with quadratic elements whose wall
+  edges are arcs of the sphere (Sec. 2.1);
 * the Taylor-Green workload (196,608 cells, test_gpu_parity.py).
 The oracle takes about half a minute per step on the large meshes.
 """
@@ -72,9 +73,10 @@ def test_blast_full_size_two_steps():
 
 
 @pytest.mark.timeout(900)
-def test_sphere_full_size_two_steps():
+@pytest.mark.parametrize("curved", [False, True], ids=["flat_wall", "quadratic_wall"])
+def test_sphere_full_size_two_steps(curved):
     gamma = 1.4
-    mesh = I.cubed_sphere_shell(32, 48, r_out=20.0, ratio=1.08)
+    mesh = I.cubed_sphere_shell(32, 48, r_out=20.0, ratio=1.08, curved=curved)
     W, gW = I.cell_averages(mesh, I.bump_stream_field(gamma, center=(1.5, 0.0, 0.0)))
     free = I.uniform_state(mesh, 1.0, (0.3, 0.0, 0.0), 1.0 / gamma, gamma)[0][:, 0]
     two_steps(mesh, dict(farfield=tuple(free)), W, gW)

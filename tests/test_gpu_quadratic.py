@@ -1,0 +1,132 @@
+"""Quadratic elements on the GPU (Sec. 2.1 quadratic faces with a normal and
+a weight per Gauss point, eq. flux-para-coord-gauss; Sec. 4.1 quadratic
+tetrahedra by the five-point rule on their map), against the oracle to the
+bars of test_gpu_parity.py, stage by stage:
+
+* the sphere shell with its wall edges on the sphere (6 panels of 4 x 4
+  cells, 4 layers out to r = 3, ratio 1.3; 2,304 cells), slip wall and far
+  field, the bump of test_gpu_sphere.py, Euler and Navier-Stokes;
+* a periodic box of 4^3 x 6 Kuhn tetrahedra whose edges are bent by up to
+  8% of h (inputs.kuhn_cube_mesh curve), the sine wave with WENO weights, the
+  viscous Taylor-Green vortex, and the second-order scheme;
+* a walled box with bent interior edges and no-slip walls, so that the
+  constrained wall fits and their positivity check meet bent cells;
+* the FP32-bulk form close to FP64, uniform flow preserved, and the adjoint
+  refusing a mesh with bent edges.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2102_01366_amd as G
+from paper_2102_01366_amd import inputs as I
+
+from test_gpu_parity import COEF_GROUPS, GW_GROUPS, W_GROUPS, assert_parity, check_face_terms, check_steps
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 1.4
+FREE = np.array([1.0, 0.3, 0.0, 0.0, (1.0 / GAMMA) / (GAMMA - 1) + 0.5 * 0.09])
+
+
+def _case(name):
+    if name in ("sphere_euler", "sphere_ns"):
+        m = I.cubed_sphere_shell(4, 4, r_out=3.0, ratio=1.3, curved=True)
+        W, gW = I.cell_averages(m, I.bump_stream_field(GAMMA))
+        kw = dict(farfield=tuple(FREE))
+        if name == "sphere_ns":
+            kw.update(viscous=True, mu=0.01, prandtl=0.72)
+        return m, kw, W, gW
+    if name == "box_sine_weno":
+        m = I.kuhn_cube_mesh(4, 1.0, 0.1, 0, True, curve=0.08)
+        W, gW = I.cell_averages(m, I.sine_wave_field())
+        return m, dict(), W, gW
+    if name == "box_tgv_viscous":
+        m = I.kuhn_cube_mesh(5, 2 * np.pi, 0.05, 1, True, curve=0.08)
+        W, gW = I.cell_averages(m, I.taylor_green_field())
+        return m, dict(viscous=True, mu=0.01, prandtl=0.72), W, gW
+    if name == "box_order2":
+        m = I.kuhn_cube_mesh(4, 1.0, 0.1, 4, True, curve=0.08)
+        W, gW = I.cell_averages(m, I.sine_wave_field())
+        return m, dict(order=2), W, gW
+    if name == "box_noslip":
+        m = I.with_walls(I.kuhn_cube_mesh(4, 1.0, 0.1, 1, False, curve=0.08),
+                         {"x0": I.FACE_NOSLIP_ADIABATIC, "y1": I.FACE_NOSLIP_ISOTHERMAL}, {"y1": (0.1, 0.0, 0.0)})
+        W, gW = I.cell_averages(m, I.box_vortex_field())
+        return m, dict(viscous=True, mu=0.01, wall_T=1.0), W, gW
+    raise KeyError(name)
+
+
+NAMES = ["sphere_euler", "sphere_ns", "box_sine_weno", "box_tgv_viscous", "box_order2", "box_noslip"]
+
+
+@pytest.fixture(params=NAMES)
+def pair(request):
+    m, kw, W, gW = _case(request.param)
+    assert m.tet_mid is not None
+    return m, G.Solver(m, G.default_config(**kw)), oracle.Oracle(m, oracle.make_config(**kw)), W, gW
+
+
+def test_quadratic_reconstruction(pair):
+    m, s, orc, W, gW = pair
+    s.init(W, gW)
+    b, coef, flag = s.debug_reconstruct()
+    co, fo = orc.reconstruct(W, gW)
+    assert_parity(b, orc.slopes(W, gW), GW_GROUPS, "slopes")
+    assert_parity(coef, co, COEF_GROUPS, "coef")
+    np.testing.assert_array_equal(flag, fo)
+
+
+def test_quadratic_face_terms(pair):
+    m, s, orc, W, gW = pair
+    s.init(W, gW)
+    check_face_terms(s, orc, W, gW, orc.compute_dt(W, 0.5))
+
+
+# The time step to 4e-15: a quadratic face's area is the sum of its point
+# weights, which the library and the oracle round differently, and the
+# viscous bound takes the inscribed radius 3|Omega|/sum|Gamma| squared.
+DT_TOL = 4e-15
+
+
+def test_quadratic_steps(pair):
+    m, s, orc, W, gW = pair
+    check_steps(m, s, orc, W, gW, check_dt=True, dt_tol=DT_TOL)
+
+
+def test_quadratic_steps_on_device_dt(pair):
+    m, s, orc, W, gW = pair
+    check_steps(m, s, orc, W, gW, by_stage=False, on_device_dt=True, dt_tol=DT_TOL)
+
+
+def test_quadratic_uniform_flow_preserved():
+    m = I.kuhn_cube_mesh(4, 1.0, 0.1, 2, True, curve=0.08)
+    W, gW = I.uniform_state(m, 1.0, (0.4, -0.3, 0.2), 1.0)
+    s = G.Solver(m, G.default_config())
+    s.init(W, gW)
+    for _ in range(3):
+        s.step_cfl(0.5)
+    W1, g1 = s.read_state()
+    assert np.abs(W1 - W).max() < 1e-13
+    assert np.abs(g1).max() < 1e-10
+
+
+def test_quadratic_fp32_bulk_close_to_fp64():
+    m, kw, W, gW = _case("sphere_euler")
+    res = []
+    for prec in (G.GKS_FP64, G.GKS_FP32_BULK):
+        s = G.Solver(m, G.default_config(precision=prec, **kw))
+        s.init(W, gW)
+        for _ in range(3):
+            s.step(0.02)
+        res.append(s.read_state()[0])
+    for g in W_GROUPS:
+        assert np.abs(res[1][g] - res[0][g]).max() <= 1e-5 * np.abs(res[0][g]).max()
+
+
+def test_adjoint_refuses_bent_edges():
+    m, kw, W, gW = _case("box_sine_weno")
+    s = G.Solver(m, G.default_config(**kw))
+    s.init(W, gW)
+    with pytest.raises(RuntimeError, match="quadratic"):
+        s.step_adjoint(0.01, *s.read_state(device=True), *s.read_state(device=True))
