@@ -260,7 +260,7 @@ static void qtet_shape(const double xi[3], double N[10], double dN[10][3])
 }
 
 /* The isoparametric map of a quadratic tetrahedron with control points x:
- * X(xi), and |det dX/dxi| there (eq. base-int-change). */
+ * X(xi), and det dX/dxi there (eq. base-int-change). */
 static double qtet_point(const double x[10][3], const double xi[3], double X[3])
 {
     double N[10], dN[10][3], J[3][3] = {{0}};
@@ -272,10 +272,9 @@ static double qtet_point(const double x[10][3], const double xi[3], double X[3])
             for (int j = 0; j < 3; ++j) J[d][j] += dN[l][j] * x[l][d];
         }
     }
-    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                 J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-    return fabs(det);
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
 }
 
 /* Sec. 2.1: the six shape functions of the quadratic triangle at (xi, eta)
@@ -425,8 +424,10 @@ or_ctx *or_create_quadratic(const or_config *cfg, int64_t n_vert, const double *
             for (int e = 0; e < 6; ++e)
                 for (int d = 0; d < 3; ++d) c->cx[i][4 + e][d] = tet_mid[(6 * i + e) * 3 + d];
             double X[5][3], w[5], V = 0.0, cen[3] = {0, 0, 0}, m2[6] = {0, 0, 0, 0, 0, 0};
+            /* a valid element keeps the straight one's orientation at every point */
+            double orient = tet_jac(c->cv[i]) > 0.0 ? 1.0 : -1.0;
             for (int q = 0; q < 5; ++q) {
-                double dj = qtet_point(c->cx[i], VQ_PTS[q], X[q]);
+                double dj = orient * qtet_point(c->cx[i], VQ_PTS[q], X[q]);
                 if (!(dj > 0.0)) { or_destroy(c); return NULL; }
                 w[q] = VQ_W[q] * dj;
                 V += w[q];
@@ -620,7 +621,7 @@ static void cell_avg_monomials(const or_ctx *c, int64_t m, const double shift[3]
         for (int d = 0; d < 3; ++d) x[k][d] = c->cx[m][k][d] + shift[d];
     for (int q = 0; q < 5; ++q) {
         double X[3], y[3];
-        double w = VQ_W[q] * qtet_point(x, VQ_PTS[q], X);
+        double w = VQ_W[q] * fabs(qtet_point(x, VQ_PTS[q], X));
         for (int d = 0; d < 3; ++d) y[d] = (X[d] - origin[d]) / h;
         s[0] += w;
         s[1] += w * y[0]; s[2] += w * y[1]; s[3] += w * y[2];
@@ -1026,7 +1027,7 @@ static real smoothness(const or_ctx *c, int64_t i, const qpoly_t *p, int r)
         double X[3], rr[3], w = VQ_W[q];
         real g[3];
         if (c->curved)
-            w *= qtet_point(c->cx[i], VQ_PTS[q], X);
+            w *= fabs(qtet_point(c->cx[i], VQ_PTS[q], X));
         else
             tet_map(c->cv[i], VQ_PTS[q], X);
         for (int d = 0; d < 3; ++d) rr[d] = X[d] - c->cen[i][d];
