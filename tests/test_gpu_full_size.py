@@ -39,7 +39,7 @@ from test_gpu_parity import GW_GROUPS, W_GROUPS, assert_elementwise, assert_pari
 pytestmark = pytest.mark.gpu
 
 
-def two_steps(mesh, kw, W, gW):
+def two_steps(mesh, kw, W, gW, dt_tol=1e-15):
     s = G.Solver(mesh, G.default_config(**kw))
     free = G.Solver(mesh, G.default_config(**kw))
     orc = oracle.Oracle(mesh, oracle.make_config(**kw))
@@ -50,7 +50,7 @@ def two_steps(mesh, kw, W, gW):
         s.init(Wo, gWo)
         s.step_cfl(0.5)
         free.step_cfl(0.5)
-        assert abs(s.last_dt() - dt) <= 1e-15 * dt and abs(free.last_dt() - dt) <= 1e-14 * dt
+        assert abs(s.last_dt() - dt) <= dt_tol * dt and abs(free.last_dt() - dt) <= 1e-14 * dt
         Wo, gWo = orc.stage(1, dt, Wo, gWo)
         ft1 = orc.last_face_terms()
         Wo, gWo = orc.stage(2, dt, Wo, gWo)
@@ -79,4 +79,6 @@ def test_sphere_full_size_two_steps(curved):
     mesh = I.cubed_sphere_shell(32, 48, r_out=20.0, ratio=1.08, curved=curved)
     W, gW = I.cell_averages(mesh, I.bump_stream_field(gamma, center=(1.5, 0.0, 0.0)))
     free = I.uniform_state(mesh, 1.0, (0.3, 0.0, 0.0), 1.0 / gamma, gamma)[0][:, 0]
-    two_steps(mesh, dict(farfield=tuple(free)), W, gW)
+    # quadratic faces: areas are sums of point weights, rounded differently
+    # by the library and the oracle (test_gpu_quadratic.DT_TOL)
+    two_steps(mesh, dict(farfield=tuple(free)), W, gW, dt_tol=4e-15 if curved else 1e-15)
