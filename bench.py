@@ -23,7 +23,9 @@ viscous Taylor-Green vortex (196,608 cells: throughput, kinetic-energy decay,
 FP32-bulk error); the differentiation form (adjoint / forward time, central
 differences, and the 3,072-cell check against the oracle's tangent build);
 the lid-driven cavity (no-slip isothermal walls, smooth-flow flux); flow past
-a sphere on a cubed-sphere shell (1.77M cells, slip wall and far field); and
+a sphere on a cubed-sphere shell (1.77M cells, quadratic slip wall and far
+field: throughput, and 2,000 steps with drag and entropy error beside the
+same mesh with straight wall faces); and
 the FP64 CPU oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
@@ -77,8 +79,8 @@ PROFILE_NAMES = {
                     "gks::flux_kernel<double, 0, false, false, true, false, false>"),
     "flux_stage2": ("gks::flux_kernel<double, 1, false, false, false, false, false>",
                     "gks::flux_kernel<double, 1, false, false, true, false, false>"),
-    "update_stage1": ("gks::update_kernel<double, 1>",),
-    "update_stage2": ("gks::update_kernel<double, 2>",),
+    "update_stage1": ("gks::update_kernel<double, 1, false>",),
+    "update_stage2": ("gks::update_kernel<double, 2, false>",),
     "dt": ("gks::dt_pass1",),
 }
 # the kernel sources whose digest the committed counter summaries record
@@ -511,22 +513,27 @@ def cavity_leg(G, I, n, steps, warmup):
     return out
 
 
-def sphere_leg(G, I, n, layers, steps, warmup):
-    """The curved-wall workload's mesh with straight faces: inviscid Mach 0.3
-    flow past the unit sphere on a cubed-sphere shell (6 panels of n x n
-    cells, `layers` radial layers stretched by 1.08 out to r = 20, each
-    hexahedron split into 6 tetrahedra), slip wall on the sphere, far field
-    by Riemann invariants, impulsive start from the free stream rho = 1,
-    U = (0.3, 0, 0), p = 1/gamma, third-order WENO, CFL 0.5; FP64 and
-    FP32-bulk."""
+def sphere_leg(G, I, n, layers, steps, warmup, long_steps):
+    """The curved-wall workload: inviscid Mach 0.3 flow past the unit sphere
+    on a cubed-sphere shell (6 panels of n x n cells, `layers` radial layers
+    stretched by 1.08 out to r = 20, each hexahedron split into 6
+    tetrahedra) with quadratic elements whose wall edges are arcs of the
+    sphere (Sec. 2.1), slip wall, far field by Riemann invariants, impulsive
+    start from the free stream rho = 1, U = (0.3, 0, 0), p = 1/gamma,
+    third-order WENO, CFL 0.5.  Throughput in FP64 and FP32-bulk over
+    `steps` steps; then `long_steps` FP64 steps with the quadratic wall and
+    with straight wall faces on the same vertices, reporting the drag
+    coefficient (the wall faces' momentum flux, the pressure force on the
+    sphere, over rho U^2 pi / 2) and the entropy error s / s_inf - 1, s =
+    p / rho^gamma, over the cells next to the wall and over all cells."""
     import numpy as np
     import torch
     gamma = 1.4
-    mesh = I.cubed_sphere_shell(n, layers, r_out=20.0, ratio=1.08)
+    mesh = I.cubed_sphere_shell(n, layers, r_out=20.0, ratio=1.08, curved=True)
     W, gW = I.uniform_state(mesh, 1.0, (0.3, 0.0, 0.0), 1.0 / gamma, gamma)
     free = tuple(W[:, 0])
     out = {"workload": f"Mach 0.3 past the unit sphere, cubed-sphere shell 6 x {n}^2 x {layers} layers "
-                       f"x 6 tets ({mesh.n_cell} cells, {mesh.n_face} faces), straight faces, slip wall, "
+                       f"x 6 tets ({mesh.n_cell} cells, {mesh.n_face} faces), quadratic wall faces, slip wall, "
                        f"Riemann-invariant far field at r = 20, Euler, CFL 0.5",
            "cells": mesh.n_cell, "faces": mesh.n_face, "steps": steps}
     for name, prec in (("fp64", G.GKS_FP64), ("fp32_bulk", G.GKS_FP32_BULK)):
@@ -546,7 +553,56 @@ def sphere_leg(G, I, n, layers, steps, warmup):
         out[name] = {"value": mesh.n_cell * 2 * steps / el, "unit": "cell-stage-updates/s",
                      "ms_per_step": el / steps * 1e3,
                      "kernels_ms": {k: ms / cnt for k, (ms, cnt) in kt.items() if cnt}}
+        del s
+    if long_steps > 0:
+        out["long_run"] = {"steps": long_steps, "quadratic_wall": sphere_long_run(G, mesh, W, gW, free, long_steps)}
+        mesh.tet_mid = None
+        out["long_run"]["straight_wall"] = sphere_long_run(G, mesh, W, gW, free, long_steps)
     return out
+
+
+def sphere_long_run(G, mesh, W, gW, free, nsteps, every=500):
+    """FP64 steps of the sphere flow from the free stream: time reached, the
+    drag coefficient every `every` steps, the entropy errors at the end; stops
+    where a cell turns non-physical."""
+    import numpy as np
+    import torch
+    gamma = 1.4
+    wall = np.nonzero(mesh.face_tag == 2)[0]
+    wall_cells = np.unique(mesh.face_cell[wall, 0])
+    s = G.Solver(mesh, G.default_config(farfield=free), device="cuda:0")
+    s.init(W, gW)
+    t, n, cd, failed = 0.0, 0, [], False
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+
+    def drag(dt):
+        ft = s.debug_face_terms(dt)
+        return float(ft[1, wall].sum() / (0.5 * 1.0 * 0.3 ** 2 * np.pi))
+
+    while n < nsteps:
+        try:
+            s.step_cfl(0.5)
+        except G.GksError:
+            failed = True
+            break
+        t += s.last_dt()
+        n += 1
+        if n % every == 0 or n == nsteps:
+            cd.append([n, t, drag(s.last_dt())])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    r = {"steps": n, "t_reached": t, "nonphysical": failed, "wall_s": el, "drag_coefficient": cd}
+    if not failed:
+        Wf = s.read_state()[0]
+        rho = Wf[0]
+        p = (gamma - 1.0) * (Wf[4] - 0.5 * (Wf[1] ** 2 + Wf[2] ** 2 + Wf[3] ** 2) / rho)
+        e = (p / rho ** gamma) / ((1.0 / gamma) / 1.0) - 1.0
+        r["entropy_error"] = {"wall_cells_rms": float(np.sqrt((e[wall_cells] ** 2).mean())),
+                              "wall_cells_max": float(np.abs(e[wall_cells]).max()),
+                              "all_cells_rms": float(np.sqrt((e ** 2).mean())),
+                              "all_cells_max": float(np.abs(e).max())}
+    return r
 
 
 def main():
@@ -572,7 +628,10 @@ def main():
     ap.add_argument("--sphere-n", type=int, default=32,
                     help="cells per panel side of the sphere leg (0 skips it)")
     ap.add_argument("--sphere-layers", type=int, default=48)
-    ap.add_argument("--sphere-steps", type=int, default=4)
+    ap.add_argument("--sphere-steps", type=int, default=20)
+    ap.add_argument("--sphere-long-steps", type=int, default=2000,
+                    help="FP64 steps of the sphere flow with quadratic and with straight wall faces "
+                         "(drag, entropy error; 0 skips them)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a 256 MiB fill (writes 256 MiB) and a 256 MiB elementwise add "
                          "(reads and writes 256 MiB): known byte counts that calibrate rocprofv3 "
@@ -723,8 +782,8 @@ def main():
     torch.cuda.empty_cache()
     print("cavity, sphere", file=sys.stderr, flush=True)
     out["cavity_noslip"] = cavity_leg(G, I, args.cavity_n, args.cavity_steps, 2) if args.cavity_n > 0 else None
-    out["sphere_farfield"] = (sphere_leg(G, I, args.sphere_n, args.sphere_layers, args.sphere_steps, 1)
-                              if args.sphere_n > 0 else None)
+    out["sphere_farfield"] = (sphere_leg(G, I, args.sphere_n, args.sphere_layers, args.sphere_steps, 1,
+                                         args.sphere_long_steps) if args.sphere_n > 0 else None)
     if not args.no_cpu_baseline:
         print("cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(I, mesh, W, gW, {}, args.cpu_baseline_steps, args.cpu_serial_n)

@@ -659,9 +659,11 @@ __global__ __launch_bounds__(kRecThreads) void wall_reconstruct_kernel(DevMesh m
 }
 
 // ===========================================================================
-// C: cell update (eqs. flux-operator, s2o4, gauss-formula, step-du)
+// C: cell update (eqs. flux-operator, s2o4, gauss-formula, step-du).
+// CURVED: the mesh has quadratic faces [nfc, nf), whose gradient terms come
+// per Gauss point; without it the face loop keeps one form for every face.
 // ===========================================================================
-template <typename R, int STAGE>
+template <typename R, int STAGE, bool CURVED>
 __global__ __launch_bounds__(kBlock) void update_kernel(DevMesh m, DevState s, double dt_, const double *dtp)
 {
     const double dt = dtp ? *dtp : dt_;
@@ -678,6 +680,21 @@ __global__ __launch_bounds__(kBlock) void update_kernel(DevMesh m, DevState s, d
         const int code = m.cface[a * n + i];
         const int f = code >> 1;
         const double sg = (code & 1) ? -1.0 : 1.0;
+        if (!CURVED) {
+            double nrm[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) nrm[d] = m.fnrm[(size_t)d * nf + f];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const size_t o = (size_t)q * nf + f;
+                if (STAGE == 1) L[q] -= sg * double(FF[o]);
+                Lt[q] -= sg * double(FT[o]);
+                const double wf = STAGE == 1 ? double(FWs[o]) : double(FW0[o]) + double(FWs[o]);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) G[3 * q + d] += sg * wf * nrm[d];
+            }
+            continue;
+        }
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             const size_t o = (size_t)q * nf + f;
@@ -940,20 +957,29 @@ hipError_t launch_wall_reconstruct(const DevMesh &m, const DevState &s, const Pa
     return hipGetLastError();
 }
 
+template <typename R, int STAGE>
+static void launch_update_t(const DevMesh &m, const DevState &s, double dt, const double *dtp, hipStream_t st)
+{
+    const dim3 g = grid_for(m.nc), b(kBlock);
+    if (m.nfc < m.nf)
+        hipLaunchKernelGGL((update_kernel<R, STAGE, true>), g, b, 0, st, m, s, dt, dtp);
+    else
+        hipLaunchKernelGGL((update_kernel<R, STAGE, false>), g, b, 0, st, m, s, dt, dtp);
+}
+
 hipError_t launch_update(const DevMesh &m, const DevState &s, double dt, const double *dtp,
                          int stage, bool fp32, hipStream_t st)
 {
-    const dim3 g = grid_for(m.nc), b(kBlock);
     if (fp32) {
         if (stage == 1)
-            hipLaunchKernelGGL((update_kernel<float, 1>), g, b, 0, st, m, s, dt, dtp);
+            launch_update_t<float, 1>(m, s, dt, dtp, st);
         else
-            hipLaunchKernelGGL((update_kernel<float, 2>), g, b, 0, st, m, s, dt, dtp);
+            launch_update_t<float, 2>(m, s, dt, dtp, st);
     } else {
         if (stage == 1)
-            hipLaunchKernelGGL((update_kernel<double, 1>), g, b, 0, st, m, s, dt, dtp);
+            launch_update_t<double, 1>(m, s, dt, dtp, st);
         else
-            hipLaunchKernelGGL((update_kernel<double, 2>), g, b, 0, st, m, s, dt, dtp);
+            launch_update_t<double, 2>(m, s, dt, dtp, st);
     }
     return hipGetLastError();
 }
