@@ -325,7 +325,9 @@ struct or_ctx {
     double (*cx)[10][3];  /* control points of each cell (curved meshes) */
     /* stage storage */
     real *Wn, *Ln, *Ltn;  /* W^n [5][nc], L(W^n), dL/dt(W^n) */
-    real *FG0;            /* stage 1: sum_k w_k W_k(0) n_k per face [15][nf] */
+    char *fflat;          /* the face's Gauss points share one normal (bitwise) */
+    real *FG0;            /* stage 1: sum_k w_k W_k(0) n_k per face [15][nf]; on a flat face
+                             rows 0..4 hold sum_k w_k W_k(0) */
     real *fgrad;          /* last face terms: sum_k w_k W_k(0) n_k and sum_k w_k W_k(dt) n_k [30][nf] */
     real *slopes, *coef, *fterm;
     int32_t *flag;
@@ -351,7 +353,7 @@ void or_destroy(or_ctx *c)
     free(c->cv); free(c->vol); free(c->cen); free(c->m2); free(c->dr);
     free(c->nbr); free(c->cface); free(c->noff); free(c->fcell); free(c->ftag); free(c->fwu);
     free(c->fshift); free(c->farea); free(c->fnorm); free(c->fgp); free(c->fpn); free(c->fpw); free(c->cx);
-    free(c->Wn); free(c->Ln); free(c->Ltn); free(c->FG0); free(c->fgrad);
+    free(c->Wn); free(c->Ln); free(c->Ltn); free(c->FG0); free(c->fgrad); free(c->fflat);
     free(c->slopes); free(c->coef); free(c->fterm); free(c->flag);
     free(c);
 }
@@ -398,6 +400,7 @@ or_ctx *or_create_quadratic(const or_config *cfg, int64_t n_vert, const double *
     c->Ln = (real *)xcalloc(5 * nc, sizeof(real));
     c->Ltn = (real *)xcalloc(5 * nc, sizeof(real));
     c->FG0 = (real *)xcalloc(15 * nf, sizeof(real));
+    c->fflat = (char *)xcalloc(nf, 1);
     c->fgrad = (real *)xcalloc(30 * nf, sizeof(real));
     c->slopes = (real *)xcalloc(15 * nc, sizeof(real));
     c->coef = (real *)xcalloc(50 * nc, sizeof(real));
@@ -533,6 +536,10 @@ or_ctx *or_create_quadratic(const or_config *cfg, int64_t n_vert, const double *
             }
             c->farea[f] = area;
         }
+        c->fflat[f] = 1;
+        for (int q = 1; q < 3; ++q)
+            for (int d = 0; d < 3; ++d)
+                if (c->fpn[f][q][d] != c->fpn[f][0][d]) c->fflat[f] = 0;
         sumarea[L] += c->farea[f];
         if (R >= 0) sumarea[R] += c->farea[f];
         /* neighbour slots */
@@ -1981,14 +1988,26 @@ int or_stage(or_ctx *c, int stage, double dt, real *W, real *gW)
     real *L = (real *)malloc(sizeof(real) * 5 * n);
     real *Lt = (real *)malloc(sizeof(real) * 5 * n);
     if (stage == 1) {
-        /* eq. step-du with a linear-in-time f: f* = (f(0) + f(dt)) / 2 */
-        for (int64_t f = 0; f < nf; ++f)
+        /* eq. step-du with a linear-in-time f: f* = (f(0) + f(dt)) / 2; on a
+         * flat face sum_k w_k W_k n_k = (sum_k w_k W_k) n */
+        for (int64_t f = 0; f < nf; ++f) {
+            if (c->fflat[f]) {
+                for (int q = 0; q < 5; ++q) {
+                    real w0 = c->fterm[(size_t)(10 + q) * nf + f];
+                    real w1 = c->fterm[(size_t)(15 + q) * nf + f];
+                    real wf = 0.5 * (w0 + w1);
+                    c->FG0[(size_t)q * nf + f] = w0;
+                    for (int d = 0; d < 3; ++d) Gf[(size_t)(3 * q + d) * nf + f] = wf * c->fpn[f][0][d];
+                }
+                continue;
+            }
             for (int k = 0; k < 15; ++k) {
                 real g0 = c->fgrad[(size_t)k * nf + f];
                 real g1 = c->fgrad[(size_t)(15 + k) * nf + f];
                 c->FG0[(size_t)k * nf + f] = g0;
                 Gf[(size_t)k * nf + f] = 0.5 * (g0 + g1);
             }
+        }
         gather(c, c->fterm, Gf, L, Lt, gW);
         /* eq. s2o4, first stage */
         for (int64_t k = 0; k < 5 * n; ++k) {
@@ -2000,10 +2019,19 @@ int or_stage(or_ctx *c, int stage, double dt, real *W, real *gW)
         c->have_stage1 = 1;
     } else {
         /* f^{n+1} = f^n + dt f_t*, f_t* = (f*(dt) - f*(0)) / dt */
-        for (int64_t f = 0; f < nf; ++f)
+        for (int64_t f = 0; f < nf; ++f) {
+            if (c->fflat[f]) {
+                for (int q = 0; q < 5; ++q) {
+                    real wf = c->FG0[(size_t)q * nf + f] + c->fterm[(size_t)(15 + q) * nf + f] -
+                              c->fterm[(size_t)(10 + q) * nf + f];
+                    for (int d = 0; d < 3; ++d) Gf[(size_t)(3 * q + d) * nf + f] = wf * c->fpn[f][0][d];
+                }
+                continue;
+            }
             for (int k = 0; k < 15; ++k)
                 Gf[(size_t)k * nf + f] = c->FG0[(size_t)k * nf + f] + c->fgrad[(size_t)(15 + k) * nf + f] -
                                          c->fgrad[(size_t)k * nf + f];
+        }
         gather(c, c->fterm, Gf, L, Lt, gW);
         /* eq. s2o4, second stage: only dL/dt(W*) enters */
         for (int64_t k = 0; k < 5 * n; ++k)

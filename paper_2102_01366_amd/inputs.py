@@ -492,8 +492,27 @@ def bump_stream_field(gamma: float = 1.4, speed: float = 0.3, center=(2.0, 0.0, 
     return f
 
 
+def _quadratic_map(x: np.ndarray, pts: np.ndarray):
+    """Points X [c, q, 3] and |det dX/dxi| [c, q] of ten-node tetrahedra with
+    nodes x [c, 10, 3] (vertices, then the points on the edges QEDGES) at
+    reference points pts [q, 3]: vertex shape functions l (2l - 1), edge ones
+    4 l_a l_b in the barycentric coordinates l."""
+    lam = np.concatenate([1.0 - pts.sum(axis=1, keepdims=True), pts], axis=1)       # [q, 4]
+    dlam = np.array([[-1.0, -1.0, -1.0], [1, 0, 0], [0, 1, 0], [0, 0, 1]])           # [4, 3]
+    N = [lam[:, a] * (2 * lam[:, a] - 1) for a in range(4)]
+    dN = [(4 * lam[:, a] - 1)[:, None] * dlam[a] for a in range(4)]
+    for a, b in QEDGES:
+        N.append(4 * lam[:, a] * lam[:, b])
+        dN.append(4 * (lam[:, b][:, None] * dlam[a] + lam[:, a][:, None] * dlam[b]))
+    N, dN = np.stack(N, axis=1), np.stack(dN, axis=1)                                # [q, 10], [q, 10, 3]
+    X = np.einsum("ql,cld->cqd", N, x)
+    J = np.einsum("qlj,cld->cqdj", dN, x)
+    return X, np.abs(np.linalg.det(J))
+
+
 def cell_averages(mesh: TetMesh, field, npts: int = 6, chunk: int = 65536):
-    """Exact (to quadrature) cell averages of a field and of its gradient.
+    """Exact (to quadrature) cell averages of a field and of its gradient;
+    over a quadratic element (``tet_mid``) through its isoparametric map.
 
     Returns ``W[5, n_cell]`` and ``gW[15, n_cell]`` (row 3 c + d)."""
     pts, wt = tet_rule(npts)
@@ -503,11 +522,19 @@ def cell_averages(mesh: TetMesh, field, npts: int = 6, chunk: int = 65536):
     v_all = mesh.xyz[mesh.tet]
     for s in range(0, nc, chunk):
         v = v_all[s:s + chunk]
-        e = v[:, 1:, :] - v[:, :1, :]
-        X = v[:, None, 0, :] + np.einsum("qk,ckd->cqd", pts, e)
-        Q, dQ = field(X)  # Q [5, c, q], dQ [5, 3, c, q]
-        W[:, s:s + chunk] = Q @ wt
-        gW[:, s:s + chunk] = (dQ @ wt).reshape(15, -1)
+        if mesh.tet_mid is None:
+            e = v[:, 1:, :] - v[:, :1, :]
+            X = v[:, None, 0, :] + np.einsum("qk,ckd->cqd", pts, e)
+            Q, dQ = field(X)  # Q [5, c, q], dQ [5, 3, c, q]
+            W[:, s:s + chunk] = Q @ wt
+            gW[:, s:s + chunk] = (dQ @ wt).reshape(15, -1)
+            continue
+        X, dj = _quadratic_map(np.concatenate([v, mesh.tet_mid[s:s + chunk]], axis=1), pts)
+        w = dj * wt
+        w = w / w.sum(axis=1, keepdims=True)
+        Q, dQ = field(X)
+        W[:, s:s + chunk] = np.einsum("pcq,cq->pc", Q, w)
+        gW[:, s:s + chunk] = np.einsum("pdcq,cq->pdc", dQ, w).reshape(15, -1)
     return W, gW
 
 
