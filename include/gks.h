@@ -115,8 +115,9 @@ void gks_default_config(gks_config *cfg);
  * owner's control points, and each of its Gauss points its own normal and
  * weight (eq. flux-para-coord-gauss).  GKS_E_MESH if det J <= 0 at a
  * quadrature point or the two cells of a face disagree on its control
- * points (after the periodic shift).  The adjoint does not cover meshes with
- * bent edges.  NULL: straight-sided tetrahedra. */
+ * points (after the periodic shift).  The adjoint covers them (the quadratic
+ * faces' points with their own normals and weights).  NULL: straight-sided
+ * tetrahedra. */
 typedef struct {
     int64_t n_vert;
     const double *xyz;        /* [n_vert][3] */

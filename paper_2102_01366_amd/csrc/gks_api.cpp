@@ -66,6 +66,7 @@ struct gks_ctx {
         void *slopes1, *slopes2, *coef1, *coef2, *FF, *FT, *FW0, *FWs;
         int *flag1, *flag2, *nonphys;
         double *CB, *own_w, *own_s, *nb_w, *nb_g, *nb_s, *nb_w1, *Wtmp, *red, *EQ, *SB;
+        void *GC0, *GCs;
     } adj{};
     double *staging = nullptr;
     int *istaging = nullptr;
@@ -1509,10 +1510,11 @@ namespace {
 enum AdjSlot {
     A_WCHK, A_GCHK, A_WS, A_GS, A_WN, A_LN, A_LTN, A_WB1, A_GB1, A_WBS, A_GBS, A_WBN, A_GBN,
     A_SLOPES1, A_SLOPES2, A_COEF1, A_COEF2, A_FF, A_FT, A_FW0, A_FWS, A_FLAG1, A_FLAG2, A_NONPHYS,
-    A_CB, A_OWNW, A_OWNS, A_NBW, A_NBG, A_NBS, A_NBW1, A_WTMP, A_RED, A_EQ, A_SB, A_COUNT
+    A_CB, A_OWNW, A_OWNS, A_NBW, A_NBG, A_NBS, A_NBW1, A_WTMP, A_RED, A_EQ, A_SB, A_GC0, A_GCS, A_COUNT
 };
 
-Layout make_adj_layout(size_t nc, size_t nf, size_t bs)
+// ncf: faces on the quadratic path (their per-point interface values)
+Layout make_adj_layout(size_t nc, size_t nf, size_t bs, size_t ncf)
 {
     const size_t d5 = 5 * nc * 8, d15 = 15 * nc * 8;
     const size_t sz[A_COUNT] = {
@@ -1521,7 +1523,8 @@ Layout make_adj_layout(size_t nc, size_t nf, size_t bs)
         5 * nf * bs, 5 * nf * bs, 5 * nf * bs, 5 * nf * bs,
         nc * sizeof(int), nc * sizeof(int), 64,
         100 * nf * 8, d5, d15, 4 * d5, 4 * d15, 4 * d15, 4 * d5, d5,
-        (8 + 5 * (size_t)gks::kRedBlocks) * 8, gks::kEqRec * 3 * nf * 8, gks::kSideRec * 6 * nf * 8};
+        (8 + 5 * (size_t)gks::kRedBlocks) * 8, gks::kEqRec * 3 * nf * 8, gks::kSideRec * 6 * nf * 8,
+        15 * ncf * bs, 15 * ncf * bs};
     Layout L;
     size_t o = 0;
     for (int k = 0; k < A_COUNT; ++k) {
@@ -1538,7 +1541,7 @@ gks_status gks_adjoint_workspace_bytes(const gks_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return GKS_E_INVAL;
     if (!c->have_mesh) return GKS_E_STATE;
-    *bytes = make_adj_layout(c->nc, c->nf, c->fp32 ? 4 : 8).total;
+    *bytes = make_adj_layout(c->nc, c->nf, c->fp32 ? 4 : 8, c->nf - c->nfc).total;
     return GKS_OK;
 }
 
@@ -1547,9 +1550,8 @@ gks_status gks_bind_adjoint_workspace(gks_ctx *c, void *dev, size_t bytes)
     if (!c || !dev) return GKS_E_INVAL;
     if (!c->bound) return fail(c, GKS_E_STATE, "bind the forward workspace first");
     if (c->adj_bound) return fail(c, GKS_E_STATE, "adjoint workspace already bound");
-    if (c->curved) return fail(c, GKS_E_INVAL, "the adjoint does not cover quadratic (bent) elements");
     if (((uintptr_t)dev) & 255) return fail(c, GKS_E_INVAL, "workspace must be 256-byte aligned");
-    const Layout L = make_adj_layout(c->nc, c->nf, c->fp32 ? 4 : 8);
+    const Layout L = make_adj_layout(c->nc, c->nf, c->fp32 ? 4 : 8, c->nf - c->nfc);
     if (bytes < L.total) return fail(c, GKS_E_NOMEM, "adjoint workspace too small");
     char *w = (char *)dev;
     auto P = [&](int k) { return (void *)(w + L.off[k]); };
@@ -1589,6 +1591,8 @@ gks_status gks_bind_adjoint_workspace(gks_ctx *c, void *dev, size_t bytes)
     a.red = (double *)P(A_RED);
     a.EQ = (double *)P(A_EQ);
     a.SB = (double *)P(A_SB);
+    a.GC0 = P(A_GC0);
+    a.GCs = P(A_GCS);
     HIP_TRY(c, gks::launch_fill_int(a.nonphys, 0, c->stream));
     c->adj_bound = true;
     return GKS_OK;
@@ -1632,6 +1636,8 @@ gks_status gks_step_adjoint(gks_ctx *c, double dt, const double *W_n, const doub
     f1.FT = a.FT;
     f1.FW0 = a.FW0;
     f1.FWs = a.FWs;
+    f1.GC0 = a.GC0;
+    f1.GCs = a.GCs;
     f1.red = a.red;
     f1.nonphys = a.nonphys;
     HIP_TRY(c, slopes_step(dm, f1, c->par, f32, s));

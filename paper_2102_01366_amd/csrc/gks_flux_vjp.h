@@ -42,7 +42,8 @@ constexpr int kFaces3A = 21 * kWavesA, kFaces6A = 10 * kWavesA;
 // Per Gauss point k of face f: the face frame, both sides' point states in it
 // (the slip ghost on a wall face) and the offsets of the polynomial
 // evaluations; with ADJ also the adjoints Fob, Wob of the point outputs,
-// formed from the cells' adjoints (the transpose of the cell update).
+// formed from the cells' adjoints (the transpose of the cell update).  A
+// quadratic face's point has its own normal and weight in both.
 // the wall tag of wall face f and its wall velocity (global frame)
 template <typename R>
 __device__ __forceinline__ int wall_bc(const DevMesh &m, int f, R u[3])
@@ -62,10 +63,14 @@ __device__ __forceinline__ void gp_setup(const DevMesh &m, const AdjFlux &a, con
     const int nf = m.nf, n = m.nc;
     const int L = m.fcell[f], Rc = WALL ? L : m.fcell[nf + f];
     const R *fg = static_cast<const R *>(m.fgeo);
+    // a face on the quadratic path: this Gauss point's own normal and weight
+    const bool quad = f >= m.nfc;
+    const int nq = nf - m.nfc, fq = f - m.nfc;
+    const R *cg = static_cast<const R *>(m.cgeo);
     R nrm[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        nrm[d] = fg[(size_t)(F_N + d) * nf + f];
+        nrm[d] = quad ? cg[(size_t)(4 * k + d) * nq + fq] : fg[(size_t)(F_N + d) * nf + f];
         off[0][d] = fg[(size_t)(F_RL + 3 * k + d) * nf + f];
         off[1][d] = off[0][d] + fg[(size_t)(F_D + d) * nf + f];
     }
@@ -84,7 +89,7 @@ __device__ __forceinline__ void gp_setup(const DevMesh &m, const AdjFlux &a, con
     const double iR = WALL ? 0.0 : m.geoD[(size_t)G_INVVOL * n + Rc];
     double nn[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) nn[d] = m.fnrm[(size_t)d * nf + f];
+    for (int d = 0; d < 3; ++d) nn[d] = quad ? m.cnrm[(size_t)(3 * k + d) * nq + fq] : m.fnrm[(size_t)d * nf + f];
     const double dt2 = dt_ * dt_;
     R accb[4][5];
 #pragma unroll
@@ -116,7 +121,7 @@ __device__ __forceinline__ void gp_setup(const DevMesh &m, const AdjFlux &a, con
         }
     }
     // acc0 = w (4 Fh - F1)/dt, acc1 = 4 w (F1 - 2 Fh)/dt^2, acc2 = w W0, acc3 = w W1
-    const R w = fg[(size_t)F_AREA * nf + f] * R(1.0 / 3.0);
+    const R w = (quad ? cg[(size_t)(4 * k + 3) * nq + fq] : fg[(size_t)F_AREA * nf + f]) * R(1.0 / 3.0);
     const R idt = R(1.0 / dt_);
     R gF1[5], gFh[5], gW0[5], gW1[5];
 #pragma unroll

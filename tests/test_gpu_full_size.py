@@ -50,14 +50,19 @@ def two_steps(mesh, kw, W, gW, dt_tol=1e-15, grad_tol=1e-12):
     free.init(W, gW)
     Wo, gWo = W, gW
     for step in range(2):
+        # progress on stdout (shown under pytest -s): the oracle takes about a
+        # minute per stage on these meshes
+        print(f"full size: {mesh.n_cell} cells, step {step}", flush=True)
         dt = orc.compute_dt(Wo, 0.5)
         s.init(Wo, gWo)
         s.step_cfl(0.5)
         free.step_cfl(0.5)
         assert abs(s.last_dt() - dt) <= dt_tol * dt and abs(free.last_dt() - dt) <= 1e-14 * dt
         Wo, gWo = orc.stage(1, dt, Wo, gWo)
+        print(f"full size: oracle stage 1 of step {step} done", flush=True)
         ft1 = orc.last_face_terms()
         Wo, gWo = orc.stage(2, dt, Wo, gWo)
+        print(f"full size: oracle stage 2 of step {step} done", flush=True)
         Wg, gWg = s.read_state()
         B = orc.gradient_bound(2, ft1)
         assert_parity(Wg, Wo, W_GROUPS, f"W step {step}")
