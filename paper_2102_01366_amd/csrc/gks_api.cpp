@@ -824,6 +824,10 @@ gks_status gks_mesh_upload(gks_ctx *c, const gks_mesh *m)
         }
         for (int d = 0; d < 3; ++d)
             avec[3 * (size_t)f + d] = (pa[0] * pn[0][d] + pa[1] * pn[1][d] + pa[2] * pn[2][d]) / 3.0;
+        if (j >= nfc) {
+            // the cell update takes this face's gradient terms per Gauss point
+            for (int d = 0; d < 3; ++d) fnrm64[(size_t)d * nf + j] = 0.0;
+        }
         if (j >= nfc)
             for (int k = 0; k < 3; ++k) {
                 for (int d = 0; d < 3; ++d) {

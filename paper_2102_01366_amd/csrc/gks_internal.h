@@ -119,7 +119,8 @@ struct DevMesh {
     const double *geoD; // [NGEO_D][nc]
     const int *fcell;   // [2][nf] owner, neighbour (-1 on a wall)
     const void *fgeo;   // [NFGEO][nf]
-    const double *fnrm; // [3][nf] unit normal in FP64 (the Gauss sums of the cell update)
+    const double *fnrm; // [3][nf] unit normal in FP64 (the Gauss sums of the cell update); zero on
+                        // the quadratic faces [nfc, nf), which use cnrm
     const int *bslot;   // [4][nc] slot of neighbour a whose face is the cell's slot a (-1 on a wall)
     const int *bmode;   // [nc] 1: fewer than three neighbours, step-1 slopes = own averaged gradient
     const int *wtag;    // [nf - nfi] WallTag of wall face nfi + k

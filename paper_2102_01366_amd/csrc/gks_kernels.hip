@@ -661,7 +661,7 @@ __global__ __launch_bounds__(kRecThreads) void wall_reconstruct_kernel(DevMesh m
 // ===========================================================================
 // C: cell update (eqs. flux-operator, s2o4, gauss-formula, step-du).
 // CURVED: the mesh has quadratic faces [nfc, nf), whose gradient terms come
-// per Gauss point; without it the face loop keeps one form for every face.
+// per Gauss point in a second pass over the cell's faces.
 // ===========================================================================
 template <typename R, int STAGE, bool CURVED>
 __global__ __launch_bounds__(kBlock) void update_kernel(DevMesh m, DevState s, double dt_, const double *dtp)
@@ -680,43 +680,31 @@ __global__ __launch_bounds__(kBlock) void update_kernel(DevMesh m, DevState s, d
         const int code = m.cface[a * n + i];
         const int f = code >> 1;
         const double sg = (code & 1) ? -1.0 : 1.0;
-        if (!CURVED) {
-            double nrm[3];
+        // on a mesh with quadratic faces their fnrm rows are zero: they add
+        // their gradient terms below
+        double nrm[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) nrm[d] = m.fnrm[(size_t)d * nf + f];
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                const size_t o = (size_t)q * nf + f;
-                if (STAGE == 1) L[q] -= sg * double(FF[o]);
-                Lt[q] -= sg * double(FT[o]);
-                const double wf = STAGE == 1 ? double(FWs[o]) : double(FW0[o]) + double(FWs[o]);
-#pragma unroll
-                for (int d = 0; d < 3; ++d) G[3 * q + d] += sg * wf * nrm[d];
-            }
-            continue;
-        }
+        for (int d = 0; d < 3; ++d) nrm[d] = m.fnrm[(size_t)d * nf + f];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             const size_t o = (size_t)q * nf + f;
             if (STAGE == 1) L[q] -= sg * double(FF[o]);
             Lt[q] -= sg * double(FT[o]);
+            const double wf = STAGE == 1 ? double(FWs[o]) : double(FW0[o]) + double(FWs[o]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) G[3 * q + d] += sg * wf * nrm[d];
         }
-        if (f < m.nfc) {
-            double nrm[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) nrm[d] = m.fnrm[(size_t)d * nf + f];
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                const size_t o = (size_t)q * nf + f;
-                const double wf = STAGE == 1 ? double(FWs[o]) : double(FW0[o]) + double(FWs[o]);
-#pragma unroll
-                for (int d = 0; d < 3; ++d) G[3 * q + d] += sg * wf * nrm[d];
-            }
-        } else {
-            // a quadratic face: each Gauss point's weighted interface value
-            // times that point's own normal
-            const R *GC0 = static_cast<const R *>(s.GC0), *GCs = static_cast<const R *>(s.GCs);
-            const int nq = nf - m.nfc, fq = f - m.nfc;
+    }
+    if (CURVED) {
+        // quadratic faces: each Gauss point's weighted interface value times
+        // that point's own normal
+        const R *GC0 = static_cast<const R *>(s.GC0), *GCs = static_cast<const R *>(s.GCs);
+        const int nq = nf - m.nfc;
+        for (int a = 0; a < 4; ++a) {
+            const int code = m.cface[a * n + i];
+            const int f = code >> 1, fq = f - m.nfc;
+            if (fq < 0) continue;
+            const double sg = (code & 1) ? -1.0 : 1.0;
             double pn[3][3];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
