@@ -555,22 +555,66 @@ def sphere_leg(G, I, n, layers, steps, warmup, long_steps):
                      "kernels_ms": {k: ms / cnt for k, (ms, cnt) in kt.items() if cnt}}
         del s
     if long_steps > 0:
-        out["long_run"] = {"steps": long_steps, "quadratic_wall": sphere_long_run(G, mesh, W, gW, free, long_steps)}
+        kw = dict(farfield=free)
+        out["long_run"] = {"steps": long_steps,
+                           "quadratic_wall": sphere_long_run(G, I, mesh, W, gW, kw, 0.3, long_steps)}
         mesh.tet_mid = None
-        out["long_run"]["straight_wall"] = sphere_long_run(G, mesh, W, gW, free, long_steps)
+        out["long_run"]["straight_wall"] = sphere_long_run(G, I, mesh, W, gW, kw, 0.3, long_steps)
+    del mesh
+    out["viscous_noslip"] = sphere_viscous_leg(G, I, n, layers, steps, warmup, long_steps)
     return out
 
 
-def sphere_long_run(G, mesh, W, gW, free, nsteps, every=500):
-    """FP64 steps of the sphere flow from the free stream: time reached, the
-    drag coefficient every `every` steps, the entropy errors at the end; stops
-    where a cell turns non-physical."""
+def sphere_viscous_leg(G, I, n, layers, steps, warmup, long_steps):
+    """The viscous sphere of Sec. 5 (Re 118 on the diameter, Mach 0.2535,
+    adiabatic no-slip wall) on the same quadratic shell: free stream rho = 1,
+    U = (0.2535, 0, 0), p = 1/gamma, mu = rho U D / 118 with D = 2, Pr 1 (the
+    paper states none), third-order WENO, CFL 0.5, impulsive start.  The
+    constrained least squares of the wall cells (Sec. 4.4) take their
+    equality rows at the Gauss points of the curved wall faces.  Throughput in
+    FP64 and FP32-bulk over `steps` steps, then `long_steps` FP64 steps with
+    the drag coefficient (pressure and viscous force on the sphere)."""
+    import numpy as np
+    import torch
+    gamma, u = 1.4, 0.2535
+    mesh = I.cubed_sphere_shell(n, layers, r_out=20.0, ratio=1.08, curved=True, wall_tag=I.FACE_NOSLIP_ADIABATIC)
+    W, gW = I.uniform_state(mesh, 1.0, (u, 0.0, 0.0), 1.0 / gamma, gamma)
+    kw = dict(farfield=tuple(W[:, 0]), viscous=True, mu=u * 2.0 / 118.0, prandtl=1.0)
+    out = {"workload": f"Re 118, Mach 0.2535 past the unit sphere, the same shell ({mesh.n_cell} cells), "
+                       f"quadratic adiabatic no-slip wall, Navier-Stokes, Pr 1, CFL 0.5",
+           "cells": mesh.n_cell, "steps": steps}
+    for name, prec in (("fp64", G.GKS_FP64), ("fp32_bulk", G.GKS_FP32_BULK)):
+        s = G.Solver(mesh, G.default_config(precision=prec, **kw), device="cuda:0")
+        s.init(W, gW)
+        for _ in range(warmup):
+            s.step_cfl(0.5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.step_cfl(0.5)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        assert np.isfinite(s.read_state()[0]).all()
+        kt, _ = timed_kernels(s, steps)
+        out[name] = {"value": mesh.n_cell * 2 * steps / el, "unit": "cell-stage-updates/s",
+                     "ms_per_step": el / steps * 1e3,
+                     "kernels_ms": {k: ms / cnt for k, (ms, cnt) in kt.items() if cnt}}
+        del s
+    if long_steps > 0:
+        out["long_run"] = sphere_long_run(G, I, mesh, W, gW, kw, u, long_steps, entropy=False)
+    return out
+
+
+def sphere_long_run(G, I, mesh, W, gW, kw, u, nsteps, every=500, entropy=True):
+    """FP64 steps of the sphere flow from the free stream (speed u): time
+    reached, the drag coefficient every `every` steps, the entropy errors at
+    the end (`entropy`); stops where a cell turns non-physical."""
     import numpy as np
     import torch
     gamma = 1.4
-    wall = np.nonzero(mesh.face_tag == 2)[0]
+    wall = np.nonzero((mesh.face_cell[:, 1] < 0) & (mesh.face_tag != I.FACE_FARFIELD))[0]
     wall_cells = np.unique(mesh.face_cell[wall, 0])
-    s = G.Solver(mesh, G.default_config(farfield=free), device="cuda:0")
+    s = G.Solver(mesh, G.default_config(**kw), device="cuda:0")
     s.init(W, gW)
     t, n, cd, failed = 0.0, 0, [], False
     torch.cuda.synchronize()
@@ -578,7 +622,7 @@ def sphere_long_run(G, mesh, W, gW, free, nsteps, every=500):
 
     def drag(dt):
         ft = s.debug_face_terms(dt)
-        return float(ft[1, wall].sum() / (0.5 * 1.0 * 0.3 ** 2 * np.pi))
+        return float(ft[1, wall].sum() / (0.5 * 1.0 * u ** 2 * np.pi))
 
     while n < nsteps:
         try:
@@ -593,7 +637,7 @@ def sphere_long_run(G, mesh, W, gW, free, nsteps, every=500):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     r = {"steps": n, "t_reached": t, "nonphysical": failed, "wall_s": el, "drag_coefficient": cd}
-    if not failed:
+    if entropy and not failed:
         Wf = s.read_state()[0]
         rho = Wf[0]
         p = (gamma - 1.0) * (Wf[4] - 0.5 * (Wf[1] ** 2 + Wf[2] ** 2 + Wf[3] ** 2) / rho)

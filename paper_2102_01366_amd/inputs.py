@@ -250,7 +250,7 @@ def _match_faces(tet: np.ndarray):
 
 
 def cubed_sphere_shell(n: int, layers: int, r_out: float = 20.0, ratio: float = 1.08,
-                       curved: bool = False) -> TetMesh:
+                       curved: bool = False, wall_tag: int = FACE_SLIP) -> TetMesh:
     """Shell 1 <= r <= r_out around the unit sphere: the cube surface cut into
     6 panels of n x n cells (n even), mapped to the sphere equiangularly
     (lattice point p with |p|_inf = n/2 goes to the direction tan(pi/4 p/(n/2))),
@@ -258,7 +258,8 @@ def cubed_sphere_shell(n: int, layers: int, r_out: float = 20.0, ratio: float = 
     Each hexahedron is split into two prisms along the surface diagonal
     through its smallest vertex id, each prism into three tetrahedra by the
     minimum-vertex-id rule, so the split conforms across cells and panel
-    seams.  Faces on r = 1 are slip walls, on r = r_out far field.
+    seams.  Faces on r = 1 are walls of kind `wall_tag` (slip by default; a
+    no-slip tag gives a sphere at rest), on r = r_out far field.
 
     curved: quadratic elements (``tet_mid``) whose edges on the wall r = 1 are
     arcs: their control point is the edge midpoint moved radially onto the
@@ -326,7 +327,7 @@ def cubed_sphere_shell(n: int, layers: int, r_out: float = 20.0, ratio: float = 
     face_vert, face_cell = _match_faces(tet)
     wall = face_cell[:, 1] < 0
     rad = np.linalg.norm(xyz[face_vert].mean(axis=1), axis=1)
-    tag = np.where(wall, np.where(rad < 0.5 * (1.0 + r_out), FACE_SLIP, FACE_FARFIELD), FACE_INTERIOR)
+    tag = np.where(wall, np.where(rad < 0.5 * (1.0 + r_out), wall_tag, FACE_FARFIELD), FACE_INTERIOR)
     fo = np.lexsort((face_cell[:, 1], face_cell[:, 0]))
     mesh = TetMesh(xyz=np.ascontiguousarray(xyz), tet=np.ascontiguousarray(tet),
                    face_vert=np.ascontiguousarray(face_vert[fo]), face_cell=np.ascontiguousarray(face_cell[fo]),

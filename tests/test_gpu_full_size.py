@@ -28,7 +28,10 @@ the normwise bar and the per-step map to the element-wise one.
   stream rho = 1, U = (0.3, 0, 0), p = 1/gamma disturbed by a smooth density
   and pressure bump next to the wall (inputs.bump_stream_field, centre
   (1.5, 0, 0)); with straight faces, and with quadratic elements whose wall
-  edges are arcs of the sphere (Sec. 2.1);
+  edges are arcs of the sphere (Sec. 2.1); and the quadratic sphere with an
+  isothermal no-slip wall at the free-stream temperature, Navier-Stokes at
+  Re 118 on the diameter, Pr 0.72 (the constrained wall fits of Sec. 4.4 at
+  the curved Gauss points);
 * the Taylor-Green workload (196,608 cells, test_gpu_parity.py).
 The oracle takes about half a minute per step on the large meshes.
 """
@@ -83,12 +86,17 @@ def test_blast_full_size_two_steps():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("curved", [False, True], ids=["flat_wall", "quadratic_wall"])
-def test_sphere_full_size_two_steps(curved):
+@pytest.mark.parametrize("curved,noslip", [(False, False), (True, False), (True, True)],
+                         ids=["flat_wall", "quadratic_wall", "quadratic_noslip"])
+def test_sphere_full_size_two_steps(curved, noslip):
     gamma = 1.4
-    mesh = I.cubed_sphere_shell(32, 48, r_out=20.0, ratio=1.08, curved=curved)
+    tag = I.FACE_NOSLIP_ISOTHERMAL if noslip else I.FACE_SLIP
+    mesh = I.cubed_sphere_shell(32, 48, r_out=20.0, ratio=1.08, curved=curved, wall_tag=tag)
     W, gW = I.cell_averages(mesh, I.bump_stream_field(gamma, center=(1.5, 0.0, 0.0)))
     free = I.uniform_state(mesh, 1.0, (0.3, 0.0, 0.0), 1.0 / gamma, gamma)[0][:, 0]
+    kw = dict(farfield=tuple(free))
+    if noslip:
+        kw.update(viscous=True, mu=0.3 * 2.0 / 118.0, prandtl=0.72, wall_T=1.0 / gamma)
     # quadratic faces: areas are sums of point weights, rounded differently
     # by the library and the oracle (test_gpu_quadratic.DT_TOL)
-    two_steps(mesh, dict(farfield=tuple(free)), W, gW, dt_tol=4e-15 if curved else 1e-15)
+    two_steps(mesh, kw, W, gW, dt_tol=4e-15 if curved else 1e-15)
