@@ -506,14 +506,22 @@ def _quadratic_map(x: np.ndarray, pts: np.ndarray):
         N.append(4 * lam[:, a] * lam[:, b])
         dN.append(4 * (lam[:, b][:, None] * dlam[a] + lam[:, a][:, None] * dlam[b]))
     N, dN = np.stack(N, axis=1), np.stack(dN, axis=1)                                # [q, 10], [q, 10, 3]
-    X = np.einsum("ql,cld->cqd", N, x)
-    J = np.einsum("qlj,cld->cqdj", dN, x)
-    return X, np.abs(np.linalg.det(J))
+    c, nq = x.shape[0], N.shape[0]
+    xt = np.ascontiguousarray(x.transpose(1, 0, 2)).reshape(10, 3 * c)                 # [l, c d]
+    X = (N @ xt).reshape(nq, c, 3).transpose(1, 0, 2)
+    # J[c, q, d, j] = sum_l dN[q, l, j] x[c, l, d], one matrix product
+    J = (dN.transpose(0, 2, 1).reshape(3 * nq, 10) @ xt).reshape(nq, 3, c, 3)        # [q, j, c, d]
+    a = J.transpose(2, 0, 3, 1)                                                         # [c, q, d, j]
+    det = (a[..., 0, 0] * (a[..., 1, 1] * a[..., 2, 2] - a[..., 1, 2] * a[..., 2, 1])
+           - a[..., 0, 1] * (a[..., 1, 0] * a[..., 2, 2] - a[..., 1, 2] * a[..., 2, 0])
+           + a[..., 0, 2] * (a[..., 1, 0] * a[..., 2, 1] - a[..., 1, 1] * a[..., 2, 0]))
+    return np.ascontiguousarray(X), np.abs(det)
 
 
-def cell_averages(mesh: TetMesh, field, npts: int = 6, chunk: int = 65536):
+def cell_averages(mesh: TetMesh, field, npts: int = 6, chunk: int = 65536, progress=None):
     """Exact (to quadrature) cell averages of a field and of its gradient;
     over a quadratic element (``tet_mid``) through its isoparametric map.
+    ``progress(done, total)``, if given, is called after each chunk of cells.
 
     Returns ``W[5, n_cell]`` and ``gW[15, n_cell]`` (row 3 c + d)."""
     pts, wt = tet_rule(npts)
@@ -529,6 +537,8 @@ def cell_averages(mesh: TetMesh, field, npts: int = 6, chunk: int = 65536):
             Q, dQ = field(X)  # Q [5, c, q], dQ [5, 3, c, q]
             W[:, s:s + chunk] = Q @ wt
             gW[:, s:s + chunk] = (dQ @ wt).reshape(15, -1)
+            if progress:
+                progress(min(s + chunk, nc), nc)
             continue
         X, dj = _quadratic_map(np.concatenate([v, mesh.tet_mid[s:s + chunk]], axis=1), pts)
         w = dj * wt
@@ -536,6 +546,8 @@ def cell_averages(mesh: TetMesh, field, npts: int = 6, chunk: int = 65536):
         Q, dQ = field(X)
         W[:, s:s + chunk] = np.einsum("pcq,cq->pc", Q, w)
         gW[:, s:s + chunk] = np.einsum("pdcq,cq->pdc", dQ, w).reshape(15, -1)
+        if progress:
+            progress(min(s + chunk, nc), nc)
     return W, gW
 
 

@@ -46,10 +46,17 @@ from test_gpu_parity import GW_GROUPS, W_GROUPS, assert_elementwise, assert_pari
 pytestmark = pytest.mark.gpu
 
 
+def _progress(done, total):
+    # the cell averages of a large mesh take minutes: keep the run visibly alive
+    print(f"full size: cell averages {done} / {total}", flush=True)
+
+
 def two_steps(mesh, kw, W, gW, dt_tol=1e-15, grad_tol=1e-12):
     s = G.Solver(mesh, G.default_config(**kw))
     free = G.Solver(mesh, G.default_config(**kw))
+    print(f"full size: {mesh.n_cell} cells, library ready", flush=True)
     orc = oracle.Oracle(mesh, oracle.make_config(**kw))
+    print(f"full size: {mesh.n_cell} cells, oracle ready", flush=True)
     free.init(W, gW)
     Wo, gWo = W, gW
     for step in range(2):
@@ -92,7 +99,9 @@ def test_sphere_full_size_two_steps(curved, noslip):
     gamma = 1.4
     tag = I.FACE_NOSLIP_ISOTHERMAL if noslip else I.FACE_SLIP
     mesh = I.cubed_sphere_shell(32, 48, r_out=20.0, ratio=1.08, curved=curved, wall_tag=tag)
-    W, gW = I.cell_averages(mesh, I.bump_stream_field(gamma, center=(1.5, 0.0, 0.0)))
+    print(f"full size: sphere mesh, {mesh.n_cell} cells", flush=True)
+    W, gW = I.cell_averages(mesh, I.bump_stream_field(gamma, center=(1.5, 0.0, 0.0)), progress=_progress)
+    print("full size: sphere cell averages", flush=True)
     free = I.uniform_state(mesh, 1.0, (0.3, 0.0, 0.0), 1.0 / gamma, gamma)[0][:, 0]
     kw = dict(farfield=tuple(free))
     if noslip:
