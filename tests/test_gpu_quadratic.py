@@ -120,8 +120,24 @@ def test_quadratic_uniform_flow_preserved():
     assert np.abs(g1).max() < 1e-10
 
 
-def test_quadratic_fp32_bulk_close_to_fp64():
-    m, kw, W, gW = _case("sphere_euler")
+@pytest.mark.parametrize("tag", [I.FACE_NOSLIP_ADIABATIC, I.FACE_NOSLIP_ISOTHERMAL],
+                         ids=["adiabatic", "isothermal"])
+def test_gas_at_rest_around_the_curved_no_slip_sphere(tag):
+    Tw = 1.0 / GAMMA
+    m = I.cubed_sphere_shell(4, 4, r_out=3.0, ratio=1.3, curved=True, wall_tag=tag)
+    W, gW = I.uniform_state(m, 1.0, (0.0, 0.0, 0.0), Tw, GAMMA)
+    s = G.Solver(m, G.default_config(viscous=True, mu=0.01, prandtl=0.72, wall_T=Tw, farfield=tuple(W[:, 0])))
+    s.init(W, gW)
+    for _ in range(3):
+        s.step_cfl(0.5)
+    W1, g1 = s.read_state()
+    assert np.abs(W1 - W).max() < 1e-13
+    assert np.abs(g1).max() < 1e-10
+
+
+@pytest.mark.parametrize("name", ["sphere_euler", "sphere_noslip_isothermal"])
+def test_quadratic_fp32_bulk_close_to_fp64(name):
+    m, kw, W, gW = _case(name)
     res = []
     for prec in (G.GKS_FP64, G.GKS_FP32_BULK):
         s = G.Solver(m, G.default_config(precision=prec, **kw))

@@ -224,3 +224,24 @@ def test_constraints_met_at_the_curved_wall_points(oracle_lib, tag):
         worst[name] = e1, e2
     assert max(worst["curved"]) < 1e-13, worst
     assert min(worst["straight"]) > 1e-3, worst
+
+
+@pytest.mark.parametrize("tag", [I.FACE_NOSLIP_ADIABATIC, I.FACE_NOSLIP_ISOTHERMAL],
+                         ids=["adiabatic", "isothermal"])
+def test_gas_at_rest_stays_at_rest_around_the_curved_no_slip_sphere(oracle_lib, tag):
+    """A gas at rest at the wall temperature around the quadratic no-slip
+    sphere, with the same gas as free stream: the constrained fits at the
+    curved wall points, the reflected ghost and the far field leave it at
+    rest (the quadratic faces close every cell)."""
+    gamma, Tw = 1.4, 1.0 / 1.4
+    m = I.cubed_sphere_shell(4, 2, r_out=2.0, ratio=1.0, curved=True, wall_tag=tag)
+    W, gW = I.uniform_state(m, 1.0, (0.0, 0.0, 0.0), Tw, gamma)
+    orc = oracle_lib.Oracle(m, oracle_lib.make_config(viscous=True, mu=0.01, prandtl=0.72, wall_T=Tw,
+                                                      farfield=tuple(W[:, 0])))
+    dt = orc.compute_dt(W, 0.5)
+    Wo, gWo = W, gW
+    for _ in range(3):
+        Wo, gWo = orc.step(dt, Wo, gWo)
+    assert np.abs(Wo - W).max() < 1e-13
+    dr = orc.geometry()[3]
+    assert np.abs(gWo).max() < 1e-13 * 3 * np.abs(W).max() / dr.min()
