@@ -513,7 +513,7 @@ def cavity_leg(G, I, n, steps, warmup):
     return out
 
 
-def sphere_leg(G, I, n, layers, steps, warmup, long_steps):
+def sphere_leg(G, I, n, layers, steps, warmup, long_steps, viscous_steps):
     """The curved-wall workload: inviscid Mach 0.3 flow past the unit sphere
     on a cubed-sphere shell (6 panels of n x n cells, `layers` radial layers
     stretched by 1.08 out to r = 20, each hexahedron split into 6
@@ -561,7 +561,7 @@ def sphere_leg(G, I, n, layers, steps, warmup, long_steps):
         mesh.tet_mid = None
         out["long_run"]["straight_wall"] = sphere_long_run(G, I, mesh, W, gW, kw, 0.3, long_steps)
     del mesh
-    out["viscous_noslip"] = sphere_viscous_leg(G, I, n, layers, steps, warmup, long_steps)
+    out["viscous_noslip"] = sphere_viscous_leg(G, I, n, layers, steps, warmup, viscous_steps)
     return out
 
 
@@ -601,7 +601,8 @@ def sphere_viscous_leg(G, I, n, layers, steps, warmup, long_steps):
                      "kernels_ms": {k: ms / cnt for k, (ms, cnt) in kt.items() if cnt}}
         del s
     if long_steps > 0:
-        out["long_run"] = sphere_long_run(G, I, mesh, W, gW, kw, u, long_steps, entropy=False)
+        out["long_run"] = sphere_long_run(G, I, mesh, W, gW, kw, u, long_steps, every=max(500, long_steps // 16),
+                                          entropy=False)
     return out
 
 
@@ -634,6 +635,8 @@ def sphere_long_run(G, I, mesh, W, gW, kw, u, nsteps, every=500, entropy=True):
         n += 1
         if n % every == 0 or n == nsteps:
             cd.append([n, t, drag(s.last_dt())])
+            print(f"sphere long run: step {n}, t {t:.3f}, drag coefficient {cd[-1][2]:.4f}", file=sys.stderr,
+                  flush=True)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     r = {"steps": n, "t_reached": t, "nonphysical": failed, "wall_s": el, "drag_coefficient": cd}
@@ -676,6 +679,9 @@ def main():
     ap.add_argument("--sphere-long-steps", type=int, default=2000,
                     help="FP64 steps of the sphere flow with quadratic and with straight wall faces "
                          "(drag, entropy error; 0 skips them)")
+    ap.add_argument("--sphere-viscous-steps", type=int, default=2000,
+                    help="FP64 steps of the viscous sphere (Re 118) from its impulsive start, with the drag "
+                         "coefficient at 16 points (0 skips them)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a 256 MiB fill (writes 256 MiB) and a 256 MiB elementwise add "
                          "(reads and writes 256 MiB): known byte counts that calibrate rocprofv3 "
@@ -827,7 +833,8 @@ def main():
     print("cavity, sphere", file=sys.stderr, flush=True)
     out["cavity_noslip"] = cavity_leg(G, I, args.cavity_n, args.cavity_steps, 2) if args.cavity_n > 0 else None
     out["sphere_farfield"] = (sphere_leg(G, I, args.sphere_n, args.sphere_layers, args.sphere_steps, 1,
-                                         args.sphere_long_steps) if args.sphere_n > 0 else None)
+                                         args.sphere_long_steps, args.sphere_viscous_steps)
+                              if args.sphere_n > 0 else None)
     if not args.no_cpu_baseline:
         print("cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(I, mesh, W, gW, {}, args.cpu_baseline_steps, args.cpu_serial_n)
