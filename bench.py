@@ -556,10 +556,11 @@ def sphere_leg(G, I, n, layers, steps, warmup, long_steps, viscous_steps):
         del s
     if long_steps > 0:
         kw = dict(farfield=free)
+        every = max(500, long_steps // 16)
         out["long_run"] = {"steps": long_steps,
-                           "quadratic_wall": sphere_long_run(G, I, mesh, W, gW, kw, 0.3, long_steps)}
+                           "quadratic_wall": sphere_long_run(G, I, mesh, W, gW, kw, 0.3, long_steps, every=every)}
         mesh.tet_mid = None
-        out["long_run"]["straight_wall"] = sphere_long_run(G, I, mesh, W, gW, kw, 0.3, long_steps)
+        out["long_run"]["straight_wall"] = sphere_long_run(G, I, mesh, W, gW, kw, 0.3, long_steps, every=every)
     del mesh
     out["viscous_noslip"] = sphere_viscous_leg(G, I, n, layers, steps, warmup, viscous_steps)
     return out
