@@ -603,14 +603,15 @@ def sphere_viscous_leg(G, I, n, layers, steps, warmup, long_steps):
         del s
     if long_steps > 0:
         out["long_run"] = sphere_long_run(G, I, mesh, W, gW, kw, u, long_steps, every=max(500, long_steps // 16),
-                                          entropy=False)
+                                          entropy=False, wake=True)
     return out
 
 
-def sphere_long_run(G, I, mesh, W, gW, kw, u, nsteps, every=500, entropy=True):
+def sphere_long_run(G, I, mesh, W, gW, kw, u, nsteps, every=500, entropy=True, wake=False):
     """FP64 steps of the sphere flow from the free stream (speed u): time
     reached, the drag coefficient every `every` steps, the entropy errors at
-    the end (`entropy`); stops where a cell turns non-physical."""
+    the end (`entropy`), the wake and separation measures at the end (`wake`:
+    sphere_wake); stops where a cell turns non-physical."""
     import numpy as np
     import torch
     gamma = 1.4
@@ -650,7 +651,59 @@ def sphere_long_run(G, I, mesh, W, gW, kw, u, nsteps, every=500, entropy=True):
                               "wall_cells_max": float(np.abs(e[wall_cells]).max()),
                               "all_cells_rms": float(np.sqrt((e ** 2).mean())),
                               "all_cells_max": float(np.abs(e).max())}
+    if wake and not failed:
+        ft = s.debug_face_terms(s.last_dt())
+        side = np.hypot(ft[2, wall].sum(), ft[3, wall].sum())
+        r["final"] = dict(sphere_wake(mesh, s.read_state()[0], wall_cells),
+                          side_force_coefficient=float(side / (0.5 * u ** 2 * np.pi)))
     return r
+
+
+def sphere_wake(mesh, W, wall_cells):
+    """Measures of the flow past the unit sphere (free stream along +x) from
+    cell averages at their vertex centroids: the length of the closed wake
+    behind the sphere in diameters (from the rear point x = 1 to where the
+    mean axial velocity of the cells within 0.15 of the downstream axis turns
+    positive) and the separation angle in degrees from the front stagnation
+    point (where the mean meridional velocity of the wall cells, binned by
+    their polar angle in 2-degree bins, first turns against the flow beyond
+    90 degrees)."""
+    import numpy as np
+    c = mesh.xyz[mesh.tet].mean(axis=1)
+    U = W[1:4] / W[0]
+    out = {}
+    on_axis = (c[:, 0] > 1.0) & (np.hypot(c[:, 1], c[:, 2]) < 0.15)
+    edges = np.arange(1.0, 6.0001, 0.05)
+    k = np.digitize(c[on_axis, 0], edges) - 1
+    ux = np.array([U[0, on_axis][k == b].mean() if np.any(k == b) else np.nan for b in range(edges.size - 1)])
+    xm = 0.5 * (edges[1:] + edges[:-1])
+    ok = np.isfinite(ux)
+    ux, xm = ux[ok], xm[ok]
+    neg = np.nonzero(ux < 0)[0]
+    if neg.size and neg[0] < 4:
+        b = neg[0]
+        while b + 1 < ux.size and not (ux[b + 1] > 0):
+            b += 1
+        if b + 1 < ux.size:
+            x0 = xm[b] + (xm[b + 1] - xm[b]) * (-ux[b]) / (ux[b + 1] - ux[b])
+            out["wake_length_diameters"] = float((x0 - 1.0) / 2.0)
+    wc = c[wall_cells]
+    r = np.linalg.norm(wc, axis=1)
+    phi = np.arccos(np.clip(-wc[:, 0] / r, -1.0, 1.0))          # 0 at the front stagnation point
+    psi = np.arctan2(wc[:, 2], wc[:, 1])
+    e_phi = np.stack([np.sin(phi), np.cos(phi) * np.cos(psi), np.cos(phi) * np.sin(psi)])
+    u_phi = (U[:, wall_cells] * e_phi).sum(axis=0)
+    bins = np.arange(0.0, 180.0001, 2.0)
+    kb = np.digitize(np.degrees(phi), bins) - 1
+    um = np.array([u_phi[kb == b].mean() if np.any(kb == b) else np.nan for b in range(bins.size - 1)])
+    pm = 0.5 * (bins[1:] + bins[:-1])
+    ok = np.isfinite(um)
+    um, pm = um[ok], pm[ok]
+    for b in range(int(np.searchsorted(pm, 90.0)), um.size - 1):
+        if um[b] > 0 and um[b + 1] <= 0:
+            out["separation_angle_degrees"] = float(pm[b] + (pm[b + 1] - pm[b]) * um[b] / (um[b] - um[b + 1]))
+            break
+    return out
 
 
 def main():
